@@ -1,0 +1,184 @@
+/*
+ * pmr.h - differentiable particle-mesh forward model and its adjoint on one MI355X (gfx950).
+ *
+ * The problem is the one of Sec. 5 (Reconstruction) of Modi, Feng & Seljak (2018): a forward
+ * model f(s) maps the linear density modes s to a halo-mass field; the loss of Sec. 5.1,
+ * Eq. (loss), adds the Gaussian prior of Eq. (priorpdf) to the displaced log-normal
+ * likelihood of Eqs. (var) and (probnoise); the optimiser of Sec. 5.2 needs dL/ds for every
+ * mode. The forward model is a Zel'dovich start, an n-step particle-mesh evolution (Sec. 3),
+ * the features of Sec. 2.2 and the per-voxel network of Sec. 2.1.
+ *
+ * Conventions
+ *   - Modes and gradients: interleaved complex float32 in real-FFT storage
+ *     [B][Np][Np][Np/2+1] (C order, unnormalised forward DFT: s(k) = sum_x d(x) e^{-i k.x}).
+ *     Every stored real and imaginary part is a parameter: grad = dL/dRe(s) + i dL/dIm(s).
+ *     Input modes are projected onto the half spectrum of a real field (the kz = 0 and
+ *     kz = Np/2 planes are averaged with the conjugate of their (-kx, -ky) partner, k = 0
+ *     is removed) before use.
+ *   - Meshes: float32 [B][N][N][N] C order, node i at position i * box / N.
+ *   - Particles start on a lattice offset by half a force-mesh cell from the mesh nodes.
+ *
+ * Ownership: every array argument is a DEVICE pointer owned by the caller, including the
+ * workspace passed to pmr_create. The library never allocates device memory. set_* calls
+ * copy their inputs into the workspace (stream-ordered), so the caller may reuse its
+ * buffers once the stream has passed the call. All calls enqueue work on the context's
+ * stream and return without synchronising it (pmr_set_loss copies a small host array).
+ *
+ * Errors: calls return PMR_OK or a negative status and never abort. Argument and shape
+ * errors are detected synchronously. A HIP launch or runtime error is reported as
+ * PMR_E_HIP and is sticky for the context.
+ *
+ * Threading: a context belongs to one stream; calls on one context are not re-entrant.
+ */
+#ifndef PMR_H
+#define PMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PMR_OK = 0,
+  PMR_E_INVALID = -1,   /* null pointer or invalid value */
+  PMR_E_SHAPE = -2,     /* unsupported sizes */
+  PMR_E_WORKSPACE = -3, /* workspace too small or misaligned (256 B) */
+  PMR_E_HIP = -4,       /* HIP runtime or launch error (sticky) */
+  PMR_E_STATE = -6      /* call out of order (adjoint before forward, missing inputs) */
+};
+
+enum { PMR_FP32 = 0, PMR_MIXED = 1 };
+enum { PMR_LOSS_DENSITY_L2 = 0, PMR_LOSS_LOGNORMAL = 1 };
+
+typedef struct pmr_config {
+  int batch;      /* independent realisations B >= 1 */
+  int n_part;     /* particles per axis Np: power of two, 16..512 */
+  int n_mesh;     /* force mesh per axis: Np or 2 Np, <= 512 */
+  int n_out;      /* output (halo-model) mesh per axis: Np or n_mesh */
+  int n_steps;    /* kick-drift-kick steps, uniform in a, >= 1 */
+  int mlp_hidden; /* hidden width H of the 3 -> H -> H -> 1 network: 8, 16, 32 or 64 */
+  int precision;  /* PMR_FP32, or PMR_MIXED (network on BF16 matrix cores) */
+  int ckpt_every; /* 0: keep every step for the adjoint; k >= 1: keep (x, p) every k steps
+                     and recompute the steps in between during the adjoint */
+  int loss_kind;  /* PMR_LOSS_LOGNORMAL (Sec. 5.1) or PMR_LOSS_DENSITY_L2 */
+  double box;     /* periodic box side, Mpc/h */
+  double a0, a1;  /* start and end scale factors (0 < a0 < a1) */
+  double omega_m; /* flat LambdaCDM matter density (Sec. 3: 0.3175) */
+  double R1, R2;  /* Gaussian feature scales, Mpc/h (Sec. 2.2) */
+} pmr_config;
+
+/* Loss parameters of one batch item (Sec. 5.1, Eq. loss; Sec. 5.2 anneals R_sm and M0). */
+typedef struct pmr_loss_params {
+  double M0;           /* nuisance mass added before the log, Eq. (var) */
+  double mu;           /* offset mu_N of the displaced log-normal */
+  double sigma_N;      /* width sigma_N (residual = (mu + x - x_data) / (2 sigma_N)) */
+  double R_mass;       /* Gaussian smoothing of model and data mass fields, Mpc/h */
+  double R_sm;         /* residual smoothing of the anneal, Mpc/h (0 = none) */
+  double prior_weight; /* weight of the prior term (1 for Eq. loss) */
+} pmr_loss_params;
+
+typedef struct pmr_ctx pmr_ctx;
+
+/* Bytes of device workspace needed for `cfg`; 0 if the configuration is invalid. */
+size_t pmr_workspace_bytes(const pmr_config* cfg);
+
+/* Create a context on `stream` (a hipStream_t; NULL = default stream) over a caller-owned
+ * device workspace of at least pmr_workspace_bytes(cfg) bytes, 256-byte aligned. The
+ * kick/drift factors and growth functions are computed on the host here (FP64). */
+int pmr_create(const pmr_config* cfg, void* workspace, size_t workspace_bytes, void* stream,
+               pmr_ctx** out);
+int pmr_set_stream(pmr_ctx* ctx, void* stream);
+int pmr_destroy(pmr_ctx* ctx);
+
+/* Prior inverse variance 1/S(k) per stored mode, float32 [Np][Np][Np/2+1], shared by all
+ * items; S = <|s(k)|^2> (Eq. priorpdf); use 0 at k = 0. Copied. */
+int pmr_set_prior(pmr_ctx* ctx, const float* inv_var);
+
+/* Network weights, float32 row-major [out][in]: W1 [H][3], b1 [H], W2 [H][H], b2 [H],
+ * W3 [1][H], b3 [1] (Sec. 2.1; frozen). Copied. Required for PMR_LOSS_LOGNORMAL. */
+int pmr_set_mlp(pmr_ctx* ctx, const float* W1, const float* b1, const float* W2,
+                const float* b2, const float* W3, const float* b3);
+
+/* Data field [B][Nout^3]: the halo mass field (log-normal loss) or the target density
+ * contrast (density-L2 loss). Copied. */
+int pmr_set_target(pmr_ctx* ctx, const float* target);
+
+/* Loss parameters, HOST array [B]. Copied to device memory. */
+int pmr_set_loss(pmr_ctx* ctx, const pmr_loss_params* params);
+
+/* Forward model and loss. modes: complex64 [B][Np][Np][Np/2+1] (device).
+ * mass_out: [B][Nout^3] model mass field (log-normal) or final density contrast
+ * (density-L2); nullable. loss_out: device double [B][3] = (total, prior, data).
+ * Keeps what the adjoint needs in the workspace; invalidated by the next forward. */
+int pmr_forward(pmr_ctx* ctx, const void* modes, float* mass_out, double* loss_out);
+
+/* Gradient of sum_b loss_bar[b] * loss[b] + <mass_bar, mass> with respect to the modes of
+ * the preceding pmr_forward. loss_bar: device double [B]; mass_bar: device float
+ * [B][Nout^3] or NULL; grad_modes: complex64, same layout as the modes. */
+int pmr_adjoint(pmr_ctx* ctx, const double* loss_bar, const float* mass_bar, void* grad_modes);
+
+const char* pmr_status_string(int status);
+
+/* ---- inspection of the last forward/adjoint (tests and profiling) ----
+ * Copies an internal buffer of item-major layout into `dst` (device). Returns the number
+ * of bytes copied, or a negative status. `step` selects the PM step where relevant.
+ *   PMR_DBG_X         positions x_step, double [B][3][Np^3] (step 0..n; only the steps the
+ *                     checkpoint policy keeps: all for ckpt_every = 0)
+ *   PMR_DBG_FORCE     force meshes at x_step, float [B][3][Nm^3] (same availability)
+ *   PMR_DBG_SORT_IDS  sorted particle ids for x_step on the force mesh, u32 [B*Np^3]
+ *   PMR_DBG_DELTA_F   final density contrast on the output mesh, float [B][Nout^3]
+ *   PMR_DBG_FEATURES  (delta_R1, delta_R2), float [2][B][Nout^3]
+ *   PMR_DBG_MASS_R    smoothed model mass M_R, float [B][Nout^3]
+ *   PMR_DBG_RES_S     smoothed residual, float [B][Nout^3]
+ *   PMR_DBG_XBAR0     adjoint of x0 after pmr_adjoint, float [B][3][Np^3]
+ *   PMR_DBG_PBAR0     adjoint of p0 after pmr_adjoint, float [B][3][Np^3]
+ *   PMR_DBG_DBAR_F    adjoint of the final density contrast, float [B][Nout^3]
+ */
+enum {
+  PMR_DBG_X = 1,
+  PMR_DBG_FORCE = 2,
+  PMR_DBG_SORT_IDS = 3,
+  PMR_DBG_DELTA_F = 4,
+  PMR_DBG_FEATURES = 5,
+  PMR_DBG_MASS_R = 6,
+  PMR_DBG_RES_S = 7,
+  PMR_DBG_XBAR0 = 8,
+  PMR_DBG_PBAR0 = 9,
+  PMR_DBG_DBAR_F = 10
+};
+long long pmr_debug_copy(pmr_ctx* ctx, int what, int step, void* dst);
+
+/* ---- stand-alone hot-path primitives (device pointers, enqueued on `stream`) ---- */
+
+/* Unnormalised forward 3-D real FFT of `batch` fields [batch][n^3] -> [batch][n][n][n/2+1]
+ * (the numpy rfftn convention). n: power of two 16..512. */
+int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream);
+
+/* Inverse 3-D real FFT including the 1/n^3 factor (numpy irfftn). The spectrum `inout`
+ * is used as scratch and overwritten. Imaginary parts that a real field cannot carry
+ * (kz = 0, n/2 columns after the inner transforms) are ignored, as irfftn does. */
+int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
+
+/* Bytes of scratch for pmr_cic_sort with `n_particles` in total and `batch` items. */
+size_t pmr_sort_scratch_bytes(int n_particles_total, int n_mesh, int batch);
+
+/* Cell keys and the stable (key, id) order of positions x: double [B][3][Np^3].
+ * key = item * n_mesh^3 + (ix * n_mesh + iy) * n_mesh + iz with i = floor(x * n_mesh / box)
+ * mod n_mesh (FP64). Outputs (u32): keys_sorted [B*Np^3], ids_sorted [B*Np^3] (global ids
+ * item * Np^3 + id) and row_start [B * n_mesh^2 + 1] (first sorted index of each row). */
+int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
+                 uint32_t* keys_sorted, uint32_t* ids_sorted, uint32_t* row_start,
+                 void* scratch, size_t scratch_bytes, void* stream);
+
+/* CIC density on an n_mesh^3 mesh: out = sum_p mass W(x_p - cell) - bias, [B][n_mesh^3],
+ * from the outputs of pmr_cic_sort. Deterministic (bitwise reproducible). */
+int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x,
+                  const uint32_t* ids_sorted, const uint32_t* row_start, float mass, float bias,
+                  float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMR_H */

@@ -1,0 +1,9 @@
+"""Differentiable particle-mesh forward model and hand-written adjoint on MI355X (gfx950).
+
+The compute path is libpmr.so (HIP); this package only binds it (see ``api``) and
+prepares inputs on the host (see ``cosmo``).
+"""
+from ._lib import (PMR_FP32, PMR_MIXED, PMR_LOSS_DENSITY_L2,  # noqa: F401
+                   PMR_LOSS_LOGNORMAL, PmrError)
+from .api import (Config, LossParams, PMContext, PMForward, cic_paint,  # noqa: F401
+                  cic_sort, fft_c2r, fft_r2c, workspace_bytes)

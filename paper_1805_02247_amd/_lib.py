@@ -1,0 +1,84 @@
+"""ctypes loader for libpmr.so (the HIP library). Argument marshalling only.
+
+The library must have been built (``__graft_entry__.build()`` or ``build.sh``); there is no
+fallback: importing the binding without it raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmr.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
+
+PMR_OK = 0
+PMR_FP32, PMR_MIXED = 0, 1
+PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
+DBG = {"x": 1, "force": 2, "sort_ids": 3, "delta_f": 4, "features": 5, "mass_r": 6,
+       "res_s": 7, "xbar0": 8, "pbar0": 9, "dbar_f": 10}
+
+
+class PmrConfig(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("n_part", ctypes.c_int), ("n_mesh", ctypes.c_int),
+                ("n_out", ctypes.c_int), ("n_steps", ctypes.c_int), ("mlp_hidden", ctypes.c_int),
+                ("precision", ctypes.c_int), ("ckpt_every", ctypes.c_int),
+                ("loss_kind", ctypes.c_int), ("box", ctypes.c_double), ("a0", ctypes.c_double),
+                ("a1", ctypes.c_double), ("omega_m", ctypes.c_double), ("R1", ctypes.c_double),
+                ("R2", ctypes.c_double)]
+
+
+class PmrLossParams(ctypes.Structure):
+    _fields_ = [("M0", ctypes.c_double), ("mu", ctypes.c_double), ("sigma_N", ctypes.c_double),
+                ("R_mass", ctypes.c_double), ("R_sm", ctypes.c_double),
+                ("prior_weight", ctypes.c_double)]
+
+
+class PmrError(RuntimeError):
+    pass
+
+
+_lib = None
+
+vp, sz, ci, cd, cf = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double, ctypes.c_float
+
+SIGNATURES = {
+    "pmr_workspace_bytes": (sz, [ctypes.POINTER(PmrConfig)]),
+    "pmr_create": (ci, [ctypes.POINTER(PmrConfig), vp, sz, vp, ctypes.POINTER(vp)]),
+    "pmr_set_stream": (ci, [vp, vp]),
+    "pmr_destroy": (ci, [vp]),
+    "pmr_set_prior": (ci, [vp, vp]),
+    "pmr_set_mlp": (ci, [vp, vp, vp, vp, vp, vp, vp]),
+    "pmr_set_target": (ci, [vp, vp]),
+    "pmr_set_loss": (ci, [vp, ctypes.POINTER(PmrLossParams)]),
+    "pmr_forward": (ci, [vp, vp, vp, vp]),
+    "pmr_adjoint": (ci, [vp, vp, vp, vp]),
+    "pmr_status_string": (ctypes.c_char_p, [ci]),
+    "pmr_debug_copy": (ctypes.c_longlong, [vp, ci, ci, vp]),
+    "pmr_fft_r2c": (ci, [ci, ci, vp, vp, vp]),
+    "pmr_fft_c2r": (ci, [ci, ci, vp, vp, vp]),
+    "pmr_sort_scratch_bytes": (sz, [ci, ci, ci]),
+    "pmr_cic_sort": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, vp, sz, vp]),
+    "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, cf, cf, vp, vp]),
+}
+
+
+def lib():
+    """Load libpmr.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libpmr.so not found at {LIB_PATH}; build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != PMR_OK:
+        msg = lib().pmr_status_string(int(status)).decode()
+        raise PmrError(f"libpmr status {status}: {msg}")
+    return status

@@ -1,0 +1,242 @@
+"""Python binding of libpmr: device memory and streams from PyTorch, compute in HIP.
+
+Every call forwards to the C ABI of include/pmr.h with the tensors' device pointers and
+torch's current stream; nothing here computes any step of the forward model or gradient.
+"""
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, numel, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+
+
+@dataclass
+class Config:
+    batch: int = 1
+    n_part: int = 32
+    n_mesh: int = 32
+    n_out: int = 32
+    n_steps: int = 5
+    mlp_hidden: int = 32
+    precision: int = L.PMR_FP32
+    ckpt_every: int = 0
+    loss_kind: int = L.PMR_LOSS_LOGNORMAL
+    box: float = 100.0
+    a0: float = 0.1
+    a1: float = 1.0
+    omega_m: float = 0.3175
+    R1: float = 1.0
+    R2: float = 2.0
+
+    def c(self):
+        return L.PmrConfig(self.batch, self.n_part, self.n_mesh, self.n_out, self.n_steps,
+                           self.mlp_hidden, self.precision, self.ckpt_every, self.loss_kind,
+                           self.box, self.a0, self.a1, self.omega_m, self.R1, self.R2)
+
+
+@dataclass
+class LossParams:
+    M0: float = 1.0
+    mu: float = 0.0
+    sigma_N: float = 0.5
+    R_mass: float = 3.0
+    R_sm: float = 0.0
+    prior_weight: float = 1.0
+
+
+def workspace_bytes(cfg):
+    c = cfg.c()
+    return int(L.lib().pmr_workspace_bytes(ctypes.byref(c)))
+
+
+class PMContext:
+    """One configuration on one device: owns the workspace tensor and the library context."""
+
+    def __init__(self, cfg, device="cuda:0"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(cfg)
+        if nbytes == 0:
+            raise L.PmrError(f"invalid configuration {cfg}")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self._ctx = ctypes.c_void_p()
+        c = cfg.c()
+        L.check(L.lib().pmr_create(ctypes.byref(c), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                   _stream(), ctypes.byref(self._ctx)))
+        B, np_, no = cfg.batch, cfg.n_part, cfg.n_out
+        self.n_modes = np_ * np_ * (np_ // 2 + 1)
+        self.n_out3 = no ** 3
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                L.lib().pmr_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    def _sync_stream(self):
+        L.check(L.lib().pmr_set_stream(self._ctx, _stream()))
+
+    def set_prior(self, inv_var):
+        inv_var = inv_var.to(self.device, torch.float32).contiguous()
+        _need(inv_var, torch.float32, self.n_modes, "inv_var")
+        self._sync_stream()
+        L.check(L.lib().pmr_set_prior(self._ctx, _ptr(inv_var)))
+        self._keep_prior = inv_var
+
+    def set_mlp(self, w):
+        H = self.cfg.mlp_hidden
+        ts = []
+        for k, n in (("W1", 3 * H), ("b1", H), ("W2", H * H), ("b2", H), ("W3", H), ("b3", 1)):
+            t = torch.as_tensor(w[k]).to(self.device, torch.float32).contiguous().reshape(-1)
+            _need(t, torch.float32, n, k)
+            ts.append(t)
+        self._sync_stream()
+        L.check(L.lib().pmr_set_mlp(self._ctx, *[_ptr(t) for t in ts]))
+        self._keep_mlp = ts
+
+    def set_target(self, target):
+        target = target.to(self.device, torch.float32).contiguous()
+        _need(target, torch.float32, self.cfg.batch * self.n_out3, "target")
+        self._sync_stream()
+        L.check(L.lib().pmr_set_target(self._ctx, _ptr(target)))
+        self._keep_target = target
+
+    def set_loss(self, params):
+        if isinstance(params, LossParams):
+            params = [params] * self.cfg.batch
+        if len(params) != self.cfg.batch:
+            raise ValueError("one LossParams per batch item")
+        arr = (L.PmrLossParams * self.cfg.batch)(
+            *[L.PmrLossParams(p.M0, p.mu, p.sigma_N, p.R_mass, p.R_sm, p.prior_weight)
+              for p in params])
+        self._sync_stream()
+        L.check(L.lib().pmr_set_loss(self._ctx, arr))
+
+    def forward(self, modes, want_mass=True):
+        """modes: complex64 [B][Np][Np][Np/2+1] -> (mass [B][Nout^3] or None, loss [B][3] f64)."""
+        _need(modes, torch.complex64, self.cfg.batch * self.n_modes, "modes")
+        mass = (torch.empty(self.cfg.batch, self.n_out3, dtype=torch.float32, device=self.device)
+                if want_mass else None)
+        loss = torch.empty(self.cfg.batch, 3, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        L.check(L.lib().pmr_forward(self._ctx, _ptr(modes), _ptr(mass), _ptr(loss)))
+        return mass, loss
+
+    def adjoint(self, loss_bar, mass_bar=None, out=None):
+        B = self.cfg.batch
+        loss_bar = loss_bar.to(self.device, torch.float64).contiguous()
+        _need(loss_bar, torch.float64, B, "loss_bar")
+        if mass_bar is not None:
+            mass_bar = mass_bar.to(self.device, torch.float32).contiguous()
+            _need(mass_bar, torch.float32, B * self.n_out3, "mass_bar")
+        if out is None:
+            out = torch.empty(B, self.n_modes, dtype=torch.complex64, device=self.device)
+        self._sync_stream()
+        L.check(L.lib().pmr_adjoint(self._ctx, _ptr(loss_bar), _ptr(mass_bar), _ptr(out)))
+        return out
+
+    def debug(self, what, step=0):
+        """Copy an internal buffer of the last forward/adjoint (see PMR_DBG_* in pmr.h)."""
+        cfg = self.cfg
+        B, np3, nm3, no3 = cfg.batch, cfg.n_part ** 3, cfg.n_mesh ** 3, cfg.n_out ** 3
+        spec = {"x": (torch.float64, (B, 3, np3)), "force": (torch.float32, (B, 3, nm3)),
+                "sort_ids": (torch.int32, (B * np3,)), "delta_f": (torch.float32, (B, no3)),
+                "features": (torch.float32, (2, B, no3)), "mass_r": (torch.float32, (B, no3)),
+                "res_s": (torch.float32, (B, no3)), "xbar0": (torch.float32, (B, 3, np3)),
+                "pbar0": (torch.float32, (B, 3, np3)), "dbar_f": (torch.float32, (B, no3))}
+        dt, shape = spec[what]
+        dst = torch.empty(shape, dtype=dt, device=self.device)
+        self._sync_stream()
+        r = L.lib().pmr_debug_copy(self._ctx, L.DBG[what], int(step), _ptr(dst))
+        if r < 0:
+            L.check(int(r))
+        return dst
+
+
+class PMForward(torch.autograd.Function):
+    """loss [B] (and mass [B][Nout^3]) from modes, with the hand-written adjoint as backward.
+
+    Usage: loss, mass = PMForward.apply(modes, pmctx)."""
+
+    @staticmethod
+    def forward(ctx, modes, pmctx):
+        mass, loss = pmctx.forward(modes.contiguous())
+        ctx.pmctx = pmctx
+        return loss[:, 0].clone(), mass
+
+    @staticmethod
+    def backward(ctx, loss_bar, mass_bar):
+        pm = ctx.pmctx
+        if loss_bar is None:
+            loss_bar = torch.zeros(pm.cfg.batch, dtype=torch.float64, device=pm.device)
+        g = pm.adjoint(loss_bar, mass_bar)
+        return g.view(pm.cfg.batch, pm.cfg.n_part, pm.cfg.n_part, pm.cfg.n_part // 2 + 1), None
+
+
+# ---------------------------------------------------------------- primitives
+def fft_r2c(x):
+    """Unnormalised 3-D real FFT of [B][n][n][n] float32 -> complex64 [B][n][n][n/2+1]."""
+    B, n = x.shape[0], x.shape[-1]
+    x = x.contiguous()
+    out = torch.empty(B, n, n, n // 2 + 1, dtype=torch.complex64, device=x.device)
+    L.check(L.lib().pmr_fft_r2c(n, B, _ptr(x), _ptr(out), _stream()))
+    return out
+
+
+def fft_c2r(X):
+    """Inverse 3-D real FFT (with 1/n^3) of complex64 [B][n][n][n/2+1] -> float32."""
+    B, n = X.shape[0], X.shape[1]
+    scratch = X.contiguous().clone()
+    out = torch.empty(B, n, n, n, dtype=torch.float32, device=X.device)
+    L.check(L.lib().pmr_fft_c2r(n, B, _ptr(scratch), _ptr(out), _stream()))
+    return out
+
+
+def cic_sort(x, n_mesh, box):
+    """x: float64 [B][3][Np^3] -> (keys_sorted, ids_sorted, row_start) as int32 tensors
+    (bit patterns of the u32 outputs)."""
+    B, np3 = x.shape[0], x.shape[2]
+    n_part = round(np3 ** (1 / 3))
+    total = B * np3
+    scratch_n = int(L.lib().pmr_sort_scratch_bytes(total, n_mesh, B))
+    scratch = torch.empty(scratch_n, dtype=torch.uint8, device=x.device)
+    keys = torch.empty(total, dtype=torch.int32, device=x.device)
+    ids = torch.empty(total, dtype=torch.int32, device=x.device)
+    rows = torch.empty(B * n_mesh * n_mesh + 1, dtype=torch.int32, device=x.device)
+    L.check(L.lib().pmr_cic_sort(n_part, n_mesh, B, float(box), _ptr(x.contiguous()), _ptr(keys),
+                                 _ptr(ids), _ptr(rows), _ptr(scratch), scratch_n, _stream()))
+    return keys, ids, rows
+
+
+def cic_paint(x, ids, rows, n_mesh, box, mass=1.0, bias=0.0):
+    B, np3 = x.shape[0], x.shape[2]
+    n_part = round(np3 ** (1 / 3))
+    out = torch.empty(B, n_mesh ** 3, dtype=torch.float32, device=x.device)
+    L.check(L.lib().pmr_cic_paint(n_part, n_mesh, B, float(box), _ptr(x.contiguous()), _ptr(ids),
+                                  _ptr(rows), float(mass), float(bias), _ptr(out), _stream()))
+    return out

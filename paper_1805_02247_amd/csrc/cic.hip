@@ -1,0 +1,673 @@
+// Particles: cell keys, the stable (cell, id) sort, cloud-in-cell paint and readout,
+// kick/drift and their adjoints.
+//
+// Particle state is kept in Lagrangian (id) order: id = (i*Np + j)*Np + k for the lattice
+// site (i, j, k), which keeps neighbouring ids close in space through the evolution, so
+// the per-particle gathers below stay cache friendly without moving the state.
+// Positions are FP64 [B][3][Np^3]; momenta and adjoints FP32 [B][3][Np^3].
+//
+// Keys carry the batch item: key = item*Nm^3 + (ix*Nm + iy)*Nm + iz, with (ix, iy, iz)
+// the lower CIC corner computed in FP64. A stable LSD radix sort of (key, id) gives the
+// unique (key, id) order; rows (item, ix, iy) are then contiguous and `row_start` indexes
+// them.
+//
+// Paint is owner-computes and atomic-free across the device: one wavefront owns one
+// target row of Nm cells in LDS and walks the four source rows that can reach it. Inside
+// a source row the particles arrive sorted by iz, so a segmented scan over the 64 lanes
+// sums equal-iz runs and only the last lane of each run touches LDS: each LDS word is
+// written by one lane per instruction, in program order, so the result is bitwise
+// reproducible.
+#include "pmr_internal.h"
+
+namespace pmr {
+namespace {
+
+constexpr int TB = 256;  // threads per block for per-particle kernels
+
+// ---------------------------------------------------------------- keys
+__device__ __forceinline__ uint32_t cell_key(const double* xyz, double scale, int nm,
+                                             uint32_t item, uint32_t cells) {
+  double f;
+  const int ix = cic_corner(xyz[0], scale, nm, &f);
+  const int iy = cic_corner(xyz[1], scale, nm, &f);
+  const int iz = cic_corner(xyz[2], scale, nm, &f);
+  return item * cells + ((uint32_t)ix * nm + iy) * nm + iz;
+}
+
+__global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total, double scale,
+                            int nm, uint32_t* __restrict__ keys) {
+  const int g = blockIdx.x * TB + threadIdx.x;
+  if (g >= total) return;
+  const size_t np3 = (size_t)1 << log_np3;
+  const uint32_t item = g >> log_np3;
+  const size_t id = g & (np3 - 1);
+  const double* xi = x + (size_t)item * 3 * np3 + id;
+  double p[3] = {xi[0], xi[np3], xi[2 * np3]};
+  keys[g] = cell_key(p, scale, nm, item, (uint32_t)nm * nm * nm);
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int SORT_WAVES = 4;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_WAVES * PMR_WAVE * SORT_ITEMS;  // 4096 keys per block
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = threadIdx.x & 63;
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Lanes of this wavefront (among `valid`) whose digit equals mine.
+template <int D>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+  uint64_t m = valid;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+// Digit histogram of each tile: hist[digit * nblocks + block].
+template <int D>
+__global__ __launch_bounds__(TB) void radix_hist_kernel(const uint32_t* __restrict__ keys, int n,
+                                                        int shift, uint32_t* __restrict__ hist) {
+  constexpr int NBK = 1 << D;
+  __shared__ uint32_t cnt[NBK];
+  for (int i = threadIdx.x; i < NBK; i += TB) cnt[i] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * SORT_TILE;
+  for (int i = threadIdx.x; i < SORT_TILE; i += TB) {
+    const size_t j = base + i;
+    if (j < (size_t)n) atomicAdd(&cnt[(keys[j] >> shift) & (NBK - 1)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NBK; i += TB) hist[(size_t)i * gridDim.x + blockIdx.x] = cnt[i];
+}
+
+// Stable scatter. Key j of the tile is handled by wave w = (j / 64) / ITEMS in order, so
+// ranks follow j: rank = offset[digit][block] + (same digit in earlier waves)
+//                      + (same digit earlier in this wave).
+// ids_in == nullptr means identity payload (id = index).
+template <int D>
+__global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ ids_in,
+                                                           int n, int shift,
+                                                           const uint32_t* __restrict__ offsets,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ ids_out) {
+  constexpr int NBK = 1 << D;
+  __shared__ uint32_t cnt[SORT_WAVES][NBK];
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < SORT_WAVES * NBK; i += TB) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)w * PMR_WAVE * SORT_ITEMS;
+  uint32_t key[SORT_ITEMS], id[SORT_ITEMS], rank[SORT_ITEMS];
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const size_t j = base + (size_t)it * PMR_WAVE + lane;
+    const bool ok = j < (size_t)n;
+    key[it] = ok ? keys_in[j] : 0u;
+    id[it] = ok ? (ids_in ? ids_in[j] : (uint32_t)j) : 0u;
+    const uint32_t d = (key[it] >> shift) & (NBK - 1);
+    const uint64_t valid = __ballot(ok);
+    const uint64_t m = match_digit<D>(d, valid);
+    uint32_t r = 0;
+    if (ok) r = cnt[w][d] + (uint32_t)__popcll(m & lt);
+    rank[it] = r;
+    // the lowest lane of each digit group advances the running count
+    if (ok && (m & lt) == 0) cnt[w][d] += (uint32_t)__popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS update visible to the next item
+  }
+  __syncthreads();
+  // exclusive prefix over waves, seeded with the global offset of (digit, block)
+  for (int d = threadIdx.x; d < NBK; d += TB) {
+    uint32_t run = offsets[(size_t)d * gridDim.x + blockIdx.x];
+#pragma unroll
+    for (int ww = 0; ww < SORT_WAVES; ++ww) {
+      const uint32_t c = cnt[ww][d];
+      cnt[ww][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const size_t j = base + (size_t)it * PMR_WAVE + lane;
+    if (j < (size_t)n) {
+      const uint32_t d = (key[it] >> shift) & (NBK - 1);
+      const uint32_t dst = cnt[w][d] + rank[it];
+      keys_out[dst] = key[it];
+      ids_out[dst] = id[it];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- exclusive scan (u32)
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = TB * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // sh: TB words
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < TB; d <<= 1) {
+    uint32_t a = t >= d ? sh[t - d] : 0u;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *total = sh[TB - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(TB) void scan_reduce_kernel(const uint32_t* __restrict__ in, size_t n,
+                                                         uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[TB];
+  const size_t base = (size_t)blockIdx.x * SCAN_TILE;
+  uint32_t s = 0;
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const size_t j = base + (size_t)threadIdx.x * SCAN_ITEMS + i;
+    if (j < n) s += in[j];
+  }
+  uint32_t tot;
+  block_exclusive_scan(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of `n` sums in place (n small).
+__global__ __launch_bounds__(TB) void scan_small_kernel(uint32_t* __restrict__ sums, int n) {
+  __shared__ uint32_t sh[TB];
+  uint32_t carry = 0;
+  for (int base = 0; base < n; base += TB) {
+    const int j = base + threadIdx.x;
+    const uint32_t v = j < n ? sums[j] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, sh, &tot);
+    if (j < n) sums[j] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(TB) void scan_down_kernel(const uint32_t* __restrict__ in, size_t n,
+                                                       const uint32_t* __restrict__ sums,
+                                                       uint32_t* __restrict__ out) {
+  __shared__ uint32_t sh[TB];
+  const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint32_t s = 0;
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, sh, &tot) + sums[blockIdx.x];
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+// ---------------------------------------------------------------- row starts
+// row_start[r] = first sorted position whose row (key >> log_nm) is >= r; r = 0..rows.
+__global__ void row_start_kernel(const uint32_t* __restrict__ keys, int n, int log_nm, int rows,
+                                 uint32_t* __restrict__ row_start) {
+  const int j = blockIdx.x * TB + threadIdx.x;
+  if (j > n) return;
+  const int r_hi = j < n ? (int)(keys[j] >> log_nm) : rows;
+  const int r_lo = j > 0 ? (int)(keys[j - 1] >> log_nm) : -1;
+  for (int r = r_lo + 1; r <= r_hi; ++r) row_start[r] = j;
+}
+
+// ---------------------------------------------------------------- paint
+enum PaintMode { PAINT_MASS = 0, PAINT_ADJ3 = 1 };
+
+struct PaintArgs {
+  const double* x;         // [B][3][Np^3]
+  const uint32_t* ids;     // sorted global ids (item*Np^3 + id)
+  const uint32_t* row_start;
+  int log_np3, nm, log_nm;
+  double scale;            // nm / box
+  float mass, bias;        // PAINT_MASS value per particle, subtracted constant
+  // PAINT_ADJ3: v_a = kick * (pbar_a + drift * xbar_a)
+  const float* pbar;
+  const float* xbar;
+  float kick, drift;
+  float* out;              // [B][C][nm^3]
+};
+
+template <int C>
+__device__ __forceinline__ void seg_scan(float (&a0)[C], float (&a1)[C], int key) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ku = __shfl_up(key, d, 64);
+    float t0[C], t1[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      t0[c] = __shfl_up(a0[c], d, 64);
+      t1[c] = __shfl_up(a1[c], d, 64);
+    }
+    if (lane >= d && ku == key) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        a0[c] += t0[c];
+        a1[c] += t1[c];
+      }
+    }
+  }
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(TB) void paint_kernel(PaintArgs a) {
+  extern __shared__ float acc_all[];
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nm = a.nm;
+  const int row = blockIdx.x * (TB / 64) + w;  // global target row (item, ix, iy)
+  const int rows_per_item = nm * nm;
+  const int item = row / rows_per_item;
+  const int rr = row - item * rows_per_item;
+  const int ix = rr / nm, iy = rr - (rr / nm) * nm;
+  float* acc = acc_all + w * C * nm;
+  for (int i = lane; i < C * nm; i += 64) acc[i] = 0.f;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  const size_t np3 = (size_t)1 << a.log_np3;
+#pragma unroll 1
+  for (int o = 0; o < 4; ++o) {
+    const int ox = o >> 1, oy = o & 1;
+    const int sx = (ix - ox + nm) & (nm - 1);
+    const int sy = (iy - oy + nm) & (nm - 1);
+    const int srow = item * rows_per_item + sx * nm + sy;
+    const uint32_t beg = a.row_start[srow], end = a.row_start[srow + 1];
+#pragma unroll 1
+    for (uint32_t c0 = beg; c0 < end; c0 += 64) {
+      const uint32_t j = c0 + lane;
+      const bool ok = j < end;
+      int iz = 0x7fffffff - lane;  // never equal across lanes when invalid
+      float a0[C], a1[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) a0[c] = a1[c] = 0.f;
+      if (ok) {
+        const uint32_t g = a.ids[j];
+        const uint32_t it = g >> a.log_np3;
+        const size_t id = g & (np3 - 1);
+        const double* xp = a.x + (size_t)it * 3 * np3 + id;
+        double fx, fy, fz;
+        cic_corner(xp[0], a.scale, nm, &fx);
+        cic_corner(xp[np3], a.scale, nm, &fy);
+        iz = cic_corner(xp[2 * np3], a.scale, nm, &fz);
+        const float wx = ox ? (float)fx : 1.f - (float)fx;
+        const float wy = oy ? (float)fy : 1.f - (float)fy;
+        const float wxy = wx * wy;
+        const float f1 = (float)fz, f0 = 1.f - (float)fz;
+        if constexpr (MODE == PAINT_MASS) {
+          const float v = a.mass * wxy;
+          a0[0] = v * f0;
+          a1[0] = v * f1;
+        } else {
+          const size_t pi = (size_t)it * 3 * np3 + id;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float v = a.kick * (a.pbar[pi + c * np3] + a.drift * a.xbar[pi + c * np3]) * wxy;
+            a0[c] = v * f0;
+            a1[c] = v * f1;
+          }
+        }
+      }
+      seg_scan<C>(a0, a1, iz);
+      const int iz_next = __shfl_down(iz, 1, 64);
+      const bool tail = ok && (lane == 63 || iz_next != iz);
+      if (tail) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) atomicAdd(&acc[c * nm + iz], a0[c]);
+      }
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      if (tail) {
+        const int iz1 = (iz + 1) & (nm - 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) atomicAdd(&acc[c * nm + iz1], a1[c]);
+      }
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  const size_t cells = (size_t)nm * nm * nm;
+  float* dst = a.out + (size_t)item * C * cells + ((size_t)ix * nm + iy) * nm;
+  for (int c = 0; c < C; ++c)
+    for (int i = lane; i < nm; i += 64) dst[c * cells + i] = acc[c * nm + i] - a.bias;
+}
+
+// ---------------------------------------------------------------- gathers
+struct Corner {
+  int i0[3], i1[3];
+  float f[3];
+};
+
+__device__ __forceinline__ Corner corner_of(const double* xyz, double scale, int nm) {
+  Corner c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double f;
+    c.i0[a] = cic_corner(xyz[a], scale, nm, &f);
+    c.i1[a] = (c.i0[a] + 1) & (nm - 1);
+    c.f[a] = (float)f;
+  }
+  return c;
+}
+
+__device__ __forceinline__ size_t cidx(const Corner& c, int ox, int oy, int oz, int nm) {
+  const int ix = ox ? c.i1[0] : c.i0[0];
+  const int iy = oy ? c.i1[1] : c.i0[1];
+  const int iz = oz ? c.i1[2] : c.i0[2];
+  return ((size_t)ix * nm + iy) * nm + iz;
+}
+
+struct StepArgs {
+  const double* x;    // [B][3][Np^3] positions x_i
+  double* x_next;     // positions x_{i+1}
+  float* p;           // momenta, updated in place
+  const float* F;     // [B][3][nm^3] force meshes at x_i
+  uint32_t* keys;     // keys of x_{i+1} (nullable)
+  int log_np3, nm, total;
+  double scale, box;
+  float kick;
+  double drift;
+  int key_nm;         // mesh of the keys emitted for x_{i+1}
+  double key_scale;
+};
+
+// p += kick * F(x_i);  x_{i+1} = wrap(x_i + drift * p);  key(x_{i+1})
+__global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
+  const int g = blockIdx.x * TB + threadIdx.x;
+  if (g >= a.total) return;
+  const size_t np3 = (size_t)1 << a.log_np3;
+  const int item = g >> a.log_np3;
+  const size_t id = g & (np3 - 1);
+  const size_t pi = (size_t)item * 3 * np3 + id;
+  double xyz[3] = {a.x[pi], a.x[pi + np3], a.x[pi + 2 * np3]};
+  const int nm = a.nm;
+  const Corner c = corner_of(xyz, a.scale, nm);
+  const size_t cells = (size_t)nm * nm * nm;
+  const float* F = a.F + (size_t)item * 3 * cells;
+  float fa[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+    const float w = (ox ? c.f[0] : 1.f - c.f[0]) * (oy ? c.f[1] : 1.f - c.f[1]) *
+                     (oz ? c.f[2] : 1.f - c.f[2]);
+    const size_t ci = cidx(c, ox, oy, oz, nm);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) fa[q] += w * F[q * cells + ci];
+  }
+  double xn[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float pq = a.p[pi + q * np3] + a.kick * fa[q];
+    a.p[pi + q * np3] = pq;
+    xn[q] = wrap_box(xyz[q] + a.drift * (double)pq, a.box);
+    a.x_next[pi + q * np3] = xn[q];
+  }
+  if (a.keys) {
+    const uint32_t kn = (uint32_t)a.key_nm;
+    a.keys[g] = cell_key(xn, a.key_scale, a.key_nm, item, kn * kn * kn);
+  }
+}
+
+struct AdjArgs {
+  const double* x;     // positions x_i
+  float* xbar;         // in: xbar_{i+1}; out: xbar_i
+  float* pbar;         // in: pbar_{i+1/2}; out: pbar_{i-1/2}
+  const float* F;      // force meshes at x_i [B][3][nm^3] (nullable: final-paint adjoint)
+  const float* dbar;   // density adjoint mesh [B][nm^3]
+  int log_np3, nm, total;
+  double scale;
+  float kick, drift, mass;
+  int final_mode;      // 1: xbar = mass * grad(dbar), pbar = 0
+};
+
+// Step adjoint (reverse of kick then drift):
+//   pbar' = pbar + drift * xbar;  Fbar = kick * pbar'
+//   xbar' = xbar + sum_cell dW(x - cell)/dx * (sum_a Fbar_a F_a(cell) + mass * dbar(cell))
+__global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
+  const int g = blockIdx.x * TB + threadIdx.x;
+  if (g >= a.total) return;
+  const size_t np3 = (size_t)1 << a.log_np3;
+  const int item = g >> a.log_np3;
+  const size_t id = g & (np3 - 1);
+  const size_t pi = (size_t)item * 3 * np3 + id;
+  double xyz[3] = {a.x[pi], a.x[pi + np3], a.x[pi + 2 * np3]};
+  const int nm = a.nm;
+  const Corner c = corner_of(xyz, a.scale, nm);
+  const size_t cells = (size_t)nm * nm * nm;
+  float pb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, fb[3] = {0.f, 0.f, 0.f};
+  if (!a.final_mode) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      xb[q] = a.xbar[pi + q * np3];
+      pb[q] = a.pbar[pi + q * np3] + a.drift * xb[q];
+      fb[q] = a.kick * pb[q];
+    }
+  }
+  const float* F = a.F ? a.F + (size_t)item * 3 * cells : nullptr;
+  const float* D = a.dbar + (size_t)item * cells;
+  const float s = (float)a.scale;
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+    const float wx = ox ? c.f[0] : 1.f - c.f[0];
+    const float wy = oy ? c.f[1] : 1.f - c.f[1];
+    const float wz = oz ? c.f[2] : 1.f - c.f[2];
+    const float dx = ox ? s : -s, dy = oy ? s : -s, dz = oz ? s : -s;
+    const size_t ci = cidx(c, ox, oy, oz, nm);
+    float v = a.mass * D[ci];
+    if (F) v += fb[0] * F[ci] + fb[1] * F[cells + ci] + fb[2] * F[2 * cells + ci];
+    gx += dx * wy * wz * v;
+    gy += wx * dy * wz * v;
+    gz += wx * wy * dz * v;
+  }
+  a.xbar[pi] = xb[0] + gx;
+  a.xbar[pi + np3] = xb[1] + gy;
+  a.xbar[pi + 2 * np3] = xb[2] + gz;
+  a.pbar[pi] = pb[0];
+  a.pbar[pi + np3] = pb[1];
+  a.pbar[pi + 2 * np3] = pb[2];
+}
+
+// Zel'dovich start: x0 = wrap(q + D0 Psi), p0 = Gp0 Psi; q = idx * (box/np) + box / (2 nm).
+__global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ psi, int np,
+                                                     int log_np3, int total, double box,
+                                                     double half_cell, double D0, float Gp0,
+                                                     double* __restrict__ x, float* __restrict__ p,
+                                                     uint32_t* __restrict__ keys, int key_nm,
+                                                     double key_scale) {
+  const int g = blockIdx.x * TB + threadIdx.x;
+  if (g >= total) return;
+  const size_t np3 = (size_t)1 << log_np3;
+  const int item = g >> log_np3;
+  const size_t id = g & (np3 - 1);
+  const size_t pi = (size_t)item * 3 * np3 + id;
+  const int idx[3] = {(int)(id / ((size_t)np * np)), (int)((id / np) % np), (int)(id % np)};
+  const double dq = box / (double)np;
+  double xn[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float ps = psi[pi + q * np3];
+    const double q0 = (double)idx[q] * dq + half_cell;
+    xn[q] = wrap_box(q0 + D0 * (double)ps, box);
+    x[pi + q * np3] = xn[q];
+    p[pi + q * np3] = Gp0 * ps;
+  }
+  const uint32_t kn = (uint32_t)key_nm;
+  keys[g] = cell_key(xn, key_scale, key_nm, item, kn * kn * kn);
+}
+
+}  // namespace
+
+// ================================================================ host launchers
+size_t sort_scratch_bytes(int n, int key_bits) {
+  const int passes = (key_bits + 8) / 9;
+  const int D = (key_bits + passes - 1) / passes;
+  const size_t nb = (size_t)((n + SORT_TILE - 1) / SORT_TILE);
+  const size_t hist = nb << D;
+  const size_t sums = (hist + SCAN_TILE - 1) / SCAN_TILE;
+  // keys/ids ping-pong buffers (2 x n), histogram, offsets, block sums
+  return (2 * (size_t)n + 2 * hist + sums + 64) * sizeof(uint32_t);
+}
+
+template <int D>
+static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
+                      int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* sums,
+                      hipStream_t s) {
+  const int nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const size_t hn = (size_t)nb << D;
+  radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
+  const int ns = (int)((hn + SCAN_TILE - 1) / SCAN_TILE);
+  scan_reduce_kernel<<<ns, TB, 0, s>>>(hist, hn, sums);
+  scan_small_kernel<<<1, TB, 0, s>>>(sums, ns);
+  scan_down_kernel<<<ns, TB, 0, s>>>(hist, hn, sums, offs);
+  radix_scatter_kernel<D><<<nb, TB, 0, s>>>(kin, iin, n, shift, offs, kout, iout);
+}
+
+// Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
+// and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
+void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
+                 uint32_t* ids_sorted, void* scratch, hipStream_t s) {
+  const int passes = (key_bits + 8) / 9;
+  const int D = (key_bits + passes - 1) / passes;
+  const int nb = (n + SORT_TILE - 1) / SORT_TILE;
+  const size_t hn = (size_t)nb << D;
+  uint32_t* w = (uint32_t*)scratch;
+  uint32_t* ka = w;
+  uint32_t* ia = ka + n;
+  uint32_t* hist = ia + n;
+  uint32_t* offs = hist + hn;
+  uint32_t* sums = offs + hn;
+  const uint32_t* kin = keys_io;
+  const uint32_t* iin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    // last pass lands in the caller's output arrays
+    const bool last = p == passes - 1;
+    const bool to_a = ((passes - 1 - p) & 1) == 1;
+    uint32_t* ko = last ? keys_sorted : (to_a ? ka : keys_sorted);
+    uint32_t* io = last ? ids_sorted : (to_a ? ia : ids_sorted);
+    const int shift = p * D;
+    switch (D) {
+#define CASE(DD) \
+  case DD: sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, sums, s); break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
+#undef CASE
+      default: break;
+    }
+    kin = ko;
+    iin = io;
+  }
+}
+
+void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
+                      uint32_t* row_start, hipStream_t s) {
+  row_start_kernel<<<(n + 1 + TB - 1) / TB, TB, 0, s>>>(keys_sorted, n, log_nm, rows, row_start);
+}
+
+void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
+                 hipStream_t s) {
+  keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys);
+}
+
+void launch_paint_mass(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
+                       int log_np3, int nm, double scale, float mass, float bias, float* out,
+                       hipStream_t s) {
+  PaintArgs a{};
+  a.x = x;
+  a.ids = ids;
+  a.row_start = row_start;
+  a.log_np3 = log_np3;
+  a.nm = nm;
+  a.scale = scale;
+  a.mass = mass;
+  a.bias = bias;
+  a.out = out;
+  const int rows = batch * nm * nm;
+  paint_kernel<1, PAINT_MASS><<<rows / (TB / 64), TB, (TB / 64) * nm * sizeof(float), s>>>(a);
+}
+
+void launch_paint_adj3(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
+                       int log_np3, int nm, double scale, const float* pbar, const float* xbar,
+                       float kick, float drift, float* out, hipStream_t s) {
+  PaintArgs a{};
+  a.x = x;
+  a.ids = ids;
+  a.row_start = row_start;
+  a.log_np3 = log_np3;
+  a.nm = nm;
+  a.scale = scale;
+  a.pbar = pbar;
+  a.xbar = xbar;
+  a.kick = kick;
+  a.drift = drift;
+  a.out = out;
+  const int rows = batch * nm * nm;
+  paint_kernel<3, PAINT_ADJ3><<<rows / (TB / 64), TB, (TB / 64) * 3 * nm * sizeof(float), s>>>(a);
+}
+
+void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
+                       int batch, int log_np3, int nm, double box, float kick, double drift,
+                       int key_nm, hipStream_t s) {
+  StepArgs a{};
+  a.x = x;
+  a.x_next = x_next;
+  a.p = p;
+  a.F = F;
+  a.keys = keys;
+  a.log_np3 = log_np3;
+  a.nm = nm;
+  a.total = batch << log_np3;
+  a.scale = (double)nm / box;
+  a.box = box;
+  a.kick = kick;
+  a.drift = drift;
+  a.key_nm = key_nm;
+  a.key_scale = (double)key_nm / box;
+  kick_drift_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
+}
+
+void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
+                           const float* dbar, int batch, int log_np3, int nm, double box,
+                           float kick, float drift, float mass, int final_mode, hipStream_t s) {
+  AdjArgs a{};
+  a.x = x;
+  a.xbar = xbar;
+  a.pbar = pbar;
+  a.F = F;
+  a.dbar = dbar;
+  a.log_np3 = log_np3;
+  a.nm = nm;
+  a.total = batch << log_np3;
+  a.scale = (double)nm / box;
+  a.kick = kick;
+  a.drift = drift;
+  a.mass = mass;
+  a.final_mode = final_mode;
+  adjoint_gather_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
+}
+
+void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, int key_nm,
+                    hipStream_t s) {
+  const int total = batch << log_np3;
+  za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, np, log_np3, total, box, half_cell, D0,
+                                                       Gp0, x, p, keys, key_nm,
+                                                       (double)key_nm / box);
+}
+
+}  // namespace pmr

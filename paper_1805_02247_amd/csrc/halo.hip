@@ -1,0 +1,340 @@
+// Halo-mass model and likelihood on the output mesh (Sec. 2.1, Sec. 2.2, Sec. 5.1).
+//
+// Per voxel: features f = (delta_0, delta_R1, delta_R1 - delta_R2); a 3 -> H -> H -> 1
+// network with ReLU hidden layers and a softplus on the output gives the mass M.
+// Likelihood: x = log(M_R + M0), residual r = (mu + x - x_data) / (2 sigma_N); the
+// residual is Gaussian-smoothed on R_sm (the anneal) and squared. Sums are reduced in
+// FP64 with a fixed tree, so the loss is bitwise reproducible.
+//
+// Loss parameters live in device memory, [B][6] doubles:
+//   (M0, mu, sigma_N, R_mass, R_sm, prior_weight).
+#include "pmr_internal.h"
+
+namespace pmr {
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ float softplus_f(float y) {
+  return fmaxf(y, 0.f) + log1pf(expf(-fabsf(y)));
+}
+__device__ __forceinline__ float sigmoid_f(float y) { return 1.f / (1.f + expf(-y)); }
+
+// Weight block layout (floats): W1[H][3], b1[H], W2[H][H], b2[H], W3[H], b3[1].
+template <int H>
+struct WOff {
+  static constexpr int W1 = 0, B1 = 3 * H, W2 = 4 * H, B2 = 4 * H + H * H, W3 = 5 * H + H * H,
+                       B3 = 6 * H + H * H, SIZE = 6 * H + H * H + 1;
+};
+
+template <int H>
+__device__ __forceinline__ void load_weights(float* sw, const float* __restrict__ w) {
+  for (int i = threadIdx.x; i < WOff<H>::SIZE; i += TB) sw[i] = w[i];
+  __syncthreads();
+}
+
+// M = softplus(W3 relu(W2 relu(W1 f + b1) + b2) + b3), FP32.
+template <int H>
+__global__ __launch_bounds__(TB) void mlp_fwd_kernel(const float* __restrict__ d0,
+                                                     const float* __restrict__ d1,
+                                                     const float* __restrict__ d2, size_t n,
+                                                     const float* __restrict__ w,
+                                                     float* __restrict__ mass) {
+  using O = WOff<H>;
+  __shared__ float sw[O::SIZE];
+  load_weights<H>(sw, w);
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= n) return;
+  const float f0 = d0[v], f1 = d1[v], f2 = d1[v] - d2[v];
+  float h1[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+    h1[j] = fmaxf(sw[O::W1 + 3 * j] * f0 + sw[O::W1 + 3 * j + 1] * f1 + sw[O::W1 + 3 * j + 2] * f2 +
+                      sw[O::B1 + j],
+                  0.f);
+  float y = sw[O::B3];
+#pragma unroll 4
+  for (int j = 0; j < H; ++j) {
+    float a = sw[O::B2 + j];
+#pragma unroll
+    for (int i = 0; i < H; ++i) a += sw[O::W2 + j * H + i] * h1[i];
+    y += sw[O::W3 + j] * fmaxf(a, 0.f);
+  }
+  mass[v] = softplus_f(y);
+}
+
+// Input gradient with weights frozen (recomputing the forward pass):
+//   ybar = Mbar sigmoid(y); a2bar = ybar W3 [a2 > 0]; a1bar = (W2^T a2bar) [a1 > 0];
+//   fbar = W1^T a1bar. Writes fbar0, fbar1 + fbar2 and fbar2 (the features' adjoint needs
+//   G_R1 (fbar1 + fbar2) - G_R2 fbar2).
+template <int H>
+__global__ __launch_bounds__(TB) void mlp_bwd_kernel(const float* __restrict__ d0,
+                                                     const float* __restrict__ d1,
+                                                     const float* __restrict__ d2, size_t n,
+                                                     const float* __restrict__ w,
+                                                     const float* __restrict__ mbar,
+                                                     float* __restrict__ g0, float* __restrict__ g12,
+                                                     float* __restrict__ g2) {
+  using O = WOff<H>;
+  __shared__ float sw[O::SIZE];
+  load_weights<H>(sw, w);
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= n) return;
+  const float f0 = d0[v], f1 = d1[v], f2 = d1[v] - d2[v];
+  float a1[H], a2[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+    a1[j] = sw[O::W1 + 3 * j] * f0 + sw[O::W1 + 3 * j + 1] * f1 + sw[O::W1 + 3 * j + 2] * f2 +
+            sw[O::B1 + j];
+  float y = sw[O::B3];
+#pragma unroll 4
+  for (int j = 0; j < H; ++j) {
+    float a = sw[O::B2 + j];
+#pragma unroll
+    for (int i = 0; i < H; ++i) a += sw[O::W2 + j * H + i] * fmaxf(a1[i], 0.f);
+    a2[j] = a;
+    y += sw[O::W3 + j] * fmaxf(a, 0.f);
+  }
+  const float yb = mbar[v] * sigmoid_f(y);
+#pragma unroll
+  for (int j = 0; j < H; ++j) a2[j] = a2[j] > 0.f ? yb * sw[O::W3 + j] : 0.f;
+  float fb0 = 0.f, fb1 = 0.f, fb2 = 0.f;
+#pragma unroll 4
+  for (int i = 0; i < H; ++i) {
+    float hb = 0.f;
+#pragma unroll
+    for (int j = 0; j < H; ++j) hb += sw[O::W2 + j * H + i] * a2[j];
+    if (a1[i] > 0.f) {
+      fb0 += sw[O::W1 + 3 * i] * hb;
+      fb1 += sw[O::W1 + 3 * i + 1] * hb;
+      fb2 += sw[O::W1 + 3 * i + 2] * hb;
+    }
+  }
+  g0[v] = fb0;
+  g12[v] = fb1 + fb2;
+  g2[v] = fb2;
+}
+
+// x_data = log(MtR + M0)
+__global__ void target_x_kernel(const float* __restrict__ mtr, size_t per_item, int batch,
+                                const double* __restrict__ prm, float* __restrict__ xd) {
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= per_item * batch) return;
+  const int b = (int)(v / per_item);
+  xd[v] = logf(mtr[v] + (float)prm[b * 6 + 0]);
+}
+
+// r = (mu + log(MR + M0) - x_data) / (2 sigma_N)
+__global__ void residual_kernel(const float* __restrict__ mr, const float* __restrict__ xd,
+                                size_t per_item, int batch, const double* __restrict__ prm,
+                                float* __restrict__ r) {
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= per_item * batch) return;
+  const int b = (int)(v / per_item);
+  const float M0 = (float)prm[b * 6 + 0], mu = (float)prm[b * 6 + 1];
+  const float inv2s = (float)(0.5 / prm[b * 6 + 2]);
+  r[v] = (mu + logf(mr[v] + M0) - xd[v]) * inv2s;
+}
+
+// MRbar = rbar / (2 sigma_N (MR + M0))
+__global__ void mrbar_kernel(const float* __restrict__ rbar, const float* __restrict__ mr,
+                             size_t per_item, int batch, const double* __restrict__ prm,
+                             float* __restrict__ out) {
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= per_item * batch) return;
+  const int b = (int)(v / per_item);
+  const float M0 = (float)prm[b * 6 + 0];
+  const float inv2s = (float)(0.5 / prm[b * 6 + 2]);
+  out[v] = rbar[v] * inv2s / (mr[v] + M0);
+}
+
+// density-L2 adjoint: dbar = 2 loss_bar (delta - target) (+ extra)
+__global__ void l2_adj_kernel(const float* __restrict__ d, const float* __restrict__ t,
+                              size_t per_item, int batch, const double* __restrict__ loss_bar,
+                              const float* __restrict__ extra, float* __restrict__ out) {
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= per_item * batch) return;
+  const int b = (int)(v / per_item);
+  float g = 2.f * (float)loss_bar[b] * (d[v] - t[v]);
+  if (extra) g += extra[v];
+  out[v] = g;
+}
+
+// ---------------------------------------------------------------- FP64 reductions
+__device__ __forceinline__ double block_sum_fixed(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+constexpr int RED_ITEMS = 16;
+constexpr int RED_TILE = TB * RED_ITEMS;
+
+// partial[b * nblk + blk] = sum over the tile of (a - c)^2 (c nullable), FP64 accumulation.
+__global__ __launch_bounds__(TB) void sumsq_partial_kernel(const float* __restrict__ a,
+                                                           const float* __restrict__ c,
+                                                           size_t per_item, int nblk,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[TB];
+  const int b = blockIdx.y;
+  const size_t base = (size_t)b * per_item + (size_t)blockIdx.x * RED_TILE;
+  const size_t lim = (size_t)b * per_item + per_item;
+  double s = 0.0;
+  for (int i = 0; i < RED_ITEMS; ++i) {
+    const size_t j = base + (size_t)i * TB + threadIdx.x;
+    if (j < lim) {
+      const double d = c ? (double)a[j] - (double)c[j] : (double)a[j];
+      s += d * d;
+    }
+  }
+  const double tot = block_sum_fixed(s, sh);
+  if (threadIdx.x == 0) partial[(size_t)b * nblk + blockIdx.x] = tot;
+}
+
+// out[b] = sum_k partial[b][k] in a fixed order (one block per item)
+__global__ __launch_bounds__(TB) void sum_partials_kernel(const double* __restrict__ partial,
+                                                          int nblk, double* __restrict__ out) {
+  __shared__ double sh[TB];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += TB) s += partial[(size_t)b * nblk + k];
+  const double tot = block_sum_fixed(s, sh);
+  if (threadIdx.x == 0) out[b] = tot;
+}
+
+// loss_out[b] = (prior_weight * prior + data, prior, data)
+__global__ void finalize_loss_kernel(const double* __restrict__ prior, const double* __restrict__ data,
+                                     const double* __restrict__ prm, int batch,
+                                     double* __restrict__ loss_out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  loss_out[3 * b + 0] = prm[b * 6 + 5] * prior[b] + data[b];
+  loss_out[3 * b + 1] = prior[b];
+  loss_out[3 * b + 2] = data[b];
+}
+
+// ---------------------------------------------------------------- modes
+// P s on the stored half spectrum: on kz in {0, n/2} average with conj of the (-i, -j)
+// partner; zero k = 0. Also the prior partial sums 0.5 * w * |P s|^2 / S.
+__global__ __launch_bounds__(TB) void project_prior_kernel(const float2* __restrict__ s, int n,
+                                                           const float* __restrict__ inv_var,
+                                                           float2* __restrict__ ps, int nblk,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[TB];
+  const int nh = n / 2 + 1;
+  const size_t per = (size_t)n * n * nh;
+  const int b = blockIdx.y;
+  const float2* sb = s + b * per;
+  double acc = 0.0;
+  for (int i = 0; i < RED_ITEMS; ++i) {
+    const size_t e = (size_t)blockIdx.x * RED_TILE + (size_t)i * TB + threadIdx.x;
+    if (e >= per) continue;
+    const int kz = (int)(e % nh);
+    const int iy = (int)((e / nh) % n);
+    const int ix = (int)(e / ((size_t)nh * n));
+    float2 v = sb[e];
+    double w = 2.0;
+    if (kz == 0 || kz == n / 2) {
+      const int jx = (n - ix) & (n - 1), jy = (n - iy) & (n - 1);
+      const float2 q = sb[((size_t)jx * n + jy) * nh + kz];
+      v = make_float2(0.5f * (v.x + q.x), 0.5f * (v.y - q.y));
+      w = 1.0;
+    }
+    if (e == 0) v = make_float2(0.f, 0.f);
+    ps[b * per + e] = v;
+    acc += 0.5 * w * ((double)v.x * v.x + (double)v.y * v.y) * (double)inv_var[e];
+  }
+  const double tot = block_sum_fixed(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)b * nblk + blockIdx.x] = tot;
+}
+
+template <int H>
+void mlp_fwd_t(const float* d0, const float* d1, const float* d2, size_t n, const float* w,
+               float* mass, hipStream_t s) {
+  mlp_fwd_kernel<H><<<(unsigned)((n + TB - 1) / TB), TB, 0, s>>>(d0, d1, d2, n, w, mass);
+}
+template <int H>
+void mlp_bwd_t(const float* d0, const float* d1, const float* d2, size_t n, const float* w,
+               const float* mbar, float* g0, float* g12, float* g2, hipStream_t s) {
+  mlp_bwd_kernel<H><<<(unsigned)((n + TB - 1) / TB), TB, 0, s>>>(d0, d1, d2, n, w, mbar, g0, g12,
+                                                                 g2);
+}
+
+}  // namespace
+
+size_t mlp_weight_floats(int H) { return (size_t)6 * H + (size_t)H * H + 1; }
+
+int launch_mlp_fwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                   const float* w, float* mass, hipStream_t s) {
+  switch (H) {
+    case 8: mlp_fwd_t<8>(d0, d1, d2, n, w, mass, s); return 0;
+    case 16: mlp_fwd_t<16>(d0, d1, d2, n, w, mass, s); return 0;
+    case 32: mlp_fwd_t<32>(d0, d1, d2, n, w, mass, s); return 0;
+    case 64: mlp_fwd_t<64>(d0, d1, d2, n, w, mass, s); return 0;
+    default: return -1;
+  }
+}
+
+int launch_mlp_bwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                   const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                   hipStream_t s) {
+  switch (H) {
+    case 8: mlp_bwd_t<8>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 16: mlp_bwd_t<16>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 32: mlp_bwd_t<32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 64: mlp_bwd_t<64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    default: return -1;
+  }
+}
+
+static unsigned grid1(size_t n) { return (unsigned)((n + TB - 1) / TB); }
+
+void launch_target_x(const float* mtr, size_t per_item, int batch, const double* prm, float* xd,
+                     hipStream_t s) {
+  target_x_kernel<<<grid1(per_item * batch), TB, 0, s>>>(mtr, per_item, batch, prm, xd);
+}
+void launch_residual(const float* mr, const float* xd, size_t per_item, int batch,
+                     const double* prm, float* r, hipStream_t s) {
+  residual_kernel<<<grid1(per_item * batch), TB, 0, s>>>(mr, xd, per_item, batch, prm, r);
+}
+void launch_mrbar(const float* rbar, const float* mr, size_t per_item, int batch,
+                  const double* prm, float* out, hipStream_t s) {
+  mrbar_kernel<<<grid1(per_item * batch), TB, 0, s>>>(rbar, mr, per_item, batch, prm, out);
+}
+void launch_l2_adj(const float* d, const float* t, size_t per_item, int batch,
+                   const double* loss_bar, const float* extra, float* out, hipStream_t s) {
+  l2_adj_kernel<<<grid1(per_item * batch), TB, 0, s>>>(d, t, per_item, batch, loss_bar, extra, out);
+}
+
+int reduce_blocks(size_t per_item) { return (int)((per_item + RED_TILE - 1) / RED_TILE); }
+
+// out[b] = sum over item b of (a - c)^2, deterministic.
+void launch_sumsq(const float* a, const float* c, size_t per_item, int batch, double* partial,
+                  double* out, hipStream_t s) {
+  const int nblk = reduce_blocks(per_item);
+  sumsq_partial_kernel<<<dim3(nblk, batch), TB, 0, s>>>(a, c, per_item, nblk, partial);
+  sum_partials_kernel<<<batch, TB, 0, s>>>(partial, nblk, out);
+}
+
+void launch_project_prior(const float2* modes, int n, int batch, const float* inv_var, float2* ps,
+                          double* partial, double* prior_out, hipStream_t s) {
+  const size_t per = (size_t)n * n * (n / 2 + 1);
+  const int nblk = reduce_blocks(per);
+  project_prior_kernel<<<dim3(nblk, batch), TB, 0, s>>>(modes, n, inv_var, ps, nblk, partial);
+  sum_partials_kernel<<<batch, TB, 0, s>>>(partial, nblk, prior_out);
+}
+
+void launch_finalize_loss(const double* prior, const double* data, const double* prm, int batch,
+                          double* loss_out, hipStream_t s) {
+  finalize_loss_kernel<<<(batch + 63) / 64, 64, 0, s>>>(prior, data, prm, batch, loss_out);
+}
+
+}  // namespace pmr

@@ -1,0 +1,823 @@
+// C ABI of libpmr: configuration, workspace plan, growth factors and the forward/adjoint
+// schedules. All device work is enqueued on the context's stream; nothing here allocates
+// device memory.
+#include "../../include/pmr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pmr_internal.h"
+
+using namespace pmr;
+
+namespace {
+
+// ---------------------------------------------------------------- growth (host, FP64)
+// Flat LambdaCDM: E(a) = sqrt(Om a^-3 + 1 - Om); D = C E(a) int_0^a da' / (a' E)^3,
+// D(1) = 1; G_p = a^3 E dD/da. The integral is taken over t = sqrt(a') (a' = t^2), which
+// makes the integrand smooth at 0, with adaptive Simpson.
+struct Cosmo {
+  double om;
+  double E(double a) const { return std::sqrt(om / (a * a * a) + 1.0 - om); }
+  double dE(double a) const { return -1.5 * om / (a * a * a * a) / E(a); }
+  double integrand_t(double t) const {
+    if (t <= 0.0) return 0.0;
+    const double a = t * t;
+    const double ae = a * E(a);
+    return 2.0 * t / (ae * ae * ae);
+  }
+  double simpson(double lo, double hi, double flo, double fmid, double fhi, double whole,
+                 double tol, int depth) const {
+    const double mid = 0.5 * (lo + hi);
+    const double lm = 0.5 * (lo + mid), rm = 0.5 * (mid + hi);
+    const double flm = integrand_t(lm), frm = integrand_t(rm);
+    const double left = (mid - lo) / 6.0 * (flo + 4.0 * flm + fmid);
+    const double right = (hi - mid) / 6.0 * (fmid + 4.0 * frm + fhi);
+    const double diff = left + right - whole;
+    if (depth <= 0 || std::fabs(diff) <= 15.0 * tol) return left + right + diff / 15.0;
+    return simpson(lo, mid, flo, flm, fmid, left, 0.5 * tol, depth - 1) +
+           simpson(mid, hi, fmid, frm, fhi, right, 0.5 * tol, depth - 1);
+  }
+  double I(double a) const {
+    const double hi = std::sqrt(a);
+    const double f0 = integrand_t(0.0), f1 = integrand_t(0.5 * hi), f2 = integrand_t(hi);
+    const double whole = hi / 6.0 * (f0 + 4.0 * f1 + f2);
+    return simpson(0.0, hi, f0, f1, f2, whole, 1e-15, 40);
+  }
+  double norm() const { return E(1.0) * I(1.0); }
+  double D(double a) const { return E(a) * I(a) / norm(); }
+  double Gp(double a) const {
+    const double dD = (dE(a) * I(a) + 1.0 / (a * a * a * E(a) * E(a))) / norm();
+    return a * a * a * E(a) * dD;
+  }
+};
+
+#define HIPC(c, call)                                        \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess && (c)->status == PMR_OK) (c)->status = PMR_E_HIP; \
+  } while (0)
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+int ilog2(size_t v) {
+  int l = 0;
+  while (((size_t)1 << l) < v) ++l;
+  return l;
+}
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct pmr_ctx {
+  pmr_config cfg;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int status;       // sticky error
+  int have_prior, have_mlp, have_target, have_loss, xd_dirty, fwd_done;
+  // sizes
+  int B, np, nm, no, n, H, k;
+  size_t np3, nm3, no3, cp, cm, co, cmax;
+  int log_np3, log_nm, log_no;
+  int key_bits_m, key_bits_o;
+  // factors
+  double D0, Gp0;
+  std::vector<double> kick, drift;
+  float mass_m, mass_o;
+  // device buffers
+  float* inv_var;
+  float* mlp_w;
+  float* target;
+  double* params;
+  float* xd;
+  float2* ps;
+  double* xs;   // position slots [S][B][3][np3]
+  int n_xslots;
+  double* ckx;  // checkpoints [nck][B][3][np3]
+  float* ckp;
+  int n_ck;
+  float* p;     // [B][3][np3]
+  float* F;     // force slots [SF][B][3][nm3]
+  uint32_t* ids;   // sort slots [SF][B*np3]
+  uint32_t* rows;  // [SF][B*nm*nm + 1]
+  int n_fslots;
+  uint32_t* keys;
+  uint32_t* keys_sorted;
+  void* sort_scratch;
+  size_t sort_scratch_bytes;
+  uint32_t* ids_o;
+  uint32_t* rows_o;
+  float* dens;   // [B][nm3]
+  float2* cA;    // [B][cmax]
+  float2* cB;    // [B][3][cmax]
+  float* psi;    // [B][3][np3]
+  float* delta_f;  // [B][no3]
+  float* dR;       // [2][B][no3]
+  float* mass;
+  float* MR;
+  float* r;
+  float* rs;
+  float* xbar;
+  float* pbar;
+  float* Fbar;   // [B][3][nm3]
+  float* dbar;   // [B][nm3]
+  float* ob;     // [4][B][no3]
+  double* partial;
+  double* prior;
+  double* data;
+};
+
+namespace {
+
+int validate(const pmr_config* c) {
+  if (!c) return PMR_E_INVALID;
+  if (c->batch < 1 || c->n_steps < 1 || c->ckpt_every < 0) return PMR_E_INVALID;
+  if (!pow2_in(c->n_part, 16, 512) || !pow2_in(c->n_mesh, 16, 512) || !pow2_in(c->n_out, 16, 512))
+    return PMR_E_SHAPE;
+  if (c->n_mesh != c->n_part && c->n_mesh != 2 * c->n_part) return PMR_E_SHAPE;
+  if (c->n_out != c->n_part && c->n_out != c->n_mesh) return PMR_E_SHAPE;
+  if (c->loss_kind != PMR_LOSS_DENSITY_L2 && c->loss_kind != PMR_LOSS_LOGNORMAL) return PMR_E_INVALID;
+  if (c->loss_kind == PMR_LOSS_LOGNORMAL && c->mlp_hidden != 8 && c->mlp_hidden != 16 &&
+      c->mlp_hidden != 32 && c->mlp_hidden != 64)
+    return PMR_E_SHAPE;
+  if (c->precision != PMR_FP32 && c->precision != PMR_MIXED) return PMR_E_INVALID;
+  if (!(c->box > 0) || !(c->a0 > 0) || !(c->a1 > c->a0) || !(c->omega_m > 0) || !(c->omega_m <= 1))
+    return PMR_E_INVALID;
+  if (!(c->R1 >= 0) || !(c->R2 >= 0)) return PMR_E_INVALID;
+  const double np3 = (double)c->n_part * c->n_part * c->n_part;
+  const double nm3 = (double)c->n_mesh * c->n_mesh * c->n_mesh;
+  const double no3 = (double)c->n_out * c->n_out * c->n_out;
+  if (c->batch * np3 >= 2147483648.0) return PMR_E_SHAPE;  // int particle index
+  if (c->batch * nm3 > 4294967296.0 || c->batch * no3 > 4294967296.0) return PMR_E_SHAPE;
+  return PMR_OK;
+}
+
+// Workspace plan: a bump allocator that either measures (base == nullptr) or assigns.
+struct Plan {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+void plan(pmr_ctx* c, Plan& P) {
+  const size_t B = c->B;
+  c->inv_var = P.take<float>(c->cp);
+  c->mlp_w = P.take<float>(mlp_weight_floats(c->H > 0 ? c->H : 8));
+  c->target = P.take<float>(B * c->no3);
+  c->params = P.take<double>(B * 6);
+  c->xd = P.take<float>(B * c->no3);
+  c->ps = P.take<float2>(B * c->cp);
+  c->xs = P.take<double>((size_t)c->n_xslots * B * 3 * c->np3);
+  c->ckx = P.take<double>((size_t)c->n_ck * B * 3 * c->np3);
+  c->ckp = P.take<float>((size_t)c->n_ck * B * 3 * c->np3);
+  c->p = P.take<float>(B * 3 * c->np3);
+  c->F = P.take<float>((size_t)c->n_fslots * B * 3 * c->nm3);
+  c->ids = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
+  c->rows = P.take<uint32_t>((size_t)c->n_fslots * (B * c->nm * c->nm + 1));
+  c->keys = P.take<uint32_t>(B * c->np3);
+  c->keys_sorted = P.take<uint32_t>(B * c->np3);
+  {
+    const size_t sm = sort_scratch_bytes((int)(B * c->np3), c->key_bits_m);
+    const size_t so = sort_scratch_bytes((int)(B * c->np3), c->key_bits_o);
+    c->sort_scratch_bytes = sm > so ? sm : so;
+  }
+  c->sort_scratch = P.take<char>(c->sort_scratch_bytes);
+  c->ids_o = P.take<uint32_t>(B * c->np3);
+  c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
+  c->dens = P.take<float>(B * c->nm3);
+  c->cA = P.take<float2>(B * c->cmax);
+  c->cB = P.take<float2>(B * 3 * c->cmax);
+  c->psi = P.take<float>(B * 3 * c->np3);
+  c->delta_f = P.take<float>(B * c->no3);
+  c->dR = P.take<float>(2 * B * c->no3);
+  c->mass = P.take<float>(B * c->no3);
+  c->MR = P.take<float>(B * c->no3);
+  c->r = P.take<float>(B * c->no3);
+  c->rs = P.take<float>(B * c->no3);
+  c->xbar = P.take<float>(B * 3 * c->np3);
+  c->pbar = P.take<float>(B * 3 * c->np3);
+  c->Fbar = P.take<float>(B * 3 * c->nm3);
+  c->dbar = P.take<float>(B * c->nm3);
+  c->ob = P.take<float>(4 * B * c->no3);
+  const size_t nred = (size_t)reduce_blocks(c->cmax > c->no3 ? c->cmax : c->no3);
+  c->partial = P.take<double>(B * nred);
+  c->prior = P.take<double>(B);
+  c->data = P.take<double>(B);
+}
+
+void init_sizes(pmr_ctx* c, const pmr_config* cfg) {
+  c->cfg = *cfg;
+  c->B = cfg->batch;
+  c->np = cfg->n_part;
+  c->nm = cfg->n_mesh;
+  c->no = cfg->n_out;
+  c->n = cfg->n_steps;
+  c->H = cfg->loss_kind == PMR_LOSS_LOGNORMAL ? cfg->mlp_hidden : 0;
+  c->k = cfg->ckpt_every >= cfg->n_steps ? 0 : cfg->ckpt_every;
+  c->np3 = (size_t)c->np * c->np * c->np;
+  c->nm3 = (size_t)c->nm * c->nm * c->nm;
+  c->no3 = (size_t)c->no * c->no * c->no;
+  c->cp = (size_t)c->np * c->np * (c->np / 2 + 1);
+  c->cm = (size_t)c->nm * c->nm * (c->nm / 2 + 1);
+  c->co = (size_t)c->no * c->no * (c->no / 2 + 1);
+  c->cmax = c->cp > c->cm ? c->cp : c->cm;
+  if (c->co > c->cmax) c->cmax = c->co;
+  c->log_np3 = ilog2(c->np3);
+  c->log_nm = ilog2((size_t)c->nm);
+  c->log_no = ilog2((size_t)c->no);
+  c->key_bits_m = ilog2((size_t)c->B * c->nm3);
+  c->key_bits_o = ilog2((size_t)c->B * c->no3);
+  if (c->k == 0) {
+    c->n_xslots = c->n + 1;
+    c->n_fslots = c->n;
+    c->n_ck = 0;
+  } else {
+    c->n_xslots = c->k + 1;
+    c->n_fslots = c->k;
+    c->n_ck = (c->n + c->k - 1) / c->k;
+  }
+  c->mass_m = (float)std::pow((double)c->nm / c->np, 3);
+  c->mass_o = (float)std::pow((double)c->no / c->np, 3);
+}
+
+void init_factors(pmr_ctx* c) {
+  Cosmo cos{c->cfg.omega_m};
+  const int n = c->n;
+  std::vector<double> a(n + 1), D(n + 1), Gp(n + 1), Gph(n);
+  for (int i = 0; i <= n; ++i) {
+    a[i] = c->cfg.a0 + (c->cfg.a1 - c->cfg.a0) * (double)i / (double)n;
+    D[i] = cos.D(a[i]);
+    Gp[i] = cos.Gp(a[i]);
+  }
+  for (int i = 0; i < n; ++i) Gph[i] = cos.Gp(0.5 * (a[i] + a[i + 1]));
+  c->kick.resize(n);
+  c->drift.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const double glo = i == 0 ? Gp[0] : Gph[i - 1];
+    c->kick[i] = (Gph[i] - glo) / D[i];
+    c->drift[i] = (D[i + 1] - D[i]) / Gph[i];
+  }
+  c->D0 = D[0];
+  c->Gp0 = Gp[0];
+}
+
+int check(pmr_ctx* c) {
+  if (c->status != PMR_OK) return c->status;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) c->status = PMR_E_HIP;
+  return c->status;
+}
+
+// ---------------------------------------------------------------- pass helpers
+FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride) {
+  FieldMap m;
+  m.fpi = fpi;
+  m.item_stride = item_stride;
+  m.comp_stride = comp_stride;
+  return m;
+}
+
+XPassArgs xargs(pmr_ctx* c, int n) {
+  XPassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.batch = c->B;
+  a.box = c->cfg.box;
+  a.R1 = c->cfg.R1;
+  a.R2 = c->cfg.R2;
+  a.params = c->params;
+  return a;
+}
+
+size_t cplx(int n) { return (size_t)n * n * (n / 2 + 1); }
+
+// Real fields [B][ncomp][n^3] -> spectra in cB [B][3][cmax] (components 0..ncomp-1),
+// completing the z and y passes; the x pass is fused with the caller's operator.
+void r2c_zy(pmr_ctx* c, int n, int ncomp, const float* in, size_t in_item_stride,
+            size_t in_comp_stride, const float* in2, float a1, float a2, const double* scale,
+            float2* out, size_t out_item_stride, size_t out_comp_stride) {
+  const int fields = c->B * ncomp;
+  launch_zpass_r2c(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), in2, a1, a2, scale,
+                   out, fmap(ncomp, out_item_stride, out_comp_stride), c->stream);
+  launch_ypass(n, fields, out, fmap(ncomp, out_item_stride, out_comp_stride), false, c->stream);
+}
+
+// Spectra after the x pass -> real fields: inverse y, then c2r along z (with optional add).
+void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, size_t in_comp_stride,
+            float* out, size_t out_item_stride, size_t out_comp_stride, const float* add) {
+  const int fields = c->B * ncomp;
+  launch_ypass(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), true, c->stream);
+  launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), out,
+                   fmap(ncomp, out_item_stride, out_comp_stride), add, c->stream);
+}
+
+// Gaussian smoothing of a real field [B][n^3] on R (per item, params[param_index]).
+void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, const float* add,
+            const double* scale = nullptr, float a1 = 1.f) {
+  const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  r2c_zy(c, n, 1, in, n3, 0, nullptr, a1, 0.f, scale, c->cA, cn, 0);
+  XPassArgs a = xargs(c, n);
+  a.n_in = 1;
+  a.n_out = 1;
+  a.in[0] = c->cA;
+  a.out[0] = c->cB;
+  a.in_item_stride = cn;
+  a.out_item_stride = cn;
+  a.param_index = param_index;
+  launch_xpass(XOP_GAUSS, a, c->stream);
+  c2r_yz(c, n, 1, c->cB, cn, 0, out, n3, 0, add);
+}
+
+// ---------------------------------------------------------------- PM pieces
+double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
+float* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * 3 * c->nm3; }
+uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
+uint32_t* rowslot(pmr_ctx* c, int s) { return c->rows + (size_t)s * (c->B * c->nm * c->nm + 1); }
+int xs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
+int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
+
+// One forward PM step i: sort x_i, paint, force, kick + drift (keys of x_{i+1} emitted on
+// the force mesh, or on the output mesh after the last step).
+void pm_step(pmr_ctx* c, int i) {
+  const int B = c->B;
+  const int total = (int)(B * c->np3);
+  const int xsl = xs_of(c, i);
+  const int fsl = fs_of(c, i);
+  double* x = xslot(c, xsl);
+  double* xn = xslot(c, xsl + 1);
+  launch_sort(c->keys, total, c->key_bits_m, c->keys_sorted, idslot(c, fsl), c->sort_scratch,
+              c->stream);
+  launch_row_start(c->keys_sorted, total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl), c->stream);
+  const double scale_m = (double)c->nm / c->cfg.box;
+  launch_paint_mass(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->mass_m,
+                    1.f, c->dens, c->stream);
+  const size_t cm = c->cm;
+  r2c_zy(c, c->nm, 1, c->dens, c->nm3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, cm, 0);
+  XPassArgs a = xargs(c, c->nm);
+  a.n_in = 1;
+  a.n_out = 3;
+  a.in[0] = c->cA;
+  for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cm;
+  a.in_item_stride = cm;
+  a.out_item_stride = 3 * cm;
+  launch_xpass(XOP_FORCE, a, c->stream);
+  float* F = fslot(c, fsl);
+  c2r_yz(c, c->nm, 3, c->cB, 3 * cm, cm, F, 3 * c->nm3, c->nm3, nullptr);
+  const int key_nm = (i == c->n - 1) ? c->no : c->nm;
+  launch_kick_drift(x, xn, c->p, F, c->keys, B, c->log_np3, c->nm, c->cfg.box, (float)c->kick[i],
+                    c->drift[i], key_nm, c->stream);
+}
+
+// Run forward steps [i0, i1) (positions x_{i0} in its slot, momenta in c->p), taking
+// checkpoints at segment starts when `take_ckpt`.
+void pm_run(pmr_ctx* c, int i0, int i1, bool take_ckpt) {
+  const size_t xbytes = c->B * 3 * c->np3 * sizeof(double);
+  const size_t pbytes = c->B * 3 * c->np3 * sizeof(float);
+  for (int i = i0; i < i1; ++i) {
+    if (c->k > 0 && i % c->k == 0) {
+      if (i > i0) HIPC(c, hipMemcpyAsync(xslot(c, 0), xslot(c, c->k), xbytes, hipMemcpyDeviceToDevice, c->stream));
+      if (take_ckpt) {
+        const int j = i / c->k;
+        HIPC(c, hipMemcpyAsync(c->ckx + (size_t)j * c->B * 3 * c->np3, xslot(c, 0), xbytes,
+                       hipMemcpyDeviceToDevice, c->stream));
+        HIPC(c, hipMemcpyAsync(c->ckp + (size_t)j * c->B * 3 * c->np3, c->p, pbytes,
+                       hipMemcpyDeviceToDevice, c->stream));
+      }
+    }
+    pm_step(c, i);
+  }
+}
+
+int final_xslot(pmr_ctx* c) { return c->k == 0 ? c->n : ((c->n - 1) % c->k) + 1; }
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+size_t pmr_workspace_bytes(const pmr_config* cfg) {
+  if (validate(cfg) != PMR_OK) return 0;
+  pmr_ctx c;
+  init_sizes(&c, cfg);
+  Plan P{nullptr, 0};
+  plan(&c, P);
+  return P.off;
+}
+
+int pmr_create(const pmr_config* cfg, void* workspace, size_t bytes, void* stream, pmr_ctx** out) {
+  if (!out) return PMR_E_INVALID;
+  *out = nullptr;
+  int st = validate(cfg);
+  if (st != PMR_OK) return st;
+  if (!workspace || ((uintptr_t)workspace & 255)) return PMR_E_WORKSPACE;
+  if (bytes < pmr_workspace_bytes(cfg)) return PMR_E_WORKSPACE;
+  pmr_ctx* c = new (std::nothrow) pmr_ctx();
+  if (!c) return PMR_E_INVALID;
+  init_sizes(c, cfg);
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = bytes;
+  c->status = PMR_OK;
+  Plan P{c->ws, 0};
+  plan(c, P);
+  init_factors(c);
+  *out = c;
+  return PMR_OK;
+}
+
+int pmr_set_stream(pmr_ctx* c, void* stream) {
+  if (!c) return PMR_E_INVALID;
+  c->stream = (hipStream_t)stream;
+  return PMR_OK;
+}
+
+int pmr_destroy(pmr_ctx* c) {
+  delete c;
+  return PMR_OK;
+}
+
+int pmr_set_prior(pmr_ctx* c, const float* inv_var) {
+  if (!c || !inv_var) return PMR_E_INVALID;
+  HIPC(c, hipMemcpyAsync(c->inv_var, inv_var, c->cp * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  c->have_prior = 1;
+  return check(c);
+}
+
+int pmr_set_mlp(pmr_ctx* c, const float* W1, const float* b1, const float* W2, const float* b2,
+                const float* W3, const float* b3) {
+  if (!c || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return PMR_E_INVALID;
+  if (c->H == 0) return PMR_E_STATE;
+  const int H = c->H;
+  float* w = c->mlp_w;
+  const size_t f = sizeof(float);
+  HIPC(c, hipMemcpyAsync(w, W1, 3 * H * f, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(w + 3 * H, b1, H * f, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(w + 4 * H, W2, (size_t)H * H * f, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(w + 4 * H + H * H, b2, H * f, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(w + 5 * H + H * H, W3, H * f, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(w + 6 * H + H * H, b3, f, hipMemcpyDeviceToDevice, c->stream));
+  c->have_mlp = 1;
+  return check(c);
+}
+
+int pmr_set_target(pmr_ctx* c, const float* target) {
+  if (!c || !target) return PMR_E_INVALID;
+  HIPC(c, hipMemcpyAsync(c->target, target, c->B * c->no3 * sizeof(float), hipMemcpyDeviceToDevice,
+                 c->stream));
+  c->have_target = 1;
+  c->xd_dirty = 1;
+  return check(c);
+}
+
+int pmr_set_loss(pmr_ctx* c, const pmr_loss_params* prm) {
+  if (!c || !prm) return PMR_E_INVALID;
+  std::vector<double> h(6 * (size_t)c->B);
+  for (int b = 0; b < c->B; ++b) {
+    const pmr_loss_params& q = prm[b];
+    if (!(q.sigma_N > 0) || !(q.M0 > 0 || c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) ||
+        !(q.R_mass >= 0) || !(q.R_sm >= 0) || !std::isfinite(q.mu) || !std::isfinite(q.prior_weight))
+      return PMR_E_INVALID;
+    h[6 * b + 0] = q.M0;
+    h[6 * b + 1] = q.mu;
+    h[6 * b + 2] = q.sigma_N;
+    h[6 * b + 3] = q.R_mass;
+    h[6 * b + 4] = q.R_sm;
+    h[6 * b + 5] = q.prior_weight;
+  }
+  // pageable source: the copy completes before this call returns
+  HIPC(c, hipMemcpyAsync(c->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  c->have_loss = 1;
+  c->xd_dirty = 1;
+  return check(c);
+}
+
+int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out) {
+  if (!c || !modes || !loss_out) return PMR_E_INVALID;
+  if (c->status != PMR_OK) return c->status;
+  if (!c->have_prior || !c->have_target || !c->have_loss) return PMR_E_STATE;
+  if (c->cfg.loss_kind == PMR_LOSS_LOGNORMAL && !c->have_mlp) return PMR_E_STATE;
+  const int B = c->B;
+  hipStream_t s = c->stream;
+  // H0: projection and prior
+  launch_project_prior((const float2*)modes, c->np, B, c->inv_var, c->ps, c->partial, c->prior, s);
+  // data term of the target (log-normal): x_data = log(G_Rmass * M_t + M0)
+  if (c->cfg.loss_kind == PMR_LOSS_LOGNORMAL && c->xd_dirty) {
+    smooth(c, c->no, c->target, 3, c->ob, nullptr);
+    launch_target_x(c->ob, c->no3, B, c->params, c->xd, s);
+    c->xd_dirty = 0;
+  }
+  // H1: Zel'dovich displacement on the particle lattice
+  {
+    const size_t cp = c->cp;
+    XPassArgs a = xargs(c, c->np);
+    a.n_in = 1;
+    a.n_out = 3;
+    a.in[0] = c->ps;
+    for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cp;
+    a.in_item_stride = cp;
+    a.out_item_stride = 3 * cp;
+    launch_xpass(XOP_ZA, a, s);
+    c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->psi, 3 * c->np3, c->np3, nullptr);
+    const int key_nm = c->n == 0 ? c->no : c->nm;
+    launch_za_init(c->psi, B, c->np, c->log_np3, c->cfg.box, 0.5 * (c->cfg.box / c->nm), c->D0,
+                   (float)c->Gp0, xslot(c, 0), c->p, c->keys, key_nm, s);
+  }
+  // H2-H7: the PM steps
+  pm_run(c, 0, c->n, true);
+  // H8: final paint on the output mesh
+  const int total = (int)(B * c->np3);
+  double* xn = xslot(c, final_xslot(c));
+  launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, s);
+  launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
+  launch_paint_mass(xn, c->ids_o, c->rows_o, B, c->log_np3, c->no, (double)c->no / c->cfg.box,
+                    c->mass_o, 1.f, c->delta_f, s);
+  // H9-H11: halo model and likelihood
+  if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
+    launch_sumsq(c->delta_f, c->target, c->no3, B, c->partial, c->data, s);
+    if (mass_out)
+      HIPC(c, hipMemcpyAsync(mass_out, c->delta_f, B * c->no3 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  } else {
+    const size_t no3 = c->no3, co = c->co;
+    r2c_zy(c, c->no, 1, c->delta_f, no3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, co, 0);
+    XPassArgs a = xargs(c, c->no);
+    a.n_in = 1;
+    a.n_out = 2;
+    a.in[0] = c->cA;
+    a.out[0] = c->cB;
+    a.out[1] = c->cB + co;
+    a.in_item_stride = co;
+    a.out_item_stride = 3 * co;
+    launch_xpass(XOP_GAUSS2, a, s);
+    c2r_yz(c, c->no, 2, c->cB, 3 * co, co, c->dR, no3, (size_t)B * no3, nullptr);
+    if (launch_mlp_fwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w,
+                       c->mass, s) != 0)
+      return PMR_E_SHAPE;
+    smooth(c, c->no, c->mass, 3, c->MR, nullptr);
+    launch_residual(c->MR, c->xd, no3, B, c->params, c->r, s);
+    smooth(c, c->no, c->r, 4, c->rs, nullptr);
+    launch_sumsq(c->rs, nullptr, no3, B, c->partial, c->data, s);
+    if (mass_out) HIPC(c, hipMemcpyAsync(mass_out, c->mass, B * no3 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  launch_finalize_loss(c->prior, c->data, c->params, B, loss_out, s);
+  c->fwd_done = 1;
+  return check(c);
+}
+
+int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void* grad) {
+  if (!c || !loss_bar || !grad) return PMR_E_INVALID;
+  if (c->status != PMR_OK) return c->status;
+  if (!c->fwd_done) return PMR_E_STATE;
+  const int B = c->B;
+  hipStream_t s = c->stream;
+  const size_t no3 = c->no3, co = c->co;
+  float* dbar_f = c->ob + 3 * (size_t)B * no3;
+  // H12-H13: likelihood, network and feature adjoints -> dbar_f
+  if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
+    launch_l2_adj(c->delta_f, c->target, no3, B, loss_bar, mass_bar, dbar_f, s);
+  } else {
+    float* o0 = c->ob;
+    float* o1 = c->ob + (size_t)B * no3;
+    float* o2 = c->ob + 2 * (size_t)B * no3;
+    smooth(c, c->no, c->rs, 4, o0, nullptr, loss_bar, 2.f);  // rbar = G_Rsm (2 loss_bar r_s)
+    launch_mrbar(o0, c->MR, no3, B, c->params, o1, s);       // MRbar
+    smooth(c, c->no, o1, 3, o2, mass_bar);                   // Mbar (+ mass_bar)
+    launch_mlp_bwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w, o2,
+                   o0, o1, dbar_f, s);
+    // g0 -> o0, g12 -> o1, g2 -> dbar_f (temporarily); feature adjoint:
+    // dbar_f = g0 + irfft(G1 rfft(g12) - G2 rfft(g2))
+    launch_zpass_r2c(c->no, B, o1, fmap(1, no3, 0), nullptr, 1.f, 0.f, nullptr, c->cB,
+                     fmap(1, 3 * co, 0), s);
+    launch_zpass_r2c(c->no, B, dbar_f, fmap(1, no3, 0), nullptr, 1.f, 0.f, nullptr, c->cB + co,
+                     fmap(1, 3 * co, 0), s);
+    launch_ypass(c->no, 2 * B, c->cB, fmap(2, 3 * co, co), false, s);
+    XPassArgs a = xargs(c, c->no);
+    a.n_in = 2;
+    a.n_out = 1;
+    a.in[0] = c->cB;
+    a.in[1] = c->cB + co;
+    a.out[0] = c->cA;
+    a.in_item_stride = 3 * co;
+    a.out_item_stride = co;
+    launch_xpass(XOP_FEAT_ADJ, a, s);
+    c2r_yz(c, c->no, 1, c->cA, co, 0, dbar_f, no3, 0, o0);
+  }
+  // H14: final-paint adjoint -> xbar_n, pbar = 0
+  const double* xn = xslot(c, final_xslot(c));
+  launch_adjoint_gather(xn, c->xbar, c->pbar, nullptr, dbar_f, B, c->log_np3, c->no, c->cfg.box,
+                        0.f, 0.f, c->mass_o, 1, s);
+  // H15: reverse PM steps (recomputing segments from checkpoints when needed)
+  const size_t cm = c->cm;
+  const double scale_m = (double)c->nm / c->cfg.box;
+  int resident_lo = c->k == 0 ? 0 : ((c->n - 1) / c->k) * c->k;  // first step held in slots
+  for (int i = c->n - 1; i >= 0; --i) {
+    if (c->k > 0 && i < resident_lo) {
+      const int j = (i / c->k) * c->k;
+      const size_t xbytes = B * 3 * c->np3 * sizeof(double);
+      const size_t pbytes = B * 3 * c->np3 * sizeof(float);
+      HIPC(c, hipMemcpyAsync(xslot(c, 0), c->ckx + (size_t)(j / c->k) * B * 3 * c->np3, xbytes,
+                     hipMemcpyDeviceToDevice, s));
+      HIPC(c, hipMemcpyAsync(c->p, c->ckp + (size_t)(j / c->k) * B * 3 * c->np3, pbytes,
+                     hipMemcpyDeviceToDevice, s));
+      launch_keys(xslot(c, 0), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys, s);
+      const int end = j + c->k < c->n ? j + c->k : c->n;
+      for (int q = j; q < end; ++q) pm_step(c, q);
+      resident_lo = j;
+    }
+    const int fsl = fs_of(c, i);
+    const double* x = xslot(c, xs_of(c, i));
+    const float K = (float)c->kick[i], Dr = (float)c->drift[i];
+    launch_paint_adj3(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->pbar,
+                      c->xbar, K, Dr, c->Fbar, s);
+    r2c_zy(c, c->nm, 3, c->Fbar, 3 * c->nm3, c->nm3, nullptr, 1.f, 0.f, nullptr, c->cB, 3 * cm, cm);
+    XPassArgs a = xargs(c, c->nm);
+    a.n_in = 3;
+    a.n_out = 1;
+    for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cm;
+    a.out[0] = c->cA;
+    a.in_item_stride = 3 * cm;
+    a.out_item_stride = cm;
+    launch_xpass(XOP_FORCE_ADJ, a, s);
+    c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
+    launch_adjoint_gather(x, c->xbar, c->pbar, fslot(c, fsl), c->dbar, B, c->log_np3, c->nm,
+                          c->cfg.box, K, Dr, c->mass_m, 0, s);
+  }
+  // H16: Zel'dovich adjoint and gradient assembly (with the prior)
+  {
+    const size_t cp = c->cp;
+    r2c_zy(c, c->np, 3, c->xbar, 3 * c->np3, c->np3, c->pbar, (float)c->D0, (float)c->Gp0, nullptr,
+           c->cB, 3 * cp, cp);
+    XPassArgs a = xargs(c, c->np);
+    a.n_in = 3;
+    a.n_out = 1;
+    for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cp;
+    a.out[0] = (float2*)grad;
+    a.in_item_stride = 3 * cp;
+    a.out_item_stride = cp;
+    a.aux_item_stride = cp;
+    a.proj_modes = c->ps;
+    a.inv_var = c->inv_var;
+    a.loss_bar = loss_bar;
+    launch_xpass(XOP_ZA_ADJ, a, s);
+  }
+  return check(c);
+}
+
+const char* pmr_status_string(int st) {
+  switch (st) {
+    case PMR_OK: return "ok";
+    case PMR_E_INVALID: return "invalid argument";
+    case PMR_E_SHAPE: return "unsupported shape";
+    case PMR_E_WORKSPACE: return "workspace too small or misaligned";
+    case PMR_E_HIP: return "HIP runtime error";
+    case PMR_E_STATE: return "call out of order or missing inputs";
+    default: return "unknown status";
+  }
+}
+
+long long pmr_debug_copy(pmr_ctx* c, int what, int step, void* dst) {
+  if (!c || !dst) return PMR_E_INVALID;
+  const size_t B = c->B;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (what) {
+    case PMR_DBG_X: {
+      if (step < 0 || step > c->n) return PMR_E_INVALID;
+      int sl;
+      if (c->k == 0) sl = step;
+      else {
+        const int lo = ((c->n - 1) / c->k) * c->k;
+        if (step < lo) return PMR_E_STATE;
+        sl = step - lo;
+      }
+      src = xslot(c, sl);
+      bytes = B * 3 * c->np3 * sizeof(double);
+      break;
+    }
+    case PMR_DBG_FORCE:
+    case PMR_DBG_SORT_IDS: {
+      if (step < 0 || step >= c->n) return PMR_E_INVALID;
+      int sl;
+      if (c->k == 0) sl = step;
+      else {
+        const int lo = ((c->n - 1) / c->k) * c->k;
+        if (step < lo) return PMR_E_STATE;
+        sl = step - lo;
+      }
+      if (what == PMR_DBG_FORCE) {
+        src = fslot(c, sl);
+        bytes = B * 3 * c->nm3 * sizeof(float);
+      } else {
+        src = idslot(c, sl);
+        bytes = B * c->np3 * sizeof(uint32_t);
+      }
+      break;
+    }
+    case PMR_DBG_DELTA_F: src = c->delta_f; bytes = B * c->no3 * sizeof(float); break;
+    case PMR_DBG_FEATURES: src = c->dR; bytes = 2 * B * c->no3 * sizeof(float); break;
+    case PMR_DBG_MASS_R: src = c->MR; bytes = B * c->no3 * sizeof(float); break;
+    case PMR_DBG_RES_S: src = c->rs; bytes = B * c->no3 * sizeof(float); break;
+    case PMR_DBG_XBAR0: src = c->xbar; bytes = B * 3 * c->np3 * sizeof(float); break;
+    case PMR_DBG_PBAR0: src = c->pbar; bytes = B * 3 * c->np3 * sizeof(float); break;
+    case PMR_DBG_DBAR_F: src = c->ob + 3 * B * c->no3; bytes = B * c->no3 * sizeof(float); break;
+    default: return PMR_E_INVALID;
+  }
+  HIPC(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+  const int st = check(c);
+  return st == PMR_OK ? (long long)bytes : st;
+}
+
+// ---------------------------------------------------------------- primitives
+int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream) {
+  if (!in || !out || batch < 1) return PMR_E_INVALID;
+  if (!pow2_in(n, 16, 512)) return PMR_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  float2* o = (float2*)out;
+  launch_zpass_r2c(n, batch, in, fmap(1, n3, 0), nullptr, 1.f, 0.f, nullptr, o, fmap(1, cn, 0), s);
+  launch_ypass(n, batch, o, fmap(1, cn, 0), false, s);
+  XPassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.batch = batch;
+  a.n_in = a.n_out = 1;
+  a.in[0] = o;
+  a.out[0] = o;
+  a.in_item_stride = a.out_item_stride = cn;
+  a.box = 1.0;
+  launch_xpass(XOP_FWD, a, s);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
+  if (!inout || !out || batch < 1) return PMR_E_INVALID;
+  if (!pow2_in(n, 16, 512)) return PMR_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  float2* d = (float2*)inout;
+  XPassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.batch = batch;
+  a.n_in = a.n_out = 1;
+  a.in[0] = d;
+  a.out[0] = d;
+  a.in_item_stride = a.out_item_stride = cn;
+  a.box = 1.0;
+  launch_xpass(XOP_INV, a, s);
+  launch_ypass(n, batch, d, fmap(1, cn, 0), true, s);
+  launch_zpass_c2r(n, batch, d, fmap(1, cn, 0), out, fmap(1, n3, 0), nullptr, s);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+size_t pmr_sort_scratch_bytes(int n_total, int n_mesh, int batch) {
+  if (n_total < 1 || !pow2_in(n_mesh, 16, 512) || batch < 1) return 0;
+  return sort_scratch_bytes(n_total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh)) +
+         2 * align256((size_t)n_total * sizeof(uint32_t));
+}
+
+int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
+                 uint32_t* keys_sorted, uint32_t* ids_sorted, uint32_t* row_start, void* scratch,
+                 size_t scratch_bytes, void* stream) {
+  if (!x || !keys_sorted || !ids_sorted || !row_start || !scratch || !(box > 0) || batch < 1)
+    return PMR_E_INVALID;
+  if (!pow2_in(n_part, 16, 512) || !pow2_in(n_mesh, 16, 512)) return PMR_E_SHAPE;
+  const size_t np3 = (size_t)n_part * n_part * n_part;
+  if ((double)batch * np3 >= 2147483648.0 ||
+      (double)batch * n_mesh * n_mesh * n_mesh > 4294967296.0)
+    return PMR_E_SHAPE;
+  const int total = (int)(batch * np3);
+  if (scratch_bytes < pmr_sort_scratch_bytes(total, n_mesh, batch)) return PMR_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* keys = (uint32_t*)scratch;
+  void* rest = (char*)scratch + 2 * align256((size_t)total * sizeof(uint32_t));
+  launch_keys(x, ilog2(np3), total, (double)n_mesh / box, n_mesh, keys, s);
+  launch_sort(keys, total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh), keys_sorted,
+              ids_sorted, rest, s);
+  launch_row_start(keys_sorted, total, ilog2((size_t)n_mesh), batch * n_mesh * n_mesh, row_start,
+                   s);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x,
+                  const uint32_t* ids_sorted, const uint32_t* row_start, float mass, float bias,
+                  float* out, void* stream) {
+  if (!x || !ids_sorted || !row_start || !out || !(box > 0) || batch < 1) return PMR_E_INVALID;
+  if (!pow2_in(n_part, 16, 512) || !pow2_in(n_mesh, 16, 512)) return PMR_E_SHAPE;
+  const size_t np3 = (size_t)n_part * n_part * n_part;
+  launch_paint_mass(x, ids_sorted, row_start, batch, ilog2(np3), n_mesh, (double)n_mesh / box,
+                    mass, bias, out, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal device/host helpers shared by the HIP translation units of libpmr.
+// gfx950 (CDNA4) only: 64-lane wavefronts, 160 KB LDS per CU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define PMR_WAVE 64
+
+namespace pmr {
+
+// ------------------------------------------------------------------ complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by +i (dir > 0) or -i (dir < 0)
+template <int DIR>
+__device__ __forceinline__ float2 cmul_i(float2 a) {
+  return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ------------------------------------------------------------------ k-space helpers
+// integer wavenumber of storage index i on an axis of n points (full axes)
+__device__ __forceinline__ int wavenumber(int i, int n) { return i <= n / 2 ? i : i - n; }
+
+// ------------------------------------------------------------------ CIC helpers
+// Lower-corner index and fraction of one coordinate, FP64 (bit-identical rule everywhere):
+// u = x * scale, fl = floor(u), i0 = (int)fl mod n, f = u - fl.
+__device__ __forceinline__ int cic_corner(double x, double scale, int n, double* frac) {
+  double u = x * scale;
+  double fl = floor(u);
+  *frac = u - fl;
+  int i = (int)fl;
+  i %= n;
+  if (i < 0) i += n;
+  return i;
+}
+
+__device__ __forceinline__ double wrap_box(double x, double box) {
+  return x - box * floor(x / box);
+}
+
+}  // namespace pmr
+
+// ------------------------------------------------------------------ launch declarations
+// (defined in the .hip files; all enqueue on `stream`, no synchronisation)
+namespace pmr {
+
+// Addressing of the fields of a batched pass: field f belongs to item f / fpi and is
+// component f % fpi of it.
+struct FieldMap {
+  int fpi;
+  size_t item_stride, comp_stride;  // elements (of the array's type)
+  __host__ __device__ size_t off(int f) const {
+    return (size_t)(f / fpi) * item_stride + (size_t)(f % fpi) * comp_stride;
+  }
+};
+
+// Kinds of fused k-space operation performed in the outermost-axis pass.
+enum XOp : int {
+  XOP_FWD = 0,        // forward transform only (completes an r2c); 1 in -> 1 out (spectrum)
+  XOP_INV = 1,        // inverse only, scaled by 1/n^3; 1 in (spectrum) -> 1 out
+  XOP_FORCE = 2,      // fwd, * i k_a / k^2 / n^3, inv; 1 in -> 3 out
+  XOP_FORCE_ADJ = 3,  // 3 in: fwd each, sum conj(i k_a / k^2) / n^3, inv; -> 1 out
+  XOP_GAUSS = 4,      // fwd, * exp(-k^2 R_b^2 / 2) / n^3, inv; 1 in -> 1 out (R per batch item)
+  XOP_GAUSS2 = 5,     // fwd, * exp(-k^2 R1^2/2)/n^3 and exp(-k^2 R2^2/2)/n^3, inv; 1 -> 2
+  XOP_FEAT_ADJ = 6,   // 2 in (A, B): fwd, (G1 A - G2 B)/n^3, inv; -> 1 out
+  XOP_ZA = 7,         // 1 in (projected modes, already spectral): * i k_a / k^2 / n^3, inv; -> 3
+  XOP_ZA_ADJ = 8,     // 3 in: fwd, gradient assembly with the prior term; -> caller's gradient
+};
+
+struct XPassArgs {
+  int n;            // points per axis
+  int batch;
+  int n_in, n_out;
+  const float2* in[3];
+  float2* out[3];
+  size_t in_item_stride, out_item_stride;  // complex elements between batch items
+  size_t aux_item_stride;                  // for proj_modes
+  double box;
+  double R1, R2;       // feature scales (XOP_GAUSS2 / XOP_FEAT_ADJ)
+  const double* params;  // device loss params [B][6] (XOP_GAUSS reads R at param_index)
+  int param_index;
+  // gradient assembly (XOP_ZA_ADJ)
+  const float2* proj_modes;  // P s
+  const float* inv_var;      // 1 / S(k), shared by all items
+  const double* loss_bar;    // [B]
+};
+
+// z pass r2c over `fields` fields; loaded value = a1*in (+ a2*in2) (* scale_dev[item])
+void launch_zpass_r2c(int n, int fields, const float* in, FieldMap im, const float* in2, float a1,
+                      float a2, const double* scale_dev, float2* out, FieldMap om, hipStream_t s);
+// z pass c2r (unnormalised); optional out += add (add uses the output map)
+void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* out, FieldMap om,
+                      const float* add, hipStream_t s);
+void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
+void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
+
+// cic.hip
+size_t sort_scratch_bytes(int n, int key_bits);
+void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
+                 uint32_t* ids_sorted, void* scratch, hipStream_t s);
+void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
+                      uint32_t* row_start, hipStream_t s);
+void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
+                 hipStream_t s);
+void launch_paint_mass(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
+                       int log_np3, int nm, double scale, float mass, float bias, float* out,
+                       hipStream_t s);
+void launch_paint_adj3(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
+                       int log_np3, int nm, double scale, const float* pbar, const float* xbar,
+                       float kick, float drift, float* out, hipStream_t s);
+void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
+                       int batch, int log_np3, int nm, double box, float kick, double drift,
+                       int key_nm, hipStream_t s);
+void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
+                           const float* dbar, int batch, int log_np3, int nm, double box,
+                           float kick, float drift, float mass, int final_mode, hipStream_t s);
+void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, int key_nm,
+                    hipStream_t s);
+
+// halo.hip
+size_t mlp_weight_floats(int H);
+int launch_mlp_fwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                   const float* w, float* mass, hipStream_t s);
+int launch_mlp_bwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                   const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                   hipStream_t s);
+void launch_target_x(const float* mtr, size_t per_item, int batch, const double* prm, float* xd,
+                     hipStream_t s);
+void launch_residual(const float* mr, const float* xd, size_t per_item, int batch,
+                     const double* prm, float* r, hipStream_t s);
+void launch_mrbar(const float* rbar, const float* mr, size_t per_item, int batch,
+                  const double* prm, float* out, hipStream_t s);
+void launch_l2_adj(const float* d, const float* t, size_t per_item, int batch,
+                   const double* loss_bar, const float* extra, float* out, hipStream_t s);
+int reduce_blocks(size_t per_item);
+void launch_sumsq(const float* a, const float* c, size_t per_item, int batch, double* partial,
+                  double* out, hipStream_t s);
+void launch_project_prior(const float2* modes, int n, int batch, const float* inv_var, float2* ps,
+                          double* partial, double* prior_out, hipStream_t s);
+void launch_finalize_loss(const double* prior, const double* data, const double* prm, int batch,
+                          double* loss_out, hipStream_t s);
+
+}  // namespace pmr

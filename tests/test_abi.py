@@ -1,0 +1,70 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol include/pmr.h declares,
+and validates configurations on the host (no device calls)."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+from paper_1805_02247_amd import _lib as L
+from paper_1805_02247_amd import api
+
+
+def _declared():
+    src = open(L.HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def test_status_strings():
+    lib = L.lib()
+    for st in (0, -1, -2, -3, -4, -6):
+        assert lib.pmr_status_string(st)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_part=24), dict(n_part=8), dict(n_mesh=64, n_part=16), dict(n_out=64),
+    dict(batch=0), dict(n_steps=0), dict(mlp_hidden=12), dict(box=0.0), dict(a1=0.05),
+    dict(ckpt_every=-1), dict(precision=7), dict(loss_kind=3), dict(n_part=512, n_mesh=512,
+                                                                     n_out=512, batch=32)])
+def test_invalid_configs_rejected(bad):
+    cfg = api.Config(**{**dict(n_part=16, n_mesh=16, n_out=16), **bad})
+    assert api.workspace_bytes(cfg) == 0
+    ctx = ctypes.c_void_p()
+    c = cfg.c()
+    assert L.lib().pmr_create(ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None,
+                              ctypes.byref(ctx)) != 0
+
+
+def test_workspace_plan_and_checks():
+    cfg = api.Config(batch=2, n_part=16, n_mesh=32, n_out=16, n_steps=3, mlp_hidden=8)
+    n = api.workspace_bytes(cfg)
+    assert n > 0 and n % 256 == 0
+    ctx = ctypes.c_void_p()
+    c = cfg.c()
+    lib = L.lib()
+    # misaligned or short workspace
+    assert lib.pmr_create(ctypes.byref(c), ctypes.c_void_p(256 + 8), n, None, ctypes.byref(ctx)) == -3
+    assert lib.pmr_create(ctypes.byref(c), ctypes.c_void_p(256), n - 1, None, ctypes.byref(ctx)) == -3
+    # checkpointing needs less memory than keeping every step
+    more = api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10))
+    less = api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
+                                          ckpt_every=2))
+    assert less < more
+
+
+def test_primitives_reject_bad_shapes_without_touching_memory():
+    lib = L.lib()
+    assert lib.pmr_fft_r2c(24, 1, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -2
+    assert lib.pmr_fft_c2r(16, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -1
+    assert lib.pmr_sort_scratch_bytes(1000, 24, 1) == 0
+    assert lib.pmr_cic_sort(16, 16, 1, 1.0, None, None, None, None, None, 0, None) == -1

@@ -1,0 +1,137 @@
+"""End-to-end GPU parity: forward model, loss and mode gradient against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cosmology as OC
+from oracle import model as OM
+import paper_1805_02247_amd as P
+from _gpu import DEV, cosine, rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0.1):
+    ocfg = OM.Config(box, n, nm, no, steps, loss_kind=kind)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    modes = [OM.linear_modes(synth.white_noise(seed + 10 * b, n), box, power) for b in range(B)]
+    w = synth.mlp_weights(3, hidden) if kind == OM.LOSS_LOGNORMAL else None
+    targets, params = [], []
+    for b in range(B):
+        st = OM.linear_modes(synth.white_noise(seed + 10 * b + 5, n), box, power)
+        if kind == OM.LOSS_LOGNORMAL:
+            t = OM.forward(ocfg, st, inv, np.ones((no,) * 3), OM.default_params(), w)["mass"]
+            prm = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=R_sm[b % len(R_sm)], mu=mu)
+        else:
+            t = OM.forward(ocfg, st, inv, np.zeros((no,) * 3), OM.default_params())["delta_f"]
+            prm = OM.default_params(prior_weight=0.0)
+        targets.append(t)
+        params.append(prm)
+    return ocfg, inv, modes, w, targets, params
+
+
+def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, kind=None):
+    B = len(modes)
+    n = ocfg.n_part
+    cfg = P.Config(batch=B, n_part=n, n_mesh=ocfg.n_mesh, n_out=ocfg.n_out, n_steps=ocfg.n_steps,
+                   mlp_hidden=hidden, box=ocfg.box, ckpt_every=ckpt,
+                   loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    if w is not None:
+        pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+    pm.set_target(torch.from_numpy(np.stack(targets).astype(np.float32)).reshape(B, -1))
+    pm.set_loss([P.LossParams(**p) for p in params])
+    m = torch.from_numpy(np.stack(modes).astype(np.complex64)).reshape(B, -1).to(DEV)
+    mass, loss = pm.forward(m)
+    xs = [pm.debug("x", i).cpu().numpy() for i in range(ocfg.n_steps + 1)] if ckpt == 0 else None
+    delta_f = pm.debug("delta_f").cpu().numpy()
+    g = pm.adjoint(torch.ones(B, dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    return dict(pm=pm, mass=mass.cpu().numpy(), loss=loss.cpu().numpy(), xs=xs,
+                delta_f=delta_f, grad=g.cpu().numpy(), xbar0=pm.debug("xbar0").cpu().numpy())
+
+
+def _compare(ocfg, inv, modes, w, targets, params, res, tol):
+    B = len(modes)
+    for b in range(B):
+        ref, G = OM.gradient(ocfg, modes[b], inv, targets[b], params[b], w)
+        out = {}
+        if res["xs"] is not None:
+            dx = 0.0
+            for i, xr in enumerate(ref["xs"]):
+                d = res["xs"][i][b] - xr
+                d = (d + ocfg.box / 2) % ocfg.box - ocfg.box / 2
+                dx = max(dx, np.abs(d).max() / (ocfg.box / ocfg.n_mesh))
+            out["max_dx_cells"] = dx
+        out["delta_f"] = rel_l2(res["delta_f"][b], ref["delta_f"].ravel())
+        out["loss"] = abs(res["loss"][b, 0] - ref["loss"]) / abs(ref["loss"])
+        out["prior"] = abs(res["loss"][b, 1] - ref["loss_prior"]) / abs(ref["loss_prior"])
+        g = res["grad"][b].reshape(G.shape)
+        out["grad_cos"] = cosine(g, G)
+        out["grad_rel"] = rel_l2(g, G)
+        if ref.get("mass") is not None:
+            out["mass"] = rel_l2(res["mass"][b], ref["mass"].ravel())
+        say(f"  item {b}: " + ", ".join(f"{k}={v:.3e}" for k, v in out.items()))
+        for k, lim in tol.items():
+            if k == "grad_cos":
+                assert out[k] >= lim, (k, out[k])
+            elif k in out:
+                assert out[k] <= lim, (k, out[k])
+
+
+TOL_FP32 = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "loss": 1e-4, "prior": 1e-5, "mass": 1e-4,
+            "grad_cos": 0.9999, "grad_rel": 1e-2}
+
+
+def test_density_l2_small_box():
+    """32^3 particles on a 32^3 mesh, L = 100 Mpc/h, 5 steps, density-L2 loss."""
+    require_gpu()
+    say("pipeline: density-L2 32^3")
+    prob = _problem(32, 32, 32, 100.0, 5, OM.LOSS_DENSITY_L2, 1)
+    res = _gpu_run(*prob)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_lognormal_batch_with_anneal_stages():
+    """Two items with different residual smoothing (R_sm = 0 and 4 Mpc/h), 32^3, H = 32."""
+    require_gpu()
+    say("pipeline: log-normal 32^3, B=2")
+    prob = _problem(32, 32, 32, 100.0, 4, OM.LOSS_LOGNORMAL, 2, hidden=32, R_sm=(0.0, 4.0))
+    res = _gpu_run(*prob, hidden=32)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_force_mesh_twice_particle_mesh():
+    """16^3 particles, 32^3 force mesh, 16^3 output mesh, 3 steps."""
+    require_gpu()
+    say("pipeline: 16^3 particles on 32^3 force mesh")
+    prob = _problem(16, 32, 16, 50.0, 3, OM.LOSS_LOGNORMAL, 1, hidden=8, R_sm=(1.0,))
+    res = _gpu_run(*prob)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_checkpointing_reproduces_stored_gradient_bitwise():
+    """ckpt_every = 2 recomputes steps from checkpoints; deterministic kernels make the
+    gradient identical to keeping every step."""
+    require_gpu()
+    say("pipeline: checkpoint every 2 vs keep all")
+    prob = _problem(16, 16, 16, 50.0, 5, OM.LOSS_LOGNORMAL, 2, hidden=8, R_sm=(2.0, 0.0))
+    a = _gpu_run(*prob, ckpt=0)
+    b = _gpu_run(*prob, ckpt=2)
+    c = _gpu_run(*prob, ckpt=3)
+    assert np.array_equal(a["loss"], b["loss"]) and np.array_equal(a["loss"], c["loss"])
+    assert np.array_equal(a["grad"], b["grad"]), np.abs(a["grad"] - b["grad"]).max()
+    assert np.array_equal(a["grad"], c["grad"])
+
+
+def test_run_to_run_bitwise():
+    require_gpu()
+    prob = _problem(32, 32, 32, 100.0, 3, OM.LOSS_LOGNORMAL, 1, hidden=16, R_sm=(2.0,))
+    a = _gpu_run(*prob, hidden=16)
+    b = _gpu_run(*prob, hidden=16)
+    assert np.array_equal(a["loss"], b["loss"])
+    assert np.array_equal(a["grad"], b["grad"])
+    assert np.array_equal(a["mass"], b["mass"])
