@@ -1,0 +1,177 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable PM forward model + adjoint on one MI355X.
+
+One bench step = one full gradient evaluation (pmr_forward + pmr_adjoint) of a batch:
+the Zel'dovich start, n PM steps, the halo model and log-normal loss, and every adjoint.
+The metric counts PM steps: value = n_steps * batch * K / T over K timed gradient
+evaluations (inputs resident in HBM before the timed region).
+
+Prints ONE JSON line. The FP64 oracle is used only in the cpu_baseline leg.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PM forward+adjoint steps/s at 128^3 & 256^3; % HBM roofline; err vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # L = 400 Mpc/h, 128^3 particles on a 128^3 mesh, 5 PM steps, 3-32-32-1 network, the
+    # residual-smoothing anneal stages R_sm = 4, 2, 1, 0 Mpc/h as the 4 batch items.
+    "cfg2_128": dict(batch=4, n_part=128, n_mesh=128, n_out=128, n_steps=5, mlp_hidden=32,
+                     precision=0, ckpt_every=0, box=400.0, R_sm=[4.0, 2.0, 1.0, 0.0]),
+    # L = 400 Mpc/h, 256^3 particles, 512^3 force mesh, 256^3 output, 10 steps, 3-64-64-1,
+    # checkpoint every 2 steps.
+    "cfg3_256": dict(batch=1, n_part=256, n_mesh=512, n_out=256, n_steps=10, mlp_hidden=64,
+                     precision=1, ckpt_every=2, box=400.0, R_sm=[2.0]),
+    # 32 realisations at L = 200 Mpc/h, 64^3 on 64^3, 5 steps.
+    "cfg4_64x32": dict(batch=32, n_part=64, n_mesh=64, n_out=64, n_steps=5, mlp_hidden=32,
+                       precision=0, ckpt_every=0, box=200.0, R_sm=[0.0]),
+}
+
+
+def make_context(w, dev):
+    import torch
+
+    import synth
+    import paper_1805_02247_amd as P
+    from paper_1805_02247_amd import cosmo
+
+    cfg = P.Config(batch=w["batch"], n_part=w["n_part"], n_mesh=w["n_mesh"], n_out=w["n_out"],
+                   n_steps=w["n_steps"], mlp_hidden=w["mlp_hidden"], precision=w["precision"],
+                   ckpt_every=w["ckpt_every"], box=w["box"], loss_kind=P.PMR_LOSS_LOGNORMAL)
+    B, n, box = cfg.batch, cfg.n_part, cfg.box
+    power = cosmo.linear_power(0.8, 0.2)
+    pm = P.PMContext(cfg, dev)
+    pm.set_prior(torch.from_numpy(cosmo.prior_inv_variance(n, box, power)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in synth.mlp_weights(3, cfg.mlp_hidden).items()})
+
+    def modes(seed0):
+        return torch.stack([torch.from_numpy(cosmo.modes_from_white_noise(
+            synth.white_noise(seed0 + b, n), box, power).reshape(-1)) for b in range(B)]).to(dev)
+
+    # data: the same pipeline at other seeds (target mass field)
+    pm.set_target(torch.ones(B, cfg.n_out ** 3, device=dev))
+    pm.set_loss(P.LossParams(M0=1.0))
+    target, _ = pm.forward(modes(1000))
+    M0 = [float(np.percentile(target[b].cpu().numpy(), 50)) for b in range(B)]
+    pm.set_target(target)
+    R = w["R_sm"]
+    pm.set_loss([P.LossParams(M0=M0[b], mu=0.0, sigma_N=0.5, R_mass=3.0, R_sm=R[b % len(R)])
+                 for b in range(B)])
+    return pm, modes(1)
+
+
+def cpu_baseline(w):
+    """FP64 oracle gradient of one batch item of the same workload (single thread)."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import cosmology as OC
+    from oracle import model as OM
+
+    n, box = w["n_part"], w["box"]
+    cfg = OM.Config(box, n, w["n_mesh"], w["n_out"], w["n_steps"])
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    s = OM.linear_modes(synth.white_noise(1, n), box, power)
+    mlp = synth.mlp_weights(3, w["mlp_hidden"])
+    # synthetic positive data field (the oracle's timing does not depend on its values)
+    tgt = np.exp(synth.unit_normal(7, (w["n_out"],) * 3))
+    prm = OM.default_params(M0=1.0, R_sm=w["R_sm"][0])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        OM.gradient(cfg, s, inv, tgt, prm, mlp)
+        dt = time.perf_counter() - t0
+    return {"value": w["n_steps"] / dt, "unit": "PM steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one batch item (of {w['batch']}): one FP64 gradient evaluation, "
+                      f"{n}^3 particles, {w['n_steps']} PM steps, {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2_128", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import torch
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[args.workload]
+    pm, modes = make_context(w, dev)
+    ones = torch.ones(w["batch"], dtype=torch.float64, device=dev)
+    grad = torch.empty(w["batch"], pm.n_modes, dtype=torch.complex64, device=dev)
+
+    def step():
+        pm.forward(modes, want_mass=False)
+        pm.adjoint(ones, out=grad)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # the kernel class with the largest event time in one untimed gradient evaluation
+    classes = ["paint", "paint3", "xpass_force", "xpass_force_adj", "ypass", "zpass",
+               "kick_drift", "adj_gather"]
+    probe = {}
+    for cls in classes:
+        pm.profile_begin(cls)
+        step()
+        probe[cls] = pm.profile_end()
+    dominant = max(classes, key=lambda c: probe[c][0])
+    # timed region, with the dominant class bracketed by HIP events on the library's stream
+    pm.profile_begin(dominant, max_launches=64 * (args.steps + 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    ev_ms, ev_n, ev_bytes = pm.profile_end()
+    pm_steps = w["n_steps"] * w["batch"] * args.steps
+    out = {
+        "metric": METRIC,
+        "value": pm_steps / T,
+        "unit": "PM steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if w["precision"] == 0 else "bf16+f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "batch": w["batch"], "n_part": w["n_part"],
+                   "n_mesh": w["n_mesh"], "n_out": w["n_out"], "pm_steps": w["n_steps"],
+                   "mlp_hidden": w["mlp_hidden"], "box_mpch": w["box"],
+                   "ckpt_every": w["ckpt_every"], "parallelism": "single GPU"},
+    }
+    avg_s = ev_ms * 1e-3 / max(ev_n, 1)
+    per_launch = ev_bytes / max(ev_n, 1)
+    achieved = per_launch / avg_s / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": dominant, "achieved": achieved,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": None, "avg_launch_us": avg_s * 1e6, "launches": ev_n,
+                       "alg_bytes_per_launch": per_launch,
+                       "share_of_step": ev_ms / (1e3 * T)}
+    out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,27 @@ enum {
 };
 long long pmr_debug_copy(pmr_ctx* ctx, int what, int step, void* dst);
 
+/* ---- event timing of one kernel class (measurement) ----
+ * Between pmr_profile_begin and pmr_profile_end, every launch of `kernel_class` enqueued by
+ * pmr_forward / pmr_adjoint on this context is bracketed by a pair of HIP events on the
+ * context stream (at most `max_launches` launches are recorded; events are created on the
+ * host at the first call). pmr_profile_end synchronises the stream and returns the summed
+ * event time, the number of launches and their summed algorithmic bytes (the compulsory
+ * HBM traffic of each launch: inputs read once, outputs written once). */
+enum {
+  PMR_PROF_NONE = 0,
+  PMR_PROF_PAINT = 1,             /* density paint on the force mesh (one channel) */
+  PMR_PROF_XPASS_FORCE = 2,       /* outermost-axis pass with the force operator, 1 -> 3 */
+  PMR_PROF_YPASS = 3,             /* middle-axis FFT passes */
+  PMR_PROF_ZPASS = 4,             /* contiguous-axis r2c / c2r passes */
+  PMR_PROF_KICK_DRIFT = 5,        /* readout + kick + drift + keys */
+  PMR_PROF_PAINT3 = 6,            /* three-channel adjoint paint */
+  PMR_PROF_XPASS_FORCE_ADJ = 7,   /* outermost-axis pass with the force adjoint, 3 -> 1 */
+  PMR_PROF_ADJ_GATHER = 8         /* step-adjoint gather */
+};
+int pmr_profile_begin(pmr_ctx* ctx, int kernel_class, int max_launches);
+int pmr_profile_end(pmr_ctx* ctx, double* total_ms, long long* launches, double* alg_bytes);
+
 /* ---- stand-alone hot-path primitives (device pointers, enqueued on `stream`) ---- */
 
 /* Unnormalised forward 3-D real FFT of `batch` fields [batch][n^3] -> [batch][n][n][n/2+1]

@@ -58,7 +58,12 @@ SIGNATURES = {
     "pmr_sort_scratch_bytes": (sz, [ci, ci, ci]),
     "pmr_cic_sort": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, vp, sz, vp]),
     "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, cf, cf, vp, vp]),
+    "pmr_profile_begin": (ci, [vp, ci, ci]),
+    "pmr_profile_end": (ci, [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_longlong),
+                             ctypes.POINTER(cd)]),
 }
+PROF = {"paint": 1, "xpass_force": 2, "ypass": 3, "zpass": 4, "kick_drift": 5, "paint3": 6,
+        "xpass_force_adj": 7, "adj_gather": 8}
 
 
 def lib():

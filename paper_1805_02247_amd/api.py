@@ -160,6 +160,17 @@ class PMContext:
         L.check(L.lib().pmr_adjoint(self._ctx, _ptr(loss_bar), _ptr(mass_bar), _ptr(out)))
         return out
 
+    def profile_begin(self, kernel_class, max_launches=4096):
+        """Start event timing of one kernel class (see PMR_PROF_* in pmr.h)."""
+        L.check(L.lib().pmr_profile_begin(self._ctx, L.PROF[kernel_class], int(max_launches)))
+
+    def profile_end(self):
+        """-> (total_ms, launches, algorithmic_bytes) since profile_begin (synchronises)."""
+        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        L.check(L.lib().pmr_profile_end(self._ctx, ctypes.byref(ms), ctypes.byref(n),
+                                        ctypes.byref(b)))
+        return ms.value, n.value, b.value
+
     def debug(self, what, step=0):
         """Copy an internal buffer of the last forward/adjoint (see PMR_DBG_* in pmr.h)."""
         cfg = self.cfg

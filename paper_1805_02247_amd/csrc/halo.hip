@@ -115,6 +115,251 @@ __global__ __launch_bounds__(TB) void mlp_bwd_kernel(const float* __restrict__ d
   g2[v] = fb2;
 }
 
+// ---------------------------------------------------------------- BF16 matrix-core network
+// Mixed precision: the H x H layer runs on v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32
+// accumulation); the 3 -> H and H -> 1 layers, biases, activations and the softplus stay
+// FP32 on the vector units. One wavefront owns 64 voxels (four 16-row blocks).
+// Operand layouts of the 16x16x32 instruction (lane l, j = 0..7, i = 0..3):
+//   A[m][k]: m = l % 16, k = 8 (l / 16) + j      B[k][n]: n = l % 16, k = 8 (l / 16) + j
+//   C[m][n]: n = l % 16, m = 4 (l / 16) + i
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// BF16 copies of W2 (row-major [n][k]) and W2^T, placed after the FP32 block.
+template <int H>
+struct WBf {
+  static constexpr size_t W2 = ((size_t)WOff<H>::SIZE * 4 + 15) / 16 * 16;  // byte offset
+  static constexpr size_t W2T = W2 + (size_t)H * H * 2;
+  static constexpr size_t BYTES = W2T + (size_t)H * H * 2;
+};
+
+template <int H>
+__global__ void mlp_prepare_bf16_kernel(float* w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= H * H) return;
+  const int n = t / H, k = t % H;
+  char* base = reinterpret_cast<char*>(w);
+  __bf16* w2 = reinterpret_cast<__bf16*>(base + WBf<H>::W2);
+  __bf16* w2t = reinterpret_cast<__bf16*>(base + WBf<H>::W2T);
+  const float v = w[WOff<H>::W2 + n * H + k];
+  w2[n * H + k] = (__bf16)v;
+  w2t[k * H + n] = (__bf16)v;
+}
+
+__device__ __forceinline__ float group16_sum(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
+template <int H>
+struct MfmaShape {
+  static constexpr int MB = 4, KB = H / 32, NB = H / 16;
+  static_assert(H % 32 == 0, "H multiple of 32");
+};
+
+// h1 fragments (A layout) for the 4 row blocks of this wave; returns false past the end.
+template <int H>
+__device__ __forceinline__ void h1_fragments(const float* sw, const float* __restrict__ d0,
+                                             const float* __restrict__ d1,
+                                             const float* __restrict__ d2, size_t v0, size_t n,
+                                             bf16x8_t (&a)[4][H / 32]) {
+  using O = WOff<H>;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const size_t v = v0 + mb * 16 + (l & 15);
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    if (v < n) {
+      f0 = d0[v];
+      f1 = d1[v];
+      f2 = d1[v] - d2[v];
+    }
+#pragma unroll
+    for (int kb = 0; kb < H / 32; ++kb) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = kb * 32 + 8 * (l >> 4) + j;
+        const float h = fmaxf(sw[O::W1 + 3 * k] * f0 + sw[O::W1 + 3 * k + 1] * f1 +
+                                  sw[O::W1 + 3 * k + 2] * f2 + sw[O::B1 + k],
+                              0.f);
+        a[mb][kb][j] = (__bf16)h;
+      }
+    }
+  }
+}
+
+template <int H>
+__device__ __forceinline__ void load_b(const __bf16* __restrict__ m, bf16x8_t (&b)[H / 32][H / 16]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int kb = 0; kb < H / 32; ++kb)
+#pragma unroll
+    for (int nb = 0; nb < H / 16; ++nb)
+      b[kb][nb] = *reinterpret_cast<const bf16x8_t*>(m + (size_t)(nb * 16 + (l & 15)) * H + kb * 32 +
+                                                     8 * (l >> 4));
+}
+
+template <int H>
+__device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[4][H / 32],
+                                           const bf16x8_t (&b)[H / 32][H / 16],
+                                           floatx4_t (&c)[4][H / 16]) {
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < H / 16; ++nb) {
+      floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < H / 32; ++kb)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb][kb], b[kb][nb], acc, 0, 0, 0);
+      c[mb][nb] = acc;
+    }
+}
+
+// y for the 4 rows (4 (l/16) + i) of row block mb, on every lane of the 16-lane group.
+template <int H>
+__device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[4][H / 16], int mb,
+                                       float (&y)[4]) {
+  using O = WOff<H>;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float p = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < H / 16; ++nb) {
+      const int nn = nb * 16 + (l & 15);
+      p += sw[O::W3 + nn] * fmaxf(c[mb][nb][i] + sw[O::B2 + nn], 0.f);
+    }
+    y[i] = group16_sum(p) + sw[O::B3];
+  }
+}
+
+template <int H>
+__global__ __launch_bounds__(TB) void mlp_fwd_mfma_kernel(const float* __restrict__ d0,
+                                                          const float* __restrict__ d1,
+                                                          const float* __restrict__ d2, size_t n,
+                                                          const float* __restrict__ w,
+                                                          float* __restrict__ mass) {
+  using O = WOff<H>;
+  __shared__ float sw[O::SIZE];
+  load_weights<H>(sw, w);
+  const int l = threadIdx.x & 63;
+  const size_t v0 = ((size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6)) * 64;
+  bf16x8_t a[4][H / 32];
+  bf16x8_t b[H / 32][H / 16];
+  floatx4_t c[4][H / 16];
+  h1_fragments<H>(sw, d0, d1, d2, v0, n, a);
+  load_b<H>(reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(w) + WBf<H>::W2), b);
+  mfma_layer<H>(a, b, c);
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    float y[4];
+    layer3<H>(sw, c, mb, y);
+    const int i = l & 15;
+    if (i < 4) {
+      const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
+      const float yi = i == 0 ? y[0] : i == 1 ? y[1] : i == 2 ? y[2] : y[3];
+      if (v < n) mass[v] = softplus_f(yi);
+    }
+  }
+}
+
+template <int H>
+__global__ __launch_bounds__(TB) void mlp_bwd_mfma_kernel(const float* __restrict__ d0,
+                                                          const float* __restrict__ d1,
+                                                          const float* __restrict__ d2, size_t n,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ mbar,
+                                                          float* __restrict__ g0,
+                                                          float* __restrict__ g12,
+                                                          float* __restrict__ g2) {
+  using O = WOff<H>;
+  __shared__ float sw[O::SIZE];
+  __shared__ __bf16 tile[TB / 64][64 * H];
+  load_weights<H>(sw, w);
+  const int l = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const size_t v0 = ((size_t)blockIdx.x * (TB / 64) + wv) * 64;
+  const char* wb = reinterpret_cast<const char*>(w);
+  floatx4_t c[4][H / 16];
+  {
+    bf16x8_t a[4][H / 32];
+    bf16x8_t b[H / 32][H / 16];
+    h1_fragments<H>(sw, d0, d1, d2, v0, n, a);
+    load_b<H>(reinterpret_cast<const __bf16*>(wb + WBf<H>::W2), b);
+    mfma_layer<H>(a, b, c);
+  }
+  __bf16* T = tile[wv];
+  // a2bar = ybar W3 [a2 > 0], stored (BF16) as a 64 x H tile for the transposed read
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    float y[4];
+    layer3<H>(sw, c, mb, y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = mb * 16 + 4 * (l >> 4) + i;
+      const size_t v = v0 + r;
+      const float yb = v < n ? mbar[v] * sigmoid_f(y[i]) : 0.f;
+#pragma unroll
+      for (int nb = 0; nb < H / 16; ++nb) {
+        const int nn = nb * 16 + (l & 15);
+        const float a2 = c[mb][nb][i] + sw[O::B2 + nn];
+        T[r * H + nn] = (__bf16)(a2 > 0.f ? yb * sw[O::W3 + nn] : 0.f);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  // h1bar = a2bar W2 on the matrix cores
+  {
+    bf16x8_t a[4][H / 32];
+    bf16x8_t b[H / 32][H / 16];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int kb = 0; kb < H / 32; ++kb)
+        a[mb][kb] = *reinterpret_cast<const bf16x8_t*>(T + (mb * 16 + (l & 15)) * H + kb * 32 +
+                                                       8 * (l >> 4));
+    load_b<H>(reinterpret_cast<const __bf16*>(wb + WBf<H>::W2T), b);
+    mfma_layer<H>(a, b, c);
+  }
+  // a1bar = h1bar [a1 > 0]; fbar = W1^T a1bar (rows of the C layout)
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
+      float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+      if (v < n) {
+        f0 = d0[v];
+        f1 = d1[v];
+        f2 = d1[v] - d2[v];
+      }
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < H / 16; ++nb) {
+        const int k = nb * 16 + (l & 15);
+        const float a1 = sw[O::W1 + 3 * k] * f0 + sw[O::W1 + 3 * k + 1] * f1 +
+                         sw[O::W1 + 3 * k + 2] * f2 + sw[O::B1 + k];
+        const float hb = a1 > 0.f ? c[mb][nb][i] : 0.f;
+        p0 += sw[O::W1 + 3 * k] * hb;
+        p1 += sw[O::W1 + 3 * k + 1] * hb;
+        p2 += sw[O::W1 + 3 * k + 2] * hb;
+      }
+      p0 = group16_sum(p0);
+      p1 = group16_sum(p1);
+      p2 = group16_sum(p2);
+      if ((l & 15) == i && v < n) {
+        g0[v] = p0;
+        g12[v] = p1 + p2;
+        g2[v] = p2;
+      }
+    }
+  }
+}
+
 // x_data = log(MtR + M0)
 __global__ void target_x_kernel(const float* __restrict__ mtr, size_t per_item, int batch,
                                 const double* __restrict__ prm, float* __restrict__ xd) {
@@ -270,7 +515,51 @@ void mlp_bwd_t(const float* d0, const float* d1, const float* d2, size_t n, cons
 
 }  // namespace
 
-size_t mlp_weight_floats(int H) { return (size_t)6 * H + (size_t)H * H + 1; }
+size_t mlp_weight_floats(int H) {
+  // FP32 block, then BF16 W2 and W2^T (16-byte aligned)
+  return ((size_t)6 * H + (size_t)H * H + 1 + 3) / 4 * 4 + (size_t)H * H + 4;
+}
+
+int launch_mlp_prepare_bf16(int H, float* w, hipStream_t s) {
+  switch (H) {
+    case 32: mlp_prepare_bf16_kernel<32><<<(32 * 32 + 255) / 256, 256, 0, s>>>(w); return 0;
+    case 64: mlp_prepare_bf16_kernel<64><<<(64 * 64 + 255) / 256, 256, 0, s>>>(w); return 0;
+    default: return -1;
+  }
+}
+
+template <int H>
+static void mlp_fwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
+                           const float* w, float* mass, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + TB - 1) / TB);
+  mlp_fwd_mfma_kernel<H><<<blocks, TB, 0, s>>>(d0, d1, d2, n, w, mass);
+}
+template <int H>
+static void mlp_bwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
+                           const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                           hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + TB - 1) / TB);
+  mlp_bwd_mfma_kernel<H><<<blocks, TB, 0, s>>>(d0, d1, d2, n, w, mbar, g0, g12, g2);
+}
+
+int launch_mlp_fwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                        const float* w, float* mass, hipStream_t s) {
+  switch (H) {
+    case 32: mlp_fwd_mfma_t<32>(d0, d1, d2, n, w, mass, s); return 0;
+    case 64: mlp_fwd_mfma_t<64>(d0, d1, d2, n, w, mass, s); return 0;
+    default: return -1;
+  }
+}
+
+int launch_mlp_bwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                        const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                        hipStream_t s) {
+  switch (H) {
+    case 32: mlp_bwd_mfma_t<32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 64: mlp_bwd_mfma_t<64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    default: return -1;
+  }
+}
 
 int launch_mlp_fwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
                    const float* w, float* mass, hipStream_t s) {

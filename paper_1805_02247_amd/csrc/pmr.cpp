@@ -130,6 +130,11 @@ struct pmr_ctx {
   double* partial;
   double* prior;
   double* data;
+  // event timing of one kernel class (pmr_profile_begin/end)
+  int prof_class;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used;
+  double prof_bytes;
 };
 
 namespace {
@@ -146,6 +151,9 @@ int validate(const pmr_config* c) {
       c->mlp_hidden != 32 && c->mlp_hidden != 64)
     return PMR_E_SHAPE;
   if (c->precision != PMR_FP32 && c->precision != PMR_MIXED) return PMR_E_INVALID;
+  if (c->precision == PMR_MIXED && c->loss_kind == PMR_LOSS_LOGNORMAL && c->mlp_hidden != 32 &&
+      c->mlp_hidden != 64)
+    return PMR_E_SHAPE;  // the matrix-core network tiles K in steps of 32
   if (!(c->box > 0) || !(c->a0 > 0) || !(c->a1 > c->a0) || !(c->omega_m > 0) || !(c->omega_m <= 1))
     return PMR_E_INVALID;
   if (!(c->R1 >= 0) || !(c->R2 >= 0)) return PMR_E_INVALID;
@@ -278,6 +286,26 @@ int check(pmr_ctx* c) {
   return c->status;
 }
 
+// Records a (start, stop) event pair around the launches of the profiled kernel class on
+// the context stream; `bytes` are the launch's algorithmic bytes.
+struct ProfScope {
+  pmr_ctx* c;
+  bool on;
+  ProfScope(pmr_ctx* ctx, int cls, double bytes) : c(ctx), on(false) {
+    if (c->prof_class == cls && c->prof_used + 2 <= c->prof_ev.size()) {
+      on = true;
+      HIPC(c, hipEventRecord(c->prof_ev[c->prof_used], c->stream));
+      c->prof_bytes += bytes;
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      HIPC(c, hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream));
+      c->prof_used += 2;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- pass helpers
 FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride) {
   FieldMap m;
@@ -307,18 +335,32 @@ void r2c_zy(pmr_ctx* c, int n, int ncomp, const float* in, size_t in_item_stride
             size_t in_comp_stride, const float* in2, float a1, float a2, const double* scale,
             float2* out, size_t out_item_stride, size_t out_comp_stride) {
   const int fields = c->B * ncomp;
-  launch_zpass_r2c(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), in2, a1, a2, scale,
-                   out, fmap(ncomp, out_item_stride, out_comp_stride), c->stream);
-  launch_ypass(n, fields, out, fmap(ncomp, out_item_stride, out_comp_stride), false, c->stream);
+  const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
+  {
+    ProfScope ps(c, PMR_PROF_ZPASS, fields * ((in2 ? 8.0 : 4.0) * n3 + 8.0 * cn));
+    launch_zpass_r2c(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), in2, a1, a2,
+                     scale, out, fmap(ncomp, out_item_stride, out_comp_stride), c->stream);
+  }
+  {
+    ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
+    launch_ypass(n, fields, out, fmap(ncomp, out_item_stride, out_comp_stride), false, c->stream);
+  }
 }
 
 // Spectra after the x pass -> real fields: inverse y, then c2r along z (with optional add).
 void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, size_t in_comp_stride,
             float* out, size_t out_item_stride, size_t out_comp_stride, const float* add) {
   const int fields = c->B * ncomp;
-  launch_ypass(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), true, c->stream);
-  launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), out,
-                   fmap(ncomp, out_item_stride, out_comp_stride), add, c->stream);
+  const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
+  {
+    ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
+    launch_ypass(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), true, c->stream);
+  }
+  {
+    ProfScope ps(c, PMR_PROF_ZPASS, fields * (8.0 * cn + (add ? 8.0 : 4.0) * n3));
+    launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), out,
+                     fmap(ncomp, out_item_stride, out_comp_stride), add, c->stream);
+  }
 }
 
 // Gaussian smoothing of a real field [B][n^3] on R (per item, params[param_index]).
@@ -359,8 +401,11 @@ void pm_step(pmr_ctx* c, int i) {
               c->stream);
   launch_row_start(c->keys_sorted, total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl), c->stream);
   const double scale_m = (double)c->nm / c->cfg.box;
-  launch_paint_mass(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->mass_m,
-                    1.f, c->dens, c->stream);
+  {
+    ProfScope ps(c, PMR_PROF_PAINT, 24.0 * B * c->np3 + 4.0 * B * c->nm3);
+    launch_paint_mass(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->mass_m,
+                      1.f, c->dens, c->stream);
+  }
   const size_t cm = c->cm;
   r2c_zy(c, c->nm, 1, c->dens, c->nm3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, cm, 0);
   XPassArgs a = xargs(c, c->nm);
@@ -370,12 +415,18 @@ void pm_step(pmr_ctx* c, int i) {
   for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cm;
   a.in_item_stride = cm;
   a.out_item_stride = 3 * cm;
-  launch_xpass(XOP_FORCE, a, c->stream);
+  {
+    ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * cm);
+    launch_xpass(XOP_FORCE, a, c->stream);
+  }
   float* F = fslot(c, fsl);
   c2r_yz(c, c->nm, 3, c->cB, 3 * cm, cm, F, 3 * c->nm3, c->nm3, nullptr);
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
-  launch_kick_drift(x, xn, c->p, F, c->keys, B, c->log_np3, c->nm, c->cfg.box, (float)c->kick[i],
-                    c->drift[i], key_nm, c->stream);
+  {
+    ProfScope ps(c, PMR_PROF_KICK_DRIFT, 76.0 * B * c->np3 + 12.0 * B * c->nm3);
+    launch_kick_drift(x, xn, c->p, F, c->keys, B, c->log_np3, c->nm, c->cfg.box,
+                      (float)c->kick[i], c->drift[i], key_nm, c->stream);
+  }
 }
 
 // Run forward steps [i0, i1) (positions x_{i0} in its slot, momenta in c->p), taking
@@ -442,6 +493,8 @@ int pmr_set_stream(pmr_ctx* c, void* stream) {
 }
 
 int pmr_destroy(pmr_ctx* c) {
+  if (c)
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   delete c;
   return PMR_OK;
 }
@@ -466,6 +519,8 @@ int pmr_set_mlp(pmr_ctx* c, const float* W1, const float* b1, const float* W2, c
   HIPC(c, hipMemcpyAsync(w + 4 * H + H * H, b2, H * f, hipMemcpyDeviceToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(w + 5 * H + H * H, W3, H * f, hipMemcpyDeviceToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(w + 6 * H + H * H, b3, f, hipMemcpyDeviceToDevice, c->stream));
+  if (c->cfg.precision == PMR_MIXED && launch_mlp_prepare_bf16(H, w, c->stream) != 0)
+    return PMR_E_SHAPE;
   c->have_mlp = 1;
   return check(c);
 }
@@ -560,9 +615,12 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     a.out_item_stride = 3 * co;
     launch_xpass(XOP_GAUSS2, a, s);
     c2r_yz(c, c->no, 2, c->cB, 3 * co, co, c->dR, no3, (size_t)B * no3, nullptr);
-    if (launch_mlp_fwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w,
-                       c->mass, s) != 0)
-      return PMR_E_SHAPE;
+    const int rc = c->cfg.precision == PMR_MIXED
+                       ? launch_mlp_fwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
+                                             (size_t)B * no3, c->mlp_w, c->mass, s)
+                       : launch_mlp_fwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
+                                        (size_t)B * no3, c->mlp_w, c->mass, s);
+    if (rc != 0) return PMR_E_SHAPE;
     smooth(c, c->no, c->mass, 3, c->MR, nullptr);
     launch_residual(c->MR, c->xd, no3, B, c->params, c->r, s);
     smooth(c, c->no, c->r, 4, c->rs, nullptr);
@@ -592,8 +650,12 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     smooth(c, c->no, c->rs, 4, o0, nullptr, loss_bar, 2.f);  // rbar = G_Rsm (2 loss_bar r_s)
     launch_mrbar(o0, c->MR, no3, B, c->params, o1, s);       // MRbar
     smooth(c, c->no, o1, 3, o2, mass_bar);                   // Mbar (+ mass_bar)
-    launch_mlp_bwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w, o2,
-                   o0, o1, dbar_f, s);
+    if (c->cfg.precision == PMR_MIXED)
+      launch_mlp_bwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,
+                          c->mlp_w, o2, o0, o1, dbar_f, s);
+    else
+      launch_mlp_bwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w,
+                     o2, o0, o1, dbar_f, s);
     // g0 -> o0, g12 -> o1, g2 -> dbar_f (temporarily); feature adjoint:
     // dbar_f = g0 + irfft(G1 rfft(g12) - G2 rfft(g2))
     launch_zpass_r2c(c->no, B, o1, fmap(1, no3, 0), nullptr, 1.f, 0.f, nullptr, c->cB,
@@ -637,8 +699,11 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const int fsl = fs_of(c, i);
     const double* x = xslot(c, xs_of(c, i));
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
-    launch_paint_adj3(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->pbar,
-                      c->xbar, K, Dr, c->Fbar, s);
+    {
+      ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 24.0) * B * c->np3 + 12.0 * B * c->nm3);
+      launch_paint_adj3(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m,
+                        c->pbar, c->xbar, K, Dr, c->Fbar, s);
+    }
     r2c_zy(c, c->nm, 3, c->Fbar, 3 * c->nm3, c->nm3, nullptr, 1.f, 0.f, nullptr, c->cB, 3 * cm, cm);
     XPassArgs a = xargs(c, c->nm);
     a.n_in = 3;
@@ -647,10 +712,16 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     a.out[0] = c->cA;
     a.in_item_stride = 3 * cm;
     a.out_item_stride = cm;
-    launch_xpass(XOP_FORCE_ADJ, a, s);
+    {
+      ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, 32.0 * B * cm);
+      launch_xpass(XOP_FORCE_ADJ, a, s);
+    }
     c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
-    launch_adjoint_gather(x, c->xbar, c->pbar, fslot(c, fsl), c->dbar, B, c->log_np3, c->nm,
-                          c->cfg.box, K, Dr, c->mass_m, 0, s);
+    {
+      ProfScope ps(c, PMR_PROF_ADJ_GATHER, (24.0 + 24.0 + 24.0) * B * c->np3 + 16.0 * B * c->nm3);
+      launch_adjoint_gather(x, c->xbar, c->pbar, fslot(c, fsl), c->dbar, B, c->log_np3, c->nm,
+                            c->cfg.box, K, Dr, c->mass_m, 0, s);
+    }
   }
   // H16: Zel'dovich adjoint and gradient assembly (with the prior)
   {
@@ -670,6 +741,38 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     a.loss_bar = loss_bar;
     launch_xpass(XOP_ZA_ADJ, a, s);
   }
+  return check(c);
+}
+
+int pmr_profile_begin(pmr_ctx* c, int kernel_class, int max_launches) {
+  if (!c || kernel_class < 0 || max_launches < 0) return PMR_E_INVALID;
+  const size_t need = 2 * (size_t)max_launches;
+  while (c->prof_ev.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return PMR_E_HIP;
+    c->prof_ev.push_back(e);
+  }
+  c->prof_class = kernel_class;
+  c->prof_used = 0;
+  c->prof_bytes = 0.0;
+  return PMR_OK;
+}
+
+int pmr_profile_end(pmr_ctx* c, double* total_ms, long long* launches, double* alg_bytes) {
+  if (!c || !total_ms || !launches || !alg_bytes) return PMR_E_INVALID;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+    float t = 0.f;
+    HIPC(c, hipEventElapsedTime(&t, c->prof_ev[i], c->prof_ev[i + 1]));
+    ms += t;
+  }
+  *total_ms = ms;
+  *launches = (long long)(c->prof_used / 2);
+  *alg_bytes = c->prof_bytes;
+  c->prof_class = 0;
+  c->prof_used = 0;
+  c->prof_bytes = 0.0;
   return check(c);
 }
 

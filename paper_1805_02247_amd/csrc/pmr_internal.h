@@ -128,6 +128,12 @@ void launch_za_init(const float* psi, int batch, int np, int log_np3, double box
 size_t mlp_weight_floats(int H);
 int launch_mlp_fwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
                    const float* w, float* mass, hipStream_t s);
+int launch_mlp_prepare_bf16(int H, float* w, hipStream_t s);
+int launch_mlp_fwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                        const float* w, float* mass, hipStream_t s);
+int launch_mlp_bwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,
+                        const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                        hipStream_t s);
 int launch_mlp_bwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
                    const float* w, const float* mbar, float* g0, float* g12, float* g2,
                    hipStream_t s);

@@ -32,11 +32,11 @@ def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0
     return ocfg, inv, modes, w, targets, params
 
 
-def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, kind=None):
+def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P.PMR_FP32):
     B = len(modes)
     n = ocfg.n_part
     cfg = P.Config(batch=B, n_part=n, n_mesh=ocfg.n_mesh, n_out=ocfg.n_out, n_steps=ocfg.n_steps,
-                   mlp_hidden=hidden, box=ocfg.box, ckpt_every=ckpt,
+                   mlp_hidden=hidden, box=ocfg.box, ckpt_every=ckpt, precision=precision,
                    loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2)
     pm = P.PMContext(cfg, DEV)
     pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
@@ -135,3 +135,17 @@ def test_run_to_run_bitwise():
     assert np.array_equal(a["loss"], b["loss"])
     assert np.array_equal(a["grad"], b["grad"])
     assert np.array_equal(a["mass"], b["mass"])
+
+
+TOL_MIXED = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "prior": 1e-5, "loss": 3e-3, "mass": 2e-2,
+             "grad_cos": 0.999, "grad_rel": 5e-2}
+
+
+@pytest.mark.parametrize("hidden", [32, 64])
+def test_mixed_precision_network(hidden):
+    """BF16 matrix-core network (FP32 accumulation) against the FP64 oracle."""
+    require_gpu()
+    say(f"pipeline: mixed precision, H={hidden}")
+    prob = _problem(32, 32, 32, 100.0, 3, OM.LOSS_LOGNORMAL, 2, hidden=hidden, R_sm=(2.0, 0.0))
+    res = _gpu_run(*prob, hidden=hidden, precision=P.PMR_MIXED)
+    _compare(*prob, res, TOL_MIXED)
