@@ -182,6 +182,14 @@ int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream);
  * (kz = 0, n/2 columns after the inner transforms) are ignored, as irfftn does. */
 int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
 
+/* Tile shape of the strided FFT passes for size n (process-wide; the autotuner sets it):
+ * `columns` consecutive kz columns per workgroup tile (8, 16 or 32) and `threads` per
+ * workgroup (256 or 512), with n * columns >= threads and the tile within 160 KB of LDS.
+ * Defaults: 16 columns, 256 threads. Not synchronised with work in flight: set it before
+ * enqueueing. */
+int pmr_fft_set_tile(int n, int columns, int threads);
+int pmr_fft_get_tile(int n, int* columns, int* threads);
+
 /* Bytes of scratch for pmr_cic_sort with `n_particles` in total and `batch` items. */
 size_t pmr_sort_scratch_bytes(int n_particles_total, int n_mesh, int batch);
 
@@ -194,10 +202,12 @@ int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
                  void* scratch, size_t scratch_bytes, void* stream);
 
 /* CIC density on an n_mesh^3 mesh: out = sum_p mass W(x_p - cell) - bias, [B][n_mesh^3],
- * from the outputs of pmr_cic_sort. Deterministic (bitwise reproducible). */
+ * from the outputs of pmr_cic_sort. Deterministic (bitwise reproducible). `scratch` holds
+ * the sorted fraction stream: at least 16 * B * Np^3 bytes. */
 int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x,
-                  const uint32_t* ids_sorted, const uint32_t* row_start, float mass, float bias,
-                  float* out, void* stream);
+                  const uint32_t* keys_sorted, const uint32_t* ids_sorted,
+                  const uint32_t* row_start, float mass, float bias, float* out, void* scratch,
+                  size_t scratch_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -57,7 +57,9 @@ SIGNATURES = {
     "pmr_fft_c2r": (ci, [ci, ci, vp, vp, vp]),
     "pmr_sort_scratch_bytes": (sz, [ci, ci, ci]),
     "pmr_cic_sort": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, vp, sz, vp]),
-    "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, cf, cf, vp, vp]),
+    "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, cf, cf, vp, vp, sz, vp]),
+    "pmr_fft_set_tile": (ci, [ci, ci, ci]),
+    "pmr_fft_get_tile": (ci, [ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]),
     "pmr_profile_begin": (ci, [vp, ci, ci]),
     "pmr_profile_end": (ci, [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_longlong),
                              ctypes.POINTER(cd)]),
@@ -79,6 +81,8 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        from . import tune  # applies the autotuned FFT tile shapes, if any
+        tune.apply_cache()
     return _lib
 
 

@@ -244,10 +244,13 @@ def cic_sort(x, n_mesh, box):
     return keys, ids, rows
 
 
-def cic_paint(x, ids, rows, n_mesh, box, mass=1.0, bias=0.0):
+def cic_paint(x, keys, ids, rows, n_mesh, box, mass=1.0, bias=0.0):
+    """CIC density of positions x (float64 [B][3][Np^3]) from the outputs of cic_sort."""
     B, np3 = x.shape[0], x.shape[2]
     n_part = round(np3 ** (1 / 3))
     out = torch.empty(B, n_mesh ** 3, dtype=torch.float32, device=x.device)
-    L.check(L.lib().pmr_cic_paint(n_part, n_mesh, B, float(box), _ptr(x.contiguous()), _ptr(ids),
-                                  _ptr(rows), float(mass), float(bias), _ptr(out), _stream()))
+    scratch = torch.empty(B * np3 * 16, dtype=torch.uint8, device=x.device)
+    L.check(L.lib().pmr_cic_paint(n_part, n_mesh, B, float(box), _ptr(x.contiguous()), _ptr(keys),
+                                  _ptr(ids), _ptr(rows), float(mass), float(bias), _ptr(out),
+                                  _ptr(scratch), scratch.numel(), _stream()))
     return out

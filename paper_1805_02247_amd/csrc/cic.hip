@@ -226,125 +226,222 @@ __global__ void row_start_kernel(const uint32_t* __restrict__ keys, int n, int l
   for (int r = r_lo + 1; r <= r_hi; ++r) row_start[r] = j;
 }
 
-// ---------------------------------------------------------------- paint
-enum PaintMode { PAINT_MASS = 0, PAINT_ADJ3 = 1 };
+// ---------------------------------------------------------------- sorted particle streams
+// Per sorted position j: the CIC fractions of particle ids[j] (FP64 rule, rounded to FP32).
+__global__ __launch_bounds__(TB) void stream_frac_kernel(const uint32_t* __restrict__ ids,
+                                                         const double* __restrict__ x, int total,
+                                                         int log_np3, double scale, int nm,
+                                                         float4* __restrict__ frac) {
+  const int j = blockIdx.x * TB + threadIdx.x;
+  if (j >= total) return;
+  const size_t np3 = (size_t)1 << log_np3;
+  const uint32_t g = ids[j];
+  const size_t pi = (size_t)(g >> log_np3) * 3 * np3 + (g & (np3 - 1));
+  double fx, fy, fz;
+  cic_corner(x[pi], scale, nm, &fx);
+  cic_corner(x[pi + np3], scale, nm, &fy);
+  cic_corner(x[pi + 2 * np3], scale, nm, &fz);
+  frac[j] = make_float4((float)fx, (float)fy, (float)fz, 0.f);
+}
 
+// Per sorted position j: the adjoint paint values kick * (pbar + drift * xbar) of ids[j].
+__global__ __launch_bounds__(TB) void stream_adj_kernel(const uint32_t* __restrict__ ids,
+                                                        const float* __restrict__ pbar,
+                                                        const float* __restrict__ xbar, int total,
+                                                        int log_np3, float kick, float drift,
+                                                        float4* __restrict__ val) {
+  const int j = blockIdx.x * TB + threadIdx.x;
+  if (j >= total) return;
+  const size_t np3 = (size_t)1 << log_np3;
+  const uint32_t g = ids[j];
+  const size_t pi = (size_t)(g >> log_np3) * 3 * np3 + (g & (np3 - 1));
+  float v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = kick * (pbar[pi + c * np3] + drift * xbar[pi + c * np3]);
+  val[j] = make_float4(v[0], v[1], v[2], 0.f);
+}
+
+// ---------------------------------------------------------------- paint
+// One wavefront owns TY consecutive target rows (item, ix, iy0 .. iy0+TY-1), accumulated
+// in LDS. For each ox in {0, 1} its source rows (ix - ox, iy0 - 1 .. iy0 + TY - 1) are one
+// contiguous run of the sorted stream (two runs when iy0 - 1 wraps), walked in full 64-lane
+// chunks. A particle in source row sy reaches target rows sy and sy + 1. Within a chunk the
+// keys are sorted, so a segmented scan sums equal-(sy, iz) runs and only the last lane of a
+// run writes, to a cell no other lane of that instruction touches: every LDS word receives
+// its additions in one fixed order and the mesh is bitwise reproducible.
 struct PaintArgs {
-  const double* x;         // [B][3][Np^3]
-  const uint32_t* ids;     // sorted global ids (item*Np^3 + id)
+  const uint32_t* keys;     // sorted keys
+  const float4* frac;       // sorted fractions
+  const float4* val;        // sorted values (C = 3), or nullptr (C = 1, constant mass)
   const uint32_t* row_start;
-  int log_np3, nm, log_nm;
-  double scale;            // nm / box
-  float mass, bias;        // PAINT_MASS value per particle, subtracted constant
-  // PAINT_ADJ3: v_a = kick * (pbar_a + drift * xbar_a)
-  const float* pbar;
-  const float* xbar;
-  float kick, drift;
-  float* out;              // [B][C][nm^3]
+  int nm, log_nm;
+  float mass, bias;
+  float* out;               // [B][C][nm^3]
+};
+
+// Segmented inclusive scan over the 64 lanes by equal key, on DPP lane moves (VALU, no
+// LDS): row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and row_bcast 31
+// across rows. Keys are sorted across the lanes, so "source key == my key" means the
+// source lane is in my segment. Lanes whose DPP source is out of range read 0.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_f(float src) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, RMASK, 0xF, false));
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ uint32_t dpp_k(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)src, CTRL, RMASK, 0xF, false);
+}
+
+template <int NV, int CTRL, int RMASK>
+__device__ __forceinline__ void seg_step(float (&v)[NV], uint32_t key) {
+  const uint32_t ks = dpp_k<CTRL, RMASK>(key);
+  float t[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) t[q] = dpp_f<CTRL, RMASK>(v[q]);
+  if (ks == key) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += t[q];
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void seg_scan(float (&v)[NV], uint32_t key) {
+  seg_step<NV, 0x111, 0xF>(v, key);  // row_shr:1
+  seg_step<NV, 0x112, 0xF>(v, key);  // row_shr:2
+  seg_step<NV, 0x114, 0xF>(v, key);  // row_shr:4
+  seg_step<NV, 0x118, 0xF>(v, key);  // row_shr:8
+  seg_step<NV, 0x142, 0xA>(v, key);  // row_bcast:15 into rows 1, 3
+  seg_step<NV, 0x143, 0xC>(v, key);  // row_bcast:31 into rows 2, 3
+}
+
+// One 64-particle chunk of a source run: per lane the four (oy, oz) weights of each channel.
+template <int C>
+struct Chunk {
+  uint32_t key;
+  int sy, iz;
+  bool ok;
+  float v[4 * C];
 };
 
 template <int C>
-__device__ __forceinline__ void seg_scan(float (&a0)[C], float (&a1)[C], int key) {
+__device__ __forceinline__ void load_chunk(const PaintArgs& a, uint32_t j, uint32_t end, int ox,
+                                           Chunk<C>& ch) {
   const int lane = threadIdx.x & 63;
+  const int nm = a.nm;
+  ch.ok = j < end;
+  ch.key = 0xffffffffu - lane;  // never equal across lanes when invalid
+  ch.sy = 0;
+  ch.iz = 0;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int ku = __shfl_up(key, d, 64);
-    float t0[C], t1[C];
+  for (int q = 0; q < 4 * C; ++q) ch.v[q] = 0.f;
+  if (ch.ok) {
+    const uint32_t key = a.keys[j];
+    const float4 f = a.frac[j];
+    ch.key = key;
+    ch.iz = (int)(key & (uint32_t)(nm - 1));
+    ch.sy = (int)((key >> a.log_nm) & (uint32_t)(nm - 1));
+    const float wx = ox ? f.x : 1.f - f.x;
+    float val[C];
+    if constexpr (C == 1) {
+      val[0] = a.mass * wx;
+    } else {
+      const float4 u = a.val[j];
+      val[0] = u.x * wx;
+      val[1] = u.y * wx;
+      val[2] = u.z * wx;
+    }
+    const float wy0 = 1.f - f.y, wy1 = f.y, wz0 = 1.f - f.z, wz1 = f.z;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      t0[c] = __shfl_up(a0[c], d, 64);
-      t1[c] = __shfl_up(a1[c], d, 64);
-    }
-    if (lane >= d && ku == key) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        a0[c] += t0[c];
-        a1[c] += t1[c];
-      }
+      ch.v[4 * c + 0] = val[c] * wy0 * wz0;
+      ch.v[4 * c + 1] = val[c] * wy0 * wz1;
+      ch.v[4 * c + 2] = val[c] * wy1 * wz0;
+      ch.v[4 * c + 3] = val[c] * wy1 * wz1;
     }
   }
 }
 
-template <int C, int MODE>
+// Last lane of each run adds the run's sums to its two target rows; one LDS word per lane
+// per instruction.
+template <int C, int TY>
+__device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, int iy0) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kn = __shfl_down(ch.key, 1, 64);
+  const int ok_next = __shfl_down((int)ch.ok, 1, 64);
+  const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
+  const int iz1 = (ch.iz + 1) & (nm - 1);
+#pragma unroll
+  for (int oy = 0; oy < 2; ++oy) {
+    const int jt = ((ch.sy + oy) & (nm - 1)) - iy0;
+    const bool in = tail && jt >= 0 && jt < TY;
+    float* row = acc + (size_t)jt * C * nm;
+    if (in) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) atomicAdd(&row[c * nm + ch.iz], ch.v[4 * c + 2 * oy]);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    if (in) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) atomicAdd(&row[c * nm + iz1], ch.v[4 * c + 2 * oy + 1]);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+  }
+}
+
+template <int C, int TY>
 __global__ __launch_bounds__(TB) void paint_kernel(PaintArgs a) {
   extern __shared__ float acc_all[];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int nm = a.nm;
-  const int row = blockIdx.x * (TB / 64) + w;  // global target row (item, ix, iy)
-  const int rows_per_item = nm * nm;
-  const int item = row / rows_per_item;
-  const int rr = row - item * rows_per_item;
-  const int ix = rr / nm, iy = rr - (rr / nm) * nm;
-  float* acc = acc_all + w * C * nm;
-  for (int i = lane; i < C * nm; i += 64) acc[i] = 0.f;
+  const int seg = blockIdx.x * (TB / 64) + w;  // (item, ix, column segment)
+  const int segs_per_x = nm / TY;
+  const int item = seg / (nm * segs_per_x);
+  const int rr = seg - item * nm * segs_per_x;
+  const int ix = rr / segs_per_x;
+  const int iy0 = (rr - ix * segs_per_x) * TY;
+  float* acc = acc_all + (size_t)w * TY * C * nm;  // [TY][C][nm]
+  for (int i = lane; i < TY * C * nm; i += 64) acc[i] = 0.f;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0xc07f);
-  const size_t np3 = (size_t)1 << a.log_np3;
+  const int rows_item = item * nm * nm;
 #pragma unroll 1
-  for (int o = 0; o < 4; ++o) {
-    const int ox = o >> 1, oy = o & 1;
+  for (int ox = 0; ox < 2; ++ox) {
     const int sx = (ix - ox + nm) & (nm - 1);
-    const int sy = (iy - oy + nm) & (nm - 1);
-    const int srow = item * rows_per_item + sx * nm + sy;
-    const uint32_t beg = a.row_start[srow], end = a.row_start[srow + 1];
+    const int rbase = rows_item + sx * nm;
+    // runs of source rows: [iy0 - 1, iy0 + TY - 1], split when iy0 - 1 wraps
+    int lo0 = iy0 - 1, hi0 = iy0 + TY - 1, lo1 = 1, hi1 = 0;
+    if (iy0 == 0) {
+      lo0 = 0;
+      lo1 = nm - 1;
+      hi1 = nm - 1;
+    }
 #pragma unroll 1
-    for (uint32_t c0 = beg; c0 < end; c0 += 64) {
-      const uint32_t j = c0 + lane;
-      const bool ok = j < end;
-      int iz = 0x7fffffff - lane;  // never equal across lanes when invalid
-      float a0[C], a1[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) a0[c] = a1[c] = 0.f;
-      if (ok) {
-        const uint32_t g = a.ids[j];
-        const uint32_t it = g >> a.log_np3;
-        const size_t id = g & (np3 - 1);
-        const double* xp = a.x + (size_t)it * 3 * np3 + id;
-        double fx, fy, fz;
-        cic_corner(xp[0], a.scale, nm, &fx);
-        cic_corner(xp[np3], a.scale, nm, &fy);
-        iz = cic_corner(xp[2 * np3], a.scale, nm, &fz);
-        const float wx = ox ? (float)fx : 1.f - (float)fx;
-        const float wy = oy ? (float)fy : 1.f - (float)fy;
-        const float wxy = wx * wy;
-        const float f1 = (float)fz, f0 = 1.f - (float)fz;
-        if constexpr (MODE == PAINT_MASS) {
-          const float v = a.mass * wxy;
-          a0[0] = v * f0;
-          a1[0] = v * f1;
-        } else {
-          const size_t pi = (size_t)it * 3 * np3 + id;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const float v = a.kick * (a.pbar[pi + c * np3] + a.drift * a.xbar[pi + c * np3]) * wxy;
-            a0[c] = v * f0;
-            a1[c] = v * f1;
-          }
-        }
+    for (int run = 0; run < 2; ++run) {
+      const int lo = run == 0 ? lo0 : lo1, hi = run == 0 ? hi0 : hi1;
+      if (lo > hi) continue;
+      const uint32_t beg = a.row_start[rbase + lo], end = a.row_start[rbase + hi + 1];
+      // two chunks in flight; their deposits stay in chunk order
+#pragma unroll 1
+      for (uint32_t c0 = beg; c0 < end; c0 += 128) {
+        Chunk<C> A, Bc;
+        load_chunk<C>(a, c0 + lane, end, ox, A);
+        load_chunk<C>(a, c0 + 64 + lane, end, ox, Bc);
+        seg_scan<4 * C>(A.v, A.key);
+        seg_scan<4 * C>(Bc.v, Bc.key);
+        deposit<C, TY>(A, acc, nm, iy0);
+        if (c0 + 64 < end) deposit<C, TY>(Bc, acc, nm, iy0);
       }
-      seg_scan<C>(a0, a1, iz);
-      const int iz_next = __shfl_down(iz, 1, 64);
-      const bool tail = ok && (lane == 63 || iz_next != iz);
-      if (tail) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) atomicAdd(&acc[c * nm + iz], a0[c]);
-      }
-      __builtin_amdgcn_s_waitcnt(0xc07f);
-      if (tail) {
-        const int iz1 = (iz + 1) & (nm - 1);
-#pragma unroll
-        for (int c = 0; c < C; ++c) atomicAdd(&acc[c * nm + iz1], a1[c]);
-      }
-      __builtin_amdgcn_s_waitcnt(0xc07f);
     }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0xc07f);
   const size_t cells = (size_t)nm * nm * nm;
-  float* dst = a.out + (size_t)item * C * cells + ((size_t)ix * nm + iy) * nm;
-  for (int c = 0; c < C; ++c)
-    for (int i = lane; i < nm; i += 64) dst[c * cells + i] = acc[c * nm + i] - a.bias;
+  for (int t = 0; t < TY; ++t) {
+    float* dst = a.out + (size_t)item * C * cells + ((size_t)ix * nm + iy0 + t) * nm;
+    for (int c = 0; c < C; ++c)
+      for (int i = lane; i < nm; i += 64) dst[c * cells + i] = acc[(t * C + c) * nm + i] - a.bias;
+  }
 }
 
 // ---------------------------------------------------------------- gathers
@@ -584,40 +681,75 @@ void launch_keys(const double* x, int log_np3, int total, double scale, int nm, 
   keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys);
 }
 
-void launch_paint_mass(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
-                       int log_np3, int nm, double scale, float mass, float bias, float* out,
-                       hipStream_t s) {
+// Rows per wave: keep the wave's LDS accumulator within 2048 floats.
+static int paint_ty(int nm, int C) {
+  int ty = 2048 / (nm * C);
+  if (ty > 16) ty = 16;
+  if (ty > nm / 2) ty = nm / 2;  // TY + 1 distinct source rows per run
+  int p = 1;
+  while (p * 2 <= ty) p *= 2;
+  return p;
+}
+
+template <int C, int TY>
+static void paint_launch(const PaintArgs& a, int batch, hipStream_t s) {
+  const int waves = batch * a.nm * (a.nm / TY);
+  const size_t lds = (size_t)(TB / 64) * TY * C * a.nm * sizeof(float);
+  paint_kernel<C, TY><<<waves / (TB / 64), TB, lds, s>>>(a);
+}
+
+template <int C>
+static void paint_dispatch(const PaintArgs& a, int batch, hipStream_t s) {
+  switch (paint_ty(a.nm, C)) {
+    case 1: paint_launch<C, 1>(a, batch, s); break;
+    case 2: paint_launch<C, 2>(a, batch, s); break;
+    case 4: paint_launch<C, 4>(a, batch, s); break;
+    case 8: paint_launch<C, 8>(a, batch, s); break;
+    default: paint_launch<C, 16>(a, batch, s); break;
+  }
+}
+
+void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,
+                        double box, float4* frac, hipStream_t s) {
+  stream_frac_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, x, total, log_np3,
+                                                          (double)nm / box, nm, frac);
+}
+
+void launch_stream_adj(const uint32_t* ids, const float* pbar, const float* xbar, int total,
+                       int log_np3, float kick, float drift, float4* val, hipStream_t s) {
+  stream_adj_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, pbar, xbar, total, log_np3, kick,
+                                                         drift, val);
+}
+
+void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
+                       int batch, int nm, float mass, float bias, float* out, hipStream_t s) {
   PaintArgs a{};
-  a.x = x;
-  a.ids = ids;
+  a.keys = keys;
+  a.frac = frac;
   a.row_start = row_start;
-  a.log_np3 = log_np3;
   a.nm = nm;
-  a.scale = scale;
+  int l = 0;
+  while ((1 << l) < nm) ++l;
+  a.log_nm = l;
   a.mass = mass;
   a.bias = bias;
   a.out = out;
-  const int rows = batch * nm * nm;
-  paint_kernel<1, PAINT_MASS><<<rows / (TB / 64), TB, (TB / 64) * nm * sizeof(float), s>>>(a);
+  paint_dispatch<1>(a, batch, s);
 }
 
-void launch_paint_adj3(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
-                       int log_np3, int nm, double scale, const float* pbar, const float* xbar,
-                       float kick, float drift, float* out, hipStream_t s) {
+void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
+                       const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s) {
   PaintArgs a{};
-  a.x = x;
-  a.ids = ids;
+  a.keys = keys;
+  a.frac = frac;
+  a.val = val;
   a.row_start = row_start;
-  a.log_np3 = log_np3;
   a.nm = nm;
-  a.scale = scale;
-  a.pbar = pbar;
-  a.xbar = xbar;
-  a.kick = kick;
-  a.drift = drift;
+  int l = 0;
+  while ((1 << l) < nm) ++l;
+  a.log_nm = l;
   a.out = out;
-  const int rows = batch * nm * nm;
-  paint_kernel<3, PAINT_ADJ3><<<rows / (TB / 64), TB, (TB / 64) * 3 * nm * sizeof(float), s>>>(a);
+  paint_dispatch<3>(a, batch, s);
 }
 
 void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,

@@ -74,18 +74,18 @@ __device__ __forceinline__ void bfly(float2* u) {
 // Stage with radix R after earlier stages of total radix PREV: butterfly i (0..M/R-1)
 // reads points i + r M/R, twiddles by w^(r k M / (PREV R)) with k = i mod PREV, and
 // writes point (i - k) R + k + r PREV. Twiddle table: tw[j * TWS] = exp(-2 pi i j / M).
-template <int M, int R, int PREV, int LINES, int SN, int SL, int TWS, int DIR>
+template <int M, int R, int PREV, int LINES, int SN, int SL, int TWS, int DIR, int NTH>
 __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
   constexpr int NB = (M / R) * LINES;
-  constexpr int PER = (NB + NT - 1) / NT;
+  constexpr int PER = (NB + NTH - 1) / NTH;
   float2 u[PER][R];
   int ii[PER], ll[PER];
   const int t = threadIdx.x;
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int b = t + m * NT;
+    const int b = t + m * NTH;
     ii[m] = -1;
-    if (NB % NT == 0 || b < NB) {
+    if (NB % NTH == 0 || b < NB) {
       int i, l;
       if constexpr (SL == 1) {
         l = b % LINES;
@@ -103,7 +103,7 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    if (NB % NT == 0 || ii[m] >= 0) {
+    if (NB % NTH == 0 || ii[m] >= 0) {
       const int i = ii[m], l = ll[m];
       const int k = i & (PREV - 1);
       if constexpr (PREV > 1) {
@@ -124,23 +124,23 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
 }
 
 // Full M-point transform: radix-8 stages, then one radix-4 or radix-2 stage.
-template <int M, int LINES, int SN, int SL, int TWS, int DIR>
+template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw) {
   static_assert(M >= 2 && (M & (M - 1)) == 0, "power of two");
-  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR>(lds, tw);
-  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR>(lds, tw);
-  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR>(lds, tw);
+  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
+  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
+  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
   constexpr int P8 = M >= 512 ? 512 : M >= 64 ? 64 : M >= 8 ? 8 : 1;
   constexpr int REM = M / P8;
-  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR>(lds, tw);
-  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR>(lds, tw);
+  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
+  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
   static_assert(M <= 512, "at most 512 points per line");
 }
 
 // exp(-2 pi i j / N) for j < N, from FP64 sincospi.
-template <int N>
+template <int N, int NTH = NT>
 __device__ __forceinline__ void make_twiddles(float2* tw) {
-  for (int j = threadIdx.x; j < N; j += NT) {
+  for (int j = threadIdx.x; j < N; j += NTH) {
     double s, c;
     sincospi(-2.0 * (double)j / (double)N, &s, &c);
     tw[j] = make_float2((float)c, (float)s);
@@ -279,39 +279,39 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
 // ---------------------------------------------------------------- strided passes
 // Tile: PCOL consecutive kz columns (from kz0) of the N points of one line family.
 // Element (n, l) of a tile sits at base + n * stride + l.
-template <int N>
+template <int N, int PC, int NTH>
 __device__ __forceinline__ void load_tile(float2* lds, const float2* __restrict__ base,
                                           size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PCOL; e += NT) {
-    const int n = e / PCOL, l = e % PCOL;
+  for (int e = threadIdx.x; e < N * PC; e += NTH) {
+    const int n = e / PC, l = e % PC;
     lds[e] = l < ncols ? base[(size_t)n * stride + l] : make_float2(0.f, 0.f);
   }
 }
 
-template <int N>
+template <int N, int PC, int NTH>
 __device__ __forceinline__ void store_tile(const float2* lds, float2* __restrict__ base,
                                            size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PCOL; e += NT) {
-    const int n = e / PCOL, l = e % PCOL;
+  for (int e = threadIdx.x; e < N * PC; e += NTH) {
+    const int n = e / PC, l = e % PC;
     if (l < ncols) base[(size_t)n * stride + l] = lds[e];
   }
 }
 
 // y pass: in-place forward or inverse transform along y of each field.
-template <int N, int DIR>
-__global__ __launch_bounds__(NT) void ypass_kernel(float2* __restrict__ data, FieldMap m) {
+template <int N, int DIR, int PC, int NTH>
+__global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, FieldMap m) {
   constexpr int NH = N / 2 + 1;
-  __shared__ float2 lds[N * PCOL];
+  __shared__ float2 lds[N * PC];
   __shared__ float2 tw[N];
-  make_twiddles<N>(tw);
-  const int kz0 = blockIdx.x * PCOL;
-  const int ncols = min(PCOL, NH - kz0);
+  make_twiddles<N, NTH>(tw);
+  const int kz0 = blockIdx.x * PC;
+  const int ncols = min(PC, NH - kz0);
   const int ix = blockIdx.y;
   float2* base = data + m.off(blockIdx.z) + (size_t)ix * N * NH + kz0;
-  load_tile<N>(lds, base, NH, ncols);
+  load_tile<N, PC, NTH>(lds, base, NH, ncols);
   __syncthreads();
-  fft_lds<N, PCOL, PCOL, 1, 1, DIR>(lds, tw);
-  store_tile<N>(lds, base, NH, ncols);
+  fft_lds<N, PC, PC, 1, 1, DIR, NTH>(lds, tw);
+  store_tile<N, PC, NTH>(lds, base, NH, ncols);
 }
 
 // ---------------------------------------------------------------- x pass with operators
@@ -343,17 +343,17 @@ __device__ __forceinline__ float grad_coef(const KVec& k, int a) {
   return ka / k.k2;
 }
 
-template <int N, int OP>
-__global__ __launch_bounds__(NT) void xpass_kernel(XPassArgs a) {
+template <int N, int OP, int PC, int NTH>
+__global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a) {
   constexpr int NH = N / 2 + 1;
-  constexpr int NE = N * PCOL;
-  constexpr int PER = NE / NT;
-  static_assert(NE % NT == 0, "tile");
+  constexpr int NE = N * PC;
+  constexpr int PER = NE / NTH;
+  static_assert(NE % NTH == 0, "tile");
   __shared__ float2 lds[NE];
   __shared__ float2 tw[N];
-  make_twiddles<N>(tw);
-  const int kz0 = blockIdx.x * PCOL;
-  const int ncols = min(PCOL, NH - kz0);
+  make_twiddles<N, NTH>(tw);
+  const int kz0 = blockIdx.x * PC;
+  const int ncols = min(PC, NH - kz0);
   const int iy = blockIdx.y;
   const int item = blockIdx.z;
   const size_t stride = (size_t)N * NH;
@@ -373,13 +373,13 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XPassArgs a) {
   float Rg = 0.f;
   if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
   for (int i = 0; i < n_in; ++i) {
-    load_tile<N>(lds, a.in[i] + ioff, stride, ncols);
+    load_tile<N, PC, NTH>(lds, a.in[i] + ioff, stride, ncols);
     __syncthreads();
-    if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PCOL, PCOL, 1, 1, -1>(lds, tw);
+    if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
-      const int e = t + m * NT;
-      const int n = e / PCOL, l = e % PCOL;
+      const int e = t + m * NTH;
+      const int n = e / PC, l = e % PC;
       const float2 v = lds[e];
       if constexpr (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) {
         const KVec k = kvec<N>(n, iy, kz0 + l, kf);
@@ -403,16 +403,16 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XPassArgs a) {
   // -------- outputs
   if constexpr (OP == XOP_FWD) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) lds[t + m * NT] = hold[m];
+    for (int m = 0; m < PER; ++m) lds[t + m * NTH] = hold[m];
     __syncthreads();
-    store_tile<N>(lds, a.out[0] + ooff, stride, ncols);
+    store_tile<N, PC, NTH>(lds, a.out[0] + ooff, stride, ncols);
   } else if constexpr (OP == XOP_ZA_ADJ) {
     // G = w(kz) * (sum_a conj(M_a) g_a / n^3 + prior_weight * loss_bar * P s / S), G(0) = 0
     const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
-      const int e = t + m * NT;
-      const int n = e / PCOL, l = e % PCOL;
+      const int e = t + m * NTH;
+      const int n = e / PC, l = e % PC;
       const int kz = kz0 + l;
       if (l >= ncols) continue;
       const size_t gi = (size_t)n * stride + (size_t)iy * NH + kz;
@@ -431,8 +431,8 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XPassArgs a) {
     for (int o = 0; o < n_out; ++o) {
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
-        const int e = t + m * NT;
-        const int n = e / PCOL, l = e % PCOL;
+        const int e = t + m * NTH;
+        const int n = e / PC, l = e % PC;
         float2 v = hold[m];
         if constexpr (OP == XOP_FORCE || OP == XOP_ZA) {
           const KVec k = kvec<N>(n, iy, kz0 + l, kf);
@@ -453,8 +453,8 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XPassArgs a) {
         lds[e] = v;
       }
       __syncthreads();
-      fft_lds<N, PCOL, PCOL, 1, 1, +1>(lds, tw);
-      store_tile<N>(lds, a.out[o] + ooff, stride, ncols);
+      fft_lds<N, PC, PC, 1, 1, +1, NTH>(lds, tw);
+      store_tile<N, PC, NTH>(lds, a.out[o] + ooff, stride, ncols);
       __syncthreads();
     }
   }
@@ -476,19 +476,69 @@ void zc2r(int fields, const float2* in, FieldMap im, float* out, FieldMap om, co
   zpass_c2r_kernel<N><<<grid, NT, 0, s>>>(in, im, out, om, add);
 }
 
+// Tile shape of the strided passes (columns per tile, threads per workgroup), per size;
+// set by pmr_fft_set_tile (the autotuner) or left at the defaults.
+struct TileShape {
+  int pc, nth;
+};
+TileShape g_tile[10] = {{16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256},
+                        {16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256}};
+int log2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+template <int N, int PC, int NTH>
+void ypass_t(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
+  dim3 grid((N / 2 + 1 + PC - 1) / PC, N, fields);
+  if (inv)
+    ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m);
+  else
+    ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m);
+}
+
+template <int N, int OP, int PC, int NTH>
+void xpass_t(const XPassArgs& a, hipStream_t s) {
+  dim3 grid((N / 2 + 1 + PC - 1) / PC, N, a.batch);
+  xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a);
+}
+
+// Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
+// tile N * PC * 8 B + N * 8 B within 160 KB.
+template <int N>
+constexpr bool shape_ok(int pc, int nth) {
+  return N * pc >= nth && (N * pc + N) * 8 <= 160 * 1024;
+}
+
+#define PMR_FOR_SHAPE(M) M(8, 256) M(16, 256) M(32, 256) M(8, 512) M(16, 512) M(32, 512)
+
 template <int N>
 void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
-  dim3 grid((N / 2 + 1 + PCOL - 1) / PCOL, N, fields);
-  if (inv)
-    ypass_kernel<N, +1><<<grid, NT, 0, s>>>(d, m);
-  else
-    ypass_kernel<N, -1><<<grid, NT, 0, s>>>(d, m);
+  const TileShape t = g_tile[log2i(N)];
+#define SHAPE(PC, NTH)                                        \
+  if constexpr (shape_ok<N>(PC, NTH))                         \
+    if (t.pc == PC && t.nth == NTH) {                         \
+      ypass_t<N, PC, NTH>(fields, d, m, inv, s);              \
+      return;                                                 \
+    }
+  PMR_FOR_SHAPE(SHAPE)
+#undef SHAPE
+  ypass_t<N, 16, 256>(fields, d, m, inv, s);
 }
 
 template <int N, int OP>
 void xpass_op(const XPassArgs& a, hipStream_t s) {
-  dim3 grid((N / 2 + 1 + PCOL - 1) / PCOL, N, a.batch);
-  xpass_kernel<N, OP><<<grid, NT, 0, s>>>(a);
+  const TileShape t = g_tile[log2i(N)];
+#define SHAPE(PC, NTH)                                        \
+  if constexpr (shape_ok<N>(PC, NTH))                         \
+    if (t.pc == PC && t.nth == NTH) {                         \
+      xpass_t<N, OP, PC, NTH>(a, s);                          \
+      return;                                                 \
+    }
+  PMR_FOR_SHAPE(SHAPE)
+#undef SHAPE
+  xpass_t<N, OP, 16, 256>(a, s);
 }
 
 template <int N>
@@ -542,6 +592,21 @@ void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hip
 #undef CASE
     default: break;
   }
+}
+
+int set_fft_tile(int n, int pc, int nth) {
+  if (n < 16 || n > 512 || (n & (n - 1))) return -1;
+  if (pc != 8 && pc != 16 && pc != 32) return -1;
+  if (nth != 256 && nth != 512) return -1;
+  if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024) return -1;
+  g_tile[log2i(n)] = {pc, nth};
+  return 0;
+}
+
+void get_fft_tile(int n, int* pc, int* nth) {
+  const TileShape t = g_tile[log2i(n)];
+  *pc = t.pc;
+  *nth = t.nth;
 }
 
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s) {

@@ -104,6 +104,8 @@ struct pmr_ctx {
   float* p;     // [B][3][np3]
   float* F;     // force slots [SF][B][3][nm3]
   uint32_t* ids;   // sort slots [SF][B*np3]
+  uint32_t* skeys; // sorted keys [SF][B*np3]
+  float4* frac;    // sorted CIC fractions [SF][B*np3]
   uint32_t* rows;  // [SF][B*nm*nm + 1]
   int n_fslots;
   uint32_t* keys;
@@ -111,6 +113,8 @@ struct pmr_ctx {
   void* sort_scratch;
   size_t sort_scratch_bytes;
   uint32_t* ids_o;
+  float4* frac_o;
+  float4* vstream;  // sorted adjoint paint values [B*np3]
   uint32_t* rows_o;
   float* dens;   // [B][nm3]
   float2* cA;    // [B][cmax]
@@ -191,6 +195,8 @@ void plan(pmr_ctx* c, Plan& P) {
   c->p = P.take<float>(B * 3 * c->np3);
   c->F = P.take<float>((size_t)c->n_fslots * B * 3 * c->nm3);
   c->ids = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
+  c->skeys = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
+  c->frac = P.take<float4>((size_t)c->n_fslots * B * c->np3);
   c->rows = P.take<uint32_t>((size_t)c->n_fslots * (B * c->nm * c->nm + 1));
   c->keys = P.take<uint32_t>(B * c->np3);
   c->keys_sorted = P.take<uint32_t>(B * c->np3);
@@ -201,6 +207,8 @@ void plan(pmr_ctx* c, Plan& P) {
   }
   c->sort_scratch = P.take<char>(c->sort_scratch_bytes);
   c->ids_o = P.take<uint32_t>(B * c->np3);
+  c->frac_o = P.take<float4>(B * c->np3);
+  c->vstream = P.take<float4>(B * c->np3);
   c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
   c->dens = P.take<float>(B * c->nm3);
   c->cA = P.take<float2>(B * c->cmax);
@@ -384,6 +392,8 @@ void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, con
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
 float* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * 3 * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
+uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
+float4* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
 uint32_t* rowslot(pmr_ctx* c, int s) { return c->rows + (size_t)s * (c->B * c->nm * c->nm + 1); }
 int xs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
@@ -397,13 +407,15 @@ void pm_step(pmr_ctx* c, int i) {
   const int fsl = fs_of(c, i);
   double* x = xslot(c, xsl);
   double* xn = xslot(c, xsl + 1);
-  launch_sort(c->keys, total, c->key_bits_m, c->keys_sorted, idslot(c, fsl), c->sort_scratch,
+  launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
               c->stream);
-  launch_row_start(c->keys_sorted, total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl), c->stream);
-  const double scale_m = (double)c->nm / c->cfg.box;
+  launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
+                   c->stream);
+  launch_stream_frac(idslot(c, fsl), x, total, c->log_np3, c->nm, c->cfg.box, fracslot(c, fsl),
+                     c->stream);
   {
     ProfScope ps(c, PMR_PROF_PAINT, 24.0 * B * c->np3 + 4.0 * B * c->nm3);
-    launch_paint_mass(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m, c->mass_m,
+    launch_paint_mass(keyslot(c, fsl), fracslot(c, fsl), rowslot(c, fsl), B, c->nm, c->mass_m,
                       1.f, c->dens, c->stream);
   }
   const size_t cm = c->cm;
@@ -595,8 +607,8 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   double* xn = xslot(c, final_xslot(c));
   launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, s);
   launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
-  launch_paint_mass(xn, c->ids_o, c->rows_o, B, c->log_np3, c->no, (double)c->no / c->cfg.box,
-                    c->mass_o, 1.f, c->delta_f, s);
+  launch_stream_frac(c->ids_o, xn, total, c->log_np3, c->no, c->cfg.box, c->frac_o, s);
+  launch_paint_mass(c->keys_sorted, c->frac_o, c->rows_o, B, c->no, c->mass_o, 1.f, c->delta_f, s);
   // H9-H11: halo model and likelihood
   if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
     launch_sumsq(c->delta_f, c->target, c->no3, B, c->partial, c->data, s);
@@ -699,10 +711,12 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const int fsl = fs_of(c, i);
     const double* x = xslot(c, xs_of(c, i));
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
+    launch_stream_adj(idslot(c, fsl), c->pbar, c->xbar, (int)(B * c->np3), c->log_np3, K, Dr,
+                      c->vstream, s);
     {
-      ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 24.0) * B * c->np3 + 12.0 * B * c->nm3);
-      launch_paint_adj3(x, idslot(c, fsl), rowslot(c, fsl), B, c->log_np3, c->nm, scale_m,
-                        c->pbar, c->xbar, K, Dr, c->Fbar, s);
+      ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 12.0 * B * c->nm3);
+      launch_paint_adj3(keyslot(c, fsl), fracslot(c, fsl), c->vstream, rowslot(c, fsl), B, c->nm,
+                        c->Fbar, s);
     }
     r2c_zy(c, c->nm, 3, c->Fbar, 3 * c->nm3, c->nm3, nullptr, 1.f, 0.f, nullptr, c->cB, 3 * cm, cm);
     XPassArgs a = xargs(c, c->nm);
@@ -883,6 +897,16 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 
+int pmr_fft_set_tile(int n, int columns, int threads) {
+  return set_fft_tile(n, columns, threads) == 0 ? PMR_OK : PMR_E_INVALID;
+}
+
+int pmr_fft_get_tile(int n, int* columns, int* threads) {
+  if (!columns || !threads || !pow2_in(n, 16, 512)) return PMR_E_INVALID;
+  get_fft_tile(n, columns, threads);
+  return PMR_OK;
+}
+
 size_t pmr_sort_scratch_bytes(int n_total, int n_mesh, int batch) {
   if (n_total < 1 || !pow2_in(n_mesh, 16, 512) || batch < 1) return 0;
   return sort_scratch_bytes(n_total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh)) +
@@ -913,13 +937,23 @@ int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
 }
 
 int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x,
-                  const uint32_t* ids_sorted, const uint32_t* row_start, float mass, float bias,
-                  float* out, void* stream) {
-  if (!x || !ids_sorted || !row_start || !out || !(box > 0) || batch < 1) return PMR_E_INVALID;
+                  const uint32_t* keys_sorted, const uint32_t* ids_sorted,
+                  const uint32_t* row_start, float mass, float bias, float* out, void* scratch,
+                  size_t scratch_bytes, void* stream) {
+  if (!x || !keys_sorted || !ids_sorted || !row_start || !out || !scratch || !(box > 0) ||
+      batch < 1)
+    return PMR_E_INVALID;
   if (!pow2_in(n_part, 16, 512) || !pow2_in(n_mesh, 16, 512)) return PMR_E_SHAPE;
   const size_t np3 = (size_t)n_part * n_part * n_part;
-  launch_paint_mass(x, ids_sorted, row_start, batch, ilog2(np3), n_mesh, (double)n_mesh / box,
-                    mass, bias, out, (hipStream_t)stream);
+  if ((double)batch * np3 >= 2147483648.0 ||
+      (double)batch * n_mesh * n_mesh * n_mesh > 4294967296.0)
+    return PMR_E_SHAPE;
+  const int total = (int)(batch * np3);
+  if (scratch_bytes < (size_t)total * sizeof(float4)) return PMR_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  float4* frac = (float4*)scratch;
+  launch_stream_frac(ids_sorted, x, total, ilog2(np3), n_mesh, box, frac, s);
+  launch_paint_mass(keys_sorted, frac, row_start, batch, n_mesh, mass, bias, out, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 

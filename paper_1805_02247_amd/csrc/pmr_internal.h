@@ -99,6 +99,8 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
                       const float* add, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
+int set_fft_tile(int n, int pc, int nth);
+void get_fft_tile(int n, int* pc, int* nth);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);
@@ -108,12 +110,14 @@ void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
                       uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
                  hipStream_t s);
-void launch_paint_mass(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
-                       int log_np3, int nm, double scale, float mass, float bias, float* out,
-                       hipStream_t s);
-void launch_paint_adj3(const double* x, const uint32_t* ids, const uint32_t* row_start, int batch,
-                       int log_np3, int nm, double scale, const float* pbar, const float* xbar,
-                       float kick, float drift, float* out, hipStream_t s);
+void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,
+                        double box, float4* frac, hipStream_t s);
+void launch_stream_adj(const uint32_t* ids, const float* pbar, const float* xbar, int total,
+                       int log_np3, float kick, float drift, float4* val, hipStream_t s);
+void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
+                       int batch, int nm, float mass, float bias, float* out, hipStream_t s);
+void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
+                       const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
 void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
                        int batch, int log_np3, int nm, double box, float kick, double drift,
                        int key_nm, hipStream_t s);

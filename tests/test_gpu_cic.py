@@ -56,10 +56,10 @@ def test_paint_matches_oracle_and_is_reproducible(B, npart, nm):
     say(f"paint B={B} np={npart} nm={nm}")
     x = _clustered(B * 7 + nm, B, npart, box)
     xt = torch.from_numpy(x).to(DEV)
-    _, ids, rows = api.cic_sort(xt, nm, box)
+    keys, ids, rows = api.cic_sort(xt, nm, box)
     mass = (nm / npart) ** 3
-    d1 = api.cic_paint(xt, ids, rows, nm, box, mass, 1.0)
-    d2 = api.cic_paint(xt, ids, rows, nm, box, mass, 1.0)
+    d1 = api.cic_paint(xt, keys, ids, rows, nm, box, mass, 1.0)
+    d2 = api.cic_paint(xt, keys, ids, rows, nm, box, mass, 1.0)
     assert torch.equal(d1, d2)
     got = d1.cpu().numpy()
     for b in range(B):
@@ -78,8 +78,8 @@ def test_paint_empty_rows_and_single_particle():
     x = np.full((1, 3, npart ** 3), 5.25)
     x[0, 2] = 7.5
     xt = torch.from_numpy(x).to(DEV)
-    _, ids, rows = api.cic_sort(xt, nm, box)
-    d = api.cic_paint(xt, ids, rows, nm, box, 1.0, 0.0).cpu().numpy()[0].reshape(nm, nm, nm)
+    keys, ids, rows = api.cic_sort(xt, nm, box)
+    d = api.cic_paint(xt, keys, ids, rows, nm, box, 1.0, 0.0).cpu().numpy()[0].reshape(nm, nm, nm)
     ref = M.cic_paint(x[0], nm, box, np.ones(npart ** 3))
     np.testing.assert_allclose(d, ref, rtol=1e-6)
     assert np.count_nonzero(d) == 8

@@ -12,7 +12,8 @@ from _gpu import DEV, cosine, rel_l2, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0.1):
+def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0.1,
+             prior_weight=1.0):
     ocfg = OM.Config(box, n, nm, no, steps, loss_kind=kind)
     power = OC.bbks_power()
     inv = OM.prior_inv_variance(n, box, power)
@@ -23,7 +24,8 @@ def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0
         st = OM.linear_modes(synth.white_noise(seed + 10 * b + 5, n), box, power)
         if kind == OM.LOSS_LOGNORMAL:
             t = OM.forward(ocfg, st, inv, np.ones((no,) * 3), OM.default_params(), w)["mass"]
-            prm = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=R_sm[b % len(R_sm)], mu=mu)
+            prm = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=R_sm[b % len(R_sm)], mu=mu,
+                                    prior_weight=prior_weight)
         else:
             t = OM.forward(ocfg, st, inv, np.zeros((no,) * 3), OM.default_params())["delta_f"]
             prm = OM.default_params(prior_weight=0.0)
@@ -100,6 +102,16 @@ def test_lognormal_batch_with_anneal_stages():
     require_gpu()
     say("pipeline: log-normal 32^3, B=2")
     prob = _problem(32, 32, 32, 100.0, 4, OM.LOSS_LOGNORMAL, 2, hidden=32, R_sm=(0.0, 4.0))
+    res = _gpu_run(*prob, hidden=32)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_lognormal_data_term_alone():
+    """Prior weight 0: the gradient is the data term's alone (PM + network + likelihood)."""
+    require_gpu()
+    say("pipeline: log-normal data term only, 32^3")
+    prob = _problem(32, 32, 32, 100.0, 5, OM.LOSS_LOGNORMAL, 2, hidden=32, R_sm=(2.0, 0.0),
+                    prior_weight=0.0)
     res = _gpu_run(*prob, hidden=32)
     _compare(*prob, res, TOL_FP32)
 
