@@ -34,8 +34,20 @@ __device__ __forceinline__ uint32_t cell_key(const double* xyz, double scale, in
   return item * cells + ((uint32_t)ix * nm + iy) * nm + iz;
 }
 
+// Key and CIC fractions (id order) of one particle on an nm mesh.
+__device__ __forceinline__ uint32_t key_frac(const double* xyz, double scale, int nm, uint32_t item,
+                                             float4* frac) {
+  double f[3];
+  const int ix = cic_corner(xyz[0], scale, nm, &f[0]);
+  const int iy = cic_corner(xyz[1], scale, nm, &f[1]);
+  const int iz = cic_corner(xyz[2], scale, nm, &f[2]);
+  *frac = make_float4((float)f[0], (float)f[1], (float)f[2], 0.f);
+  const uint32_t cells = (uint32_t)nm * nm * nm;
+  return item * cells + ((uint32_t)ix * nm + iy) * nm + iz;
+}
+
 __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total, double scale,
-                            int nm, uint32_t* __restrict__ keys) {
+                            int nm, uint32_t* __restrict__ keys, float4* __restrict__ frac) {
   const int g = blockIdx.x * TB + threadIdx.x;
   if (g >= total) return;
   const size_t np3 = (size_t)1 << log_np3;
@@ -43,7 +55,9 @@ __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total
   const size_t id = g & (np3 - 1);
   const double* xi = x + (size_t)item * 3 * np3 + id;
   double p[3] = {xi[0], xi[np3], xi[2 * np3]};
-  keys[g] = cell_key(p, scale, nm, item, (uint32_t)nm * nm * nm);
+  float4 f;
+  keys[g] = key_frac(p, scale, nm, item, &f);
+  if (frac) frac[g] = f;
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -87,8 +101,9 @@ __global__ __launch_bounds__(TB) void radix_hist_kernel(const uint32_t* __restri
 }
 
 // Stable scatter. Key j of the tile is handled by wave w = (j / 64) / ITEMS in order, so
-// ranks follow j: rank = offset[digit][block] + (same digit in earlier waves)
-//                      + (same digit earlier in this wave).
+// ranks follow j: local rank = (same digit in earlier waves) + (same digit earlier in this
+// wave). The tile is first placed in LDS in digit order, then each digit's run is written
+// to its global range [offset[digit][block], ...) contiguously.
 // ids_in == nullptr means identity payload (id = index).
 template <int D>
 __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
@@ -96,14 +111,22 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
                                                            int n, int shift,
                                                            const uint32_t* __restrict__ offsets,
                                                            uint32_t* __restrict__ keys_out,
-                                                           uint32_t* __restrict__ ids_out) {
+                                                           uint32_t* __restrict__ ids_out,
+                                                           const float4* __restrict__ pay_in,
+                                                           float4* __restrict__ pay_out) {
   constexpr int NBK = 1 << D;
   __shared__ uint32_t cnt[SORT_WAVES][NBK];
+  __shared__ uint32_t dstart[NBK];   // block-local start of each digit
+  __shared__ uint32_t gbase[NBK];    // global start of each digit for this block
+  __shared__ uint32_t skey[SORT_TILE];
+  __shared__ uint32_t sid[SORT_TILE];
+  __shared__ uint32_t wsum[TB / 64];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < SORT_WAVES * NBK; i += TB) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)w * PMR_WAVE * SORT_ITEMS;
+  const size_t tile0 = (size_t)blockIdx.x * SORT_TILE;
+  const size_t base = tile0 + (size_t)w * PMR_WAVE * SORT_ITEMS;
   uint32_t key[SORT_ITEMS], id[SORT_ITEMS], rank[SORT_ITEMS];
   const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -124,26 +147,73 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS update visible to the next item
   }
   __syncthreads();
-  // exclusive prefix over waves, seeded with the global offset of (digit, block)
-  for (int d = threadIdx.x; d < NBK; d += TB) {
-    uint32_t run = offsets[(size_t)d * gridDim.x + blockIdx.x];
+  // per digit: exclusive prefix over waves, and the block total
+  uint32_t tot_local[(NBK + TB - 1) / TB];
 #pragma unroll
-    for (int ww = 0; ww < SORT_WAVES; ++ww) {
-      const uint32_t c = cnt[ww][d];
-      cnt[ww][d] = run;
-      run += c;
+  for (int q = 0; q < (NBK + TB - 1) / TB; ++q) {
+    const int d = threadIdx.x + q * TB;
+    uint32_t run = 0;
+    if (d < NBK) {
+#pragma unroll
+      for (int ww = 0; ww < SORT_WAVES; ++ww) {
+        const uint32_t c = cnt[ww][d];
+        cnt[ww][d] = run;
+        run += c;
+      }
+      gbase[d] = offsets[(size_t)d * gridDim.x + blockIdx.x];
+    }
+    tot_local[q] = run;
+  }
+  // exclusive scan of the block totals over digits (digit d = thread + q * TB)
+  {
+    uint32_t carry = 0;
+#pragma unroll
+    for (int q = 0; q < (NBK + TB - 1) / TB; ++q) {
+      const uint32_t v = tot_local[q];
+      // wave-level inclusive scan
+      uint32_t x = v;
+#pragma unroll
+      for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t y = __shfl_up(x, dd, 64);
+        if (lane >= dd) x += y;
+      }
+      if (lane == 63) wsum[w] = x;
+      __syncthreads();
+      uint32_t wpre = 0, total = 0;
+#pragma unroll
+      for (int ww = 0; ww < TB / 64; ++ww) {
+        const uint32_t sv = wsum[ww];
+        if (ww < w) wpre += sv;
+        total += sv;
+      }
+      const int d = threadIdx.x + q * TB;
+      if (d < NBK) dstart[d] = carry + wpre + x - v;
+      carry += total;
+      __syncthreads();
     }
   }
   __syncthreads();
+  // place the tile in LDS in (digit, rank) order
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const size_t j = base + (size_t)it * PMR_WAVE + lane;
     if (j < (size_t)n) {
       const uint32_t d = (key[it] >> shift) & (NBK - 1);
-      const uint32_t dst = cnt[w][d] + rank[it];
-      keys_out[dst] = key[it];
-      ids_out[dst] = id[it];
+      const uint32_t lp = dstart[d] + cnt[w][d] + rank[it];
+      skey[lp] = key[it];
+      sid[lp] = id[it];
     }
+  }
+  __syncthreads();
+  const int count = (int)min((size_t)SORT_TILE, (size_t)n - tile0);
+  for (int e = threadIdx.x; e < count; e += TB) {
+    const uint32_t k = skey[e];
+    const uint32_t d = (k >> shift) & (NBK - 1);
+    const uint32_t dst = gbase[d] + (uint32_t)e - dstart[d];
+    const uint32_t idv = sid[e];
+    keys_out[dst] = k;
+    ids_out[dst] = idv;
+    if (pay_out) pay_out[dst] = pay_in[idv];
   }
 }
 
@@ -244,21 +314,13 @@ __global__ __launch_bounds__(TB) void stream_frac_kernel(const uint32_t* __restr
   frac[j] = make_float4((float)fx, (float)fy, (float)fz, 0.f);
 }
 
-// Per sorted position j: the adjoint paint values kick * (pbar + drift * xbar) of ids[j].
-__global__ __launch_bounds__(TB) void stream_adj_kernel(const uint32_t* __restrict__ ids,
-                                                        const float* __restrict__ pbar,
-                                                        const float* __restrict__ xbar, int total,
-                                                        int log_np3, float kick, float drift,
-                                                        float4* __restrict__ val) {
+// Per sorted position j: the payload of particle ids[j] (id-order float4 -> sorted order).
+__global__ __launch_bounds__(TB) void stream_gather_kernel(const uint32_t* __restrict__ ids,
+                                                           const float4* __restrict__ src,
+                                                           int total, float4* __restrict__ dst) {
   const int j = blockIdx.x * TB + threadIdx.x;
   if (j >= total) return;
-  const size_t np3 = (size_t)1 << log_np3;
-  const uint32_t g = ids[j];
-  const size_t pi = (size_t)(g >> log_np3) * 3 * np3 + (g & (np3 - 1));
-  float v[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = kick * (pbar[pi + c * np3] + drift * xbar[pi + c * np3]);
-  val[j] = make_float4(v[0], v[1], v[2], 0.f);
+  dst[j] = src[ids[j]];
 }
 
 // ---------------------------------------------------------------- paint
@@ -304,14 +366,23 @@ __device__ __forceinline__ void seg_step(float (&v)[NV], uint32_t key) {
   }
 }
 
+// Only the steps the chunk needs run (wave-uniform): with eq = lanes whose key equals the
+// previous lane's, the longest run of set bits bounds the within-row shifts, and the
+// row-crossing steps run only when a segment crosses lane 16/48 or 32.
 template <int NV>
 __device__ __forceinline__ void seg_scan(float (&v)[NV], uint32_t key) {
-  seg_step<NV, 0x111, 0xF>(v, key);  // row_shr:1
-  seg_step<NV, 0x112, 0xF>(v, key);  // row_shr:2
-  seg_step<NV, 0x114, 0xF>(v, key);  // row_shr:4
-  seg_step<NV, 0x118, 0xF>(v, key);  // row_shr:8
-  seg_step<NV, 0x142, 0xA>(v, key);  // row_bcast:15 into rows 1, 3
-  seg_step<NV, 0x143, 0xC>(v, key);  // row_bcast:31 into rows 2, 3
+  const uint32_t kp = __shfl_up(key, 1, 64);
+  const int lane = threadIdx.x & 63;
+  const uint64_t eq = __ballot(lane > 0 && kp == key);
+  if (eq == 0) return;
+  int run = 0;  // longest run of ones in eq
+  for (uint64_t m = eq; m; m &= (m >> 1)) ++run;
+  seg_step<NV, 0x111, 0xF>(v, key);                       // row_shr:1
+  if (run >= 2) seg_step<NV, 0x112, 0xF>(v, key);         // row_shr:2
+  if (run >= 4) seg_step<NV, 0x114, 0xF>(v, key);         // row_shr:4
+  if (run >= 8) seg_step<NV, 0x118, 0xF>(v, key);         // row_shr:8
+  if (eq & ((1ull << 16) | (1ull << 48))) seg_step<NV, 0x142, 0xA>(v, key);  // row_bcast:15
+  if (eq & (1ull << 32)) seg_step<NV, 0x143, 0xC>(v, key);  // row_bcast:31
 }
 
 // One 64-particle chunk of a source run: per lane the four (oy, oz) weights of each channel.
@@ -361,8 +432,14 @@ __device__ __forceinline__ void load_chunk(const PaintArgs& a, uint32_t j, uint3
   }
 }
 
-// Last lane of each run adds the run's sums to its two target rows; one LDS word per lane
-// per instruction.
+// Last lane of each run adds the run's sums to its two target rows. The accumulator is
+// private to the wavefront and, within one phase below, the tails of a chunk touch
+// distinct words, so a plain read-add-write is race-free inside a phase. Different phases
+// (and chunks) may touch the same word from different lanes: a compiler barrier keeps the
+// phases in program order, and LDS instructions of one wavefront execute in issue order,
+// so every word receives its additions in one fixed order.
+#define PMR_PHASE_FENCE() asm volatile("" ::: "memory")
+
 template <int C, int TY>
 __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, int iy0) {
   const int lane = threadIdx.x & 63;
@@ -371,20 +448,16 @@ __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, 
   const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
   const int iz1 = (ch.iz + 1) & (nm - 1);
 #pragma unroll
-  for (int oy = 0; oy < 2; ++oy) {
+  for (int ph = 0; ph < 4; ++ph) {
+    const int oy = ph >> 1, oz = ph & 1;
     const int jt = ((ch.sy + oy) & (nm - 1)) - iy0;
-    const bool in = tail && jt >= 0 && jt < TY;
-    float* row = acc + (size_t)jt * C * nm;
-    if (in) {
+    PMR_PHASE_FENCE();
+    if (tail && jt >= 0 && jt < TY) {
+      float* row = acc + (size_t)jt * C * nm + (oz ? iz1 : ch.iz);
 #pragma unroll
-      for (int c = 0; c < C; ++c) atomicAdd(&row[c * nm + ch.iz], ch.v[4 * c + 2 * oy]);
+      for (int c = 0; c < C; ++c) row[c * nm] = row[c * nm] + ch.v[4 * c + 2 * oy + oz];
     }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    if (in) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) atomicAdd(&row[c * nm + iz1], ch.v[4 * c + 2 * oy + 1]);
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
+    PMR_PHASE_FENCE();
   }
 }
 
@@ -475,6 +548,7 @@ struct StepArgs {
   float* p;           // momenta, updated in place
   const float* F;     // [B][3][nm^3] force meshes at x_i
   uint32_t* keys;     // keys of x_{i+1} (nullable)
+  float4* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
   int log_np3, nm, total;
   double scale, box;
   float kick;
@@ -515,8 +589,9 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
     a.x_next[pi + q * np3] = xn[q];
   }
   if (a.keys) {
-    const uint32_t kn = (uint32_t)a.key_nm;
-    a.keys[g] = cell_key(xn, a.key_scale, a.key_nm, item, kn * kn * kn);
+    float4 f;
+    a.keys[g] = key_frac(xn, a.key_scale, a.key_nm, item, &f);
+    a.frac[g] = f;
   }
 }
 
@@ -530,6 +605,8 @@ struct AdjArgs {
   double scale;
   float kick, drift, mass;
   int final_mode;      // 1: xbar = mass * grad(dbar), pbar = 0
+  float4* vnext;       // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
+  float kick_next, drift_next;  // reverse step (its adjoint paint values), id order
 };
 
 // Step adjoint (reverse of kick then drift):
@@ -573,12 +650,17 @@ __global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
     gy += wx * dy * wz * v;
     gz += wx * wy * dz * v;
   }
-  a.xbar[pi] = xb[0] + gx;
-  a.xbar[pi + np3] = xb[1] + gy;
-  a.xbar[pi + 2 * np3] = xb[2] + gz;
+  const float xn[3] = {xb[0] + gx, xb[1] + gy, xb[2] + gz};
+  a.xbar[pi] = xn[0];
+  a.xbar[pi + np3] = xn[1];
+  a.xbar[pi + 2 * np3] = xn[2];
   a.pbar[pi] = pb[0];
   a.pbar[pi + np3] = pb[1];
   a.pbar[pi + 2 * np3] = pb[2];
+  if (a.vnext)
+    a.vnext[g] = make_float4(a.kick_next * (pb[0] + a.drift_next * xn[0]),
+                             a.kick_next * (pb[1] + a.drift_next * xn[1]),
+                             a.kick_next * (pb[2] + a.drift_next * xn[2]), 0.f);
 }
 
 // Zel'dovich start: x0 = wrap(q + D0 Psi), p0 = Gp0 Psi; q = idx * (box/np) + box / (2 nm).
@@ -586,7 +668,8 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
                                                      int log_np3, int total, double box,
                                                      double half_cell, double D0, float Gp0,
                                                      double* __restrict__ x, float* __restrict__ p,
-                                                     uint32_t* __restrict__ keys, int key_nm,
+                                                     uint32_t* __restrict__ keys,
+                                                     float4* __restrict__ frac, int key_nm,
                                                      double key_scale) {
   const int g = blockIdx.x * TB + threadIdx.x;
   if (g >= total) return;
@@ -605,8 +688,9 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
     x[pi + q * np3] = xn[q];
     p[pi + q * np3] = Gp0 * ps;
   }
-  const uint32_t kn = (uint32_t)key_nm;
-  keys[g] = cell_key(xn, key_scale, key_nm, item, kn * kn * kn);
+  float4 f;
+  keys[g] = key_frac(xn, key_scale, key_nm, item, &f);
+  frac[g] = f;
 }
 
 }  // namespace
@@ -625,7 +709,7 @@ size_t sort_scratch_bytes(int n, int key_bits) {
 template <int D>
 static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
                       int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* sums,
-                      hipStream_t s) {
+                      const float4* pin, float4* pout, hipStream_t s) {
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
   const size_t hn = (size_t)nb << D;
   radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
@@ -633,13 +717,14 @@ static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, 
   scan_reduce_kernel<<<ns, TB, 0, s>>>(hist, hn, sums);
   scan_small_kernel<<<1, TB, 0, s>>>(sums, ns);
   scan_down_kernel<<<ns, TB, 0, s>>>(hist, hn, sums, offs);
-  radix_scatter_kernel<D><<<nb, TB, 0, s>>>(kin, iin, n, shift, offs, kout, iout);
+  radix_scatter_kernel<D><<<nb, TB, 0, s>>>(kin, iin, n, shift, offs, kout, iout, pin, pout);
 }
 
 // Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
 // and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
 void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, hipStream_t s) {
+                 uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
+                 hipStream_t s) {
   const int passes = (key_bits + 8) / 9;
   const int D = (key_bits + passes - 1) / passes;
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
@@ -661,7 +746,10 @@ void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
     const int shift = p * D;
     switch (D) {
 #define CASE(DD) \
-  case DD: sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, sums, s); break;
+  case DD:                                                                                  \
+    sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, sums, last ? pay_in : nullptr,      \
+                  last ? pay_out : nullptr, s);                                                \
+    break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 #undef CASE
       default: break;
@@ -677,8 +765,8 @@ void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
 }
 
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
-                 hipStream_t s) {
-  keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys);
+                 float4* frac, hipStream_t s) {
+  keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys, frac);
 }
 
 // Rows per wave: keep the wave's LDS accumulator within 2048 floats.
@@ -715,10 +803,9 @@ void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log
                                                           (double)nm / box, nm, frac);
 }
 
-void launch_stream_adj(const uint32_t* ids, const float* pbar, const float* xbar, int total,
-                       int log_np3, float kick, float drift, float4* val, hipStream_t s) {
-  stream_adj_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, pbar, xbar, total, log_np3, kick,
-                                                         drift, val);
+void launch_stream_gather(const uint32_t* ids, const float4* src, int total, float4* dst,
+                          hipStream_t s) {
+  stream_gather_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, src, total, dst);
 }
 
 void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
@@ -753,9 +840,10 @@ void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* v
 }
 
 void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
-                       int batch, int log_np3, int nm, double box, float kick, double drift,
-                       int key_nm, hipStream_t s) {
+                       float4* frac, int batch, int log_np3, int nm, double box, float kick,
+                       double drift, int key_nm, hipStream_t s) {
   StepArgs a{};
+  a.frac = frac;
   a.x = x;
   a.x_next = x_next;
   a.p = p;
@@ -775,8 +863,12 @@ void launch_kick_drift(const double* x, double* x_next, float* p, const float* F
 
 void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
                            const float* dbar, int batch, int log_np3, int nm, double box,
-                           float kick, float drift, float mass, int final_mode, hipStream_t s) {
+                           float kick, float drift, float mass, int final_mode, float4* vnext,
+                           float kick_next, float drift_next, hipStream_t s) {
   AdjArgs a{};
+  a.vnext = vnext;
+  a.kick_next = kick_next;
+  a.drift_next = drift_next;
   a.x = x;
   a.xbar = xbar;
   a.pbar = pbar;
@@ -794,11 +886,11 @@ void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const floa
 }
 
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, int key_nm,
-                    hipStream_t s) {
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
+                    int key_nm, hipStream_t s) {
   const int total = batch << log_np3;
   za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, np, log_np3, total, box, half_cell, D0,
-                                                       Gp0, x, p, keys, key_nm,
+                                                       Gp0, x, p, keys, frac, key_nm,
                                                        (double)key_nm / box);
 }
 

@@ -114,7 +114,9 @@ struct pmr_ctx {
   size_t sort_scratch_bytes;
   uint32_t* ids_o;
   float4* frac_o;
-  float4* vstream;  // sorted adjoint paint values [B*np3]
+  float4* frac_id;  // CIC fractions of the current positions, id order [B*np3]
+  float4* vid;      // adjoint paint values of the next reverse step, id order [B*np3]
+  float4* vstream;  // the same in sorted order [B*np3]
   uint32_t* rows_o;
   float* dens;   // [B][nm3]
   float2* cA;    // [B][cmax]
@@ -208,6 +210,8 @@ void plan(pmr_ctx* c, Plan& P) {
   c->sort_scratch = P.take<char>(c->sort_scratch_bytes);
   c->ids_o = P.take<uint32_t>(B * c->np3);
   c->frac_o = P.take<float4>(B * c->np3);
+  c->frac_id = P.take<float4>(B * c->np3);
+  c->vid = P.take<float4>(B * c->np3);
   c->vstream = P.take<float4>(B * c->np3);
   c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
   c->dens = P.take<float>(B * c->nm3);
@@ -408,11 +412,9 @@ void pm_step(pmr_ctx* c, int i) {
   double* x = xslot(c, xsl);
   double* xn = xslot(c, xsl + 1);
   launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
-              c->stream);
+              c->frac_id, fracslot(c, fsl), c->stream);
   launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
                    c->stream);
-  launch_stream_frac(idslot(c, fsl), x, total, c->log_np3, c->nm, c->cfg.box, fracslot(c, fsl),
-                     c->stream);
   {
     ProfScope ps(c, PMR_PROF_PAINT, 24.0 * B * c->np3 + 4.0 * B * c->nm3);
     launch_paint_mass(keyslot(c, fsl), fracslot(c, fsl), rowslot(c, fsl), B, c->nm, c->mass_m,
@@ -436,7 +438,7 @@ void pm_step(pmr_ctx* c, int i) {
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
   {
     ProfScope ps(c, PMR_PROF_KICK_DRIFT, 76.0 * B * c->np3 + 12.0 * B * c->nm3);
-    launch_kick_drift(x, xn, c->p, F, c->keys, B, c->log_np3, c->nm, c->cfg.box,
+    launch_kick_drift(x, xn, c->p, F, c->keys, c->frac_id, B, c->log_np3, c->nm, c->cfg.box,
                       (float)c->kick[i], c->drift[i], key_nm, c->stream);
   }
 }
@@ -598,16 +600,16 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->psi, 3 * c->np3, c->np3, nullptr);
     const int key_nm = c->n == 0 ? c->no : c->nm;
     launch_za_init(c->psi, B, c->np, c->log_np3, c->cfg.box, 0.5 * (c->cfg.box / c->nm), c->D0,
-                   (float)c->Gp0, xslot(c, 0), c->p, c->keys, key_nm, s);
+                   (float)c->Gp0, xslot(c, 0), c->p, c->keys, c->frac_id, key_nm, s);
   }
   // H2-H7: the PM steps
   pm_run(c, 0, c->n, true);
   // H8: final paint on the output mesh
   const int total = (int)(B * c->np3);
   double* xn = xslot(c, final_xslot(c));
-  launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, s);
+  launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, c->frac_id,
+              c->frac_o, s);
   launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
-  launch_stream_frac(c->ids_o, xn, total, c->log_np3, c->no, c->cfg.box, c->frac_o, s);
   launch_paint_mass(c->keys_sorted, c->frac_o, c->rows_o, B, c->no, c->mass_o, 1.f, c->delta_f, s);
   // H9-H11: halo model and likelihood
   if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
@@ -689,7 +691,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
   // H14: final-paint adjoint -> xbar_n, pbar = 0
   const double* xn = xslot(c, final_xslot(c));
   launch_adjoint_gather(xn, c->xbar, c->pbar, nullptr, dbar_f, B, c->log_np3, c->no, c->cfg.box,
-                        0.f, 0.f, c->mass_o, 1, s);
+                        0.f, 0.f, c->mass_o, 1, c->vid, (float)c->kick[c->n - 1],
+                        (float)c->drift[c->n - 1], s);
   // H15: reverse PM steps (recomputing segments from checkpoints when needed)
   const size_t cm = c->cm;
   const double scale_m = (double)c->nm / c->cfg.box;
@@ -703,7 +706,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
                      hipMemcpyDeviceToDevice, s));
       HIPC(c, hipMemcpyAsync(c->p, c->ckp + (size_t)(j / c->k) * B * 3 * c->np3, pbytes,
                      hipMemcpyDeviceToDevice, s));
-      launch_keys(xslot(c, 0), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys, s);
+      launch_keys(xslot(c, 0), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys, c->frac_id,
+                  s);
       const int end = j + c->k < c->n ? j + c->k : c->n;
       for (int q = j; q < end; ++q) pm_step(c, q);
       resident_lo = j;
@@ -711,8 +715,7 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const int fsl = fs_of(c, i);
     const double* x = xslot(c, xs_of(c, i));
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
-    launch_stream_adj(idslot(c, fsl), c->pbar, c->xbar, (int)(B * c->np3), c->log_np3, K, Dr,
-                      c->vstream, s);
+    launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
     {
       ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 12.0 * B * c->nm3);
       launch_paint_adj3(keyslot(c, fsl), fracslot(c, fsl), c->vstream, rowslot(c, fsl), B, c->nm,
@@ -734,7 +737,9 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     {
       ProfScope ps(c, PMR_PROF_ADJ_GATHER, (24.0 + 24.0 + 24.0) * B * c->np3 + 16.0 * B * c->nm3);
       launch_adjoint_gather(x, c->xbar, c->pbar, fslot(c, fsl), c->dbar, B, c->log_np3, c->nm,
-                            c->cfg.box, K, Dr, c->mass_m, 0, s);
+                            c->cfg.box, K, Dr, c->mass_m, 0, i > 0 ? c->vid : nullptr,
+                            i > 0 ? (float)c->kick[i - 1] : 0.f,
+                            i > 0 ? (float)c->drift[i - 1] : 0.f, s);
     }
   }
   // H16: Zel'dovich adjoint and gradient assembly (with the prior)
@@ -928,9 +933,9 @@ int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
   hipStream_t s = (hipStream_t)stream;
   uint32_t* keys = (uint32_t*)scratch;
   void* rest = (char*)scratch + 2 * align256((size_t)total * sizeof(uint32_t));
-  launch_keys(x, ilog2(np3), total, (double)n_mesh / box, n_mesh, keys, s);
+  launch_keys(x, ilog2(np3), total, (double)n_mesh / box, n_mesh, keys, nullptr, s);
   launch_sort(keys, total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh), keys_sorted,
-              ids_sorted, rest, s);
+              ids_sorted, rest, nullptr, nullptr, s);
   launch_row_start(keys_sorted, total, ilog2((size_t)n_mesh), batch * n_mesh * n_mesh, row_start,
                    s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;

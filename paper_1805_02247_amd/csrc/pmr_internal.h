@@ -104,29 +104,32 @@ void get_fft_tile(int n, int* pc, int* nth);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);
+// Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr.
 void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, hipStream_t s);
+                 uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
+                 hipStream_t s);
 void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
                       uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
-                 hipStream_t s);
+                 float4* frac, hipStream_t s);
 void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,
                         double box, float4* frac, hipStream_t s);
-void launch_stream_adj(const uint32_t* ids, const float* pbar, const float* xbar, int total,
-                       int log_np3, float kick, float drift, float4* val, hipStream_t s);
+void launch_stream_gather(const uint32_t* ids, const float4* src, int total, float4* dst,
+                          hipStream_t s);
 void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s);
 void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
                        const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
 void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
-                       int batch, int log_np3, int nm, double box, float kick, double drift,
-                       int key_nm, hipStream_t s);
+                       float4* frac, int batch, int log_np3, int nm, double box, float kick,
+                       double drift, int key_nm, hipStream_t s);
 void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
                            const float* dbar, int batch, int log_np3, int nm, double box,
-                           float kick, float drift, float mass, int final_mode, hipStream_t s);
+                           float kick, float drift, float mass, int final_mode, float4* vnext,
+                           float kick_next, float drift_next, hipStream_t s);
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, int key_nm,
-                    hipStream_t s);
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
+                    int key_nm, hipStream_t s);
 
 // halo.hip
 size_t mlp_weight_floats(int H);
