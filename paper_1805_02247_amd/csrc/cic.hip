@@ -318,7 +318,7 @@ __global__ __launch_bounds__(TB) void stream_frac_kernel(const uint32_t* __restr
 __global__ __launch_bounds__(TB) void stream_gather_kernel(const uint32_t* __restrict__ ids,
                                                            const float4* __restrict__ src,
                                                            int total, float4* __restrict__ dst) {
-  const int j = blockIdx.x * TB + threadIdx.x;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= total) return;
   dst[j] = src[ids[j]];
 }
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(TB) void paint_kernel(PaintArgs a) {
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int nm = a.nm;
-  const int seg = blockIdx.x * (TB / 64) + w;  // (item, ix, column segment)
+  const int seg = xcd_block(blockIdx.x, gridDim.x) * (TB / 64) + w;  // (item, ix, segment)
   const int segs_per_x = nm / TY;
   const int item = seg / (nm * segs_per_x);
   const int rr = seg - item * nm * segs_per_x;
@@ -559,7 +559,7 @@ struct StepArgs {
 
 // p += kick * F(x_i);  x_{i+1} = wrap(x_i + drift * p);  key(x_{i+1})
 __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
-  const int g = blockIdx.x * TB + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (g >= a.total) return;
   const size_t np3 = (size_t)1 << a.log_np3;
   const int item = g >> a.log_np3;
@@ -613,7 +613,7 @@ struct AdjArgs {
 //   pbar' = pbar + drift * xbar;  Fbar = kick * pbar'
 //   xbar' = xbar + sum_cell dW(x - cell)/dx * (sum_a Fbar_a F_a(cell) + mass * dbar(cell))
 __global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
-  const int g = blockIdx.x * TB + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (g >= a.total) return;
   const size_t np3 = (size_t)1 << a.log_np3;
   const int item = g >> a.log_np3;

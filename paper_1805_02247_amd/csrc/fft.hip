@@ -1,563 +1,53 @@
-// 3-D real FFTs of n^3 meshes (n = 16..512, power of two), staged in LDS.
-//
-// Layout: real fields [n][n][n] row-major (z fastest); spectra [n][n][n/2+1] interleaved
-// complex (numpy rfftn layout). Forward transform unnormalised; every inverse path
-// carries its 1/n^3 inside the k-space operator of the outermost-axis pass.
-//
-// The transform is three passes, each reading and writing the whole array once:
-//   z pass : contiguous rows; r2c as an n/2-point complex FFT of (x_even + i x_odd)
-//            followed by the standard split step (c2r: the inverse split, then the FFT).
-//   y pass : lines of stride n/2+1; a workgroup owns 16 consecutive kz columns of one
-//            x-plane, so every global access is a 128-byte run.
-//   x pass : lines of stride n(n/2+1); same tiling. This pass sees complete k-vectors,
-//            so the k-space operators (force, Gaussian smoothing, their adjoints, the
-//            Zel'dovich displacement and the gradient assembly) run inside it,
-//            between a forward and an inverse transform, without extra HBM traffic.
-// Each line transform is a self-sorting Stockham FFT (radix 8, then 4 or 2) in LDS;
-// twiddles are evaluated once per workgroup in FP64 and rounded to FP32.
+// Host dispatch of the 3-D FFT passes over the supported sizes, and the tile-shape table.
+// The kernels live in fft_kernels.h, instantiated per size by fft_size.hip.
 #include "pmr_internal.h"
 
 namespace pmr {
-namespace {
 
-constexpr int NT = 256;   // threads per FFT workgroup (4 waves)
-constexpr int PCOL = 16;  // columns per strided-pass tile (16 complex = 128 B)
-
-// ---------------------------------------------------------------- butterflies
-template <int DIR>
-__device__ __forceinline__ void bfly2(float2* u) {
-  float2 a = u[0];
-  u[0] = cadd(a, u[1]);
-  u[1] = csub(a, u[1]);
-}
-
-template <int DIR>
-__device__ __forceinline__ void bfly4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
-  float2 t2 = cadd(a1, a3), t3 = cmul_i<DIR>(csub(a1, a3));
-  a0 = cadd(t0, t2);
-  a2 = csub(t0, t2);
-  a1 = cadd(t1, t3);
-  a3 = csub(t1, t3);
-}
-
-template <int DIR>
-__device__ __forceinline__ void bfly8(float2* u) {
-  const float c = 0.70710678118654752440f;
-  bfly4<DIR>(u[0], u[2], u[4], u[6]);
-  bfly4<DIR>(u[1], u[3], u[5], u[7]);
-  // odd half times omega_8^q, omega_8 = exp(DIR * 2 pi i / 8)
-  float2 o1 = u[3], o2 = u[5], o3 = u[7];
-  o1 = make_float2(c * (o1.x - DIR * o1.y), c * (o1.y + DIR * o1.x));
-  o2 = cmul_i<DIR>(o2);
-  o3 = make_float2(c * (-o3.x - DIR * o3.y), c * (DIR * o3.x - o3.y));
-  float2 e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6], o0 = u[1];
-  u[0] = cadd(e0, o0);
-  u[4] = csub(e0, o0);
-  u[1] = cadd(e1, o1);
-  u[5] = csub(e1, o1);
-  u[2] = cadd(e2, o2);
-  u[6] = csub(e2, o2);
-  u[3] = cadd(e3, o3);
-  u[7] = csub(e3, o3);
-}
-
-template <int R, int DIR>
-__device__ __forceinline__ void bfly(float2* u) {
-  if constexpr (R == 2) bfly2<DIR>(u);
-  if constexpr (R == 4) bfly4<DIR>(u[0], u[1], u[2], u[3]);
-  if constexpr (R == 8) bfly8<DIR>(u);
-}
-
-// ---------------------------------------------------------------- Stockham stage
-// M-point transforms of LINES lines held in LDS; point n of line l at lds[n*SN + l*SL].
-// Stage with radix R after earlier stages of total radix PREV: butterfly i (0..M/R-1)
-// reads points i + r M/R, twiddles by w^(r k M / (PREV R)) with k = i mod PREV, and
-// writes point (i - k) R + k + r PREV. Twiddle table: tw[j * TWS] = exp(-2 pi i j / M).
-template <int M, int R, int PREV, int LINES, int SN, int SL, int TWS, int DIR, int NTH>
-__device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
-  constexpr int NB = (M / R) * LINES;
-  constexpr int PER = (NB + NTH - 1) / NTH;
-  float2 u[PER][R];
-  int ii[PER], ll[PER];
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int b = t + m * NTH;
-    ii[m] = -1;
-    if (NB % NTH == 0 || b < NB) {
-      int i, l;
-      if constexpr (SL == 1) {
-        l = b % LINES;
-        i = b / LINES;
-      } else {
-        i = b % (M / R);
-        l = b / (M / R);
-      }
-      ii[m] = i;
-      ll[m] = l;
-#pragma unroll
-      for (int r = 0; r < R; ++r) u[m][r] = lds[(i + r * (M / R)) * SN + l * SL];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    if (NB % NTH == 0 || ii[m] >= 0) {
-      const int i = ii[m], l = ll[m];
-      const int k = i & (PREV - 1);
-      if constexpr (PREV > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * (M / (PREV * R)) * TWS];
-          if (DIR > 0) w.y = -w.y;
-          u[m][r] = cmul(u[m][r], w);
-        }
-      }
-      bfly<R, DIR>(u[m]);
-      const int j0 = (i - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[(j0 + r * PREV) * SN + l * SL] = u[m][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Full M-point transform: radix-8 stages, then one radix-4 or radix-2 stage.
-template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT>
-__device__ __forceinline__ void fft_lds(float2* lds, const float2* tw) {
-  static_assert(M >= 2 && (M & (M - 1)) == 0, "power of two");
-  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  constexpr int P8 = M >= 512 ? 512 : M >= 64 ? 64 : M >= 8 ? 8 : 1;
-  constexpr int REM = M / P8;
-  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  static_assert(M <= 512, "at most 512 points per line");
-}
-
-// exp(-2 pi i j / N) for j < N, from FP64 sincospi.
-template <int N, int NTH = NT>
-__device__ __forceinline__ void make_twiddles(float2* tw) {
-  for (int j = threadIdx.x; j < N; j += NTH) {
-    double s, c;
-    sincospi(-2.0 * (double)j / (double)N, &s, &c);
-    tw[j] = make_float2((float)c, (float)s);
-  }
-}
-
-// ---------------------------------------------------------------- z pass, r2c
-template <int N>
-struct ZTile {
-  static constexpr int H = N / 2;                        // complex points per row
-  static constexpr int ROWS = (2048 / H) > 0 ? 2048 / H : 1;
-  static constexpr int PITCH = H + 1;                    // LDS row pitch (complex)
-};
-
-// in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex.
-// Value loaded: a1 * in (+ a2 * in2 if in2) (* scale_dev[field / fields_per_item]).
-template <int N>
-__global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__ in, FieldMap im,
-                                                       const float* __restrict__ in2, float a1,
-                                                       float a2, const double* __restrict__ scale_dev,
-                                                       float2* __restrict__ out, FieldMap om) {
-  using T = ZTile<N>;
-  constexpr int H = T::H, ROWS = T::ROWS, PITCH = T::PITCH;
-  __shared__ float2 lds[ROWS * PITCH];
-  __shared__ float2 tw[N];
-  make_twiddles<N>(tw);
-  const int field = blockIdx.y;
-  const size_t row0 = (size_t)blockIdx.x * ROWS;
-  const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
-  const float2* src2 =
-      in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
-  float sc = 1.0f;
-  if (scale_dev) sc = (float)scale_dev[field / im.fpi];
-  const float b1 = a1 * sc, b2 = a2 * sc;
-  for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-    float2 v = src[e];
-    v.x *= b1;
-    v.y *= b1;
-    if (src2) {
-      float2 w = src2[e];
-      v.x += b2 * w.x;
-      v.y += b2 * w.y;
-    }
-    lds[(e / H) * PITCH + (e % H)] = v;
-  }
-  __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, -1>(lds, tw);
-  // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2, W = e^{-2 pi i/N}
-  float2* dst = out + om.off(field) + row0 * (H + 1);
-  constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
-  for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-    const int r = e / Q, k = e % Q;
-    const float2* z = lds + r * PITCH;
-    float2* d = dst + (size_t)r * (H + 1);
-    if (k == 0) {
-      float2 z0 = z[0];
-      d[0] = make_float2(z0.x + z0.y, 0.f);
-      d[H] = make_float2(z0.x - z0.y, 0.f);
-    } else {
-      const float2 zk = z[k], zm = z[H - k];
-      {
-        float2 s = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        float2 df = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-        float2 w = tw[k];
-        float2 t = cmul(w, df);  // W^k * diff
-        d[k] = make_float2(s.x + t.y, s.y - t.x);  // s - i t
-      }
-      if (k != H - k) {
-        float2 s = make_float2(0.5f * (zm.x + zk.x), 0.5f * (zm.y - zk.y));
-        float2 df = make_float2(0.5f * (zm.x - zk.x), 0.5f * (zm.y + zk.y));
-        float2 w = tw[H - k];
-        float2 t = cmul(w, df);
-        d[H - k] = make_float2(s.x + t.y, s.y - t.x);
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------- z pass, c2r
-// in: fields of n*n*(n/2+1) complex; out: fields of n^3 reals = unnormalised inverse
-// transform along z of each row (imaginary parts of the kz = 0 and n/2 entries ignored).
-// Optional epilogue: out += add.
-template <int N>
-__global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict__ in, FieldMap im,
-                                                       float* __restrict__ out, FieldMap om,
-                                                       const float* __restrict__ add) {
-  using T = ZTile<N>;
-  constexpr int H = T::H, ROWS = T::ROWS, PITCH = T::PITCH;
-  __shared__ float2 lds[ROWS * PITCH];
-  __shared__ float2 tw[N];
-  make_twiddles<N>(tw);
-  const int field = blockIdx.y;
-  const size_t row0 = (size_t)blockIdx.x * ROWS;
-  const float2* src = in + im.off(field) + row0 * (H + 1);
-  __syncthreads();
-  // inverse split: Z[k] = E + i O, E = X[k] + conj X[H-k], O = (X[k] - conj X[H-k]) conj(W^k)
-  constexpr int Q = H / 2 + 1;
-  for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-    const int r = e / Q, k = e % Q;
-    const float2* x = src + (size_t)r * (H + 1);
-    float2* z = lds + r * PITCH;
-    if (k == 0) {
-      const float a = x[0].x, b = x[H].x;
-      z[0] = make_float2(a + b, a - b);
-    } else {
-      const float2 xk = x[k], xm = x[H - k];
-      {
-        float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
-        float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
-        float2 O = cmul(D, cconj(tw[k]));
-        z[k] = make_float2(E.x - O.y, E.y + O.x);  // E + i O
-      }
-      if (k != H - k) {
-        float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
-        float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
-        float2 O = cmul(D, cconj(tw[H - k]));
-        z[H - k] = make_float2(E.x - O.y, E.y + O.x);
-      }
-    }
-  }
-  __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, +1>(lds, tw);
-  float2* dst = reinterpret_cast<float2*>(out + om.off(field)) + row0 * H;
-  const float2* ad = add ? reinterpret_cast<const float2*>(add + om.off(field)) + row0 * H : nullptr;
-  for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-    float2 v = lds[(e / H) * PITCH + (e % H)];
-    if (ad) {
-      float2 w = ad[e];
-      v.x += w.x;
-      v.y += w.y;
-    }
-    dst[e] = v;
-  }
-}
-
-// ---------------------------------------------------------------- strided passes
-// Tile: PCOL consecutive kz columns (from kz0) of the N points of one line family.
-// Element (n, l) of a tile sits at base + n * stride + l.
-template <int N, int PC, int NTH>
-__device__ __forceinline__ void load_tile(float2* lds, const float2* __restrict__ base,
-                                          size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PC; e += NTH) {
-    const int n = e / PC, l = e % PC;
-    lds[e] = l < ncols ? base[(size_t)n * stride + l] : make_float2(0.f, 0.f);
-  }
-}
-
-template <int N, int PC, int NTH>
-__device__ __forceinline__ void store_tile(const float2* lds, float2* __restrict__ base,
-                                           size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PC; e += NTH) {
-    const int n = e / PC, l = e % PC;
-    if (l < ncols) base[(size_t)n * stride + l] = lds[e];
-  }
-}
-
-// y pass: in-place forward or inverse transform along y of each field.
-template <int N, int DIR, int PC, int NTH>
-__global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, FieldMap m) {
-  constexpr int NH = N / 2 + 1;
-  __shared__ float2 lds[N * PC];
-  __shared__ float2 tw[N];
-  make_twiddles<N, NTH>(tw);
-  const int kz0 = blockIdx.x * PC;
-  const int ncols = min(PC, NH - kz0);
-  const int ix = blockIdx.y;
-  float2* base = data + m.off(blockIdx.z) + (size_t)ix * N * NH + kz0;
-  load_tile<N, PC, NTH>(lds, base, NH, ncols);
-  __syncthreads();
-  fft_lds<N, PC, PC, 1, 1, DIR, NTH>(lds, tw);
-  store_tile<N, PC, NTH>(lds, base, NH, ncols);
-}
-
-// ---------------------------------------------------------------- x pass with operators
-struct KVec {
-  float kx, ky, kz, k2;
-  int mx, my, mz;
-};
-
-template <int N>
-__device__ __forceinline__ KVec kvec(int n, int iy, int kz, float kf) {
-  KVec k;
-  k.mx = wavenumber(n, N);
-  k.my = wavenumber(iy, N);
-  k.mz = kz;
-  k.kx = kf * k.mx;
-  k.ky = kf * k.my;
-  k.kz = kf * k.mz;
-  k.k2 = k.kx * k.kx + k.ky * k.ky + k.kz * k.kz;
-  return k;
-}
-
-// i k_a / k^2 with the Nyquist plane of axis a and k = 0 removed; returned as the
-// imaginary coefficient c (multiplier = i c).
-template <int N>
-__device__ __forceinline__ float grad_coef(const KVec& k, int a) {
-  const int m = a == 0 ? k.mx : a == 1 ? k.my : k.mz;
-  const float ka = a == 0 ? k.kx : a == 1 ? k.ky : k.kz;
-  if (k.k2 == 0.f || m == N / 2 || m == -N / 2) return 0.f;
-  return ka / k.k2;
-}
-
-template <int N, int OP, int PC, int NTH>
-__global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a) {
-  constexpr int NH = N / 2 + 1;
-  constexpr int NE = N * PC;
-  constexpr int PER = NE / NTH;
-  static_assert(NE % NTH == 0, "tile");
-  __shared__ float2 lds[NE];
-  __shared__ float2 tw[N];
-  make_twiddles<N, NTH>(tw);
-  const int kz0 = blockIdx.x * PC;
-  const int ncols = min(PC, NH - kz0);
-  const int iy = blockIdx.y;
-  const int item = blockIdx.z;
-  const size_t stride = (size_t)N * NH;
-  const size_t toff = (size_t)iy * NH + kz0;
-  const size_t ioff = item * a.in_item_stride + toff;
-  const size_t ooff = item * a.out_item_stride + toff;
-  const float kf = (float)(2.0 * M_PI / a.box);
-  const float inv_n3 = (float)(1.0 / ((double)N * N * N));
-  const int t = threadIdx.x;
-
-  float2 hold[PER];  // spectrum (1-in ops) or accumulator (n-in ops)
-
-  // -------- inputs
-  const int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
-#pragma unroll
-  for (int m = 0; m < PER; ++m) hold[m] = make_float2(0.f, 0.f);
-  float Rg = 0.f;
-  if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
-  for (int i = 0; i < n_in; ++i) {
-    load_tile<N, PC, NTH>(lds, a.in[i] + ioff, stride, ncols);
-    __syncthreads();
-    if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = t + m * NTH;
-      const int n = e / PC, l = e % PC;
-      const float2 v = lds[e];
-      if constexpr (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) {
-        const KVec k = kvec<N>(n, iy, kz0 + l, kf);
-        const float c = grad_coef<N>(k, i);  // conj(i c) = -i c
-        const float2 w = cmul_i<-1>(v);
-        hold[m].x += c * w.x;
-        hold[m].y += c * w.y;
-      } else if constexpr (OP == XOP_FEAT_ADJ) {
-        const KVec k = kvec<N>(n, iy, kz0 + l, kf);
-        const float g = i == 0 ? expf(-0.5f * k.k2 * (float)(a.R1 * a.R1))
-                               : -expf(-0.5f * k.k2 * (float)(a.R2 * a.R2));
-        hold[m].x += g * v.x;
-        hold[m].y += g * v.y;
-      } else {
-        hold[m] = v;
-      }
-    }
-    __syncthreads();
-  }
-
-  // -------- outputs
-  if constexpr (OP == XOP_FWD) {
-#pragma unroll
-    for (int m = 0; m < PER; ++m) lds[t + m * NTH] = hold[m];
-    __syncthreads();
-    store_tile<N, PC, NTH>(lds, a.out[0] + ooff, stride, ncols);
-  } else if constexpr (OP == XOP_ZA_ADJ) {
-    // G = w(kz) * (sum_a conj(M_a) g_a / n^3 + prior_weight * loss_bar * P s / S), G(0) = 0
-    const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = t + m * NTH;
-      const int n = e / PC, l = e % PC;
-      const int kz = kz0 + l;
-      if (l >= ncols) continue;
-      const size_t gi = (size_t)n * stride + (size_t)iy * NH + kz;
-      const float wz = (kz == 0 || kz == N / 2) ? 1.f : 2.f;
-      const float2 ps = a.proj_modes[item * a.aux_item_stride + gi];
-      const float iv = a.inv_var[gi];
-      float2 g = make_float2(hold[m].x * inv_n3 + (float)lam * iv * ps.x,
-                             hold[m].y * inv_n3 + (float)lam * iv * ps.y);
-      g.x *= wz;
-      g.y *= wz;
-      if (n == 0 && iy == 0 && kz == 0) g = make_float2(0.f, 0.f);
-      a.out[0][item * a.out_item_stride + gi] = g;
-    }
-  } else {
-    const int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
-    for (int o = 0; o < n_out; ++o) {
-#pragma unroll
-      for (int m = 0; m < PER; ++m) {
-        const int e = t + m * NTH;
-        const int n = e / PC, l = e % PC;
-        float2 v = hold[m];
-        if constexpr (OP == XOP_FORCE || OP == XOP_ZA) {
-          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
-          const float c = grad_coef<N>(k, o) * inv_n3;
-          v = cmul_i<1>(make_float2(c * v.x, c * v.y));
-        } else if constexpr (OP == XOP_GAUSS) {
-          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
-          const float g = expf(-0.5f * k.k2 * Rg * Rg) * inv_n3;
-          v = make_float2(g * v.x, g * v.y);
-        } else if constexpr (OP == XOP_GAUSS2) {
-          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
-          const float R = (float)(o == 0 ? a.R1 : a.R2);
-          const float g = expf(-0.5f * k.k2 * R * R) * inv_n3;
-          v = make_float2(g * v.x, g * v.y);
-        } else {  // XOP_INV, XOP_FORCE_ADJ, XOP_FEAT_ADJ
-          v = make_float2(v.x * inv_n3, v.y * inv_n3);
-        }
-        lds[e] = v;
-      }
-      __syncthreads();
-      fft_lds<N, PC, PC, 1, 1, +1, NTH>(lds, tw);
-      store_tile<N, PC, NTH>(lds, a.out[o] + ooff, stride, ncols);
-      __syncthreads();
-    }
-  }
-}
-
-template <int N>
-void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, float a2,
-          const double* sc, float2* out, FieldMap om, hipStream_t s) {
-  using T = ZTile<N>;
-  dim3 grid((N * N) / T::ROWS, fields);
-  zpass_r2c_kernel<N><<<grid, NT, 0, s>>>(in, im, in2, a1, a2, sc, out, om);
-}
-
-template <int N>
-void zc2r(int fields, const float2* in, FieldMap im, float* out, FieldMap om, const float* add,
-          hipStream_t s) {
-  using T = ZTile<N>;
-  dim3 grid((N * N) / T::ROWS, fields);
-  zpass_c2r_kernel<N><<<grid, NT, 0, s>>>(in, im, out, om, add);
-}
-
-// Tile shape of the strided passes (columns per tile, threads per workgroup), per size;
-// set by pmr_fft_set_tile (the autotuner) or left at the defaults.
 struct TileShape {
   int pc, nth;
 };
-TileShape g_tile[10] = {{16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256},
-                        {16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256}};
+TileShape g_fft_tile[10] = {{16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256},
+                            {16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256}};
+
+namespace {
 int log2i(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
 }
-
-template <int N, int PC, int NTH>
-void ypass_t(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
-  dim3 grid((N / 2 + 1 + PC - 1) / PC, N, fields);
-  if (inv)
-    ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m);
-  else
-    ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m);
-}
-
-template <int N, int OP, int PC, int NTH>
-void xpass_t(const XPassArgs& a, hipStream_t s) {
-  dim3 grid((N / 2 + 1 + PC - 1) / PC, N, a.batch);
-  xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a);
-}
-
-// Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
-// tile N * PC * 8 B + N * 8 B within 160 KB.
-template <int N>
-constexpr bool shape_ok(int pc, int nth) {
-  return N * pc >= nth && (N * pc + N) * 8 <= 160 * 1024;
-}
-
-#define PMR_FOR_SHAPE(M) M(8, 256) M(16, 256) M(32, 256) M(8, 512) M(16, 512) M(32, 512)
-
-template <int N>
-void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
-  const TileShape t = g_tile[log2i(N)];
-#define SHAPE(PC, NTH)                                        \
-  if constexpr (shape_ok<N>(PC, NTH))                         \
-    if (t.pc == PC && t.nth == NTH) {                         \
-      ypass_t<N, PC, NTH>(fields, d, m, inv, s);              \
-      return;                                                 \
-    }
-  PMR_FOR_SHAPE(SHAPE)
-#undef SHAPE
-  ypass_t<N, 16, 256>(fields, d, m, inv, s);
-}
-
-template <int N, int OP>
-void xpass_op(const XPassArgs& a, hipStream_t s) {
-  const TileShape t = g_tile[log2i(N)];
-#define SHAPE(PC, NTH)                                        \
-  if constexpr (shape_ok<N>(PC, NTH))                         \
-    if (t.pc == PC && t.nth == NTH) {                         \
-      xpass_t<N, OP, PC, NTH>(a, s);                          \
-      return;                                                 \
-    }
-  PMR_FOR_SHAPE(SHAPE)
-#undef SHAPE
-  xpass_t<N, OP, 16, 256>(a, s);
-}
-
-template <int N>
-void xpass_dispatch(int op, const XPassArgs& a, hipStream_t s) {
-  switch (op) {
-    case XOP_FWD: xpass_op<N, XOP_FWD>(a, s); break;
-    case XOP_INV: xpass_op<N, XOP_INV>(a, s); break;
-    case XOP_FORCE: xpass_op<N, XOP_FORCE>(a, s); break;
-    case XOP_FORCE_ADJ: xpass_op<N, XOP_FORCE_ADJ>(a, s); break;
-    case XOP_GAUSS: xpass_op<N, XOP_GAUSS>(a, s); break;
-    case XOP_GAUSS2: xpass_op<N, XOP_GAUSS2>(a, s); break;
-    case XOP_FEAT_ADJ: xpass_op<N, XOP_FEAT_ADJ>(a, s); break;
-    case XOP_ZA: xpass_op<N, XOP_ZA>(a, s); break;
-    case XOP_ZA_ADJ: xpass_op<N, XOP_ZA_ADJ>(a, s); break;
-    default: break;
-  }
-}
-
 }  // namespace
+
+void fft_zr2c_16(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_16(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_16(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_16(int, const XPassArgs&, hipStream_t);
+void fft_zr2c_32(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_32(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_32(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_32(int, const XPassArgs&, hipStream_t);
+void fft_zr2c_64(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_64(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_64(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_64(int, const XPassArgs&, hipStream_t);
+void fft_zr2c_128(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_128(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_128(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_128(int, const XPassArgs&, hipStream_t);
+void fft_zr2c_256(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_256(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_256(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_256(int, const XPassArgs&, hipStream_t);
+void fft_zr2c_512(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
+               FieldMap, hipStream_t);
+void fft_zc2r_512(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
+void fft_ypass_512(int, float2*, FieldMap, bool, hipStream_t);
+void fft_xpass_512(int, const XPassArgs&, hipStream_t);
 
 #define PMR_FOR_N(MACRO) \
   MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512)
@@ -566,7 +56,7 @@ void launch_zpass_r2c(int n, int fields, const float* in, FieldMap im, const flo
                       float a2, const double* scale_dev, float2* out, FieldMap om, hipStream_t s) {
   switch (n) {
 #define CASE(NN) \
-  case NN: zr2c<NN>(fields, in, im, in2, a1, a2, scale_dev, out, om, s); break;
+  case NN: fft_zr2c_##NN(fields, in, im, in2, a1, a2, scale_dev, out, om, s); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;
@@ -577,7 +67,7 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
                       const float* add, hipStream_t s) {
   switch (n) {
 #define CASE(NN) \
-  case NN: zc2r<NN>(fields, in, im, out, om, add, s); break;
+  case NN: fft_zc2r_##NN(fields, in, im, out, om, add, s); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;
@@ -587,7 +77,7 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s) {
   switch (n) {
 #define CASE(NN) \
-  case NN: ypass<NN>(fields, data, m, inverse, s); break;
+  case NN: fft_ypass_##NN(fields, data, m, inverse, s); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;
@@ -599,12 +89,12 @@ int set_fft_tile(int n, int pc, int nth) {
   if (pc != 8 && pc != 16 && pc != 32) return -1;
   if (nth != 256 && nth != 512) return -1;
   if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024) return -1;
-  g_tile[log2i(n)] = {pc, nth};
+  g_fft_tile[log2i(n)] = {pc, nth};
   return 0;
 }
 
 void get_fft_tile(int n, int* pc, int* nth) {
-  const TileShape t = g_tile[log2i(n)];
+  const TileShape t = g_fft_tile[log2i(n)];
   *pc = t.pc;
   *nth = t.nth;
 }
@@ -612,7 +102,7 @@ void get_fft_tile(int n, int* pc, int* nth) {
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s) {
   switch (a.n) {
 #define CASE(NN) \
-  case NN: xpass_dispatch<NN>(op, a, s); break;
+  case NN: fft_xpass_##NN(op, a, s); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;

@@ -44,6 +44,16 @@ __device__ __forceinline__ double wrap_box(double x, double box) {
   return x - box * floor(x / box);
 }
 
+// Workgroups of a 1-D grid are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2. Remapping the block index gives every XCD one contiguous range of
+// logical blocks, so spatially neighbouring work shares an L2. Bijective for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = b % X, i = b / X;
+  return x * q + (x < r ? x : r) + i;
+}
+
 }  // namespace pmr
 
 // ------------------------------------------------------------------ launch declarations
