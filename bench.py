@@ -37,7 +37,7 @@ WORKLOADS = {
 }
 
 
-def make_context(w, dev):
+def make_context(w, dev, data=None):
     import torch
 
     import synth
@@ -57,43 +57,134 @@ def make_context(w, dev):
         return torch.stack([torch.from_numpy(cosmo.modes_from_white_noise(
             synth.white_noise(seed0 + b, n), box, power).reshape(-1)) for b in range(B)]).to(dev)
 
-    # data: the same pipeline at other seeds (target mass field)
-    pm.set_target(torch.ones(B, cfg.n_out ** 3, device=dev))
-    pm.set_loss(P.LossParams(M0=1.0))
-    target, _ = pm.forward(modes(1000))
-    M0 = [float(np.percentile(target[b].cpu().numpy(), 50)) for b in range(B)]
+    # data: the same pipeline at other seeds (target mass field), unless given
+    if data is None:
+        pm.set_target(torch.ones(B, cfg.n_out ** 3, device=dev))
+        pm.set_loss(P.LossParams(M0=1.0))
+        target, _ = pm.forward(modes(1000))
+        M0 = [float(np.percentile(target[b].cpu().numpy(), 50)) for b in range(B)]
+        data = (target.clone(), M0)
+    target, M0 = data
     pm.set_target(target)
     R = w["R_sm"]
     pm.set_loss([P.LossParams(M0=M0[b], mu=0.0, sigma_N=0.5, R_mass=3.0, R_sm=R[b % len(R)])
                  for b in range(B)])
+    pm.data = data
     return pm, modes(1)
+
+
+def oracle_inputs(w):
+    """Seeded inputs shared by the oracle leg and the GPU error check: white noise seed 1,
+    a log-normal synthetic data field (seed 7) and the workload's first anneal stage."""
+    import synth
+    n = w["n_part"]
+    return dict(white=synth.white_noise(1, n), mlp=synth.mlp_weights(3, w["mlp_hidden"]),
+                target=np.exp(synth.unit_normal(7, (w["n_out"],) * 3)),
+                M0=1.0, R_sm=w["R_sm"][0])
 
 
 def cpu_baseline(w):
     """FP64 oracle gradient of one batch item of the same workload (single thread)."""
     from threadpoolctl import threadpool_limits
 
-    import synth
     from oracle import cosmology as OC
     from oracle import model as OM
 
     n, box = w["n_part"], w["box"]
+    inp = oracle_inputs(w)
     cfg = OM.Config(box, n, w["n_mesh"], w["n_out"], w["n_steps"])
     power = OC.bbks_power()
     inv = OM.prior_inv_variance(n, box, power)
-    s = OM.linear_modes(synth.white_noise(1, n), box, power)
-    mlp = synth.mlp_weights(3, w["mlp_hidden"])
-    # synthetic positive data field (the oracle's timing does not depend on its values)
-    tgt = np.exp(synth.unit_normal(7, (w["n_out"],) * 3))
-    prm = OM.default_params(M0=1.0, R_sm=w["R_sm"][0])
+    s = OM.linear_modes(inp["white"], box, power)
+    prm = OM.default_params(M0=inp["M0"], R_sm=inp["R_sm"])
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        OM.gradient(cfg, s, inv, tgt, prm, mlp)
+        fwd, G = OM.gradient(cfg, s, inv, inp["target"], prm, inp["mlp"])
         dt = time.perf_counter() - t0
-    return {"value": w["n_steps"] / dt, "unit": "PM steps/s", "cores": 1, "kind": "oracle",
+    base = {"value": w["n_steps"] / dt, "unit": "PM steps/s", "cores": 1, "kind": "oracle",
             "sample": f"one batch item (of {w['batch']}): one FP64 gradient evaluation, "
                       f"{n}^3 particles, {w['n_steps']} PM steps, {dt:.1f} s",
             "seconds": dt}
+    return base, (fwd["loss"], G)
+
+
+def gpu_item_gradient(w, dev):
+    """GPU loss and gradient of the oracle leg's item (batch of one, same inputs)."""
+    import torch
+
+    import paper_1805_02247_amd as P
+    from paper_1805_02247_amd import cosmo
+
+    n, box = w["n_part"], w["box"]
+    inp = oracle_inputs(w)
+    cfg = P.Config(batch=1, n_part=n, n_mesh=w["n_mesh"], n_out=w["n_out"],
+                   n_steps=w["n_steps"], mlp_hidden=w["mlp_hidden"], precision=w["precision"],
+                   ckpt_every=w["ckpt_every"], box=box, loss_kind=P.PMR_LOSS_LOGNORMAL)
+    power = cosmo.linear_power(0.8, 0.2)
+    pm = P.PMContext(cfg, dev)
+    pm.set_prior(torch.from_numpy(cosmo.prior_inv_variance(n, box, power)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in inp["mlp"].items()})
+    pm.set_target(torch.from_numpy(inp["target"].astype(np.float32)).reshape(1, -1).to(dev))
+    pm.set_loss(P.LossParams(M0=inp["M0"], R_sm=inp["R_sm"]))
+    s = torch.from_numpy(cosmo.modes_from_white_noise(inp["white"], box, power)).reshape(1, -1)
+    _, loss = pm.forward(s.to(dev), want_mass=False)
+    g = pm.adjoint(torch.ones(1, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    out = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128))
+    del pm
+    return out
+
+
+def error_vs(ref_loss, ref_g, loss, g):
+    ref_g = np.asarray(ref_g).reshape(-1)
+    g = np.asarray(g).reshape(-1)
+    cos = float(np.real(np.vdot(ref_g, g)) / (np.linalg.norm(ref_g) * np.linalg.norm(g)))
+    return {"loss_rel": abs(loss - ref_loss) / abs(ref_loss),
+            "grad_rel_l2": float(np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)),
+            "grad_cos": cos}
+
+
+def time_gradient(pm, modes, steps, warmup):
+    import torch
+    ones = torch.ones(pm.cfg.batch, dtype=torch.float64, device=modes.device)
+    grad = torch.empty(pm.cfg.batch, pm.n_modes, dtype=torch.complex64, device=modes.device)
+    for _ in range(warmup):
+        pm.forward(modes, want_mass=False)
+        pm.adjoint(ones, out=grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pm.forward(modes, want_mass=False)
+        pm.adjoint(ones, out=grad)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, grad
+
+
+def mixed_vs_fp32(dev, steps):
+    """The 256^3 / 512^3 mixed-precision workload against the plain FP32 GPU path (the same
+    inputs with the network on FP32 vector units): time per gradient, speedup, and the
+    mixed path's error against the FP32 one at full size."""
+    import torch
+    w = WORKLOADS["cfg3_256"]
+    res = {}
+    grads = {}
+    data = None
+    for name, prec in (("fp32", 0), ("mixed", 1)):
+        pm, modes = make_context(dict(w, precision=prec), dev, data)
+        data = pm.data
+        t, g = time_gradient(pm, modes, steps, 1)
+        _, loss = pm.forward(modes, want_mass=False)
+        torch.cuda.synchronize()
+        res[name] = {"ms_per_gradient": 1e3 * t, "value": w["n_steps"] * w["batch"] / t,
+                     "unit": "PM steps/s"}
+        grads[name] = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128))
+        del pm, modes, g
+        torch.cuda.empty_cache()
+    del data
+    res["speedup_mixed_over_fp32"] = res["fp32"]["ms_per_gradient"] / res["mixed"]["ms_per_gradient"]
+    res["mixed_err_vs_fp32"] = error_vs(*grads["fp32"], *grads["mixed"])
+    res["workload"] = "cfg3_256"
+    return res
 
 
 def main():
@@ -103,6 +194,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-256", action="store_true",
+                    help="skip the 256^3/512^3 mixed-precision vs FP32 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for counters)")
     args = ap.parse_args()
@@ -177,7 +270,17 @@ def main():
                        "alg_bytes_per_launch": per_launch,
                        "share_of_step": ev_ms / (1e3 * T)}
     out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
+    if args.no_cpu_baseline:
+        out["cpu_baseline"] = None
+    else:
+        base, ref = cpu_baseline(w)
+        out["cpu_baseline"] = base
+        out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev)),
+                                  sample="batch item 0 inputs, full workload size")
+    if not args.no_256 and args.workload != "cfg3_256":
+        del pm, modes, grad
+        torch.cuda.empty_cache()
+        out["at_256"] = mixed_vs_fp32(dev, max(2, min(args.steps, 10)))
     print(json.dumps(out), flush=True)
 
 

@@ -184,7 +184,8 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
 
 /* Tile shape of the strided FFT passes for size n (process-wide; the autotuner sets it):
  * `columns` consecutive kz columns per workgroup tile (8, 16 or 32) and `threads` per
- * workgroup (256 or 512), with n * columns >= threads and the tile within 160 KB of LDS.
+ * workgroup (256 or 512), with threads <= n * columns <= 16 * threads and the tile within
+ * 160 KB of LDS.
  * Defaults: 16 columns, 256 threads. Not synchronised with work in flight: set it before
  * enqueueing. */
 int pmr_fft_set_tile(int n, int columns, int threads);

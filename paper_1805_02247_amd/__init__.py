@@ -5,5 +5,5 @@ prepares inputs on the host (see ``cosmo``).
 """
 from ._lib import (PMR_FP32, PMR_MIXED, PMR_LOSS_DENSITY_L2,  # noqa: F401
                    PMR_LOSS_LOGNORMAL, PmrError)
-from .api import (Config, LossParams, PMContext, PMForward, cic_paint,  # noqa: F401
-                  cic_sort, fft_c2r, fft_r2c, workspace_bytes)
+from .api import (Config, GradientGraph, LossParams, PMContext, PMForward,  # noqa: F401
+                  cic_paint, cic_sort, fft_c2r, fft_r2c, workspace_bytes)

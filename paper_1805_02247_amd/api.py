@@ -254,3 +254,46 @@ def cic_paint(x, keys, ids, rows, n_mesh, box, mass=1.0, bias=0.0):
                                   _ptr(ids), _ptr(rows), float(mass), float(bias), _ptr(out),
                                   _ptr(scratch), scratch.numel(), _stream()))
     return out
+
+
+class GradientGraph:
+    """A gradient evaluation (pmr_forward + pmr_adjoint) captured once as a HIP graph and
+    replayed. Inputs and outputs are fixed device buffers: write new modes into
+    `self.modes` (and loss_bar into `self.loss_bar`) before `replay()`; read `self.loss`
+    and `self.grad` after it. Loss parameters live in device memory, so a new
+    pmr_set_loss (anneal stage) is picked up by the next replay without recapture.
+
+    The library enqueues only kernels and device-to-device copies (no memsets), so the
+    captured graph replays exactly what the eager calls do.
+    """
+
+    def __init__(self, pmctx, modes, warmup=1):
+        self.pm = pmctx
+        B = pmctx.cfg.batch
+        self.modes = modes.clone().contiguous()
+        self.loss_bar = torch.ones(B, dtype=torch.float64, device=pmctx.device)
+        self.loss = torch.empty(B, 3, dtype=torch.float64, device=pmctx.device)
+        self.grad = torch.empty(B, pmctx.n_modes, dtype=torch.complex64, device=pmctx.device)
+        s = torch.cuda.Stream(device=pmctx.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self._enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        torch.cuda.synchronize()
+
+    def _enqueue(self):
+        pm = self.pm
+        pm._sync_stream()
+        L.check(L.lib().pmr_forward(pm._ctx, _ptr(self.modes), None, _ptr(self.loss)))
+        L.check(L.lib().pmr_adjoint(pm._ctx, _ptr(self.loss_bar), None, _ptr(self.grad)))
+
+    def replay(self):
+        self.graph.replay()
+        # later eager calls must see the library's stream, not the capture stream
+        self.pm._sync_stream()
+        return self.loss, self.grad

@@ -88,7 +88,7 @@ int set_fft_tile(int n, int pc, int nth) {
   if (n < 16 || n > 512 || (n & (n - 1))) return -1;
   if (pc != 8 && pc != 16 && pc != 32) return -1;
   if (nth != 256 && nth != 512) return -1;
-  if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024) return -1;
+  if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024 || n * pc / nth > 16) return -1;
   g_fft_tile[log2i(n)] = {pc, nth};
   return 0;
 }

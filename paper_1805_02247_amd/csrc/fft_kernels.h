@@ -562,6 +562,328 @@ int log2i(int n) {
   return l;
 }
 
+// ---------------------------------------------------------------- register-resident passes
+// Each thread keeps P = N * PC / NTH points of its lines in registers across a whole
+// transform. A stage with radix R works on P / R butterflies per thread, slot j of thread t
+// being butterfly b = t + j * NTH (line l = b % PC, index i = b / PC). The first stage
+// reads its inputs straight from HBM and the last stage writes straight to HBM; LDS is
+// used only for the permutations between stages. The inverse runs the radices in reverse
+// order, so the forward's output registers are exactly the inverse's input registers and a
+// k-space operator sits between them with no data movement.
+template <int N, bool REV>
+struct RPlan {
+  static constexpr int S8 = N >= 512 ? 3 : N >= 64 ? 2 : N >= 8 ? 1 : 0;
+  static constexpr int P8 = S8 == 3 ? 512 : S8 == 2 ? 64 : S8 == 1 ? 8 : 1;
+  static constexpr int REM = N / P8;  // 1, 2 or 4
+  static constexpr int S = S8 + (REM > 1 ? 1 : 0);
+  static constexpr int radix(int s) {
+    return REV ? ((REM > 1 && s == 0) ? REM : 8) : (s < S8 ? 8 : REM);
+  }
+  static constexpr int prev(int s) {
+    int p = 1;
+    for (int q = 0; q < s; ++q) p *= radix(q);
+    return p;
+  }
+};
+
+template <int N, int PC, int NTH>
+constexpr bool reg_ok() {
+  return (N * PC) % NTH == 0 && (N * PC / NTH) >= 8 && ((N * PC / NTH) % 8) == 0 && N >= 64;
+}
+
+// Butterflies of one stage, in registers (twiddles for PREV > 1 from the table tw[], which
+// holds exp(-2 pi i j / N), j < N).
+template <int N, int PC, int NTH, int R, int PREV, int DIR>
+__device__ __forceinline__ void reg_stage(float2* v, const float2* tw) {
+  constexpr int P = N * PC / NTH;
+#pragma unroll
+  for (int j = 0; j < P / R; ++j) {
+    float2* u = v + j * R;
+    if constexpr (PREV > 1) {
+      const int i = (threadIdx.x + j * NTH) / PC;
+      const int k = i & (PREV - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * (N / (PREV * R))];
+        if (DIR > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+    }
+    bfly<R, DIR>(u);
+  }
+}
+
+// Permutation from the outputs of stage (R, PREV) to the inputs of stage (R2) through LDS.
+template <int N, int PC, int NTH, int R, int PREV, int R2>
+__device__ __forceinline__ void reg_exchange(float2* v, float2* lds) {
+  constexpr int P = N * PC / NTH;
+#pragma unroll
+  for (int j = 0; j < P / R; ++j) {
+    const int b = threadIdx.x + j * NTH;
+    const int i = b / PC, l = b % PC;
+    const int k = i & (PREV - 1);
+    const int j0 = (i - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[(j0 + r * PREV) * PC + l] = v[j * R + r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < P / R2; ++j) {
+    const int b = threadIdx.x + j * NTH;
+    const int i = b / PC, l = b % PC;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[j * R2 + r] = lds[(i + r * (N / R2)) * PC + l];
+  }
+  __syncthreads();
+}
+
+template <int N, int PC, int NTH, bool REV, int DIR, int S>
+__device__ __forceinline__ void reg_stages_from(float2* v, float2* lds, const float2* tw) {
+  using PL = RPlan<N, REV>;
+  if constexpr (S < PL::S) {
+    constexpr int R = PL::radix(S), PV = PL::prev(S);
+    reg_stage<N, PC, NTH, R, PV, DIR>(v, tw);
+    if constexpr (S + 1 < PL::S) {
+      reg_exchange<N, PC, NTH, R, PV, PL::radix(S + 1)>(v, lds);
+      reg_stages_from<N, PC, NTH, REV, DIR, S + 1>(v, lds, tw);
+    }
+  }
+}
+
+// Whole transform of the thread's lines: v holds the inputs in the first stage's slot order
+// and returns the outputs in the last stage's slot order.
+template <int N, int PC, int NTH, bool REV, int DIR>
+__device__ __forceinline__ void reg_fft(float2* v, float2* lds, const float2* tw) {
+  reg_stages_from<N, PC, NTH, REV, DIR, 0>(v, lds, tw);
+}
+
+// HBM <-> registers in first-stage order (inputs at i + r N/R) or last-stage order (outputs
+// at i + r N/R of the last radix R, since the last stage has PREV = N/R).
+template <int N, int PC, int NTH, int R>
+__device__ __forceinline__ void reg_load(float2* v, const float2* __restrict__ base,
+                                         size_t stride, int ncols) {
+  constexpr int P = N * PC / NTH;
+#pragma unroll
+  for (int j = 0; j < P / R; ++j) {
+    const int b = threadIdx.x + j * NTH;
+    const int i = b / PC, l = b % PC;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      v[j * R + r] = l < ncols ? base[(size_t)(i + r * (N / R)) * stride + l] : make_float2(0.f, 0.f);
+  }
+}
+
+template <int N, int PC, int NTH, int R>
+__device__ __forceinline__ void reg_store(const float2* v, float2* __restrict__ base, size_t stride,
+                                          int ncols) {
+  constexpr int P = N * PC / NTH;
+#pragma unroll
+  for (int j = 0; j < P / R; ++j) {
+    const int b = threadIdx.x + j * NTH;
+    const int i = b / PC, l = b % PC;
+    if (l < ncols) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[(size_t)(i + r * (N / R)) * stride + l] = v[j * R + r];
+    }
+  }
+}
+
+// Point index (along the transformed axis) and line of register slot q in last-stage order.
+template <int N, int PC, int NTH, int R>
+__device__ __forceinline__ void reg_slot(int q, int& pos, int& l) {
+  const int j = q / R, r = q % R;
+  const int b = threadIdx.x + j * NTH;
+  l = b % PC;
+  pos = b / PC + r * (N / R);
+}
+
+template <int N, int DIR, int PC, int NTH>
+__global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ data, FieldMap m,
+                                                        int ntiles) {
+  constexpr int NH = N / 2 + 1;
+  constexpr int NCH = (NH + PC - 1) / PC;
+  constexpr int P = N * PC / NTH;
+  constexpr bool REV = DIR > 0;
+  using PL = RPlan<N, REV>;
+  constexpr int R0 = PL::radix(0), RL = PL::radix(PL::S - 1);
+  __shared__ float2 lds[N * PC];
+  __shared__ float2 tw[N];
+  make_twiddles<N, NTH>(tw);
+  auto tile_base = [&](int tau, int& ncols) {
+    const int ch = tau % NCH, rest = tau / NCH;
+    const int ix = rest % N, f = rest / N;
+    ncols = min(PC, NH - ch * PC);
+    return data + m.off(f) + (size_t)ix * N * NH + ch * PC;
+  };
+  int tau = blockIdx.x;
+  int nc;
+  float2* b = tile_base(tau, nc);
+  float2 pre[P], v[P];
+  reg_load<N, PC, NTH, R0>(pre, b, NH, nc);
+  __syncthreads();  // twiddles
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = pre[q];
+    const int next = tau + gridDim.x;
+    int nc2 = 0;
+    float2* b2 = nullptr;
+    if (next < ntiles) {
+      b2 = tile_base(next, nc2);
+      reg_load<N, PC, NTH, R0>(pre, b2, NH, nc2);
+    }
+    reg_fft<N, PC, NTH, REV, DIR>(v, lds, tw);
+    reg_store<N, PC, NTH, RL>(v, b, NH, nc);
+    if (next >= ntiles) break;
+    tau = next;
+    b = b2;
+    nc = nc2;
+  }
+}
+
+template <int N, int OP, int PC, int NTH>
+__global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles) {
+  constexpr int NH = N / 2 + 1;
+  constexpr int NCH = (NH + PC - 1) / PC;
+  constexpr int P = N * PC / NTH;
+  using PF = RPlan<N, false>;
+  using PI = RPlan<N, true>;
+  constexpr int R0F = PF::radix(0), RLF = PF::radix(PF::S - 1);
+  constexpr int RLI = PI::radix(PI::S - 1);
+  static_assert(PI::radix(0) == RLF, "inverse starts with the forward's last radix");
+  constexpr bool SPECTRAL_IN = (OP == XOP_ZA || OP == XOP_INV);
+  constexpr int RIN = SPECTRAL_IN ? RLF : R0F;  // layout in which inputs are loaded
+  __shared__ float2 lds[N * PC];
+  __shared__ float2 tw[N];
+  make_twiddles<N, NTH>(tw);
+  const size_t stride = (size_t)N * NH;
+  const float kf = (float)(2.0 * M_PI / a.box);
+  const float inv_n3 = (float)(1.0 / ((double)N * N * N));
+  constexpr int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
+  constexpr int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
+
+  auto in_base = [&](int tau, int i, int& ncols) {
+    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    ncols = min(PC, NH - ch * PC);
+    return a.in[i] + item * a.in_item_stride + (size_t)iy * NH + ch * PC;
+  };
+  int tau = blockIdx.x;
+  float2 pre[P];
+  {
+    int nc;
+    const float2* b0 = in_base(tau, 0, nc);
+    reg_load<N, PC, NTH, RIN>(pre, b0, stride, nc);
+  }
+  __syncthreads();  // twiddles
+  for (;;) {
+    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    const int kz0 = ch * PC;
+    const int ncols = min(PC, NH - kz0);
+    const size_t ooff = item * a.out_item_stride + (size_t)iy * NH + kz0;
+    const int next = tau + gridDim.x;
+    float Rg = 0.f;
+    if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
+
+    float2 hold[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) hold[q] = make_float2(0.f, 0.f);
+    // -------- inputs (each prefetched while the previous one is transformed)
+#pragma unroll 1
+    for (int i = 0; i < n_in; ++i) {
+      float2 v[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = pre[q];
+      if (i + 1 < n_in) {
+        int nc;
+        const float2* bi = in_base(tau, i + 1, nc);
+        reg_load<N, PC, NTH, RIN>(pre, bi, stride, nc);
+      } else if (next < ntiles) {
+        int nc;
+        const float2* bn = in_base(next, 0, nc);
+        reg_load<N, PC, NTH, RIN>(pre, bn, stride, nc);
+      }
+      if constexpr (!SPECTRAL_IN) reg_fft<N, PC, NTH, false, -1>(v, lds, tw);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        if constexpr (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) {
+          int n, l;
+          reg_slot<N, PC, NTH, RLF>(q, n, l);
+          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+          const float c = grad_coef<N>(k, i);  // conj(i c) = -i c
+          const float2 w = cmul_i<-1>(v[q]);
+          hold[q].x += c * w.x;
+          hold[q].y += c * w.y;
+        } else if constexpr (OP == XOP_FEAT_ADJ) {
+          int n, l;
+          reg_slot<N, PC, NTH, RLF>(q, n, l);
+          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+          const float g = i == 0 ? __expf(-0.5f * k.k2 * (float)(a.R1 * a.R1))
+                                 : -__expf(-0.5f * k.k2 * (float)(a.R2 * a.R2));
+          hold[q].x += g * v[q].x;
+          hold[q].y += g * v[q].y;
+        } else {
+          hold[q] = v[q];
+        }
+      }
+    }
+    // -------- outputs
+    if constexpr (OP == XOP_FWD) {
+      reg_store<N, PC, NTH, RLF>(hold, a.out[0] + ooff, stride, ncols);
+    } else if constexpr (OP == XOP_ZA_ADJ) {
+      // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
+      const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        int n, l;
+        reg_slot<N, PC, NTH, RLF>(q, n, l);
+        const int kz = kz0 + l;
+        if (l >= ncols) continue;
+        const size_t gi = (size_t)n * stride + (size_t)iy * NH + kz;
+        const float wz = (kz == 0 || kz == N / 2) ? 1.f : 2.f;
+        const float2 ps = a.proj_modes[item * a.aux_item_stride + gi];
+        const float iv = a.inv_var[gi];
+        float2 g = make_float2(hold[q].x * inv_n3 + (float)lam * iv * ps.x,
+                               hold[q].y * inv_n3 + (float)lam * iv * ps.y);
+        g.x *= wz;
+        g.y *= wz;
+        if (n == 0 && iy == 0 && kz == 0) g = make_float2(0.f, 0.f);
+        a.out[0][item * a.out_item_stride + gi] = g;
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < n_out; ++o) {
+        float2 v[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          int n, l;
+          reg_slot<N, PC, NTH, RLF>(q, n, l);
+          float2 x = hold[q];
+          if constexpr (OP == XOP_FORCE || OP == XOP_ZA) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            const float c = grad_coef<N>(k, o) * inv_n3;
+            x = cmul_i<1>(make_float2(c * x.x, c * x.y));
+          } else if constexpr (OP == XOP_GAUSS) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            const float g = __expf(-0.5f * k.k2 * Rg * Rg) * inv_n3;
+            x = make_float2(g * x.x, g * x.y);
+          } else if constexpr (OP == XOP_GAUSS2) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            const float R = (float)(o == 0 ? a.R1 : a.R2);
+            const float g = __expf(-0.5f * k.k2 * R * R) * inv_n3;
+            x = make_float2(g * x.x, g * x.y);
+          } else {  // XOP_INV, XOP_FORCE_ADJ, XOP_FEAT_ADJ
+            x = make_float2(x.x * inv_n3, x.y * inv_n3);
+          }
+          v[q] = x;
+        }
+        reg_fft<N, PC, NTH, true, +1>(v, lds, tw);
+        reg_store<N, PC, NTH, RLI>(v, a.out[o] + ooff, stride, ncols);
+      }
+    }
+    if (next >= ntiles) break;
+    tau = next;
+  }
+}
+
 // Workgroups launched for the tile loops: enough to fill the chip several times over.
 constexpr int kTileBlocks = 2048;
 
@@ -569,24 +891,34 @@ template <int N, int PC, int NTH>
 void ypass_t(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * fields;
   const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
-  if (inv)
-    ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-  else
-    ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+  if constexpr (reg_ok<N, PC, NTH>()) {
+    if (inv)
+      ypass_reg_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+    else
+      ypass_reg_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+  } else {
+    if (inv)
+      ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+    else
+      ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+  }
 }
 
 template <int N, int OP, int PC, int NTH>
 void xpass_t(const XPassArgs& a, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * a.batch;
   const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
-  xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+  if constexpr (reg_ok<N, PC, NTH>())
+    xpass_reg_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+  else
+    xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
 }
 
 // Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
 // tile N * PC * 8 B + N * 8 B within 160 KB.
 template <int N>
 constexpr bool shape_ok(int pc, int nth) {
-  return N * pc >= nth && (N * pc + N) * 8 <= 160 * 1024;
+  return N * pc >= nth && (N * pc + N) * 8 <= 160 * 1024 && N * pc / nth <= 16;
 }
 
 #define PMR_FOR_SHAPE(M) M(8, 256) M(16, 256) M(32, 256) M(8, 512) M(16, 512) M(32, 512)
@@ -605,14 +937,24 @@ void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
   ypass_t<N, 16, 256>(fields, d, m, inv, s);
 }
 
+// Multi-input operators hold three register images (accumulator, current, prefetch); at
+// more than 8 points per thread they would spill, so they run on half-width tiles.
+template <int OP>
+constexpr bool multi_input() {
+  return OP == XOP_FORCE_ADJ || OP == XOP_FEAT_ADJ || OP == XOP_ZA_ADJ;
+}
+
 template <int N, int OP>
 void xpass_op(const XPassArgs& a, hipStream_t s) {
   const TileShape t = g_fft_tile[log2i(N)];
-#define SHAPE(PC, NTH)                                        \
-  if constexpr (shape_ok<N>(PC, NTH))                         \
-    if (t.pc == PC && t.nth == NTH) {                         \
-      xpass_t<N, OP, PC, NTH>(a, s);                          \
-      return;                                                 \
+#define SHAPE(PC, NTH)                                                         \
+  if constexpr (shape_ok<N>(PC, NTH))                                          \
+    if (t.pc == PC && t.nth == NTH) {                                          \
+      if constexpr (multi_input<OP>() && N * PC / NTH > 8 && PC > 8)           \
+        xpass_t<N, OP, PC / 2, NTH>(a, s);                                     \
+      else                                                                     \
+        xpass_t<N, OP, PC, NTH>(a, s);                                         \
+      return;                                                                  \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE

@@ -465,6 +465,15 @@ void pm_run(pmr_ctx* c, int i0, int i1, bool take_ckpt) {
 
 int final_xslot(pmr_ctx* c) { return c->k == 0 ? c->n : ((c->n - 1) % c->k) + 1; }
 
+// x_data = log(G_Rmass * M_target + M0), enqueued as soon as both target and loss
+// parameters are known, so that captured forward passes never depend on host state.
+void refresh_xd(pmr_ctx* c) {
+  if (c->cfg.loss_kind != PMR_LOSS_LOGNORMAL || !c->have_target || !c->have_loss) return;
+  smooth(c, c->no, c->target, 3, c->ob, nullptr);
+  launch_target_x(c->ob, c->no3, c->B, c->params, c->xd, c->stream);
+  c->xd_dirty = 0;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -545,6 +554,7 @@ int pmr_set_target(pmr_ctx* c, const float* target) {
                  c->stream));
   c->have_target = 1;
   c->xd_dirty = 1;
+  refresh_xd(c);
   return check(c);
 }
 
@@ -568,6 +578,7 @@ int pmr_set_loss(pmr_ctx* c, const pmr_loss_params* prm) {
   HIPC(c, hipStreamSynchronize(c->stream));
   c->have_loss = 1;
   c->xd_dirty = 1;
+  refresh_xd(c);
   return check(c);
 }
 
@@ -581,11 +592,7 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   // H0: projection and prior
   launch_project_prior((const float2*)modes, c->np, B, c->inv_var, c->ps, c->partial, c->prior, s);
   // data term of the target (log-normal): x_data = log(G_Rmass * M_t + M0)
-  if (c->cfg.loss_kind == PMR_LOSS_LOGNORMAL && c->xd_dirty) {
-    smooth(c, c->no, c->target, 3, c->ob, nullptr);
-    launch_target_x(c->ob, c->no3, B, c->params, c->xd, s);
-    c->xd_dirty = 0;
-  }
+  if (c->xd_dirty) refresh_xd(c);
   // H1: Zel'dovich displacement on the particle lattice
   {
     const size_t cp = c->cp;

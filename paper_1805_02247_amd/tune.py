@@ -20,7 +20,7 @@ SHAPES = [(8, 256), (16, 256), (32, 256), (8, 512), (16, 512), (32, 512)]
 
 
 def valid(n, pc, nth):
-    return n * pc >= nth and (n * pc + n) * 8 <= 160 * 1024
+    return n * pc >= nth and (n * pc + n) * 8 <= 160 * 1024 and n * pc // nth <= 16
 
 
 def time_shape(n, pc, nth, batch, reps):
