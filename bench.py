@@ -105,7 +105,7 @@ def cpu_baseline(w):
             "sample": f"one batch item (of {w['batch']}): one FP64 gradient evaluation, "
                       f"{n}^3 particles, {w['n_steps']} PM steps, {dt:.1f} s",
             "seconds": dt}
-    return base, (fwd["loss"], G)
+    return base, (fwd["loss"], G, fwd["xs"][-1])
 
 
 def gpu_item_gradient(w, dev):
@@ -128,20 +128,30 @@ def gpu_item_gradient(w, dev):
     pm.set_loss(P.LossParams(M0=inp["M0"], R_sm=inp["R_sm"]))
     s = torch.from_numpy(cosmo.modes_from_white_noise(inp["white"], box, power)).reshape(1, -1)
     _, loss = pm.forward(s.to(dev), want_mass=False)
+    x = pm.debug("x", w["n_steps"]).cpu().numpy()[0] if w["ckpt_every"] == 0 else None
     g = pm.adjoint(torch.ones(1, dtype=torch.float64, device=dev))
     torch.cuda.synchronize()
-    out = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128))
+    out = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128), x)
     del pm
     return out
 
 
-def error_vs(ref_loss, ref_g, loss, g):
+def error_vs(ref_loss, ref_g, ref_x, loss, g, x, box=None, n_mesh=None):
     ref_g = np.asarray(ref_g).reshape(-1)
     g = np.asarray(g).reshape(-1)
     cos = float(np.real(np.vdot(ref_g, g)) / (np.linalg.norm(ref_g) * np.linalg.norm(g)))
-    return {"loss_rel": abs(loss - ref_loss) / abs(ref_loss),
-            "grad_rel_l2": float(np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)),
-            "grad_cos": cos}
+    out = {"loss_rel": abs(loss - ref_loss) / abs(ref_loss),
+           "grad_rel_l2": float(np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)),
+           "grad_cos": cos}
+    if ref_x is not None and x is not None:
+        h = box / n_mesh
+        x = x.reshape(3, -1)
+        ref_x = ref_x.reshape(3, -1)
+        d = (x - ref_x + box / 2) % box - box / 2
+        out["final_max_dx_cells"] = float(np.abs(d).max() / h)
+        cells = lambda v: np.floor(v / h).astype(np.int64) % n_mesh
+        out["final_cell_mismatch_frac"] = float(np.any(cells(x) != cells(ref_x), axis=0).mean())
+    return out
 
 
 def time_gradient(pm, modes, steps, warmup):
@@ -177,7 +187,7 @@ def mixed_vs_fp32(dev, steps):
         torch.cuda.synchronize()
         res[name] = {"ms_per_gradient": 1e3 * t, "value": w["n_steps"] * w["batch"] / t,
                      "unit": "PM steps/s"}
-        grads[name] = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128))
+        grads[name] = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128), None)
         del pm, modes, g
         torch.cuda.empty_cache()
     del data
@@ -194,6 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip timing the HIP-graph replay of a gradient evaluation")
     ap.add_argument("--no-256", action="store_true",
                     help="skip the 256^3/512^3 mixed-precision vs FP32 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -205,6 +217,8 @@ def main():
         sys.exit(2)
 
     import torch
+
+    import paper_1805_02247_amd as P
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -270,12 +284,26 @@ def main():
                        "alg_bytes_per_launch": per_launch,
                        "share_of_step": ev_ms / (1e3 * T)}
     out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
+    if not args.no_graph:
+        G = P.GradientGraph(pm, modes)
+        for _ in range(args.warmup):
+            G.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            G.replay()
+        torch.cuda.synchronize()
+        Tg = time.perf_counter() - t0
+        out["graph_replay"] = {"ms_per_step": 1e3 * Tg / args.steps, "value": pm_steps / Tg,
+                               "unit": "PM steps/s"}
+        del G
     if args.no_cpu_baseline:
         out["cpu_baseline"] = None
     else:
         base, ref = cpu_baseline(w)
         out["cpu_baseline"] = base
-        out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev)),
+        out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev), box=w["box"],
+                                           n_mesh=w["n_mesh"]),
                                   sample="batch item 0 inputs, full workload size")
     if not args.no_256 and args.workload != "cfg3_256":
         del pm, modes, grad

@@ -182,14 +182,19 @@ int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream);
  * (kz = 0, n/2 columns after the inner transforms) are ignored, as irfftn does. */
 int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
 
-/* Tile shape of the strided FFT passes for size n (process-wide; the autotuner sets it):
- * `columns` consecutive kz columns per workgroup tile (8, 16 or 32) and `threads` per
- * workgroup (256 or 512), with threads <= n * columns <= 16 * threads and the tile within
- * 160 KB of LDS.
- * Defaults: 16 columns, 256 threads. Not synchronised with work in flight: set it before
- * enqueueing. */
-int pmr_fft_set_tile(int n, int columns, int threads);
-int pmr_fft_get_tile(int n, int* columns, int* threads);
+/* Tile shape of one strided FFT pass for size n (process-wide; the autotuner sets it).
+ * `pass` PMR_FFT_YPASS (the middle axis) or PMR_FFT_XPASS (the outermost axis, which also
+ * applies the k-space operators). `columns` consecutive kz columns per workgroup tile
+ * (8, 16 or 32) and `threads` per workgroup (256 or 512), with
+ * threads <= n * columns <= 16 * threads and the tile within 160 KB of LDS. `staging` 0 runs
+ * the butterflies on register images of the tile (used where n * columns / threads is a
+ * multiple of 8 and n >= 64; LDS only permutes between radix stages), 1 runs every stage on
+ * the LDS-staged tile. Invalid values return PMR_E_INVALID and leave the shape unchanged.
+ * Defaults: 16 columns, 256 threads, staging 0. Not synchronised with work in flight: set it
+ * before enqueueing. */
+enum { PMR_FFT_YPASS = 0, PMR_FFT_XPASS = 1 };
+int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging);
+int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging);
 
 /* Bytes of scratch for pmr_cic_sort with `n_particles` in total and `batch` items. */
 size_t pmr_sort_scratch_bytes(int n_particles_total, int n_mesh, int batch);

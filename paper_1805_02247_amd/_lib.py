@@ -13,6 +13,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
 PMR_OK = 0
 PMR_FP32, PMR_MIXED = 0, 1
 PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
+PMR_FFT_YPASS, PMR_FFT_XPASS = 0, 1
 DBG = {"x": 1, "force": 2, "sort_ids": 3, "delta_f": 4, "features": 5, "mass_r": 6,
        "res_s": 7, "xbar0": 8, "pbar0": 9, "dbar_f": 10}
 
@@ -58,8 +59,8 @@ SIGNATURES = {
     "pmr_sort_scratch_bytes": (sz, [ci, ci, ci]),
     "pmr_cic_sort": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, vp, sz, vp]),
     "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, cf, cf, vp, vp, sz, vp]),
-    "pmr_fft_set_tile": (ci, [ci, ci, ci]),
-    "pmr_fft_get_tile": (ci, [ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]),
+    "pmr_fft_set_tile": (ci, [ci, ci, ci, ci, ci]),
+    "pmr_fft_get_tile": (ci, [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
     "pmr_profile_begin": (ci, [vp, ci, ci]),
     "pmr_profile_end": (ci, [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_longlong),
                              ctypes.POINTER(cd)]),

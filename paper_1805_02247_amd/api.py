@@ -210,6 +210,18 @@ class PMForward(torch.autograd.Function):
 
 
 # ---------------------------------------------------------------- primitives
+def fft_get_tile(n, pass_):
+    """(columns, threads, staging) of the strided FFT pass `pass_` (PMR_FFT_YPASS or
+    PMR_FFT_XPASS) for size n."""
+    c, t, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    L.check(L.lib().pmr_fft_get_tile(n, pass_, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)))
+    return c.value, t.value, s.value
+
+
+def fft_set_tile(n, pass_, columns, threads, staging):
+    L.check(L.lib().pmr_fft_set_tile(n, pass_, columns, threads, staging))
+
+
 def fft_r2c(x):
     """Unnormalised 3-D real FFT of [B][n][n][n] float32 -> complex64 [B][n][n][n/2+1]."""
     B, n = x.shape[0], x.shape[-1]

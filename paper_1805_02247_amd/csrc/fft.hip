@@ -4,11 +4,11 @@
 
 namespace pmr {
 
-struct TileShape {
-  int pc, nth;
-};
-TileShape g_fft_tile[10] = {{16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256},
-                            {16, 256}, {16, 256}, {16, 256}, {16, 256}, {16, 256}};
+TileShape g_fft_tile[2][10] = {
+    {{16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
+     {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}},
+    {{16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
+     {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}}};
 
 namespace {
 int log2i(int n) {
@@ -84,19 +84,22 @@ void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hip
   }
 }
 
-int set_fft_tile(int n, int pc, int nth) {
+int set_fft_tile(int n, int pass, int pc, int nth, int lds) {
+  if (pass != 0 && pass != 1) return -1;
   if (n < 16 || n > 512 || (n & (n - 1))) return -1;
   if (pc != 8 && pc != 16 && pc != 32) return -1;
   if (nth != 256 && nth != 512) return -1;
   if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024 || n * pc / nth > 16) return -1;
-  g_fft_tile[log2i(n)] = {pc, nth};
+  if (lds != 0 && lds != 1) return -1;
+  g_fft_tile[pass][log2i(n)] = {pc, nth, lds};
   return 0;
 }
 
-void get_fft_tile(int n, int* pc, int* nth) {
-  const TileShape t = g_fft_tile[log2i(n)];
+void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds) {
+  const TileShape t = g_fft_tile[pass][log2i(n)];
   *pc = t.pc;
   *nth = t.nth;
+  *lds = t.lds;
 }
 
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s) {

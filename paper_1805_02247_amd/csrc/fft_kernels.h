@@ -20,12 +20,6 @@
 
 namespace pmr {
 
-// Tile shape of the strided passes (columns per tile, threads per workgroup), per log2(n);
-// set by pmr_fft_set_tile (the autotuner) or left at the defaults. Defined in fft.hip.
-struct TileShape {
-  int pc, nth;
-};
-extern TileShape g_fft_tile[10];
 
 namespace {
 
@@ -888,30 +882,35 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
 constexpr int kTileBlocks = 2048;
 
 template <int N, int PC, int NTH>
-void ypass_t(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
+void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * fields;
   const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
   if constexpr (reg_ok<N, PC, NTH>()) {
-    if (inv)
-      ypass_reg_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-    else
-      ypass_reg_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-  } else {
-    if (inv)
-      ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-    else
-      ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+    if (!lds) {
+      if (inv)
+        ypass_reg_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+      else
+        ypass_reg_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+      return;
+    }
   }
+  if (inv)
+    ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+  else
+    ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
 }
 
 template <int N, int OP, int PC, int NTH>
-void xpass_t(const XPassArgs& a, hipStream_t s) {
+void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * a.batch;
   const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
-  if constexpr (reg_ok<N, PC, NTH>())
-    xpass_reg_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
-  else
-    xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+  if constexpr (reg_ok<N, PC, NTH>()) {
+    if (!lds) {
+      xpass_reg_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+      return;
+    }
+  }
+  xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
 }
 
 // Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
@@ -925,16 +924,16 @@ constexpr bool shape_ok(int pc, int nth) {
 
 template <int N>
 void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
-  const TileShape t = g_fft_tile[log2i(N)];
+  const TileShape t = g_fft_tile[0][log2i(N)];
 #define SHAPE(PC, NTH)                                        \
   if constexpr (shape_ok<N>(PC, NTH))                         \
     if (t.pc == PC && t.nth == NTH) {                         \
-      ypass_t<N, PC, NTH>(fields, d, m, inv, s);              \
+      ypass_t<N, PC, NTH>(fields, d, m, inv, t.lds, s);       \
       return;                                                 \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE
-  ypass_t<N, 16, 256>(fields, d, m, inv, s);
+  ypass_t<N, 16, 256>(fields, d, m, inv, t.lds, s);
 }
 
 // Multi-input operators hold three register images (accumulator, current, prefetch); at
@@ -946,19 +945,21 @@ constexpr bool multi_input() {
 
 template <int N, int OP>
 void xpass_op(const XPassArgs& a, hipStream_t s) {
-  const TileShape t = g_fft_tile[log2i(N)];
+  const TileShape t = g_fft_tile[1][log2i(N)];
 #define SHAPE(PC, NTH)                                                         \
   if constexpr (shape_ok<N>(PC, NTH))                                          \
     if (t.pc == PC && t.nth == NTH) {                                          \
       if constexpr (multi_input<OP>() && N * PC / NTH > 8 && PC > 8)           \
-        xpass_t<N, OP, PC / 2, NTH>(a, s);                                     \
-      else                                                                     \
-        xpass_t<N, OP, PC, NTH>(a, s);                                         \
+        if (!t.lds) {                                                          \
+          xpass_t<N, OP, PC / 2, NTH>(a, false, s);                            \
+          return;                                                              \
+        }                                                                      \
+      xpass_t<N, OP, PC, NTH>(a, t.lds, s);                                    \
       return;                                                                  \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE
-  xpass_t<N, OP, 16, 256>(a, s);
+  xpass_t<N, OP, 16, 256>(a, t.lds, s);
 }
 
 template <int N>

@@ -909,13 +909,14 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 
-int pmr_fft_set_tile(int n, int columns, int threads) {
-  return set_fft_tile(n, columns, threads) == 0 ? PMR_OK : PMR_E_INVALID;
+int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging) {
+  return set_fft_tile(n, pass, columns, threads, staging) == 0 ? PMR_OK : PMR_E_INVALID;
 }
 
-int pmr_fft_get_tile(int n, int* columns, int* threads) {
-  if (!columns || !threads || !pow2_in(n, 16, 512)) return PMR_E_INVALID;
-  get_fft_tile(n, columns, threads);
+int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging) {
+  if (!columns || !threads || !staging || !pow2_in(n, 16, 512) || (pass != 0 && pass != 1))
+    return PMR_E_INVALID;
+  get_fft_tile(n, pass, columns, threads, staging);
   return PMR_OK;
 }
 

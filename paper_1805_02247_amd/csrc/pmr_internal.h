@@ -109,8 +109,17 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
                       const float* add, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
-int set_fft_tile(int n, int pc, int nth);
-void get_fft_tile(int n, int* pc, int* nth);
+// Tile shape of the strided passes (columns per tile, threads per workgroup, and whether the
+// butterflies run on register images (0) or on the LDS-staged tile (1)), per pass (0: y pass,
+// 1: x pass with its k-space operators) and log2(n); set by pmr_fft_set_tile (the autotuner)
+// or left at the defaults. Defined in fft.hip.
+struct TileShape {
+  int pc, nth, lds;
+};
+extern TileShape g_fft_tile[2][10];
+
+int set_fft_tile(int n, int pass, int pc, int nth, int lds);
+void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);

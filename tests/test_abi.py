@@ -68,3 +68,29 @@ def test_primitives_reject_bad_shapes_without_touching_memory():
     assert lib.pmr_fft_c2r(16, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == -1
     assert lib.pmr_sort_scratch_bytes(1000, 24, 1) == 0
     assert lib.pmr_cic_sort(16, 16, 1, 1.0, None, None, None, None, None, 0, None) == -1
+
+
+def test_fft_tile_shape_validation():
+    """Tile shapes are host state: valid ones are stored and read back per pass, invalid ones
+    (pass, columns, threads, LDS size, points per thread, staging) are refused unchanged."""
+    lib = L.lib()
+    c, t, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+
+    def get(n, p):
+        assert lib.pmr_fft_get_tile(n, p, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == 0
+        return (c.value, t.value, s.value)
+    saved = {p: get(128, p) for p in (0, 1)}
+    try:
+        assert lib.pmr_fft_set_tile(128, 0, 32, 256, 1) == 0
+        assert lib.pmr_fft_set_tile(128, 1, 8, 512, 0) == 0
+        assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
+        for bad in [(128, 2, 16, 256, 0), (128, 0, 12, 256, 0), (128, 0, 16, 384, 0),
+                    (128, 1, 32, 256, 2), (512, 0, 32, 256, 0), (96, 0, 16, 256, 0),
+                    (16, 1, 8, 256, 0)]:
+            assert lib.pmr_fft_set_tile(*bad) == -1, bad
+        assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
+        assert lib.pmr_fft_get_tile(24, 0, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1
+        assert lib.pmr_fft_get_tile(64, 2, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1
+    finally:
+        for p, v in saved.items():
+            lib.pmr_fft_set_tile(128, p, *v)

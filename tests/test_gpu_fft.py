@@ -90,3 +90,33 @@ def test_roundtrip_large(n):
     e = (torch.linalg.vector_norm((y - xt).double()) / torch.linalg.vector_norm(xt.double())).item()
     say(f"  rel-L2 {e:.2e}")
     assert e < 2 * TOL
+
+
+SHAPES = [(8, 256), (16, 256), (32, 256), (8, 512), (16, 512), (32, 512)]
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_every_tile_shape_and_staging(n):
+    """Each supported tile shape, with register and LDS staging, in each strided pass, against
+    the oracle (the other pass held at its current shape)."""
+    require_gpu()
+    import paper_1805_02247_amd as P
+    from paper_1805_02247_amd.tune import candidates
+    saved = {p: P.fft_get_tile(n, p) for p in (P.PMR_FFT_YPASS, P.PMR_FFT_XPASS)}
+    x = synth.unit_normal(3 * n, (1, n, n, n)).astype(np.float32)
+    ref = M.rfft3(x[0].astype(np.float64))
+    X = np.stack([ref]).astype(np.complex64)
+    ref_inv = M.irfft3(X[0].astype(np.complex128), n)
+    try:
+        for p in saved:
+            for c in candidates(n):
+                P.fft_set_tile(n, p, *c)
+                got = api.fft_r2c(torch.from_numpy(x).to(DEV)).cpu().numpy()[0]
+                inv = api.fft_c2r(torch.from_numpy(X).to(DEV)).cpu().numpy()[0]
+                e1, e2 = rel_l2(got, ref), rel_l2(inv, ref_inv)
+                say(f"  n={n} pass {p} {c}: r2c {e1:.2e} c2r {e2:.2e}")
+                assert e1 < TOL and e2 < TOL
+            P.fft_set_tile(n, p, *saved[p])
+    finally:
+        for p, v in saved.items():
+            P.fft_set_tile(n, p, *v)

@@ -56,10 +56,13 @@ def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P
                 delta_f=delta_f, grad=g.cpu().numpy(), xbar0=pm.debug("xbar0").cpu().numpy())
 
 
-def _compare(ocfg, inv, modes, w, targets, params, res, tol):
+def _compare(ocfg, inv, modes, w, targets, params, res, tol, refs=None):
     B = len(modes)
     for b in range(B):
-        ref, G = OM.gradient(ocfg, modes[b], inv, targets[b], params[b], w)
+        if refs is None:
+            ref, G = OM.gradient(ocfg, modes[b], inv, targets[b], params[b], w)
+        else:
+            ref, G = refs[b]
         out = {}
         if res["xs"] is not None:
             dx = 0.0
@@ -68,6 +71,12 @@ def _compare(ocfg, inv, modes, w, targets, params, res, tol):
                 d = (d + ocfg.box / 2) % ocfg.box - ocfg.box / 2
                 dx = max(dx, np.abs(d).max() / (ocfg.box / ocfg.n_mesh))
             out["max_dx_cells"] = dx
+            # particles whose final CIC cell differs from the oracle's (reported, not failed:
+            # a position within rounding of a cell face may land on either side)
+            h = ocfg.box / ocfg.n_mesh
+            cg = np.floor(res["xs"][-1][b] / h).astype(np.int64) % ocfg.n_mesh
+            cr = np.floor(ref["xs"][-1] / h).astype(np.int64) % ocfg.n_mesh
+            out["cell_flips"] = float(np.any(cg != cr, axis=0).sum())
         out["delta_f"] = rel_l2(res["delta_f"][b], ref["delta_f"].ravel())
         out["loss"] = abs(res["loss"][b, 0] - ref["loss"]) / abs(ref["loss"])
         out["prior"] = abs(res["loss"][b, 1] - ref["loss_prior"]) / abs(ref["loss_prior"])
@@ -161,3 +170,54 @@ def test_mixed_precision_network(hidden):
     prob = _problem(32, 32, 32, 100.0, 3, OM.LOSS_LOGNORMAL, 2, hidden=hidden, R_sm=(2.0, 0.0))
     res = _gpu_run(*prob, hidden=hidden, precision=P.PMR_MIXED)
     _compare(*prob, res, TOL_MIXED)
+
+
+@pytest.fixture
+def tile_shape():
+    """Sets the FFT tile shape of given sizes (both strided passes) for one test and restores
+    it afterwards."""
+    saved = {}
+
+    def set_shape(n, pc, nth, staging):
+        for p in (P.PMR_FFT_YPASS, P.PMR_FFT_XPASS):
+            if (n, p) not in saved:
+                saved[(n, p)] = P.fft_get_tile(n, p)
+            P.fft_set_tile(n, p, pc, nth, staging)
+
+    yield set_shape
+    for (n, p), v in saved.items():
+        P.fft_set_tile(n, p, *v)
+
+
+@pytest.mark.parametrize("staging", [0, 1])
+def test_register_and_lds_fft_staging_64_on_128(tile_shape, staging):
+    """64^3 particles on a 128^3 force mesh (64^3 output), 3 steps, H = 32: sizes where the
+    strided passes and every fused k-space operator run on register images (staging 0,
+    8 and 16 points per thread) or on LDS-staged tiles (staging 1)."""
+    require_gpu()
+    say(f"pipeline: 64^3 on 128^3, staging {staging}")
+    tile_shape(64, 32, 256, staging)
+    tile_shape(128, 32, 256, staging)
+    prob = _problem(64, 128, 64, 200.0, 3, OM.LOSS_LOGNORMAL, 1, hidden=32, R_sm=(2.0,))
+    res = _gpu_run(*prob, hidden=32)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_large_mesh_shape_scaled_to_64_on_128():
+    """The 256^3-particle / 512^3-mesh workload scaled down to 64^3 particles on a 128^3 force
+    mesh (64^3 output) at the same box (400 Mpc/h), 10 steps, 3-64-64-1 network and
+    checkpointing every 2 steps: the FP32 path and the mixed path (BF16 network) against the
+    oracle, and against each other."""
+    require_gpu()
+    say("pipeline: 64^3 on 128^3, 10 steps, H=64, FP32 and mixed")
+    prob = _problem(64, 128, 64, 400.0, 10, OM.LOSS_LOGNORMAL, 1, hidden=64, R_sm=(2.0,))
+    ocfg, inv, modes, w, targets, params = prob
+    refs = [OM.gradient(ocfg, modes[0], inv, targets[0], params[0], w)]
+    grads = {}
+    for precision, tol in ((P.PMR_FP32, TOL_FP32), (P.PMR_MIXED, TOL_MIXED)):
+        say(f"  precision {precision}")
+        res = _gpu_run(*prob, hidden=64, ckpt=2, precision=precision)
+        _compare(*prob, res, tol, refs=refs)
+        grads[precision] = res["grad"][0]
+    a, b = grads[P.PMR_FP32], grads[P.PMR_MIXED]
+    say(f"  mixed vs FP32: grad rel-L2 {rel_l2(b, a):.3e}, cos {cosine(b, a):.6f}")
