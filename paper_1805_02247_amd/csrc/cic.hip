@@ -546,7 +546,7 @@ struct StepArgs {
   const double* x;    // [B][3][Np^3] positions x_i
   double* x_next;     // positions x_{i+1}
   float* p;           // momenta, updated in place
-  const float* F;     // [B][3][nm^3] force meshes at x_i
+  const float4* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz, -) at x_i
   uint32_t* keys;     // keys of x_{i+1} (nullable)
   float4* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
   int log_np3, nm, total;
@@ -569,16 +569,17 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   const int nm = a.nm;
   const Corner c = corner_of(xyz, a.scale, nm);
   const size_t cells = (size_t)nm * nm * nm;
-  const float* F = a.F + (size_t)item * 3 * cells;
+  const float4* F = a.F + (size_t)item * cells;
   float fa[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
     const float w = (ox ? c.f[0] : 1.f - c.f[0]) * (oy ? c.f[1] : 1.f - c.f[1]) *
                      (oz ? c.f[2] : 1.f - c.f[2]);
-    const size_t ci = cidx(c, ox, oy, oz, nm);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) fa[q] += w * F[q * cells + ci];
+    const float4 f = F[cidx(c, ox, oy, oz, nm)];
+    fa[0] += w * f.x;
+    fa[1] += w * f.y;
+    fa[2] += w * f.z;
   }
   double xn[3];
 #pragma unroll
@@ -599,7 +600,7 @@ struct AdjArgs {
   const double* x;     // positions x_i
   float* xbar;         // in: xbar_{i+1}; out: xbar_i
   float* pbar;         // in: pbar_{i+1/2}; out: pbar_{i-1/2}
-  const float* F;      // force meshes at x_i [B][3][nm^3] (nullable: final-paint adjoint)
+  const float4* F;     // interleaved force mesh at x_i [B][nm^3] (nullable: final-paint adjoint)
   const float* dbar;   // density adjoint mesh [B][nm^3]
   int log_np3, nm, total;
   double scale;
@@ -632,7 +633,7 @@ __global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
       fb[q] = a.kick * pb[q];
     }
   }
-  const float* F = a.F ? a.F + (size_t)item * 3 * cells : nullptr;
+  const float4* F = a.F ? a.F + (size_t)item * cells : nullptr;
   const float* D = a.dbar + (size_t)item * cells;
   const float s = (float)a.scale;
   float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -645,7 +646,10 @@ __global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
     const float dx = ox ? s : -s, dy = oy ? s : -s, dz = oz ? s : -s;
     const size_t ci = cidx(c, ox, oy, oz, nm);
     float v = a.mass * D[ci];
-    if (F) v += fb[0] * F[ci] + fb[1] * F[cells + ci] + fb[2] * F[2 * cells + ci];
+    if (F) {
+      const float4 f = F[ci];
+      v += fb[0] * f.x + fb[1] * f.y + fb[2] * f.z;
+    }
     gx += dx * wy * wz * v;
     gy += wx * dy * wz * v;
     gz += wx * wy * dz * v;
@@ -839,7 +843,7 @@ void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* v
   paint_dispatch<3>(a, batch, s);
 }
 
-void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
+void launch_kick_drift(const double* x, double* x_next, float* p, const float4* F, uint32_t* keys,
                        float4* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s) {
   StepArgs a{};
@@ -861,7 +865,7 @@ void launch_kick_drift(const double* x, double* x_next, float* p, const float* F
   kick_drift_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
-void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
+void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float4* F,
                            const float* dbar, int batch, int log_np3, int nm, double box,
                            float kick, float drift, float mass, int final_mode, float4* vnext,
                            float kick_next, float drift_next, hipStream_t s) {

@@ -102,7 +102,7 @@ struct pmr_ctx {
   float* ckp;
   int n_ck;
   float* p;     // [B][3][np3]
-  float* F;     // force slots [SF][B][3][nm3]
+  float4* F;    // force slots [SF][B][nm3], interleaved (Fx, Fy, Fz, -)
   uint32_t* ids;   // sort slots [SF][B*np3]
   uint32_t* skeys; // sorted keys [SF][B*np3]
   float4* frac;    // sorted CIC fractions [SF][B*np3]
@@ -195,7 +195,7 @@ void plan(pmr_ctx* c, Plan& P) {
   c->ckx = P.take<double>((size_t)c->n_ck * B * 3 * c->np3);
   c->ckp = P.take<float>((size_t)c->n_ck * B * 3 * c->np3);
   c->p = P.take<float>(B * 3 * c->np3);
-  c->F = P.take<float>((size_t)c->n_fslots * B * 3 * c->nm3);
+  c->F = P.take<float4>((size_t)c->n_fslots * B * c->nm3);
   c->ids = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->skeys = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->frac = P.take<float4>((size_t)c->n_fslots * B * c->np3);
@@ -375,6 +375,22 @@ void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, siz
   }
 }
 
+// Spectra of the three force components after the x pass -> interleaved float4 force mesh.
+void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_comp_stride,
+             float4* out) {
+  const int fields = c->B * 3;
+  const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
+  {
+    ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
+    launch_ypass(n, fields, in, fmap(3, in_item_stride, in_comp_stride), true, c->stream);
+  }
+  {
+    ProfScope ps(c, PMR_PROF_ZPASS, fields * 8.0 * cn + c->B * 16.0 * n3);
+    launch_zpass_c2r3(n, c->B, in, fmap(3, in_item_stride, in_comp_stride), out, (size_t)n * n * n,
+                      c->stream);
+  }
+}
+
 // Gaussian smoothing of a real field [B][n^3] on R (per item, params[param_index]).
 void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, const float* add,
             const double* scale = nullptr, float a1 = 1.f) {
@@ -394,7 +410,7 @@ void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, con
 
 // ---------------------------------------------------------------- PM pieces
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
-float* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * 3 * c->nm3; }
+float4* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
 uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
 float4* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
@@ -433,8 +449,8 @@ void pm_step(pmr_ctx* c, int i) {
     ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * cm);
     launch_xpass(XOP_FORCE, a, c->stream);
   }
-  float* F = fslot(c, fsl);
-  c2r_yz(c, c->nm, 3, c->cB, 3 * cm, cm, F, 3 * c->nm3, c->nm3, nullptr);
+  float4* F = fslot(c, fsl);
+  c2r_yz3(c, c->nm, c->cB, 3 * cm, cm, F);
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
   {
     ProfScope ps(c, PMR_PROF_KICK_DRIFT, 76.0 * B * c->np3 + 12.0 * B * c->nm3);
@@ -845,7 +861,7 @@ long long pmr_debug_copy(pmr_ctx* c, int what, int step, void* dst) {
       }
       if (what == PMR_DBG_FORCE) {
         src = fslot(c, sl);
-        bytes = B * 3 * c->nm3 * sizeof(float);
+        bytes = B * c->nm3 * sizeof(float4);
       } else {
         src = idslot(c, sl);
         bytes = B * c->np3 * sizeof(uint32_t);

@@ -107,6 +107,10 @@ void launch_zpass_r2c(int n, int fields, const float* in, FieldMap im, const flo
 // z pass c2r (unnormalised); optional out += add (add uses the output map)
 void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* out, FieldMap om,
                       const float* add, hipStream_t s);
+// Inverse z pass of the three components of a vector field per item (im: 3 fields per item)
+// into one interleaved float4 mesh [item][n^3] = (f0, f1, f2, 0).
+void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, float4* out,
+                       size_t out_item_stride, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
 // Tile shape of the strided passes (columns per tile, threads per workgroup, and whether the
@@ -139,10 +143,11 @@ void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t*
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s);
 void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
                        const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
-void launch_kick_drift(const double* x, double* x_next, float* p, const float* F, uint32_t* keys,
+// F: interleaved force mesh [B][nm^3] float4 (Fx, Fy, Fz, unused).
+void launch_kick_drift(const double* x, double* x_next, float* p, const float4* F, uint32_t* keys,
                        float4* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s);
-void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float* F,
+void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float4* F,
                            const float* dbar, int batch, int log_np3, int nm, double box,
                            float kick, float drift, float mass, int final_mode, float4* vnext,
                            float kick_next, float drift_next, hipStream_t s);
