@@ -73,12 +73,21 @@ __device__ __forceinline__ void bfly(float2* u) {
 }
 
 // ---------------------------------------------------------------- Stockham stage
-// M-point transforms of LINES lines held in LDS; point n of line l at lds[n*SN + l*SL].
+// M-point transforms of LINES lines held in LDS; point n of line l at lds[n*SN + l*SL], or at
+// lds[n + (n >> 5) + l*SL] when PAD (SN = 1): one padding slot every 32 points keeps the
+// strided butterfly writes of the first stages on distinct LDS banks.
 // Stage with radix R after earlier stages of total radix PREV: butterfly i (0..M/R-1)
 // reads points i + r M/R, twiddles by w^(r k M / (PREV R)) with k = i mod PREV, and
 // writes point (i - k) R + k + r PREV. Twiddle table: tw[j * TWS] = exp(-2 pi i j / M).
-template <int M, int R, int PREV, int LINES, int SN, int SL, int TWS, int DIR, int NTH>
+template <int SN, bool PAD>
+__device__ __forceinline__ int lpos(int n) {
+  if constexpr (PAD) return n + (n >> 5);
+  return n * SN;
+}
+
+template <int M, int R, int PREV, int LINES, int SN, int SL, int TWS, int DIR, int NTH, bool PAD>
 __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
+  static_assert(!PAD || SN == 1, "padding applies to unit-stride lines");
   constexpr int NB = (M / R) * LINES;
   constexpr int PER = (NB + NTH - 1) / NTH;
   float2 u[PER][R];
@@ -100,7 +109,7 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
       ii[m] = i;
       ll[m] = l;
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[m][r] = lds[(i + r * (M / R)) * SN + l * SL];
+      for (int r = 0; r < R; ++r) u[m][r] = lds[lpos<SN, PAD>(i + r * (M / R)) + l * SL];
     }
   }
   __syncthreads();
@@ -120,23 +129,23 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
       bfly<R, DIR>(u[m]);
       const int j0 = (i - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[(j0 + r * PREV) * SN + l * SL] = u[m][r];
+      for (int r = 0; r < R; ++r) lds[lpos<SN, PAD>(j0 + r * PREV) + l * SL] = u[m][r];
     }
   }
   __syncthreads();
 }
 
 // Full M-point transform: radix-8 stages, then one radix-4 or radix-2 stage.
-template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT>
+template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT, bool PAD = false>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw) {
   static_assert(M >= 2 && (M & (M - 1)) == 0, "power of two");
-  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
+  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
   constexpr int P8 = M >= 512 ? 512 : M >= 64 ? 64 : M >= 8 ? 8 : 1;
   constexpr int REM = M / P8;
-  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
-  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH>(lds, tw);
+  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
   static_assert(M <= 512, "at most 512 points per line");
 }
 
@@ -155,8 +164,11 @@ template <int N>
 struct ZTile {
   static constexpr int H = N / 2;                        // complex points per row
   static constexpr int ROWS = (2048 / H) > 0 ? 2048 / H : 1;
-  static constexpr int PITCH = H + 1;                    // LDS row pitch (complex)
+  static constexpr int PITCH = H + H / 32 + 1;           // LDS row pitch (complex, padded)
 };
+
+// LDS slot of point k of a z-pass row (one padding slot every 32 points, see lpos).
+__device__ __forceinline__ int zk(int k) { return k + (k >> 5); }
 
 // in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex.
 // Value loaded: a1 * in (+ a2 * in2 if in2) (* scale_dev[field / fields_per_item]).
@@ -171,7 +183,7 @@ __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
   const int field = blockIdx.y;
-  const size_t row0 = (size_t)blockIdx.x * ROWS;
+  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
   const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
   const float2* src2 =
       in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
@@ -187,33 +199,33 @@ __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__
       v.x += b2 * w.x;
       v.y += b2 * w.y;
     }
-    lds[(e / H) * PITCH + (e % H)] = v;
+    lds[(e / H) * PITCH + zk(e % H)] = v;
   }
   __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, -1>(lds, tw);
+  fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
   // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2, W = e^{-2 pi i/N}
-  float2* dst = out + om.off(field) + row0 * (H + 1);
+  float2* dst = out + om.off(field) + row0 * om.pitch;
   constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
   for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
     const int r = e / Q, k = e % Q;
     const float2* z = lds + r * PITCH;
-    float2* d = dst + (size_t)r * (H + 1);
+    float2* d = dst + (size_t)r * om.pitch;
     if (k == 0) {
       float2 z0 = z[0];
       d[0] = make_float2(z0.x + z0.y, 0.f);
       d[H] = make_float2(z0.x - z0.y, 0.f);
     } else {
-      const float2 zk = z[k], zm = z[H - k];
+      const float2 zv = z[zk(k)], zm = z[zk(H - k)];
       {
-        float2 s = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        float2 df = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+        float2 s = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
+        float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
         float2 w = tw[k];
         float2 t = cmul(w, df);  // W^k * diff
         d[k] = make_float2(s.x + t.y, s.y - t.x);  // s - i t
       }
       if (k != H - k) {
-        float2 s = make_float2(0.5f * (zm.x + zk.x), 0.5f * (zm.y - zk.y));
-        float2 df = make_float2(0.5f * (zm.x - zk.x), 0.5f * (zm.y + zk.y));
+        float2 s = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
+        float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
         float2 w = tw[H - k];
         float2 t = cmul(w, df);
         d[H - k] = make_float2(s.x + t.y, s.y - t.x);
@@ -236,14 +248,14 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
   const int field = blockIdx.y;
-  const size_t row0 = (size_t)blockIdx.x * ROWS;
-  const float2* src = in + im.off(field) + row0 * (H + 1);
+  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+  const float2* src = in + im.off(field) + row0 * im.pitch;
   __syncthreads();
   // inverse split: Z[k] = E + i O, E = X[k] + conj X[H-k], O = (X[k] - conj X[H-k]) conj(W^k)
   constexpr int Q = H / 2 + 1;
   for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
     const int r = e / Q, k = e % Q;
-    const float2* x = src + (size_t)r * (H + 1);
+    const float2* x = src + (size_t)r * im.pitch;
     float2* z = lds + r * PITCH;
     if (k == 0) {
       const float a = x[0].x, b = x[H].x;
@@ -254,22 +266,22 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
         float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
         float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
         float2 O = cmul(D, cconj(tw[k]));
-        z[k] = make_float2(E.x - O.y, E.y + O.x);  // E + i O
+        z[zk(k)] = make_float2(E.x - O.y, E.y + O.x);  // E + i O
       }
       if (k != H - k) {
         float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
         float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
         float2 O = cmul(D, cconj(tw[H - k]));
-        z[H - k] = make_float2(E.x - O.y, E.y + O.x);
+        z[zk(H - k)] = make_float2(E.x - O.y, E.y + O.x);
       }
     }
   }
   __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, +1>(lds, tw);
+  fft_lds<H, ROWS, 1, PITCH, 2, +1, NT, true>(lds, tw);
   float2* dst = reinterpret_cast<float2*>(out + om.off(field)) + row0 * H;
   const float2* ad = add ? reinterpret_cast<const float2*>(add + om.off(field)) + row0 * H : nullptr;
   for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-    float2 v = lds[(e / H) * PITCH + (e % H)];
+    float2 v = lds[(e / H) * PITCH + zk(e % H)];
     if (ad) {
       float2 w = ad[e];
       v.x += w.x;
@@ -297,13 +309,13 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
   const int item = blockIdx.y;
-  const size_t row0 = (size_t)blockIdx.x * R;
+  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * R;
   __syncthreads();
   constexpr int Q = H / 2 + 1;
   for (int e = threadIdx.x; e < 3 * R * Q; e += NT) {
     const int line = e / Q, k = e % Q;  // line = component * R + row
     const int f = line / R, r = line % R;
-    const float2* x = in + im.off(item * 3 + f) + (row0 + r) * (H + 1);
+    const float2* x = in + im.off(item * 3 + f) + (row0 + r) * im.pitch;
     float2* z = lds + line * PITCH;
     if (k == 0) {
       const float a = x[0].x, b = x[H].x;
@@ -314,24 +326,25 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
         float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
         float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
         float2 O = cmul(D, cconj(tw[k]));
-        z[k] = make_float2(E.x - O.y, E.y + O.x);
+        z[zk(k)] = make_float2(E.x - O.y, E.y + O.x);
       }
       if (k != H - k) {
         float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
         float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
         float2 O = cmul(D, cconj(tw[H - k]));
-        z[H - k] = make_float2(E.x - O.y, E.y + O.x);
+        z[zk(H - k)] = make_float2(E.x - O.y, E.y + O.x);
       }
     }
   }
   __syncthreads();
-  fft_lds<H, 3 * R, 1, PITCH, 2, +1>(lds, tw);
+  fft_lds<H, 3 * R, 1, PITCH, 2, +1, NT, true>(lds, tw);
   float4* dst = out + item * out_item_stride + row0 * N;
   const float* l = reinterpret_cast<const float*>(lds);
   for (int e = threadIdx.x; e < R * N; e += NT) {
     const int r = e / N, zz = e % N;
-    dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + zz], l[(1 * R + r) * 2 * PITCH + zz],
-                         l[(2 * R + r) * 2 * PITCH + zz], 0.f);
+    const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
+    dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
+                         l[(2 * R + r) * 2 * PITCH + q], 0.f);
   }
 }
 
@@ -392,13 +405,13 @@ __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, F
     const int ch = tau % NCH, rest = tau / NCH;
     const int ix = rest % N, f = rest / N;
     ncols = min(PC, NH - ch * PC);
-    return data + m.off(f) + (size_t)ix * N * NH + ch * PC;
+    return data + m.off(f) + (size_t)ix * N * m.pitch + ch * PC;
   };
-  int tau = blockIdx.x;
+  int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   int nc;
   float2* b = tile_base(tau, nc);
   float2 pre[PER];
-  load_regs<N, PC, NTH>(pre, b, NH, nc);
+  load_regs<N, PC, NTH>(pre, b, m.pitch, nc);
   for (;;) {
     regs_to_lds<N, PC, NTH>(pre, lds);
     __syncthreads();
@@ -407,10 +420,10 @@ __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, F
     float2* b2 = nullptr;
     if (next < ntiles) {
       b2 = tile_base(next, nc2);
-      load_regs<N, PC, NTH>(pre, b2, NH, nc2);
+      load_regs<N, PC, NTH>(pre, b2, m.pitch, nc2);
     }
     fft_lds<N, PC, PC, 1, 1, DIR, NTH>(lds, tw);
-    store_tile<N, PC, NTH>(lds, b, NH, nc);
+    store_tile<N, PC, NTH>(lds, b, m.pitch, nc);
     if (next >= ntiles) break;
     __syncthreads();
     tau = next;
@@ -458,28 +471,28 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   __shared__ float2 lds[NE];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
-  const size_t stride = (size_t)N * NH;
+  const size_t istride = (size_t)N * a.in_pitch, ostride = (size_t)N * a.out_pitch;
+  const size_t stride = (size_t)N * NH;  // prior table and projected modes (standard layout)
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
   const int t = threadIdx.x;
   const int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
   const int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
 
-  int tau = blockIdx.x;
+  int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   float2 pre[PER];  // first input of the current tile (prefetched)
   {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     const int kz0 = ch * PC;
-    load_regs<N, PC, NTH>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * NH + kz0, stride,
-                          min(PC, NH - kz0));
+    load_regs<N, PC, NTH>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0,
+                          istride, min(PC, NH - kz0));
   }
   for (;;) {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
-    const size_t toff = (size_t)iy * NH + kz0;
-    const size_t ioff = item * a.in_item_stride + toff;
-    const size_t ooff = item * a.out_item_stride + toff;
+    const size_t ioff = item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0;
+    const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
     const int next = tau + gridDim.x;
 
     float2 hold[PER];  // spectrum (1-in ops) or accumulator (n-in ops)
@@ -493,14 +506,14 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
       if (i == 0) {
         regs_to_lds<N, PC, NTH>(pre, lds);
       } else {
-        load_tile<N, PC, NTH>(lds, a.in[i] + ioff, stride, ncols);
+        load_tile<N, PC, NTH>(lds, a.in[i] + ioff, istride, ncols);
       }
       __syncthreads();
       if (i == 0 && next < ntiles) {
         const int nch = next % NCH, niy = (next / NCH) % N, nit = next / (NCH * N);
         const int nkz0 = nch * PC;
-        load_regs<N, PC, NTH>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * NH + nkz0,
-                              stride, min(PC, NH - nkz0));
+        load_regs<N, PC, NTH>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
+                              istride, min(PC, NH - nkz0));
       }
       if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
 #pragma unroll
@@ -532,7 +545,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
 #pragma unroll
       for (int m = 0; m < PER; ++m) lds[t + m * NTH] = hold[m];
       __syncthreads();
-      store_tile<N, PC, NTH>(lds, a.out[0] + ooff, stride, ncols);
+      store_tile<N, PC, NTH>(lds, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
       const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
         }
         __syncthreads();
         fft_lds<N, PC, PC, 1, 1, +1, NTH>(lds, tw);
-        store_tile<N, PC, NTH>(lds, a.out[o] + ooff, stride, ncols);
+        store_tile<N, PC, NTH>(lds, a.out[o] + ooff, ostride, ncols);
         __syncthreads();
       }
     }
@@ -770,13 +783,13 @@ __global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ dat
     const int ch = tau % NCH, rest = tau / NCH;
     const int ix = rest % N, f = rest / N;
     ncols = min(PC, NH - ch * PC);
-    return data + m.off(f) + (size_t)ix * N * NH + ch * PC;
+    return data + m.off(f) + (size_t)ix * N * m.pitch + ch * PC;
   };
-  int tau = blockIdx.x;
+  int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   int nc;
   float2* b = tile_base(tau, nc);
   float2 pre[P], v[P];
-  reg_load<N, PC, NTH, R0>(pre, b, NH, nc);
+  reg_load<N, PC, NTH, R0>(pre, b, m.pitch, nc);
   __syncthreads();  // twiddles
   for (;;) {
 #pragma unroll
@@ -786,10 +799,10 @@ __global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ dat
     float2* b2 = nullptr;
     if (next < ntiles) {
       b2 = tile_base(next, nc2);
-      reg_load<N, PC, NTH, R0>(pre, b2, NH, nc2);
+      reg_load<N, PC, NTH, R0>(pre, b2, m.pitch, nc2);
     }
     reg_fft<N, PC, NTH, REV, DIR>(v, lds, tw);
-    reg_store<N, PC, NTH, RL>(v, b, NH, nc);
+    reg_store<N, PC, NTH, RL>(v, b, m.pitch, nc);
     if (next >= ntiles) break;
     tau = next;
     b = b2;
@@ -812,7 +825,8 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   __shared__ float2 lds[N * PC];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
-  const size_t stride = (size_t)N * NH;
+  const size_t istride = (size_t)N * a.in_pitch, ostride = (size_t)N * a.out_pitch;
+  const size_t stride = (size_t)N * NH;  // prior table, projected modes, gradient
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
   constexpr int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
@@ -821,21 +835,21 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   auto in_base = [&](int tau, int i, int& ncols) {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     ncols = min(PC, NH - ch * PC);
-    return a.in[i] + item * a.in_item_stride + (size_t)iy * NH + ch * PC;
+    return a.in[i] + item * a.in_item_stride + (size_t)iy * a.in_pitch + ch * PC;
   };
-  int tau = blockIdx.x;
+  int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   float2 pre[P];
   {
     int nc;
     const float2* b0 = in_base(tau, 0, nc);
-    reg_load<N, PC, NTH, RIN>(pre, b0, stride, nc);
+    reg_load<N, PC, NTH, RIN>(pre, b0, istride, nc);
   }
   __syncthreads();  // twiddles
   for (;;) {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
-    const size_t ooff = item * a.out_item_stride + (size_t)iy * NH + kz0;
+    const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
     const int next = tau + gridDim.x;
     float Rg = 0.f;
     if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
@@ -852,11 +866,11 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
       if (i + 1 < n_in) {
         int nc;
         const float2* bi = in_base(tau, i + 1, nc);
-        reg_load<N, PC, NTH, RIN>(pre, bi, stride, nc);
+        reg_load<N, PC, NTH, RIN>(pre, bi, istride, nc);
       } else if (next < ntiles) {
         int nc;
         const float2* bn = in_base(next, 0, nc);
-        reg_load<N, PC, NTH, RIN>(pre, bn, stride, nc);
+        reg_load<N, PC, NTH, RIN>(pre, bn, istride, nc);
       }
       if constexpr (!SPECTRAL_IN) reg_fft<N, PC, NTH, false, -1>(v, lds, tw);
 #pragma unroll
@@ -884,7 +898,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
     }
     // -------- outputs
     if constexpr (OP == XOP_FWD) {
-      reg_store<N, PC, NTH, RLF>(hold, a.out[0] + ooff, stride, ncols);
+      reg_store<N, PC, NTH, RLF>(hold, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
       const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
@@ -933,7 +947,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
           v[q] = x;
         }
         reg_fft<N, PC, NTH, true, +1>(v, lds, tw);
-        reg_store<N, PC, NTH, RLI>(v, a.out[o] + ooff, stride, ncols);
+        reg_store<N, PC, NTH, RLI>(v, a.out[o] + ooff, ostride, ncols);
       }
     }
     if (next >= ntiles) break;

@@ -73,6 +73,11 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// Row pitch of the library's internal half spectra, in complex elements: n/2 + 1 rounded up
+// to 16 (128 bytes), so that every row of a strided FFT tile starts on a cache line. Arrays
+// crossing the API (modes, gradient, prior table) keep the standard pitch n/2 + 1.
+size_t spec_pitch(int n) { return ((size_t)(n / 2 + 1) + 15) / 16 * 16; }
+
 struct pmr_ctx {
   pmr_config cfg;
   hipStream_t stream;
@@ -82,7 +87,8 @@ struct pmr_ctx {
   int have_prior, have_mlp, have_target, have_loss, xd_dirty, fwd_done;
   // sizes
   int B, np, nm, no, n, H, k;
-  size_t np3, nm3, no3, cp, cm, co, cmax;
+  size_t np3, nm3, no3, cp, cm, co;  // standard half-spectrum sizes n * n * (n/2 + 1)
+  size_t sp, sm, so, cmax;           // internal spectra: n * n * row pitch (rows of 128 B)
   int log_np3, log_nm, log_no;
   int key_bits_m, key_bits_o;
   // factors
@@ -250,8 +256,11 @@ void init_sizes(pmr_ctx* c, const pmr_config* cfg) {
   c->cp = (size_t)c->np * c->np * (c->np / 2 + 1);
   c->cm = (size_t)c->nm * c->nm * (c->nm / 2 + 1);
   c->co = (size_t)c->no * c->no * (c->no / 2 + 1);
-  c->cmax = c->cp > c->cm ? c->cp : c->cm;
-  if (c->co > c->cmax) c->cmax = c->co;
+  c->sp = (size_t)c->np * c->np * spec_pitch(c->np);
+  c->sm = (size_t)c->nm * c->nm * spec_pitch(c->nm);
+  c->so = (size_t)c->no * c->no * spec_pitch(c->no);
+  c->cmax = c->sp > c->sm ? c->sp : c->sm;
+  if (c->so > c->cmax) c->cmax = c->so;
   c->log_np3 = ilog2(c->np3);
   c->log_nm = ilog2((size_t)c->nm);
   c->log_no = ilog2((size_t)c->no);
@@ -319,11 +328,12 @@ struct ProfScope {
 };
 
 // ---------------------------------------------------------------- pass helpers
-FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride) {
+FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride, size_t pitch = 0) {
   FieldMap m;
   m.fpi = fpi;
   m.item_stride = item_stride;
   m.comp_stride = comp_stride;
+  m.pitch = pitch;
   return m;
 }
 
@@ -336,6 +346,7 @@ XPassArgs xargs(pmr_ctx* c, int n) {
   a.R1 = c->cfg.R1;
   a.R2 = c->cfg.R2;
   a.params = c->params;
+  a.in_pitch = a.out_pitch = spec_pitch(n);
   return a;
 }
 
@@ -351,11 +362,13 @@ void r2c_zy(pmr_ctx* c, int n, int ncomp, const float* in, size_t in_item_stride
   {
     ProfScope ps(c, PMR_PROF_ZPASS, fields * ((in2 ? 8.0 : 4.0) * n3 + 8.0 * cn));
     launch_zpass_r2c(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), in2, a1, a2,
-                     scale, out, fmap(ncomp, out_item_stride, out_comp_stride), c->stream);
+                     scale, out, fmap(ncomp, out_item_stride, out_comp_stride, spec_pitch(n)),
+                     c->stream);
   }
   {
     ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
-    launch_ypass(n, fields, out, fmap(ncomp, out_item_stride, out_comp_stride), false, c->stream);
+    launch_ypass(n, fields, out, fmap(ncomp, out_item_stride, out_comp_stride, spec_pitch(n)), false,
+                 c->stream);
   }
 }
 
@@ -366,11 +379,12 @@ void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, siz
   const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
   {
     ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
-    launch_ypass(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), true, c->stream);
+    launch_ypass(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride, spec_pitch(n)), true,
+                 c->stream);
   }
   {
     ProfScope ps(c, PMR_PROF_ZPASS, fields * (8.0 * cn + (add ? 8.0 : 4.0) * n3));
-    launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride), out,
+    launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride, spec_pitch(n)), out,
                      fmap(ncomp, out_item_stride, out_comp_stride), add, c->stream);
   }
 }
@@ -382,19 +396,20 @@ void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_com
   const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
   {
     ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
-    launch_ypass(n, fields, in, fmap(3, in_item_stride, in_comp_stride), true, c->stream);
+    launch_ypass(n, fields, in, fmap(3, in_item_stride, in_comp_stride, spec_pitch(n)), true,
+                 c->stream);
   }
   {
     ProfScope ps(c, PMR_PROF_ZPASS, fields * 8.0 * cn + c->B * 16.0 * n3);
-    launch_zpass_c2r3(n, c->B, in, fmap(3, in_item_stride, in_comp_stride), out, (size_t)n * n * n,
-                      c->stream);
+    launch_zpass_c2r3(n, c->B, in, fmap(3, in_item_stride, in_comp_stride, spec_pitch(n)), out,
+                      (size_t)n * n * n, c->stream);
   }
 }
 
 // Gaussian smoothing of a real field [B][n^3] on R (per item, params[param_index]).
 void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, const float* add,
             const double* scale = nullptr, float a1 = 1.f) {
-  const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  const size_t n3 = (size_t)n * n * n, cn = (size_t)n * n * spec_pitch(n);
   r2c_zy(c, n, 1, in, n3, 0, nullptr, a1, 0.f, scale, c->cA, cn, 0);
   XPassArgs a = xargs(c, n);
   a.n_in = 1;
@@ -436,7 +451,7 @@ void pm_step(pmr_ctx* c, int i) {
     launch_paint_mass(keyslot(c, fsl), fracslot(c, fsl), rowslot(c, fsl), B, c->nm, c->mass_m,
                       1.f, c->dens, c->stream);
   }
-  const size_t cm = c->cm;
+  const size_t cm = c->sm;
   r2c_zy(c, c->nm, 1, c->dens, c->nm3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, cm, 0);
   XPassArgs a = xargs(c, c->nm);
   a.n_in = 1;
@@ -446,7 +461,7 @@ void pm_step(pmr_ctx* c, int i) {
   a.in_item_stride = cm;
   a.out_item_stride = 3 * cm;
   {
-    ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * cm);
+    ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * c->cm);
     launch_xpass(XOP_FORCE, a, c->stream);
   }
   float4* F = fslot(c, fsl);
@@ -611,13 +626,14 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   if (c->xd_dirty) refresh_xd(c);
   // H1: Zel'dovich displacement on the particle lattice
   {
-    const size_t cp = c->cp;
+    const size_t cp = c->sp;
     XPassArgs a = xargs(c, c->np);
     a.n_in = 1;
     a.n_out = 3;
-    a.in[0] = c->ps;
+    a.in[0] = c->ps;  // projected modes, standard layout
     for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cp;
-    a.in_item_stride = cp;
+    a.in_item_stride = c->cp;
+    a.in_pitch = (size_t)(c->np / 2 + 1);
     a.out_item_stride = 3 * cp;
     launch_xpass(XOP_ZA, a, s);
     c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->psi, 3 * c->np3, c->np3, nullptr);
@@ -640,7 +656,7 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     if (mass_out)
       HIPC(c, hipMemcpyAsync(mass_out, c->delta_f, B * c->no3 * sizeof(float), hipMemcpyDeviceToDevice, s));
   } else {
-    const size_t no3 = c->no3, co = c->co;
+    const size_t no3 = c->no3, co = c->so;
     r2c_zy(c, c->no, 1, c->delta_f, no3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, co, 0);
     XPassArgs a = xargs(c, c->no);
     a.n_in = 1;
@@ -675,7 +691,7 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
   if (!c->fwd_done) return PMR_E_STATE;
   const int B = c->B;
   hipStream_t s = c->stream;
-  const size_t no3 = c->no3, co = c->co;
+  const size_t no3 = c->no3, co = c->so;
   float* dbar_f = c->ob + 3 * (size_t)B * no3;
   // H12-H13: likelihood, network and feature adjoints -> dbar_f
   if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
@@ -695,11 +711,12 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
                      o2, o0, o1, dbar_f, s);
     // g0 -> o0, g12 -> o1, g2 -> dbar_f (temporarily); feature adjoint:
     // dbar_f = g0 + irfft(G1 rfft(g12) - G2 rfft(g2))
+    const size_t po = spec_pitch(c->no);
     launch_zpass_r2c(c->no, B, o1, fmap(1, no3, 0), nullptr, 1.f, 0.f, nullptr, c->cB,
-                     fmap(1, 3 * co, 0), s);
+                     fmap(1, 3 * co, 0, po), s);
     launch_zpass_r2c(c->no, B, dbar_f, fmap(1, no3, 0), nullptr, 1.f, 0.f, nullptr, c->cB + co,
-                     fmap(1, 3 * co, 0), s);
-    launch_ypass(c->no, 2 * B, c->cB, fmap(2, 3 * co, co), false, s);
+                     fmap(1, 3 * co, 0, po), s);
+    launch_ypass(c->no, 2 * B, c->cB, fmap(2, 3 * co, co, po), false, s);
     XPassArgs a = xargs(c, c->no);
     a.n_in = 2;
     a.n_out = 1;
@@ -717,7 +734,7 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
                         0.f, 0.f, c->mass_o, 1, c->vid, (float)c->kick[c->n - 1],
                         (float)c->drift[c->n - 1], s);
   // H15: reverse PM steps (recomputing segments from checkpoints when needed)
-  const size_t cm = c->cm;
+  const size_t cm = c->sm;
   const double scale_m = (double)c->nm / c->cfg.box;
   int resident_lo = c->k == 0 ? 0 : ((c->n - 1) / c->k) * c->k;  // first step held in slots
   for (int i = c->n - 1; i >= 0; --i) {
@@ -753,7 +770,7 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     a.in_item_stride = 3 * cm;
     a.out_item_stride = cm;
     {
-      ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, 32.0 * B * cm);
+      ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, 32.0 * B * c->cm);
       launch_xpass(XOP_FORCE_ADJ, a, s);
     }
     c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
@@ -767,17 +784,18 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
   }
   // H16: Zel'dovich adjoint and gradient assembly (with the prior)
   {
-    const size_t cp = c->cp;
+    const size_t cp = c->sp;
     r2c_zy(c, c->np, 3, c->xbar, 3 * c->np3, c->np3, c->pbar, (float)c->D0, (float)c->Gp0, nullptr,
            c->cB, 3 * cp, cp);
     XPassArgs a = xargs(c, c->np);
     a.n_in = 3;
     a.n_out = 1;
     for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cp;
-    a.out[0] = (float2*)grad;
+    a.out[0] = (float2*)grad;  // standard layout, like proj_modes and the prior table
     a.in_item_stride = 3 * cp;
-    a.out_item_stride = cp;
-    a.aux_item_stride = cp;
+    a.out_item_stride = c->cp;
+    a.out_pitch = (size_t)(c->np / 2 + 1);
+    a.aux_item_stride = c->cp;
     a.proj_modes = c->ps;
     a.inv_var = c->inv_var;
     a.loss_bar = loss_bar;
@@ -888,9 +906,11 @@ int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream) {
   if (!pow2_in(n, 16, 512)) return PMR_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
   const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  const size_t nh = (size_t)(n / 2 + 1);  // the caller's array has the standard pitch
   float2* o = (float2*)out;
-  launch_zpass_r2c(n, batch, in, fmap(1, n3, 0), nullptr, 1.f, 0.f, nullptr, o, fmap(1, cn, 0), s);
-  launch_ypass(n, batch, o, fmap(1, cn, 0), false, s);
+  launch_zpass_r2c(n, batch, in, fmap(1, n3, 0), nullptr, 1.f, 0.f, nullptr, o, fmap(1, cn, 0, nh),
+                   s);
+  launch_ypass(n, batch, o, fmap(1, cn, 0, nh), false, s);
   XPassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = n;
@@ -899,6 +919,7 @@ int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream) {
   a.in[0] = o;
   a.out[0] = o;
   a.in_item_stride = a.out_item_stride = cn;
+  a.in_pitch = a.out_pitch = nh;
   a.box = 1.0;
   launch_xpass(XOP_FWD, a, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
@@ -909,6 +930,7 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
   if (!pow2_in(n, 16, 512)) return PMR_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
   const size_t n3 = (size_t)n * n * n, cn = cplx(n);
+  const size_t nh = (size_t)(n / 2 + 1);
   float2* d = (float2*)inout;
   XPassArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -918,10 +940,11 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
   a.in[0] = d;
   a.out[0] = d;
   a.in_item_stride = a.out_item_stride = cn;
+  a.in_pitch = a.out_pitch = nh;
   a.box = 1.0;
   launch_xpass(XOP_INV, a, s);
-  launch_ypass(n, batch, d, fmap(1, cn, 0), true, s);
-  launch_zpass_c2r(n, batch, d, fmap(1, cn, 0), out, fmap(1, n3, 0), nullptr, s);
+  launch_ypass(n, batch, d, fmap(1, cn, 0, nh), true, s);
+  launch_zpass_c2r(n, batch, d, fmap(1, cn, 0, nh), out, fmap(1, n3, 0), nullptr, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 

@@ -65,6 +65,7 @@ namespace pmr {
 struct FieldMap {
   int fpi;
   size_t item_stride, comp_stride;  // elements (of the array's type)
+  size_t pitch;                     // spectra: complex elements per (x, y) row, >= n/2 + 1
   __host__ __device__ size_t off(int f) const {
     return (size_t)(f / fpi) * item_stride + (size_t)(f % fpi) * comp_stride;
   }
@@ -90,7 +91,8 @@ struct XPassArgs {
   const float2* in[3];
   float2* out[3];
   size_t in_item_stride, out_item_stride;  // complex elements between batch items
-  size_t aux_item_stride;                  // for proj_modes
+  size_t in_pitch, out_pitch;              // complex elements per (x, y) row of in / out
+  size_t aux_item_stride;                  // for proj_modes (standard layout, pitch n/2 + 1)
   double box;
   double R1, R2;       // feature scales (XOP_GAUSS2 / XOP_FEAT_ADJ)
   const double* params;  // device loss params [B][6] (XOP_GAUSS reads R at param_index)
