@@ -170,124 +170,189 @@ struct ZTile {
 // LDS slot of point k of a z-pass row (one padding slot every 32 points, see lpos).
 __device__ __forceinline__ int zk(int k) { return k + (k >> 5); }
 
-// in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex.
+// The z passes are tile loops: a workgroup walks tiles blockIdx-remapped, blockIdx + grid, ...
+// (tile = one field's group of consecutive rows), prefetching the next tile's input into
+// registers while the current one is transformed, and computes its twiddles once.
+
+// Inverse split of one row pair: Z[k] = E + i O with E = X[k] + conj X[H-k] and
+// O = (X[k] - conj X[H-k]) conj(W^k), W = e^{-2 pi i / N}; k = 0 combines X[0] and X[H].
+template <int H>
+__device__ __forceinline__ void inv_split(float2* z, int k, float2 xk, float2 xm, const float2* tw) {
+  if (k == 0) {
+    z[0] = make_float2(xk.x + xm.x, xk.x - xm.x);  // xk = X[0], xm = X[H] (real parts)
+    return;
+  }
+  {
+    float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
+    float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
+    float2 O = cmul(D, cconj(tw[k]));
+    z[zk(k)] = make_float2(E.x - O.y, E.y + O.x);
+  }
+  if (k != H - k) {
+    float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
+    float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
+    float2 O = cmul(D, cconj(tw[H - k]));
+    z[zk(H - k)] = make_float2(E.x - O.y, E.y + O.x);
+  }
+}
+
+// in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex (row pitch om.pitch).
 // Value loaded: a1 * in (+ a2 * in2 if in2) (* scale_dev[field / fields_per_item]).
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__ in, FieldMap im,
                                                        const float* __restrict__ in2, float a1,
                                                        float a2, const double* __restrict__ scale_dev,
-                                                       float2* __restrict__ out, FieldMap om) {
+                                                       float2* __restrict__ out, FieldMap om,
+                                                       int tiles_per_field, int ntiles) {
   using T = ZTile<N>;
   constexpr int H = T::H, ROWS = T::ROWS, PITCH = T::PITCH;
+  constexpr int PER = (ROWS * H + NT - 1) / NT;
   __shared__ float2 lds[ROWS * PITCH];
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
-  const int field = blockIdx.y;
-  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
-  const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
-  const float2* src2 =
-      in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
-  float sc = 1.0f;
-  if (scale_dev) sc = (float)scale_dev[field / im.fpi];
-  const float b1 = a1 * sc, b2 = a2 * sc;
-  for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-    float2 v = src[e];
-    v.x *= b1;
-    v.y *= b1;
-    if (src2) {
-      float2 w = src2[e];
-      v.x += b2 * w.x;
-      v.y += b2 * w.y;
-    }
-    lds[(e / H) * PITCH + zk(e % H)] = v;
-  }
-  __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
-  // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2, W = e^{-2 pi i/N}
-  float2* dst = out + om.off(field) + row0 * om.pitch;
-  constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
-  for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-    const int r = e / Q, k = e % Q;
-    const float2* z = lds + r * PITCH;
-    float2* d = dst + (size_t)r * om.pitch;
-    if (k == 0) {
-      float2 z0 = z[0];
-      d[0] = make_float2(z0.x + z0.y, 0.f);
-      d[H] = make_float2(z0.x - z0.y, 0.f);
-    } else {
-      const float2 zv = z[zk(k)], zm = z[zk(H - k)];
-      {
-        float2 s = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
-        float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
-        float2 w = tw[k];
-        float2 t = cmul(w, df);  // W^k * diff
-        d[k] = make_float2(s.x + t.y, s.y - t.x);  // s - i t
+  auto load = [&](int t, float2 (&r)[PER]) {
+    const int field = t / tiles_per_field;
+    const size_t row0 = (size_t)(t % tiles_per_field) * ROWS;
+    const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
+    const float2* src2 =
+        in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
+    const float sc = scale_dev ? (float)scale_dev[field / im.fpi] : 1.0f;
+    const float b1 = a1 * sc, b2 = a2 * sc;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      float2 v = make_float2(0.f, 0.f);
+      if ((ROWS * H) % NT == 0 || e < ROWS * H) {
+        v = src[e];
+        v.x *= b1;
+        v.y *= b1;
+        if (src2) {
+          const float2 w = src2[e];
+          v.x += b2 * w.x;
+          v.y += b2 * w.y;
+        }
       }
-      if (k != H - k) {
-        float2 s = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
-        float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
-        float2 w = tw[H - k];
-        float2 t = cmul(w, df);
-        d[H - k] = make_float2(s.x + t.y, s.y - t.x);
+      r[m] = v;
+    }
+  };
+  int tau = xcd_block(blockIdx.x, gridDim.x);
+  float2 pre[PER];
+  load(tau, pre);
+  __syncthreads();  // twiddles
+  for (;;) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if ((ROWS * H) % NT == 0 || e < ROWS * H) lds[(e / H) * PITCH + zk(e % H)] = pre[m];
+    }
+    __syncthreads();
+    const int next = tau + gridDim.x;
+    if (next < ntiles) load(next, pre);
+    fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
+    // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2
+    const int field = tau / tiles_per_field;
+    const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
+    float2* dst = out + om.off(field) + row0 * om.pitch;
+    constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
+    for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
+      const int r = e / Q, k = e % Q;
+      const float2* z = lds + r * PITCH;
+      float2* d = dst + (size_t)r * om.pitch;
+      if (k == 0) {
+        float2 z0 = z[0];
+        d[0] = make_float2(z0.x + z0.y, 0.f);
+        d[H] = make_float2(z0.x - z0.y, 0.f);
+      } else {
+        const float2 zv = z[zk(k)], zm = z[zk(H - k)];
+        {
+          float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
+          float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
+          float2 t = cmul(tw[k], df);  // W^k * diff
+          d[k] = make_float2(sm.x + t.y, sm.y - t.x);  // sm - i t
+        }
+        if (k != H - k) {
+          float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
+          float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
+          float2 t = cmul(tw[H - k], df);
+          d[H - k] = make_float2(sm.x + t.y, sm.y - t.x);
+        }
       }
     }
+    if (next >= ntiles) break;
+    __syncthreads();  // the split has read the tile
+    tau = next;
   }
 }
 
-// ---------------------------------------------------------------- z pass, c2r
-// in: fields of n*n*(n/2+1) complex; out: fields of n^3 reals = unnormalised inverse
-// transform along z of each row (imaginary parts of the kz = 0 and n/2 entries ignored).
-// Optional epilogue: out += add.
+// Row pairs (k, H - k) of a c2r tile held in registers: pair e = threadIdx + m NT of the
+// tile's LINES * Q pairs (line = e / Q, k = e % Q).
+template <int H, int LINES>
+struct PairRegs {
+  static constexpr int Q = H / 2 + 1;
+  static constexpr int PER = (LINES * Q + NT - 1) / NT;
+  float2 a[PER], b[PER];
+};
+
+// in: fields of n*n*(n/2+1) complex (row pitch im.pitch); out: fields of n^3 reals = the
+// unnormalised inverse transform along z of each row (imaginary parts of the kz = 0 and n/2
+// entries ignored). Optional epilogue: out += add.
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict__ in, FieldMap im,
                                                        float* __restrict__ out, FieldMap om,
-                                                       const float* __restrict__ add) {
+                                                       const float* __restrict__ add,
+                                                       int tiles_per_field, int ntiles) {
   using T = ZTile<N>;
   constexpr int H = T::H, ROWS = T::ROWS, PITCH = T::PITCH;
+  using PR = PairRegs<H, ROWS>;
+  constexpr int Q = PR::Q;
   __shared__ float2 lds[ROWS * PITCH];
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
-  const int field = blockIdx.y;
-  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
-  const float2* src = in + im.off(field) + row0 * im.pitch;
-  __syncthreads();
-  // inverse split: Z[k] = E + i O, E = X[k] + conj X[H-k], O = (X[k] - conj X[H-k]) conj(W^k)
-  constexpr int Q = H / 2 + 1;
-  for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-    const int r = e / Q, k = e % Q;
-    const float2* x = src + (size_t)r * im.pitch;
-    float2* z = lds + r * PITCH;
-    if (k == 0) {
-      const float a = x[0].x, b = x[H].x;
-      z[0] = make_float2(a + b, a - b);
-    } else {
-      const float2 xk = x[k], xm = x[H - k];
-      {
-        float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
-        float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
-        float2 O = cmul(D, cconj(tw[k]));
-        z[zk(k)] = make_float2(E.x - O.y, E.y + O.x);  // E + i O
-      }
-      if (k != H - k) {
-        float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
-        float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
-        float2 O = cmul(D, cconj(tw[H - k]));
-        z[zk(H - k)] = make_float2(E.x - O.y, E.y + O.x);
+  auto load = [&](int t, PR& r) {
+    const int field = t / tiles_per_field;
+    const size_t row0 = (size_t)(t % tiles_per_field) * ROWS;
+    const float2* src = in + im.off(field) + row0 * im.pitch;
+#pragma unroll
+    for (int m = 0; m < PR::PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if (e < ROWS * Q) {
+        const int rr = e / Q, k = e % Q;
+        const float2* x = src + (size_t)rr * im.pitch;
+        r.a[m] = x[k];
+        r.b[m] = x[H - k];
       }
     }
-  }
-  __syncthreads();
-  fft_lds<H, ROWS, 1, PITCH, 2, +1, NT, true>(lds, tw);
-  float2* dst = reinterpret_cast<float2*>(out + om.off(field)) + row0 * H;
-  const float2* ad = add ? reinterpret_cast<const float2*>(add + om.off(field)) + row0 * H : nullptr;
-  for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-    float2 v = lds[(e / H) * PITCH + zk(e % H)];
-    if (ad) {
-      float2 w = ad[e];
-      v.x += w.x;
-      v.y += w.y;
+  };
+  int tau = xcd_block(blockIdx.x, gridDim.x);
+  PR pre;
+  load(tau, pre);
+  __syncthreads();  // twiddles
+  for (;;) {
+#pragma unroll
+    for (int m = 0; m < PR::PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if (e < ROWS * Q) inv_split<H>(lds + (e / Q) * PITCH, e % Q, pre.a[m], pre.b[m], tw);
     }
-    dst[e] = v;
+    __syncthreads();
+    const int next = tau + gridDim.x;
+    if (next < ntiles) load(next, pre);
+    fft_lds<H, ROWS, 1, PITCH, 2, +1, NT, true>(lds, tw);
+    const int field = tau / tiles_per_field;
+    const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
+    float2* dst = reinterpret_cast<float2*>(out + om.off(field)) + row0 * H;
+    const float2* ad = add ? reinterpret_cast<const float2*>(add + om.off(field)) + row0 * H : nullptr;
+    for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+      float2 v = lds[(e / H) * PITCH + zk(e % H)];
+      if (ad) {
+        const float2 w = ad[e];
+        v.x += w.x;
+        v.y += w.y;
+      }
+      dst[e] = v;
+    }
+    if (next >= ntiles) break;
+    __syncthreads();
+    tau = next;
   }
 }
 
@@ -302,49 +367,57 @@ struct ZTile3 {
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict__ in, FieldMap im,
                                                         float4* __restrict__ out,
-                                                        size_t out_item_stride) {
+                                                        size_t out_item_stride,
+                                                        int tiles_per_item, int ntiles) {
   using T = ZTile<N>;
   constexpr int H = T::H, PITCH = T::PITCH, R = ZTile3<N>::R;
+  using PR = PairRegs<H, 3 * R>;
+  constexpr int Q = PR::Q;
   __shared__ float2 lds[3 * R * PITCH];
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
-  const int item = blockIdx.y;
-  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * R;
-  __syncthreads();
-  constexpr int Q = H / 2 + 1;
-  for (int e = threadIdx.x; e < 3 * R * Q; e += NT) {
-    const int line = e / Q, k = e % Q;  // line = component * R + row
-    const int f = line / R, r = line % R;
-    const float2* x = in + im.off(item * 3 + f) + (row0 + r) * im.pitch;
-    float2* z = lds + line * PITCH;
-    if (k == 0) {
-      const float a = x[0].x, b = x[H].x;
-      z[0] = make_float2(a + b, a - b);
-    } else {
-      const float2 xk = x[k], xm = x[H - k];
-      {
-        float2 E = make_float2(xk.x + xm.x, xk.y - xm.y);
-        float2 D = make_float2(xk.x - xm.x, xk.y + xm.y);
-        float2 O = cmul(D, cconj(tw[k]));
-        z[zk(k)] = make_float2(E.x - O.y, E.y + O.x);
-      }
-      if (k != H - k) {
-        float2 E = make_float2(xm.x + xk.x, xm.y - xk.y);
-        float2 D = make_float2(xm.x - xk.x, xm.y + xk.y);
-        float2 O = cmul(D, cconj(tw[H - k]));
-        z[zk(H - k)] = make_float2(E.x - O.y, E.y + O.x);
+  auto load = [&](int t, PR& r) {
+    const int item = t / tiles_per_item;
+    const size_t row0 = (size_t)(t % tiles_per_item) * R;
+#pragma unroll
+    for (int m = 0; m < PR::PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if (e < 3 * R * Q) {
+        const int line = e / Q, k = e % Q;  // line = component * R + row
+        const int f = line / R, rr = line % R;
+        const float2* x = in + im.off(item * 3 + f) + (row0 + rr) * im.pitch;
+        r.a[m] = x[k];
+        r.b[m] = x[H - k];
       }
     }
-  }
-  __syncthreads();
-  fft_lds<H, 3 * R, 1, PITCH, 2, +1, NT, true>(lds, tw);
-  float4* dst = out + item * out_item_stride + row0 * N;
-  const float* l = reinterpret_cast<const float*>(lds);
-  for (int e = threadIdx.x; e < R * N; e += NT) {
-    const int r = e / N, zz = e % N;
-    const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
-    dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
-                         l[(2 * R + r) * 2 * PITCH + q], 0.f);
+  };
+  int tau = xcd_block(blockIdx.x, gridDim.x);
+  PR pre;
+  load(tau, pre);
+  __syncthreads();  // twiddles
+  for (;;) {
+#pragma unroll
+    for (int m = 0; m < PR::PER; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if (e < 3 * R * Q) inv_split<H>(lds + (e / Q) * PITCH, e % Q, pre.a[m], pre.b[m], tw);
+    }
+    __syncthreads();
+    const int next = tau + gridDim.x;
+    if (next < ntiles) load(next, pre);
+    fft_lds<H, 3 * R, 1, PITCH, 2, +1, NT, true>(lds, tw);
+    const int item = tau / tiles_per_item;
+    const size_t row0 = (size_t)(tau % tiles_per_item) * R;
+    float4* dst = out + item * out_item_stride + row0 * N;
+    const float* l = reinterpret_cast<const float*>(lds);
+    for (int e = threadIdx.x; e < R * N; e += NT) {
+      const int r = e / N, zz = e % N;
+      const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
+      dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
+                           l[(2 * R + r) * 2 * PITCH + q], 0.f);
+    }
+    if (next >= ntiles) break;
+    __syncthreads();
+    tau = next;
   }
 }
 
@@ -603,27 +676,31 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   }
 }
 
+// Workgroups launched for the z-pass tile loops.
+constexpr int kZBlocks = 2048;
+
 template <int N>
 void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, float a2,
           const double* sc, float2* out, FieldMap om, hipStream_t s) {
-  using T = ZTile<N>;
-  dim3 grid((N * N) / T::ROWS, fields);
-  zpass_r2c_kernel<N><<<grid, NT, 0, s>>>(in, im, in2, a1, a2, sc, out, om);
+  const int per = (N * N) / ZTile<N>::ROWS, ntiles = per * fields;
+  zpass_r2c_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+      in, im, in2, a1, a2, sc, out, om, per, ntiles);
 }
 
 template <int N>
 void zc2r3(int items, const float2* in, FieldMap im, float4* out, size_t out_item_stride,
            hipStream_t s) {
-  dim3 grid((N * N) / ZTile3<N>::R, items);
-  zpass_c2r3_kernel<N><<<grid, NT, 0, s>>>(in, im, out, out_item_stride);
+  const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
+  zpass_c2r3_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+      in, im, out, out_item_stride, per, ntiles);
 }
 
 template <int N>
 void zc2r(int fields, const float2* in, FieldMap im, float* out, FieldMap om, const float* add,
           hipStream_t s) {
-  using T = ZTile<N>;
-  dim3 grid((N * N) / T::ROWS, fields);
-  zpass_c2r_kernel<N><<<grid, NT, 0, s>>>(in, im, out, om, add);
+  const int per = (N * N) / ZTile<N>::ROWS, ntiles = per * fields;
+  zpass_c2r_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+      in, im, out, om, add, per, ntiles);
 }
 
 int log2i(int n) {
