@@ -249,37 +249,49 @@ __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__
     const int next = tau + gridDim.x;
     if (next < ntiles) load(next, pre);
     fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
-    // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2
-    const int field = tau / tiles_per_field;
-    const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
-    float2* dst = out + om.off(field) + row0 * om.pitch;
+    // split, in place (each pair (k, H-k) belongs to one thread):
+    // X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2; X[H] from Z[0]
     constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
       const int r = e / Q, k = e % Q;
-      const float2* z = lds + r * PITCH;
-      float2* d = dst + (size_t)r * om.pitch;
+      float2* z = lds + r * PITCH;
       if (k == 0) {
-        float2 z0 = z[0];
-        d[0] = make_float2(z0.x + z0.y, 0.f);
-        d[H] = make_float2(z0.x - z0.y, 0.f);
+        const float2 z0 = z[0];
+        z[0] = make_float2(z0.x + z0.y, 0.f);
+        z[zk(H)] = make_float2(z0.x - z0.y, 0.f);
       } else {
         const float2 zv = z[zk(k)], zm = z[zk(H - k)];
         {
           float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
           float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
           float2 t = cmul(tw[k], df);  // W^k * diff
-          d[k] = make_float2(sm.x + t.y, sm.y - t.x);  // sm - i t
+          z[zk(k)] = make_float2(sm.x + t.y, sm.y - t.x);  // sm - i t
         }
         if (k != H - k) {
           float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
           float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
           float2 t = cmul(tw[H - k], df);
-          d[H - k] = make_float2(sm.x + t.y, sm.y - t.x);
+          z[zk(H - k)] = make_float2(sm.x + t.y, sm.y - t.x);
         }
       }
     }
+    __syncthreads();
+    // rows out: a fixed, unrolled sequence of stores per thread (the wait for the prefetched
+    // loads at the top of the next tile then need not drain them)
+    const int field = tau / tiles_per_field;
+    const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
+    float2* dst = out + om.off(field) + row0 * om.pitch;
+    constexpr int PO = (ROWS * (H + 1) + NT - 1) / NT;
+#pragma unroll
+    for (int m = 0; m < PO; ++m) {
+      const int e = threadIdx.x + m * NT;
+      if (e < ROWS * (H + 1)) {
+        const int r = e / (H + 1), k = e % (H + 1);
+        dst[(size_t)r * om.pitch + k] = lds[r * PITCH + zk(k)];
+      }
+    }
     if (next >= ntiles) break;
-    __syncthreads();  // the split has read the tile
+    __syncthreads();  // the rows have been read
     tau = next;
   }
 }
@@ -341,7 +353,10 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
     const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
     float2* dst = reinterpret_cast<float2*>(out + om.off(field)) + row0 * H;
     const float2* ad = add ? reinterpret_cast<const float2*>(add + om.off(field)) + row0 * H : nullptr;
-    for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+    static_assert((ROWS * H) % NT == 0, "whole rows per thread sweep");
+#pragma unroll
+    for (int m = 0; m < ROWS * H / NT; ++m) {
+      const int e = threadIdx.x + m * NT;
       float2 v = lds[(e / H) * PITCH + zk(e % H)];
       if (ad) {
         const float2 w = ad[e];
@@ -409,7 +424,10 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
     const size_t row0 = (size_t)(tau % tiles_per_item) * R;
     float4* dst = out + item * out_item_stride + row0 * N;
     const float* l = reinterpret_cast<const float*>(lds);
-    for (int e = threadIdx.x; e < R * N; e += NT) {
+    static_assert((R * N) % NT == 0, "whole rows per thread sweep");
+#pragma unroll
+    for (int m = 0; m < R * N / NT; ++m) {
+      const int e = threadIdx.x + m * NT;
       const int r = e / N, zz = e % N;
       const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
       dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
@@ -436,7 +454,10 @@ __device__ __forceinline__ void load_tile(float2* lds, const float2* __restrict_
 template <int N, int PC, int NTH>
 __device__ __forceinline__ void store_tile(const float2* lds, float2* __restrict__ base,
                                            size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PC; e += NTH) {
+  static_assert((N * PC) % NTH == 0, "whole tile per thread sweep");
+#pragma unroll
+  for (int m = 0; m < N * PC / NTH; ++m) {
+    const int e = threadIdx.x + m * NTH;
     const int n = e / PC, l = e % PC;
     if (l < ncols) base[(size_t)n * stride + l] = lds[e];
   }
