@@ -697,14 +697,12 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   }
 }
 
-// Workgroups launched for the z-pass tile loops.
-constexpr int kZBlocks = 2048;
-
 template <int N>
 void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, float a2,
           const double* sc, float2* out, FieldMap om, hipStream_t s) {
   const int per = (N * N) / ZTile<N>::ROWS, ntiles = per * fields;
-  zpass_r2c_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+  const int res = resident_grid<zpass_r2c_kernel<N>, NT>();
+  zpass_r2c_kernel<N><<<ntiles < res ? ntiles : res, NT, 0, s>>>(
       in, im, in2, a1, a2, sc, out, om, per, ntiles);
 }
 
@@ -712,7 +710,8 @@ template <int N>
 void zc2r3(int items, const float2* in, FieldMap im, float4* out, size_t out_item_stride,
            hipStream_t s) {
   const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
-  zpass_c2r3_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+  const int res = resident_grid<zpass_c2r3_kernel<N>, NT>();
+  zpass_c2r3_kernel<N><<<ntiles < res ? ntiles : res, NT, 0, s>>>(
       in, im, out, out_item_stride, per, ntiles);
 }
 
@@ -720,7 +719,8 @@ template <int N>
 void zc2r(int fields, const float2* in, FieldMap im, float* out, FieldMap om, const float* add,
           hipStream_t s) {
   const int per = (N * N) / ZTile<N>::ROWS, ntiles = per * fields;
-  zpass_c2r_kernel<N><<<ntiles < kZBlocks ? ntiles : kZBlocks, NT, 0, s>>>(
+  const int res = resident_grid<zpass_c2r_kernel<N>, NT>();
+  zpass_c2r_kernel<N><<<ntiles < res ? ntiles : res, NT, 0, s>>>(
       in, im, out, om, add, per, ntiles);
 }
 
@@ -1053,39 +1053,49 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   }
 }
 
-// Workgroups launched for the tile loops: enough to fill the chip several times over.
-constexpr int kTileBlocks = 2048;
+// Tile loops launch the resident number of workgroups (at most the number of tiles).
+template <auto Kernel, int NTH>
+int tile_grid(int ntiles) {
+  const int res = resident_grid<Kernel, NTH>();
+  return ntiles < res ? ntiles : res;
+}
 
 template <int N, int PC, int NTH>
 void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * fields;
-  const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
   if constexpr (reg_ok<N, PC, NTH>()) {
     if (!lds) {
-      if (inv)
-        ypass_reg_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-      else
-        ypass_reg_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+      if (inv) {
+        constexpr auto k = ypass_reg_kernel<N, +1, PC, NTH>;
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+      } else {
+        constexpr auto k = ypass_reg_kernel<N, -1, PC, NTH>;
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+      }
       return;
     }
   }
-  if (inv)
-    ypass_kernel<N, +1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
-  else
-    ypass_kernel<N, -1, PC, NTH><<<grid, NTH, 0, s>>>(d, m, ntiles);
+  if (inv) {
+    constexpr auto k = ypass_kernel<N, +1, PC, NTH>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+  } else {
+    constexpr auto k = ypass_kernel<N, -1, PC, NTH>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+  }
 }
 
 template <int N, int OP, int PC, int NTH>
 void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
   const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * a.batch;
-  const int grid = ntiles < kTileBlocks ? ntiles : kTileBlocks;
   if constexpr (reg_ok<N, PC, NTH>()) {
     if (!lds) {
-      xpass_reg_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+      constexpr auto k = xpass_reg_kernel<N, OP, PC, NTH>;
+      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
       return;
     }
   }
-  xpass_kernel<N, OP, PC, NTH><<<grid, NTH, 0, s>>>(a, ntiles);
+  constexpr auto k = xpass_kernel<N, OP, PC, NTH>;
+  k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
 }
 
 // Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS

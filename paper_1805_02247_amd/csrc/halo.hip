@@ -125,6 +125,27 @@ __global__ __launch_bounds__(TB) void mlp_bwd_kernel(const float* __restrict__ d
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
+// Compact block of the FP32 weights the matrix-core kernels need (W2 runs in BF16 from its
+// own copy): W1[H][3], b1[H], b2[H], W3[H], b3.
+template <int H>
+struct SOff {
+  static constexpr int W1 = 0, B1 = 3 * H, B2 = 4 * H, W3 = 5 * H, B3 = 6 * H, SIZE = 6 * H + 1;
+};
+
+template <int H>
+__device__ __forceinline__ void load_small_weights(float* sw, const float* __restrict__ w) {
+  using O = WOff<H>;
+  for (int i = threadIdx.x; i < SOff<H>::SIZE; i += TB) {
+    float v;
+    if (i < 4 * H) v = w[i];  // W1 and b1 sit at the same offsets in both blocks
+    else if (i < 5 * H) v = w[O::B2 + (i - 4 * H)];
+    else if (i < 6 * H) v = w[O::W3 + (i - 5 * H)];
+    else v = w[O::B3];
+    sw[i] = v;
+  }
+  __syncthreads();
+}
+
 // BF16 copies of W2 (row-major [n][k]) and W2^T, placed after the FP32 block.
 template <int H>
 struct WBf {
@@ -160,16 +181,19 @@ struct MfmaShape {
   static_assert(H % 32 == 0, "H multiple of 32");
 };
 
-// h1 fragments (A layout) for the 4 row blocks of this wave; returns false past the end.
-template <int H>
+// Row blocks of 16 voxels a wavefront processes at a time (4 VGPRs of accumulator per 16x16
+// output block, so fewer blocks keep more waves resident).
+constexpr int MFMA_MB = 2;
+
+// h1 fragments (A layout) for the MB row blocks of this wave (zero past the end).
+template <int H, class O, int MB>
 __device__ __forceinline__ void h1_fragments(const float* sw, const float* __restrict__ d0,
                                              const float* __restrict__ d1,
                                              const float* __restrict__ d2, size_t v0, size_t n,
-                                             bf16x8_t (&a)[4][H / 32]) {
-  using O = WOff<H>;
+                                             bf16x8_t (&a)[MB][H / 32]) {
   const int l = threadIdx.x & 63;
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+  for (int mb = 0; mb < MB; ++mb) {
     const size_t v = v0 + mb * 16 + (l & 15);
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
     if (v < n) {
@@ -202,12 +226,12 @@ __device__ __forceinline__ void load_b(const __bf16* __restrict__ m, bf16x8_t (&
                                                      8 * (l >> 4));
 }
 
-template <int H>
-__device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[4][H / 32],
+template <int H, int MB>
+__device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[MB][H / 32],
                                            const bf16x8_t (&b)[H / 32][H / 16],
-                                           floatx4_t (&c)[4][H / 16]) {
+                                           floatx4_t (&c)[MB][H / 16]) {
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < H / 16; ++nb) {
       floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
@@ -219,10 +243,9 @@ __device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[4][H / 32],
 }
 
 // y for the 4 rows (4 (l/16) + i) of row block mb, on every lane of the 16-lane group.
-template <int H>
-__device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[4][H / 16], int mb,
+template <int H, class O, int MB>
+__device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[MB][H / 16], int mb,
                                        float (&y)[4]) {
-  using O = WOff<H>;
   const int l = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -236,32 +259,39 @@ __device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[4][
   }
 }
 
+// Persistent: each wavefront walks 64-voxel groups (wave, wave + all waves, ...) with the
+// small FP32 weights in LDS and the W2 fragments in registers, loaded once.
 template <int H>
 __global__ __launch_bounds__(TB) void mlp_fwd_mfma_kernel(const float* __restrict__ d0,
                                                           const float* __restrict__ d1,
                                                           const float* __restrict__ d2, size_t n,
                                                           const float* __restrict__ w,
                                                           float* __restrict__ mass) {
-  using O = WOff<H>;
-  __shared__ float sw[O::SIZE];
-  load_weights<H>(sw, w);
+  using S = SOff<H>;
+  __shared__ float sw[S::SIZE];
+  load_small_weights<H>(sw, w);
   const int l = threadIdx.x & 63;
-  const size_t v0 = ((size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6)) * 64;
-  bf16x8_t a[4][H / 32];
   bf16x8_t b[H / 32][H / 16];
-  floatx4_t c[4][H / 16];
-  h1_fragments<H>(sw, d0, d1, d2, v0, n, a);
   load_b<H>(reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(w) + WBf<H>::W2), b);
-  mfma_layer<H>(a, b, c);
+  constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
+  const size_t groups = (n + GV - 1) / GV;
+  const size_t nwaves = (size_t)gridDim.x * (TB / 64);
+  for (size_t g = (size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); g < groups; g += nwaves) {
+    const size_t v0 = g * GV;
+    bf16x8_t a[MB][H / 32];
+    floatx4_t c[MB][H / 16];
+    h1_fragments<H, S, MB>(sw, d0, d1, d2, v0, n, a);
+    mfma_layer<H, MB>(a, b, c);
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    float y[4];
-    layer3<H>(sw, c, mb, y);
-    const int i = l & 15;
-    if (i < 4) {
-      const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
-      const float yi = i == 0 ? y[0] : i == 1 ? y[1] : i == 2 ? y[2] : y[3];
-      if (v < n) mass[v] = softplus_f(yi);
+    for (int mb = 0; mb < MB; ++mb) {
+      float y[4];
+      layer3<H, S, MB>(sw, c, mb, y);
+      const int i = l & 15;
+      if (i < 4) {
+        const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
+        const float yi = i == 0 ? y[0] : i == 1 ? y[1] : i == 2 ? y[2] : y[3];
+        if (v < n) mass[v] = softplus_f(yi);
+      }
     }
   }
 }
@@ -275,86 +305,99 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mfma_kernel(const float* __restric
                                                           float* __restrict__ g0,
                                                           float* __restrict__ g12,
                                                           float* __restrict__ g2) {
-  using O = WOff<H>;
-  __shared__ float sw[O::SIZE];
-  __shared__ __bf16 tile[TB / 64][64 * H];
-  load_weights<H>(sw, w);
+  using S = SOff<H>;
+  __shared__ float sw[S::SIZE];
+  __shared__ __bf16 wbf[2 * H * H];  // W2 and W2^T (BF16)
+  constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
+  __shared__ __bf16 tile[TB / 64][GV * H];
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(w) + WBf<H>::W2);
+    uint4* dst = reinterpret_cast<uint4*>(wbf);
+    for (int i = threadIdx.x; i < 2 * H * H * 2 / 16; i += TB) dst[i] = src[i];
+  }
+  load_small_weights<H>(sw, w);  // ends with a barrier
   const int l = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const size_t v0 = ((size_t)blockIdx.x * (TB / 64) + wv) * 64;
-  const char* wb = reinterpret_cast<const char*>(w);
-  floatx4_t c[4][H / 16];
-  {
-    bf16x8_t a[4][H / 32];
-    bf16x8_t b[H / 32][H / 16];
-    h1_fragments<H>(sw, d0, d1, d2, v0, n, a);
-    load_b<H>(reinterpret_cast<const __bf16*>(wb + WBf<H>::W2), b);
-    mfma_layer<H>(a, b, c);
-  }
   __bf16* T = tile[wv];
-  // a2bar = ybar W3 [a2 > 0], stored (BF16) as a 64 x H tile for the transposed read
+  const size_t groups = (n + GV - 1) / GV;
+  const size_t nwaves = (size_t)gridDim.x * (TB / 64);
+  for (size_t g = (size_t)blockIdx.x * (TB / 64) + wv; g < groups; g += nwaves) {
+    const size_t v0 = g * GV;
+    floatx4_t c[MB][H / 16];
+    {
+      bf16x8_t a[MB][H / 32];
+      bf16x8_t b[H / 32][H / 16];
+      h1_fragments<H, S, MB>(sw, d0, d1, d2, v0, n, a);
+      load_b<H>(wbf, b);
+      mfma_layer<H, MB>(a, b, c);
+    }
+    // a2bar = ybar W3 [a2 > 0], stored (BF16) as a GV x H tile for the transposed read
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    float y[4];
-    layer3<H>(sw, c, mb, y);
+    for (int mb = 0; mb < MB; ++mb) {
+      float y[4];
+      layer3<H, S, MB>(sw, c, mb, y);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = mb * 16 + 4 * (l >> 4) + i;
-      const size_t v = v0 + r;
-      const float yb = v < n ? mbar[v] * sigmoid_f(y[i]) : 0.f;
+      for (int i = 0; i < 4; ++i) {
+        const int r = mb * 16 + 4 * (l >> 4) + i;
+        const size_t v = v0 + r;
+        const float yb = v < n ? mbar[v] * sigmoid_f(y[i]) : 0.f;
 #pragma unroll
-      for (int nb = 0; nb < H / 16; ++nb) {
-        const int nn = nb * 16 + (l & 15);
-        const float a2 = c[mb][nb][i] + sw[O::B2 + nn];
-        T[r * H + nn] = (__bf16)(a2 > 0.f ? yb * sw[O::W3 + nn] : 0.f);
+        for (int nb = 0; nb < H / 16; ++nb) {
+          const int nn = nb * 16 + (l & 15);
+          const float a2 = c[mb][nb][i] + sw[S::B2 + nn];
+          T[r * H + nn] = (__bf16)(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
+        }
       }
     }
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_s_waitcnt(0xc07f);
-  // h1bar = a2bar W2 on the matrix cores
-  {
-    bf16x8_t a[4][H / 32];
-    bf16x8_t b[H / 32][H / 16];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    // h1bar = a2bar W2 on the matrix cores
+    {
+      bf16x8_t a[MB][H / 32];
+      bf16x8_t b[H / 32][H / 16];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int kb = 0; kb < H / 32; ++kb)
-        a[mb][kb] = *reinterpret_cast<const bf16x8_t*>(T + (mb * 16 + (l & 15)) * H + kb * 32 +
-                                                       8 * (l >> 4));
-    load_b<H>(reinterpret_cast<const __bf16*>(wb + WBf<H>::W2T), b);
-    mfma_layer<H>(a, b, c);
-  }
-  // a1bar = h1bar [a1 > 0]; fbar = W1^T a1bar (rows of the C layout)
+        for (int kb = 0; kb < H / 32; ++kb)
+          a[mb][kb] = *reinterpret_cast<const bf16x8_t*>(T + (mb * 16 + (l & 15)) * H + kb * 32 +
+                                                         8 * (l >> 4));
+      load_b<H>(wbf + H * H, b);
+      mfma_layer<H, MB>(a, b, c);
+    }
+    // the tile is rewritten by the next group: its reads above must have completed
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // a1bar = h1bar [a1 > 0]; fbar = W1^T a1bar (rows of the C layout)
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
-      float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-      if (v < n) {
-        f0 = d0[v];
-        f1 = d1[v];
-        f2 = d1[v] - d2[v];
-      }
-      float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+      for (int i = 0; i < 4; ++i) {
+        const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+        if (v < n) {
+          f0 = d0[v];
+          f1 = d1[v];
+          f2 = d1[v] - d2[v];
+        }
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
 #pragma unroll
-      for (int nb = 0; nb < H / 16; ++nb) {
-        const int k = nb * 16 + (l & 15);
-        const float a1 = sw[O::W1 + 3 * k] * f0 + sw[O::W1 + 3 * k + 1] * f1 +
-                         sw[O::W1 + 3 * k + 2] * f2 + sw[O::B1 + k];
-        const float hb = a1 > 0.f ? c[mb][nb][i] : 0.f;
-        p0 += sw[O::W1 + 3 * k] * hb;
-        p1 += sw[O::W1 + 3 * k + 1] * hb;
-        p2 += sw[O::W1 + 3 * k + 2] * hb;
-      }
-      p0 = group16_sum(p0);
-      p1 = group16_sum(p1);
-      p2 = group16_sum(p2);
-      if ((l & 15) == i && v < n) {
-        g0[v] = p0;
-        g12[v] = p1 + p2;
-        g2[v] = p2;
+        for (int nb = 0; nb < H / 16; ++nb) {
+          const int k = nb * 16 + (l & 15);
+          const float a1 = sw[S::W1 + 3 * k] * f0 + sw[S::W1 + 3 * k + 1] * f1 +
+                           sw[S::W1 + 3 * k + 2] * f2 + sw[S::B1 + k];
+          const float hb = a1 > 0.f ? c[mb][nb][i] : 0.f;
+          p0 += sw[S::W1 + 3 * k] * hb;
+          p1 += sw[S::W1 + 3 * k + 1] * hb;
+          p2 += sw[S::W1 + 3 * k + 2] * hb;
+        }
+        p0 = group16_sum(p0);
+        p1 = group16_sum(p1);
+        p2 = group16_sum(p2);
+        if ((l & 15) == i && v < n) {
+          g0[v] = p0;
+          g12[v] = p1 + p2;
+          g2[v] = p2;
+        }
       }
     }
   }
@@ -528,18 +571,27 @@ int launch_mlp_prepare_bf16(int H, float* w, hipStream_t s) {
   }
 }
 
+// Workgroups of the persistent matrix-core kernels: the resident number, fewer when the
+// mesh is small.
+template <auto Kernel>
+static unsigned mfma_blocks(size_t n) {
+  const size_t need = (n + TB - 1) / TB;
+  const size_t res = (size_t)resident_grid<Kernel, TB>();
+  return (unsigned)(need < res ? need : res);
+}
+
 template <int H>
 static void mlp_fwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
                            const float* w, float* mass, hipStream_t s) {
-  const unsigned blocks = (unsigned)((n + TB - 1) / TB);
-  mlp_fwd_mfma_kernel<H><<<blocks, TB, 0, s>>>(d0, d1, d2, n, w, mass);
+  mlp_fwd_mfma_kernel<H><<<mfma_blocks<mlp_fwd_mfma_kernel<H>>(n), TB, 0, s>>>(d0, d1, d2, n, w,
+                                                                                mass);
 }
 template <int H>
 static void mlp_bwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
                            const float* w, const float* mbar, float* g0, float* g12, float* g2,
                            hipStream_t s) {
-  const unsigned blocks = (unsigned)((n + TB - 1) / TB);
-  mlp_bwd_mfma_kernel<H><<<blocks, TB, 0, s>>>(d0, d1, d2, n, w, mbar, g0, g12, g2);
+  mlp_bwd_mfma_kernel<H><<<mfma_blocks<mlp_bwd_mfma_kernel<H>>(n), TB, 0, s>>>(d0, d1, d2, n, w,
+                                                                                mbar, g0, g12, g2);
 }
 
 int launch_mlp_fwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,

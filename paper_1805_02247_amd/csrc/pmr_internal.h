@@ -47,6 +47,28 @@ __device__ __forceinline__ double wrap_box(double x, double box) {
 // Workgroups of a 1-D grid are dispatched round-robin over the 8 XCDs of the chip, each
 // with its own L2. Remapping the block index gives every XCD one contiguous range of
 // logical blocks, so spatially neighbouring work shares an L2. Bijective for any nb.
+// Workgroups of `kernel` (launched with `threads` threads and no dynamic LDS) that the
+// current device holds at once: occupancy per CU (registers, LDS, waves) times the CUs.
+// Persistent tile loops launch this many, so that no workgroup waits for a second round.
+// Computed once per kernel (and block size); the library runs on one device model per process.
+inline int resident_grid_of(const void* kernel, int threads) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return per_cu * cus;
+}
+
+template <auto Kernel, int Threads>
+inline int resident_grid() {
+  static const int grid = resident_grid_of(reinterpret_cast<const void*>(Kernel), Threads);
+  return grid;
+}
+
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   constexpr int X = 8;
   const int q = nb / X, r = nb % X;
