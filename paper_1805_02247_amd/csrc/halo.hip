@@ -115,18 +115,42 @@ __global__ __launch_bounds__(TB) void mlp_bwd_kernel(const float* __restrict__ d
   g2[v] = fb2;
 }
 
-// ---------------------------------------------------------------- BF16 matrix-core network
-// Mixed precision: the H x H layer runs on v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32
-// accumulation); the 3 -> H and H -> 1 layers, biases, activations and the softplus stay
-// FP32 on the vector units. One wavefront owns 64 voxels (four 16-row blocks).
-// Operand layouts of the 16x16x32 instruction (lane l, j = 0..7, i = 0..3):
-//   A[m][k]: m = l % 16, k = 8 (l / 16) + j      B[k][n]: n = l % 16, k = 8 (l / 16) + j
+// ---------------------------------------------------------------- matrix-core network
+// The H x H layer runs on the matrix cores, in one of two precisions:
+//   BF16: v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32 accumulation) - the mixed path;
+//   FP32: v_mfma_f32_16x16x4_f32 (FP32 inputs and accumulation) - the FP32 path.
+// The 3 -> H and H -> 1 layers, biases, activations and the softplus stay FP32 on the vector
+// units. Operand layouts (lane l, i = 0..3), with KS the instruction's k extent and
+// J = KS / 4 consecutive k per lane:
+//   A[m][k]: m = l % 16, k = J (l / 16) + j      B[k][n]: n = l % 16, k = J (l / 16) + j
 //   C[m][n]: n = l % 16, m = 4 (l / 16) + i
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-// Compact block of the FP32 weights the matrix-core kernels need (W2 runs in BF16 from its
-// own copy): W1[H][3], b1[H], b2[H], W3[H], b3.
+struct MxBF16 {
+  static constexpr int KS = 32, J = 8;
+  typedef bf16x8_t frag;
+  typedef __bf16 elem;
+  __device__ static floatx4_t mma(frag a, frag b, floatx4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static void set(frag& f, int j, float v) { f[j] = (__bf16)v; }
+  __device__ static elem cvt(float v) { return (__bf16)v; }
+};
+
+struct MxF32 {
+  static constexpr int KS = 4, J = 1;
+  typedef float frag;
+  typedef float elem;
+  __device__ static floatx4_t mma(frag a, frag b, floatx4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static void set(frag& f, int, float v) { f = v; }
+  __device__ static elem cvt(float v) { return v; }
+};
+
+// Compact block of the FP32 weights the matrix-core kernels keep in LDS: W1[H][3], b1[H],
+// b2[H], W3[H], b3.
 template <int H>
 struct SOff {
   static constexpr int W1 = 0, B1 = 3 * H, B2 = 4 * H, W3 = 5 * H, B3 = 6 * H, SIZE = 6 * H + 1;
@@ -175,22 +199,17 @@ __device__ __forceinline__ float group16_sum(float v) {
   return v;
 }
 
-template <int H>
-struct MfmaShape {
-  static constexpr int MB = 4, KB = H / 32, NB = H / 16;
-  static_assert(H % 32 == 0, "H multiple of 32");
-};
-
 // Row blocks of 16 voxels a wavefront processes at a time (4 VGPRs of accumulator per 16x16
 // output block, so fewer blocks keep more waves resident).
 constexpr int MFMA_MB = 2;
 
 // h1 fragments (A layout) for the MB row blocks of this wave (zero past the end).
-template <int H, class O, int MB>
+template <class P, int H, int MB>
 __device__ __forceinline__ void h1_fragments(const float* sw, const float* __restrict__ d0,
                                              const float* __restrict__ d1,
                                              const float* __restrict__ d2, size_t v0, size_t n,
-                                             bf16x8_t (&a)[MB][H / 32]) {
+                                             typename P::frag (&a)[MB][H / P::KS]) {
+  using S = SOff<H>;
   const int l = threadIdx.x & 63;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
@@ -202,33 +221,35 @@ __device__ __forceinline__ void h1_fragments(const float* sw, const float* __res
       f2 = d1[v] - d2[v];
     }
 #pragma unroll
-    for (int kb = 0; kb < H / 32; ++kb) {
+    for (int kb = 0; kb < H / P::KS; ++kb) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = kb * 32 + 8 * (l >> 4) + j;
-        const float h = fmaxf(sw[O::W1 + 3 * k] * f0 + sw[O::W1 + 3 * k + 1] * f1 +
-                                  sw[O::W1 + 3 * k + 2] * f2 + sw[O::B1 + k],
+      for (int j = 0; j < P::J; ++j) {
+        const int k = kb * P::KS + P::J * (l >> 4) + j;
+        const float h = fmaxf(sw[S::W1 + 3 * k] * f0 + sw[S::W1 + 3 * k + 1] * f1 +
+                                  sw[S::W1 + 3 * k + 2] * f2 + sw[S::B1 + k],
                               0.f);
-        a[mb][kb][j] = (__bf16)h;
+        P::set(a[mb][kb], j, h);
       }
     }
   }
 }
 
-template <int H>
-__device__ __forceinline__ void load_b(const __bf16* __restrict__ m, bf16x8_t (&b)[H / 32][H / 16]) {
+// B fragments of a row-major [n][k] matrix m (B[k][n] = m[n][k]), element type of P.
+template <class P, int H>
+__device__ __forceinline__ void load_b(const typename P::elem* __restrict__ m,
+                                       typename P::frag (&b)[H / P::KS][H / 16]) {
   const int l = threadIdx.x & 63;
 #pragma unroll
-  for (int kb = 0; kb < H / 32; ++kb)
+  for (int kb = 0; kb < H / P::KS; ++kb)
 #pragma unroll
     for (int nb = 0; nb < H / 16; ++nb)
-      b[kb][nb] = *reinterpret_cast<const bf16x8_t*>(m + (size_t)(nb * 16 + (l & 15)) * H + kb * 32 +
-                                                     8 * (l >> 4));
+      b[kb][nb] = *reinterpret_cast<const typename P::frag*>(
+          m + (size_t)(nb * 16 + (l & 15)) * H + kb * P::KS + P::J * (l >> 4));
 }
 
-template <int H, int MB>
-__device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[MB][H / 32],
-                                           const bf16x8_t (&b)[H / 32][H / 16],
+template <class P, int H, int MB>
+__device__ __forceinline__ void mfma_layer(const typename P::frag (&a)[MB][H / P::KS],
+                                           const typename P::frag (&b)[H / P::KS][H / 16],
                                            floatx4_t (&c)[MB][H / 16]) {
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -236,16 +257,16 @@ __device__ __forceinline__ void mfma_layer(const bf16x8_t (&a)[MB][H / 32],
     for (int nb = 0; nb < H / 16; ++nb) {
       floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kb = 0; kb < H / 32; ++kb)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb][kb], b[kb][nb], acc, 0, 0, 0);
+      for (int kb = 0; kb < H / P::KS; ++kb) acc = P::mma(a[mb][kb], b[kb][nb], acc);
       c[mb][nb] = acc;
     }
 }
 
 // y for the 4 rows (4 (l/16) + i) of row block mb, on every lane of the 16-lane group.
-template <int H, class O, int MB>
+template <int H, int MB>
 __device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[MB][H / 16], int mb,
                                        float (&y)[4]) {
+  using S = SOff<H>;
   const int l = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -253,39 +274,49 @@ __device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[MB]
 #pragma unroll
     for (int nb = 0; nb < H / 16; ++nb) {
       const int nn = nb * 16 + (l & 15);
-      p += sw[O::W3 + nn] * fmaxf(c[mb][nb][i] + sw[O::B2 + nn], 0.f);
+      p += sw[S::W3 + nn] * fmaxf(c[mb][nb][i] + sw[S::B2 + nn], 0.f);
     }
-    y[i] = group16_sum(p) + sw[O::B3];
+    y[i] = group16_sum(p) + sw[S::B3];
   }
 }
 
-// Persistent: each wavefront walks 64-voxel groups (wave, wave + all waves, ...) with the
-// small FP32 weights in LDS and the W2 fragments in registers, loaded once.
-template <int H>
-__global__ __launch_bounds__(TB) void mlp_fwd_mfma_kernel(const float* __restrict__ d0,
-                                                          const float* __restrict__ d1,
-                                                          const float* __restrict__ d2, size_t n,
-                                                          const float* __restrict__ w,
-                                                          float* __restrict__ mass) {
+// W2 (row-major [n][k]) and W2^T in the element type of P: the BF16 copies after the FP32
+// block, or (FP32) the block's own W2 and a transposed copy made in LDS by the caller.
+template <class P, int H>
+__device__ __forceinline__ const typename P::elem* w2_rows(const float* w) {
+  if constexpr (sizeof(typename P::elem) == 2)
+    return reinterpret_cast<const typename P::elem*>(reinterpret_cast<const char*>(w) + WBf<H>::W2);
+  else
+    return reinterpret_cast<const typename P::elem*>(w + WOff<H>::W2);
+}
+
+// Persistent: each wavefront walks groups of 16 MB voxels (wave, wave + all waves, ...) with
+// the small FP32 weights in LDS and the W2 fragments in registers, loaded once.
+template <class P, int H>
+__global__ __launch_bounds__(TB) void mlp_fwd_mx_kernel(const float* __restrict__ d0,
+                                                        const float* __restrict__ d1,
+                                                        const float* __restrict__ d2, size_t n,
+                                                        const float* __restrict__ w,
+                                                        float* __restrict__ mass) {
   using S = SOff<H>;
+  constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
   __shared__ float sw[S::SIZE];
   load_small_weights<H>(sw, w);
   const int l = threadIdx.x & 63;
-  bf16x8_t b[H / 32][H / 16];
-  load_b<H>(reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(w) + WBf<H>::W2), b);
-  constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
+  typename P::frag b[H / P::KS][H / 16];
+  load_b<P, H>(w2_rows<P, H>(w), b);
   const size_t groups = (n + GV - 1) / GV;
   const size_t nwaves = (size_t)gridDim.x * (TB / 64);
   for (size_t g = (size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); g < groups; g += nwaves) {
     const size_t v0 = g * GV;
-    bf16x8_t a[MB][H / 32];
+    typename P::frag a[MB][H / P::KS];
     floatx4_t c[MB][H / 16];
-    h1_fragments<H, S, MB>(sw, d0, d1, d2, v0, n, a);
-    mfma_layer<H, MB>(a, b, c);
+    h1_fragments<P, H, MB>(sw, d0, d1, d2, v0, n, a);
+    mfma_layer<P, H, MB>(a, b, c);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       float y[4];
-      layer3<H, S, MB>(sw, c, mb, y);
+      layer3<H, MB>(sw, c, mb, y);
       const int i = l & 15;
       if (i < 4) {
         const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
@@ -296,46 +327,54 @@ __global__ __launch_bounds__(TB) void mlp_fwd_mfma_kernel(const float* __restric
   }
 }
 
-template <int H>
-__global__ __launch_bounds__(TB) void mlp_bwd_mfma_kernel(const float* __restrict__ d0,
-                                                          const float* __restrict__ d1,
-                                                          const float* __restrict__ d2, size_t n,
-                                                          const float* __restrict__ w,
-                                                          const float* __restrict__ mbar,
-                                                          float* __restrict__ g0,
-                                                          float* __restrict__ g12,
-                                                          float* __restrict__ g2) {
+// Input gradient (weights frozen, forward recomputed), as mlp_bwd_kernel, with both H x H
+// products (W2 h1 and W2^T a2bar) on the matrix cores.
+template <class P, int H>
+__global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict__ d0,
+                                                        const float* __restrict__ d1,
+                                                        const float* __restrict__ d2, size_t n,
+                                                        const float* __restrict__ w,
+                                                        const float* __restrict__ mbar,
+                                                        float* __restrict__ g0,
+                                                        float* __restrict__ g12,
+                                                        float* __restrict__ g2) {
   using S = SOff<H>;
-  __shared__ float sw[S::SIZE];
-  __shared__ __bf16 wbf[2 * H * H];  // W2 and W2^T (BF16)
+  using E = typename P::elem;
   constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
-  __shared__ __bf16 tile[TB / 64][GV * H];
+  __shared__ float sw[S::SIZE];
+  // 16-byte aligned: fragments are read from them as 16-byte vectors
+  __shared__ __attribute__((aligned(16))) E wm[2 * H * H];  // W2 and W2^T, row-major
+  __shared__ __attribute__((aligned(16))) E tile[TB / 64][GV * H];
   {
-    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(w) + WBf<H>::W2);
-    uint4* dst = reinterpret_cast<uint4*>(wbf);
-    for (int i = threadIdx.x; i < 2 * H * H * 2 / 16; i += TB) dst[i] = src[i];
+    const E* w2 = w2_rows<P, H>(w);
+    for (int i = threadIdx.x; i < H * H; i += TB) {
+      const int r = i / H, c = i % H;
+      const E v = w2[i];
+      wm[i] = v;
+      wm[H * H + c * H + r] = v;
+    }
   }
   load_small_weights<H>(sw, w);  // ends with a barrier
   const int l = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  __bf16* T = tile[wv];
+  E* T = tile[wv];
   const size_t groups = (n + GV - 1) / GV;
   const size_t nwaves = (size_t)gridDim.x * (TB / 64);
   for (size_t g = (size_t)blockIdx.x * (TB / 64) + wv; g < groups; g += nwaves) {
     const size_t v0 = g * GV;
     floatx4_t c[MB][H / 16];
     {
-      bf16x8_t a[MB][H / 32];
-      bf16x8_t b[H / 32][H / 16];
-      h1_fragments<H, S, MB>(sw, d0, d1, d2, v0, n, a);
-      load_b<H>(wbf, b);
-      mfma_layer<H, MB>(a, b, c);
+      typename P::frag a[MB][H / P::KS];
+      typename P::frag b[H / P::KS][H / 16];
+      h1_fragments<P, H, MB>(sw, d0, d1, d2, v0, n, a);
+      load_b<P, H>(wm, b);
+      mfma_layer<P, H, MB>(a, b, c);
     }
-    // a2bar = ybar W3 [a2 > 0], stored (BF16) as a GV x H tile for the transposed read
+    // a2bar = ybar W3 [a2 > 0], stored as a GV x H tile for the transposed read
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       float y[4];
-      layer3<H, S, MB>(sw, c, mb, y);
+      layer3<H, MB>(sw, c, mb, y);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = mb * 16 + 4 * (l >> 4) + i;
@@ -345,24 +384,24 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mfma_kernel(const float* __restric
         for (int nb = 0; nb < H / 16; ++nb) {
           const int nn = nb * 16 + (l & 15);
           const float a2 = c[mb][nb][i] + sw[S::B2 + nn];
-          T[r * H + nn] = (__bf16)(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
+          T[r * H + nn] = P::cvt(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
         }
       }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);
-    // h1bar = a2bar W2 on the matrix cores
+    // h1bar = a2bar W2 on the matrix cores (B = W2 read as W2^T rows)
     {
-      bf16x8_t a[MB][H / 32];
-      bf16x8_t b[H / 32][H / 16];
+      typename P::frag a[MB][H / P::KS];
+      typename P::frag b[H / P::KS][H / 16];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int kb = 0; kb < H / 32; ++kb)
-          a[mb][kb] = *reinterpret_cast<const bf16x8_t*>(T + (mb * 16 + (l & 15)) * H + kb * 32 +
-                                                         8 * (l >> 4));
-      load_b<H>(wbf + H * H, b);
-      mfma_layer<H, MB>(a, b, c);
+        for (int kb = 0; kb < H / P::KS; ++kb)
+          a[mb][kb] = *reinterpret_cast<const typename P::frag*>(
+              T + (mb * 16 + (l & 15)) * H + kb * P::KS + P::J * (l >> 4));
+      load_b<P, H>(wm + H * H, b);
+      mfma_layer<P, H, MB>(a, b, c);
     }
     // the tile is rewritten by the next group: its reads above must have completed
     __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -574,31 +613,31 @@ int launch_mlp_prepare_bf16(int H, float* w, hipStream_t s) {
 // Workgroups of the persistent matrix-core kernels: the resident number, fewer when the
 // mesh is small.
 template <auto Kernel>
-static unsigned mfma_blocks(size_t n) {
+static unsigned mx_blocks(size_t n) {
   const size_t need = (n + TB - 1) / TB;
   const size_t res = (size_t)resident_grid<Kernel, TB>();
   return (unsigned)(need < res ? need : res);
 }
 
-template <int H>
-static void mlp_fwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
-                           const float* w, float* mass, hipStream_t s) {
-  mlp_fwd_mfma_kernel<H><<<mfma_blocks<mlp_fwd_mfma_kernel<H>>(n), TB, 0, s>>>(d0, d1, d2, n, w,
-                                                                                mass);
+template <class P, int H>
+static void mlp_fwd_mx_t(const float* d0, const float* d1, const float* d2, size_t n,
+                         const float* w, float* mass, hipStream_t s) {
+  constexpr auto k = mlp_fwd_mx_kernel<P, H>;
+  k<<<mx_blocks<k>(n), TB, 0, s>>>(d0, d1, d2, n, w, mass);
 }
-template <int H>
-static void mlp_bwd_mfma_t(const float* d0, const float* d1, const float* d2, size_t n,
-                           const float* w, const float* mbar, float* g0, float* g12, float* g2,
-                           hipStream_t s) {
-  mlp_bwd_mfma_kernel<H><<<mfma_blocks<mlp_bwd_mfma_kernel<H>>(n), TB, 0, s>>>(d0, d1, d2, n, w,
-                                                                                mbar, g0, g12, g2);
+template <class P, int H>
+static void mlp_bwd_mx_t(const float* d0, const float* d1, const float* d2, size_t n,
+                         const float* w, const float* mbar, float* g0, float* g12, float* g2,
+                         hipStream_t s) {
+  constexpr auto k = mlp_bwd_mx_kernel<P, H>;
+  k<<<mx_blocks<k>(n), TB, 0, s>>>(d0, d1, d2, n, w, mbar, g0, g12, g2);
 }
 
 int launch_mlp_fwd_mfma(int H, const float* d0, const float* d1, const float* d2, size_t n,
                         const float* w, float* mass, hipStream_t s) {
   switch (H) {
-    case 32: mlp_fwd_mfma_t<32>(d0, d1, d2, n, w, mass, s); return 0;
-    case 64: mlp_fwd_mfma_t<64>(d0, d1, d2, n, w, mass, s); return 0;
+    case 32: mlp_fwd_mx_t<MxBF16, 32>(d0, d1, d2, n, w, mass, s); return 0;
+    case 64: mlp_fwd_mx_t<MxBF16, 64>(d0, d1, d2, n, w, mass, s); return 0;
     default: return -1;
   }
 }
@@ -607,19 +646,21 @@ int launch_mlp_bwd_mfma(int H, const float* d0, const float* d1, const float* d2
                         const float* w, const float* mbar, float* g0, float* g12, float* g2,
                         hipStream_t s) {
   switch (H) {
-    case 32: mlp_bwd_mfma_t<32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
-    case 64: mlp_bwd_mfma_t<64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 32: mlp_bwd_mx_t<MxBF16, 32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 64: mlp_bwd_mx_t<MxBF16, 64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
     default: return -1;
   }
 }
 
+// FP32 network: H x H layer on the FP32 matrix cores where H is a multiple of 16, else one
+// thread per voxel on the vector units.
 int launch_mlp_fwd(int H, const float* d0, const float* d1, const float* d2, size_t n,
                    const float* w, float* mass, hipStream_t s) {
   switch (H) {
     case 8: mlp_fwd_t<8>(d0, d1, d2, n, w, mass, s); return 0;
-    case 16: mlp_fwd_t<16>(d0, d1, d2, n, w, mass, s); return 0;
-    case 32: mlp_fwd_t<32>(d0, d1, d2, n, w, mass, s); return 0;
-    case 64: mlp_fwd_t<64>(d0, d1, d2, n, w, mass, s); return 0;
+    case 16: mlp_fwd_mx_t<MxF32, 16>(d0, d1, d2, n, w, mass, s); return 0;
+    case 32: mlp_fwd_mx_t<MxF32, 32>(d0, d1, d2, n, w, mass, s); return 0;
+    case 64: mlp_fwd_mx_t<MxF32, 64>(d0, d1, d2, n, w, mass, s); return 0;
     default: return -1;
   }
 }
@@ -629,9 +670,9 @@ int launch_mlp_bwd(int H, const float* d0, const float* d1, const float* d2, siz
                    hipStream_t s) {
   switch (H) {
     case 8: mlp_bwd_t<8>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
-    case 16: mlp_bwd_t<16>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
-    case 32: mlp_bwd_t<32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
-    case 64: mlp_bwd_t<64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 16: mlp_bwd_mx_t<MxF32, 16>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 32: mlp_bwd_mx_t<MxF32, 32>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
+    case 64: mlp_bwd_mx_t<MxF32, 64>(d0, d1, d2, n, w, mbar, g0, g12, g2, s); return 0;
     default: return -1;
   }
 }

@@ -221,3 +221,13 @@ def test_large_mesh_shape_scaled_to_64_on_128():
         grads[precision] = res["grad"][0]
     a, b = grads[P.PMR_FP32], grads[P.PMR_MIXED]
     say(f"  mixed vs FP32: grad rel-L2 {rel_l2(b, a):.3e}, cos {cosine(b, a):.6f}")
+
+
+@pytest.mark.parametrize("hidden", [8, 16])
+def test_small_networks(hidden):
+    """H = 8 (vector units) and H = 16 (FP32 matrix cores, one 16-wide block), 16^3, 3 steps."""
+    require_gpu()
+    say(f"pipeline: 16^3, H={hidden}")
+    prob = _problem(16, 16, 16, 50.0, 3, OM.LOSS_LOGNORMAL, 2, hidden=hidden, R_sm=(1.0, 0.0))
+    res = _gpu_run(*prob, hidden=hidden)
+    _compare(*prob, res, TOL_FP32)
