@@ -92,17 +92,9 @@ __global__ __launch_bounds__(TB) void radix_hist_kernel(const uint32_t* __restri
   for (int i = threadIdx.x; i < NBK; i += TB) cnt[i] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * SORT_TILE;
-  // all loads first, so that their latencies overlap
-  uint32_t kk[SORT_TILE / TB];
-#pragma unroll
-  for (int m = 0; m < SORT_TILE / TB; ++m) {
-    const size_t j = base + threadIdx.x + (size_t)m * TB;
-    kk[m] = j < (size_t)n ? keys[j] : 0u;
-  }
-#pragma unroll
-  for (int m = 0; m < SORT_TILE / TB; ++m) {
-    const size_t j = base + threadIdx.x + (size_t)m * TB;
-    if (j < (size_t)n) atomicAdd(&cnt[(kk[m] >> shift) & (NBK - 1)], 1u);
+  for (int i = threadIdx.x; i < SORT_TILE; i += TB) {
+    const size_t j = base + i;
+    if (j < (size_t)n) atomicAdd(&cnt[(keys[j] >> shift) & (NBK - 1)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NBK; i += TB) hist[(size_t)i * gridDim.x + blockIdx.x] = cnt[i];
@@ -137,18 +129,12 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
   const size_t base = tile0 + (size_t)w * PMR_WAVE * SORT_ITEMS;
   uint32_t key[SORT_ITEMS], id[SORT_ITEMS], rank[SORT_ITEMS];
   const uint64_t lt = lanemask_lt();
-  // all loads first, so that their latencies overlap instead of one per ranked item
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const size_t j = base + (size_t)it * PMR_WAVE + lane;
     const bool ok = j < (size_t)n;
     key[it] = ok ? keys_in[j] : 0u;
     id[it] = ok ? (ids_in ? ids_in[j] : (uint32_t)j) : 0u;
-  }
-#pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
-    const size_t j = base + (size_t)it * PMR_WAVE + lane;
-    const bool ok = j < (size_t)n;
     const uint32_t d = (key[it] >> shift) & (NBK - 1);
     const uint64_t valid = __ballot(ok);
     const uint64_t m = match_digit<D>(d, valid);
@@ -220,39 +206,14 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
   }
   __syncthreads();
   const int count = (int)min((size_t)SORT_TILE, (size_t)n - tile0);
-  static_assert(SORT_TILE % TB == 0, "whole tile per thread sweep");
-  constexpr int PER = SORT_TILE / TB;
-  uint32_t kv[PER], iv[PER], dv[PER];
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = threadIdx.x + m * TB;
-    kv[m] = iv[m] = dv[m] = 0u;
-    if (e < count) {
-      kv[m] = skey[e];
-      iv[m] = sid[e];
-      const uint32_t d = (kv[m] >> shift) & (NBK - 1);
-      dv[m] = gbase[d] + (uint32_t)e - dstart[d];
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    if (threadIdx.x + m * TB < count) {
-      keys_out[dv[m]] = kv[m];
-      ids_out[dv[m]] = iv[m];
-    }
-  }
-  if (pay_out) {
-    // gather the payload in batches of 8 so that the loads of a batch overlap
-#pragma unroll
-    for (int m0 = 0; m0 < PER; m0 += 8) {
-      float4 pv[8];
-#pragma unroll
-      for (int m = 0; m < 8; ++m)
-        if (threadIdx.x + (m0 + m) * TB < count) pv[m] = pay_in[iv[m0 + m]];
-#pragma unroll
-      for (int m = 0; m < 8; ++m)
-        if (threadIdx.x + (m0 + m) * TB < count) pay_out[dv[m0 + m]] = pv[m];
-    }
+  for (int e = threadIdx.x; e < count; e += TB) {
+    const uint32_t k = skey[e];
+    const uint32_t d = (k >> shift) & (NBK - 1);
+    const uint32_t dst = gbase[d] + (uint32_t)e - dstart[d];
+    const uint32_t idv = sid[e];
+    keys_out[dst] = k;
+    ids_out[dst] = idv;
+    if (pay_out) pay_out[dst] = pay_in[idv];
   }
 }
 

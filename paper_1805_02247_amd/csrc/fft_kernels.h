@@ -17,6 +17,7 @@
 // twiddles are evaluated once per workgroup in FP64 and rounded to FP32.
 #pragma once
 #include "pmr_internal.h"
+#include "twiddle.h"
 
 namespace pmr {
 
@@ -149,13 +150,15 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw) {
   static_assert(M <= 512, "at most 512 points per line");
 }
 
-// exp(-2 pi i j / N) for j < N, from FP64 sincospi.
+// exp(-2 pi i j / N) for j < N: copied from the compile-time table (twiddle.h).
+template <int N>
+__device__ constexpr TwTable<N> kTw = make_tw_table<N>();
+
 template <int N, int NTH = NT>
 __device__ __forceinline__ void make_twiddles(float2* tw) {
   for (int j = threadIdx.x; j < N; j += NTH) {
-    double s, c;
-    sincospi(-2.0 * (double)j / (double)N, &s, &c);
-    tw[j] = make_float2((float)c, (float)s);
+    const TwEntry e = kTw<N>.v[j];
+    tw[j] = make_float2(e.re, e.im);
   }
 }
 
@@ -196,103 +199,68 @@ __device__ __forceinline__ void inv_split(float2* z, int k, float2 xk, float2 xm
   }
 }
 
-// in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex (row pitch om.pitch).
+// in: fields of n^3 reals; out = fields of n*n*(n/2+1) complex (row pitch om.pitch). One tile
+// (ROWS rows of one field) per workgroup: measured faster here than a prefetching tile loop.
 // Value loaded: a1 * in (+ a2 * in2 if in2) (* scale_dev[field / fields_per_item]).
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__ in, FieldMap im,
                                                        const float* __restrict__ in2, float a1,
                                                        float a2, const double* __restrict__ scale_dev,
-                                                       float2* __restrict__ out, FieldMap om,
-                                                       int tiles_per_field, int ntiles) {
+                                                       float2* __restrict__ out, FieldMap om) {
   using T = ZTile<N>;
   constexpr int H = T::H, ROWS = T::ROWS, PITCH = T::PITCH;
-  constexpr int PER = (ROWS * H + NT - 1) / NT;
   __shared__ float2 lds[ROWS * PITCH];
   __shared__ float2 tw[N];
   make_twiddles<N>(tw);
-  auto load = [&](int t, float2 (&r)[PER]) {
-    const int field = t / tiles_per_field;
-    const size_t row0 = (size_t)(t % tiles_per_field) * ROWS;
-    const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
-    const float2* src2 =
-        in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
-    const float sc = scale_dev ? (float)scale_dev[field / im.fpi] : 1.0f;
-    const float b1 = a1 * sc, b2 = a2 * sc;
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = threadIdx.x + m * NT;
-      float2 v = make_float2(0.f, 0.f);
-      if ((ROWS * H) % NT == 0 || e < ROWS * H) {
-        v = src[e];
-        v.x *= b1;
-        v.y *= b1;
-        if (src2) {
-          const float2 w = src2[e];
-          v.x += b2 * w.x;
-          v.y += b2 * w.y;
-        }
+  const int field = blockIdx.y;
+  const size_t row0 = (size_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+  const float2* src = reinterpret_cast<const float2*>(in + im.off(field)) + row0 * H;
+  const float2* src2 =
+      in2 ? reinterpret_cast<const float2*>(in2 + im.off(field)) + row0 * H : nullptr;
+  float sc = 1.0f;
+  if (scale_dev) sc = (float)scale_dev[field / im.fpi];
+  const float b1 = a1 * sc, b2 = a2 * sc;
+  for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+    float2 v = src[e];
+    v.x *= b1;
+    v.y *= b1;
+    if (src2) {
+      float2 w = src2[e];
+      v.x += b2 * w.x;
+      v.y += b2 * w.y;
+    }
+    lds[(e / H) * PITCH + zk(e % H)] = v;
+  }
+  __syncthreads();
+  fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
+  // split: X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2, W = e^{-2 pi i/N}
+  float2* dst = out + om.off(field) + row0 * om.pitch;
+  constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
+  for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
+    const int r = e / Q, k = e % Q;
+    const float2* z = lds + r * PITCH;
+    float2* d = dst + (size_t)r * om.pitch;
+    if (k == 0) {
+      float2 z0 = z[0];
+      d[0] = make_float2(z0.x + z0.y, 0.f);
+      d[H] = make_float2(z0.x - z0.y, 0.f);
+    } else {
+      const float2 zv = z[zk(k)], zm = z[zk(H - k)];
+      {
+        float2 s = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
+        float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
+        float2 w = tw[k];
+        float2 t = cmul(w, df);  // W^k * diff
+        d[k] = make_float2(s.x + t.y, s.y - t.x);  // s - i t
       }
-      r[m] = v;
-    }
-  };
-  int tau = xcd_block(blockIdx.x, gridDim.x);
-  float2 pre[PER];
-  load(tau, pre);
-  __syncthreads();  // twiddles
-  for (;;) {
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int e = threadIdx.x + m * NT;
-      if ((ROWS * H) % NT == 0 || e < ROWS * H) lds[(e / H) * PITCH + zk(e % H)] = pre[m];
-    }
-    __syncthreads();
-    const int next = tau + gridDim.x;
-    if (next < ntiles) load(next, pre);
-    fft_lds<H, ROWS, 1, PITCH, 2, -1, NT, true>(lds, tw);
-    // split, in place (each pair (k, H-k) belongs to one thread):
-    // X[k] = (Z[k] + conj Z[H-k]) / 2 - i W^k (Z[k] - conj Z[H-k]) / 2; X[H] from Z[0]
-    constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
-    for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-      const int r = e / Q, k = e % Q;
-      float2* z = lds + r * PITCH;
-      if (k == 0) {
-        const float2 z0 = z[0];
-        z[0] = make_float2(z0.x + z0.y, 0.f);
-        z[zk(H)] = make_float2(z0.x - z0.y, 0.f);
-      } else {
-        const float2 zv = z[zk(k)], zm = z[zk(H - k)];
-        {
-          float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
-          float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
-          float2 t = cmul(tw[k], df);  // W^k * diff
-          z[zk(k)] = make_float2(sm.x + t.y, sm.y - t.x);  // sm - i t
-        }
-        if (k != H - k) {
-          float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
-          float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
-          float2 t = cmul(tw[H - k], df);
-          z[zk(H - k)] = make_float2(sm.x + t.y, sm.y - t.x);
-        }
+      if (k != H - k) {
+        float2 s = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
+        float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
+        float2 w = tw[H - k];
+        float2 t = cmul(w, df);
+        d[H - k] = make_float2(s.x + t.y, s.y - t.x);
       }
     }
-    __syncthreads();
-    // rows out: a fixed, unrolled sequence of stores per thread (the wait for the prefetched
-    // loads at the top of the next tile then need not drain them)
-    const int field = tau / tiles_per_field;
-    const size_t row0 = (size_t)(tau % tiles_per_field) * ROWS;
-    float2* dst = out + om.off(field) + row0 * om.pitch;
-    constexpr int PO = (ROWS * (H + 1) + NT - 1) / NT;
-#pragma unroll
-    for (int m = 0; m < PO; ++m) {
-      const int e = threadIdx.x + m * NT;
-      if (e < ROWS * (H + 1)) {
-        const int r = e / (H + 1), k = e % (H + 1);
-        dst[(size_t)r * om.pitch + k] = lds[r * PITCH + zk(k)];
-      }
-    }
-    if (next >= ntiles) break;
-    __syncthreads();  // the rows have been read
-    tau = next;
   }
 }
 
@@ -700,10 +668,8 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
 template <int N>
 void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, float a2,
           const double* sc, float2* out, FieldMap om, hipStream_t s) {
-  // one tile per workgroup: measured faster than the resident tile loop for this pass
-  const int per = (N * N) / ZTile<N>::ROWS, ntiles = per * fields;
-  zpass_r2c_kernel<N><<<ntiles, NT, 0, s>>>(
-      in, im, in2, a1, a2, sc, out, om, per, ntiles);
+  dim3 grid((N * N) / ZTile<N>::ROWS, fields);
+  zpass_r2c_kernel<N><<<grid, NT, 0, s>>>(in, im, in2, a1, a2, sc, out, om);
 }
 
 template <int N>

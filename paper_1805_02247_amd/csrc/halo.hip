@@ -234,8 +234,8 @@ __device__ __forceinline__ void h1_fragments(const float* sw, const float* __res
   }
 }
 
-// B fragments of a row-major [n][k] matrix m (B[k][n] = m[n][k]), element type of P.
-template <class P, int H>
+// B fragments of a row-major [n][k] matrix m with row pitch RP (B[k][n] = m[n][k]).
+template <class P, int H, int RP = H>
 __device__ __forceinline__ void load_b(const typename P::elem* __restrict__ m,
                                        typename P::frag (&b)[H / P::KS][H / 16]) {
   const int l = threadIdx.x & 63;
@@ -244,7 +244,7 @@ __device__ __forceinline__ void load_b(const typename P::elem* __restrict__ m,
 #pragma unroll
     for (int nb = 0; nb < H / 16; ++nb)
       b[kb][nb] = *reinterpret_cast<const typename P::frag*>(
-          m + (size_t)(nb * 16 + (l & 15)) * H + kb * P::KS + P::J * (l >> 4));
+          m + (size_t)(nb * 16 + (l & 15)) * RP + kb * P::KS + P::J * (l >> 4));
 }
 
 template <class P, int H, int MB>
@@ -342,16 +342,18 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict_
   using E = typename P::elem;
   constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
   __shared__ float sw[S::SIZE];
-  // 16-byte aligned: fragments are read from them as 16-byte vectors
-  __shared__ __attribute__((aligned(16))) E wm[2 * H * H];  // W2 and W2^T, row-major
-  __shared__ __attribute__((aligned(16))) E tile[TB / 64][GV * H];
+  // Row pitch RP: rows of the LDS copies are padded so that the 16 rows a fragment read
+  // touches fall on distinct banks. 16-byte aligned: BF16 fragments are 16-byte vectors.
+  constexpr int RP = H + (sizeof(E) == 2 ? 8 : 1);
+  __shared__ __attribute__((aligned(16))) E wm[2 * H * RP];  // W2 and W2^T, row-major
+  __shared__ __attribute__((aligned(16))) E tile[TB / 64][GV * RP];
   {
     const E* w2 = w2_rows<P, H>(w);
     for (int i = threadIdx.x; i < H * H; i += TB) {
       const int r = i / H, c = i % H;
       const E v = w2[i];
-      wm[i] = v;
-      wm[H * H + c * H + r] = v;
+      wm[r * RP + c] = v;
+      wm[H * RP + c * RP + r] = v;
     }
   }
   load_small_weights<H>(sw, w);  // ends with a barrier
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict_
       typename P::frag a[MB][H / P::KS];
       typename P::frag b[H / P::KS][H / 16];
       h1_fragments<P, H, MB>(sw, d0, d1, d2, v0, n, a);
-      load_b<P, H>(wm, b);
+      load_b<P, H, RP>(wm, b);
       mfma_layer<P, H, MB>(a, b, c);
     }
     // a2bar = ybar W3 [a2 > 0], stored as a GV x H tile for the transposed read
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict_
         for (int nb = 0; nb < H / 16; ++nb) {
           const int nn = nb * 16 + (l & 15);
           const float a2 = c[mb][nb][i] + sw[S::B2 + nn];
-          T[r * H + nn] = P::cvt(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
+          T[r * RP + nn] = P::cvt(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
         }
       }
     }
@@ -399,8 +401,8 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict_
 #pragma unroll
         for (int kb = 0; kb < H / P::KS; ++kb)
           a[mb][kb] = *reinterpret_cast<const typename P::frag*>(
-              T + (mb * 16 + (l & 15)) * H + kb * P::KS + P::J * (l >> 4));
-      load_b<P, H>(wm + H * H, b);
+              T + (mb * 16 + (l & 15)) * RP + kb * P::KS + P::J * (l >> 4));
+      load_b<P, H, RP>(wm + H * RP, b);
       mfma_layer<P, H, MB>(a, b, c);
     }
     // the tile is rewritten by the next group: its reads above must have completed
