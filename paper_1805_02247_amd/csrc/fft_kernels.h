@@ -408,59 +408,90 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
 }
 
 // ---------------------------------------------------------------- strided passes
-// Tile: PCOL consecutive kz columns (from kz0) of the N points of one line family.
-// Element (n, l) of a tile sits at base + n * stride + l.
-template <int N, int PC, int NTH>
+// Tile: PC consecutive kz columns (from kz0) of the N points of one line family.
+// Element (n, l) of a tile sits at base + n * stride + l; in LDS at n * PC + l.
+// Global accesses move V consecutive columns at once: V = 1 (one complex value, 8 bytes) or
+// V = 2 (a 16-byte column pair; used where rows have an even pitch, so pairs are aligned and
+// the partner of an odd last column is row padding, read and written but never used).
+template <int V>
+struct VecT;
+template <>
+struct VecT<1> {
+  typedef float2 type;
+  __device__ static float2 zero() { return make_float2(0.f, 0.f); }
+};
+template <>
+struct VecT<2> {
+  typedef float4 type;
+  __device__ static float4 zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+
+template <int N, int PC, int NTH, int V>
 __device__ __forceinline__ void load_tile(float2* lds, const float2* __restrict__ base,
                                           size_t stride, int ncols) {
-  for (int e = threadIdx.x; e < N * PC; e += NTH) {
-    const int n = e / PC, l = e % PC;
-    lds[e] = l < ncols ? base[(size_t)n * stride + l] : make_float2(0.f, 0.f);
+  using T = typename VecT<V>::type;
+  static_assert((N * PC) % (NTH * V) == 0, "whole tile per thread sweep");
+#pragma unroll
+  for (int m = 0; m < N * PC / (NTH * V); ++m) {
+    const int p = threadIdx.x + m * NTH;
+    const int n = p / (PC / V), l = (p % (PC / V)) * V;
+    reinterpret_cast<T*>(lds)[p] =
+        l < ncols ? *reinterpret_cast<const T*>(base + (size_t)n * stride + l) : VecT<V>::zero();
   }
 }
 
-template <int N, int PC, int NTH>
+template <int N, int PC, int NTH, int V>
 __device__ __forceinline__ void store_tile(const float2* lds, float2* __restrict__ base,
                                            size_t stride, int ncols) {
-  static_assert((N * PC) % NTH == 0, "whole tile per thread sweep");
+  using T = typename VecT<V>::type;
+  static_assert((N * PC) % (NTH * V) == 0, "whole tile per thread sweep");
 #pragma unroll
-  for (int m = 0; m < N * PC / NTH; ++m) {
-    const int e = threadIdx.x + m * NTH;
-    const int n = e / PC, l = e % PC;
-    if (l < ncols) base[(size_t)n * stride + l] = lds[e];
+  for (int m = 0; m < N * PC / (NTH * V); ++m) {
+    const int p = threadIdx.x + m * NTH;
+    const int n = p / (PC / V), l = (p % (PC / V)) * V;
+    if (l < ncols)
+      *reinterpret_cast<T*>(base + (size_t)n * stride + l) = reinterpret_cast<const T*>(lds)[p];
   }
 }
 
-// Register image of a tile: thread t holds elements e = t + m * NTH (point n = e / PC, column
-// l = e % PC). Loading the next tile into registers while the current one is transformed
-// overlaps the HBM latency with the LDS work.
-template <int N, int PC, int NTH>
-__device__ __forceinline__ void load_regs(float2 (&r)[N * PC / NTH], const float2* __restrict__ base,
+// Register image of a tile: thread t holds the units p = t + m * NTH (V columns each).
+// Loading the next tile into registers while the current one is transformed overlaps the
+// HBM latency with the LDS work.
+template <int N, int PC, int NTH, int V>
+struct TileRegs {
+  static constexpr int PER = N * PC / (NTH * V);
+  typename VecT<V>::type r[PER];
+};
+
+template <int N, int PC, int NTH, int V>
+__device__ __forceinline__ void load_regs(TileRegs<N, PC, NTH, V>& t, const float2* __restrict__ base,
                                           size_t stride, int ncols) {
+  using T = typename VecT<V>::type;
 #pragma unroll
-  for (int m = 0; m < N * PC / NTH; ++m) {
-    const int e = threadIdx.x + m * NTH;
-    const int n = e / PC, l = e % PC;
-    r[m] = l < ncols ? base[(size_t)n * stride + l] : make_float2(0.f, 0.f);
+  for (int m = 0; m < TileRegs<N, PC, NTH, V>::PER; ++m) {
+    const int p = threadIdx.x + m * NTH;
+    const int n = p / (PC / V), l = (p % (PC / V)) * V;
+    t.r[m] = l < ncols ? *reinterpret_cast<const T*>(base + (size_t)n * stride + l) : VecT<V>::zero();
   }
 }
 
-template <int N, int PC, int NTH>
-__device__ __forceinline__ void regs_to_lds(const float2 (&r)[N * PC / NTH], float2* lds) {
+template <int N, int PC, int NTH, int V>
+__device__ __forceinline__ void regs_to_lds(const TileRegs<N, PC, NTH, V>& t, float2* lds) {
+  using T = typename VecT<V>::type;
 #pragma unroll
-  for (int m = 0; m < N * PC / NTH; ++m) lds[threadIdx.x + m * NTH] = r[m];
+  for (int m = 0; m < TileRegs<N, PC, NTH, V>::PER; ++m)
+    reinterpret_cast<T*>(lds)[threadIdx.x + m * NTH] = t.r[m];
 }
 
 // y pass: in-place forward or inverse transform along y of each field. A workgroup walks
 // the tiles blockIdx.x, blockIdx.x + gridDim.x, ... (tile = (field, x plane, kz chunk)),
 // prefetching the next tile into registers.
-template <int N, int DIR, int PC, int NTH>
+template <int N, int DIR, int PC, int NTH, int V>
 __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, FieldMap m,
                                                     int ntiles) {
   constexpr int NH = N / 2 + 1;
   constexpr int NCH = (NH + PC - 1) / PC;
-  constexpr int PER = N * PC / NTH;
-  __shared__ float2 lds[N * PC];
+  __shared__ __attribute__((aligned(16))) float2 lds[N * PC];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
   auto tile_base = [&](int tau, int& ncols) {
@@ -472,20 +503,20 @@ __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, F
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   int nc;
   float2* b = tile_base(tau, nc);
-  float2 pre[PER];
-  load_regs<N, PC, NTH>(pre, b, m.pitch, nc);
+  TileRegs<N, PC, NTH, V> pre;
+  load_regs<N, PC, NTH, V>(pre, b, m.pitch, nc);
   for (;;) {
-    regs_to_lds<N, PC, NTH>(pre, lds);
+    regs_to_lds<N, PC, NTH, V>(pre, lds);
     __syncthreads();
     const int next = tau + gridDim.x;
     int nc2 = 0;
     float2* b2 = nullptr;
     if (next < ntiles) {
       b2 = tile_base(next, nc2);
-      load_regs<N, PC, NTH>(pre, b2, m.pitch, nc2);
+      load_regs<N, PC, NTH, V>(pre, b2, m.pitch, nc2);
     }
     fft_lds<N, PC, PC, 1, 1, DIR, NTH>(lds, tw);
-    store_tile<N, PC, NTH>(lds, b, m.pitch, nc);
+    store_tile<N, PC, NTH, V>(lds, b, m.pitch, nc);
     if (next >= ntiles) break;
     __syncthreads();
     tau = next;
@@ -523,14 +554,14 @@ __device__ __forceinline__ float grad_coef(const KVec& k, int a) {
   return ka * __builtin_amdgcn_rcpf(k.k2);
 }
 
-template <int N, int OP, int PC, int NTH>
+template <int N, int OP, int PC, int NTH, int V>
 __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   constexpr int NH = N / 2 + 1;
   constexpr int NCH = (NH + PC - 1) / PC;
   constexpr int NE = N * PC;
   constexpr int PER = NE / NTH;
   static_assert(NE % NTH == 0, "tile");
-  __shared__ float2 lds[NE];
+  __shared__ __attribute__((aligned(16))) float2 lds[NE];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
   const size_t istride = (size_t)N * a.in_pitch, ostride = (size_t)N * a.out_pitch;
@@ -542,11 +573,11 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   const int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
 
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
-  float2 pre[PER];  // first input of the current tile (prefetched)
+  TileRegs<N, PC, NTH, V> pre;  // first input of the current tile (prefetched)
   {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     const int kz0 = ch * PC;
-    load_regs<N, PC, NTH>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0,
+    load_regs<N, PC, NTH, V>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0,
                           istride, min(PC, NH - kz0));
   }
   for (;;) {
@@ -566,15 +597,15 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
     // -------- inputs
     for (int i = 0; i < n_in; ++i) {
       if (i == 0) {
-        regs_to_lds<N, PC, NTH>(pre, lds);
+        regs_to_lds<N, PC, NTH, V>(pre, lds);
       } else {
-        load_tile<N, PC, NTH>(lds, a.in[i] + ioff, istride, ncols);
+        load_tile<N, PC, NTH, V>(lds, a.in[i] + ioff, istride, ncols);
       }
       __syncthreads();
       if (i == 0 && next < ntiles) {
         const int nch = next % NCH, niy = (next / NCH) % N, nit = next / (NCH * N);
         const int nkz0 = nch * PC;
-        load_regs<N, PC, NTH>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
+        load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
                               istride, min(PC, NH - nkz0));
       }
       if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
@@ -607,7 +638,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
 #pragma unroll
       for (int m = 0; m < PER; ++m) lds[t + m * NTH] = hold[m];
       __syncthreads();
-      store_tile<N, PC, NTH>(lds, a.out[0] + ooff, ostride, ncols);
+      store_tile<N, PC, NTH, V>(lds, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
       const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
@@ -655,7 +686,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
         }
         __syncthreads();
         fft_lds<N, PC, PC, 1, 1, +1, NTH>(lds, tw);
-        store_tile<N, PC, NTH>(lds, a.out[o] + ooff, ostride, ncols);
+        store_tile<N, PC, NTH, V>(lds, a.out[o] + ooff, ostride, ncols);
         __syncthreads();
       }
     }
@@ -1019,6 +1050,12 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   }
 }
 
+// 16-byte column pairs need an even number of elements per thread.
+template <int N, int PC, int NTH>
+constexpr bool pairs_ok() {
+  return (N * PC) % (2 * NTH) == 0;
+}
+
 // Tile loops launch the resident number of workgroups (at most the number of tiles).
 template <auto Kernel, int NTH>
 int tile_grid(int ntiles) {
@@ -1041,11 +1078,23 @@ void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t 
       return;
     }
   }
+  if constexpr (pairs_ok<N, PC, NTH>()) {
+    if (m.pitch % 2 == 0) {
+      if (inv) {
+        constexpr auto k = ypass_kernel<N, +1, PC, NTH, 2>;
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+      } else {
+        constexpr auto k = ypass_kernel<N, -1, PC, NTH, 2>;
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+      }
+      return;
+    }
+  }
   if (inv) {
-    constexpr auto k = ypass_kernel<N, +1, PC, NTH>;
+    constexpr auto k = ypass_kernel<N, +1, PC, NTH, 1>;
     k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
   } else {
-    constexpr auto k = ypass_kernel<N, -1, PC, NTH>;
+    constexpr auto k = ypass_kernel<N, -1, PC, NTH, 1>;
     k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
   }
 }
@@ -1060,7 +1109,14 @@ void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
       return;
     }
   }
-  constexpr auto k = xpass_kernel<N, OP, PC, NTH>;
+  if constexpr (pairs_ok<N, PC, NTH>() && OP != XOP_ZA && OP != XOP_ZA_ADJ) {
+    if (a.in_pitch % 2 == 0 && a.out_pitch % 2 == 0) {
+      constexpr auto k = xpass_kernel<N, OP, PC, NTH, 2>;
+      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
+      return;
+    }
+  }
+  constexpr auto k = xpass_kernel<N, OP, PC, NTH, 1>;
   k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
 }
 
