@@ -184,8 +184,10 @@ int pmr_fft_r2c(int n, int batch, const float* in, void* out, void* stream);
 int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
 
 /* Tile shape of one strided FFT pass for size n (process-wide; the autotuner sets it).
- * `pass` PMR_FFT_YPASS (the middle axis) or PMR_FFT_XPASS (the outermost axis, which also
- * applies the k-space operators). `columns` consecutive kz columns per workgroup tile
+ * `pass` PMR_FFT_YPASS (the middle axis), PMR_FFT_XPASS (the outermost axis with a
+ * single-input k-space operator: forward or inverse only, force, smoothing, Zel'dovich) or
+ * PMR_FFT_XPASS_MULTI (the outermost axis with a multi-input operator: force adjoint, feature
+ * adjoint, gradient assembly). `columns` consecutive kz columns per workgroup tile
  * (8, 16 or 32) and `threads` per workgroup (256 or 512), with
  * threads <= n * columns <= 16 * threads and the tile within 160 KB of LDS. `staging` 0 runs
  * the butterflies on register images of the tile (used where n * columns / threads is a
@@ -193,7 +195,7 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
  * the LDS-staged tile. Invalid values return PMR_E_INVALID and leave the shape unchanged.
  * Defaults: 16 columns, 256 threads, staging 0. Not synchronised with work in flight: set it
  * before enqueueing. */
-enum { PMR_FFT_YPASS = 0, PMR_FFT_XPASS = 1 };
+enum { PMR_FFT_YPASS = 0, PMR_FFT_XPASS = 1, PMR_FFT_XPASS_MULTI = 2 };
 int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging);
 int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging);
 

@@ -13,7 +13,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
 PMR_OK = 0
 PMR_FP32, PMR_MIXED = 0, 1
 PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
-PMR_FFT_YPASS, PMR_FFT_XPASS = 0, 1
+PMR_FFT_YPASS, PMR_FFT_XPASS, PMR_FFT_XPASS_MULTI = 0, 1, 2
 DBG = {"x": 1, "force": 2, "sort_ids": 3, "delta_f": 4, "features": 5, "mass_r": 6,
        "res_s": 7, "xbar0": 8, "pbar0": 9, "dbar_f": 10}
 

@@ -4,7 +4,9 @@
 
 namespace pmr {
 
-TileShape g_fft_tile[2][10] = {
+TileShape g_fft_tile[3][10] = {
+    {{16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
+     {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}},
     {{16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
      {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}},
     {{16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0}, {16, 256, 0},
@@ -102,7 +104,7 @@ void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hip
 }
 
 int set_fft_tile(int n, int pass, int pc, int nth, int lds) {
-  if (pass != 0 && pass != 1) return -1;
+  if (pass < 0 || pass > 2) return -1;
   if (n < 16 || n > 512 || (n & (n - 1))) return -1;
   if (pc != 8 && pc != 16 && pc != 32) return -1;
   if (nth != 256 && nth != 512) return -1;

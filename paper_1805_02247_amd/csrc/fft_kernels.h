@@ -1152,7 +1152,7 @@ constexpr bool multi_input() {
 
 template <int N, int OP>
 void xpass_op(const XPassArgs& a, hipStream_t s) {
-  const TileShape t = g_fft_tile[1][log2i(N)];
+  const TileShape t = g_fft_tile[multi_input<OP>() ? 2 : 1][log2i(N)];
 #define SHAPE(PC, NTH)                                                         \
   if constexpr (shape_ok<N>(PC, NTH))                                          \
     if (t.pc == PC && t.nth == NTH) {                                          \

@@ -953,7 +953,7 @@ int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging) {
 }
 
 int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging) {
-  if (!columns || !threads || !staging || !pow2_in(n, 16, 512) || (pass != 0 && pass != 1))
+  if (!columns || !threads || !staging || !pow2_in(n, 16, 512) || pass < 0 || pass > 2)
     return PMR_E_INVALID;
   get_fft_tile(n, pass, columns, threads, staging);
   return PMR_OK;

@@ -139,12 +139,12 @@ void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hip
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
 // Tile shape of the strided passes (columns per tile, threads per workgroup, and whether the
 // butterflies run on register images (0) or on the LDS-staged tile (1)), per pass (0: y pass,
-// 1: x pass with its k-space operators) and log2(n); set by pmr_fft_set_tile (the autotuner)
-// or left at the defaults. Defined in fft.hip.
+// 1: x pass with a single-input operator, 2: x pass with a multi-input operator) and log2(n);
+// set by pmr_fft_set_tile (the autotuner) or left at the defaults. Defined in fft.hip.
 struct TileShape {
   int pc, nth, lds;
 };
-extern TileShape g_fft_tile[2][10];
+extern TileShape g_fft_tile[3][10];
 
 int set_fft_tile(int n, int pass, int pc, int nth, int lds);
 void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);

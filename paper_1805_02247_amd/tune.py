@@ -1,6 +1,7 @@
 """Autotuner for the tile shapes of the strided FFT passes (columns per tile, threads per
-workgroup, register or LDS staging of the butterflies), separately for the y pass and the
-x pass (which carries the k-space operators), per mesh size, on the current GPU.
+workgroup, register or LDS staging of the butterflies), separately for the y pass, the x pass
+with single-input k-space operators and the x pass with multi-input operators, per mesh size,
+on the current GPU.
 
     python -m paper_1805_02247_amd.tune --sizes 64 128 256 512 [--write]
     python -m paper_1805_02247_amd.tune --workload 256 512 256 10 1 64 [--write]
@@ -21,7 +22,7 @@ from . import _lib as L
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fft_tiles.json")
 SHAPES = [(8, 256), (16, 256), (32, 256), (8, 512), (16, 512), (32, 512)]
-PASSES = {"y": L.PMR_FFT_YPASS, "x": L.PMR_FFT_XPASS}
+PASSES = {"y": L.PMR_FFT_YPASS, "x": L.PMR_FFT_XPASS, "xm": L.PMR_FFT_XPASS_MULTI}
 
 
 def valid(n, pc, nth):

@@ -84,13 +84,13 @@ def test_fft_tile_shape_validation():
         assert lib.pmr_fft_set_tile(128, 0, 32, 256, 1) == 0
         assert lib.pmr_fft_set_tile(128, 1, 8, 512, 0) == 0
         assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
-        for bad in [(128, 2, 16, 256, 0), (128, 0, 12, 256, 0), (128, 0, 16, 384, 0),
+        for bad in [(128, 3, 16, 256, 0), (128, 0, 12, 256, 0), (128, 0, 16, 384, 0),
                     (128, 1, 32, 256, 2), (512, 0, 32, 256, 0), (96, 0, 16, 256, 0),
                     (16, 1, 8, 256, 0)]:
             assert lib.pmr_fft_set_tile(*bad) == -1, bad
         assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
         assert lib.pmr_fft_get_tile(24, 0, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1
-        assert lib.pmr_fft_get_tile(64, 2, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1
+        assert lib.pmr_fft_get_tile(64, 3, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1
     finally:
         for p, v in saved.items():
             lib.pmr_fft_set_tile(128, p, *v)

@@ -179,7 +179,7 @@ def tile_shape():
     saved = {}
 
     def set_shape(n, pc, nth, staging):
-        for p in (P.PMR_FFT_YPASS, P.PMR_FFT_XPASS):
+        for p in (P.PMR_FFT_YPASS, P.PMR_FFT_XPASS, P.PMR_FFT_XPASS_MULTI):
             if (n, p) not in saved:
                 saved[(n, p)] = P.fft_get_tile(n, p)
             P.fft_set_tile(n, p, pc, nth, staging)
