@@ -535,11 +535,12 @@ __device__ __forceinline__ Corner corner_of(const double* xyz, double scale, int
   return c;
 }
 
-__device__ __forceinline__ size_t cidx(const Corner& c, int ox, int oy, int oz, int nm) {
-  const int ix = ox ? c.i1[0] : c.i0[0];
-  const int iy = oy ? c.i1[1] : c.i0[1];
-  const int iz = oz ? c.i1[2] : c.i0[2];
-  return ((size_t)ix * nm + iy) * nm + iz;
+// Cell index within one item's mesh (nm^3 <= 2^27 fits 32 bits).
+__device__ __forceinline__ uint32_t cidx(const Corner& c, int ox, int oy, int oz, int nm) {
+  const uint32_t ix = ox ? c.i1[0] : c.i0[0];
+  const uint32_t iy = oy ? c.i1[1] : c.i0[1];
+  const uint32_t iz = oz ? c.i1[2] : c.i0[2];
+  return (ix * (uint32_t)nm + iy) * (uint32_t)nm + iz;
 }
 
 struct StepArgs {
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
     const float wy = oy ? c.f[1] : 1.f - c.f[1];
     const float wz = oz ? c.f[2] : 1.f - c.f[2];
     const float dx = ox ? s : -s, dy = oy ? s : -s, dz = oz ? s : -s;
-    const size_t ci = cidx(c, ox, oy, oz, nm);
+    const uint32_t ci = cidx(c, ox, oy, oz, nm);
     float v = a.mass * D[ci];
     if (F) {
       const float4 f = F[ci];

@@ -34,10 +34,7 @@ __device__ __forceinline__ int cic_corner(double x, double scale, int n, double*
   double u = x * scale;
   double fl = floor(u);
   *frac = u - fl;
-  int i = (int)fl;
-  i %= n;
-  if (i < 0) i += n;
-  return i;
+  return (int)fl & (n - 1);  // floor(u) mod n (n a power of two; also for negative floor)
 }
 
 __device__ __forceinline__ double wrap_box(double x, double box) {
