@@ -435,7 +435,7 @@ int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 
 // One forward PM step i: sort x_i, paint, force, kick + drift (keys of x_{i+1} emitted on
 // the force mesh, or on the output mesh after the last step).
-void pm_step(pmr_ctx* c, int i) {
+void pm_step(pmr_ctx* c, int i, bool advance = true) {
   const int B = c->B;
   const int total = (int)(B * c->np3);
   const int xsl = xs_of(c, i);
@@ -466,6 +466,7 @@ void pm_step(pmr_ctx* c, int i) {
   }
   float4* F = fslot(c, fsl);
   c2r_yz3(c, c->nm, c->cB, 3 * cm, cm, F);
+  if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
   {
     ProfScope ps(c, PMR_PROF_KICK_DRIFT, 76.0 * B * c->np3 + 12.0 * B * c->nm3);
@@ -749,7 +750,9 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       launch_keys(xslot(c, 0), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys, c->frac_id,
                   s);
       const int end = j + c->k < c->n ? j + c->k : c->n;
-      for (int q = j; q < end; ++q) pm_step(c, q);
+      // the adjoint of steps j .. end-1 needs x, the sort and F of each step, not the
+      // positions the last kick and drift would produce (the next checkpoint)
+      for (int q = j; q < end; ++q) pm_step(c, q, q + 1 < end);
       resident_lo = j;
     }
     const int fsl = fs_of(c, i);
