@@ -24,6 +24,8 @@ namespace pmr {
 
 namespace {
 
+#include "paint_kernels.h"
+
 constexpr int NT = 256;   // threads per FFT workgroup (4 waves)
 constexpr int PCOL = 16;  // columns per strided-pass tile (16 complex = 128 B)
 
@@ -262,6 +264,85 @@ __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__
       }
     }
   }
+}
+
+// CIC paint fused with the z pass of the following r2c (Sec. 3: the density that feeds the
+// force, or the three adjoint channels in the step adjoint): a workgroup owns W * TY
+// consecutive target rows of one (item, ix) plane (TY per wavefront, deposited as in the
+// paint kernels, into LDS rows already in the z pass's padded complex layout), then
+// transforms those rows in place and writes their half spectra. The real mesh never goes
+// through HBM. rho - bias only changes X[0] of each row, by bias * N.
+template <int N>
+constexpr int paint_r2c_ty(int C) {
+  int ty = 2048 / (N * C);
+  if (ty > 16) ty = 16;
+  if (ty > N / 2) ty = N / 2;
+  if (ty > N / (NT / 64)) ty = N / (NT / 64);  // whole workgroups of rows per plane
+  int p = 1;
+  while (p * 2 <= ty) p *= 2;
+  return p;
+}
+
+template <int C, int TY, int N>
+__global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __restrict__ out,
+                                                       FieldMap om) {
+  using T = ZTile<N>;
+  constexpr int H = T::H, PITCH = T::PITCH, RP = 2 * PITCH;  // row pitch: complex, floats
+  constexpr int W = NT / 64;
+  constexpr int LINES = W * TY * C;
+  constexpr int BPX = N / (W * TY);  // workgroups per (item, ix) plane
+  __shared__ __attribute__((aligned(16))) float acc_all[LINES * RP];
+  __shared__ float2 tw[N];
+  make_twiddles<N>(tw);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int item = blk / (N * BPX);
+  const int rr = blk - item * N * BPX;
+  const int ix = rr / BPX;
+  const int iyb = (rr - ix * BPX) * (W * TY);  // first row of the workgroup
+  float* acc = acc_all + (size_t)w * TY * C * RP;
+  for (int i = lane; i < TY * C * RP; i += 64) acc[i] = 0.f;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  paint_rows<C, TY, true>(a, item, ix, iyb + w * TY, acc, RP);
+  __syncthreads();  // every row of the workgroup deposited; twiddles in place
+  float2* lds = reinterpret_cast<float2*>(acc_all);
+  fft_lds<H, LINES, 1, PITCH, 2, -1, NT, true>(lds, tw);
+  constexpr int Q = H / 2 + 1;  // pairs (k, H-k) for k = 0..H/2
+  const float bN = a.bias * (float)N;
+  for (int e = threadIdx.x; e < LINES * Q; e += NT) {
+    const int line = e / Q, k = e % Q;  // line = (wave * TY + t) * C + c
+    const int c = line % C, t = line / C;  // t: row within the workgroup
+    const float2* z = lds + line * PITCH;
+    float2* d = out + om.off(item * C + c) + ((size_t)ix * N + iyb + t) * om.pitch;
+    if (k == 0) {
+      const float2 z0 = z[0];
+      d[0] = make_float2(z0.x + z0.y - bN, 0.f);
+      d[H] = make_float2(z0.x - z0.y, 0.f);
+    } else {
+      const float2 zv = z[zk(k)], zm = z[zk(H - k)];
+      {
+        float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
+        float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
+        float2 t2 = cmul(tw[k], df);
+        d[k] = make_float2(sm.x + t2.y, sm.y - t2.x);
+      }
+      if (k != H - k) {
+        float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
+        float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
+        float2 t2 = cmul(tw[H - k], df);
+        d[H - k] = make_float2(sm.x + t2.y, sm.y - t2.x);
+      }
+    }
+  }
+}
+
+template <int C, int N>
+void paint_r2c(const PaintArgs& a, int batch, float2* out, FieldMap om, hipStream_t s) {
+  constexpr int TY = paint_r2c_ty<N>(C);
+  constexpr int W = NT / 64;
+  const int blocks = batch * N * (N / (W * TY));
+  paint_r2c_kernel<C, TY, N><<<blocks, NT, 0, s>>>(a, out, om);
 }
 
 // Row pairs (k, H - k) of a c2r tile held in registers: pair e = threadIdx + m NT of the

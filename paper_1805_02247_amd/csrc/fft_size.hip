@@ -26,6 +26,14 @@ void PMR_CAT(fft_zc2r3_, PMR_FFT_SIZE)(int items, const float2* in, FieldMap im,
   zc2r3<PMR_FFT_SIZE>(items, in, im, out, out_item_stride, s);
 }
 
+void PMR_CAT(fft_paint_r2c_, PMR_FFT_SIZE)(int channels, const PaintArgs& a, int batch,
+                                           float2* out, FieldMap om, hipStream_t s) {
+  if (channels == 3)
+    paint_r2c<3, PMR_FFT_SIZE>(a, batch, out, om, s);
+  else
+    paint_r2c<1, PMR_FFT_SIZE>(a, batch, out, om, s);
+}
+
 void PMR_CAT(fft_ypass_, PMR_FFT_SIZE)(int fields, float2* d, FieldMap m, bool inv,
                                        hipStream_t s) {
   ypass<PMR_FFT_SIZE>(fields, d, m, inv, s);

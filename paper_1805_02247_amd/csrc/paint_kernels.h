@@ -1,0 +1,180 @@
+// CIC paint building blocks shared by the paint kernels (cic.hip) and the paint fused with
+// the first FFT pass (fft_kernels.h): sorted-stream chunks, the wave-level segmented scan and
+// the phase-ordered deposit into a wavefront's LDS rows. Include inside namespace pmr's
+// anonymous namespace.
+#pragma once
+
+
+// Segmented inclusive scan over the 64 lanes by equal key, on DPP lane moves (VALU, no
+// LDS): row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and row_bcast 31
+// across rows. Keys are sorted across the lanes, so "source key == my key" means the
+// source lane is in my segment. Lanes whose DPP source is out of range read 0.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_f(float src) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, RMASK, 0xF, false));
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ uint32_t dpp_k(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)src, CTRL, RMASK, 0xF, false);
+}
+
+template <int NV, int CTRL, int RMASK>
+__device__ __forceinline__ void seg_step(float (&v)[NV], uint32_t key) {
+  const uint32_t ks = dpp_k<CTRL, RMASK>(key);
+  float t[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) t[q] = dpp_f<CTRL, RMASK>(v[q]);
+  if (ks == key) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += t[q];
+  }
+}
+
+// Only the steps the chunk needs run (wave-uniform): with eq = lanes whose key equals the
+// previous lane's, the longest run of set bits bounds the within-row shifts, and the
+// row-crossing steps run only when a segment crosses lane 16/48 or 32.
+template <int NV>
+__device__ __forceinline__ void seg_scan(float (&v)[NV], uint32_t key) {
+  const uint32_t kp = __shfl_up(key, 1, 64);
+  const int lane = threadIdx.x & 63;
+  const uint64_t eq = __ballot(lane > 0 && kp == key);
+  if (eq == 0) return;
+  int run = 0;  // longest run of ones in eq
+  for (uint64_t m = eq; m; m &= (m >> 1)) ++run;
+  seg_step<NV, 0x111, 0xF>(v, key);                       // row_shr:1
+  if (run >= 2) seg_step<NV, 0x112, 0xF>(v, key);         // row_shr:2
+  if (run >= 4) seg_step<NV, 0x114, 0xF>(v, key);         // row_shr:4
+  if (run >= 8) seg_step<NV, 0x118, 0xF>(v, key);         // row_shr:8
+  if (eq & ((1ull << 16) | (1ull << 48))) seg_step<NV, 0x142, 0xA>(v, key);  // row_bcast:15
+  if (eq & (1ull << 32)) seg_step<NV, 0x143, 0xC>(v, key);  // row_bcast:31
+}
+
+// One 64-particle chunk of a source run: per lane the four (oy, oz) weights of each channel.
+template <int C>
+struct Chunk {
+  uint32_t key;
+  int sy, iz;
+  bool ok;
+  float v[4 * C];
+};
+
+template <int C>
+__device__ __forceinline__ void load_chunk(const PaintArgs& a, uint32_t j, uint32_t end, int ox,
+                                           Chunk<C>& ch) {
+  const int lane = threadIdx.x & 63;
+  const int nm = a.nm;
+  ch.ok = j < end;
+  ch.key = 0xffffffffu - lane;  // never equal across lanes when invalid
+  ch.sy = 0;
+  ch.iz = 0;
+#pragma unroll
+  for (int q = 0; q < 4 * C; ++q) ch.v[q] = 0.f;
+  if (ch.ok) {
+    const uint32_t key = a.keys[j];
+    const float4 f = a.frac[j];
+    ch.key = key;
+    ch.iz = (int)(key & (uint32_t)(nm - 1));
+    ch.sy = (int)((key >> a.log_nm) & (uint32_t)(nm - 1));
+    const float wx = ox ? f.x : 1.f - f.x;
+    float val[C];
+    if constexpr (C == 1) {
+      val[0] = a.mass * wx;
+    } else {
+      const float4 u = a.val[j];
+      val[0] = u.x * wx;
+      val[1] = u.y * wx;
+      val[2] = u.z * wx;
+    }
+    const float wy0 = 1.f - f.y, wy1 = f.y, wz0 = 1.f - f.z, wz1 = f.z;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ch.v[4 * c + 0] = val[c] * wy0 * wz0;
+      ch.v[4 * c + 1] = val[c] * wy0 * wz1;
+      ch.v[4 * c + 2] = val[c] * wy1 * wz0;
+      ch.v[4 * c + 3] = val[c] * wy1 * wz1;
+    }
+  }
+}
+
+// Last lane of each run adds the run's sums to its two target rows. The accumulator is
+// private to the wavefront and, within one phase below, the tails of a chunk touch
+// distinct words, so a plain read-add-write is race-free inside a phase. Different phases
+// (and chunks) may touch the same word from different lanes: a compiler barrier keeps the
+// phases in program order, and LDS instructions of one wavefront execute in issue order,
+// so every word receives its additions in one fixed order.
+#define PMR_PHASE_FENCE() asm volatile("" ::: "memory")
+
+// Float slot of cell iz in an LDS row: plain (iz), or, for rows that the z-pass FFT then
+// transforms in place, the padded complex layout (one spare complex slot every 32 complex
+// values: real point iz is half of complex point iz / 2).
+template <bool PAD>
+__device__ __forceinline__ int row_slot(int iz) {
+  if constexpr (PAD) {
+    const int k = iz >> 1;
+    return 2 * (k + (k >> 5)) + (iz & 1);
+  }
+  return iz;
+}
+
+// acc rows: [TY][C] rows of rp floats each.
+template <int C, int TY, bool PAD = false>
+__device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, int iy0, int rp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kn = __shfl_down(ch.key, 1, 64);
+  const int ok_next = __shfl_down((int)ch.ok, 1, 64);
+  const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
+  const int iz1 = (ch.iz + 1) & (nm - 1);
+#pragma unroll
+  for (int ph = 0; ph < 4; ++ph) {
+    const int oy = ph >> 1, oz = ph & 1;
+    const int jt = ((ch.sy + oy) & (nm - 1)) - iy0;
+    PMR_PHASE_FENCE();
+    if (tail && jt >= 0 && jt < TY) {
+      float* row = acc + (size_t)jt * C * rp + row_slot<PAD>(oz ? iz1 : ch.iz);
+#pragma unroll
+      for (int c = 0; c < C; ++c) row[c * rp] = row[c * rp] + ch.v[4 * c + 2 * oy + oz];
+    }
+    PMR_PHASE_FENCE();
+  }
+}
+
+// Deposits of all particles that reach the TY target rows [iy0, iy0 + TY) of plane ix of one
+// item, into the wavefront's rows acc (zeroed by the caller): the two source planes ix - 1
+// and ix, each as one or two contiguous runs of source rows.
+template <int C, int TY, bool PAD = false>
+__device__ __forceinline__ void paint_rows(const PaintArgs& a, int item, int ix, int iy0,
+                                           float* acc, int rp) {
+  const int lane = threadIdx.x & 63;
+  const int nm = a.nm;
+  const int rows_item = item * nm * nm;
+#pragma unroll 1
+  for (int ox = 0; ox < 2; ++ox) {
+    const int sx = (ix - ox + nm) & (nm - 1);
+    const int rbase = rows_item + sx * nm;
+    // runs of source rows: [iy0 - 1, iy0 + TY - 1], split when iy0 - 1 wraps
+    int lo0 = iy0 - 1, hi0 = iy0 + TY - 1, lo1 = 1, hi1 = 0;
+    if (iy0 == 0) {
+      lo0 = 0;
+      lo1 = nm - 1;
+      hi1 = nm - 1;
+    }
+#pragma unroll 1
+    for (int run = 0; run < 2; ++run) {
+      const int lo = run == 0 ? lo0 : lo1, hi = run == 0 ? hi0 : hi1;
+      if (lo > hi) continue;
+      const uint32_t beg = a.row_start[rbase + lo], end = a.row_start[rbase + hi + 1];
+      // two chunks in flight; their deposits stay in chunk order
+#pragma unroll 1
+      for (uint32_t c0 = beg; c0 < end; c0 += 128) {
+        Chunk<C> A, Bc;
+        load_chunk<C>(a, c0 + lane, end, ox, A);
+        load_chunk<C>(a, c0 + 64 + lane, end, ox, Bc);
+        seg_scan<4 * C>(A.v, A.key);
+        seg_scan<4 * C>(Bc.v, Bc.key);
+        deposit<C, TY, PAD>(A, acc, nm, iy0, rp);
+        if (c0 + 64 < end) deposit<C, TY, PAD>(Bc, acc, nm, iy0, rp);
+      }
+    }
+  }
+}
+

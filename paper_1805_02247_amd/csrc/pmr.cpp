@@ -124,7 +124,6 @@ struct pmr_ctx {
   float4* vid;      // adjoint paint values of the next reverse step, id order [B*np3]
   float4* vstream;  // the same in sorted order [B*np3]
   uint32_t* rows_o;
-  float* dens;   // [B][nm3]
   float2* cA;    // [B][cmax]
   float2* cB;    // [B][3][cmax]
   float* psi;    // [B][3][np3]
@@ -136,7 +135,6 @@ struct pmr_ctx {
   float* rs;
   float* xbar;
   float* pbar;
-  float* Fbar;   // [B][3][nm3]
   float* dbar;   // [B][nm3]
   float* ob;     // [4][B][no3]
   double* partial;
@@ -220,7 +218,6 @@ void plan(pmr_ctx* c, Plan& P) {
   c->vid = P.take<float4>(B * c->np3);
   c->vstream = P.take<float4>(B * c->np3);
   c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
-  c->dens = P.take<float>(B * c->nm3);
   c->cA = P.take<float2>(B * c->cmax);
   c->cB = P.take<float2>(B * 3 * c->cmax);
   c->psi = P.take<float>(B * 3 * c->np3);
@@ -232,7 +229,6 @@ void plan(pmr_ctx* c, Plan& P) {
   c->rs = P.take<float>(B * c->no3);
   c->xbar = P.take<float>(B * 3 * c->np3);
   c->pbar = P.take<float>(B * 3 * c->np3);
-  c->Fbar = P.take<float>(B * 3 * c->nm3);
   c->dbar = P.take<float>(B * c->nm3);
   c->ob = P.take<float>(4 * B * c->no3);
   const size_t nred = (size_t)reduce_blocks(c->cmax > c->no3 ? c->cmax : c->no3);
@@ -335,6 +331,20 @@ FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride, size_t pitch = 0)
   m.comp_stride = comp_stride;
   m.pitch = pitch;
   return m;
+}
+
+PaintArgs paint_args(const uint32_t* keys, const float4* frac, const float4* val,
+                     const uint32_t* rows, int nm, float mass, float bias) {
+  PaintArgs a{};
+  a.keys = keys;
+  a.frac = frac;
+  a.val = val;
+  a.row_start = rows;
+  a.nm = nm;
+  a.log_nm = (int)ilog2((size_t)nm);
+  a.mass = mass;
+  a.bias = bias;
+  return a;
 }
 
 XPassArgs xargs(pmr_ctx* c, int n) {
@@ -446,13 +456,19 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
               c->frac_id, fracslot(c, fsl), c->stream);
   launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
                    c->stream);
-  {
-    ProfScope ps(c, PMR_PROF_PAINT, 24.0 * B * c->np3 + 4.0 * B * c->nm3);
-    launch_paint_mass(keyslot(c, fsl), fracslot(c, fsl), rowslot(c, fsl), B, c->nm, c->mass_m,
-                      1.f, c->dens, c->stream);
-  }
   const size_t cm = c->sm;
-  r2c_zy(c, c->nm, 1, c->dens, c->nm3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, cm, 0);
+  const FieldMap dm = fmap(1, cm, 0, spec_pitch(c->nm));
+  {
+    // density contrast painted and z-transformed in one pass (the real mesh stays in LDS)
+    ProfScope ps(c, PMR_PROF_PAINT, 24.0 * B * c->np3 + 8.0 * B * c->cm);
+    launch_paint_r2c(c->nm, 1, paint_args(keyslot(c, fsl), fracslot(c, fsl), nullptr,
+                                          rowslot(c, fsl), c->nm, c->mass_m, 1.f),
+                     B, c->cA, dm, c->stream);
+  }
+  {
+    ProfScope ps(c, PMR_PROF_YPASS, 16.0 * B * c->cm);
+    launch_ypass(c->nm, B, c->cA, dm, false, c->stream);
+  }
   XPassArgs a = xargs(c, c->nm);
   a.n_in = 1;
   a.n_out = 3;
@@ -759,12 +775,18 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const double* x = xslot(c, xs_of(c, i));
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
     launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
+    const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
     {
-      ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 12.0 * B * c->nm3);
-      launch_paint_adj3(keyslot(c, fsl), fracslot(c, fsl), c->vstream, rowslot(c, fsl), B, c->nm,
-                        c->Fbar, s);
+      // adjoint paint of the three force channels, z-transformed in the same pass
+      ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 24.0 * B * c->cm);
+      launch_paint_r2c(c->nm, 3, paint_args(keyslot(c, fsl), fracslot(c, fsl), c->vstream,
+                                            rowslot(c, fsl), c->nm, 1.f, 0.f),
+                       B, c->cB, fm3, s);
     }
-    r2c_zy(c, c->nm, 3, c->Fbar, 3 * c->nm3, c->nm3, nullptr, 1.f, 0.f, nullptr, c->cB, 3 * cm, cm);
+    {
+      ProfScope ps(c, PMR_PROF_YPASS, 3 * 16.0 * B * c->cm);
+      launch_ypass(c->nm, 3 * B, c->cB, fm3, false, s);
+    }
     XPassArgs a = xargs(c, c->nm);
     a.n_in = 3;
     a.n_out = 1;

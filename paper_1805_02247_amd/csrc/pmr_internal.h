@@ -90,6 +90,17 @@ struct FieldMap {
   }
 };
 
+// Inputs of the CIC paint kernels: the particle streams in (key, id) order and the row index.
+struct PaintArgs {
+  const uint32_t* keys;     // sorted keys
+  const float4* frac;       // sorted fractions
+  const float4* val;        // sorted values (C = 3), or nullptr (C = 1, constant mass)
+  const uint32_t* row_start;
+  int nm, log_nm;
+  float mass, bias;
+  float* out;               // [B][C][nm^3]
+};
+
 // Kinds of fused k-space operation performed in the outermost-axis pass.
 enum XOp : int {
   XOP_FWD = 0,        // forward transform only (completes an r2c); 1 in -> 1 out (spectrum)
@@ -130,6 +141,11 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
                       const float* add, hipStream_t s);
 // Inverse z pass of the three components of a vector field per item (im: 3 fields per item)
 // into one interleaved float4 mesh [item][n^3] = (f0, f1, f2, 0).
+// CIC paint of `channels` (1: mass, bias subtracted; 3: adjoint values) fused with the z pass
+// of the r2c: writes the z-transformed half spectra of the painted meshes (om: fields per
+// item = channels); the y and x passes complete the transform.
+void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2* out, FieldMap om,
+                      hipStream_t s);
 void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, float4* out,
                        size_t out_item_stride, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
