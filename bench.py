@@ -22,6 +22,57 @@ sys.path.insert(0, ROOT)
 METRIC = "PM forward+adjoint steps/s at 128^3 & 256^3; % HBM roofline; err vs FP64"
 HBM_PEAK_GBS = 8000.0
 
+# Counter summaries (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a 1 GiB copy)
+# per workload, and the kernels each profiled class consists of.
+TRAFFIC_PROFILES = {"cfg2_128": "hbm_traffic_128cube_B4_fp32.txt",
+                    "cfg3_256": "hbm_traffic_256cube_512mesh.txt"}
+CLASS_KERNELS = {
+    "paint": r"paint_r2c_kernel<1,", "paint3": r"paint_r2c_kernel<3,",
+    "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
+    "ypass": r"ypass(_reg)?_kernel<", "zpass": r"zpass_", "kick_drift": r"kick_drift_kernel",
+    "adj_gather": r"adjoint_gather_kernel",
+}
+
+
+def source_fingerprint():
+    """SHA-256 over the kernel sources; a counter summary taken from other sources is stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1805_02247_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(src, "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload, cls):
+    """HBM bytes per launch of kernel class `cls` from the committed counter summary, or None
+    when there is none or it was taken from other kernel sources."""
+    import re
+    name = TRAFFIC_PROFILES.get(workload)
+    if not name or cls not in CLASS_KERNELS:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    fp, disp, total = None, 0, 0.0
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# sources sha256:"):
+                fp = line.split(":", 1)[1].strip()
+            if line.startswith("#") or not line.strip() or line.split()[0] == "dispatches":
+                continue
+            parts = line.split(None, 3)
+            n, rd, wr, kern = int(parts[0]), float(parts[1]), float(parts[2]), parts[3]
+            if re.search(CLASS_KERNELS[cls], kern):
+                disp += n
+                total += n * (rd + wr) * 2 ** 20
+    if fp != source_fingerprint() or disp == 0:
+        return None
+    return total / disp
+
 WORKLOADS = {
     # L = 400 Mpc/h, 128^3 particles on a 128^3 mesh, 5 PM steps, 3-32-32-1 network, the
     # residual-smoothing anneal stages R_sm = 4, 2, 1, 0 Mpc/h as the 4 batch items.
@@ -280,7 +331,8 @@ def main():
     achieved = per_launch / avg_s / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": dominant, "achieved": achieved,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": None, "avg_launch_us": avg_s * 1e6, "launches": ev_n,
+                       "traffic": counter_traffic(args.workload, dominant),
+                       "avg_launch_us": avg_s * 1e6, "launches": ev_n,
                        "alg_bytes_per_launch": per_launch,
                        "share_of_step": ev_ms / (1e3 * T)}
     out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
