@@ -30,7 +30,7 @@ CLASS_KERNELS = {
     "paint": r"paint_r2c_kernel<1,", "paint3": r"paint_r2c_kernel<3,",
     "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
     "ypass": r"ypass(_reg)?_kernel<", "zpass": r"zpass_", "kick_drift": r"kick_drift_kernel",
-    "adj_gather": r"adjoint_gather_kernel",
+    "adj_gather": r"adjoint_positions_kernel", "adj_update": r"adjoint_update_kernel",
 }
 
 
@@ -291,7 +291,7 @@ def main():
     torch.cuda.synchronize()
     # the kernel class with the largest event time in one untimed gradient evaluation
     classes = ["paint", "paint3", "xpass_force", "xpass_force_adj", "ypass", "zpass",
-               "kick_drift", "adj_gather"]
+               "kick_drift", "adj_gather", "adj_update"]
     probe = {}
     for cls in classes:
         pm.profile_begin(cls)

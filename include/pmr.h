@@ -167,7 +167,8 @@ enum {
   PMR_PROF_KICK_DRIFT = 5,        /* readout + kick + drift + keys */
   PMR_PROF_PAINT3 = 6,            /* three-channel adjoint paint */
   PMR_PROF_XPASS_FORCE_ADJ = 7,   /* outermost-axis pass with the force adjoint, 3 -> 1 */
-  PMR_PROF_ADJ_GATHER = 8         /* step-adjoint gather */
+  PMR_PROF_ADJ_GATHER = 8,        /* step-adjoint position gradient (sorted-order gather) */
+  PMR_PROF_ADJ_UPDATE = 9         /* step-adjoint kick / drift transposes (id order) */
 };
 int pmr_profile_begin(pmr_ctx* ctx, int kernel_class, int max_launches);
 int pmr_profile_end(pmr_ctx* ctx, double* total_ms, long long* launches, double* alg_bytes);

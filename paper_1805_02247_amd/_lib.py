@@ -66,7 +66,7 @@ SIGNATURES = {
                              ctypes.POINTER(cd)]),
 }
 PROF = {"paint": 1, "xpass_force": 2, "ypass": 3, "zpass": 4, "kick_drift": 5, "paint3": 6,
-        "xpass_force_adj": 7, "adj_gather": 8}
+        "xpass_force_adj": 7, "adj_gather": 8, "adj_update": 9}
 
 
 def lib():

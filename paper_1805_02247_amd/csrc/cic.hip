@@ -440,65 +440,99 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   }
 }
 
+// Position gradient of the step adjoint, in sort order (the transpose of the paint, so the
+// mesh reads are as coherent as the paint's writes):
+//   g(p) = sum_cell dW(x_p - cell)/dx * (sum_a Fbar_a(p) F_a(cell) + mass * dbar(cell))
+// with the corner cell and fractions of particle p taken from its key and sorted fractions
+// (the same FP64-derived values the paint used) and Fbar(p) from the sorted adjoint-paint
+// stream. Written to g_out[id] (id order) for the update below.
+struct AdjPosArgs {
+  const uint32_t* keys;  // sorted keys
+  const float4* frac;    // sorted fractions
+  const float4* fbar;    // sorted Fbar (nullable: final-paint adjoint, no force term)
+  const uint32_t* ids;   // sorted ids
+  const float4* F;       // interleaved force mesh at x_i [B][nm^3] (nullable with fbar)
+  const float* dbar;     // density adjoint mesh [B][nm^3]
+  float4* g_out;         // [B * Np^3], id order
+  int nm, log_nm, total;
+  float scale, mass;
+};
+
+__global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
+  const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
+  if (j >= a.total) return;
+  const uint32_t key = a.keys[j];
+  const float4 fr = a.frac[j];
+  const int nm = a.nm, lg = a.log_nm;
+  const uint32_t item = key >> (3 * lg);
+  const uint32_t i0[3] = {(key >> (2 * lg)) & (uint32_t)(nm - 1), (key >> lg) & (uint32_t)(nm - 1),
+                          key & (uint32_t)(nm - 1)};
+  const uint32_t i1[3] = {(i0[0] + 1) & (uint32_t)(nm - 1), (i0[1] + 1) & (uint32_t)(nm - 1),
+                          (i0[2] + 1) & (uint32_t)(nm - 1)};
+  const float f[3] = {fr.x, fr.y, fr.z};
+  const size_t cells = (size_t)1 << (3 * lg);
+  float fb[3] = {0.f, 0.f, 0.f};
+  if (a.fbar) {
+    const float4 v = a.fbar[j];
+    fb[0] = v.x;
+    fb[1] = v.y;
+    fb[2] = v.z;
+  }
+  const float4* F = a.F ? a.F + (size_t)item * cells : nullptr;
+  const float* D = a.dbar + (size_t)item * cells;
+  const float s = a.scale;
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+    const float wx = ox ? f[0] : 1.f - f[0];
+    const float wy = oy ? f[1] : 1.f - f[1];
+    const float wz = oz ? f[2] : 1.f - f[2];
+    const float dx = ox ? s : -s, dy = oy ? s : -s, dz = oz ? s : -s;
+    const uint32_t ci = ((ox ? i1[0] : i0[0]) * (uint32_t)nm + (oy ? i1[1] : i0[1])) * (uint32_t)nm +
+                        (oz ? i1[2] : i0[2]);
+    float v = a.mass * D[ci];
+    if (F) {
+      const float4 fv = F[ci];
+      v += fb[0] * fv.x + fb[1] * fv.y + fb[2] * fv.z;
+    }
+    gx += dx * wy * wz * v;
+    gy += wx * dy * wz * v;
+    gz += wx * wy * dz * v;
+  }
+  a.g_out[a.ids[j]] = make_float4(gx, gy, gz, 0.f);
+}
+
 struct AdjArgs {
-  const double* x;     // positions x_i
-  float* xbar;         // in: xbar_{i+1}; out: xbar_i
-  float* pbar;         // in: pbar_{i+1/2}; out: pbar_{i-1/2}
-  const float4* F;     // interleaved force mesh at x_i [B][nm^3] (nullable: final-paint adjoint)
-  const float* dbar;   // density adjoint mesh [B][nm^3]
-  int log_np3, nm, total;
-  double scale;
-  float kick, drift, mass;
-  int final_mode;      // 1: xbar = mass * grad(dbar), pbar = 0
-  float4* vnext;       // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
+  float* xbar;          // in: xbar_{i+1}; out: xbar_i
+  float* pbar;          // in: pbar_{i+1/2}; out: pbar_{i-1/2}
+  const float4* gpos;   // position gradient of the step (id order)
+  int log_np3, total;
+  float kick, drift;
+  int final_mode;       // 1: xbar = gpos, pbar = 0
+  float4* vnext;        // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
   float kick_next, drift_next;  // reverse step (its adjoint paint values), id order
 };
 
-// Step adjoint (reverse of kick then drift):
-//   pbar' = pbar + drift * xbar;  Fbar = kick * pbar'
-//   xbar' = xbar + sum_cell dW(x - cell)/dx * (sum_a Fbar_a F_a(cell) + mass * dbar(cell))
-__global__ __launch_bounds__(TB) void adjoint_gather_kernel(AdjArgs a) {
+// Step adjoint (reverse of kick then drift), with the position gradient g from above:
+//   pbar' = pbar + drift * xbar;  xbar' = xbar + g
+__global__ __launch_bounds__(TB) void adjoint_update_kernel(AdjArgs a) {
   const int g = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (g >= a.total) return;
   const size_t np3 = (size_t)1 << a.log_np3;
   const int item = g >> a.log_np3;
   const size_t id = g & (np3 - 1);
   const size_t pi = (size_t)item * 3 * np3 + id;
-  double xyz[3] = {a.x[pi], a.x[pi + np3], a.x[pi + 2 * np3]};
-  const int nm = a.nm;
-  const Corner c = corner_of(xyz, a.scale, nm);
-  const size_t cells = (size_t)nm * nm * nm;
-  float pb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, fb[3] = {0.f, 0.f, 0.f};
+  float pb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f};
   if (!a.final_mode) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       xb[q] = a.xbar[pi + q * np3];
       pb[q] = a.pbar[pi + q * np3] + a.drift * xb[q];
-      fb[q] = a.kick * pb[q];
     }
   }
-  const float4* F = a.F ? a.F + (size_t)item * cells : nullptr;
-  const float* D = a.dbar + (size_t)item * cells;
-  const float s = (float)a.scale;
-  float gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
-    const float wx = ox ? c.f[0] : 1.f - c.f[0];
-    const float wy = oy ? c.f[1] : 1.f - c.f[1];
-    const float wz = oz ? c.f[2] : 1.f - c.f[2];
-    const float dx = ox ? s : -s, dy = oy ? s : -s, dz = oz ? s : -s;
-    const uint32_t ci = cidx(c, ox, oy, oz, nm);
-    float v = a.mass * D[ci];
-    if (F) {
-      const float4 f = F[ci];
-      v += fb[0] * f.x + fb[1] * f.y + fb[2] * f.z;
-    }
-    gx += dx * wy * wz * v;
-    gy += wx * dy * wz * v;
-    gz += wx * wy * dz * v;
-  }
-  const float xn[3] = {xb[0] + gx, xb[1] + gy, xb[2] + gz};
+  const float4 gp = a.gpos[g];
+  const float xn[3] = {xb[0] + gp.x, xb[1] + gp.y, xb[2] + gp.z};
   a.xbar[pi] = xn[0];
   a.xbar[pi + np3] = xn[1];
   a.xbar[pi + 2 * np3] = xn[2];
@@ -709,28 +743,43 @@ void launch_kick_drift(const double* x, double* x_next, float* p, const float4* 
   kick_drift_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
-void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float4* F,
-                           const float* dbar, int batch, int log_np3, int nm, double box,
-                           float kick, float drift, float mass, int final_mode, float4* vnext,
-                           float kick_next, float drift_next, hipStream_t s) {
+void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
+                              const uint32_t* ids, const float4* F, const float* dbar, int total,
+                              int nm, double box, float mass, float4* g_out, hipStream_t s) {
+  AdjPosArgs a{};
+  a.keys = keys;
+  a.frac = frac;
+  a.fbar = fbar;
+  a.ids = ids;
+  a.F = F;
+  a.dbar = dbar;
+  a.g_out = g_out;
+  a.nm = nm;
+  int l = 0;
+  while ((1 << l) < nm) ++l;
+  a.log_nm = l;
+  a.total = total;
+  a.scale = (float)((double)nm / box);
+  a.mass = mass;
+  adjoint_positions_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(a);
+}
+
+void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
+                           float kick, float drift, int final_mode, float4* vnext, float kick_next,
+                           float drift_next, hipStream_t s) {
   AdjArgs a{};
+  a.xbar = xbar;
+  a.pbar = pbar;
+  a.gpos = gpos;
+  a.log_np3 = log_np3;
+  a.total = batch << log_np3;
+  a.kick = kick;
+  a.drift = drift;
+  a.final_mode = final_mode;
   a.vnext = vnext;
   a.kick_next = kick_next;
   a.drift_next = drift_next;
-  a.x = x;
-  a.xbar = xbar;
-  a.pbar = pbar;
-  a.F = F;
-  a.dbar = dbar;
-  a.log_np3 = log_np3;
-  a.nm = nm;
-  a.total = batch << log_np3;
-  a.scale = (double)nm / box;
-  a.kick = kick;
-  a.drift = drift;
-  a.mass = mass;
-  a.final_mode = final_mode;
-  adjoint_gather_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
+  adjoint_update_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,

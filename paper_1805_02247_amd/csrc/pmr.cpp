@@ -123,6 +123,7 @@ struct pmr_ctx {
   float4* frac_id;  // CIC fractions of the current positions, id order [B*np3]
   float4* vid;      // adjoint paint values of the next reverse step, id order [B*np3]
   float4* vstream;  // the same in sorted order [B*np3]
+  float4* gpos;     // position gradient of the current step adjoint, id order [B*np3]
   uint32_t* rows_o;
   float2* cA;    // [B][cmax]
   float2* cB;    // [B][3][cmax]
@@ -217,6 +218,7 @@ void plan(pmr_ctx* c, Plan& P) {
   c->frac_id = P.take<float4>(B * c->np3);
   c->vid = P.take<float4>(B * c->np3);
   c->vstream = P.take<float4>(B * c->np3);
+  c->gpos = P.take<float4>(B * c->np3);
   c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
   c->cA = P.take<float2>(B * c->cmax);
   c->cB = P.take<float2>(B * 3 * c->cmax);
@@ -746,10 +748,11 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     c2r_yz(c, c->no, 1, c->cA, co, 0, dbar_f, no3, 0, o0);
   }
   // H14: final-paint adjoint -> xbar_n, pbar = 0
-  const double* xn = xslot(c, final_xslot(c));
-  launch_adjoint_gather(xn, c->xbar, c->pbar, nullptr, dbar_f, B, c->log_np3, c->no, c->cfg.box,
-                        0.f, 0.f, c->mass_o, 1, c->vid, (float)c->kick[c->n - 1],
-                        (float)c->drift[c->n - 1], s);
+  // (the sort of the final positions on the output mesh is still held from the forward)
+  launch_adjoint_positions(c->keys_sorted, c->frac_o, nullptr, c->ids_o, nullptr, dbar_f,
+                           (int)(B * c->np3), c->no, c->cfg.box, c->mass_o, c->gpos, s);
+  launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, 0.f, 0.f, 1, c->vid,
+                        (float)c->kick[c->n - 1], (float)c->drift[c->n - 1], s);
   // H15: reverse PM steps (recomputing segments from checkpoints when needed)
   const size_t cm = c->sm;
   const double scale_m = (double)c->nm / c->cfg.box;
@@ -772,7 +775,6 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       resident_lo = j;
     }
     const int fsl = fs_of(c, i);
-    const double* x = xslot(c, xs_of(c, i));
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
     launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
     const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
@@ -800,10 +802,17 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     }
     c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
     {
-      ProfScope ps(c, PMR_PROF_ADJ_GATHER, (24.0 + 24.0 + 24.0) * B * c->np3 + 16.0 * B * c->nm3);
-      launch_adjoint_gather(x, c->xbar, c->pbar, fslot(c, fsl), c->dbar, B, c->log_np3, c->nm,
-                            c->cfg.box, K, Dr, c->mass_m, 0, i > 0 ? c->vid : nullptr,
-                            i > 0 ? (float)c->kick[i - 1] : 0.f,
+      // sorted keys, fractions, Fbar and ids in; F and dbar gathered; g out
+      ProfScope ps(c, PMR_PROF_ADJ_GATHER, 56.0 * B * c->np3 + 20.0 * B * c->nm3);
+      launch_adjoint_positions(keyslot(c, fsl), fracslot(c, fsl), c->vstream, idslot(c, fsl),
+                               fslot(c, fsl), c->dbar, (int)(B * c->np3), c->nm, c->cfg.box,
+                               c->mass_m, c->gpos, s);
+    }
+    {
+      // xbar, pbar and g in; xbar, pbar and the next paint values out
+      ProfScope ps(c, PMR_PROF_ADJ_UPDATE, (i > 0 ? 80.0 : 64.0) * B * c->np3);
+      launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, K, Dr, 0,
+                            i > 0 ? c->vid : nullptr, i > 0 ? (float)c->kick[i - 1] : 0.f,
                             i > 0 ? (float)c->drift[i - 1] : 0.f, s);
     }
   }

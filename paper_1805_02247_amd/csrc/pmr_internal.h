@@ -184,10 +184,17 @@ void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* v
 void launch_kick_drift(const double* x, double* x_next, float* p, const float4* F, uint32_t* keys,
                        float4* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s);
-void launch_adjoint_gather(const double* x, float* xbar, float* pbar, const float4* F,
-                           const float* dbar, int batch, int log_np3, int nm, double box,
-                           float kick, float drift, float mass, int final_mode, float4* vnext,
-                           float kick_next, float drift_next, hipStream_t s);
+// Position gradient of a step adjoint (or of the final paint: fbar = F = nullptr), computed in
+// sort order and written to g_out in id order:
+//   g = sum_corners dW/dx * (Fbar . F(corner) + mass * dbar(corner)).
+void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
+                              const uint32_t* ids, const float4* F, const float* dbar, int total,
+                              int nm, double box, float mass, float4* g_out, hipStream_t s);
+// Kick and drift transposes with that gradient: pbar += drift xbar; xbar += g (final mode:
+// xbar = g, pbar = 0); optionally the next reverse step's paint values into vnext.
+void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
+                           float kick, float drift, int final_mode, float4* vnext, float kick_next,
+                           float drift_next, hipStream_t s);
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
                     double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
                     int key_nm, hipStream_t s);
