@@ -61,9 +61,13 @@ __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total
 }
 
 // ---------------------------------------------------------------- radix sort
-constexpr int SORT_WAVES = 4;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_WAVES * PMR_WAVE * SORT_ITEMS;  // 4096 keys per block
+#ifndef PMR_SORT_WAVES
+#define PMR_SORT_WAVES 8
+#endif
+constexpr int SORT_TILE = 4096;  // keys per tile
+constexpr int SORT_WAVES = PMR_SORT_WAVES;
+constexpr int SORT_TB = SORT_WAVES * PMR_WAVE;
+constexpr int SORT_ITEMS = SORT_TILE / SORT_TB;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = threadIdx.x & 63;
@@ -106,10 +110,11 @@ __global__ __launch_bounds__(TB) void radix_hist_kernel(const uint32_t* __restri
 // to its global range [offset[digit][block], ...) contiguously.
 // ids_in == nullptr means identity payload (id = index).
 template <int D>
-__global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
+__global__ __launch_bounds__(SORT_TB) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ ids_in,
                                                            int n, int shift,
                                                            const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ digit_total,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ ids_out,
                                                            const float4* __restrict__ pay_in,
@@ -120,12 +125,15 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
   __shared__ uint32_t gbase[NBK];    // global start of each digit for this block
   __shared__ uint32_t skey[SORT_TILE];
   __shared__ uint32_t sid[SORT_TILE];
-  __shared__ uint32_t wsum[TB / 64];
+  __shared__ uint32_t wsum[2 * SORT_WAVES];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < SORT_WAVES * NBK; i += TB) (&cnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < SORT_WAVES * NBK; i += SORT_TB) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const size_t tile0 = (size_t)blockIdx.x * SORT_TILE;
+  // consecutive tiles on one XCD: their runs of each digit are adjacent in the output, so
+  // the partial lines they write meet in one L2
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const size_t tile0 = (size_t)tile * SORT_TILE;
   const size_t base = tile0 + (size_t)w * PMR_WAVE * SORT_ITEMS;
   uint32_t key[SORT_ITEMS], id[SORT_ITEMS], rank[SORT_ITEMS];
   const uint64_t lt = lanemask_lt();
@@ -148,11 +156,12 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
   }
   __syncthreads();
   // per digit: exclusive prefix over waves, and the block total
-  uint32_t tot_local[(NBK + TB - 1) / TB];
+  constexpr int Q = (NBK + SORT_TB - 1) / SORT_TB;
+  uint32_t tot_local[Q], dig_tot[Q];
 #pragma unroll
-  for (int q = 0; q < (NBK + TB - 1) / TB; ++q) {
-    const int d = threadIdx.x + q * TB;
-    uint32_t run = 0;
+  for (int q = 0; q < Q; ++q) {
+    const int d = threadIdx.x + q * SORT_TB;
+    uint32_t run = 0, dt = 0;
     if (d < NBK) {
 #pragma unroll
       for (int ww = 0; ww < SORT_WAVES; ++ww) {
@@ -160,35 +169,53 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
         cnt[ww][d] = run;
         run += c;
       }
-      gbase[d] = offsets[(size_t)d * gridDim.x + blockIdx.x];
+      gbase[d] = offsets[(size_t)d * gridDim.x + tile];
+      dt = digit_total[d];
     }
     tot_local[q] = run;
+    dig_tot[q] = dt;
   }
-  // exclusive scan of the block totals over digits (digit d = thread + q * TB)
+  // exclusive scans over digits (digit d = thread + q * SORT_TB) of the block totals (start
+  // of each digit in the tile) and of the global digit totals (start of each digit's range)
   {
-    uint32_t carry = 0;
+    uint32_t carry = 0, gcarry = 0;
 #pragma unroll
-    for (int q = 0; q < (NBK + TB - 1) / TB; ++q) {
-      const uint32_t v = tot_local[q];
-      // wave-level inclusive scan
-      uint32_t x = v;
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t v = tot_local[q], gv = dig_tot[q];
+      // wave-level inclusive scans
+      uint32_t x = v, gx = gv;
 #pragma unroll
       for (int dd = 1; dd < 64; dd <<= 1) {
         const uint32_t y = __shfl_up(x, dd, 64);
-        if (lane >= dd) x += y;
+        const uint32_t gy = __shfl_up(gx, dd, 64);
+        if (lane >= dd) {
+          x += y;
+          gx += gy;
+        }
       }
-      if (lane == 63) wsum[w] = x;
+      if (lane == 63) {
+        wsum[w] = x;
+        wsum[SORT_WAVES + w] = gx;
+      }
       __syncthreads();
-      uint32_t wpre = 0, total = 0;
+      uint32_t wpre = 0, total = 0, gpre = 0, gtotal = 0;
 #pragma unroll
-      for (int ww = 0; ww < TB / 64; ++ww) {
-        const uint32_t sv = wsum[ww];
-        if (ww < w) wpre += sv;
+      for (int ww = 0; ww < SORT_WAVES; ++ww) {
+        const uint32_t sv = wsum[ww], gs = wsum[SORT_WAVES + ww];
+        if (ww < w) {
+          wpre += sv;
+          gpre += gs;
+        }
         total += sv;
+        gtotal += gs;
       }
-      const int d = threadIdx.x + q * TB;
-      if (d < NBK) dstart[d] = carry + wpre + x - v;
+      const int d = threadIdx.x + q * SORT_TB;
+      if (d < NBK) {
+        dstart[d] = carry + wpre + x - v;
+        gbase[d] += gcarry + gpre + gx - gv;
+      }
       carry += total;
+      gcarry += gtotal;
       __syncthreads();
     }
   }
@@ -206,7 +233,7 @@ __global__ __launch_bounds__(TB) void radix_scatter_kernel(const uint32_t* __res
   }
   __syncthreads();
   const int count = (int)min((size_t)SORT_TILE, (size_t)n - tile0);
-  for (int e = threadIdx.x; e < count; e += TB) {
+  for (int e = threadIdx.x; e < count; e += SORT_TB) {
     const uint32_t k = skey[e];
     const uint32_t d = (k >> shift) & (NBK - 1);
     const uint32_t dst = gbase[d] + (uint32_t)e - dstart[d];
@@ -238,51 +265,33 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return incl - v;
 }
 
-__global__ __launch_bounds__(TB) void scan_reduce_kernel(const uint32_t* __restrict__ in, size_t n,
-                                                         uint32_t* __restrict__ sums) {
+// Per digit (one block each): exclusive scan of the tile histograms over tiles, giving each
+// tile's start within the digit's range, and the digit's total.
+__global__ __launch_bounds__(TB) void digit_scan_kernel(const uint32_t* __restrict__ hist, int nb,
+                                                        uint32_t* __restrict__ offs,
+                                                        uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t sh[TB];
-  const size_t base = (size_t)blockIdx.x * SCAN_TILE;
-  uint32_t s = 0;
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const size_t j = base + (size_t)threadIdx.x * SCAN_ITEMS + i;
-    if (j < n) s += in[j];
-  }
-  uint32_t tot;
-  block_exclusive_scan(s, sh, &tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-// Single block: exclusive scan of `n` sums in place (n small).
-__global__ __launch_bounds__(TB) void scan_small_kernel(uint32_t* __restrict__ sums, int n) {
-  __shared__ uint32_t sh[TB];
+  const size_t row = (size_t)blockIdx.x * nb;
   uint32_t carry = 0;
-  for (int base = 0; base < n; base += TB) {
-    const int j = base + threadIdx.x;
-    const uint32_t v = j < n ? sums[j] : 0u;
+  for (int b0 = 0; b0 < nb; b0 += SCAN_TILE) {
+    const int t0 = b0 + threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      v[i] = t0 + i < nb ? hist[row + t0 + i] : 0u;
+      sum += v[i];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, sh, &tot);
-    if (j < n) sums[j] = carry + ex;
+    uint32_t run = carry + block_exclusive_scan(sum, sh, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      if (t0 + i < nb) offs[row + t0 + i] = run;
+      run += v[i];
+    }
     carry += tot;
   }
-}
-
-__global__ __launch_bounds__(TB) void scan_down_kernel(const uint32_t* __restrict__ in, size_t n,
-                                                       const uint32_t* __restrict__ sums,
-                                                       uint32_t* __restrict__ out) {
-  __shared__ uint32_t sh[TB];
-  const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-  uint32_t v[SCAN_ITEMS];
-  uint32_t s = 0;
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0u;
-    s += v[i];
-  }
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, sh, &tot) + sums[blockIdx.x];
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    if (base + i < n) out[base + i] = run;
-    run += v[i];
-  }
+  if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
 // ---------------------------------------------------------------- row starts
@@ -583,23 +592,19 @@ size_t sort_scratch_bytes(int n, int key_bits) {
   const int D = (key_bits + passes - 1) / passes;
   const size_t nb = (size_t)((n + SORT_TILE - 1) / SORT_TILE);
   const size_t hist = nb << D;
-  const size_t sums = (hist + SCAN_TILE - 1) / SCAN_TILE;
-  // keys/ids ping-pong buffers (2 x n), histogram, offsets, block sums
-  return (2 * (size_t)n + 2 * hist + sums + 64) * sizeof(uint32_t);
+  // keys/ids ping-pong buffers (2 x n), histogram, offsets, digit totals
+  return (2 * (size_t)n + 2 * hist + ((size_t)1 << D) + 64) * sizeof(uint32_t);
 }
 
 template <int D>
 static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
-                      int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* sums,
+                      int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* dtot,
                       const float4* pin, float4* pout, hipStream_t s) {
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
-  const size_t hn = (size_t)nb << D;
   radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
-  const int ns = (int)((hn + SCAN_TILE - 1) / SCAN_TILE);
-  scan_reduce_kernel<<<ns, TB, 0, s>>>(hist, hn, sums);
-  scan_small_kernel<<<1, TB, 0, s>>>(sums, ns);
-  scan_down_kernel<<<ns, TB, 0, s>>>(hist, hn, sums, offs);
-  radix_scatter_kernel<D><<<nb, TB, 0, s>>>(kin, iin, n, shift, offs, kout, iout, pin, pout);
+  digit_scan_kernel<<<1 << D, TB, 0, s>>>(hist, nb, offs, dtot);
+  radix_scatter_kernel<D><<<nb, SORT_TB, 0, s>>>(kin, iin, n, shift, offs, dtot, kout, iout, pin,
+                                                  pout);
 }
 
 // Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
@@ -616,7 +621,7 @@ void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
   uint32_t* ia = ka + n;
   uint32_t* hist = ia + n;
   uint32_t* offs = hist + hn;
-  uint32_t* sums = offs + hn;
+  uint32_t* dtot = offs + hn;
   const uint32_t* kin = keys_io;
   const uint32_t* iin = nullptr;
   for (int p = 0; p < passes; ++p) {
@@ -629,7 +634,7 @@ void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
     switch (D) {
 #define CASE(DD) \
   case DD:                                                                                  \
-    sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, sums, last ? pay_in : nullptr,      \
+    sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, dtot, last ? pay_in : nullptr,      \
                   last ? pay_out : nullptr, s);                                                \
     break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)

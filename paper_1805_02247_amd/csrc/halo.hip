@@ -149,11 +149,12 @@ struct MxF32 {
   __device__ static elem cvt(float v) { return v; }
 };
 
-// Compact block of the FP32 weights the matrix-core kernels keep in LDS: W1[H][3], b1[H],
-// b2[H], W3[H], b3.
+// Compact block of the FP32 weights the matrix-core kernels keep in LDS, per neuron:
+// (W1[k][0..2], b1[k]) as one float4 at 4 k, then (b2[u], W3[u]) as one float2 at 4 H + 2 u,
+// then b3.
 template <int H>
 struct SOff {
-  static constexpr int W1 = 0, B1 = 3 * H, B2 = 4 * H, W3 = 5 * H, B3 = 6 * H, SIZE = 6 * H + 1;
+  static constexpr int L1 = 0, L2 = 4 * H, B3 = 6 * H, SIZE = 6 * H + 1;
 };
 
 template <int H>
@@ -161,13 +162,43 @@ __device__ __forceinline__ void load_small_weights(float* sw, const float* __res
   using O = WOff<H>;
   for (int i = threadIdx.x; i < SOff<H>::SIZE; i += TB) {
     float v;
-    if (i < 4 * H) v = w[i];  // W1 and b1 sit at the same offsets in both blocks
-    else if (i < 5 * H) v = w[O::B2 + (i - 4 * H)];
-    else if (i < 6 * H) v = w[O::W3 + (i - 5 * H)];
-    else v = w[O::B3];
+    if (i < 4 * H) {
+      const int k = i >> 2, e = i & 3;
+      v = e < 3 ? w[O::W1 + 3 * k + e] : w[O::B1 + k];
+    } else if (i < 6 * H) {
+      const int u = (i - 4 * H) >> 1;
+      v = (i & 1) ? w[O::W3 + u] : w[O::B2 + u];
+    } else {
+      v = w[O::B3];
+    }
     sw[i] = v;
   }
   __syncthreads();
+}
+
+template <int H>
+__device__ __forceinline__ float4 l1_row(const float* sw, int k) {
+  return *reinterpret_cast<const float4*>(sw + SOff<H>::L1 + 4 * k);
+}
+template <int H>
+__device__ __forceinline__ float2 l2_row(const float* sw, int u) {
+  return *reinterpret_cast<const float2*>(sw + SOff<H>::L2 + 2 * u);
+}
+
+// Where the register budget is tight (the BF16 network, whose vector work bounds it, and
+// H = 64), the per-neuron weights are read from LDS where they are used rather than held in
+// registers across the group loop (an opaque zero offset keeps the compiler from hoisting
+// them), so that more waves stay resident. The FP32 network at H <= 32 is bound by its
+// matrix-core work and keeps them in registers.
+template <class P, int H>
+__device__ __forceinline__ const float* lds_fence(const float* sw) {
+  if constexpr (sizeof(typename P::elem) == 2 || H >= 64) {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return sw + z;
+  } else {
+    return sw;
+  }
 }
 
 // BF16 copies of W2 (row-major [n][k]) and W2^T, placed after the FP32 block.
@@ -191,97 +222,118 @@ __global__ void mlp_prepare_bf16_kernel(float* w) {
   w2t[k * H + n] = (__bf16)v;
 }
 
-__device__ __forceinline__ float group16_sum(float v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
+// Row blocks of 16 voxels a wavefront processes at a time.
+constexpr int MFMA_MB = 2;
+
+// Transposed products: voxels are the N (column) dimension of both H x H products, so the
+// activations of a voxel stay in the lanes of its column c = l % 16 from the inputs to the
+// outputs. The C layout gives lane group g = l / 16 the neurons 16 q + 4 g + i (q < H / 16,
+// i < 4); the K slots (instruction kb, element j) of a product are mapped onto that same set,
+//   slot t = kb J + j  ->  neuron 16 (t / 4) + 4 g + t % 4,
+// so the accumulators of one product are the B fragments of the next with no data movement,
+// and the layer-1 ReLU masks sit in the lanes of the layer-1 adjoint. Sums over neurons are
+// in-lane partial sums plus two cross-group shuffles.
+__device__ __forceinline__ int slot_neuron(int t, int g) { return 16 * (t >> 2) + 4 * g + (t & 3); }
+
+template <class P>
+__device__ __forceinline__ void put(typename P::frag& f, int j, typename P::elem v) {
+  if constexpr (P::J == 1) f = v;
+  else f[j] = v;
+}
+
+__device__ __forceinline__ float group_sum4(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
 
-// Row blocks of 16 voxels a wavefront processes at a time (4 VGPRs of accumulator per 16x16
-// output block, so fewer blocks keep more waves resident).
-constexpr int MFMA_MB = 2;
-
-// h1 fragments (A layout) for the MB row blocks of this wave (zero past the end).
-template <class P, int H, int MB>
-__device__ __forceinline__ void h1_fragments(const float* sw, const float* __restrict__ d0,
-                                             const float* __restrict__ d1,
-                                             const float* __restrict__ d2, size_t v0, size_t n,
-                                             typename P::frag (&a)[MB][H / P::KS]) {
-  using S = SOff<H>;
-  const int l = threadIdx.x & 63;
+// A fragments of W2 (rows: output neurons of block r; K: hidden units in slot order), or of
+// W2^T (rows: hidden units of block r; K: output neurons in slot order). w2 is row-major
+// [out][in] in the element type of P.
+template <class P, int H, bool T>
+__device__ __forceinline__ void load_w2_frags(const typename P::elem* __restrict__ w2,
+                                              typename P::frag (&a)[H / 16][H / P::KS]) {
+  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    const size_t v = v0 + mb * 16 + (l & 15);
-    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-    if (v < n) {
-      f0 = d0[v];
-      f1 = d1[v];
-      f2 = d1[v] - d2[v];
-    }
+  for (int r = 0; r < H / 16; ++r)
 #pragma unroll
-    for (int kb = 0; kb < H / P::KS; ++kb) {
+    for (int kb = 0; kb < H / P::KS; ++kb)
 #pragma unroll
       for (int j = 0; j < P::J; ++j) {
-        const int k = kb * P::KS + P::J * (l >> 4) + j;
-        const float h = fmaxf(sw[S::W1 + 3 * k] * f0 + sw[S::W1 + 3 * k + 1] * f1 +
-                                  sw[S::W1 + 3 * k + 2] * f2 + sw[S::B1 + k],
-                              0.f);
-        P::set(a[mb][kb], j, h);
+        const int u = slot_neuron(kb * P::J + j, g), row = 16 * r + c;
+        put<P>(a[r][kb], j, T ? w2[(size_t)u * H + row] : w2[(size_t)row * H + u]);
       }
-    }
+}
+
+// Raw inputs (d0, d1, d2) of the MB voxel columns of a group; past the end the last voxel is
+// read (its results are not stored).
+template <int MB>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ d0,
+                                            const float* __restrict__ d1,
+                                            const float* __restrict__ d2, size_t v0, size_t n,
+                                            float (&in)[MB][3]) {
+  const int c = threadIdx.x & 15;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    size_t v = v0 + 16 * mb + c;
+    v = v < n ? v : n - 1;
+    in[mb][0] = d0[v];
+    in[mb][1] = d1[v];
+    in[mb][2] = d2[v];
   }
 }
 
-// B fragments of a row-major [n][k] matrix m with row pitch RP (B[k][n] = m[n][k]).
-template <class P, int H, int RP = H>
-__device__ __forceinline__ void load_b(const typename P::elem* __restrict__ m,
-                                       typename P::frag (&b)[H / P::KS][H / 16]) {
-  const int l = threadIdx.x & 63;
+// Layer 1 as B fragments (K slots = hidden units, N = voxels) and its ReLU mask (bit t).
+template <class P, int H>
+__device__ __forceinline__ void h1_frags(const float* sw, const float (&in)[3],
+                                         typename P::frag (&b)[H / P::KS], uint32_t& mask) {
+  const int g = (threadIdx.x & 63) >> 4;
+  const float f0 = in[0], f1 = in[1], f2 = in[1] - in[2];
+  mask = 0;
 #pragma unroll
   for (int kb = 0; kb < H / P::KS; ++kb)
 #pragma unroll
-    for (int nb = 0; nb < H / 16; ++nb)
-      b[kb][nb] = *reinterpret_cast<const typename P::frag*>(
-          m + (size_t)(nb * 16 + (l & 15)) * RP + kb * P::KS + P::J * (l >> 4));
-}
-
-template <class P, int H, int MB>
-__device__ __forceinline__ void mfma_layer(const typename P::frag (&a)[MB][H / P::KS],
-                                           const typename P::frag (&b)[H / P::KS][H / 16],
-                                           floatx4_t (&c)[MB][H / 16]) {
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < H / 16; ++nb) {
-      floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kb = 0; kb < H / P::KS; ++kb) acc = P::mma(a[mb][kb], b[kb][nb], acc);
-      c[mb][nb] = acc;
+    for (int j = 0; j < P::J; ++j) {
+      const int t = kb * P::J + j, k = slot_neuron(t, g);
+      const float4 r = l1_row<H>(sw, k);
+      const float a1 = r.x * f0 + r.y * f1 + r.z * f2 + r.w;
+      P::set(b[kb], j, fmaxf(a1, 0.f));
+      mask |= (a1 > 0.f ? 1u : 0u) << t;
     }
 }
 
-// y for the 4 rows (4 (l/16) + i) of row block mb, on every lane of the 16-lane group.
-template <int H, int MB>
-__device__ __forceinline__ void layer3(const float* sw, const floatx4_t (&c)[MB][H / 16], int mb,
-                                       float (&y)[4]) {
-  using S = SOff<H>;
-  const int l = threadIdx.x & 63;
+// acc[r] = sum_kb A[r][kb] B[kb] (16 x 16 blocks r of the output neurons, one voxel block).
+template <class P, int H>
+__device__ __forceinline__ void product(const typename P::frag (&a)[H / 16][H / P::KS],
+                                        const typename P::frag (&b)[H / P::KS],
+                                        floatx4_t (&acc)[H / 16]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float p = 0.f;
+  for (int r = 0; r < H / 16; ++r) {
+    floatx4_t x = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int nb = 0; nb < H / 16; ++nb) {
-      const int nn = nb * 16 + (l & 15);
-      p += sw[S::W3 + nn] * fmaxf(c[mb][nb][i] + sw[S::B2 + nn], 0.f);
-    }
-    y[i] = group16_sum(p) + sw[S::B3];
+    for (int kb = 0; kb < H / P::KS; ++kb) x = P::mma(a[r][kb], b[kb], x);
+    acc[r] = x;
   }
 }
 
-// W2 (row-major [n][k]) and W2^T in the element type of P: the BF16 copies after the FP32
-// block, or (FP32) the block's own W2 and a transposed copy made in LDS by the caller.
+// y = W3 relu(a2 + b2) + b3 for the voxel of this lane's column (on all four lane groups).
+template <int H>
+__device__ __forceinline__ float out_layer(const float* sw, const floatx4_t (&acc)[H / 16]) {
+  using S = SOff<H>;
+  const int g = (threadIdx.x & 63) >> 4;
+  float p = 0.f;
+#pragma unroll
+  for (int q = 0; q < H / 16; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float2 r = l2_row<H>(sw, 16 * q + 4 * g + i);
+      p += r.y * fmaxf(acc[q][i] + r.x, 0.f);
+    }
+  return group_sum4(p) + sw[S::B3];
+}
+
+// W2 in the element type of P, row-major [out][in]: the BF16 copy after the FP32 block, or
+// (FP32) the block's own W2.
 template <class P, int H>
 __device__ __forceinline__ const typename P::elem* w2_rows(const float* w) {
   if constexpr (sizeof(typename P::elem) == 2)
@@ -291,7 +343,8 @@ __device__ __forceinline__ const typename P::elem* w2_rows(const float* w) {
 }
 
 // Persistent: each wavefront walks groups of 16 MB voxels (wave, wave + all waves, ...) with
-// the small FP32 weights in LDS and the W2 fragments in registers, loaded once.
+// the small FP32 weights in LDS and the W2 fragments in registers, loaded once; the inputs
+// of the next group are fetched while the current one is computed.
 template <class P, int H>
 __global__ __launch_bounds__(TB) void mlp_fwd_mx_kernel(const float* __restrict__ d0,
                                                         const float* __restrict__ d1,
@@ -300,29 +353,36 @@ __global__ __launch_bounds__(TB) void mlp_fwd_mx_kernel(const float* __restrict_
                                                         float* __restrict__ mass) {
   using S = SOff<H>;
   constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
-  __shared__ float sw[S::SIZE];
+  __shared__ __attribute__((aligned(16))) float sw[S::SIZE];
   load_small_weights<H>(sw, w);
+  if (n == 0) return;
   const int l = threadIdx.x & 63;
-  typename P::frag b[H / P::KS][H / 16];
-  load_b<P, H>(w2_rows<P, H>(w), b);
+  typename P::frag aw[H / 16][H / P::KS];
+  load_w2_frags<P, H, false>(w2_rows<P, H>(w), aw);
   const size_t groups = (n + GV - 1) / GV;
   const size_t nwaves = (size_t)gridDim.x * (TB / 64);
-  for (size_t g = (size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); g < groups; g += nwaves) {
-    const size_t v0 = g * GV;
-    typename P::frag a[MB][H / P::KS];
-    floatx4_t c[MB][H / 16];
-    h1_fragments<P, H, MB>(sw, d0, d1, d2, v0, n, a);
-    mfma_layer<P, H, MB>(a, b, c);
+  size_t gi = (size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
+  float nxt[MB][3];
+  load_inputs<MB>(d0, d1, d2, gi * GV, n, nxt);
+  for (; gi < groups; gi += nwaves) {
+    const size_t v0 = gi * GV;
+    float in[MB][3];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) in[mb][q] = nxt[mb][q];
+    load_inputs<MB>(d0, d1, d2, v0 + nwaves * GV, n, nxt);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      float y[4];
-      layer3<H, MB>(sw, c, mb, y);
-      const int i = l & 15;
-      if (i < 4) {
-        const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
-        const float yi = i == 0 ? y[0] : i == 1 ? y[1] : i == 2 ? y[2] : y[3];
-        if (v < n) mass[v] = softplus_f(yi);
-      }
+      typename P::frag b[H / P::KS];
+      uint32_t mask;
+      const float* ws = lds_fence<P, H>(sw);
+      h1_frags<P, H>(ws, in[mb], b, mask);
+      floatx4_t acc[H / 16];
+      product<P, H>(aw, b, acc);
+      const float y = out_layer<H>(ws, acc);
+      const size_t v = v0 + 16 * mb + (l & 15);
+      if (l < 16 && v < n) mass[v] = softplus_f(y);
     }
   }
 }
@@ -339,106 +399,81 @@ __global__ __launch_bounds__(TB) void mlp_bwd_mx_kernel(const float* __restrict_
                                                         float* __restrict__ g12,
                                                         float* __restrict__ g2) {
   using S = SOff<H>;
-  using E = typename P::elem;
   constexpr int MB = MFMA_MB, GV = 16 * MB;  // voxels per group
-  __shared__ float sw[S::SIZE];
-  // Row pitch RP: rows of the LDS copies are padded so that the 16 rows a fragment read
-  // touches fall on distinct banks. 16-byte aligned: BF16 fragments are 16-byte vectors.
-  constexpr int RP = H + (sizeof(E) == 2 ? 8 : 1);
-  __shared__ __attribute__((aligned(16))) E wm[2 * H * RP];  // W2 and W2^T, row-major
-  __shared__ __attribute__((aligned(16))) E tile[TB / 64][GV * RP];
-  {
-    const E* w2 = w2_rows<P, H>(w);
-    for (int i = threadIdx.x; i < H * H; i += TB) {
-      const int r = i / H, c = i % H;
-      const E v = w2[i];
-      wm[r * RP + c] = v;
-      wm[H * RP + c * RP + r] = v;
-    }
-  }
-  load_small_weights<H>(sw, w);  // ends with a barrier
-  const int l = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  E* T = tile[wv];
+  constexpr int KB = H / P::KS;
+  __shared__ __attribute__((aligned(16))) float sw[S::SIZE];
+  load_small_weights<H>(sw, w);
+  if (n == 0) return;
+  const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+  typename P::frag aw[H / 16][KB], at[H / 16][KB];
+  load_w2_frags<P, H, false>(w2_rows<P, H>(w), aw);
+  load_w2_frags<P, H, true>(w2_rows<P, H>(w), at);
   const size_t groups = (n + GV - 1) / GV;
   const size_t nwaves = (size_t)gridDim.x * (TB / 64);
-  for (size_t g = (size_t)blockIdx.x * (TB / 64) + wv; g < groups; g += nwaves) {
-    const size_t v0 = g * GV;
-    floatx4_t c[MB][H / 16];
-    {
-      typename P::frag a[MB][H / P::KS];
-      typename P::frag b[H / P::KS][H / 16];
-      h1_fragments<P, H, MB>(sw, d0, d1, d2, v0, n, a);
-      load_b<P, H, RP>(wm, b);
-      mfma_layer<P, H, MB>(a, b, c);
-    }
-    // a2bar = ybar W3 [a2 > 0], stored as a GV x H tile for the transposed read
+  size_t gi = (size_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
+  float nxt[MB][3], nmb[MB];
+  load_inputs<MB>(d0, d1, d2, gi * GV, n, nxt);
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      float y[4];
-      layer3<H, MB>(sw, c, mb, y);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = mb * 16 + 4 * (l >> 4) + i;
-        const size_t v = v0 + r;
-        const float yb = v < n ? mbar[v] * sigmoid_f(y[i]) : 0.f;
-#pragma unroll
-        for (int nb = 0; nb < H / 16; ++nb) {
-          const int nn = nb * 16 + (l & 15);
-          const float a2 = c[mb][nb][i] + sw[S::B2 + nn];
-          T[r * RP + nn] = P::cvt(a2 > 0.f ? yb * sw[S::W3 + nn] : 0.f);
-        }
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    // h1bar = a2bar W2 on the matrix cores (B = W2 read as W2^T rows)
-    {
-      typename P::frag a[MB][H / P::KS];
-      typename P::frag b[H / P::KS][H / 16];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int kb = 0; kb < H / P::KS; ++kb)
-          a[mb][kb] = *reinterpret_cast<const typename P::frag*>(
-              T + (mb * 16 + (l & 15)) * RP + kb * P::KS + P::J * (l >> 4));
-      load_b<P, H, RP>(wm + H * RP, b);
-      mfma_layer<P, H, MB>(a, b, c);
-    }
-    // the tile is rewritten by the next group: its reads above must have completed
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
-    // a1bar = h1bar [a1 > 0]; fbar = W1^T a1bar (rows of the C layout)
+  for (int mb = 0; mb < MB; ++mb) {
+    const size_t v = gi * GV + 16 * mb + c;
+    nmb[mb] = mbar[v < n ? v : n - 1];
+  }
+  for (; gi < groups; gi += nwaves) {
+    const size_t v0 = gi * GV;
+    float in[MB][3], mbr[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const size_t v = v0 + mb * 16 + 4 * (l >> 4) + i;
-        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-        if (v < n) {
-          f0 = d0[v];
-          f1 = d1[v];
-          f2 = d1[v] - d2[v];
-        }
-        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+      for (int q = 0; q < 3; ++q) in[mb][q] = nxt[mb][q];
+      mbr[mb] = nmb[mb];
+    }
+    load_inputs<MB>(d0, d1, d2, v0 + nwaves * GV, n, nxt);
 #pragma unroll
-        for (int nb = 0; nb < H / 16; ++nb) {
-          const int k = nb * 16 + (l & 15);
-          const float a1 = sw[S::W1 + 3 * k] * f0 + sw[S::W1 + 3 * k + 1] * f1 +
-                           sw[S::W1 + 3 * k + 2] * f2 + sw[S::B1 + k];
-          const float hb = a1 > 0.f ? c[mb][nb][i] : 0.f;
-          p0 += sw[S::W1 + 3 * k] * hb;
-          p1 += sw[S::W1 + 3 * k + 1] * hb;
-          p2 += sw[S::W1 + 3 * k + 2] * hb;
+    for (int mb = 0; mb < MB; ++mb) {
+      const size_t v = v0 + nwaves * GV + 16 * mb + c;
+      nmb[mb] = mbar[v < n ? v : n - 1];
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const size_t v = v0 + 16 * mb + c;
+      typename P::frag b[KB];
+      uint32_t mask;
+      const float* ws = lds_fence<P, H>(sw);
+      h1_frags<P, H>(ws, in[mb], b, mask);
+      floatx4_t acc[H / 16];
+      product<P, H>(aw, b, acc);
+      const float y = out_layer<H>(ws, acc);
+      const float yb = v < n ? mbr[mb] * sigmoid_f(y) : 0.f;
+      // a2bar = ybar W3 [a2 > 0] as B fragments (K slots = output neurons)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int j = 0; j < P::J; ++j) {
+          const int t = kb * P::J + j, q = t >> 2, i = t & 3;
+          const float2 r = l2_row<H>(ws, 16 * q + 4 * g + i);
+          P::set(b[kb], j, acc[q][i] + r.x > 0.f ? yb * r.y : 0.f);
         }
-        p0 = group16_sum(p0);
-        p1 = group16_sum(p1);
-        p2 = group16_sum(p2);
-        if ((l & 15) == i && v < n) {
-          g0[v] = p0;
-          g12[v] = p1 + p2;
-          g2[v] = p2;
+      // h1bar = W2^T a2bar; a1bar = h1bar [a1 > 0]; fbar = W1^T a1bar
+      product<P, H>(at, b, acc);
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+      for (int q = 0; q < H / 16; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = 4 * q + i, k = 16 * q + 4 * g + i;
+          const float hb = (mask >> t) & 1u ? acc[q][i] : 0.f;
+          const float4 r = l1_row<H>(ws, k);
+          p0 += r.x * hb;
+          p1 += r.y * hb;
+          p2 += r.z * hb;
         }
+      p0 = group_sum4(p0);
+      p1 = group_sum4(p1);
+      p2 = group_sum4(p2);
+      if (l < 16 && v < n) {
+        g0[v] = p0;
+        g12[v] = p1 + p2;
+        g2[v] = p2;
       }
     }
   }

@@ -35,7 +35,8 @@ def _oracle_order(x, n_mesh, box):
     return keys[order], order
 
 
-@pytest.mark.parametrize("B,npart,nm", [(1, 16, 16), (2, 16, 32), (3, 32, 64), (1, 128, 128)])
+@pytest.mark.parametrize("B,npart,nm", [(1, 16, 16), (2, 16, 32), (3, 32, 64), (1, 128, 128),
+                                       (4, 32, 128), (2, 64, 256)])
 def test_keys_and_order_bit_exact(B, npart, nm):
     require_gpu()
     box = 100.0
