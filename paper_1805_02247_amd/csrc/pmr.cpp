@@ -412,7 +412,7 @@ void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_com
                  c->stream);
   }
   {
-    ProfScope ps(c, PMR_PROF_ZPASS, fields * 8.0 * cn + c->B * 16.0 * n3);
+    ProfScope ps(c, PMR_PROF_ZPASS, fields * 8.0 * cn + c->B * 12.0 * n3);
     launch_zpass_c2r3(n, c->B, in, fmap(3, in_item_stride, in_comp_stride, spec_pitch(n)), out,
                       (size_t)n * n * n, c->stream);
   }
@@ -802,15 +802,15 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     }
     c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
     {
-      // sorted keys, fractions, Fbar and ids in; F and dbar gathered; g out
-      ProfScope ps(c, PMR_PROF_ADJ_GATHER, 56.0 * B * c->np3 + 20.0 * B * c->nm3);
+      // compulsory: position (FP64), Fbar in and g out per particle; F and dbar per cell
+      ProfScope ps(c, PMR_PROF_ADJ_GATHER, 48.0 * B * c->np3 + 16.0 * B * c->nm3);
       launch_adjoint_positions(keyslot(c, fsl), fracslot(c, fsl), c->vstream, idslot(c, fsl),
                                fslot(c, fsl), c->dbar, (int)(B * c->np3), c->nm, c->cfg.box,
                                c->mass_m, c->gpos, s);
     }
     {
       // xbar, pbar and g in; xbar, pbar and the next paint values out
-      ProfScope ps(c, PMR_PROF_ADJ_UPDATE, (i > 0 ? 80.0 : 64.0) * B * c->np3);
+      ProfScope ps(c, PMR_PROF_ADJ_UPDATE, (i > 0 ? 72.0 : 60.0) * B * c->np3);
       launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, K, Dr, 0,
                             i > 0 ? c->vid : nullptr, i > 0 ? (float)c->kick[i - 1] : 0.f,
                             i > 0 ? (float)c->drift[i - 1] : 0.f, s);
