@@ -656,10 +656,10 @@ void launch_keys(const double* x, int log_np3, int total, double scale, int nm, 
   keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys, frac);
 }
 
-// Rows per wave: keep the wave's LDS accumulator within 2048 floats.
+// Rows per wave (see PMR_PAINT_LDS_FLOATS).
 static int paint_ty(int nm, int C) {
-  int ty = 2048 / (nm * C);
-  if (ty > 16) ty = 16;
+  int ty = PMR_PAINT_LDS_FLOATS / (nm * C);
+  if (ty > PMR_PAINT_TY_MAX) ty = PMR_PAINT_TY_MAX;
   if (ty > nm / 2) ty = nm / 2;  // TY + 1 distinct source rows per run
   int p = 1;
   while (p * 2 <= ty) p *= 2;

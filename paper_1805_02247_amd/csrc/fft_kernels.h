@@ -274,8 +274,8 @@ __global__ __launch_bounds__(NT) void zpass_r2c_kernel(const float* __restrict__
 // through HBM. rho - bias only changes X[0] of each row, by bias * N.
 template <int N>
 constexpr int paint_r2c_ty(int C) {
-  int ty = 2048 / (N * C);
-  if (ty > 16) ty = 16;
+  int ty = PMR_PAINT_LDS_FLOATS / (N * C);
+  if (ty > PMR_PAINT_TY_MAX) ty = PMR_PAINT_TY_MAX;
   if (ty > N / 2) ty = N / 2;
   if (ty > N / (NT / 64)) ty = N / (NT / 64);  // whole workgroups of rows per plane
   int p = 1;

@@ -91,6 +91,16 @@ struct FieldMap {
 };
 
 // Inputs of the CIC paint kernels: the particle streams in (key, id) order and the row index.
+// Rows per wave of the paints: TY = min(PMR_PAINT_LDS_FLOATS / (N C), PMR_PAINT_TY_MAX),
+// rounded down to a power of two. Fewer rows per wave balance the clustered rows of late
+// steps across more waves, at the cost of re-reading one source row per TY target rows.
+#ifndef PMR_PAINT_TY_MAX
+#define PMR_PAINT_TY_MAX 8
+#endif
+#ifndef PMR_PAINT_LDS_FLOATS
+#define PMR_PAINT_LDS_FLOATS 1024
+#endif
+
 struct PaintArgs {
   const uint32_t* keys;     // sorted keys
   const float4* frac;       // sorted fractions
