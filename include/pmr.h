@@ -116,7 +116,11 @@ int pmr_forward(pmr_ctx* ctx, const void* modes, float* mass_out, double* loss_o
 
 /* Gradient of sum_b loss_bar[b] * loss[b] + <mass_bar, mass> with respect to the modes of
  * the preceding pmr_forward. loss_bar: device double [B]; mass_bar: device float
- * [B][Nout^3] or NULL; grad_modes: complex64, same layout as the modes. */
+ * [B][Nout^3] or NULL; grad_modes: complex64, same layout as the modes. Without
+ * checkpointing (ckpt_every = 0, or ckpt_every >= n_steps) the adjoint may be called again
+ * for the same forward; when it had to recompute checkpoint segments, the per-step state of
+ * the last segment is gone and a further call returns PMR_E_STATE until the next
+ * pmr_forward. */
 int pmr_adjoint(pmr_ctx* ctx, const double* loss_bar, const float* mass_bar, void* grad_modes);
 
 const char* pmr_status_string(int status);

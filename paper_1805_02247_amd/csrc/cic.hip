@@ -118,7 +118,8 @@ __global__ __launch_bounds__(SORT_TB) void radix_scatter_kernel(const uint32_t* 
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ ids_out,
                                                            const float4* __restrict__ pay_in,
-                                                           float4* __restrict__ pay_out) {
+                                                           float4* __restrict__ pay_out,
+                                                           uint32_t* __restrict__ inv_out) {
   constexpr int NBK = 1 << D;
   __shared__ uint32_t cnt[SORT_WAVES][NBK];
   __shared__ uint32_t dstart[NBK];   // block-local start of each digit
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(SORT_TB) void radix_scatter_kernel(const uint32_t* 
     keys_out[dst] = k;
     ids_out[dst] = idv;
     if (pay_out) pay_out[dst] = pay_in[idv];
+    if (inv_out) inv_out[idv] = dst;
   }
 }
 
@@ -520,7 +522,9 @@ struct AdjArgs {
   float kick, drift;
   int final_mode;       // 1: xbar = gpos, pbar = 0
   float4* vnext;        // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
-  float kick_next, drift_next;  // reverse step (its adjoint paint values), id order
+  float kick_next, drift_next;  // reverse step (its adjoint paint values)
+  const uint32_t* vperm;  // nullable: sorted position of each particle in the next reverse
+                          // step's sort (vnext is then written in that sort order)
 };
 
 // Step adjoint (reverse of kick then drift), with the position gradient g from above:
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(TB) void adjoint_update_kernel(AdjArgs a) {
   a.pbar[pi + np3] = pb[1];
   a.pbar[pi + 2 * np3] = pb[2];
   if (a.vnext)
-    a.vnext[g] = make_float4(a.kick_next * (pb[0] + a.drift_next * xn[0]),
+    a.vnext[a.vperm ? a.vperm[g] : (uint32_t)g] = make_float4(a.kick_next * (pb[0] + a.drift_next * xn[0]),
                              a.kick_next * (pb[1] + a.drift_next * xn[1]),
                              a.kick_next * (pb[2] + a.drift_next * xn[2]), 0.f);
 }
@@ -599,19 +603,19 @@ size_t sort_scratch_bytes(int n, int key_bits) {
 template <int D>
 static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
                       int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* dtot,
-                      const float4* pin, float4* pout, hipStream_t s) {
+                      const float4* pin, float4* pout, uint32_t* inv, hipStream_t s) {
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
   radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
   digit_scan_kernel<<<1 << D, TB, 0, s>>>(hist, nb, offs, dtot);
   radix_scatter_kernel<D><<<nb, SORT_TB, 0, s>>>(kin, iin, n, shift, offs, dtot, kout, iout, pin,
-                                                  pout);
+                                                  pout, inv);
 }
 
 // Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
 // and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
 void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
                  uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
-                 hipStream_t s) {
+                 hipStream_t s, uint32_t* inv) {
   const int passes = (key_bits + 8) / 9;
   const int D = (key_bits + passes - 1) / passes;
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
@@ -635,7 +639,7 @@ void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
 #define CASE(DD) \
   case DD:                                                                                  \
     sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, dtot, last ? pay_in : nullptr,      \
-                  last ? pay_out : nullptr, s);                                                \
+                  last ? pay_out : nullptr, last ? inv : nullptr, s);                          \
     break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 #undef CASE
@@ -771,7 +775,7 @@ void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const fl
 
 void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
                            float kick, float drift, int final_mode, float4* vnext, float kick_next,
-                           float drift_next, hipStream_t s) {
+                           float drift_next, const uint32_t* vperm, hipStream_t s) {
   AdjArgs a{};
   a.xbar = xbar;
   a.pbar = pbar;
@@ -784,6 +788,7 @@ void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int bat
   a.vnext = vnext;
   a.kick_next = kick_next;
   a.drift_next = drift_next;
+  a.vperm = vperm;
   adjoint_update_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 

@@ -113,6 +113,7 @@ struct pmr_ctx {
   uint32_t* skeys; // sorted keys [SF][B*np3]
   float4* frac;    // sorted CIC fractions [SF][B*np3]
   uint32_t* rows;  // [SF][B*nm*nm + 1]
+  uint32_t* inv;   // inverse sort permutations (sorted position of each id) [SF][B*np3]
   int n_fslots;
   uint32_t* keys;
   uint32_t* keys_sorted;
@@ -188,6 +189,13 @@ struct Plan {
   }
 };
 
+// The reverse step's paint values go straight into the next step's sort order (through the
+// inverse sort permutation) only while the particle arrays stay cache-resident: both the
+// inverse permutation and those values are random writes, which at 2^24 particles cost more
+// (measured) than the coherent id-order write plus a sorted gather.
+constexpr size_t kDirectSortedValuesMax = (size_t)1 << 23;
+bool direct_sorted_values(const pmr_ctx* c) { return (size_t)c->B * c->np3 <= kDirectSortedValuesMax; }
+
 void plan(pmr_ctx* c, Plan& P) {
   const size_t B = c->B;
   c->inv_var = P.take<float>(c->cp);
@@ -205,6 +213,7 @@ void plan(pmr_ctx* c, Plan& P) {
   c->skeys = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->frac = P.take<float4>((size_t)c->n_fslots * B * c->np3);
   c->rows = P.take<uint32_t>((size_t)c->n_fslots * (B * c->nm * c->nm + 1));
+  c->inv = P.take<uint32_t>(direct_sorted_values(c) ? (size_t)c->n_fslots * B * c->np3 : 0);
   c->keys = P.take<uint32_t>(B * c->np3);
   c->keys_sorted = P.take<uint32_t>(B * c->np3);
   {
@@ -441,6 +450,9 @@ float4* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
 uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
 float4* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
+uint32_t* invslot(pmr_ctx* c, int s) {
+  return direct_sorted_values(c) ? c->inv + (size_t)s * c->B * c->np3 : nullptr;
+}
 uint32_t* rowslot(pmr_ctx* c, int s) { return c->rows + (size_t)s * (c->B * c->nm * c->nm + 1); }
 int xs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
@@ -455,7 +467,7 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
   double* x = xslot(c, xsl);
   double* xn = xslot(c, xsl + 1);
   launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
-              c->frac_id, fracslot(c, fsl), c->stream);
+              c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl));
   launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
                    c->stream);
   const size_t cm = c->sm;
@@ -751,8 +763,12 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
   // (the sort of the final positions on the output mesh is still held from the forward)
   launch_adjoint_positions(c->keys_sorted, c->frac_o, nullptr, c->ids_o, nullptr, dbar_f,
                            (int)(B * c->np3), c->no, c->cfg.box, c->mass_o, c->gpos, s);
-  launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, 0.f, 0.f, 1, c->vid,
-                        (float)c->kick[c->n - 1], (float)c->drift[c->n - 1], s);
+  // the paint values of step n - 1, in its sort order when they go there directly (its
+  // slot is held)
+  bool vsorted = direct_sorted_values(c);  // c->vstream holds step i's values in sort order
+  launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, 0.f, 0.f, 1,
+                        vsorted ? c->vstream : c->vid, (float)c->kick[c->n - 1],
+                        (float)c->drift[c->n - 1], invslot(c, fs_of(c, c->n - 1)), s);
   // H15: reverse PM steps (recomputing segments from checkpoints when needed)
   const size_t cm = c->sm;
   const double scale_m = (double)c->nm / c->cfg.box;
@@ -773,10 +789,12 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       // positions the last kick and drift would produce (the next checkpoint)
       for (int q = j; q < end; ++q) pm_step(c, q, q + 1 < end);
       resident_lo = j;
+      // the slots no longer hold the last segment: another adjoint needs a new forward
+      c->fwd_done = 0;
     }
     const int fsl = fs_of(c, i);
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
-    launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
+    if (!vsorted) launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
     const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
     {
       // adjoint paint of the three force channels, z-transformed in the same pass
@@ -811,9 +829,15 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     {
       // xbar, pbar and g in; xbar, pbar and the next paint values out
       ProfScope ps(c, PMR_PROF_ADJ_UPDATE, (i > 0 ? 72.0 : 60.0) * B * c->np3);
+      // step i - 1's paint values: into its sort order when that sort is held, else in id
+      // order for a gather after its segment has been recomputed
+      const bool next_sorted = direct_sorted_values(c) && i > 0 && i - 1 >= resident_lo;
       launch_adjoint_update(c->xbar, c->pbar, c->gpos, B, c->log_np3, K, Dr, 0,
-                            i > 0 ? c->vid : nullptr, i > 0 ? (float)c->kick[i - 1] : 0.f,
-                            i > 0 ? (float)c->drift[i - 1] : 0.f, s);
+                            i == 0 ? nullptr : next_sorted ? c->vstream : c->vid,
+                            i > 0 ? (float)c->kick[i - 1] : 0.f,
+                            i > 0 ? (float)c->drift[i - 1] : 0.f,
+                            next_sorted ? invslot(c, fs_of(c, i - 1)) : nullptr, s);
+      vsorted = next_sorted;
     }
   }
   // H16: Zel'dovich adjoint and gradient assembly (with the prior)

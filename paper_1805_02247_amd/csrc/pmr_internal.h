@@ -174,10 +174,11 @@ void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);
-// Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr.
+// Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr,
+// and inv[id] = dst (the inverse permutation) when inv != nullptr.
 void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
                  uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
-                 hipStream_t s);
+                 hipStream_t s, uint32_t* inv = nullptr);
 void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
                       uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
@@ -201,10 +202,11 @@ void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const fl
                               const uint32_t* ids, const float4* F, const float* dbar, int total,
                               int nm, double box, float mass, float4* g_out, hipStream_t s);
 // Kick and drift transposes with that gradient: pbar += drift xbar; xbar += g (final mode:
-// xbar = g, pbar = 0); optionally the next reverse step's paint values into vnext.
+// xbar = g, pbar = 0); optionally the next reverse step's paint values into vnext, in id
+// order, or in that step's sort order when vperm (its inverse permutation) is given.
 void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
                            float kick, float drift, int final_mode, float4* vnext, float kick_next,
-                           float drift_next, hipStream_t s);
+                           float drift_next, const uint32_t* vperm, hipStream_t s);
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
                     double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
                     int key_nm, hipStream_t s);

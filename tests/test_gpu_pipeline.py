@@ -53,7 +53,8 @@ def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P
     g = pm.adjoint(torch.ones(B, dtype=torch.float64, device=DEV))
     torch.cuda.synchronize()
     return dict(pm=pm, mass=mass.cpu().numpy(), loss=loss.cpu().numpy(), xs=xs,
-                delta_f=delta_f, grad=g.cpu().numpy(), xbar0=pm.debug("xbar0").cpu().numpy())
+                delta_f=delta_f, grad=g.cpu().numpy(), xbar0=pm.debug("xbar0").cpu().numpy(),
+                modes=m)
 
 
 def _compare(ocfg, inv, modes, w, targets, params, res, tol, refs=None):
@@ -146,6 +147,25 @@ def test_checkpointing_reproduces_stored_gradient_bitwise():
     assert np.array_equal(a["loss"], b["loss"]) and np.array_equal(a["loss"], c["loss"])
     assert np.array_equal(a["grad"], b["grad"]), np.abs(a["grad"] - b["grad"]).max()
     assert np.array_equal(a["grad"], c["grad"])
+
+
+def test_repeated_adjoint_and_recompute_guard():
+    """Without recomputation a second adjoint of the same forward repeats the gradient
+    bitwise; after an adjoint that recomputed checkpoint segments the per-step state of the
+    last segment is gone, so another adjoint is refused until the next forward, which then
+    gives the same gradient again."""
+    require_gpu()
+    say("pipeline: repeated adjoint, with and without recomputation")
+    prob = _problem(16, 16, 16, 50.0, 5, OM.LOSS_LOGNORMAL, 1, hidden=8, R_sm=(2.0,))
+    ones = torch.ones(1, dtype=torch.float64, device=DEV)
+    a = _gpu_run(*prob, ckpt=0)
+    assert np.array_equal(a["pm"].adjoint(ones).cpu().numpy(), a["grad"])
+    b = _gpu_run(*prob, ckpt=2)
+    with pytest.raises(P.PmrError):
+        b["pm"].adjoint(ones)
+    b["pm"].forward(b["modes"])
+    assert np.array_equal(b["pm"].adjoint(ones).cpu().numpy(), b["grad"])
+    assert np.array_equal(a["grad"], b["grad"])
 
 
 def test_run_to_run_bitwise():
