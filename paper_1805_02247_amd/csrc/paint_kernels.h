@@ -138,43 +138,58 @@ __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, 
   }
 }
 
+// Chunks of 64 particles loaded together before their scans and deposits (memory-level
+// parallelism of a wave's walk over its source rows).
+#ifndef PMR_PAINT_CHUNKS
+#define PMR_PAINT_CHUNKS 2
+#endif
+
 // Deposits of all particles that reach the TY target rows [iy0, iy0 + TY) of plane ix of one
 // item, into the wavefront's rows acc (zeroed by the caller): the two source planes ix - 1
-// and ix, each as one or two contiguous runs of source rows.
+// and ix, each as one or two contiguous runs of source rows. Chunks are deposited in stream
+// order, so the result does not depend on how many are in flight.
 template <int C, int TY, bool PAD = false>
 __device__ __forceinline__ void paint_rows(const PaintArgs& a, int item, int ix, int iy0,
                                            float* acc, int rp) {
+  constexpr int CH = PMR_PAINT_CHUNKS;
   const int lane = threadIdx.x & 63;
   const int nm = a.nm;
   const int rows_item = item * nm * nm;
+  // main runs of source rows [iy0 - 1, iy0 + TY - 1] of both planes (from row 0 when iy0 - 1
+  // wraps; row nm - 1 is then a second run)
+  const int lo0 = iy0 == 0 ? 0 : iy0 - 1, hi0 = iy0 + TY - 1;
+  uint32_t beg0[2], end0[2];
+#pragma unroll
+  for (int ox = 0; ox < 2; ++ox) {
+    const int rbase = rows_item + ((ix - ox + nm) & (nm - 1)) * nm;
+    beg0[ox] = a.row_start[rbase + lo0];
+    end0[ox] = a.row_start[rbase + hi0 + 1];
+  }
 #pragma unroll 1
   for (int ox = 0; ox < 2; ++ox) {
-    const int sx = (ix - ox + nm) & (nm - 1);
-    const int rbase = rows_item + sx * nm;
-    // runs of source rows: [iy0 - 1, iy0 + TY - 1], split when iy0 - 1 wraps
-    int lo0 = iy0 - 1, hi0 = iy0 + TY - 1, lo1 = 1, hi1 = 0;
-    if (iy0 == 0) {
-      lo0 = 0;
-      lo1 = nm - 1;
-      hi1 = nm - 1;
-    }
+    const int rbase = rows_item + ((ix - ox + nm) & (nm - 1)) * nm;
 #pragma unroll 1
     for (int run = 0; run < 2; ++run) {
-      const int lo = run == 0 ? lo0 : lo1, hi = run == 0 ? hi0 : hi1;
-      if (lo > hi) continue;
-      const uint32_t beg = a.row_start[rbase + lo], end = a.row_start[rbase + hi + 1];
-      // two chunks in flight; their deposits stay in chunk order
+      uint32_t beg, end;
+      if (run == 0) {
+        beg = ox == 0 ? beg0[0] : beg0[1];
+        end = ox == 0 ? end0[0] : end0[1];
+      } else {
+        if (iy0 != 0) continue;
+        beg = a.row_start[rbase + nm - 1];
+        end = a.row_start[rbase + nm];
+      }
 #pragma unroll 1
-      for (uint32_t c0 = beg; c0 < end; c0 += 128) {
-        Chunk<C> A, Bc;
-        load_chunk<C>(a, c0 + lane, end, ox, A);
-        load_chunk<C>(a, c0 + 64 + lane, end, ox, Bc);
-        seg_scan<4 * C>(A.v, A.key);
-        seg_scan<4 * C>(Bc.v, Bc.key);
-        deposit<C, TY, PAD>(A, acc, nm, iy0, rp);
-        if (c0 + 64 < end) deposit<C, TY, PAD>(Bc, acc, nm, iy0, rp);
+      for (uint32_t c0 = beg; c0 < end; c0 += 64 * CH) {
+        Chunk<C> ch[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) load_chunk<C>(a, c0 + 64 * q + lane, end, ox, ch[q]);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) seg_scan<4 * C>(ch[q].v, ch[q].key);
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+          if (q == 0 || c0 + 64 * q < end) deposit<C, TY, PAD>(ch[q], acc, nm, iy0, rp);
       }
     }
   }
 }
-
