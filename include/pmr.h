@@ -130,7 +130,7 @@ const char* pmr_status_string(int status);
  * of bytes copied, or a negative status. `step` selects the PM step where relevant.
  *   PMR_DBG_X         positions x_step, double [B][3][Np^3] (step 0..n; only the steps the
  *                     checkpoint policy keeps: all for ckpt_every = 0)
- *   PMR_DBG_FORCE     force mesh at x_step, interleaved float [B][Nm^3][4] = (Fx, Fy, Fz, 0)
+ *   PMR_DBG_FORCE     force mesh at x_step, interleaved float [B][Nm^3][3] = (Fx, Fy, Fz)
  *                     (same availability)
  *   PMR_DBG_SORT_IDS  sorted particle ids for x_step on the force mesh, u32 [B*Np^3]
  *   PMR_DBG_DELTA_F   final density contrast on the output mesh, float [B][Nout^3]

@@ -175,7 +175,7 @@ class PMContext:
         """Copy an internal buffer of the last forward/adjoint (see PMR_DBG_* in pmr.h)."""
         cfg = self.cfg
         B, np3, nm3, no3 = cfg.batch, cfg.n_part ** 3, cfg.n_mesh ** 3, cfg.n_out ** 3
-        spec = {"x": (torch.float64, (B, 3, np3)), "force": (torch.float32, (B, nm3, 4)),
+        spec = {"x": (torch.float64, (B, 3, np3)), "force": (torch.float32, (B, nm3, 3)),
                 "sort_ids": (torch.int32, (B * np3,)), "delta_f": (torch.float32, (B, no3)),
                 "features": (torch.float32, (2, B, no3)), "mass_r": (torch.float32, (B, no3)),
                 "res_s": (torch.float32, (B, no3)), "xbar0": (torch.float32, (B, 3, np3)),

@@ -401,7 +401,7 @@ struct StepArgs {
   const double* x;    // [B][3][Np^3] positions x_i
   double* x_next;     // positions x_{i+1}
   float* p;           // momenta, updated in place
-  const float4* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz, -) at x_i
+  const Force3* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz) at x_i
   uint32_t* keys;     // keys of x_{i+1} (nullable)
   float4* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
   int log_np3, nm, total;
@@ -424,14 +424,14 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   const int nm = a.nm;
   const Corner c = corner_of(xyz, a.scale, nm);
   const size_t cells = (size_t)nm * nm * nm;
-  const float4* F = a.F + (size_t)item * cells;
+  const Force3* F = a.F + (size_t)item * cells;
   float fa[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
     const float w = (ox ? c.f[0] : 1.f - c.f[0]) * (oy ? c.f[1] : 1.f - c.f[1]) *
                      (oz ? c.f[2] : 1.f - c.f[2]);
-    const float4 f = F[cidx(c, ox, oy, oz, nm)];
+    const Force3 f = F[cidx(c, ox, oy, oz, nm)];
     fa[0] += w * f.x;
     fa[1] += w * f.y;
     fa[2] += w * f.z;
@@ -462,7 +462,7 @@ struct AdjPosArgs {
   const float4* frac;    // sorted fractions
   const float4* fbar;    // sorted Fbar (nullable: final-paint adjoint, no force term)
   const uint32_t* ids;   // sorted ids
-  const float4* F;       // interleaved force mesh at x_i [B][nm^3] (nullable with fbar)
+  const Force3* F;       // interleaved force mesh at x_i [B][nm^3] (nullable with fbar)
   const float* dbar;     // density adjoint mesh [B][nm^3]
   float4* g_out;         // [B * Np^3], id order
   int nm, log_nm, total;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
     fb[1] = v.y;
     fb[2] = v.z;
   }
-  const float4* F = a.F ? a.F + (size_t)item * cells : nullptr;
+  const Force3* F = a.F ? a.F + (size_t)item * cells : nullptr;
   const float* D = a.dbar + (size_t)item * cells;
   const float s = a.scale;
   float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
                         (oz ? i1[2] : i0[2]);
     float v = a.mass * D[ci];
     if (F) {
-      const float4 fv = F[ci];
+      const Force3 fv = F[ci];
       v += fb[0] * fv.x + fb[1] * fv.y + fb[2] * fv.z;
     }
     gx += dx * wy * wz * v;
@@ -730,7 +730,7 @@ void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* v
   paint_dispatch<3>(a, batch, s);
 }
 
-void launch_kick_drift(const double* x, double* x_next, float* p, const float4* F, uint32_t* keys,
+void launch_kick_drift(const double* x, double* x_next, float* p, const Force3* F, uint32_t* keys,
                        float4* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s) {
   StepArgs a{};
@@ -753,7 +753,7 @@ void launch_kick_drift(const double* x, double* x_next, float* p, const float4* 
 }
 
 void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
-                              const uint32_t* ids, const float4* F, const float* dbar, int total,
+                              const uint32_t* ids, const Force3* F, const float* dbar, int total,
                               int nm, double box, float mass, float4* g_out, hipStream_t s) {
   AdjPosArgs a{};
   a.keys = keys;

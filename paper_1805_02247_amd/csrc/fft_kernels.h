@@ -420,9 +420,10 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
   }
 }
 
-// Three fields per item (the components of a vector field) -> one interleaved float4 mesh
-// (f0, f1, f2, 0) [item][n^3]: a CIC readout of all three components at a corner is then one
-// 16-byte load instead of three loads from three meshes. Same transform as zpass_c2r_kernel.
+// Three fields per item (the components of a vector field) -> one interleaved mesh of
+// (f0, f1, f2) cells [item][n^3]: a CIC readout of all three components at a corner is then
+// one 12-byte load instead of three loads from three meshes. Same transform as
+// zpass_c2r_kernel.
 template <int N>
 struct ZTile3 {
   static constexpr int R = ZTile<N>::ROWS / 2 > 0 ? ZTile<N>::ROWS / 2 : 1;  // rows per field
@@ -430,7 +431,7 @@ struct ZTile3 {
 
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict__ in, FieldMap im,
-                                                        float4* __restrict__ out,
+                                                        Force3* __restrict__ out,
                                                         size_t out_item_stride,
                                                         int tiles_per_item, int ntiles) {
   using T = ZTile<N>;
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
     fft_lds<H, 3 * R, 1, PITCH, 2, +1, NT, true>(lds, tw);
     const int item = tau / tiles_per_item;
     const size_t row0 = (size_t)(tau % tiles_per_item) * R;
-    float4* dst = out + item * out_item_stride + row0 * N;
+    Force3* dst = out + item * out_item_stride + row0 * N;
     const float* l = reinterpret_cast<const float*>(lds);
     static_assert((R * N) % NT == 0, "whole rows per thread sweep");
 #pragma unroll
@@ -479,8 +480,8 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
       const int e = threadIdx.x + m * NT;
       const int r = e / N, zz = e % N;
       const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
-      dst[e] = make_float4(l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
-                           l[(2 * R + r) * 2 * PITCH + q], 0.f);
+      dst[e] = Force3{l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
+                      l[(2 * R + r) * 2 * PITCH + q]};
     }
     if (next >= ntiles) break;
     __syncthreads();
@@ -785,7 +786,7 @@ void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, 
 }
 
 template <int N>
-void zc2r3(int items, const float2* in, FieldMap im, float4* out, size_t out_item_stride,
+void zc2r3(int items, const float2* in, FieldMap im, Force3* out, size_t out_item_stride,
            hipStream_t s) {
   const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
   const int res = resident_grid<zpass_c2r3_kernel<N>, NT>();

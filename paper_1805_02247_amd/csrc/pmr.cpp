@@ -108,7 +108,7 @@ struct pmr_ctx {
   float* ckp;
   int n_ck;
   float* p;     // [B][3][np3]
-  float4* F;    // force slots [SF][B][nm3], interleaved (Fx, Fy, Fz, -)
+  Force3* F;    // force slots [SF][B][nm3], interleaved (Fx, Fy, Fz)
   uint32_t* ids;   // sort slots [SF][B*np3]
   uint32_t* skeys; // sorted keys [SF][B*np3]
   float4* frac;    // sorted CIC fractions [SF][B*np3]
@@ -208,7 +208,7 @@ void plan(pmr_ctx* c, Plan& P) {
   c->ckx = P.take<double>((size_t)c->n_ck * B * 3 * c->np3);
   c->ckp = P.take<float>((size_t)c->n_ck * B * 3 * c->np3);
   c->p = P.take<float>(B * 3 * c->np3);
-  c->F = P.take<float4>((size_t)c->n_fslots * B * c->nm3);
+  c->F = P.take<Force3>((size_t)c->n_fslots * B * c->nm3);
   c->ids = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->skeys = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->frac = P.take<float4>((size_t)c->n_fslots * B * c->np3);
@@ -410,9 +410,9 @@ void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, siz
   }
 }
 
-// Spectra of the three force components after the x pass -> interleaved float4 force mesh.
+// Spectra of the three force components after the x pass -> interleaved force mesh.
 void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_comp_stride,
-             float4* out) {
+             Force3* out) {
   const int fields = c->B * 3;
   const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
   {
@@ -446,7 +446,7 @@ void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, con
 
 // ---------------------------------------------------------------- PM pieces
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
-float4* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
+Force3* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
 uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
 float4* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
@@ -494,7 +494,7 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
     ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * c->cm);
     launch_xpass(XOP_FORCE, a, c->stream);
   }
-  float4* F = fslot(c, fsl);
+  Force3* F = fslot(c, fsl);
   c2r_yz3(c, c->nm, c->cB, 3 * cm, cm, F);
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
@@ -937,7 +937,7 @@ long long pmr_debug_copy(pmr_ctx* c, int what, int step, void* dst) {
       }
       if (what == PMR_DBG_FORCE) {
         src = fslot(c, sl);
-        bytes = B * c->nm3 * sizeof(float4);
+        bytes = B * c->nm3 * sizeof(Force3);
       } else {
         src = idslot(c, sl);
         bytes = B * c->np3 * sizeof(uint32_t);

@@ -101,6 +101,12 @@ struct FieldMap {
 #define PMR_PAINT_LDS_FLOATS 1024
 #endif
 
+// One cell of the force mesh: (F_x, F_y, F_z), 12 bytes, cells contiguous, so that a CIC
+// corner is one three-dword load.
+struct Force3 {
+  float x, y, z;
+};
+
 struct PaintArgs {
   const uint32_t* keys;     // sorted keys
   const float4* frac;       // sorted fractions
@@ -156,7 +162,7 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
 // item = channels); the y and x passes complete the transform.
 void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2* out, FieldMap om,
                       hipStream_t s);
-void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, float4* out,
+void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Force3* out,
                        size_t out_item_stride, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
@@ -192,14 +198,14 @@ void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t*
 void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
                        const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
 // F: interleaved force mesh [B][nm^3] float4 (Fx, Fy, Fz, unused).
-void launch_kick_drift(const double* x, double* x_next, float* p, const float4* F, uint32_t* keys,
+void launch_kick_drift(const double* x, double* x_next, float* p, const Force3* F, uint32_t* keys,
                        float4* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s);
 // Position gradient of a step adjoint (or of the final paint: fbar = F = nullptr), computed in
 // sort order and written to g_out in id order:
 //   g = sum_corners dW/dx * (Fbar . F(corner) + mass * dbar(corner)).
 void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
-                              const uint32_t* ids, const float4* F, const float* dbar, int total,
+                              const uint32_t* ids, const Force3* F, const float* dbar, int total,
                               int nm, double box, float mass, float4* g_out, hipStream_t s);
 // Kick and drift transposes with that gradient: pbar += drift xbar; xbar += g (final mode:
 // xbar = g, pbar = 0); optionally the next reverse step's paint values into vnext, in id
