@@ -3,4 +3,4 @@
 TEST INFRASTRUCTURE ONLY: used by tests/, by the smoke check and by the benchmark's
 CPU-baseline leg. The product (the HIP library and its binding) never imports it.
 """
-from . import cosmology, mesh, model  # noqa: F401
+from . import cosmology, lbfgs, mesh, model, stats  # noqa: F401
