@@ -223,6 +223,47 @@ int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x
                   const uint32_t* row_start, float mass, float bias, float* out, void* scratch,
                   size_t scratch_bytes, void* stream);
 
+/* ---- reconstruction driver support ----
+ * The optimiser of Sec. 5.2 is L-BFGS over all stored real and imaginary parts of the
+ * modes; its inner products run in FP64 on the device and its scalars stay in device
+ * memory, so a direction costs no host synchronisation. Vectors are float arrays of n
+ * elements (a complex64 mode array is 2 x n_modes floats). Reductions use a fixed grid and
+ * a fixed tree: bitwise reproducible. All calls enqueue on `stream` (a hipStream_t or NULL)
+ * and return without synchronising; errors are PMR_E_INVALID for bad arguments. */
+
+/* Bytes of device scratch `work` for pmr_vec_dot and pmr_lbfgs_direction on n floats with
+ * a history of m pairs (m = 0 for pmr_vec_dot). */
+size_t pmr_vec_work_bytes(size_t n, int m);
+
+/* out[0] (device double) = sum_i a[i] b[i], products and sums in FP64. */
+int pmr_vec_dot(size_t n, const float* a, const float* b, double* out, void* work, void* stream);
+
+/* out = alpha a + beta b elementwise (FP32; host scalars; out may alias a or b). */
+int pmr_vec_axpby(size_t n, double alpha, const float* a, double beta, const float* b,
+                  float* out, void* stream);
+
+/* L-BFGS search direction d = -H g (two-loop recursion; Nocedal & Wright, Numerical
+ * Optimization, Alg. 7.4) with H0 = gamma I, gamma = s.y / y.y of the newest pair.
+ * S, Y: device [m][n] floats, the history pairs s = x_{k+1} - x_k, y = g_{k+1} - g_k in
+ * slots 0..m-1; order: HOST int array of `count` distinct slots, newest first; sy, yy:
+ * device doubles [m] with s.y and y.y of each slot (pmr_vec_dot). count = 0 gives d = -g.
+ * g and d must not alias. */
+int pmr_lbfgs_direction(size_t n, int m, int count, const int* order, const float* S,
+                        const float* Y, const double* sy, const double* yy, const float* g,
+                        float* d, void* work, void* stream);
+
+/* Bytes of device scratch for pmr_power_bins with `nbins` shells. */
+size_t pmr_power_work_bytes(int nbins);
+
+/* Binned auto and cross power of two half spectra a, b (complex64 [n][n][n/2+1], numpy
+ * rfftn layout) of a box of side `box` (two point functions, Sec. 4.3). Shell i holds the
+ * full-spectrum modes with i <= |m| < i + 1 (m the integer wavevector; k = 2 pi m / box),
+ * the k = 0 mode excluded. out: device doubles [4][nbins] = (count, P_aa, P_bb, P_ab) with
+ * P = box^3 / n^6 * mean over the shell's full-spectrum modes of |a|^2, |b|^2, Re a conj b
+ * (0 for an empty shell). n: power of two 2..1024; 1 <= nbins <= 2 n. */
+int pmr_power_bins(int n, double box, const void* a, const void* b, int nbins, double* out,
+                   void* work, size_t work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,13 +22,12 @@ from . import mesh as M
 def power_bins(a, b, box, nbins):
     """-> (count, P_aa, P_bb, P_ab), each [nbins] (FP64)."""
     n = a.shape[0]
-    kv = M.wavevectors(n, box)
-    k = np.sqrt(kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2)
-    k = np.broadcast_to(k, a.shape)
+    mx, my, mz = M.int_wavenumbers(n)
+    m2 = np.broadcast_to(mx ** 2 + my ** 2 + mz ** 2, a.shape)  # exact integers
     w = np.broadcast_to(M.hermitian_weight(n), a.shape)
-    dk = 2.0 * np.pi / box
-    idx = np.floor(k / dk).astype(np.int64)
-    use = (k > 0) & (idx < nbins)
+    # shell of |k| in units of dk = 2 pi / L: floor(sqrt(m^2)), exact for perfect squares
+    idx = np.floor(np.sqrt(m2)).astype(np.int64)
+    use = (m2 > 0) & (idx < nbins)
     cnt = np.zeros(nbins)
     paa = np.zeros(nbins)
     pbb = np.zeros(nbins)

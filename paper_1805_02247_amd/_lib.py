@@ -61,6 +61,13 @@ SIGNATURES = {
     "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, cf, cf, vp, vp, sz, vp]),
     "pmr_fft_set_tile": (ci, [ci, ci, ci, ci, ci]),
     "pmr_fft_get_tile": (ci, [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
+    "pmr_vec_work_bytes": (sz, [sz, ci]),
+    "pmr_vec_dot": (ci, [sz, vp, vp, vp, vp, vp]),
+    "pmr_vec_axpby": (ci, [sz, cd, vp, cd, vp, vp, vp]),
+    "pmr_lbfgs_direction": (ci, [sz, ci, ci, ctypes.POINTER(ci), vp, vp, vp, vp, vp, vp, vp,
+                                 vp]),
+    "pmr_power_work_bytes": (sz, [ci]),
+    "pmr_power_bins": (ci, [ci, cd, vp, vp, ci, vp, vp, sz, vp]),
     "pmr_profile_begin": (ci, [vp, ci, ci]),
     "pmr_profile_end": (ci, [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_longlong),
                              ctypes.POINTER(cd)]),

@@ -1,0 +1,195 @@
+"""Reconstruction driver (Sec. 5.2, Sec. 5.3): L-BFGS over the linear modes of one
+realisation, run over an anneal schedule of loss stages, and the binned two-point
+statistics of Sec. 4.3 that score the result against the true modes.
+
+Every vector operation runs in libpmr kernels: FP64 inner products with device-resident
+scalars, the two-loop recursion (pmr_lbfgs_direction) and the updates. The host keeps the
+control flow: the Armijo test on the loss copied back once per evaluation, the curvature
+test on three inner products copied back once per accepted step, the history ring and the
+stopping rule. The parameters are all stored real and imaginary parts of the modes, so the
+complex64 mode tensor is used as a float32 vector of twice its length.
+
+Readings (the paper names L-BFGS and the anneal but gives no optimiser parameters):
+history m = 10; the first iteration of a stage moves a unit distance along -g (step
+1 / |g|), later ones start the backtracking at step 1; Armijo constant c1 = 1e-4, at most
+30 halvings (failure ends the stage); a pair is kept only if s.y > 1e-10 |s| |y|; a
+non-descent direction clears the history; a stage ends when the loss falls by less than
+0.1% of its value between successive iterations (Sec. 5.3), at a zero gradient, or after
+max_iter iterations; each stage starts from the previous optimum with an empty history.
+"""
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+from .api import LossParams, _ptr, _stream
+
+HISTORY = 10
+C1 = 1e-4
+MAX_HALVINGS = 30
+CURVATURE_EPS = 1e-10
+REL_TOL = 1e-3
+
+
+class VecOps:
+    """FP64 inner products, updates and L-BFGS directions on float32 device vectors of n."""
+
+    def __init__(self, n, m, device):
+        self.n, self.m = int(n), int(m)
+        nb = int(L.lib().pmr_vec_work_bytes(self.n, self.m))
+        self.work = torch.empty(nb // 8 + 1, dtype=torch.float64, device=device)
+
+    def dot(self, a, b, out):
+        """out: a 0-d or 1-element float64 device tensor view."""
+        L.check(L.lib().pmr_vec_dot(self.n, _ptr(a), _ptr(b), _ptr(out), _ptr(self.work),
+                                    _stream()))
+
+    def axpby(self, alpha, a, beta, b, out):
+        L.check(L.lib().pmr_vec_axpby(self.n, float(alpha), _ptr(a), float(beta), _ptr(b),
+                                      _ptr(out), _stream()))
+
+    def direction(self, g, d, order, S, Y, sy, yy):
+        cnt = len(order)
+        arr = (ctypes.c_int * max(cnt, 1))(*order)
+        L.check(L.lib().pmr_lbfgs_direction(self.n, self.m, cnt, arr, _ptr(S), _ptr(Y), _ptr(sy),
+                                            _ptr(yy), _ptr(g), _ptr(d), _ptr(self.work),
+                                            _stream()))
+
+
+def _floats(modes):
+    return modes.view(torch.float32).reshape(-1)
+
+
+@dataclass
+class StageResult:
+    params: LossParams
+    losses: list = field(default_factory=list)
+    evals: int = 0
+    iters: int = 0
+    reason: str = "max_iter"
+    seconds: float = 0.0
+
+
+def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop_below=None):
+    """L-BFGS from `modes` (complex64 [1][n_modes], updated in place) with the loss already
+    set on `pm` (a PMContext of batch 1). stop_below: optional loss at which to stop early.
+    Returns a StageResult."""
+    if pm.cfg.batch != 1:
+        raise ValueError("the driver optimises one realisation (batch 1)")
+    dev = modes.device
+    x = _floats(modes)
+    n = x.numel()
+    slots = m + 1  # the history plus one slot for the candidate pair
+    ops = VecOps(n, slots, dev)
+    g = torch.empty_like(x)
+    xt = torch.empty_like(x)
+    gt = torch.empty_like(x)
+    d = torch.empty_like(x)
+    S = torch.empty(slots, n, dtype=torch.float32, device=dev)
+    Y = torch.empty(slots, n, dtype=torch.float32, device=dev)
+    sy = torch.zeros(slots, dtype=torch.float64, device=dev)
+    yy = torch.zeros(slots, dtype=torch.float64, device=dev)
+    tmp = torch.zeros(4, dtype=torch.float64, device=dev)
+    ones = torch.ones(1, dtype=torch.float64, device=dev)
+    res = StageResult(params=None)
+    t0 = time.perf_counter()
+
+    def evaluate(src, grad_out):
+        _, loss = pm.forward(src.view(torch.complex64).reshape(1, -1), want_mass=False)
+        pm.adjoint(ones, out=grad_out.view(torch.complex64).reshape(1, -1))
+        res.evals += 1
+        return float(loss[0, 0].item())
+
+    f = evaluate(x, g)
+    res.losses.append(f)
+    order = []  # history slots, newest first (at most m)
+    for it in range(max_iter):
+        ops.dot(g, g, tmp[0:1])
+        gg = float(tmp[0].item())
+        if gg == 0.0:
+            res.reason = "stationary"
+            break
+        ops.direction(g, d, order, S, Y, sy, yy)
+        ops.dot(g, d, tmp[1:2])
+        gd = float(tmp[1].item())
+        if gd >= 0.0:
+            order = []
+            ops.axpby(-1.0, g, 0.0, g, d)
+            gd = -gg
+        t = 1.0 if order else 1.0 / gg ** 0.5
+        ok = False
+        for _ in range(MAX_HALVINGS + 1):
+            ops.axpby(1.0, x, t, d, xt)
+            fn = evaluate(xt, gt)
+            if fn <= f + C1 * t * gd:
+                ok = True
+                break
+            t *= 0.5
+        if not ok:
+            res.reason = "line_search"
+            break
+        slot = next(k for k in range(slots) if k not in order)
+        ops.axpby(1.0, xt, -1.0, x, S[slot])
+        ops.axpby(1.0, gt, -1.0, g, Y[slot])
+        ops.dot(S[slot], Y[slot], sy[slot:slot + 1])
+        ops.dot(Y[slot], Y[slot], yy[slot:slot + 1])
+        ops.dot(S[slot], S[slot], tmp[2:3])
+        h = torch.stack([sy[slot], yy[slot], tmp[2]]).cpu()
+        if float(h[0]) > CURVATURE_EPS * (float(h[1]) * float(h[2])) ** 0.5:
+            order = ([slot] + order)[:m]  # the oldest pair leaves when m are held
+        ops.axpby(1.0, xt, 0.0, xt, x)
+        ops.axpby(1.0, gt, 0.0, gt, g)
+        rel = (f - fn) / abs(f) if f != 0.0 else 0.0
+        f = fn
+        res.losses.append(f)
+        res.iters = it + 1
+        if log:
+            log(it, f, t, res.evals)
+        if stop_below is not None and f <= stop_below:
+            res.reason = "target_loss"
+            break
+        if rel < rel_tol:
+            res.reason = "converged"
+            break
+    torch.cuda.synchronize(dev)
+    res.seconds = time.perf_counter() - t0
+    return res
+
+
+def reconstruct(pm, modes, stages, max_iter=100, log=None):
+    """Runs minimize over the anneal stages (LossParams each) in order, from `modes`
+    (updated in place). Returns the list of StageResult."""
+    out = []
+    for p in stages:
+        pm.set_loss(p)
+        r = minimize(pm, modes, max_iter=max_iter, log=log)
+        r.params = p
+        out.append(r)
+    return out
+
+
+def power_bins(a, b, n, box, nbins):
+    """Binned (count, P_aa, P_bb, P_ab) of two half spectra (complex64, n x n x (n/2+1)
+    elements each, on the device) -> float64 device tensor [4][nbins]."""
+    a = a.reshape(n, n, n // 2 + 1).contiguous()
+    b = b.reshape(n, n, n // 2 + 1).contiguous()
+    out = torch.empty(4, nbins, dtype=torch.float64, device=a.device)
+    wb = int(L.lib().pmr_power_work_bytes(nbins))
+    work = torch.empty(wb // 8 + 1, dtype=torch.float64, device=a.device)
+    L.check(L.lib().pmr_power_bins(n, float(box), _ptr(a), _ptr(b), nbins, _ptr(out), _ptr(work),
+                                   work.numel() * 8, _stream()))
+    return out
+
+
+def metrics(bins):
+    """(r_c, stochasticity, TF) per shell from power_bins output (host float64 tensors)."""
+    b = bins.cpu()
+    paa, pbb, pab = b[1], b[2], b[3]
+    ok = (paa * pbb) > 0
+    rc = torch.where(ok, pab / torch.sqrt(torch.where(ok, paa * pbb, torch.ones_like(paa))),
+                     torch.zeros_like(paa))
+    tf = torch.where(paa > 0, torch.sqrt(torch.where(paa > 0, pbb / torch.where(paa > 0, paa,
+                     torch.ones_like(paa)), torch.zeros_like(paa))), torch.zeros_like(paa))
+    return rc, paa * (1.0 - rc ** 2), tf

@@ -94,3 +94,34 @@ def test_fft_tile_shape_validation():
     finally:
         for p, v in saved.items():
             lib.pmr_fft_set_tile(128, p, *v)
+
+
+def test_reconstruction_calls_validate_arguments_on_the_host():
+    """Bad arguments of the driver calls are refused before any device work."""
+    lib = L.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)  # never dereferenced: every call below fails validation first
+    order = (ctypes.c_int * 3)(0, 1, 1)
+    assert lib.pmr_vec_work_bytes(1000, -1) == 0
+    assert lib.pmr_vec_work_bytes(1000, 4) > lib.pmr_vec_work_bytes(1000, 0) > 0
+    assert lib.pmr_vec_dot(0, fake, fake, fake, fake, None) == -1
+    assert lib.pmr_vec_dot(10, None, fake, fake, fake, None) == -1
+    assert lib.pmr_vec_axpby(10, 1.0, fake, 1.0, fake, None, None) == -1
+    # count > m, duplicate slot, slot out of range, g aliasing d, m out of range
+    assert lib.pmr_lbfgs_direction(10, 2, 3, order, fake, fake, fake, fake, P(8192), fake,
+                                   fake, None) == -1
+    assert lib.pmr_lbfgs_direction(10, 4, 3, order, fake, fake, fake, fake, P(8192), fake,
+                                   fake, None) == -1
+    bad = (ctypes.c_int * 1)(5)
+    assert lib.pmr_lbfgs_direction(10, 4, 1, bad, fake, fake, fake, fake, P(8192), fake,
+                                   fake, None) == -1
+    assert lib.pmr_lbfgs_direction(10, 4, 0, None, None, None, None, None, fake, fake, fake,
+                                   None) == -1
+    assert lib.pmr_lbfgs_direction(10, 65, 0, None, None, None, None, None, P(8192), fake,
+                                   fake, None) == -1
+    assert lib.pmr_power_work_bytes(0) == 0 and lib.pmr_power_work_bytes(8) > 0
+    need = lib.pmr_power_work_bytes(8)
+    assert lib.pmr_power_bins(12, 100.0, fake, fake, 8, fake, fake, need, None) == -2
+    assert lib.pmr_power_bins(16, 100.0, fake, fake, 33, fake, fake, need, None) == -2
+    assert lib.pmr_power_bins(16, 0.0, fake, fake, 8, fake, fake, need, None) == -1
+    assert lib.pmr_power_bins(16, 100.0, fake, fake, 8, fake, fake, need - 8, None) == -3

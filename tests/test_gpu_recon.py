@@ -1,0 +1,183 @@
+"""GPU parity of the reconstruction driver: FP64 inner products, the L-BFGS two-loop
+recursion, the binned two-point statistics, and whole L-BFGS runs against the FP64
+oracle driver."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cosmology as OC
+from oracle import lbfgs as LB
+from oracle import model as OM
+from oracle import stats as ST
+import paper_1805_02247_amd as P
+from paper_1805_02247_amd import recon as R
+from _gpu import DEV, rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n", [1, 1000, 1_048_576 + 77])
+def test_vec_dot_fp64_and_reproducible(n):
+    require_gpu()
+    say(f"recon: dot n={n}")
+    r = np.random.default_rng(n)
+    a = r.normal(size=n).astype(np.float32) * 1e3
+    b = r.normal(size=n).astype(np.float32)
+    ops = R.VecOps(n, 0, DEV)
+    out = torch.zeros(2, dtype=torch.float64, device=DEV)
+    ta, tb = torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)
+    ops.dot(ta, tb, out[0:1])
+    ops.dot(ta, tb, out[1:2])
+    o = out.cpu().numpy()
+    ref = float(np.sum(a.astype(np.float64) * b.astype(np.float64)))
+    assert abs(o[0] - ref) <= 1e-12 * np.sum(np.abs(a.astype(np.float64) * b))
+    assert o[0] == o[1]
+
+
+def test_vec_axpby_and_aliasing():
+    require_gpu()
+    n = 100_003
+    r = np.random.default_rng(1)
+    a = r.normal(size=n).astype(np.float32)
+    b = r.normal(size=n).astype(np.float32)
+    ops = R.VecOps(n, 0, DEV)
+    ta, tb = torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)
+    out = torch.empty_like(ta)
+    ops.axpby(0.5, ta, -2.0, tb, out)
+    np.testing.assert_allclose(out.cpu().numpy(), 0.5 * a - 2.0 * b, rtol=1e-6, atol=1e-6)
+    ops.axpby(1.0, ta, 3.0, tb, ta)  # out aliases a
+    np.testing.assert_allclose(ta.cpu().numpy(), a + 3.0 * b, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("m,order", [(4, []), (4, [2, 1, 0]), (6, [1, 0, 5, 4, 3])])
+def test_lbfgs_direction_matches_oracle_two_loop(m, order):
+    """Ring-ordered FP32 history on the device against the FP64 two-loop recursion of the
+    same pairs (oldest first)."""
+    require_gpu()
+    say(f"recon: two-loop m={m} order={order}")
+    n = 50_000
+    r = np.random.default_rng(7 + m + len(order))
+    diag = np.geomspace(1.0, 50.0, n)
+    S = r.normal(size=(m, n)).astype(np.float32)
+    Y = (S * diag * (1.0 + 0.1 * r.random((m, n)))).astype(np.float32)  # s.y > 0
+    g = r.normal(size=n).astype(np.float32)
+    tS, tY = torch.from_numpy(S).to(DEV), torch.from_numpy(Y).to(DEV)
+    tg = torch.from_numpy(g).to(DEV)
+    d = torch.empty_like(tg)
+    ops = R.VecOps(n, m, DEV)
+    sy = torch.zeros(m, dtype=torch.float64, device=DEV)
+    yy = torch.zeros(m, dtype=torch.float64, device=DEV)
+    for i in range(m):
+        ops.dot(tS[i], tY[i], sy[i:i + 1])
+        ops.dot(tY[i], tY[i], yy[i:i + 1])
+    ops.direction(tg, d, order, tS, tY, sy, yy)
+    S64, Y64 = S.astype(np.float64), Y.astype(np.float64)
+    oldest_first = list(reversed(order))
+    ref = -LB.two_loop(g.astype(np.float64), [S64[i] for i in oldest_first],
+                       [Y64[i] for i in oldest_first])
+    got = d.cpu().numpy().astype(np.float64)
+    if not order:
+        assert np.array_equal(got, -g.astype(np.float64))
+    assert rel_l2(got, ref) < 1e-5, rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("n,nbins", [(16, 16), (32, 28), (64, 56)])
+def test_power_bins_match_oracle(n, nbins):
+    require_gpu()
+    say(f"recon: power bins n={n}")
+    box = 250.0
+    a = np.fft.rfftn(synth.unit_normal(31, (n, n, n))).astype(np.complex64)
+    b = (0.7 * a + np.fft.rfftn(synth.unit_normal(32, (n, n, n)))).astype(np.complex64)
+    ta, tb = torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)
+    got = R.power_bins(ta, tb, n, box, nbins).cpu().numpy()
+    ref = ST.power_bins(a.astype(np.complex128), b.astype(np.complex128), box, nbins)
+    np.testing.assert_array_equal(got[0], ref[0])  # shell counts are integers
+    for q in range(1, 4):
+        np.testing.assert_allclose(got[q], ref[q], rtol=1e-10, atol=1e-300)
+    got2 = R.power_bins(ta, tb, n, box, nbins).cpu().numpy()
+    assert np.array_equal(got, got2)
+
+
+def _l2_problem(n, steps, seed_true=21, seed_start=22):
+    box = 100.0
+    ocfg = OM.Config(box, n, n, n, steps, loss_kind=OM.LOSS_DENSITY_L2)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    s_true = OM.linear_modes(synth.white_noise(seed_true, n), box, power)
+    target = OM.forward(ocfg, s_true, inv, np.zeros((n, n, n)), OM.default_params())["delta_f"]
+    s0 = np.sqrt(0.1) * OM.linear_modes(synth.white_noise(seed_start, n), box, power)
+    return ocfg, inv, s_true, target, s0
+
+
+def test_gpu_lbfgs_follows_the_oracle_driver():
+    """The same L-BFGS on the density-L2 problem (16^3, 3 steps) with the GPU gradient and
+    the FP64 oracle gradient: the loss trajectories agree over the first iterations, both
+    recover the large scales."""
+    require_gpu()
+    say("recon: L-BFGS GPU vs oracle, 16^3 density-L2")
+    n, iters = 16, 12
+    ocfg, inv, s_true, target, s0 = _l2_problem(n, 3)
+
+    def fg(s):
+        fwd, G = OM.gradient(ocfg, s, inv, target, OM.default_params())
+        return fwd["loss"], G
+
+    xo, fo, info = LB.minimize(fg, s0, max_iter=iters, rel_tol=0.0)
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, box=ocfg.box,
+                   loss_kind=P.PMR_LOSS_DENSITY_L2)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+    pm.set_loss(P.LossParams())
+    modes = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+    res = R.minimize(pm, modes, max_iter=iters, rel_tol=0.0)
+    Lg, Lo = np.array(res.losses), np.array(info["losses"])
+    say(f"  gpu {Lg[:5]} ... {Lg[-1]:.4f} ({res.evals} evals); oracle {Lo[-1]:.4f} "
+        f"({info['evals']} evals)")
+    k = min(len(Lg), len(Lo), 6)
+    np.testing.assert_allclose(Lg[:k], Lo[:k], rtol=2e-3)
+    assert abs(Lg[-1] - Lo[-1]) <= 0.05 * Lo[-1]
+    assert all(b <= a for a, b in zip(Lg, Lg[1:]))
+    xg = modes.cpu().numpy().reshape(s0.shape).astype(np.complex128)
+    rc_g, _, _ = ST.metrics(*ST.power_bins(s_true, xg, ocfg.box, 6)[1:])
+    rc_o, _, _ = ST.metrics(*ST.power_bins(s_true, xo, ocfg.box, 6)[1:])
+    assert np.all(rc_g[1:4] > 0.9) and np.all(np.abs(rc_g[1:4] - rc_o[1:4]) < 0.02)
+
+
+def test_gpu_anneal_stages_lognormal():
+    """Two log-normal stages (R_sm = 2 then 0) through the driver: each stage's losses never
+    increase and the second stage starts from the first stage's optimum."""
+    require_gpu()
+    say("recon: anneal stages, 16^3 log-normal")
+    n, box = 16, 100.0
+    ocfg = OM.Config(box, n, n, n, 3, loss_kind=OM.LOSS_LOGNORMAL)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    s_true = OM.linear_modes(synth.white_noise(21, n), box, power)
+    w = synth.mlp_weights(3, 8)
+    target = OM.forward(ocfg, s_true, inv, np.ones((n, n, n)), OM.default_params(), w)["mass"]
+    s0 = np.sqrt(0.1) * OM.linear_modes(synth.white_noise(22, n), box, power)
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, mlp_hidden=8, box=box)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+    pm.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+    M0 = float(np.median(target))
+    modes = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+    stages = [P.LossParams(M0=M0, R_sm=2.0), P.LossParams(M0=M0, R_sm=0.0)]
+    out = R.reconstruct(pm, modes, stages, max_iter=4)
+    for st in out:
+        assert all(b <= a for a, b in zip(st.losses, st.losses[1:])), st.losses
+        assert st.evals >= st.iters + 1
+    # the second stage's first loss is the first stage's optimum under R_sm = 0
+    pm2 = P.PMContext(cfg, DEV)
+    pm2.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm2.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+    pm2.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+    pm2.set_loss(stages[0])
+    m2 = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+    R.minimize(pm2, m2, max_iter=4)
+    pm2.set_loss(stages[1])
+    _, loss = pm2.forward(m2, want_mass=False)
+    assert float(loss[0, 0]) == out[1].losses[0]
