@@ -248,6 +248,90 @@ def mixed_vs_fp32(dev, steps):
     return res
 
 
+def reconstruction_leg(dev, iterations=200, nbins=64):
+    """The reconstruction loop at 128^3 (one realisation, 5 PM steps, the 3-32-32-1 network,
+    L = 400 Mpc/h): target = the model mass of hidden modes (seed 4000) times log-normal
+    scatter exp(0.3 eps) (eps seed 4001); start = independent modes (seed 4002) at 10% of the
+    fiducial power; L-BFGS over the anneal stages R_sm = 4, 2, 1, 0 Mpc/h at M0 = the 75th
+    percentile of the target (25% of the cells above it), then R_sm = 1, 0 at the median
+    (50% above), at most iterations / 6 iterations per stage. Run in FP32 and in mixed
+    precision: wall time, evaluations, final loss, the time the mixed path takes to reach
+    the FP32 final loss, and the cross-correlation r_c of the recovered with the true modes
+    per k shell."""
+    import torch
+
+    import synth
+    import paper_1805_02247_amd as P
+    from paper_1805_02247_amd import cosmo
+    from paper_1805_02247_amd import recon as R
+
+    n, box, steps, H = 128, 400.0, 5, 32
+    power = cosmo.linear_power(0.8, 0.2)
+
+    def modes(seed, scale=1.0):
+        m = cosmo.modes_from_white_noise(synth.white_noise(seed, n), box, power) * scale
+        return torch.from_numpy(m.astype(np.complex64).reshape(1, -1)).to(dev)
+
+    true = modes(4000)
+    out = {"workload": "128^3 particles/mesh, L = 400 Mpc/h, 5 PM steps, 3-32-32-1 network, "
+                       "one realisation", "iteration_budget": iterations}
+    target, stages, l32 = None, None, None
+    for name, prec in (("fp32", P.PMR_FP32), ("mixed", P.PMR_MIXED)):
+        cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=steps, mlp_hidden=H,
+                       precision=prec, box=box, loss_kind=P.PMR_LOSS_LOGNORMAL)
+        pm = P.PMContext(cfg, dev)
+        pm.set_prior(torch.from_numpy(cosmo.prior_inv_variance(n, box, power)))
+        pm.set_mlp({k: torch.from_numpy(v) for k, v in synth.mlp_weights(3, H).items()})
+        if target is None:
+            pm.set_target(torch.ones(1, n ** 3, device=dev))
+            pm.set_loss(P.LossParams(M0=1.0))
+            mass, _ = pm.forward(true)
+            eps = torch.from_numpy(synth.unit_normal(4001, (1, n ** 3)).astype(np.float32)).to(dev)
+            target = (mass * torch.exp(0.3 * eps)).contiguous()
+            tc = target.cpu().numpy()
+            M0a, M0b = float(np.percentile(tc, 75)), float(np.percentile(tc, 50))
+            stages = ([P.LossParams(M0=M0a, R_sm=r) for r in (4.0, 2.0, 1.0, 0.0)] +
+                      [P.LossParams(M0=M0b, R_sm=r) for r in (1.0, 0.0)])
+        pm.set_target(target)
+        x = modes(4002, np.sqrt(0.1))
+        x0 = x.clone()
+        cap = iterations // len(stages)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = []
+        for i, p in enumerate(stages):
+            pm.set_loss(p)
+            last = i == len(stages) - 1
+            res.append(R.minimize(pm, x, max_iter=cap,
+                                  stop_below=l32 if (name == "mixed" and last) else None))
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        final = res[-1].losses[-1]
+        ev = sum(r.evals for r in res)
+        leg = {"seconds": T, "iterations": sum(r.iters for r in res), "evaluations": ev,
+               "ms_per_evaluation": 1e3 * T / ev, "final_loss": final,
+               "stages": [{"R_sm": st.R_sm, "M0": st.M0,
+                           "iters": r.iters, "evals": r.evals, "loss": r.losses[-1],
+                           "stop": r.reason} for r, st in zip(res, stages)]}
+        if name == "fp32":
+            l32 = final
+        else:
+            leg["reached_fp32_loss"] = final <= l32
+            leg["seconds_to_fp32_loss"] = T if final <= l32 else None
+        rc, _, tf = R.metrics(R.power_bins(true, x, n, box, nbins))
+        leg["r_c"] = [round(float(v), 4) for v in rc]
+        leg["transfer"] = [round(float(v), 4) for v in tf]
+        if name == "fp32":
+            rc0, _, _ = R.metrics(R.power_bins(true, x0, n, box, nbins))
+            out["r_c_start"] = [round(float(v), 4) for v in rc0]
+        out[name] = leg
+        del pm
+        torch.cuda.empty_cache()
+    out["k_h_per_mpc"] = [round((i + 0.5) * 2 * np.pi / box, 5) for i in range(nbins)]
+    out["speedup_mixed_over_fp32"] = out["fp32"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +343,8 @@ def main():
                     help="skip timing the HIP-graph replay of a gradient evaluation")
     ap.add_argument("--no-256", action="store_true",
                     help="skip the 256^3/512^3 mixed-precision vs FP32 comparison")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the 128^3 reconstruction loop (L-BFGS over the anneal stages)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for counters)")
     args = ap.parse_args()
@@ -361,6 +447,8 @@ def main():
         del pm, modes, grad
         torch.cuda.empty_cache()
         out["at_256"] = mixed_vs_fp32(dev, max(2, min(args.steps, 10)))
+    if not args.no_recon and args.workload == "cfg2_128":
+        out["reconstruction"] = reconstruction_leg(dev)
     print(json.dumps(out), flush=True)
 
 

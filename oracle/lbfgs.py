@@ -26,7 +26,8 @@ Readings (the paper gives no parameters of its optimiser):
 * if d is not a descent direction the history is cleared and -g is used;
 * a stage ends when the loss decreases by less than rel_tol = 1e-3 of its value between
   successive iterations (the paper's 0.1% rule, Sec. 5.3), at a zero gradient, or after
-  max_iter iterations;
+  max_iter iterations; the rule is not applied to a unit-length step taken without
+  history (its decrease says nothing about convergence);
 * the anneal stages run in order, each starting from the previous stage's optimum with an
   empty history.
 """
@@ -90,6 +91,7 @@ def minimize(fg, x0, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None):
             S, Y = [], []
             d = -g
             gd = inner(g, d)
+        probe = not S  # unit-length step without history
         t = 1.0 if S else 1.0 / np.sqrt(inner(g, g))
         ok = False
         for _ in range(MAX_HALVINGS + 1):
@@ -116,7 +118,7 @@ def minimize(fg, x0, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None):
         losses.append(f)
         if log:
             log(it, f, t, evals)
-        if rel < rel_tol:
+        if rel < rel_tol and not probe:
             reason = "converged"
             break
     return x, f, {"losses": losses, "evals": evals, "reason": reason}

@@ -15,7 +15,8 @@ history m = 10; the first iteration of a stage moves a unit distance along -g (s
 30 halvings (failure ends the stage); a pair is kept only if s.y > 1e-10 |s| |y|; a
 non-descent direction clears the history; a stage ends when the loss falls by less than
 0.1% of its value between successive iterations (Sec. 5.3), at a zero gradient, or after
-max_iter iterations; each stage starts from the previous optimum with an empty history.
+max_iter iterations (the rule is not applied to a unit-length step taken without history);
+each stage starts from the previous optimum with an empty history.
 """
 import ctypes
 import time
@@ -118,6 +119,7 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
             order = []
             ops.axpby(-1.0, g, 0.0, g, d)
             gd = -gg
+        probe = not order  # unit-length step without history
         t = 1.0 if order else 1.0 / gg ** 0.5
         ok = False
         for _ in range(MAX_HALVINGS + 1):
@@ -150,7 +152,7 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
         if stop_below is not None and f <= stop_below:
             res.reason = "target_loss"
             break
-        if rel < rel_tol:
+        if rel < rel_tol and not probe:
             res.reason = "converged"
             break
     torch.cuda.synchronize(dev)
