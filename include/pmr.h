@@ -217,7 +217,7 @@ int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
 
 /* CIC density on an n_mesh^3 mesh: out = sum_p mass W(x_p - cell) - bias, [B][n_mesh^3],
  * from the outputs of pmr_cic_sort. Deterministic (bitwise reproducible). `scratch` holds
- * the sorted fraction stream: at least 16 * B * Np^3 bytes. */
+ * the sorted fraction stream: at least 12 * B * Np^3 bytes. */
 int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x,
                   const uint32_t* keys_sorted, const uint32_t* ids_sorted,
                   const uint32_t* row_start, float mass, float bias, float* out, void* scratch,

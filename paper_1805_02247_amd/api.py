@@ -261,7 +261,7 @@ def cic_paint(x, keys, ids, rows, n_mesh, box, mass=1.0, bias=0.0):
     B, np3 = x.shape[0], x.shape[2]
     n_part = round(np3 ** (1 / 3))
     out = torch.empty(B, n_mesh ** 3, dtype=torch.float32, device=x.device)
-    scratch = torch.empty(B * np3 * 16, dtype=torch.uint8, device=x.device)
+    scratch = torch.empty(B * np3 * 12, dtype=torch.uint8, device=x.device)
     L.check(L.lib().pmr_cic_paint(n_part, n_mesh, B, float(box), _ptr(x.contiguous()), _ptr(keys),
                                   _ptr(ids), _ptr(rows), float(mass), float(bias), _ptr(out),
                                   _ptr(scratch), scratch.numel(), _stream()))

@@ -36,18 +36,18 @@ __device__ __forceinline__ uint32_t cell_key(const double* xyz, double scale, in
 
 // Key and CIC fractions (id order) of one particle on an nm mesh.
 __device__ __forceinline__ uint32_t key_frac(const double* xyz, double scale, int nm, uint32_t item,
-                                             float4* frac) {
+                                             Vec3* frac) {
   double f[3];
   const int ix = cic_corner(xyz[0], scale, nm, &f[0]);
   const int iy = cic_corner(xyz[1], scale, nm, &f[1]);
   const int iz = cic_corner(xyz[2], scale, nm, &f[2]);
-  *frac = make_float4((float)f[0], (float)f[1], (float)f[2], 0.f);
+  *frac = Vec3{(float)f[0], (float)f[1], (float)f[2]};
   const uint32_t cells = (uint32_t)nm * nm * nm;
   return item * cells + ((uint32_t)ix * nm + iy) * nm + iz;
 }
 
 __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total, double scale,
-                            int nm, uint32_t* __restrict__ keys, float4* __restrict__ frac) {
+                            int nm, uint32_t* __restrict__ keys, Vec3* __restrict__ frac) {
   const int g = blockIdx.x * TB + threadIdx.x;
   if (g >= total) return;
   const size_t np3 = (size_t)1 << log_np3;
@@ -55,7 +55,7 @@ __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total
   const size_t id = g & (np3 - 1);
   const double* xi = x + (size_t)item * 3 * np3 + id;
   double p[3] = {xi[0], xi[np3], xi[2 * np3]};
-  float4 f;
+  Vec3 f;
   keys[g] = key_frac(p, scale, nm, item, &f);
   if (frac) frac[g] = f;
 }
@@ -117,8 +117,8 @@ __global__ __launch_bounds__(SORT_TB) void radix_scatter_kernel(const uint32_t* 
                                                            const uint32_t* __restrict__ digit_total,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ ids_out,
-                                                           const float4* __restrict__ pay_in,
-                                                           float4* __restrict__ pay_out,
+                                                           const Vec3* __restrict__ pay_in,
+                                                           Vec3* __restrict__ pay_out,
                                                            uint32_t* __restrict__ inv_out) {
   constexpr int NBK = 1 << D;
   __shared__ uint32_t cnt[SORT_WAVES][NBK];
@@ -312,7 +312,7 @@ __global__ void row_start_kernel(const uint32_t* __restrict__ keys, int n, int l
 __global__ __launch_bounds__(TB) void stream_frac_kernel(const uint32_t* __restrict__ ids,
                                                          const double* __restrict__ x, int total,
                                                          int log_np3, double scale, int nm,
-                                                         float4* __restrict__ frac) {
+                                                         Vec3* __restrict__ frac) {
   const int j = blockIdx.x * TB + threadIdx.x;
   if (j >= total) return;
   const size_t np3 = (size_t)1 << log_np3;
@@ -322,13 +322,13 @@ __global__ __launch_bounds__(TB) void stream_frac_kernel(const uint32_t* __restr
   cic_corner(x[pi], scale, nm, &fx);
   cic_corner(x[pi + np3], scale, nm, &fy);
   cic_corner(x[pi + 2 * np3], scale, nm, &fz);
-  frac[j] = make_float4((float)fx, (float)fy, (float)fz, 0.f);
+  frac[j] = Vec3{(float)fx, (float)fy, (float)fz};
 }
 
-// Per sorted position j: the payload of particle ids[j] (id-order float4 -> sorted order).
+// Per sorted position j: the payload of particle ids[j] (id-order Vec3 -> sorted order).
 __global__ __launch_bounds__(TB) void stream_gather_kernel(const uint32_t* __restrict__ ids,
-                                                           const float4* __restrict__ src,
-                                                           int total, float4* __restrict__ dst) {
+                                                           const Vec3* __restrict__ src,
+                                                           int total, Vec3* __restrict__ dst) {
   const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= total) return;
   dst[j] = src[ids[j]];
@@ -401,9 +401,9 @@ struct StepArgs {
   const double* x;    // [B][3][Np^3] positions x_i
   double* x_next;     // positions x_{i+1}
   float* p;           // momenta, updated in place
-  const Force3* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz) at x_i
+  const Vec3* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz) at x_i
   uint32_t* keys;     // keys of x_{i+1} (nullable)
-  float4* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
+  Vec3* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
   int log_np3, nm, total;
   double scale, box;
   float kick;
@@ -424,14 +424,14 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   const int nm = a.nm;
   const Corner c = corner_of(xyz, a.scale, nm);
   const size_t cells = (size_t)nm * nm * nm;
-  const Force3* F = a.F + (size_t)item * cells;
+  const Vec3* F = a.F + (size_t)item * cells;
   float fa[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
     const float w = (ox ? c.f[0] : 1.f - c.f[0]) * (oy ? c.f[1] : 1.f - c.f[1]) *
                      (oz ? c.f[2] : 1.f - c.f[2]);
-    const Force3 f = F[cidx(c, ox, oy, oz, nm)];
+    const Vec3 f = F[cidx(c, ox, oy, oz, nm)];
     fa[0] += w * f.x;
     fa[1] += w * f.y;
     fa[2] += w * f.z;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
     a.x_next[pi + q * np3] = xn[q];
   }
   if (a.keys) {
-    float4 f;
+    Vec3 f;
     a.keys[g] = key_frac(xn, a.key_scale, a.key_nm, item, &f);
     a.frac[g] = f;
   }
@@ -459,12 +459,12 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
 // stream. Written to g_out[id] (id order) for the update below.
 struct AdjPosArgs {
   const uint32_t* keys;  // sorted keys
-  const float4* frac;    // sorted fractions
-  const float4* fbar;    // sorted Fbar (nullable: final-paint adjoint, no force term)
+  const Vec3* frac;    // sorted fractions
+  const Vec3* fbar;    // sorted Fbar (nullable: final-paint adjoint, no force term)
   const uint32_t* ids;   // sorted ids
-  const Force3* F;       // interleaved force mesh at x_i [B][nm^3] (nullable with fbar)
+  const Vec3* F;       // interleaved force mesh at x_i [B][nm^3] (nullable with fbar)
   const float* dbar;     // density adjoint mesh [B][nm^3]
-  float4* g_out;         // [B * Np^3], id order
+  Vec3* g_out;         // [B * Np^3], id order
   int nm, log_nm, total;
   float scale, mass;
 };
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
   const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= a.total) return;
   const uint32_t key = a.keys[j];
-  const float4 fr = a.frac[j];
+  const Vec3 fr = a.frac[j];
   const int nm = a.nm, lg = a.log_nm;
   const uint32_t item = key >> (3 * lg);
   const uint32_t i0[3] = {(key >> (2 * lg)) & (uint32_t)(nm - 1), (key >> lg) & (uint32_t)(nm - 1),
@@ -484,12 +484,12 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
   const size_t cells = (size_t)1 << (3 * lg);
   float fb[3] = {0.f, 0.f, 0.f};
   if (a.fbar) {
-    const float4 v = a.fbar[j];
+    const Vec3 v = a.fbar[j];
     fb[0] = v.x;
     fb[1] = v.y;
     fb[2] = v.z;
   }
-  const Force3* F = a.F ? a.F + (size_t)item * cells : nullptr;
+  const Vec3* F = a.F ? a.F + (size_t)item * cells : nullptr;
   const float* D = a.dbar + (size_t)item * cells;
   const float s = a.scale;
   float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -504,24 +504,24 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
                         (oz ? i1[2] : i0[2]);
     float v = a.mass * D[ci];
     if (F) {
-      const Force3 fv = F[ci];
+      const Vec3 fv = F[ci];
       v += fb[0] * fv.x + fb[1] * fv.y + fb[2] * fv.z;
     }
     gx += dx * wy * wz * v;
     gy += wx * dy * wz * v;
     gz += wx * wy * dz * v;
   }
-  a.g_out[a.ids[j]] = make_float4(gx, gy, gz, 0.f);
+  a.g_out[a.ids[j]] = Vec3{gx, gy, gz};
 }
 
 struct AdjArgs {
   float* xbar;          // in: xbar_{i+1}; out: xbar_i
   float* pbar;          // in: pbar_{i+1/2}; out: pbar_{i-1/2}
-  const float4* gpos;   // position gradient of the step (id order)
+  const Vec3* gpos;   // position gradient of the step (id order)
   int log_np3, total;
   float kick, drift;
   int final_mode;       // 1: xbar = gpos, pbar = 0
-  float4* vnext;        // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
+  Vec3* vnext;        // nullable: kick' * (pbar_new + drift' * xbar_new) for the next
   float kick_next, drift_next;  // reverse step (its adjoint paint values)
   const uint32_t* vperm;  // nullable: sorted position of each particle in the next reverse
                           // step's sort (vnext is then written in that sort order)
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(TB) void adjoint_update_kernel(AdjArgs a) {
       pb[q] = a.pbar[pi + q * np3] + a.drift * xb[q];
     }
   }
-  const float4 gp = a.gpos[g];
+  const Vec3 gp = a.gpos[g];
   const float xn[3] = {xb[0] + gp.x, xb[1] + gp.y, xb[2] + gp.z};
   a.xbar[pi] = xn[0];
   a.xbar[pi + np3] = xn[1];
@@ -553,9 +553,10 @@ __global__ __launch_bounds__(TB) void adjoint_update_kernel(AdjArgs a) {
   a.pbar[pi + np3] = pb[1];
   a.pbar[pi + 2 * np3] = pb[2];
   if (a.vnext)
-    a.vnext[a.vperm ? a.vperm[g] : (uint32_t)g] = make_float4(a.kick_next * (pb[0] + a.drift_next * xn[0]),
-                             a.kick_next * (pb[1] + a.drift_next * xn[1]),
-                             a.kick_next * (pb[2] + a.drift_next * xn[2]), 0.f);
+    a.vnext[a.vperm ? a.vperm[g] : (uint32_t)g] =
+        Vec3{a.kick_next * (pb[0] + a.drift_next * xn[0]),
+             a.kick_next * (pb[1] + a.drift_next * xn[1]),
+             a.kick_next * (pb[2] + a.drift_next * xn[2])};
 }
 
 // Zel'dovich start: x0 = wrap(q + D0 Psi), p0 = Gp0 Psi; q = idx * (box/np) + box / (2 nm).
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
                                                      double half_cell, double D0, float Gp0,
                                                      double* __restrict__ x, float* __restrict__ p,
                                                      uint32_t* __restrict__ keys,
-                                                     float4* __restrict__ frac, int key_nm,
+                                                     Vec3* __restrict__ frac, int key_nm,
                                                      double key_scale) {
   const int g = blockIdx.x * TB + threadIdx.x;
   if (g >= total) return;
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
     x[pi + q * np3] = xn[q];
     p[pi + q * np3] = Gp0 * ps;
   }
-  float4 f;
+  Vec3 f;
   keys[g] = key_frac(xn, key_scale, key_nm, item, &f);
   frac[g] = f;
 }
@@ -603,7 +604,7 @@ size_t sort_scratch_bytes(int n, int key_bits) {
 template <int D>
 static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
                       int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* dtot,
-                      const float4* pin, float4* pout, uint32_t* inv, hipStream_t s) {
+                      const Vec3* pin, Vec3* pout, uint32_t* inv, hipStream_t s) {
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
   radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
   digit_scan_kernel<<<1 << D, TB, 0, s>>>(hist, nb, offs, dtot);
@@ -614,7 +615,7 @@ static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, 
 // Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
 // and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
 void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
+                 uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
                  hipStream_t s, uint32_t* inv) {
   const int passes = (key_bits + 8) / 9;
   const int D = (key_bits + passes - 1) / passes;
@@ -656,7 +657,7 @@ void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
 }
 
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
-                 float4* frac, hipStream_t s) {
+                 Vec3* frac, hipStream_t s) {
   keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys, frac);
 }
 
@@ -689,17 +690,17 @@ static void paint_dispatch(const PaintArgs& a, int batch, hipStream_t s) {
 }
 
 void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,
-                        double box, float4* frac, hipStream_t s) {
+                        double box, Vec3* frac, hipStream_t s) {
   stream_frac_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, x, total, log_np3,
                                                           (double)nm / box, nm, frac);
 }
 
-void launch_stream_gather(const uint32_t* ids, const float4* src, int total, float4* dst,
+void launch_stream_gather(const uint32_t* ids, const Vec3* src, int total, Vec3* dst,
                           hipStream_t s) {
   stream_gather_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(ids, src, total, dst);
 }
 
-void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
+void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* row_start,
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s) {
   PaintArgs a{};
   a.keys = keys;
@@ -715,7 +716,7 @@ void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t*
   paint_dispatch<1>(a, batch, s);
 }
 
-void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
+void launch_paint_adj3(const uint32_t* keys, const Vec3* frac, const Vec3* val,
                        const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s) {
   PaintArgs a{};
   a.keys = keys;
@@ -730,8 +731,8 @@ void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* v
   paint_dispatch<3>(a, batch, s);
 }
 
-void launch_kick_drift(const double* x, double* x_next, float* p, const Force3* F, uint32_t* keys,
-                       float4* frac, int batch, int log_np3, int nm, double box, float kick,
+void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,
+                       Vec3* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s) {
   StepArgs a{};
   a.frac = frac;
@@ -752,9 +753,9 @@ void launch_kick_drift(const double* x, double* x_next, float* p, const Force3* 
   kick_drift_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
-void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
-                              const uint32_t* ids, const Force3* F, const float* dbar, int total,
-                              int nm, double box, float mass, float4* g_out, hipStream_t s) {
+void launch_adjoint_positions(const uint32_t* keys, const Vec3* frac, const Vec3* fbar,
+                              const uint32_t* ids, const Vec3* F, const float* dbar, int total,
+                              int nm, double box, float mass, Vec3* g_out, hipStream_t s) {
   AdjPosArgs a{};
   a.keys = keys;
   a.frac = frac;
@@ -773,8 +774,8 @@ void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const fl
   adjoint_positions_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
-void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
-                           float kick, float drift, int final_mode, float4* vnext, float kick_next,
+void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch, int log_np3,
+                           float kick, float drift, int final_mode, Vec3* vnext, float kick_next,
                            float drift_next, const uint32_t* vperm, hipStream_t s) {
   AdjArgs a{};
   a.xbar = xbar;
@@ -793,7 +794,7 @@ void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int bat
 }
 
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, Vec3* frac,
                     int key_nm, hipStream_t s) {
   const int total = batch << log_np3;
   za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, np, log_np3, total, box, half_cell, D0,

@@ -431,7 +431,7 @@ struct ZTile3 {
 
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict__ in, FieldMap im,
-                                                        Force3* __restrict__ out,
+                                                        Vec3* __restrict__ out,
                                                         size_t out_item_stride,
                                                         int tiles_per_item, int ntiles) {
   using T = ZTile<N>;
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
     fft_lds<H, 3 * R, 1, PITCH, 2, +1, NT, true>(lds, tw);
     const int item = tau / tiles_per_item;
     const size_t row0 = (size_t)(tau % tiles_per_item) * R;
-    Force3* dst = out + item * out_item_stride + row0 * N;
+    Vec3* dst = out + item * out_item_stride + row0 * N;
     const float* l = reinterpret_cast<const float*>(lds);
     static_assert((R * N) % NT == 0, "whole rows per thread sweep");
 #pragma unroll
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
       const int e = threadIdx.x + m * NT;
       const int r = e / N, zz = e % N;
       const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
-      dst[e] = Force3{l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
+      dst[e] = Vec3{l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
                       l[(2 * R + r) * 2 * PITCH + q]};
     }
     if (next >= ntiles) break;
@@ -786,7 +786,7 @@ void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, 
 }
 
 template <int N>
-void zc2r3(int items, const float2* in, FieldMap im, Force3* out, size_t out_item_stride,
+void zc2r3(int items, const float2* in, FieldMap im, Vec3* out, size_t out_item_stride,
            hipStream_t s) {
   const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
   const int res = resident_grid<zpass_c2r3_kernel<N>, NT>();

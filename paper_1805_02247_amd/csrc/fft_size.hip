@@ -21,7 +21,7 @@ void PMR_CAT(fft_zc2r_, PMR_FFT_SIZE)(int fields, const float2* in, FieldMap im,
   zc2r<PMR_FFT_SIZE>(fields, in, im, out, om, add, s);
 }
 
-void PMR_CAT(fft_zc2r3_, PMR_FFT_SIZE)(int items, const float2* in, FieldMap im, Force3* out,
+void PMR_CAT(fft_zc2r3_, PMR_FFT_SIZE)(int items, const float2* in, FieldMap im, Vec3* out,
                                        size_t out_item_stride, hipStream_t s) {
   zc2r3<PMR_FFT_SIZE>(items, in, im, out, out_item_stride, s);
 }

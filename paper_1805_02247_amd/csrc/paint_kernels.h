@@ -71,7 +71,7 @@ __device__ __forceinline__ void load_chunk(const PaintArgs& a, uint32_t j, uint3
   for (int q = 0; q < 4 * C; ++q) ch.v[q] = 0.f;
   if (ch.ok) {
     const uint32_t key = a.keys[j];
-    const float4 f = a.frac[j];
+    const Vec3 f = a.frac[j];
     ch.key = key;
     ch.iz = (int)(key & (uint32_t)(nm - 1));
     ch.sy = (int)((key >> a.log_nm) & (uint32_t)(nm - 1));
@@ -80,7 +80,7 @@ __device__ __forceinline__ void load_chunk(const PaintArgs& a, uint32_t j, uint3
     if constexpr (C == 1) {
       val[0] = a.mass * wx;
     } else {
-      const float4 u = a.val[j];
+      const Vec3 u = a.val[j];
       val[0] = u.x * wx;
       val[1] = u.y * wx;
       val[2] = u.z * wx;

@@ -108,10 +108,10 @@ struct pmr_ctx {
   float* ckp;
   int n_ck;
   float* p;     // [B][3][np3]
-  Force3* F;    // force slots [SF][B][nm3], interleaved (Fx, Fy, Fz)
+  Vec3* F;    // force slots [SF][B][nm3], interleaved (Fx, Fy, Fz)
   uint32_t* ids;   // sort slots [SF][B*np3]
   uint32_t* skeys; // sorted keys [SF][B*np3]
-  float4* frac;    // sorted CIC fractions [SF][B*np3]
+  Vec3* frac;    // sorted CIC fractions [SF][B*np3]
   uint32_t* rows;  // [SF][B*nm*nm + 1]
   uint32_t* inv;   // inverse sort permutations (sorted position of each id) [SF][B*np3]
   int n_fslots;
@@ -120,11 +120,11 @@ struct pmr_ctx {
   void* sort_scratch;
   size_t sort_scratch_bytes;
   uint32_t* ids_o;
-  float4* frac_o;
-  float4* frac_id;  // CIC fractions of the current positions, id order [B*np3]
-  float4* vid;      // adjoint paint values of the next reverse step, id order [B*np3]
-  float4* vstream;  // the same in sorted order [B*np3]
-  float4* gpos;     // position gradient of the current step adjoint, id order [B*np3]
+  Vec3* frac_o;
+  Vec3* frac_id;  // CIC fractions of the current positions, id order [B*np3]
+  Vec3* vid;      // adjoint paint values of the next reverse step, id order [B*np3]
+  Vec3* vstream;  // the same in sorted order [B*np3]
+  Vec3* gpos;     // position gradient of the current step adjoint, id order [B*np3]
   uint32_t* rows_o;
   float2* cA;    // [B][cmax]
   float2* cB;    // [B][3][cmax]
@@ -208,10 +208,10 @@ void plan(pmr_ctx* c, Plan& P) {
   c->ckx = P.take<double>((size_t)c->n_ck * B * 3 * c->np3);
   c->ckp = P.take<float>((size_t)c->n_ck * B * 3 * c->np3);
   c->p = P.take<float>(B * 3 * c->np3);
-  c->F = P.take<Force3>((size_t)c->n_fslots * B * c->nm3);
+  c->F = P.take<Vec3>((size_t)c->n_fslots * B * c->nm3);
   c->ids = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
   c->skeys = P.take<uint32_t>((size_t)c->n_fslots * B * c->np3);
-  c->frac = P.take<float4>((size_t)c->n_fslots * B * c->np3);
+  c->frac = P.take<Vec3>((size_t)c->n_fslots * B * c->np3);
   c->rows = P.take<uint32_t>((size_t)c->n_fslots * (B * c->nm * c->nm + 1));
   c->inv = P.take<uint32_t>(direct_sorted_values(c) ? (size_t)c->n_fslots * B * c->np3 : 0);
   c->keys = P.take<uint32_t>(B * c->np3);
@@ -223,11 +223,11 @@ void plan(pmr_ctx* c, Plan& P) {
   }
   c->sort_scratch = P.take<char>(c->sort_scratch_bytes);
   c->ids_o = P.take<uint32_t>(B * c->np3);
-  c->frac_o = P.take<float4>(B * c->np3);
-  c->frac_id = P.take<float4>(B * c->np3);
-  c->vid = P.take<float4>(B * c->np3);
-  c->vstream = P.take<float4>(B * c->np3);
-  c->gpos = P.take<float4>(B * c->np3);
+  c->frac_o = P.take<Vec3>(B * c->np3);
+  c->frac_id = P.take<Vec3>(B * c->np3);
+  c->vid = P.take<Vec3>(B * c->np3);
+  c->vstream = P.take<Vec3>(B * c->np3);
+  c->gpos = P.take<Vec3>(B * c->np3);
   c->rows_o = P.take<uint32_t>(B * c->no * c->no + 1);
   c->cA = P.take<float2>(B * c->cmax);
   c->cB = P.take<float2>(B * 3 * c->cmax);
@@ -344,7 +344,7 @@ FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride, size_t pitch = 0)
   return m;
 }
 
-PaintArgs paint_args(const uint32_t* keys, const float4* frac, const float4* val,
+PaintArgs paint_args(const uint32_t* keys, const Vec3* frac, const Vec3* val,
                      const uint32_t* rows, int nm, float mass, float bias) {
   PaintArgs a{};
   a.keys = keys;
@@ -412,7 +412,7 @@ void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, siz
 
 // Spectra of the three force components after the x pass -> interleaved force mesh.
 void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_comp_stride,
-             Force3* out) {
+             Vec3* out) {
   const int fields = c->B * 3;
   const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
   {
@@ -446,10 +446,10 @@ void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, con
 
 // ---------------------------------------------------------------- PM pieces
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
-Force3* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
+Vec3* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
 uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
-float4* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
+Vec3* fracslot(pmr_ctx* c, int s) { return c->frac + (size_t)s * c->B * c->np3; }
 uint32_t* invslot(pmr_ctx* c, int s) {
   return direct_sorted_values(c) ? c->inv + (size_t)s * c->B * c->np3 : nullptr;
 }
@@ -494,7 +494,7 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
     ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * c->cm);
     launch_xpass(XOP_FORCE, a, c->stream);
   }
-  Force3* F = fslot(c, fsl);
+  Vec3* F = fslot(c, fsl);
   c2r_yz3(c, c->nm, c->cB, 3 * cm, cm, F);
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
@@ -937,7 +937,7 @@ long long pmr_debug_copy(pmr_ctx* c, int what, int step, void* dst) {
       }
       if (what == PMR_DBG_FORCE) {
         src = fslot(c, sl);
-        bytes = B * c->nm3 * sizeof(Force3);
+        bytes = B * c->nm3 * sizeof(Vec3);
       } else {
         src = idslot(c, sl);
         bytes = B * c->np3 * sizeof(uint32_t);
@@ -1059,9 +1059,9 @@ int pmr_cic_paint(int n_part, int n_mesh, int batch, double box, const double* x
       (double)batch * n_mesh * n_mesh * n_mesh > 4294967296.0)
     return PMR_E_SHAPE;
   const int total = (int)(batch * np3);
-  if (scratch_bytes < (size_t)total * sizeof(float4)) return PMR_E_WORKSPACE;
+  if (scratch_bytes < (size_t)total * sizeof(Vec3)) return PMR_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  float4* frac = (float4*)scratch;
+  Vec3* frac = (Vec3*)scratch;
   launch_stream_frac(ids_sorted, x, total, ilog2(np3), n_mesh, box, frac, s);
   launch_paint_mass(keys_sorted, frac, row_start, batch, n_mesh, mass, bias, out, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;

@@ -101,16 +101,17 @@ struct FieldMap {
 #define PMR_PAINT_LDS_FLOATS 1024
 #endif
 
-// One cell of the force mesh: (F_x, F_y, F_z), 12 bytes, cells contiguous, so that a CIC
-// corner is one three-dword load.
-struct Force3 {
+// Three floats, 12 bytes: a cell of the force mesh (F_x, F_y, F_z), so that a CIC corner is
+// one three-dword load, and an element of the per-particle streams (CIC fractions, adjoint
+// paint values, position gradients).
+struct Vec3 {
   float x, y, z;
 };
 
 struct PaintArgs {
   const uint32_t* keys;     // sorted keys
-  const float4* frac;       // sorted fractions
-  const float4* val;        // sorted values (C = 3), or nullptr (C = 1, constant mass)
+  const Vec3* frac;       // sorted fractions
+  const Vec3* val;        // sorted values (C = 3), or nullptr (C = 1, constant mass)
   const uint32_t* row_start;
   int nm, log_nm;
   float mass, bias;
@@ -156,13 +157,13 @@ void launch_zpass_r2c(int n, int fields, const float* in, FieldMap im, const flo
 void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* out, FieldMap om,
                       const float* add, hipStream_t s);
 // Inverse z pass of the three components of a vector field per item (im: 3 fields per item)
-// into one interleaved float4 mesh [item][n^3] = (f0, f1, f2, 0).
+// into one interleaved Vec3 mesh [item][n^3] = (f0, f1, f2).
 // CIC paint of `channels` (1: mass, bias subtracted; 3: adjoint values) fused with the z pass
 // of the r2c: writes the z-transformed half spectra of the painted meshes (om: fields per
 // item = channels); the y and x passes complete the transform.
 void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2* out, FieldMap om,
                       hipStream_t s);
-void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Force3* out,
+void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Vec3* out,
                        size_t out_item_stride, hipStream_t s);
 void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
@@ -183,38 +184,38 @@ size_t sort_scratch_bytes(int n, int key_bits);
 // Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr,
 // and inv[id] = dst (the inverse permutation) when inv != nullptr.
 void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, const float4* pay_in, float4* pay_out,
+                 uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
                  hipStream_t s, uint32_t* inv = nullptr);
 void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
                       uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
-                 float4* frac, hipStream_t s);
+                 Vec3* frac, hipStream_t s);
 void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,
-                        double box, float4* frac, hipStream_t s);
-void launch_stream_gather(const uint32_t* ids, const float4* src, int total, float4* dst,
+                        double box, Vec3* frac, hipStream_t s);
+void launch_stream_gather(const uint32_t* ids, const Vec3* src, int total, Vec3* dst,
                           hipStream_t s);
-void launch_paint_mass(const uint32_t* keys, const float4* frac, const uint32_t* row_start,
+void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* row_start,
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s);
-void launch_paint_adj3(const uint32_t* keys, const float4* frac, const float4* val,
+void launch_paint_adj3(const uint32_t* keys, const Vec3* frac, const Vec3* val,
                        const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
-// F: interleaved force mesh [B][nm^3] float4 (Fx, Fy, Fz, unused).
-void launch_kick_drift(const double* x, double* x_next, float* p, const Force3* F, uint32_t* keys,
-                       float4* frac, int batch, int log_np3, int nm, double box, float kick,
+// F: interleaved force mesh [B][nm^3] of Vec3 (Fx, Fy, Fz).
+void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,
+                       Vec3* frac, int batch, int log_np3, int nm, double box, float kick,
                        double drift, int key_nm, hipStream_t s);
 // Position gradient of a step adjoint (or of the final paint: fbar = F = nullptr), computed in
 // sort order and written to g_out in id order:
 //   g = sum_corners dW/dx * (Fbar . F(corner) + mass * dbar(corner)).
-void launch_adjoint_positions(const uint32_t* keys, const float4* frac, const float4* fbar,
-                              const uint32_t* ids, const Force3* F, const float* dbar, int total,
-                              int nm, double box, float mass, float4* g_out, hipStream_t s);
+void launch_adjoint_positions(const uint32_t* keys, const Vec3* frac, const Vec3* fbar,
+                              const uint32_t* ids, const Vec3* F, const float* dbar, int total,
+                              int nm, double box, float mass, Vec3* g_out, hipStream_t s);
 // Kick and drift transposes with that gradient: pbar += drift xbar; xbar += g (final mode:
 // xbar = g, pbar = 0); optionally the next reverse step's paint values into vnext, in id
 // order, or in that step's sort order when vperm (its inverse permutation) is given.
-void launch_adjoint_update(float* xbar, float* pbar, const float4* gpos, int batch, int log_np3,
-                           float kick, float drift, int final_mode, float4* vnext, float kick_next,
+void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch, int log_np3,
+                           float kick, float drift, int final_mode, Vec3* vnext, float kick_next,
                            float drift_next, const uint32_t* vperm, hipStream_t s);
 void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, float4* frac,
+                    double D0, float Gp0, double* x, float* p, uint32_t* keys, Vec3* frac,
                     int key_nm, hipStream_t s);
 
 // halo.hip
