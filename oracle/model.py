@@ -174,6 +174,24 @@ def target_x(cfg, mass_target, params):
     return np.log(smooth(cfg, mass_target, params["R_mass"]) + params["M0"])
 
 
+def noise_fields(cfg, mass_target, params):
+    """Per-cell offset and width (mu_N, sigma_N) of the displaced log-normal noise (Eq.
+    probnoise). Sec. 5.1: both depend on the smoothed data mass at the cell. Without a table
+    they are the scalars of params; with params["noise_table"] = (t, mu, sigma) -- nodes t
+    ascending in log(M_R,data), natural log -- they are the linear interpolation of the
+    table at log(M_R,data), held constant beyond the end nodes (reading: the paper fits one
+    (mu, sigma) per mass bin; interpolating between bins keeps the loss continuous in the
+    data)."""
+    tab = params.get("noise_table")
+    if tab is None:
+        return params["mu"], params["sigma_N"]
+    t_nodes, mu_nodes, sig_nodes = (np.asarray(v, np.float64) for v in tab)
+    MRd = smooth(cfg, mass_target, params["R_mass"])
+    with np.errstate(divide="ignore"):
+        t = np.log(np.maximum(MRd, 0.0))
+    return np.interp(t, t_nodes, mu_nodes), np.interp(t, t_nodes, sig_nodes)
+
+
 # ------------------------------------------------------------------ forward
 
 def forward(cfg, s, inv_S, target, params, mlp=None):
@@ -198,7 +216,8 @@ def forward(cfg, s, inv_S, target, params, mlp=None):
         MR = smooth(cfg, mass, params["R_mass"])
         xd = target_x(cfg, target, params)
         xm = np.log(MR + params["M0"])
-        r = (params["mu"] + xm - xd) / (2.0 * params["sigma_N"])
+        mu_n, sig_n = noise_fields(cfg, target, params)
+        r = (mu_n + xm - xd) / (2.0 * sig_n)
         rs = smooth(cfg, r, params["R_sm"])
         out.update(features=f, mlp_cache=c, mass=mass, MR=MR, r=r, rs=rs)
         out["loss_data"] = np.sum(rs ** 2)
@@ -263,7 +282,7 @@ def halo_adjoint(cfg, fwd, target, params, mlp, loss_bar=1.0):
     """Loss -> final density contrast adjoint (log-normal likelihood, network, features)."""
     rs_bar = 2.0 * fwd["rs"] * loss_bar
     r_bar = smooth(cfg, rs_bar, params["R_sm"])
-    x_bar = r_bar / (2.0 * params["sigma_N"])
+    x_bar = r_bar / (2.0 * noise_fields(cfg, target, params)[1])
     MR_bar = x_bar / (fwd["MR"] + params["M0"])
     mass_bar = smooth(cfg, MR_bar, params["R_mass"])
     n_o = cfg.n_out

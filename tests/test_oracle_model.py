@@ -218,3 +218,81 @@ def test_gradient_finite_difference_force_mesh_twice_particles():
                    np.ones((n,) * 3), OM.default_params(), w)["mass"]
     params = OM.default_params(M0=float(np.percentile(t, 75)), R_sm=1.0)
     _fd_check(cfg, s, inv, t, params, w, seed=11)
+
+
+# ------------------------------------------------------------------ mass-dependent noise
+
+def _table_around(t, mu=(0.3, -0.1, 0.2), sig=(0.8, 0.4, 0.6)):
+    """Three interpolation nodes spanning the 10th-90th percentile of log(M_R,data)."""
+    lo, mid, hi = np.percentile(t, [10, 50, 90])
+    return (np.array([lo, mid, hi]), np.array(mu), np.array(sig))
+
+
+def _logmr(cfg, target, params):
+    with np.errstate(divide="ignore"):
+        return np.log(np.maximum(OM.smooth(cfg, target, params["R_mass"]), 0.0))
+
+
+def test_noise_table_constant_equals_scalar_model():
+    cfg, s, inv, w, t = _setup()
+    base = OM.default_params(M0=float(np.percentile(t, 50)), mu=0.1, sigma_N=0.7, R_sm=2.0)
+    tab = dict(base, noise_table=([-3.0, 0.0, 2.0], [0.1] * 3, [0.7] * 3))
+    a, Ga = OM.gradient(cfg, s, inv, t, base, w)
+    b, Gb = OM.gradient(cfg, s, inv, t, tab, w)
+    assert a["loss"] == b["loss"]
+    np.testing.assert_array_equal(Ga, Gb)
+
+
+def test_noise_table_clamps_to_end_nodes():
+    """Nodes all below (above) every cell's log(M_R,data): every cell takes the last (first)
+    node's values, i.e. the scalar model with those values."""
+    cfg, s, inv, w, t = _setup()
+    base = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=0.0)
+    lm = _logmr(cfg, t, base)
+    lo, hi = lm.min(), lm.max()
+    below = dict(base, noise_table=([lo - 3, lo - 2], [0.5, 0.2], [0.9, 0.3]))
+    above = dict(base, noise_table=([hi + 1, hi + 2], [0.5, 0.2], [0.9, 0.3]))
+    fb = OM.forward(cfg, s, inv, t, below, w)["loss"]
+    fa = OM.forward(cfg, s, inv, t, above, w)["loss"]
+    assert fb == OM.forward(cfg, s, inv, t, dict(base, mu=0.2, sigma_N=0.3), w)["loss"]
+    assert fa == OM.forward(cfg, s, inv, t, dict(base, mu=0.5, sigma_N=0.9), w)["loss"]
+
+
+def test_noise_table_width_scaling():
+    """Scaling every sigma node by lam (mu = 0) scales the data term and its gradient by
+    1 / lam^2: the width enters the residual once and its adjoint once."""
+    cfg, s, inv, w, t = _setup()
+    base = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=1.0, prior_weight=0.0)
+    nodes, _, sig = _table_around(_logmr(cfg, t, base))
+    p1 = dict(base, noise_table=(nodes, [0.0] * 3, sig))
+    p2 = dict(base, noise_table=(nodes, [0.0] * 3, 2.5 * sig))
+    a, Ga = OM.gradient(cfg, s, inv, t, p1, w)
+    b, Gb = OM.gradient(cfg, s, inv, t, p2, w)
+    assert abs(b["loss"] * 2.5 ** 2 - a["loss"]) <= 1e-12 * a["loss"]
+    np.testing.assert_allclose(Gb * 2.5 ** 2, Ga, rtol=1e-10, atol=1e-12 * np.abs(Ga).max())
+
+
+def test_noise_table_loss_at_model_equals_data():
+    """Model = data: x_model = x_data, so the data term is sum (mu_i / (2 sigma_i))^2 with
+    R_sm = 0, where the nodes' own values are taken at cells whose log(M_R,data) is a node."""
+    cfg, s, inv, w, _ = _setup()
+    t = OM.forward(cfg, s, inv, np.ones((cfg.n_out,) * 3), OM.default_params(), w)["mass"]
+    base = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=0.0)
+    lm = _logmr(cfg, t, base).ravel()
+    # nodes at the exact values of three cells
+    idx = np.argsort(lm)[[len(lm) // 10, len(lm) // 2, 9 * len(lm) // 10]]
+    nodes = lm[idx]
+    mu, sig = np.array([0.3, -0.1, 0.2]), np.array([0.8, 0.4, 0.6])
+    p = dict(base, noise_table=(nodes, mu, sig))
+    mu_i, sig_i = OM.noise_fields(cfg, t, p)
+    np.testing.assert_array_equal(mu_i.ravel()[idx], mu)
+    np.testing.assert_array_equal(sig_i.ravel()[idx], sig)
+    f = OM.forward(cfg, s, inv, t, p, w)
+    assert abs(f["loss_data"] - np.sum((mu_i / (2 * sig_i)) ** 2)) <= 1e-12 * f["loss_data"]
+
+
+def test_gradient_finite_difference_noise_table():
+    cfg, s, inv, w, t = _setup()
+    base = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=2.0)
+    params = dict(base, noise_table=_table_around(_logmr(cfg, t, base)))
+    _fd_check(cfg, s, inv, t, params, w, seed=12)
