@@ -108,6 +108,17 @@ int pmr_set_target(pmr_ctx* ctx, const float* target);
 /* Loss parameters, HOST array [B]. Copied to device memory. */
 int pmr_set_loss(pmr_ctx* ctx, const pmr_loss_params* params);
 
+/* Mass-dependent noise of the log-normal likelihood (Sec. 5.1: mu_N and sigma_N of Eq.
+ * (probnoise) depend on the smoothed data mass M_R at the cell). HOST arrays of n_nodes
+ * (<= 64): nodes log_mass (natural log of M_R of the data, strictly increasing) and the
+ * values mu and sigma (> 0) there. Each cell takes the linear interpolation at
+ * log(M_R,data), constant beyond the end nodes, for every batch item; this replaces the
+ * scalar mu and sigma_N of pmr_set_loss. n_nodes = 0 restores the scalars. Copied.
+ * Whether a table is in use is fixed into a forward pass captured in a HIP graph: capture
+ * after switching it on or off (changing the values of a table in use needs no recapture). */
+int pmr_set_noise_table(pmr_ctx* ctx, int n_nodes, const double* log_mass, const double* mu,
+                        const double* sigma);
+
 /* Forward model and loss. modes: complex64 [B][Np][Np][Np/2+1] (device).
  * mass_out: [B][Nout^3] model mass field (log-normal) or final density contrast
  * (density-L2); nullable. loss_out: device double [B][3] = (total, prior, data).

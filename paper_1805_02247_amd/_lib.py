@@ -50,6 +50,8 @@ SIGNATURES = {
     "pmr_set_mlp": (ci, [vp, vp, vp, vp, vp, vp, vp]),
     "pmr_set_target": (ci, [vp, vp]),
     "pmr_set_loss": (ci, [vp, ctypes.POINTER(PmrLossParams)]),
+    "pmr_set_noise_table": (ci, [vp, ci, ctypes.POINTER(cd), ctypes.POINTER(cd),
+                                 ctypes.POINTER(cd)]),
     "pmr_forward": (ci, [vp, vp, vp, vp]),
     "pmr_adjoint": (ci, [vp, vp, vp, vp]),
     "pmr_status_string": (ctypes.c_char_p, [ci]),

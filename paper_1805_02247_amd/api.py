@@ -137,6 +137,16 @@ class PMContext:
         self._sync_stream()
         L.check(L.lib().pmr_set_loss(self._ctx, arr))
 
+    def set_noise_table(self, log_mass=(), mu=(), sigma=()):
+        """Mass-dependent noise: nodes in log(M_R,data) with mu_N and sigma_N (empty: the
+        scalars of set_loss)."""
+        k = len(log_mass)
+        if not (len(mu) == k and len(sigma) == k):
+            raise ValueError("log_mass, mu and sigma need the same length")
+        arr = [(ctypes.c_double * max(k, 1))(*map(float, v)) for v in (log_mass, mu, sigma)]
+        self._sync_stream()
+        L.check(L.lib().pmr_set_noise_table(self._ctx, k, *arr))
+
     def forward(self, modes, want_mass=True):
         """modes: complex64 [B][Np][Np][Np/2+1] -> (mass [B][Nout^3] or None, loss [B][3] f64)."""
         _need(modes, torch.complex64, self.cfg.batch * self.n_modes, "modes")

@@ -488,27 +488,62 @@ __global__ void target_x_kernel(const float* __restrict__ mtr, size_t per_item, 
   xd[v] = logf(mtr[v] + (float)prm[b * 6 + 0]);
 }
 
-// r = (mu + log(MR + M0) - x_data) / (2 sigma_N)
+// Per-cell noise (Eq. probnoise; Sec. 5.1: mu_N and sigma_N depend on the smoothed data
+// mass at the cell): linear interpolation of the table (nodes t ascending in
+// log(M_R,data), values mu and sigma; constant beyond the end nodes) at log(M_R,data), in
+// FP64. Writes mu_N and 1 / (2 sigma_N). tab: [3][NOISE_MAX] doubles (t, mu, sigma).
+__global__ void noise_fields_kernel(const float* __restrict__ mrd, size_t total,
+                                    const double* __restrict__ tab, int k,
+                                    float* __restrict__ nmu, float* __restrict__ nw) {
+  const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (v >= total) return;
+  const double* t = tab;
+  const double* mu = tab + NOISE_MAX;
+  const double* sg = tab + 2 * NOISE_MAX;
+  const double m = mrd[v];
+  const double x = m > 0.0 ? log(m) : -INFINITY;
+  double a, s;
+  if (!(x > t[0])) {
+    a = mu[0];
+    s = sg[0];
+  } else if (!(x < t[k - 1])) {
+    a = mu[k - 1];
+    s = sg[k - 1];
+  } else {
+    int j = 0;
+    while (j + 2 < k && !(x < t[j + 1])) ++j;  // t[j] <= x < t[j + 1]
+    const double f = (x - t[j]) / (t[j + 1] - t[j]);
+    a = mu[j] + f * (mu[j + 1] - mu[j]);
+    s = sg[j] + f * (sg[j + 1] - sg[j]);
+  }
+  nmu[v] = (float)a;
+  nw[v] = (float)(0.5 / s);
+}
+
+// r = (mu + log(MR + M0) - x_data) / (2 sigma_N), with per-cell mu_N and 1 / (2 sigma_N)
+// when nmu / nw are given.
 __global__ void residual_kernel(const float* __restrict__ mr, const float* __restrict__ xd,
                                 size_t per_item, int batch, const double* __restrict__ prm,
+                                const float* __restrict__ nmu, const float* __restrict__ nw,
                                 float* __restrict__ r) {
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= per_item * batch) return;
   const int b = (int)(v / per_item);
-  const float M0 = (float)prm[b * 6 + 0], mu = (float)prm[b * 6 + 1];
-  const float inv2s = (float)(0.5 / prm[b * 6 + 2]);
+  const float M0 = (float)prm[b * 6 + 0];
+  const float mu = nmu ? nmu[v] : (float)prm[b * 6 + 1];
+  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * 6 + 2]);
   r[v] = (mu + logf(mr[v] + M0) - xd[v]) * inv2s;
 }
 
 // MRbar = rbar / (2 sigma_N (MR + M0))
 __global__ void mrbar_kernel(const float* __restrict__ rbar, const float* __restrict__ mr,
                              size_t per_item, int batch, const double* __restrict__ prm,
-                             float* __restrict__ out) {
+                             const float* __restrict__ nw, float* __restrict__ out) {
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= per_item * batch) return;
   const int b = (int)(v / per_item);
   const float M0 = (float)prm[b * 6 + 0];
-  const float inv2s = (float)(0.5 / prm[b * 6 + 2]);
+  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * 6 + 2]);
   out[v] = rbar[v] * inv2s / (mr[v] + M0);
 }
 
@@ -721,12 +756,18 @@ void launch_target_x(const float* mtr, size_t per_item, int batch, const double*
   target_x_kernel<<<grid1(per_item * batch), TB, 0, s>>>(mtr, per_item, batch, prm, xd);
 }
 void launch_residual(const float* mr, const float* xd, size_t per_item, int batch,
-                     const double* prm, float* r, hipStream_t s) {
-  residual_kernel<<<grid1(per_item * batch), TB, 0, s>>>(mr, xd, per_item, batch, prm, r);
+                     const double* prm, const float* nmu, const float* nw, float* r,
+                     hipStream_t s) {
+  residual_kernel<<<grid1(per_item * batch), TB, 0, s>>>(mr, xd, per_item, batch, prm, nmu, nw,
+                                                         r);
 }
 void launch_mrbar(const float* rbar, const float* mr, size_t per_item, int batch,
-                  const double* prm, float* out, hipStream_t s) {
-  mrbar_kernel<<<grid1(per_item * batch), TB, 0, s>>>(rbar, mr, per_item, batch, prm, out);
+                  const double* prm, const float* nw, float* out, hipStream_t s) {
+  mrbar_kernel<<<grid1(per_item * batch), TB, 0, s>>>(rbar, mr, per_item, batch, prm, nw, out);
+}
+void launch_noise_fields(const float* mrd, size_t total, const double* tab, int k, float* nmu,
+                         float* nw, hipStream_t s) {
+  noise_fields_kernel<<<grid1(total), TB, 0, s>>>(mrd, total, tab, k, nmu, nw);
 }
 void launch_l2_adj(const float* d, const float* t, size_t per_item, int batch,
                    const double* loss_bar, const float* extra, float* out, hipStream_t s) {

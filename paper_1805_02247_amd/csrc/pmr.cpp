@@ -101,6 +101,10 @@ struct pmr_ctx {
   float* target;
   double* params;
   float* xd;
+  double* noise_tab;   // [3][NOISE_MAX]: nodes in log(M_R,data), mu_N, sigma_N
+  int noise_k;         // nodes in the table; 0: the scalar mu, sigma_N of the loss parameters
+  float* noise_mu;     // per-cell mu_N [B][no3] (when noise_k > 0)
+  float* noise_w;      // per-cell 1 / (2 sigma_N) [B][no3]
   float2* ps;
   double* xs;   // position slots [S][B][3][np3]
   int n_xslots;
@@ -203,6 +207,9 @@ void plan(pmr_ctx* c, Plan& P) {
   c->target = P.take<float>(B * c->no3);
   c->params = P.take<double>(B * 6);
   c->xd = P.take<float>(B * c->no3);
+  c->noise_tab = P.take<double>(3 * NOISE_MAX);
+  c->noise_mu = P.take<float>(B * c->no3);
+  c->noise_w = P.take<float>(B * c->no3);
   c->ps = P.take<float2>(B * c->cp);
   c->xs = P.take<double>((size_t)c->n_xslots * B * 3 * c->np3);
   c->ckx = P.take<double>((size_t)c->n_ck * B * 3 * c->np3);
@@ -533,6 +540,9 @@ void refresh_xd(pmr_ctx* c) {
   if (c->cfg.loss_kind != PMR_LOSS_LOGNORMAL || !c->have_target || !c->have_loss) return;
   smooth(c, c->no, c->target, 3, c->ob, nullptr);
   launch_target_x(c->ob, c->no3, c->B, c->params, c->xd, c->stream);
+  if (c->noise_k > 0)
+    launch_noise_fields(c->ob, (size_t)c->B * c->no3, c->noise_tab, c->noise_k, c->noise_mu,
+                        c->noise_w, c->stream);
   c->xd_dirty = 0;
 }
 
@@ -615,6 +625,29 @@ int pmr_set_target(pmr_ctx* c, const float* target) {
   HIPC(c, hipMemcpyAsync(c->target, target, c->B * c->no3 * sizeof(float), hipMemcpyDeviceToDevice,
                  c->stream));
   c->have_target = 1;
+  c->xd_dirty = 1;
+  refresh_xd(c);
+  return check(c);
+}
+
+int pmr_set_noise_table(pmr_ctx* c, int n_nodes, const double* log_mass, const double* mu,
+                        const double* sigma) {
+  if (!c || n_nodes < 0 || n_nodes > NOISE_MAX) return PMR_E_INVALID;
+  if (n_nodes > 0 && (!log_mass || !mu || !sigma)) return PMR_E_INVALID;
+  std::vector<double> h(3 * NOISE_MAX, 0.0);
+  for (int j = 0; j < n_nodes; ++j) {
+    if (!std::isfinite(log_mass[j]) || !std::isfinite(mu[j]) || !(sigma[j] > 0) ||
+        !std::isfinite(sigma[j]) || (j > 0 && !(log_mass[j] > log_mass[j - 1])))
+      return PMR_E_INVALID;
+    h[j] = log_mass[j];
+    h[NOISE_MAX + j] = mu[j];
+    h[2 * NOISE_MAX + j] = sigma[j];
+  }
+  // pageable source: the copy completes before this call returns
+  HIPC(c, hipMemcpyAsync(c->noise_tab, h.data(), h.size() * sizeof(double),
+                         hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  c->noise_k = n_nodes;
   c->xd_dirty = 1;
   refresh_xd(c);
   return check(c);
@@ -706,7 +739,8 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
                                         (size_t)B * no3, c->mlp_w, c->mass, s);
     if (rc != 0) return PMR_E_SHAPE;
     smooth(c, c->no, c->mass, 3, c->MR, nullptr);
-    launch_residual(c->MR, c->xd, no3, B, c->params, c->r, s);
+    launch_residual(c->MR, c->xd, no3, B, c->params, c->noise_k ? c->noise_mu : nullptr,
+                    c->noise_k ? c->noise_w : nullptr, c->r, s);
     smooth(c, c->no, c->r, 4, c->rs, nullptr);
     launch_sumsq(c->rs, nullptr, no3, B, c->partial, c->data, s);
     if (mass_out) HIPC(c, hipMemcpyAsync(mass_out, c->mass, B * no3 * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -732,7 +766,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     float* o1 = c->ob + (size_t)B * no3;
     float* o2 = c->ob + 2 * (size_t)B * no3;
     smooth(c, c->no, c->rs, 4, o0, nullptr, loss_bar, 2.f);  // rbar = G_Rsm (2 loss_bar r_s)
-    launch_mrbar(o0, c->MR, no3, B, c->params, o1, s);       // MRbar
+    launch_mrbar(o0, c->MR, no3, B, c->params, c->noise_k ? c->noise_w : nullptr, o1,
+                 s);  // MRbar
     smooth(c, c->no, o1, 3, o2, mass_bar);                   // Mbar (+ mass_bar)
     if (c->cfg.precision == PMR_MIXED)
       launch_mlp_bwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,

@@ -234,9 +234,14 @@ int launch_mlp_bwd(int H, const float* d0, const float* d1, const float* d2, siz
 void launch_target_x(const float* mtr, size_t per_item, int batch, const double* prm, float* xd,
                      hipStream_t s);
 void launch_residual(const float* mr, const float* xd, size_t per_item, int batch,
-                     const double* prm, float* r, hipStream_t s);
+                     const double* prm, const float* nmu, const float* nw, float* r,
+                     hipStream_t s);
 void launch_mrbar(const float* rbar, const float* mr, size_t per_item, int batch,
-                  const double* prm, float* out, hipStream_t s);
+                  const double* prm, const float* nw, float* out, hipStream_t s);
+// Per-cell noise offset and 1 / (2 sigma) from the interpolation table (k nodes).
+constexpr int NOISE_MAX = 64;
+void launch_noise_fields(const float* mrd, size_t total, const double* tab, int k, float* nmu,
+                         float* nw, hipStream_t s);
 void launch_l2_adj(const float* d, const float* t, size_t per_item, int batch,
                    const double* loss_bar, const float* extra, float* out, hipStream_t s);
 int reduce_blocks(size_t per_item);

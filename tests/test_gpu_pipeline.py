@@ -34,7 +34,8 @@ def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0
     return ocfg, inv, modes, w, targets, params
 
 
-def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P.PMR_FP32):
+def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P.PMR_FP32,
+             noise=None):
     B = len(modes)
     n = ocfg.n_part
     cfg = P.Config(batch=B, n_part=n, n_mesh=ocfg.n_mesh, n_out=ocfg.n_out, n_steps=ocfg.n_steps,
@@ -45,7 +46,10 @@ def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P
     if w is not None:
         pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
     pm.set_target(torch.from_numpy(np.stack(targets).astype(np.float32)).reshape(B, -1))
-    pm.set_loss([P.LossParams(**p) for p in params])
+    pm.set_loss([P.LossParams(**{k: v for k, v in p.items() if k != "noise_table"})
+                 for p in params])
+    if noise is not None:
+        pm.set_noise_table(*noise)
     m = torch.from_numpy(np.stack(modes).astype(np.complex64)).reshape(B, -1).to(DEV)
     mass, loss = pm.forward(m)
     xs = [pm.debug("x", i).cpu().numpy() for i in range(ocfg.n_steps + 1)] if ckpt == 0 else None
@@ -124,6 +128,28 @@ def test_lognormal_data_term_alone():
                     prior_weight=0.0)
     res = _gpu_run(*prob, hidden=32)
     _compare(*prob, res, TOL_FP32)
+
+
+def test_lognormal_mass_dependent_noise_table():
+    """Per-cell mu_N, sigma_N interpolated from a table in log(M_R,data) (B = 2, R_sm = 2 and
+    0); then the table switched off again gives the scalar-noise result of the same context."""
+    require_gpu()
+    say("pipeline: log-normal with a mass-dependent noise table, 32^3")
+    prob = _problem(32, 32, 32, 100.0, 4, OM.LOSS_LOGNORMAL, 2, hidden=16, R_sm=(2.0, 0.0))
+    ocfg, inv, modes, w, targets, params = prob
+    lm = np.concatenate([np.log(OM.smooth(ocfg, t, params[0]["R_mass"])).ravel()
+                         for t in targets])
+    nodes = np.percentile(lm, [5, 35, 65, 95])
+    table = (nodes, np.array([0.3, -0.1, 0.05, 0.2]), np.array([0.9, 0.35, 0.5, 0.7]))
+    tparams = [dict(p, noise_table=table) for p in params]
+    res = _gpu_run(ocfg, inv, modes, w, targets, tparams, hidden=16, noise=table)
+    _compare(ocfg, inv, modes, w, targets, tparams, res, TOL_FP32)
+    pm = res["pm"]
+    pm.set_noise_table()
+    m = res["modes"]
+    _, loss = pm.forward(m)
+    ref = _gpu_run(*prob, hidden=16)
+    np.testing.assert_array_equal(loss.cpu().numpy(), ref["loss"])
 
 
 def test_force_mesh_twice_particle_mesh():
