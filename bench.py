@@ -435,6 +435,15 @@ def main():
         out["graph_replay"] = {"ms_per_step": 1e3 * Tg / args.steps, "value": pm_steps / Tg,
                                "unit": "PM steps/s"}
         del G
+    # mass-dependent noise: the same gradient with a 4-node table in log(M_R,data)
+    if args.workload == "cfg2_128":
+        t_plain, _ = time_gradient(pm, modes, max(2, args.steps // 2), 1)
+        lm = np.log(np.percentile(pm.data[0].cpu().numpy(), [5, 35, 65, 95]))
+        pm.set_noise_table(lm, [0.3, -0.1, 0.05, 0.2], [0.9, 0.35, 0.5, 0.7])
+        t_tab, _ = time_gradient(pm, modes, max(2, args.steps // 2), 1)
+        pm.set_noise_table()
+        out["noise_table"] = {"ms_per_step_scalar_noise": 1e3 * t_plain,
+                              "ms_per_step_table": 1e3 * t_tab, "nodes": 4}
     if args.no_cpu_baseline:
         out["cpu_baseline"] = None
     else:
