@@ -11,12 +11,17 @@
 // unique (key, id) order; rows (item, ix, iy) are then contiguous and `row_start` indexes
 // them.
 //
-// Paint is owner-computes and atomic-free across the device: one wavefront owns one
-// target row of Nm cells in LDS and walks the four source rows that can reach it. Inside
-// a source row the particles arrive sorted by iz, so a segmented scan over the 64 lanes
-// sums equal-iz runs and only the last lane of each run touches LDS: each LDS word is
-// written by one lane per instruction, in program order, so the result is bitwise
-// reproducible.
+// Paint is owner-computes and atomic-free across the device: one wavefront owns TY
+// consecutive target rows of Nm cells in LDS and walks the source rows that can reach them
+// (paint_kernels.h). Inside a source row the particles arrive sorted by iz, so a segmented
+// scan over the 64 lanes sums equal-cell runs and only the last lane of each run touches
+// LDS: each LDS word is written by one lane per instruction, in program order, so the
+// result is bitwise reproducible.
+//
+// The forward readout (kick_drift_kernel) gathers in id order; the step adjoint gathers its
+// two position terms in sort order (adjoint_positions_kernel: neighbouring lanes read
+// neighbouring cells, as in the paint) and applies the kick and drift transposes in id
+// order (adjoint_update_kernel).
 #include "pmr_internal.h"
 
 namespace pmr {
@@ -25,15 +30,6 @@ namespace {
 constexpr int TB = 256;  // threads per block for per-particle kernels
 
 // ---------------------------------------------------------------- keys
-__device__ __forceinline__ uint32_t cell_key(const double* xyz, double scale, int nm,
-                                             uint32_t item, uint32_t cells) {
-  double f;
-  const int ix = cic_corner(xyz[0], scale, nm, &f);
-  const int iy = cic_corner(xyz[1], scale, nm, &f);
-  const int iz = cic_corner(xyz[2], scale, nm, &f);
-  return item * cells + ((uint32_t)ix * nm + iy) * nm + iz;
-}
-
 // Key and CIC fractions (id order) of one particle on an nm mesh.
 __device__ __forceinline__ uint32_t key_frac(const double* xyz, double scale, int nm, uint32_t item,
                                              Vec3* frac) {
@@ -714,21 +710,6 @@ void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* r
   a.bias = bias;
   a.out = out;
   paint_dispatch<1>(a, batch, s);
-}
-
-void launch_paint_adj3(const uint32_t* keys, const Vec3* frac, const Vec3* val,
-                       const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s) {
-  PaintArgs a{};
-  a.keys = keys;
-  a.frac = frac;
-  a.val = val;
-  a.row_start = row_start;
-  a.nm = nm;
-  int l = 0;
-  while ((1 << l) < nm) ++l;
-  a.log_nm = l;
-  a.out = out;
-  paint_dispatch<3>(a, batch, s);
 }
 
 void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,

@@ -201,25 +201,20 @@ __device__ __forceinline__ const float* lds_fence(const float* sw) {
   }
 }
 
-// BF16 copies of W2 (row-major [n][k]) and W2^T, placed after the FP32 block.
+// BF16 copy of W2 (row-major [n][k]), placed after the FP32 block (16-byte aligned); the
+// matrix-core kernels read both W2 and W2^T fragments from it.
 template <int H>
 struct WBf {
   static constexpr size_t W2 = ((size_t)WOff<H>::SIZE * 4 + 15) / 16 * 16;  // byte offset
-  static constexpr size_t W2T = W2 + (size_t)H * H * 2;
-  static constexpr size_t BYTES = W2T + (size_t)H * H * 2;
+  static constexpr size_t BYTES = W2 + (size_t)H * H * 2;
 };
 
 template <int H>
 __global__ void mlp_prepare_bf16_kernel(float* w) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= H * H) return;
-  const int n = t / H, k = t % H;
-  char* base = reinterpret_cast<char*>(w);
-  __bf16* w2 = reinterpret_cast<__bf16*>(base + WBf<H>::W2);
-  __bf16* w2t = reinterpret_cast<__bf16*>(base + WBf<H>::W2T);
-  const float v = w[WOff<H>::W2 + n * H + k];
-  w2[n * H + k] = (__bf16)v;
-  w2t[k * H + n] = (__bf16)v;
+  __bf16* w2 = reinterpret_cast<__bf16*>(reinterpret_cast<char*>(w) + WBf<H>::W2);
+  w2[t] = (__bf16)w[WOff<H>::W2 + t];
 }
 
 // Row blocks of 16 voxels a wavefront processes at a time.
@@ -670,8 +665,8 @@ void mlp_bwd_t(const float* d0, const float* d1, const float* d2, size_t n, cons
 }  // namespace
 
 size_t mlp_weight_floats(int H) {
-  // FP32 block, then BF16 W2 and W2^T (16-byte aligned)
-  return ((size_t)6 * H + (size_t)H * H + 1 + 3) / 4 * 4 + (size_t)H * H + 4;
+  // FP32 block, then the BF16 W2 (16-byte aligned)
+  return ((size_t)6 * H + (size_t)H * H + 1 + 3) / 4 * 4 + ((size_t)H * H + 1) / 2 + 4;
 }
 
 int launch_mlp_prepare_bf16(int H, float* w, hipStream_t s) {

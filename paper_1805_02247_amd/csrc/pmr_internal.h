@@ -196,8 +196,6 @@ void launch_stream_gather(const uint32_t* ids, const Vec3* src, int total, Vec3*
                           hipStream_t s);
 void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* row_start,
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s);
-void launch_paint_adj3(const uint32_t* keys, const Vec3* frac, const Vec3* val,
-                       const uint32_t* row_start, int batch, int nm, float* out, hipStream_t s);
 // F: interleaved force mesh [B][nm^3] of Vec3 (Fx, Fy, Fz).
 void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,
                        Vec3* frac, int batch, int log_np3, int nm, double box, float kick,
