@@ -59,6 +59,21 @@ def gradient_multiplier(n, box, axis):
     return np.broadcast_to(mult, (n, n, n // 2 + 1))
 
 
+def hessian_multiplier(n, box, a, b):
+    """k_a k_b / k^2: maps the linear field delta to the second derivative phi_{,ab} of the
+    potential with laplacian(phi) = delta (phi_hat = -delta_hat / k^2, d_a d_b -> -k_a k_b).
+    Zero at k = 0 and on the Nyquist plane of axis a or of axis b (each derivative treated
+    as in gradient_multiplier)."""
+    kv = wavevectors(n, box)
+    mv = int_wavenumbers(n)
+    k2 = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mult = kv[a] * kv[b] / k2
+    mult = np.where(k2 == 0.0, 0.0, mult)
+    mult = np.where((np.abs(mv[a]) == n // 2) | (np.abs(mv[b]) == n // 2), 0.0, mult)
+    return np.broadcast_to(mult, (n, n, n // 2 + 1))
+
+
 def gaussian_multiplier(n, box, R):
     """exp(-k^2 R^2 / 2): Gaussian smoothing of radius R (Mpc/h); R = 0 is the identity."""
     kv = wavevectors(n, box)

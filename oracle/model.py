@@ -36,13 +36,15 @@ LOSS_LOGNORMAL = 1
 
 class Config:
     def __init__(self, box, n_part, n_mesh, n_out, n_steps, a0=0.1, a1=1.0,
-                 omega_m=cos.OMEGA_M_PAPER, R1=1.0, R2=2.0, loss_kind=LOSS_LOGNORMAL):
+                 omega_m=cos.OMEGA_M_PAPER, R1=1.0, R2=2.0, loss_kind=LOSS_LOGNORMAL,
+                 ic_order=1):
         self.box = float(box)
         self.n_part, self.n_mesh, self.n_out = int(n_part), int(n_mesh), int(n_out)
         self.n_steps = int(n_steps)
         self.a0, self.a1, self.omega_m = float(a0), float(a1), float(omega_m)
         self.R1, self.R2 = float(R1), float(R2)
         self.loss_kind = loss_kind
+        self.ic_order = int(ic_order)  # 1: Zel'dovich, 2: second-order LPT
         self.fac = cos.kdk_factors(self.a0, self.a1, self.n_steps, self.omega_m)
 
 
@@ -70,16 +72,50 @@ def prior_grad(s, inv_S):
 
 # ------------------------------------------------------------------ dynamics
 
-def zeldovich(cfg, s):
-    """Displacement Psi_a = irfft(i k_a / k^2 * P s) on the particle lattice;
-    x0 = wrap(q + D(a0) Psi), p0 = G_p(a0) Psi."""
+HESS_PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+LPT2_D = 3.0 / 7.0  # |D2| / D1^2 (second-order growth, the Omega_m = 1 relation)
+
+
+def lpt2_source(phi):
+    """Second-order source sum_{a<b} (phi_aa phi_bb - phi_ab^2) from the six phi_{,ab}
+    (in HESS_PAIRS order)."""
+    xx, yy, zz, xy, xz, yz = phi
+    return xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz
+
+
+def zeldovich(cfg, s, full=False):
+    """Initial conditions on the particle lattice q.
+    First order (Zel'dovich): Psi_a = irfft(i k_a / k^2 * P s); x0 = wrap(q + D Psi),
+    p0 = G_p Psi, with D, G_p at a0.
+    Second order (ic_order = 2; the paper's initial conditions are 2LPT, Sec. 3; the
+    standard second-order Lagrangian solution is the reading): with phi_{,ab} =
+    irfft(k_a k_b / k^2 * P s) the second derivatives of the potential of the linear field
+    and S = sum_{a<b} (phi_aa phi_bb - phi_ab^2), Psi2_a = irfft(i k_a / k^2 * rfft(S));
+    the second-order displacement is -D2 * Psi2 with D2 = -(3/7) D^2, so
+    x0 = wrap(q + D Psi + (3/7) D^2 Psi2), p0 = G_p Psi + (6/7) D G_p Psi2 (the momentum
+    factor of D^2 is 2 D G_p, since G_p = a^3 E dD/da).
+    full: also return the intermediates the adjoint needs."""
     n = cfg.n_part
     ps = M.hermitian_project(s)
     psi = np.stack([M.irfft3(M.gradient_multiplier(n, cfg.box, a) * ps, n).ravel()
                     for a in range(3)])
     q = M.lattice_positions(n, cfg.box, cfg.n_mesh)
-    x0 = M.wrap(q + cfg.fac["D0"] * psi, cfg.box)
-    p0 = cfg.fac["Gp0"] * psi
+    D, Gp = cfg.fac["D0"], cfg.fac["Gp0"]
+    extra = {}
+    if cfg.ic_order == 2:
+        phi = [M.irfft3(M.hessian_multiplier(n, cfg.box, a, b) * ps, n) for a, b in HESS_PAIRS]
+        S = lpt2_source(phi)
+        Sh = M.rfft3(S)
+        psi2 = np.stack([M.irfft3(M.gradient_multiplier(n, cfg.box, a) * Sh, n).ravel()
+                         for a in range(3)])
+        x0 = M.wrap(q + D * psi + LPT2_D * D * D * psi2, cfg.box)
+        p0 = Gp * psi + 2.0 * LPT2_D * D * Gp * psi2
+        extra = {"phi": phi, "S": S, "psi2": psi2}
+    else:
+        x0 = M.wrap(q + D * psi, cfg.box)
+        p0 = Gp * psi
+    if full:
+        return x0, p0, psi, extra
     return x0, p0, psi
 
 
@@ -197,9 +233,9 @@ def noise_fields(cfg, mass_target, params):
 def forward(cfg, s, inv_S, target, params, mlp=None):
     """Full forward model and loss for one realisation. Returns a dict of intermediates."""
     out = {}
-    x0, p0, psi = zeldovich(cfg, s)
+    x0, p0, psi, lpt2 = zeldovich(cfg, s, full=True)
     xs, ps, Fm, Fp = pm_forward(cfg, x0, p0)
-    out.update(x0=x0, p0=p0, psi=psi, xs=xs, ps=ps, Fm=Fm, Fp=Fp)
+    out.update(x0=x0, p0=p0, psi=psi, lpt2=lpt2, xs=xs, ps=ps, Fm=Fm, Fp=Fp)
     n_o = cfg.n_out
     delta_f = density(cfg, xs[-1], n_o)
     out["delta_f"] = delta_f
@@ -265,14 +301,30 @@ def pm_adjoint(cfg, fwd, x_bar_final):
     return x_bar, p_bar
 
 
-def zeldovich_adjoint(cfg, x0_bar, p0_bar):
-    """Gradient with respect to the stored modes from (x0_bar, p0_bar) (without prior)."""
+def zeldovich_adjoint(cfg, x0_bar, p0_bar, lpt2=None):
+    """Gradient with respect to the stored modes from (x0_bar, p0_bar) (without prior);
+    lpt2: the second-order intermediates of zeldovich(..., full=True) when ic_order = 2.
+    A real-space map f -> irfft(m rfft(f)) has the transpose g -> irfft(conj(m) rfft(g));
+    a map from the modes, P s -> irfft(m P s), contributes w conj(m) rfft(g) / n^3."""
     n = cfg.n_part
-    psi_bar = cfg.fac["D0"] * x0_bar + cfg.fac["Gp0"] * p0_bar
+    D, Gp = cfg.fac["D0"], cfg.fac["Gp0"]
+    psi_bar = D * x0_bar + Gp * p0_bar
     g = 0.0
     for a in range(3):
         g = g + np.conj(M.gradient_multiplier(n, cfg.box, a)) * M.rfft3(
             psi_bar[a].reshape(n, n, n))
+    if cfg.ic_order == 2:
+        psi2_bar = LPT2_D * D * D * x0_bar + 2.0 * LPT2_D * D * Gp * p0_bar
+        sb = 0.0
+        for a in range(3):
+            sb = sb + np.conj(M.gradient_multiplier(n, cfg.box, a)) * M.rfft3(
+                psi2_bar[a].reshape(n, n, n))
+        S_bar = M.irfft3(sb, n)
+        xx, yy, zz, xy, xz, yz = lpt2["phi"]
+        phi_bar = [(yy + zz) * S_bar, (xx + zz) * S_bar, (xx + yy) * S_bar,
+                   -2.0 * xy * S_bar, -2.0 * xz * S_bar, -2.0 * yz * S_bar]
+        for (a, b), pb in zip(HESS_PAIRS, phi_bar):
+            g = g + M.hessian_multiplier(n, cfg.box, a, b) * M.rfft3(pb)
     G = np.array(M.hermitian_weight(n) * g / n ** 3)
     G[0, 0, 0] = 0.0
     return G
@@ -304,7 +356,7 @@ def gradient(cfg, s, inv_S, target, params, mlp=None, loss_bar=1.0):
     xbar_n = density_adjoint_positions(cfg, fwd["xs"][-1], cfg.n_out, delta_bar)
     x0_bar, p0_bar = pm_adjoint(cfg, fwd, xbar_n)
     fwd["x0_bar"], fwd["p0_bar"] = x0_bar, p0_bar
-    G = zeldovich_adjoint(cfg, x0_bar, p0_bar)
+    G = zeldovich_adjoint(cfg, x0_bar, p0_bar, fwd["lpt2"])
     G = G + params["prior_weight"] * loss_bar * prior_grad(s, inv_S)
     return fwd, G
 

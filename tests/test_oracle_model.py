@@ -296,3 +296,72 @@ def test_gradient_finite_difference_noise_table():
     base = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=2.0)
     params = dict(base, noise_table=_table_around(_logmr(cfg, t, base)))
     _fd_check(cfg, s, inv, t, params, w, seed=12)
+
+
+# ------------------------------------------------------------------ second-order LPT
+
+def _plane_wave_modes(n, waves):
+    """Half spectrum of sum_j A_j cos(2 pi m_j . q / n) on the lattice (exact)."""
+    g = np.indices((n, n, n)).reshape(3, -1).T
+    f = np.zeros(n ** 3)
+    for A, m in waves:
+        f += A * np.cos(2 * np.pi * (g @ np.asarray(m, float)) / n)
+    return M.rfft3(f.reshape(n, n, n))
+
+
+def test_lpt2_single_plane_wave_equals_zeldovich():
+    """A one-dimensional perturbation has no second-order source: 2LPT = Zel'dovich."""
+    n, box = 16, 50.0
+    s = _plane_wave_modes(n, [(30.0, (2, 0, 0))])
+    c1 = OM.Config(box, n, n, n, 3, ic_order=1)
+    c2 = OM.Config(box, n, n, n, 3, ic_order=2)
+    x1, p1, _ = OM.zeldovich(c1, s)
+    x2, p2, _, ex = OM.zeldovich(c2, s, full=True)
+    assert np.abs(ex["S"]).max() < 1e-10 * 30.0 ** 2
+    np.testing.assert_allclose(x2, x1, rtol=0, atol=1e-12 * box)
+    np.testing.assert_allclose(p2, p1, rtol=0, atol=1e-12 * np.abs(p1).max())
+
+
+def test_lpt2_two_crossed_plane_waves_closed_form():
+    """delta = A cos(k1 x) + B cos(k2 y): phi_xx = A cos(k1 x), phi_yy = B cos(k2 y), the other
+    second derivatives vanish, so S = A B cos(k1 x) cos(k2 y) and
+    Psi2 = -A B (k1 sin(k1 x) cos(k2 y), k2 cos(k1 x) sin(k2 y), 0) / (k1^2 + k2^2)."""
+    n, box = 16, 50.0
+    A, B, m1, m2 = 3.0, 2.0, 2, 3
+    s = _plane_wave_modes(n, [(A, (m1, 0, 0)), (B, (0, m2, 0))])
+    cfg = OM.Config(box, n, n, n, 3, ic_order=2)
+    _, _, _, ex = OM.zeldovich(cfg, s, full=True)
+    i, j, _ = np.indices((n, n, n))
+    cx, sx = np.cos(2 * np.pi * m1 * i / n), np.sin(2 * np.pi * m1 * i / n)
+    cy, sy = np.cos(2 * np.pi * m2 * j / n), np.sin(2 * np.pi * m2 * j / n)
+    np.testing.assert_allclose(ex["phi"][0], A * cx, atol=1e-12)
+    np.testing.assert_allclose(ex["phi"][1], B * cy, atol=1e-12)
+    for k in (2, 3, 4, 5):
+        assert np.abs(ex["phi"][k]).max() < 1e-12
+    np.testing.assert_allclose(ex["S"], A * B * cx * cy, atol=1e-11)
+    k1, k2 = 2 * np.pi * m1 / box, 2 * np.pi * m2 / box
+    ref = -A * B / (k1 ** 2 + k2 ** 2) * np.stack([k1 * sx * cy, k2 * cx * sy, 0 * cx])
+    np.testing.assert_allclose(ex["psi2"], ref.reshape(3, -1), atol=1e-12)
+
+
+def test_lpt2_term_is_quadratic_in_the_modes():
+    cfg, s, inv, w, t = _setup()
+    c2 = OM.Config(cfg.box, cfg.n_part, cfg.n_mesh, cfg.n_out, 3, ic_order=2)
+    _, _, _, e1 = OM.zeldovich(c2, s, full=True)
+    _, _, _, e3 = OM.zeldovich(c2, 3.0 * s, full=True)
+    np.testing.assert_allclose(e3["psi2"], 9.0 * e1["psi2"], rtol=1e-10,
+                               atol=1e-12 * np.abs(e3["psi2"]).max())
+
+
+def test_gradient_finite_difference_lpt2():
+    cfg, s, inv, w, t = _setup()
+    c2 = OM.Config(cfg.box, cfg.n_part, cfg.n_mesh, cfg.n_out, cfg.n_steps, ic_order=2)
+    params = OM.default_params(M0=float(np.percentile(t, 50)), R_sm=1.0, mu=0.1)
+    _fd_check(c2, s, inv, t, params, w, seed=13)
+
+
+def test_gradient_finite_difference_lpt2_density_l2():
+    cfg, s, inv, _, t = _setup(n=16, box=50.0, steps=3, kind=OM.LOSS_DENSITY_L2)
+    c2 = OM.Config(cfg.box, cfg.n_part, cfg.n_mesh, cfg.n_out, cfg.n_steps,
+                   loss_kind=OM.LOSS_DENSITY_L2, ic_order=2)
+    _fd_check(c2, s, inv, t, OM.default_params(prior_weight=0.0), None, seed=14)
