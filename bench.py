@@ -97,7 +97,8 @@ def make_context(w, dev, data=None):
 
     cfg = P.Config(batch=w["batch"], n_part=w["n_part"], n_mesh=w["n_mesh"], n_out=w["n_out"],
                    n_steps=w["n_steps"], mlp_hidden=w["mlp_hidden"], precision=w["precision"],
-                   ckpt_every=w["ckpt_every"], box=w["box"], loss_kind=P.PMR_LOSS_LOGNORMAL)
+                   ckpt_every=w["ckpt_every"], box=w["box"], loss_kind=P.PMR_LOSS_LOGNORMAL,
+                   ic_order=w.get("ic_order", 1))
     B, n, box = cfg.batch, cfg.n_part, cfg.box
     power = cosmo.linear_power(0.8, 0.2)
     pm = P.PMContext(cfg, dev)
@@ -444,6 +445,12 @@ def main():
         pm.set_noise_table()
         out["noise_table"] = {"ms_per_step_scalar_noise": 1e3 * t_plain,
                               "ms_per_step_table": 1e3 * t_tab, "nodes": 4}
+        # second-order LPT initial conditions: the same gradient on the same data
+        pm2, modes2 = make_context(dict(w, ic_order=2), dev, data=pm.data)
+        t_2lpt, _ = time_gradient(pm2, modes2, max(2, args.steps // 2), 1)
+        out["second_order_ics"] = {"ms_per_step_zeldovich": 1e3 * t_plain,
+                                   "ms_per_step_2lpt": 1e3 * t_2lpt}
+        del pm2, modes2
     if args.no_cpu_baseline:
         out["cpu_baseline"] = None
     else:

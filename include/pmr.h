@@ -67,6 +67,8 @@ typedef struct pmr_config {
   double a0, a1;  /* start and end scale factors (0 < a0 < a1) */
   double omega_m; /* flat LambdaCDM matter density (Sec. 3: 0.3175) */
   double R1, R2;  /* Gaussian feature scales, Mpc/h (Sec. 2.2) */
+  int ic_order;   /* initial conditions (Sec. 3): 0 or 1 first-order (Zel'dovich) displacement,
+                     2 second-order LPT (adds 3/7 D0^2 Psi2 to x0 and 6/7 D0 Gp0 Psi2 to p0) */
 } pmr_config;
 
 /* Loss parameters of one batch item (Sec. 5.1, Eq. loss; Sec. 5.2 anneals R_sm and M0). */

@@ -24,7 +24,7 @@ class PmrConfig(ctypes.Structure):
                 ("precision", ctypes.c_int), ("ckpt_every", ctypes.c_int),
                 ("loss_kind", ctypes.c_int), ("box", ctypes.c_double), ("a0", ctypes.c_double),
                 ("a1", ctypes.c_double), ("omega_m", ctypes.c_double), ("R1", ctypes.c_double),
-                ("R2", ctypes.c_double)]
+                ("R2", ctypes.c_double), ("ic_order", ctypes.c_int)]
 
 
 class PmrLossParams(ctypes.Structure):

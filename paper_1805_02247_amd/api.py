@@ -47,11 +47,13 @@ class Config:
     omega_m: float = 0.3175
     R1: float = 1.0
     R2: float = 2.0
+    ic_order: int = 1  # 1: Zel'dovich initial conditions, 2: second-order LPT
 
     def c(self):
         return L.PmrConfig(self.batch, self.n_part, self.n_mesh, self.n_out, self.n_steps,
                            self.mlp_hidden, self.precision, self.ckpt_every, self.loss_kind,
-                           self.box, self.a0, self.a1, self.omega_m, self.R1, self.R2)
+                           self.box, self.a0, self.a1, self.omega_m, self.R1, self.R2,
+                           self.ic_order)
 
 
 @dataclass

@@ -555,10 +555,13 @@ __global__ __launch_bounds__(TB) void adjoint_update_kernel(AdjArgs a) {
              a.kick_next * (pb[2] + a.drift_next * xn[2])};
 }
 
-// Zel'dovich start: x0 = wrap(q + D0 Psi), p0 = Gp0 Psi; q = idx * (box/np) + box / (2 nm).
-__global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ psi, int np,
+// Lagrangian start: x0 = wrap(q + D0 Psi + c2x Psi2), p0 = Gp0 Psi + c2p Psi2 (Psi2 only at
+// second order); q = idx * (box/np) + box / (2 nm).
+__global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ psi,
+                                                     const float* __restrict__ psi2, int np,
                                                      int log_np3, int total, double box,
                                                      double half_cell, double D0, float Gp0,
+                                                     double c2x, float c2p,
                                                      double* __restrict__ x, float* __restrict__ p,
                                                      uint32_t* __restrict__ keys,
                                                      Vec3* __restrict__ frac, int key_nm,
@@ -575,10 +578,11 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const float ps = psi[pi + q * np3];
+    const float ps2 = psi2 ? psi2[pi + q * np3] : 0.f;
     const double q0 = (double)idx[q] * dq + half_cell;
-    xn[q] = wrap_box(q0 + D0 * (double)ps, box);
+    xn[q] = wrap_box(q0 + D0 * (double)ps + c2x * (double)ps2, box);
     x[pi + q * np3] = xn[q];
-    p[pi + q * np3] = Gp0 * ps;
+    p[pi + q * np3] = Gp0 * ps + c2p * ps2;
   }
   Vec3 f;
   keys[g] = key_frac(xn, key_scale, key_nm, item, &f);
@@ -774,13 +778,13 @@ void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch
   adjoint_update_kernel<<<(a.total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
-void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, Vec3* frac,
-                    int key_nm, hipStream_t s) {
+void launch_za_init(const float* psi, const float* psi2, int batch, int np, int log_np3,
+                    double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
+                    double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s) {
   const int total = batch << log_np3;
-  za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, np, log_np3, total, box, half_cell, D0,
-                                                       Gp0, x, p, keys, frac, key_nm,
-                                                       (double)key_nm / box);
+  za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, psi2, np, log_np3, total, box,
+                                                       half_cell, D0, Gp0, c2x, c2p, x, p, keys,
+                                                       frac, key_nm, (double)key_nm / box);
 }
 
 }  // namespace pmr

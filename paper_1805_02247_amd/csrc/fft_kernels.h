@@ -636,6 +636,45 @@ __device__ __forceinline__ float grad_coef(const KVec& k, int a) {
   return ka * __builtin_amdgcn_rcpf(k.k2);
 }
 
+// k_a k_b / k^2 (second derivative of the potential of the field, up to sign) with k = 0
+// and the Nyquist planes of axes a and b removed, as each derivative in grad_coef.
+template <int N>
+__device__ __forceinline__ float hess_coef(const KVec& k, int a, int b) {
+  const int ma = a == 0 ? k.mx : a == 1 ? k.my : k.mz;
+  const int mb = b == 0 ? k.mx : b == 1 ? k.my : k.mz;
+  const float ka = a == 0 ? k.kx : a == 1 ? k.ky : k.kz;
+  const float kb = b == 0 ? k.kx : b == 1 ? k.ky : k.kz;
+  if (k.k2 == 0.f || ma == N / 2 || ma == -N / 2 || mb == N / 2 || mb == -N / 2) return 0.f;
+  return ka * kb * __builtin_amdgcn_rcpf(k.k2);
+}
+
+// Pair o of a Hessian pair set: set 0 holds the diagonal (xx, yy, zz), set 1 the
+// off-diagonal (xy, xz, yz).
+__device__ __forceinline__ void hess_pair(int set, int o, int& a, int& b) {
+  if (set == 0) {
+    a = b = o;
+  } else {
+    a = o == 2 ? 1 : 0;
+    b = o == 0 ? 1 : 2;
+  }
+}
+
+template <int OP>
+constexpr int xpass_inputs() {
+  return (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ || OP == XOP_HESS_ADJ) ? 3
+         : OP == XOP_FEAT_ADJ                                          ? 2
+                                                                       : 1;
+}
+template <int OP>
+constexpr int xpass_outputs() {
+  return (OP == XOP_FORCE || OP == XOP_ZA || OP == XOP_HESS) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
+}
+// Operators whose input is already a full spectrum (no forward transform along x).
+template <int OP>
+constexpr bool spectral_input() {
+  return OP == XOP_ZA || OP == XOP_INV || OP == XOP_HESS;
+}
+
 template <int N, int OP, int PC, int NTH, int V>
 __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   constexpr int NH = N / 2 + 1;
@@ -651,8 +690,8 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
   const int t = threadIdx.x;
-  const int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
-  const int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
+  const int n_in = xpass_inputs<OP>();
+  const int n_out = xpass_outputs<OP>();
 
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   TileRegs<N, PC, NTH, V> pre;  // first input of the current tile (prefetched)
@@ -690,7 +729,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
         load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
                               istride, min(PC, NH - nkz0));
       }
-      if constexpr (OP != XOP_ZA && OP != XOP_INV) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
+      if constexpr (!spectral_input<OP>()) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
         const int e = t + m * NTH;
@@ -702,6 +741,13 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
           const float2 w = cmul_i<-1>(v);
           hold[m].x += c * w.x;
           hold[m].y += c * w.y;
+        } else if constexpr (OP == XOP_HESS_ADJ) {
+          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+          int pa, pb;
+          hess_pair(a.param_index, i, pa, pb);
+          const float h = hess_coef<N>(k, pa, pb);  // real: its own conjugate
+          hold[m].x += h * v.x;
+          hold[m].y += h * v.y;
         } else if constexpr (OP == XOP_FEAT_ADJ) {
           const KVec k = kvec<N>(n, iy, kz0 + l, kf);
           const float g = i == 0 ? __expf(-0.5f * k.k2 * (float)(a.R1 * a.R1))
@@ -741,6 +787,21 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
         if (n == 0 && iy == 0 && kz == 0) g = make_float2(0.f, 0.f);
         a.out[0][item * a.out_item_stride + gi] = g;
       }
+    } else if constexpr (OP == XOP_HESS_ADJ) {
+      // G += w(kz) sum_ab h_ab g_ab / n^3, G(0) untouched (h vanishes there)
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int e = t + m * NTH;
+        const int n = e / PC, l = e % PC;
+        const int kz = kz0 + l;
+        if (l >= ncols) continue;
+        const size_t gi = item * a.out_item_stride + (size_t)n * stride + (size_t)iy * NH + kz;
+        const float wz = ((kz == 0 || kz == N / 2) ? 1.f : 2.f) * inv_n3;
+        float2 g = a.out[0][gi];
+        g.x += wz * hold[m].x;
+        g.y += wz * hold[m].y;
+        a.out[0][gi] = g;
+      }
     } else {
       for (int o = 0; o < n_out; ++o) {
 #pragma unroll
@@ -752,6 +813,12 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float c = grad_coef<N>(k, o) * inv_n3;
             v = cmul_i<1>(make_float2(c * v.x, c * v.y));
+          } else if constexpr (OP == XOP_HESS) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            int pa, pb;
+            hess_pair(a.param_index, o, pa, pb);
+            const float h = hess_coef<N>(k, pa, pb) * inv_n3;
+            v = make_float2(h * v.x, h * v.y);
           } else if constexpr (OP == XOP_GAUSS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float g = __expf(-0.5f * k.k2 * Rg * Rg) * inv_n3;
@@ -997,7 +1064,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   constexpr int R0F = PF::radix(0), RLF = PF::radix(PF::S - 1);
   constexpr int RLI = PI::radix(PI::S - 1);
   static_assert(PI::radix(0) == RLF, "inverse starts with the forward's last radix");
-  constexpr bool SPECTRAL_IN = (OP == XOP_ZA || OP == XOP_INV);
+  constexpr bool SPECTRAL_IN = spectral_input<OP>();
   constexpr int RIN = SPECTRAL_IN ? RLF : R0F;  // layout in which inputs are loaded
   __shared__ float2 lds[N * PC];
   __shared__ float2 tw[N];
@@ -1006,8 +1073,8 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   const size_t stride = (size_t)N * NH;  // prior table, projected modes, gradient
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
-  constexpr int n_in = (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ) ? 3 : (OP == XOP_FEAT_ADJ ? 2 : 1);
-  constexpr int n_out = (OP == XOP_FORCE || OP == XOP_ZA) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
+  constexpr int n_in = xpass_inputs<OP>();
+  constexpr int n_out = xpass_outputs<OP>();
 
   auto in_base = [&](int tau, int i, int& ncols) {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
@@ -1060,6 +1127,15 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
           const float2 w = cmul_i<-1>(v[q]);
           hold[q].x += c * w.x;
           hold[q].y += c * w.y;
+        } else if constexpr (OP == XOP_HESS_ADJ) {
+          int n, l;
+          reg_slot<N, PC, NTH, RLF>(q, n, l);
+          const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+          int pa, pb;
+          hess_pair(a.param_index, i, pa, pb);
+          const float h = hess_coef<N>(k, pa, pb);  // real: its own conjugate
+          hold[q].x += h * v[q].x;
+          hold[q].y += h * v[q].y;
         } else if constexpr (OP == XOP_FEAT_ADJ) {
           int n, l;
           reg_slot<N, PC, NTH, RLF>(q, n, l);
@@ -1096,6 +1172,21 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
         if (n == 0 && iy == 0 && kz == 0) g = make_float2(0.f, 0.f);
         a.out[0][item * a.out_item_stride + gi] = g;
       }
+    } else if constexpr (OP == XOP_HESS_ADJ) {
+      // G += w(kz) sum_ab h_ab g_ab / n^3, G(0) untouched (h vanishes there)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        int n, l;
+        reg_slot<N, PC, NTH, RLF>(q, n, l);
+        const int kz = kz0 + l;
+        if (l >= ncols) continue;
+        const size_t gi = item * a.out_item_stride + (size_t)n * stride + (size_t)iy * NH + kz;
+        const float wz = ((kz == 0 || kz == N / 2) ? 1.f : 2.f) * inv_n3;
+        float2 g = a.out[0][gi];
+        g.x += wz * hold[q].x;
+        g.y += wz * hold[q].y;
+        a.out[0][gi] = g;
+      }
     } else {
 #pragma unroll
       for (int o = 0; o < n_out; ++o) {
@@ -1109,6 +1200,12 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float c = grad_coef<N>(k, o) * inv_n3;
             x = cmul_i<1>(make_float2(c * x.x, c * x.y));
+          } else if constexpr (OP == XOP_HESS) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            int pa, pb;
+            hess_pair(a.param_index, o, pa, pb);
+            const float h = hess_coef<N>(k, pa, pb) * inv_n3;
+            x = make_float2(h * x.x, h * x.y);
           } else if constexpr (OP == XOP_GAUSS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float g = __expf(-0.5f * k.k2 * Rg * Rg) * inv_n3;
@@ -1191,7 +1288,8 @@ void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
       return;
     }
   }
-  if constexpr (pairs_ok<N, PC, NTH>() && OP != XOP_ZA && OP != XOP_ZA_ADJ) {
+  if constexpr (pairs_ok<N, PC, NTH>() && OP != XOP_ZA && OP != XOP_ZA_ADJ && OP != XOP_HESS &&
+                OP != XOP_HESS_ADJ) {
     if (a.in_pitch % 2 == 0 && a.out_pitch % 2 == 0) {
       constexpr auto k = xpass_kernel<N, OP, PC, NTH, 2>;
       k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
@@ -1229,7 +1327,7 @@ void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
 // more than 8 points per thread they would spill, so they run on half-width tiles.
 template <int OP>
 constexpr bool multi_input() {
-  return OP == XOP_FORCE_ADJ || OP == XOP_FEAT_ADJ || OP == XOP_ZA_ADJ;
+  return OP == XOP_FORCE_ADJ || OP == XOP_FEAT_ADJ || OP == XOP_ZA_ADJ || OP == XOP_HESS_ADJ;
 }
 
 template <int N, int OP>
@@ -1263,6 +1361,8 @@ void xpass_dispatch(int op, const XPassArgs& a, hipStream_t s) {
     case XOP_FEAT_ADJ: xpass_op<N, XOP_FEAT_ADJ>(a, s); break;
     case XOP_ZA: xpass_op<N, XOP_ZA>(a, s); break;
     case XOP_ZA_ADJ: xpass_op<N, XOP_ZA_ADJ>(a, s); break;
+    case XOP_HESS: xpass_op<N, XOP_HESS>(a, s); break;
+    case XOP_HESS_ADJ: xpass_op<N, XOP_HESS_ADJ>(a, s); break;
     default: break;
   }
 }

@@ -133,6 +133,9 @@ struct pmr_ctx {
   float2* cA;    // [B][cmax]
   float2* cB;    // [B][3][cmax]
   float* psi;    // [B][3][np3]
+  float* psi2;   // second-order displacement [B][3][np3]; component 0 also holds S, S_bar
+  float* phi;    // second derivatives of the linear potential [B][6][np3] (xx yy zz xy xz yz)
+  float* phibar; // their adjoints [B][6][np3]
   float* delta_f;  // [B][no3]
   float* dR;       // [2][B][no3]
   float* mass;
@@ -173,6 +176,7 @@ int validate(const pmr_config* c) {
   if (!(c->box > 0) || !(c->a0 > 0) || !(c->a1 > c->a0) || !(c->omega_m > 0) || !(c->omega_m <= 1))
     return PMR_E_INVALID;
   if (!(c->R1 >= 0) || !(c->R2 >= 0)) return PMR_E_INVALID;
+  if (c->ic_order < 0 || c->ic_order > 2) return PMR_E_INVALID;
   const double np3 = (double)c->n_part * c->n_part * c->n_part;
   const double nm3 = (double)c->n_mesh * c->n_mesh * c->n_mesh;
   const double no3 = (double)c->n_out * c->n_out * c->n_out;
@@ -239,6 +243,10 @@ void plan(pmr_ctx* c, Plan& P) {
   c->cA = P.take<float2>(B * c->cmax);
   c->cB = P.take<float2>(B * 3 * c->cmax);
   c->psi = P.take<float>(B * 3 * c->np3);
+  const size_t l2 = c->cfg.ic_order == 2 ? B * c->np3 : 0;
+  c->psi2 = P.take<float>(3 * l2);
+  c->phi = P.take<float>(6 * l2);
+  c->phibar = P.take<float>(6 * l2);
   c->delta_f = P.take<float>(B * c->no3);
   c->dR = P.take<float>(2 * B * c->no3);
   c->mass = P.take<float>(B * c->no3);
@@ -452,6 +460,75 @@ void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, con
 }
 
 // ---------------------------------------------------------------- PM pieces
+// Second-order LPT (Sec. 3 starts from 2LPT): the second-order growth is D2 = -(3/7) D^2
+// (the Einstein-de Sitter ratio), so x0 gains (3/7) D0^2 Psi2 and p0 gains (6/7) D0 Gp0 Psi2.
+constexpr double kLpt2 = 3.0 / 7.0;
+
+// phi_ab = irfft(k_a k_b / k^2 P s) (two Hessian passes of three pairs), the source S, and
+// Psi2 = irfft(i k / k^2 rfft(S)) into psi2.
+void lpt2_forward(pmr_ctx* c) {
+  const size_t cp = c->sp, np3 = c->np3;
+  for (int set = 0; set < 2; ++set) {
+    XPassArgs a = xargs(c, c->np);
+    a.n_in = 1;
+    a.n_out = 3;
+    a.in[0] = c->ps;  // projected modes, standard layout
+    for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cp;
+    a.in_item_stride = c->cp;
+    a.in_pitch = (size_t)(c->np / 2 + 1);
+    a.out_item_stride = 3 * cp;
+    a.param_index = set;
+    launch_xpass(XOP_HESS, a, c->stream);
+    c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->phi + set * 3 * np3, 6 * np3, np3, nullptr);
+  }
+  launch_lpt2_source(c->phi, c->B, c->log_np3, c->psi2, 3 * np3, c->stream);
+  r2c_zy(c, c->np, 1, c->psi2, 3 * np3, 0, nullptr, 1.f, 0.f, nullptr, c->cA, cp, 0);
+  XPassArgs a = xargs(c, c->np);
+  a.n_in = 1;
+  a.n_out = 3;
+  a.in[0] = c->cA;
+  for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cp;
+  a.in_item_stride = cp;
+  a.out_item_stride = 3 * cp;
+  launch_xpass(XOP_FORCE, a, c->stream);
+  c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->psi2, 3 * np3, np3, nullptr);
+}
+
+// Adds the second-order part of the gradient: Psi2_bar = (3/7) D0^2 x_bar + (6/7) D0 Gp0 p_bar,
+// S_bar = sum_a irfft(conj(i k_a / k^2) rfft(Psi2_bar_a)), phi_bar from S_bar, and
+// G += w(kz) sum_ab k_a k_b / k^2 rfft(phi_bar_ab) / n^3.
+void lpt2_adjoint(pmr_ctx* c, float2* grad) {
+  const size_t cp = c->sp, np3 = c->np3;
+  r2c_zy(c, c->np, 3, c->xbar, 3 * np3, np3, c->pbar, (float)(kLpt2 * c->D0 * c->D0),
+         (float)(2.0 * kLpt2 * c->D0 * c->Gp0), nullptr, c->cB, 3 * cp, cp);
+  {
+    XPassArgs a = xargs(c, c->np);
+    a.n_in = 3;
+    a.n_out = 1;
+    for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cp;
+    a.out[0] = c->cA;
+    a.in_item_stride = 3 * cp;
+    a.out_item_stride = cp;
+    launch_xpass(XOP_FORCE_ADJ, a, c->stream);
+  }
+  c2r_yz(c, c->np, 1, c->cA, cp, 0, c->psi2, 3 * np3, 0, nullptr);
+  launch_lpt2_phi_bar(c->phi, c->psi2, 3 * np3, c->B, c->log_np3, c->phibar, c->stream);
+  for (int set = 0; set < 2; ++set) {
+    r2c_zy(c, c->np, 3, c->phibar + set * 3 * np3, 6 * np3, np3, nullptr, 1.f, 0.f, nullptr,
+           c->cB, 3 * cp, cp);
+    XPassArgs a = xargs(c, c->np);
+    a.n_in = 3;
+    a.n_out = 1;
+    for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cp;
+    a.out[0] = grad;  // standard layout
+    a.in_item_stride = 3 * cp;
+    a.out_item_stride = c->cp;
+    a.out_pitch = (size_t)(c->np / 2 + 1);
+    a.param_index = set;
+    launch_xpass(XOP_HESS_ADJ, a, c->stream);
+  }
+}
+
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
 Vec3* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
@@ -701,9 +778,14 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     a.out_item_stride = 3 * cp;
     launch_xpass(XOP_ZA, a, s);
     c2r_yz(c, c->np, 3, c->cB, 3 * cp, cp, c->psi, 3 * c->np3, c->np3, nullptr);
+    const bool second = c->cfg.ic_order == 2;
+    if (second) lpt2_forward(c);
     const int key_nm = c->n == 0 ? c->no : c->nm;
-    launch_za_init(c->psi, B, c->np, c->log_np3, c->cfg.box, 0.5 * (c->cfg.box / c->nm), c->D0,
-                   (float)c->Gp0, xslot(c, 0), c->p, c->keys, c->frac_id, key_nm, s);
+    launch_za_init(c->psi, second ? c->psi2 : nullptr, B, c->np, c->log_np3, c->cfg.box,
+                   0.5 * (c->cfg.box / c->nm), c->D0, (float)c->Gp0,
+                   second ? kLpt2 * c->D0 * c->D0 : 0.0,
+                   second ? (float)(2.0 * kLpt2 * c->D0 * c->Gp0) : 0.f, xslot(c, 0), c->p,
+                   c->keys, c->frac_id, key_nm, s);
   }
   // H2-H7: the PM steps
   pm_run(c, 0, c->n, true);
@@ -893,6 +975,7 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     a.inv_var = c->inv_var;
     a.loss_bar = loss_bar;
     launch_xpass(XOP_ZA_ADJ, a, s);
+    if (c->cfg.ic_order == 2) lpt2_adjoint(c, (float2*)grad);
   }
   return check(c);
 }

@@ -129,6 +129,9 @@ enum XOp : int {
   XOP_FEAT_ADJ = 6,   // 2 in (A, B): fwd, (G1 A - G2 B)/n^3, inv; -> 1 out
   XOP_ZA = 7,         // 1 in (projected modes, already spectral): * i k_a / k^2 / n^3, inv; -> 3
   XOP_ZA_ADJ = 8,     // 3 in: fwd, gradient assembly with the prior term; -> caller's gradient
+  XOP_HESS = 9,       // 1 in (projected modes): * k_a k_b / k^2 / n^3, inv; -> 3 (pair set at
+                      // param_index: 0 -> xx, yy, zz; 1 -> xy, xz, yz)
+  XOP_HESS_ADJ = 10,  // 3 in (same pair sets): fwd, sum k_a k_b / k^2 / n^3; caller's gradient +=
 };
 
 struct XPassArgs {
@@ -144,7 +147,7 @@ struct XPassArgs {
   double R1, R2;       // feature scales (XOP_GAUSS2 / XOP_FEAT_ADJ)
   const double* params;  // device loss params [B][6] (XOP_GAUSS reads R at param_index)
   int param_index;
-  // gradient assembly (XOP_ZA_ADJ)
+  // gradient assembly (XOP_ZA_ADJ, XOP_HESS_ADJ)
   const float2* proj_modes;  // P s
   const float* inv_var;      // 1 / S(k), shared by all items
   const double* loss_bar;    // [B]
@@ -212,9 +215,16 @@ void launch_adjoint_positions(const uint32_t* keys, const Vec3* frac, const Vec3
 void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch, int log_np3,
                            float kick, float drift, int final_mode, Vec3* vnext, float kick_next,
                            float drift_next, const uint32_t* vperm, hipStream_t s);
-void launch_za_init(const float* psi, int batch, int np, int log_np3, double box, double half_cell,
-                    double D0, float Gp0, double* x, float* p, uint32_t* keys, Vec3* frac,
-                    int key_nm, hipStream_t s);
+// Initial positions and momenta from the first-order displacement psi and, when psi2 is
+// not null, the second-order one: x = wrap(q + D0 psi + c2x psi2), p = Gp0 psi + c2p psi2.
+void launch_za_init(const float* psi, const float* psi2, int batch, int np, int log_np3,
+                    double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
+                    double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s);
+// Second-order LPT pointwise kernels (phi: [B][6][np^3], pairs xx, yy, zz, xy, xz, yz).
+void launch_lpt2_source(const float* phi, int batch, int log_np3, float* S, size_t s_item_stride,
+                        hipStream_t s);
+void launch_lpt2_phi_bar(const float* phi, const float* Sbar, size_t s_item_stride, int batch,
+                         int log_np3, float* phibar, hipStream_t s);
 
 // halo.hip
 size_t mlp_weight_floats(int H);

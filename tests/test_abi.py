@@ -34,7 +34,8 @@ def test_status_strings():
 @pytest.mark.parametrize("bad", [
     dict(n_part=24), dict(n_part=8), dict(n_mesh=64, n_part=16), dict(n_out=64),
     dict(batch=0), dict(n_steps=0), dict(mlp_hidden=12), dict(box=0.0), dict(a1=0.05),
-    dict(ckpt_every=-1), dict(precision=7), dict(loss_kind=3), dict(n_part=512, n_mesh=512,
+    dict(ckpt_every=-1), dict(precision=7), dict(loss_kind=3), dict(ic_order=3),
+    dict(ic_order=-1), dict(n_part=512, n_mesh=512,
                                                                      n_out=512, batch=32)])
 def test_invalid_configs_rejected(bad):
     cfg = api.Config(**{**dict(n_part=16, n_mesh=16, n_out=16), **bad})
@@ -60,6 +61,12 @@ def test_workspace_plan_and_checks():
     less = api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
                                           ckpt_every=2))
     assert less < more
+    # second-order initial conditions keep phi_ab, their adjoints and Psi2: 15 fields more
+    lpt2 = api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
+                                          ic_order=2))
+    assert lpt2 - more == 15 * 4 * 32 ** 3
+    assert api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
+                                          ic_order=0)) == more
 
 
 def test_primitives_reject_bad_shapes_without_touching_memory():

@@ -13,8 +13,8 @@ pytestmark = pytest.mark.gpu
 
 
 def _problem(n, nm, no, box, steps, kind, B, hidden=8, R_sm=(0.0,), seed=1, mu=0.1,
-             prior_weight=1.0):
-    ocfg = OM.Config(box, n, nm, no, steps, loss_kind=kind)
+             prior_weight=1.0, ic_order=1):
+    ocfg = OM.Config(box, n, nm, no, steps, loss_kind=kind, ic_order=ic_order)
     power = OC.bbks_power()
     inv = OM.prior_inv_variance(n, box, power)
     modes = [OM.linear_modes(synth.white_noise(seed + 10 * b, n), box, power) for b in range(B)]
@@ -40,7 +40,7 @@ def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P
     n = ocfg.n_part
     cfg = P.Config(batch=B, n_part=n, n_mesh=ocfg.n_mesh, n_out=ocfg.n_out, n_steps=ocfg.n_steps,
                    mlp_hidden=hidden, box=ocfg.box, ckpt_every=ckpt, precision=precision,
-                   loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2)
+                   loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2, ic_order=ocfg.ic_order)
     pm = P.PMContext(cfg, DEV)
     pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
     if w is not None:
@@ -276,4 +276,42 @@ def test_small_networks(hidden):
     say(f"pipeline: 16^3, H={hidden}")
     prob = _problem(16, 16, 16, 50.0, 3, OM.LOSS_LOGNORMAL, 2, hidden=hidden, R_sm=(1.0, 0.0))
     res = _gpu_run(*prob, hidden=hidden)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_second_order_lpt_density_l2():
+    """Second-order LPT initial conditions (32^3 particles, 64^3 force mesh, B = 2): the
+    positions, loss and mode gradient against the oracle; the second-order displacement
+    alone (x0 of the 2LPT run minus x0 of the Zel'dovich run of the same modes) against the
+    oracle's (3/7) D0^2 Psi2; a second adjoint reproduces the first bit for bit."""
+    require_gpu()
+    say("pipeline: 2LPT density-L2 32^3 / 64^3 mesh, B=2")
+    prob = _problem(32, 64, 64, 100.0, 4, OM.LOSS_DENSITY_L2, 2, ic_order=2)
+    ocfg, inv, modes, w, targets, params = prob
+    res = _gpu_run(*prob)
+    _compare(*prob, res, TOL_FP32)
+    g2 = res["pm"].adjoint(torch.ones(2, dtype=torch.float64, device=DEV)).cpu().numpy()
+    assert np.array_equal(g2, res["grad"])
+    c1 = OM.Config(ocfg.box, 32, 64, 64, 4, loss_kind=OM.LOSS_DENSITY_L2, ic_order=1)
+    res1 = _gpu_run(c1, inv, modes, w, targets, params)
+    D = ocfg.fac["D0"]
+    for b in range(2):
+        _, _, _, extra = OM.zeldovich(ocfg, modes[b], full=True)
+        ref = OM.LPT2_D * D * D * extra["psi2"]
+        d = res["xs"][0][b] - res1["xs"][0][b]
+        d = (d + ocfg.box / 2) % ocfg.box - ocfg.box / 2
+        e = rel_l2(d, ref)
+        say(f"  item {b}: second-order displacement rel_l2={e:.3e}, "
+            f"rms={np.sqrt(np.mean(ref ** 2)) / (ocfg.box / 64):.3e} cells")
+        assert e < 1e-3, e
+
+
+def test_second_order_lpt_lognormal_with_checkpoints():
+    """2LPT with the log-normal likelihood and checkpointed steps (32^3, H = 32, 6 steps,
+    a checkpoint every 2 steps)."""
+    require_gpu()
+    say("pipeline: 2LPT log-normal 32^3, ckpt 2")
+    prob = _problem(32, 32, 32, 100.0, 6, OM.LOSS_LOGNORMAL, 1, hidden=32, R_sm=(2.0,),
+                    ic_order=2)
+    res = _gpu_run(*prob, hidden=32, ckpt=2)
     _compare(*prob, res, TOL_FP32)
