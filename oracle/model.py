@@ -11,7 +11,11 @@ What is computed, in the paper's order
    particle-mesh kick-drift-kick evolution with FastPM-style linear-exact factors.
    (The paper starts from 2LPT; the Zel'dovich start is the stated reading.)
 3. Halo model (Sec. 2.1, Sec. 2.2): features (delta_0, delta_R1, delta_R1 - delta_R2) of
-   the final CIC density, a per-voxel fully connected network, mass = softplus(output).
+   the final CIC density, then either a per-voxel fully connected network with
+   mass = softplus(output) (halo_model = HALO_SINGLE), or the paper's two networks
+   (HALO_TWO): a position network on the features of the 3 x 3 x 3 neighbourhood whose
+   logistic output (sharpness a, Eq. logistic) is multiplied by a mass network on the
+   voxel's own features (Sec. 2.1, Sec. 2.3).
 4. Likelihood (Sec. 5.1, Eqs. var, probnoise, loss): x = log(M_R + M0) with M_R the
    Gaussian-smoothed mass; residual (mu + x - x_data) / (2 sigma_N); f_eff = 1.
    Residual smoothing anneal (Sec. 5.2): the residual is Gaussian-smoothed on R_sm
@@ -32,12 +36,14 @@ from . import mesh as M
 
 LOSS_DENSITY_L2 = 0
 LOSS_LOGNORMAL = 1
+HALO_SINGLE = 0
+HALO_TWO = 1
 
 
 class Config:
     def __init__(self, box, n_part, n_mesh, n_out, n_steps, a0=0.1, a1=1.0,
                  omega_m=cos.OMEGA_M_PAPER, R1=1.0, R2=2.0, loss_kind=LOSS_LOGNORMAL,
-                 ic_order=1):
+                 ic_order=1, halo_model=HALO_SINGLE):
         self.box = float(box)
         self.n_part, self.n_mesh, self.n_out = int(n_part), int(n_mesh), int(n_out)
         self.n_steps = int(n_steps)
@@ -45,11 +51,13 @@ class Config:
         self.R1, self.R2 = float(R1), float(R2)
         self.loss_kind = loss_kind
         self.ic_order = int(ic_order)  # 1: Zel'dovich, 2: second-order LPT
+        self.halo_model = int(halo_model)
         self.fac = cos.kdk_factors(self.a0, self.a1, self.n_steps, self.omega_m)
 
 
 def default_params(**kw):
-    p = dict(M0=1.0, mu=0.0, sigma_N=0.5, R_mass=3.0, R_sm=0.0, prior_weight=1.0)
+    p = dict(M0=1.0, mu=0.0, sigma_N=0.5, R_mass=3.0, R_sm=0.0, prior_weight=1.0,
+             logistic_a=3.0)
     p.update(kw)
     return p
 
@@ -200,6 +208,80 @@ def mlp_backward(w, cache, mass_bar):
     return W1.T @ a1_bar
 
 
+# The paper's two-network model (Sec. 2.1: model = NNp x NNm; Sec. 2.3: architecture).
+
+# Offsets of the 3 x 3 x 3 neighbourhood; position-network feature c * 27 + o holds
+# feature field c at the voxel displaced by STENCIL[o] (periodic mesh).
+STENCIL = tuple((dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+
+
+def elu(v):
+    """Eq. elu: v for v > 0, exp(v) - 1 otherwise."""
+    return np.where(v > 0, v, np.expm1(np.minimum(v, 0.0)))
+
+
+def logistic(x, a):
+    """Eq. logistic: 1 / (1 + exp(-a x)) (written with tanh, which cannot overflow)."""
+    return 0.5 * (1.0 + np.tanh(0.5 * a * x))
+
+
+def stencil_features(f):
+    """(3, n, n, n) feature fields -> (81, n^3): the values of each field on the voxel's
+    3 x 3 x 3 neighbourhood (Sec. 2.2: the position network sees 3 x 27 = 81 features)."""
+    rows = []
+    for c in range(3):
+        for d in STENCIL:
+            rows.append(np.roll(f[c], shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2)).ravel())
+    return np.stack(rows)
+
+
+def stencil_adjoint(Fbar, n):
+    """Transpose of stencil_features: (81, n^3) -> (3, n, n, n)."""
+    out = np.zeros((3, n, n, n))
+    for c in range(3):
+        for o, d in enumerate(STENCIL):
+            out[c] += np.roll(Fbar[c * 27 + o].reshape(n, n, n), shift=d, axis=(0, 1, 2))
+    return out
+
+
+def _w(net, k):
+    return np.asarray(net[k], dtype=np.float64)
+
+
+def two_net_forward(nets, f, a):
+    """NNp: 81 features -> 50 -> 30 (ReLU) -> 1, then logistic(., a) (the position mask);
+    NNm: 3 features -> 20 -> 10 (ELU) -> 1, linear (the mass); mass = NNp x NNm.
+    f: (3, n, n, n). Returns a dict of pre-activations and the mass (n^3,)."""
+    p, m = nets["nnp"], nets["nnm"]
+    F = stencil_features(f)
+    a1 = _w(p, "W1") @ F + _w(p, "b1")[:, None]
+    a2 = _w(p, "W2") @ relu(a1) + _w(p, "b2")[:, None]
+    y = (_w(p, "W3") @ relu(a2) + _w(p, "b3")[:, None])[0]
+    pos = logistic(y, a)
+    f3 = f.reshape(3, -1)
+    z1 = _w(m, "W1") @ f3 + _w(m, "b1")[:, None]
+    z2 = _w(m, "W2") @ elu(z1) + _w(m, "b2")[:, None]
+    mm = (_w(m, "W3") @ elu(z2) + _w(m, "b3")[:, None])[0]
+    return {"a1": a1, "a2": a2, "y": y, "pos": pos, "z1": z1, "z2": z2, "m": mm,
+            "mass": pos * mm}
+
+
+def two_net_backward(nets, cache, mass_bar, a, n):
+    """Input gradient of the two-network model (weights frozen): (3, n, n, n)."""
+    p, m = nets["nnp"], nets["nnm"]
+    pos_bar = mass_bar * cache["m"]
+    m_bar = mass_bar * cache["pos"]
+    pos = cache["pos"]
+    y_bar = pos_bar * a * pos * (1.0 - pos)  # d logistic(y, a) / dy
+    a2_bar = (_w(p, "W3")[0][:, None] * y_bar[None, :]) * (cache["a2"] > 0)
+    a1_bar = (_w(p, "W2").T @ a2_bar) * (cache["a1"] > 0)
+    fbar = stencil_adjoint(_w(p, "W1").T @ a1_bar, n)
+    delu = lambda z: np.where(z > 0, 1.0, np.exp(np.minimum(z, 0.0)))  # noqa: E731
+    z2_bar = (_w(m, "W3")[0][:, None] * m_bar[None, :]) * delu(cache["z2"])
+    z1_bar = (_w(m, "W2").T @ z2_bar) * delu(cache["z1"])
+    return fbar + (_w(m, "W1").T @ z1_bar).reshape(3, n, n, n)
+
+
 def smooth(cfg, field, R):
     n = field.shape[0]
     return M.apply_multiplier(field, M.gaussian_multiplier(n, cfg.box, R))
@@ -247,7 +329,10 @@ def forward(cfg, s, inv_S, target, params, mlp=None):
         out["mass"] = None
     else:
         f = features(cfg, delta_f)
-        c = mlp_forward(mlp, f.reshape(3, -1))
+        if cfg.halo_model == HALO_TWO:
+            c = two_net_forward(mlp, f, params["logistic_a"])
+        else:
+            c = mlp_forward(mlp, f.reshape(3, -1))
         mass = c["mass"].reshape(n_o, n_o, n_o)
         MR = smooth(cfg, mass, params["R_mass"])
         xd = target_x(cfg, target, params)
@@ -338,7 +423,11 @@ def halo_adjoint(cfg, fwd, target, params, mlp, loss_bar=1.0):
     MR_bar = x_bar / (fwd["MR"] + params["M0"])
     mass_bar = smooth(cfg, MR_bar, params["R_mass"])
     n_o = cfg.n_out
-    fbar = mlp_backward(mlp, fwd["mlp_cache"], mass_bar.ravel()).reshape(3, n_o, n_o, n_o)
+    if cfg.halo_model == HALO_TWO:
+        fbar = two_net_backward(mlp, fwd["mlp_cache"], mass_bar.ravel(), params["logistic_a"],
+                                n_o)
+    else:
+        fbar = mlp_backward(mlp, fwd["mlp_cache"], mass_bar.ravel()).reshape(3, n_o, n_o, n_o)
     g1 = M.gaussian_multiplier(n_o, cfg.box, cfg.R1)
     g2 = M.gaussian_multiplier(n_o, cfg.box, cfg.R2)
     spec = g1 * M.rfft3(fbar[1] + fbar[2]) - g2 * M.rfft3(fbar[2])

@@ -9,6 +9,7 @@ from .inputs import (  # noqa: F401
     white_noise,
     mlp_weights_raw,
     mlp_weights,
+    halo_net_weights,
     unit_normal,
     random_positions,
     random_modes_direction,

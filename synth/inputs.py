@@ -58,3 +58,28 @@ def mlp_weights(seed, hidden, n_in=3):
     for k in ("b1", "b2", "b3"):
         out[k] = np.ascontiguousarray((raw[k] * 0.01).astype(np.float32))
     return out
+
+
+def halo_net_weights(seed):
+    """Seeded weights of the two-network halo model (untrained): the position network
+    81 -> 50 -> 30 -> 1 and the mass network 3 -> 20 -> 10 -> 1, float32 row-major
+    [out][in]. Hidden weights ~ N(0, 2 / fan_in), hidden biases ~ N(0, 0.01^2); the mass
+    network's output layer is scaled by 0.1 with bias 1, so that its (linear) output stays
+    near 1 and the modelled mass stays positive."""
+    r = _rng(seed)
+
+    def layer(n_out, n_in, scale=None):
+        s = np.sqrt(2.0 / n_in) if scale is None else scale
+        return (r.standard_normal((n_out, n_in)) * s).astype(np.float32), \
+            (r.standard_normal(n_out) * 0.01).astype(np.float32)
+
+    nnp, nnm = {}, {}
+    nnp["W1"], nnp["b1"] = layer(50, 81)
+    nnp["W2"], nnp["b2"] = layer(30, 50)
+    nnp["W3"], nnp["b3"] = layer(1, 30)
+    nnm["W1"], nnm["b1"] = layer(20, 3)
+    nnm["W2"], nnm["b2"] = layer(10, 20)
+    nnm["W3"], b = layer(1, 10, scale=0.1 * np.sqrt(2.0 / 10))
+    nnm["b3"] = (b + 1.0).astype(np.float32)
+    return {"nnp": {k: np.ascontiguousarray(v) for k, v in nnp.items()},
+            "nnm": {k: np.ascontiguousarray(v) for k, v in nnm.items()}}
