@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PM forward+adjoint steps/s at 128^3 & 256^3; % HBM roofline; err vs FP64"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published; counts the packed two-lane FP32 FMA
 
 # Counter summaries (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a 1 GiB copy)
 # per workload, and the kernels each profiled class consists of.
@@ -98,12 +99,16 @@ def make_context(w, dev, data=None):
     cfg = P.Config(batch=w["batch"], n_part=w["n_part"], n_mesh=w["n_mesh"], n_out=w["n_out"],
                    n_steps=w["n_steps"], mlp_hidden=w["mlp_hidden"], precision=w["precision"],
                    ckpt_every=w["ckpt_every"], box=w["box"], loss_kind=P.PMR_LOSS_LOGNORMAL,
-                   ic_order=w.get("ic_order", 1))
+                   ic_order=w.get("ic_order", 1), halo_model=w.get("halo_model", 0))
     B, n, box = cfg.batch, cfg.n_part, cfg.box
     power = cosmo.linear_power(0.8, 0.2)
     pm = P.PMContext(cfg, dev)
     pm.set_prior(torch.from_numpy(cosmo.prior_inv_variance(n, box, power)))
-    pm.set_mlp({k: torch.from_numpy(v) for k, v in synth.mlp_weights(3, cfg.mlp_hidden).items()})
+    if cfg.halo_model == P.PMR_HALO_TWO:
+        pm.set_halo_nets(synth.halo_net_weights(3))
+    else:
+        pm.set_mlp({k: torch.from_numpy(v)
+                    for k, v in synth.mlp_weights(3, cfg.mlp_hidden).items()})
 
     def modes(seed0):
         return torch.stack([torch.from_numpy(cosmo.modes_from_white_noise(
@@ -220,6 +225,31 @@ def time_gradient(pm, modes, steps, warmup):
         pm.adjoint(ones, out=grad)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, grad
+
+
+def two_network_leg(w, dev, data, steps):
+    """The same gradient with the paper's two-network halo model on the same data, and the
+    event-timed rate of its kernels: the networks (FLOPs, vector ALU bound) and the
+    neighbourhood sum of the position network's input adjoint (HBM bytes)."""
+    import paper_1805_02247_amd as P
+    pm, modes = make_context(dict(w, halo_model=P.PMR_HALO_TWO), dev, data=data)
+    t, _ = time_gradient(pm, modes, steps, 1)
+    out = {"ms_per_step": 1e3 * t}
+    for cls in ("halo2", "halo2_stencil"):
+        pm.profile_begin(cls, max_launches=16)
+        time_gradient(pm, modes, 2, 0)
+        ms, n, alg = pm.profile_end()
+        avg = ms * 1e-3 / max(n, 1)
+        if cls == "halo2":
+            ach = alg / max(n, 1) / avg / 1e12
+            out[cls] = {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK_TFLOPS,
+                        "avg_launch_us": avg * 1e6, "launches": n}
+        else:
+            ach = alg / max(n, 1) / avg / 1e9
+            out[cls] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "avg_launch_us": avg * 1e6, "launches": n}
+    return out
 
 
 def mixed_vs_fp32(dev, steps):
@@ -451,6 +481,7 @@ def main():
         out["second_order_ics"] = {"ms_per_step_zeldovich": 1e3 * t_plain,
                                    "ms_per_step_2lpt": 1e3 * t_2lpt}
         del pm2, modes2
+        out["two_network"] = two_network_leg(w, dev, pm.data, max(2, args.steps // 2))
     if args.no_cpu_baseline:
         out["cpu_baseline"] = None
     else:

@@ -51,6 +51,11 @@ enum {
 
 enum { PMR_FP32 = 0, PMR_MIXED = 1 };
 enum { PMR_LOSS_DENSITY_L2 = 0, PMR_LOSS_LOGNORMAL = 1 };
+/* Halo model of the log-normal loss: one softplus network on the voxel's features, or the
+ * paper's product of a position network and a mass network (Sec. 2.1, Sec. 2.3). */
+enum { PMR_HALO_SINGLE = 0, PMR_HALO_TWO = 1 };
+/* Floats of the packed weight blocks of the two networks (pmr_set_halo_nets). */
+enum { PMR_NNP_FLOATS = 50 * 81 + 50 + 30 * 50 + 30 + 30 + 1, PMR_NNM_FLOATS = 20 * 3 + 20 + 10 * 20 + 10 + 10 + 1 };
 
 typedef struct pmr_config {
   int batch;      /* independent realisations B >= 1 */
@@ -58,7 +63,8 @@ typedef struct pmr_config {
   int n_mesh;     /* force mesh per axis: Np or 2 Np, <= 512 */
   int n_out;      /* output (halo-model) mesh per axis: Np or n_mesh */
   int n_steps;    /* kick-drift-kick steps, uniform in a, >= 1 */
-  int mlp_hidden; /* hidden width H of the 3 -> H -> H -> 1 network: 8, 16, 32 or 64 */
+  int mlp_hidden; /* hidden width H of the 3 -> H -> H -> 1 network: 8, 16, 32 or 64
+                     (PMR_HALO_SINGLE; ignored by PMR_HALO_TWO) */
   int precision;  /* PMR_FP32, or PMR_MIXED (network on BF16 matrix cores) */
   int ckpt_every; /* 0: keep every step for the adjoint; k >= 1: keep (x, p) every k steps
                      and recompute the steps in between during the adjoint */
@@ -69,6 +75,7 @@ typedef struct pmr_config {
   double R1, R2;  /* Gaussian feature scales, Mpc/h (Sec. 2.2) */
   int ic_order;   /* initial conditions (Sec. 3): 0 or 1 first-order (Zel'dovich) displacement,
                      2 second-order LPT (adds 3/7 D0^2 Psi2 to x0 and 6/7 D0 Gp0 Psi2 to p0) */
+  int halo_model; /* PMR_HALO_SINGLE, or PMR_HALO_TWO (log-normal loss and PMR_FP32 only) */
 } pmr_config;
 
 /* Loss parameters of one batch item (Sec. 5.1, Eq. loss; Sec. 5.2 anneals R_sm and M0). */
@@ -79,6 +86,8 @@ typedef struct pmr_loss_params {
   double R_mass;       /* Gaussian smoothing of model and data mass fields, Mpc/h */
   double R_sm;         /* residual smoothing of the anneal, Mpc/h (0 = none) */
   double prior_weight; /* weight of the prior term (1 for Eq. loss) */
+  double logistic_a;   /* sharpness a of the position network's logistic, Eq. logistic
+                          (PMR_HALO_TWO; Sec. 5.2 anneals it 1 -> 2 -> 3); > 0 */
 } pmr_loss_params;
 
 typedef struct pmr_ctx pmr_ctx;
@@ -102,6 +111,19 @@ int pmr_set_prior(pmr_ctx* ctx, const float* inv_var);
  * W3 [1][H], b3 [1] (Sec. 2.1; frozen). Copied. Required for PMR_LOSS_LOGNORMAL. */
 int pmr_set_mlp(pmr_ctx* ctx, const float* W1, const float* b1, const float* W2,
                 const float* b2, const float* W3, const float* b3);
+
+/* Weights of the two-network halo model (Sec. 2.1: model = NNp x NNm; Sec. 2.3), device
+ * float32, each network packed as its layers in order, weights row-major [out][in]:
+ *   nnp (PMR_NNP_FLOATS): W1 [50][81], b1 [50], W2 [30][50], b2 [30], W3 [1][30], b3 [1];
+ *     ReLU hidden layers, output logistic(y, a) with a the loss parameter logistic_a;
+ *     input feature c * 27 + o is feature field c (delta_0, delta_R1, delta_R1 - delta_R2)
+ *     at the voxel displaced by (dx, dy, dz) = (o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1),
+ *     periodic (Sec. 2.2: the 3 x 3 x 3 neighbourhood);
+ *   nnm (PMR_NNM_FLOATS): W1 [20][3], b1 [20], W2 [10][20], b2 [10], W3 [1][10], b3 [1];
+ *     ELU hidden layers (Eq. elu), linear output, on the voxel's own three features.
+ * The modelled mass NNp x NNm must keep M_R + M0 > 0 for the log of the likelihood.
+ * Copied (stream-ordered). PMR_E_STATE unless the context was created with PMR_HALO_TWO. */
+int pmr_set_halo_nets(pmr_ctx* ctx, const float* nnp, const float* nnm);
 
 /* Data field [B][Nout^3]: the halo mass field (log-normal loss) or the target density
  * contrast (density-L2 loss). Copied. */
@@ -185,7 +207,11 @@ enum {
   PMR_PROF_PAINT3 = 6,            /* three-channel adjoint paint */
   PMR_PROF_XPASS_FORCE_ADJ = 7,   /* outermost-axis pass with the force adjoint, 3 -> 1 */
   PMR_PROF_ADJ_GATHER = 8,        /* step-adjoint position gradient (sorted-order gather) */
-  PMR_PROF_ADJ_UPDATE = 9         /* step-adjoint kick / drift transposes (id order) */
+  PMR_PROF_ADJ_UPDATE = 9,        /* step-adjoint kick / drift transposes (id order) */
+  PMR_PROF_HALO2 = 10,            /* two-network model kernels (forward, adjoint); their
+                                     algorithmic figure is FLOPs, not bytes */
+  PMR_PROF_HALO2_STENCIL = 11     /* two-network model: neighbourhood sum of the position
+                                     network's input adjoint */
 };
 int pmr_profile_begin(pmr_ctx* ctx, int kernel_class, int max_launches);
 int pmr_profile_end(pmr_ctx* ctx, double* total_ms, long long* launches, double* alg_bytes);

@@ -9,7 +9,7 @@ What is computed, in the paper's order
    spectrum of |s|^2 / S(k), S = <|s|^2> (diagonal in k).
 2. Dynamics (Sec. 3, Sec. 5): Zel'dovich displacement at a0, then an n-step
    particle-mesh kick-drift-kick evolution with FastPM-style linear-exact factors.
-   (The paper starts from 2LPT; the Zel'dovich start is the stated reading.)
+   (The paper starts from 2LPT: ic_order = 2 adds the second-order displacement.)
 3. Halo model (Sec. 2.1, Sec. 2.2): features (delta_0, delta_R1, delta_R1 - delta_R2) of
    the final CIC density, then either a per-voxel fully connected network with
    mass = softplus(output) (halo_model = HALO_SINGLE), or the paper's two networks

@@ -13,6 +13,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
 PMR_OK = 0
 PMR_FP32, PMR_MIXED = 0, 1
 PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
+PMR_HALO_SINGLE, PMR_HALO_TWO = 0, 1
+PMR_NNP_FLOATS = 50 * 81 + 50 + 30 * 50 + 30 + 30 + 1
+PMR_NNM_FLOATS = 20 * 3 + 20 + 10 * 20 + 10 + 10 + 1
 PMR_FFT_YPASS, PMR_FFT_XPASS, PMR_FFT_XPASS_MULTI = 0, 1, 2
 DBG = {"x": 1, "force": 2, "sort_ids": 3, "delta_f": 4, "features": 5, "mass_r": 6,
        "res_s": 7, "xbar0": 8, "pbar0": 9, "dbar_f": 10}
@@ -24,13 +27,14 @@ class PmrConfig(ctypes.Structure):
                 ("precision", ctypes.c_int), ("ckpt_every", ctypes.c_int),
                 ("loss_kind", ctypes.c_int), ("box", ctypes.c_double), ("a0", ctypes.c_double),
                 ("a1", ctypes.c_double), ("omega_m", ctypes.c_double), ("R1", ctypes.c_double),
-                ("R2", ctypes.c_double), ("ic_order", ctypes.c_int)]
+                ("R2", ctypes.c_double), ("ic_order", ctypes.c_int),
+                ("halo_model", ctypes.c_int)]
 
 
 class PmrLossParams(ctypes.Structure):
     _fields_ = [("M0", ctypes.c_double), ("mu", ctypes.c_double), ("sigma_N", ctypes.c_double),
                 ("R_mass", ctypes.c_double), ("R_sm", ctypes.c_double),
-                ("prior_weight", ctypes.c_double)]
+                ("prior_weight", ctypes.c_double), ("logistic_a", ctypes.c_double)]
 
 
 class PmrError(RuntimeError):
@@ -48,6 +52,7 @@ SIGNATURES = {
     "pmr_destroy": (ci, [vp]),
     "pmr_set_prior": (ci, [vp, vp]),
     "pmr_set_mlp": (ci, [vp, vp, vp, vp, vp, vp, vp]),
+    "pmr_set_halo_nets": (ci, [vp, vp, vp]),
     "pmr_set_target": (ci, [vp, vp]),
     "pmr_set_loss": (ci, [vp, ctypes.POINTER(PmrLossParams)]),
     "pmr_set_noise_table": (ci, [vp, ci, ctypes.POINTER(cd), ctypes.POINTER(cd),
@@ -75,7 +80,8 @@ SIGNATURES = {
                              ctypes.POINTER(cd)]),
 }
 PROF = {"paint": 1, "xpass_force": 2, "ypass": 3, "zpass": 4, "kick_drift": 5, "paint3": 6,
-        "xpass_force_adj": 7, "adj_gather": 8, "adj_update": 9}
+        "xpass_force_adj": 7, "adj_gather": 8, "adj_update": 9, "halo2": 10,
+        "halo2_stencil": 11}
 
 
 def lib():

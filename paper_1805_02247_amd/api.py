@@ -48,12 +48,13 @@ class Config:
     R1: float = 1.0
     R2: float = 2.0
     ic_order: int = 1  # 1: Zel'dovich initial conditions, 2: second-order LPT
+    halo_model: int = L.PMR_HALO_SINGLE  # or PMR_HALO_TWO: the position x mass networks
 
     def c(self):
         return L.PmrConfig(self.batch, self.n_part, self.n_mesh, self.n_out, self.n_steps,
                            self.mlp_hidden, self.precision, self.ckpt_every, self.loss_kind,
                            self.box, self.a0, self.a1, self.omega_m, self.R1, self.R2,
-                           self.ic_order)
+                           self.ic_order, self.halo_model)
 
 
 @dataclass
@@ -64,6 +65,7 @@ class LossParams:
     R_mass: float = 3.0
     R_sm: float = 0.0
     prior_weight: float = 1.0
+    logistic_a: float = 3.0  # sharpness of the position network's logistic (two-network model)
 
 
 def workspace_bytes(cfg):
@@ -121,6 +123,27 @@ class PMContext:
         L.check(L.lib().pmr_set_mlp(self._ctx, *[_ptr(t) for t in ts]))
         self._keep_mlp = ts
 
+    def set_halo_nets(self, nets):
+        """Weights of the two-network model: nets = {"nnp": {W1, b1, W2, b2, W3, b3},
+        "nnm": {...}} with the shapes of pmr_set_halo_nets."""
+        sizes = {"nnp": ((50, 81), 50, (30, 50), 30, (1, 30), 1),
+                 "nnm": ((20, 3), 20, (10, 20), 10, (1, 10), 1)}
+        packed = []
+        for net in ("nnp", "nnm"):
+            parts = []
+            for k, shape in zip(("W1", "b1", "W2", "b2", "W3", "b3"), sizes[net]):
+                t = torch.as_tensor(nets[net][k]).to(torch.float32).reshape(-1)
+                n = shape[0] * shape[1] if isinstance(shape, tuple) else shape
+                if t.numel() != n:
+                    raise ValueError(f"{net}.{k}: {t.numel()} values, expected {n}")
+                parts.append(t)
+            packed.append(torch.cat(parts).to(self.device).contiguous())
+        _need(packed[0], torch.float32, L.PMR_NNP_FLOATS, "nnp")
+        _need(packed[1], torch.float32, L.PMR_NNM_FLOATS, "nnm")
+        self._sync_stream()
+        L.check(L.lib().pmr_set_halo_nets(self._ctx, _ptr(packed[0]), _ptr(packed[1])))
+        self._keep_mlp = packed
+
     def set_target(self, target):
         target = target.to(self.device, torch.float32).contiguous()
         _need(target, torch.float32, self.cfg.batch * self.n_out3, "target")
@@ -134,7 +157,8 @@ class PMContext:
         if len(params) != self.cfg.batch:
             raise ValueError("one LossParams per batch item")
         arr = (L.PmrLossParams * self.cfg.batch)(
-            *[L.PmrLossParams(p.M0, p.mu, p.sigma_N, p.R_mass, p.R_sm, p.prior_weight)
+            *[L.PmrLossParams(p.M0, p.mu, p.sigma_N, p.R_mass, p.R_sm, p.prior_weight,
+                              p.logistic_a)
               for p in params])
         self._sync_stream()
         L.check(L.lib().pmr_set_loss(self._ctx, arr))

@@ -713,7 +713,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) hold[m] = make_float2(0.f, 0.f);
     float Rg = 0.f;
-    if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
+    if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * NPRM + a.param_index];
 
     // -------- inputs
     for (int i = 0; i < n_in; ++i) {
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
       store_tile<N, PC, NTH, V>(lds, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
-      const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
+      const double lam = a.params[item * NPRM + 5] * a.loss_bar[item];
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
         const int e = t + m * NTH;
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
     const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
     const int next = tau + gridDim.x;
     float Rg = 0.f;
-    if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * 6 + a.param_index];
+    if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * NPRM + a.param_index];
 
     float2 hold[P];
 #pragma unroll
@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
       reg_store<N, PC, NTH, RLF>(hold, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
-      const double lam = a.params[item * 6 + 5] * a.loss_bar[item];
+      const double lam = a.params[item * NPRM + 5] * a.loss_bar[item];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         int n, l;

@@ -6,8 +6,8 @@
 // residual is Gaussian-smoothed on R_sm (the anneal) and squared. Sums are reduced in
 // FP64 with a fixed tree, so the loss is bitwise reproducible.
 //
-// Loss parameters live in device memory, [B][6] doubles:
-//   (M0, mu, sigma_N, R_mass, R_sm, prior_weight).
+// Loss parameters live in device memory, [B][NPRM] doubles:
+//   (M0, mu, sigma_N, R_mass, R_sm, prior_weight, logistic_a).
 #include "pmr_internal.h"
 
 namespace pmr {
@@ -480,7 +480,7 @@ __global__ void target_x_kernel(const float* __restrict__ mtr, size_t per_item, 
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= per_item * batch) return;
   const int b = (int)(v / per_item);
-  xd[v] = logf(mtr[v] + (float)prm[b * 6 + 0]);
+  xd[v] = logf(mtr[v] + (float)prm[b * NPRM + 0]);
 }
 
 // Per-cell noise (Eq. probnoise; Sec. 5.1: mu_N and sigma_N depend on the smoothed data
@@ -524,9 +524,9 @@ __global__ void residual_kernel(const float* __restrict__ mr, const float* __res
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= per_item * batch) return;
   const int b = (int)(v / per_item);
-  const float M0 = (float)prm[b * 6 + 0];
-  const float mu = nmu ? nmu[v] : (float)prm[b * 6 + 1];
-  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * 6 + 2]);
+  const float M0 = (float)prm[b * NPRM + 0];
+  const float mu = nmu ? nmu[v] : (float)prm[b * NPRM + 1];
+  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * NPRM + 2]);
   r[v] = (mu + logf(mr[v] + M0) - xd[v]) * inv2s;
 }
 
@@ -537,8 +537,8 @@ __global__ void mrbar_kernel(const float* __restrict__ rbar, const float* __rest
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= per_item * batch) return;
   const int b = (int)(v / per_item);
-  const float M0 = (float)prm[b * 6 + 0];
-  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * 6 + 2]);
+  const float M0 = (float)prm[b * NPRM + 0];
+  const float inv2s = nw ? nw[v] : (float)(0.5 / prm[b * NPRM + 2]);
   out[v] = rbar[v] * inv2s / (mr[v] + M0);
 }
 
@@ -610,7 +610,7 @@ __global__ void finalize_loss_kernel(const double* __restrict__ prior, const dou
                                      double* __restrict__ loss_out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
-  loss_out[3 * b + 0] = prm[b * 6 + 5] * prior[b] + data[b];
+  loss_out[3 * b + 0] = prm[b * NPRM + 5] * prior[b] + data[b];
   loss_out[3 * b + 1] = prior[b];
   loss_out[3 * b + 2] = data[b];
 }

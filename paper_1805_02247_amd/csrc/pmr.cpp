@@ -98,6 +98,8 @@ struct pmr_ctx {
   // device buffers
   float* inv_var;
   float* mlp_w;
+  float* halo2_w;  // prepared weights of the two-network model
+  float* u2;       // its position network's input adjoint [B][81][no3]
   float* target;
   double* params;
   float* xd;
@@ -166,13 +168,17 @@ int validate(const pmr_config* c) {
   if (c->n_mesh != c->n_part && c->n_mesh != 2 * c->n_part) return PMR_E_SHAPE;
   if (c->n_out != c->n_part && c->n_out != c->n_mesh) return PMR_E_SHAPE;
   if (c->loss_kind != PMR_LOSS_DENSITY_L2 && c->loss_kind != PMR_LOSS_LOGNORMAL) return PMR_E_INVALID;
-  if (c->loss_kind == PMR_LOSS_LOGNORMAL && c->mlp_hidden != 8 && c->mlp_hidden != 16 &&
-      c->mlp_hidden != 32 && c->mlp_hidden != 64)
+  if (c->halo_model != PMR_HALO_SINGLE && c->halo_model != PMR_HALO_TWO) return PMR_E_INVALID;
+  const bool single = c->loss_kind == PMR_LOSS_LOGNORMAL && c->halo_model == PMR_HALO_SINGLE;
+  if (single && c->mlp_hidden != 8 && c->mlp_hidden != 16 && c->mlp_hidden != 32 &&
+      c->mlp_hidden != 64)
     return PMR_E_SHAPE;
   if (c->precision != PMR_FP32 && c->precision != PMR_MIXED) return PMR_E_INVALID;
-  if (c->precision == PMR_MIXED && c->loss_kind == PMR_LOSS_LOGNORMAL && c->mlp_hidden != 32 &&
-      c->mlp_hidden != 64)
+  if (c->precision == PMR_MIXED && single && c->mlp_hidden != 32 && c->mlp_hidden != 64)
     return PMR_E_SHAPE;  // the matrix-core network tiles K in steps of 32
+  if (c->halo_model == PMR_HALO_TWO &&
+      (c->loss_kind != PMR_LOSS_LOGNORMAL || c->precision != PMR_FP32))
+    return PMR_E_SHAPE;  // the two networks exist for the log-normal loss, in FP32
   if (!(c->box > 0) || !(c->a0 > 0) || !(c->a1 > c->a0) || !(c->omega_m > 0) || !(c->omega_m <= 1))
     return PMR_E_INVALID;
   if (!(c->R1 >= 0) || !(c->R2 >= 0)) return PMR_E_INVALID;
@@ -208,8 +214,11 @@ void plan(pmr_ctx* c, Plan& P) {
   const size_t B = c->B;
   c->inv_var = P.take<float>(c->cp);
   c->mlp_w = P.take<float>(mlp_weight_floats(c->H > 0 ? c->H : 8));
+  const bool two = c->cfg.halo_model == PMR_HALO_TWO;
+  c->halo2_w = P.take<float>(two ? HALO2_WEIGHT_FLOATS : 0);
+  c->u2 = P.take<float>(two ? 81 * B * c->no3 : 0);
   c->target = P.take<float>(B * c->no3);
-  c->params = P.take<double>(B * 6);
+  c->params = P.take<double>(B * NPRM);
   c->xd = P.take<float>(B * c->no3);
   c->noise_tab = P.take<double>(3 * NOISE_MAX);
   c->noise_mu = P.take<float>(B * c->no3);
@@ -270,7 +279,9 @@ void init_sizes(pmr_ctx* c, const pmr_config* cfg) {
   c->nm = cfg->n_mesh;
   c->no = cfg->n_out;
   c->n = cfg->n_steps;
-  c->H = cfg->loss_kind == PMR_LOSS_LOGNORMAL ? cfg->mlp_hidden : 0;
+  c->H = cfg->loss_kind == PMR_LOSS_LOGNORMAL && cfg->halo_model == PMR_HALO_SINGLE
+             ? cfg->mlp_hidden
+             : 0;
   c->k = cfg->ckpt_every >= cfg->n_steps ? 0 : cfg->ckpt_every;
   c->np3 = (size_t)c->np * c->np * c->np;
   c->nm3 = (size_t)c->nm * c->nm * c->nm;
@@ -697,6 +708,14 @@ int pmr_set_mlp(pmr_ctx* c, const float* W1, const float* b1, const float* W2, c
   return check(c);
 }
 
+int pmr_set_halo_nets(pmr_ctx* c, const float* nnp, const float* nnm) {
+  if (!c || !nnp || !nnm) return PMR_E_INVALID;
+  if (c->cfg.halo_model != PMR_HALO_TWO) return PMR_E_STATE;
+  launch_halo2_prepare(nnp, nnm, c->halo2_w, c->stream);
+  c->have_mlp = 1;
+  return check(c);
+}
+
 int pmr_set_target(pmr_ctx* c, const float* target) {
   if (!c || !target) return PMR_E_INVALID;
   HIPC(c, hipMemcpyAsync(c->target, target, c->B * c->no3 * sizeof(float), hipMemcpyDeviceToDevice,
@@ -732,18 +751,22 @@ int pmr_set_noise_table(pmr_ctx* c, int n_nodes, const double* log_mass, const d
 
 int pmr_set_loss(pmr_ctx* c, const pmr_loss_params* prm) {
   if (!c || !prm) return PMR_E_INVALID;
-  std::vector<double> h(6 * (size_t)c->B);
+  std::vector<double> h(NPRM * (size_t)c->B);
   for (int b = 0; b < c->B; ++b) {
     const pmr_loss_params& q = prm[b];
     if (!(q.sigma_N > 0) || !(q.M0 > 0 || c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) ||
         !(q.R_mass >= 0) || !(q.R_sm >= 0) || !std::isfinite(q.mu) || !std::isfinite(q.prior_weight))
       return PMR_E_INVALID;
-    h[6 * b + 0] = q.M0;
-    h[6 * b + 1] = q.mu;
-    h[6 * b + 2] = q.sigma_N;
-    h[6 * b + 3] = q.R_mass;
-    h[6 * b + 4] = q.R_sm;
-    h[6 * b + 5] = q.prior_weight;
+    if (c->cfg.halo_model == PMR_HALO_TWO && !(q.logistic_a > 0 && std::isfinite(q.logistic_a)))
+      return PMR_E_INVALID;
+    double* d = h.data() + NPRM * (size_t)b;
+    d[0] = q.M0;
+    d[1] = q.mu;
+    d[2] = q.sigma_N;
+    d[3] = q.R_mass;
+    d[4] = q.R_sm;
+    d[5] = q.prior_weight;
+    d[6] = q.logistic_a;
   }
   // pageable source: the copy completes before this call returns
   HIPC(c, hipMemcpyAsync(c->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -814,12 +837,18 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     a.out_item_stride = 3 * co;
     launch_xpass(XOP_GAUSS2, a, s);
     c2r_yz(c, c->no, 2, c->cB, 3 * co, co, c->dR, no3, (size_t)B * no3, nullptr);
-    const int rc = c->cfg.precision == PMR_MIXED
-                       ? launch_mlp_fwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
-                                             (size_t)B * no3, c->mlp_w, c->mass, s)
-                       : launch_mlp_fwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
-                                        (size_t)B * no3, c->mlp_w, c->mass, s);
-    if (rc != 0) return PMR_E_SHAPE;
+    if (c->cfg.halo_model == PMR_HALO_TWO) {
+      ProfScope ps(c, PMR_PROF_HALO2, 2.0 * HALO2_FWD_FMA * B * no3);
+      launch_halo2_fwd(c->delta_f, c->dR, c->dR + (size_t)B * no3, c->log_no, (size_t)B * no3,
+                       c->halo2_w, c->params, c->mass, s);
+    } else {
+      const int rc = c->cfg.precision == PMR_MIXED
+                         ? launch_mlp_fwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
+                                               (size_t)B * no3, c->mlp_w, c->mass, s)
+                         : launch_mlp_fwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
+                                          (size_t)B * no3, c->mlp_w, c->mass, s);
+      if (rc != 0) return PMR_E_SHAPE;
+    }
     smooth(c, c->no, c->mass, 3, c->MR, nullptr);
     launch_residual(c->MR, c->xd, no3, B, c->params, c->noise_k ? c->noise_mu : nullptr,
                     c->noise_k ? c->noise_w : nullptr, c->r, s);
@@ -851,7 +880,16 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     launch_mrbar(o0, c->MR, no3, B, c->params, c->noise_k ? c->noise_w : nullptr, o1,
                  s);  // MRbar
     smooth(c, c->no, o1, 3, o2, mass_bar);                   // Mbar (+ mass_bar)
-    if (c->cfg.precision == PMR_MIXED)
+    if (c->cfg.halo_model == PMR_HALO_TWO) {
+      {
+        ProfScope ps(c, PMR_PROF_HALO2, 2.0 * HALO2_BWD_FMA * B * no3);
+        launch_halo2_bwd(c->delta_f, c->dR, c->dR + (size_t)B * no3, c->log_no, (size_t)B * no3,
+                         c->halo2_w, c->params, o2, c->u2, o0, o1, dbar_f, s);
+      }
+      // compulsory: u (81 floats) read, three adjoint fields read and written, per voxel
+      ProfScope ps(c, PMR_PROF_HALO2_STENCIL, (81.0 * 4 + 24.0) * B * no3);
+      launch_halo2_stencil_adj(c->u2, c->log_no, (size_t)B * no3, o0, o1, dbar_f, s);
+    } else if (c->cfg.precision == PMR_MIXED)
       launch_mlp_bwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,
                           c->mlp_w, o2, o0, o1, dbar_f, s);
     else

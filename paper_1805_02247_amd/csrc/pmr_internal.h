@@ -134,6 +134,10 @@ enum XOp : int {
   XOP_HESS_ADJ = 10,  // 3 in (same pair sets): fwd, sum k_a k_b / k^2 / n^3; caller's gradient +=
 };
 
+// Loss parameters per batch item in device memory (doubles):
+// M0, mu, sigma_N, R_mass, R_sm, prior_weight, logistic_a.
+constexpr int NPRM = 7;
+
 struct XPassArgs {
   int n;            // points per axis
   int batch;
@@ -145,7 +149,7 @@ struct XPassArgs {
   size_t aux_item_stride;                  // for proj_modes (standard layout, pitch n/2 + 1)
   double box;
   double R1, R2;       // feature scales (XOP_GAUSS2 / XOP_FEAT_ADJ)
-  const double* params;  // device loss params [B][6] (XOP_GAUSS reads R at param_index)
+  const double* params;  // device loss params [B][NPRM] (XOP_GAUSS reads R at param_index)
   int param_index;
   // gradient assembly (XOP_ZA_ADJ, XOP_HESS_ADJ)
   const float2* proj_modes;  // P s
@@ -220,6 +224,21 @@ void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch
 void launch_za_init(const float* psi, const float* psi2, int batch, int np, int log_np3,
                     double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
                     double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s);
+// Two-network halo model (halo2.hip). Prepared weight block of HALO2_WEIGHT_FLOATS floats.
+constexpr int HALO2_WEIGHT_FLOATS = 6228;
+void launch_halo2_prepare(const float* nnp, const float* nnm, float* w, hipStream_t s);
+void launch_halo2_fwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
+                      const float* w, const double* prm, float* mass, hipStream_t s);
+// Writes u, the position network's input adjoint [B][81][n^3], and the mass network's input
+// adjoint into (g0, g12, g2); launch_halo2_stencil_adj then adds the neighbourhood sums of u.
+void launch_halo2_bwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
+                      const float* w, const double* prm, const float* mbar, float* u, float* g0,
+                      float* g12, float* g2, hipStream_t s);
+void launch_halo2_stencil_adj(const float* u, int log_n, size_t total, float* g0, float* g12,
+                              float* g2, hipStream_t s);
+// FMAs per voxel of the two-network kernels (forward only; forward recomputed + adjoint)
+constexpr double HALO2_FWD_FMA = 81 * 50 + 50 * 30 + 30 + 3 * 20 + 20 * 10 + 10;
+constexpr double HALO2_BWD_FMA = HALO2_FWD_FMA + 30 * 50 + 50 * 81 + 10 * 20 + 20 * 3;
 // Second-order LPT pointwise kernels (phi: [B][6][np^3], pairs xx, yy, zz, xy, xz, yz).
 void launch_lpt2_source(const float* phi, int batch, int log_np3, float* S, size_t s_item_stride,
                         hipStream_t s);

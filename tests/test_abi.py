@@ -35,7 +35,8 @@ def test_status_strings():
     dict(n_part=24), dict(n_part=8), dict(n_mesh=64, n_part=16), dict(n_out=64),
     dict(batch=0), dict(n_steps=0), dict(mlp_hidden=12), dict(box=0.0), dict(a1=0.05),
     dict(ckpt_every=-1), dict(precision=7), dict(loss_kind=3), dict(ic_order=3),
-    dict(ic_order=-1), dict(n_part=512, n_mesh=512,
+    dict(ic_order=-1), dict(halo_model=2), dict(halo_model=1, loss_kind=0),
+    dict(halo_model=1, precision=1), dict(n_part=512, n_mesh=512,
                                                                      n_out=512, batch=32)])
 def test_invalid_configs_rejected(bad):
     cfg = api.Config(**{**dict(n_part=16, n_mesh=16, n_out=16), **bad})
@@ -67,6 +68,10 @@ def test_workspace_plan_and_checks():
     assert lpt2 - more == 15 * 4 * 32 ** 3
     assert api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
                                           ic_order=0)) == more
+    # the two-network model keeps its weights and the 81 position-network input adjoints
+    two = api.workspace_bytes(api.Config(batch=1, n_part=32, n_mesh=32, n_out=32, n_steps=10,
+                                         halo_model=1, mlp_hidden=12))
+    assert two > more + 81 * 4 * 32 ** 3
 
 
 def test_primitives_reject_bad_shapes_without_touching_memory():

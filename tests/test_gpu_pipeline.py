@@ -40,10 +40,13 @@ def _gpu_run(ocfg, inv, modes, w, targets, params, hidden=8, ckpt=0, precision=P
     n = ocfg.n_part
     cfg = P.Config(batch=B, n_part=n, n_mesh=ocfg.n_mesh, n_out=ocfg.n_out, n_steps=ocfg.n_steps,
                    mlp_hidden=hidden, box=ocfg.box, ckpt_every=ckpt, precision=precision,
-                   loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2, ic_order=ocfg.ic_order)
+                   loss_kind=ocfg.loss_kind, R1=ocfg.R1, R2=ocfg.R2, ic_order=ocfg.ic_order,
+                   halo_model=ocfg.halo_model)
     pm = P.PMContext(cfg, DEV)
     pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
-    if w is not None:
+    if w is not None and ocfg.halo_model == OM.HALO_TWO:
+        pm.set_halo_nets(w)
+    elif w is not None:
         pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
     pm.set_target(torch.from_numpy(np.stack(targets).astype(np.float32)).reshape(B, -1))
     pm.set_loss([P.LossParams(**{k: v for k, v in p.items() if k != "noise_table"})
@@ -314,4 +317,42 @@ def test_second_order_lpt_lognormal_with_checkpoints():
     prob = _problem(32, 32, 32, 100.0, 6, OM.LOSS_LOGNORMAL, 1, hidden=32, R_sm=(2.0,),
                     ic_order=2)
     res = _gpu_run(*prob, hidden=32, ckpt=2)
+    _compare(*prob, res, TOL_FP32)
+
+
+def _two_net_problem(n, nm, box, steps, B, R_sm, a, seed=1):
+    """Output mesh = force mesh (nm)."""
+    ocfg = OM.Config(box, n, nm, nm, steps, loss_kind=OM.LOSS_LOGNORMAL,
+                     halo_model=OM.HALO_TWO)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    nets = synth.halo_net_weights(3)
+    modes, targets, params = [], [], []
+    for b in range(B):
+        modes.append(OM.linear_modes(synth.white_noise(seed + 10 * b, n), box, power))
+        st = OM.linear_modes(synth.white_noise(seed + 10 * b + 5, n), box, power)
+        t = OM.forward(ocfg, st, inv, np.ones((nm,) * 3), OM.default_params(), nets)["mass"]
+        targets.append(t)
+        params.append(OM.default_params(M0=float(np.percentile(t, 60)), R_sm=R_sm[b], mu=0.1,
+                                        logistic_a=a[b]))
+    return ocfg, inv, modes, nets, targets, params
+
+
+def test_two_network_halo_model():
+    """The paper's position x mass networks (32^3, B = 2 with the anneal ends a = 1, R_sm = 2
+    and a = 3, R_sm = 0): mass field, loss and mode gradient against the oracle."""
+    require_gpu()
+    say("pipeline: two-network halo model 32^3, B=2")
+    prob = _two_net_problem(32, 32, 100.0, 4, 2, (2.0, 0.0), (1.0, 3.0))
+    res = _gpu_run(*prob)
+    _compare(*prob, res, TOL_FP32)
+
+
+def test_two_network_halo_model_on_the_force_mesh():
+    """Force and output meshes at twice the particle resolution (16^3 particles, 32^3
+    meshes), a = 2."""
+    require_gpu()
+    say("pipeline: two-network halo model 16^3 particles, 32^3 meshes")
+    prob = _two_net_problem(16, 32, 60.0, 3, 1, (1.0,), (2.0,), seed=6)
+    res = _gpu_run(*prob)
     _compare(*prob, res, TOL_FP32)
