@@ -100,6 +100,8 @@ struct pmr_ctx {
   float* mlp_w;
   float* halo2_w;  // prepared weights of the two-network model
   float* u2;       // its position network's input adjoint [B][81][no3]
+  float* h2aux;    // its position mask and mass-network output [2][B][no3]
+  uint32_t* h2sgn; // its position network's ReLU signs [B][no3][4]
   float* target;
   double* params;
   float* xd;
@@ -217,6 +219,8 @@ void plan(pmr_ctx* c, Plan& P) {
   const bool two = c->cfg.halo_model == PMR_HALO_TWO;
   c->halo2_w = P.take<float>(two ? HALO2_WEIGHT_FLOATS : 0);
   c->u2 = P.take<float>(two ? 81 * B * c->no3 : 0);
+  c->h2aux = P.take<float>(two ? 2 * B * c->no3 : 0);
+  c->h2sgn = P.take<uint32_t>(two ? 4 * B * c->no3 : 0);
   c->target = P.take<float>(B * c->no3);
   c->params = P.take<double>(B * NPRM);
   c->xd = P.take<float>(B * c->no3);
@@ -840,7 +844,7 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     if (c->cfg.halo_model == PMR_HALO_TWO) {
       ProfScope ps(c, PMR_PROF_HALO2, 2.0 * HALO2_FWD_FMA * B * no3);
       launch_halo2_fwd(c->delta_f, c->dR, c->dR + (size_t)B * no3, c->log_no, (size_t)B * no3,
-                       c->halo2_w, c->params, c->mass, s);
+                       c->halo2_w, c->params, c->h2aux, c->h2sgn, c->mass, s);
     } else {
       const int rc = c->cfg.precision == PMR_MIXED
                          ? launch_mlp_fwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
@@ -884,7 +888,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       {
         ProfScope ps(c, PMR_PROF_HALO2, 2.0 * HALO2_BWD_FMA * B * no3);
         launch_halo2_bwd(c->delta_f, c->dR, c->dR + (size_t)B * no3, c->log_no, (size_t)B * no3,
-                         c->halo2_w, c->params, o2, c->u2, o0, o1, dbar_f, s);
+                         c->halo2_w, c->params, o2, c->h2aux, c->h2sgn, c->u2, o0, o1, dbar_f,
+                         s);
       }
       // compulsory: u (81 floats) read, three adjoint fields read and written, per voxel
       ProfScope ps(c, PMR_PROF_HALO2_STENCIL, (81.0 * 4 + 24.0) * B * no3);

@@ -225,20 +225,24 @@ void launch_za_init(const float* psi, const float* psi2, int batch, int np, int 
                     double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
                     double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s);
 // Two-network halo model (halo2.hip). Prepared weight block of HALO2_WEIGHT_FLOATS floats.
-constexpr int HALO2_WEIGHT_FLOATS = 6228;
+constexpr int HALO2_WEIGHT_FLOATS = 448 + (4 * 21 + 2 * 16 + 4 * 8 + 6 * 16) * 64;
 void launch_halo2_prepare(const float* nnp, const float* nnm, float* w, hipStream_t s);
+// aux: [2][B][n^3] (pos, then m) and sgn: [B][n^3][4] ReLU signs, written by the forward
+// and read by the adjoint.
 void launch_halo2_fwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
-                      const float* w, const double* prm, float* mass, hipStream_t s);
+                      const float* w, const double* prm, float* aux, uint32_t* sgn, float* mass,
+                      hipStream_t s);
 // Writes u, the position network's input adjoint [B][81][n^3], and the mass network's input
 // adjoint into (g0, g12, g2); launch_halo2_stencil_adj then adds the neighbourhood sums of u.
 void launch_halo2_bwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
-                      const float* w, const double* prm, const float* mbar, float* u, float* g0,
-                      float* g12, float* g2, hipStream_t s);
+                      const float* w, const double* prm, const float* mbar, const float* aux,
+                      const uint32_t* sgn, float* u, float* g0, float* g12, float* g2,
+                      hipStream_t s);
 void launch_halo2_stencil_adj(const float* u, int log_n, size_t total, float* g0, float* g12,
                               float* g2, hipStream_t s);
-// FMAs per voxel of the two-network kernels (forward only; forward recomputed + adjoint)
+// FMAs per voxel of the two-network kernels (forward; adjoint from the stored signs)
 constexpr double HALO2_FWD_FMA = 81 * 50 + 50 * 30 + 30 + 3 * 20 + 20 * 10 + 10;
-constexpr double HALO2_BWD_FMA = HALO2_FWD_FMA + 30 * 50 + 50 * 81 + 10 * 20 + 20 * 3;
+constexpr double HALO2_BWD_FMA = 30 * 50 + 50 * 81 + 3 * 20 + 20 * 10 + 10 + 10 * 20 + 20 * 3;
 // Second-order LPT pointwise kernels (phi: [B][6][np^3], pairs xx, yy, zz, xy, xz, yz).
 void launch_lpt2_source(const float* phi, int batch, int log_np3, float* S, size_t s_item_stride,
                         hipStream_t s);
