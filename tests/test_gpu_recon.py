@@ -181,3 +181,48 @@ def test_gpu_anneal_stages_lognormal():
     pm2.set_loss(stages[1])
     _, loss = pm2.forward(m2, want_mass=False)
     assert float(loss[0, 0]) == out[1].losses[0]
+
+
+def test_gpu_anneal_stages_two_network_model():
+    """The paper's a-anneal on the two-network model (Sec. 5.2: logistic sharpness a = 1,
+    then 3, with R_sm = 2 then 0): each stage's losses never increase, the second stage
+    starts from the first stage's optimum, and the loss of the first stage's first point
+    matches the oracle's."""
+    require_gpu()
+    say("recon: a-anneal on the two-network model, 16^3")
+    n, box = 16, 100.0
+    ocfg = OM.Config(box, n, n, n, 3, loss_kind=OM.LOSS_LOGNORMAL, halo_model=OM.HALO_TWO)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    nets = synth.halo_net_weights(3)
+    s_true = OM.linear_modes(synth.white_noise(21, n), box, power)
+    target = OM.forward(ocfg, s_true, inv, np.ones((n, n, n)), OM.default_params(), nets)["mass"]
+    s0 = np.sqrt(0.1) * OM.linear_modes(synth.white_noise(22, n), box, power)
+    M0 = float(np.percentile(target, 60))
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, box=box,
+                   halo_model=P.PMR_HALO_TWO)
+
+    def context():
+        pm = P.PMContext(cfg, DEV)
+        pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+        pm.set_halo_nets(nets)
+        pm.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+        return pm
+
+    stages = [P.LossParams(M0=M0, R_sm=2.0, logistic_a=1.0),
+              P.LossParams(M0=M0, R_sm=0.0, logistic_a=3.0)]
+    pm = context()
+    modes = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+    out = R.reconstruct(pm, modes, stages, max_iter=4)
+    ref = OM.forward(ocfg, s0, inv, target, OM.default_params(M0=M0, R_sm=2.0, logistic_a=1.0),
+                     nets)["loss"]
+    assert abs(out[0].losses[0] - ref) <= 1e-4 * abs(ref), (out[0].losses[0], ref)
+    for st in out:
+        assert all(b <= a for a, b in zip(st.losses, st.losses[1:])), st.losses
+    pm2 = context()
+    pm2.set_loss(stages[0])
+    m2 = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+    R.minimize(pm2, m2, max_iter=4)
+    pm2.set_loss(stages[1])
+    _, loss = pm2.forward(m2, want_mass=False)
+    assert float(loss[0, 0]) == out[1].losses[0]
