@@ -46,6 +46,7 @@ enum {
   PMR_E_SHAPE = -2,     /* unsupported sizes */
   PMR_E_WORKSPACE = -3, /* workspace too small or misaligned (256 B) */
   PMR_E_HIP = -4,       /* HIP runtime or launch error (sticky) */
+  PMR_E_NONFINITE = -5, /* non-finite loss (only with pmr_set_check_finite on; not sticky) */
   PMR_E_STATE = -6      /* call out of order (adjoint before forward, missing inputs) */
 };
 
@@ -148,6 +149,12 @@ int pmr_set_noise_table(pmr_ctx* ctx, int n_nodes, const double* log_mass, const
  * (density-L2); nullable. loss_out: device double [B][3] = (total, prior, data).
  * Keeps what the adjoint needs in the workspace; invalidated by the next forward. */
 int pmr_forward(pmr_ctx* ctx, const void* modes, float* mass_out, double* loss_out);
+
+/* Optional check of the loss: with on != 0, pmr_forward synchronises the context stream at
+ * its end, reads the B x 3 loss values back and returns PMR_E_NONFINITE if any is NaN or
+ * infinite (its outputs are still written and pmr_adjoint may follow). Off by default; keep
+ * it off while a forward is being captured into a HIP graph (the check synchronises). */
+int pmr_set_check_finite(pmr_ctx* ctx, int on);
 
 /* Gradient of sum_b loss_bar[b] * loss[b] + <mass_bar, mass> with respect to the modes of
  * the preceding pmr_forward. loss_bar: device double [B]; mass_bar: device float

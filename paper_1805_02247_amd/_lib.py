@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libpmr.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
 
 PMR_OK = 0
+PMR_E_NONFINITE = -5
 PMR_FP32, PMR_MIXED = 0, 1
 PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
 PMR_HALO_SINGLE, PMR_HALO_TWO = 0, 1
@@ -38,7 +39,9 @@ class PmrLossParams(ctypes.Structure):
 
 
 class PmrError(RuntimeError):
-    pass
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 _lib = None
@@ -53,6 +56,7 @@ SIGNATURES = {
     "pmr_set_prior": (ci, [vp, vp]),
     "pmr_set_mlp": (ci, [vp, vp, vp, vp, vp, vp, vp]),
     "pmr_set_halo_nets": (ci, [vp, vp, vp]),
+    "pmr_set_check_finite": (ci, [vp, ci]),
     "pmr_set_target": (ci, [vp, vp]),
     "pmr_set_loss": (ci, [vp, ctypes.POINTER(PmrLossParams)]),
     "pmr_set_noise_table": (ci, [vp, ci, ctypes.POINTER(cd), ctypes.POINTER(cd),
@@ -105,5 +109,5 @@ def lib():
 def check(status):
     if status != PMR_OK:
         msg = lib().pmr_status_string(int(status)).decode()
-        raise PmrError(f"libpmr status {status}: {msg}")
+        raise PmrError(f"libpmr status {status}: {msg}", int(status))
     return status

@@ -123,6 +123,11 @@ class PMContext:
         L.check(L.lib().pmr_set_mlp(self._ctx, *[_ptr(t) for t in ts]))
         self._keep_mlp = ts
 
+    def set_check_finite(self, on=True):
+        """With on, forward() synchronises and raises PmrError (status PMR_E_NONFINITE) when
+        a loss value is NaN or infinite; the outputs are still written."""
+        L.check(L.lib().pmr_set_check_finite(self._ctx, int(bool(on))))
+
     def set_halo_nets(self, nets):
         """Weights of the two-network model: nets = {"nnp": {W1, b1, W2, b2, W3, b3},
         "nnm": {...}} with the shapes of pmr_set_halo_nets."""

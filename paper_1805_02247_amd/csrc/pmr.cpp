@@ -85,6 +85,7 @@ struct pmr_ctx {
   size_t ws_bytes;
   int status;       // sticky error
   int have_prior, have_mlp, have_target, have_loss, xd_dirty, fwd_done;
+  int check_finite;  // pmr_set_check_finite
   // sizes
   int B, np, nm, no, n, H, k;
   size_t np3, nm3, no3, cp, cm, co;  // standard half-spectrum sizes n * n * (n/2 + 1)
@@ -862,7 +863,21 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   }
   launch_finalize_loss(c->prior, c->data, c->params, B, loss_out, s);
   c->fwd_done = 1;
-  return check(c);
+  const int st = check(c);
+  if (st != PMR_OK || !c->check_finite) return st;
+  std::vector<double> h(3 * (size_t)B);
+  HIPC(c, hipMemcpyAsync(h.data(), loss_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(c, hipStreamSynchronize(s));
+  if (c->status != PMR_OK) return c->status;
+  for (double v : h)
+    if (!std::isfinite(v)) return PMR_E_NONFINITE;
+  return PMR_OK;
+}
+
+int pmr_set_check_finite(pmr_ctx* c, int on) {
+  if (!c) return PMR_E_INVALID;
+  c->check_finite = on != 0;
+  return PMR_OK;
 }
 
 int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void* grad) {
@@ -1062,6 +1077,7 @@ const char* pmr_status_string(int st) {
     case PMR_E_SHAPE: return "unsupported shape";
     case PMR_E_WORKSPACE: return "workspace too small or misaligned";
     case PMR_E_HIP: return "HIP runtime error";
+    case PMR_E_NONFINITE: return "non-finite loss";
     case PMR_E_STATE: return "call out of order or missing inputs";
     default: return "unknown status";
   }

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = L.lib()
-    for st in (0, -1, -2, -3, -4, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6):
         assert lib.pmr_status_string(st)
 
 

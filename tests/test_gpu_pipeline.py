@@ -390,3 +390,33 @@ def test_second_order_lpt_with_two_networks_64():
         assert torch.equal(grad, ref_grad), rep
         pm.forward(m, want_mass=False)
         pm.adjoint(ones)
+
+
+def test_non_finite_loss_check():
+    """pmr_set_check_finite: a data field with a NaN makes the loss NaN; with the check on the
+    forward reports PMR_E_NONFINITE (outputs still written, the adjoint may follow), with it
+    off the forward succeeds and returns the NaN loss."""
+    require_gpu()
+    say("pipeline: non-finite loss check")
+    prob = _problem(16, 16, 16, 60.0, 2, OM.LOSS_LOGNORMAL, 1)
+    ocfg, inv, modes, w, targets, params = prob
+    bad = targets[0].copy()
+    bad[3, 4, 5] = np.nan
+    cfg = P.Config(batch=1, n_part=16, n_mesh=16, n_out=16, n_steps=2, mlp_hidden=8, box=60.0)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+    pm.set_loss(P.LossParams(M0=params[0]["M0"], mu=params[0]["mu"]))
+    m = torch.from_numpy(modes[0].astype(np.complex64)).reshape(1, -1).to(DEV)
+    pm.set_target(torch.from_numpy(targets[0].astype(np.float32)).reshape(1, -1))
+    pm.set_check_finite(True)
+    _, loss = pm.forward(m)  # finite: no error
+    assert np.isfinite(loss.cpu().numpy()).all()
+    pm.set_target(torch.from_numpy(bad.astype(np.float32)).reshape(1, -1))
+    with pytest.raises(P.PmrError) as e:
+        pm.forward(m)
+    assert e.value.status == -5
+    pm.adjoint(torch.ones(1, dtype=torch.float64, device=DEV))
+    pm.set_check_finite(False)
+    _, loss = pm.forward(m)
+    assert np.isnan(loss.cpu().numpy()[0, 0])
