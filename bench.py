@@ -83,6 +83,9 @@ WORKLOADS = {
     # checkpoint every 2 steps.
     "cfg3_256": dict(batch=1, n_part=256, n_mesh=512, n_out=256, n_steps=10, mlp_hidden=64,
                      precision=1, ckpt_every=2, box=400.0, R_sm=[2.0]),
+    # Secondary shape of the 256^3 workload: the force mesh at the particle resolution.
+    "cfg3_256_mesh256": dict(batch=1, n_part=256, n_mesh=256, n_out=256, n_steps=10,
+                             mlp_hidden=64, precision=1, ckpt_every=2, box=400.0, R_sm=[2.0]),
     # 32 realisations at L = 200 Mpc/h, 64^3 on 64^3, 5 steps.
     "cfg4_64x32": dict(batch=32, n_part=64, n_mesh=64, n_out=64, n_steps=5, mlp_hidden=32,
                        precision=0, ckpt_every=0, box=200.0, R_sm=[0.0]),
@@ -225,6 +228,25 @@ def time_gradient(pm, modes, steps, warmup):
         pm.adjoint(ones, out=grad)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, grad
+
+
+def copy_bandwidth(dev, reps=5):
+    """Device-to-device copy rate of a 1 GiB buffer (bytes read + written per second, GB/s):
+    the bandwidth a streaming kernel can reach on this GPU, beside the 8 TB/s figure."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / t / 1e9
 
 
 def two_network_leg(w, dev, data, steps):
@@ -452,6 +474,9 @@ def main():
                        "avg_launch_us": avg_s * 1e6, "launches": ev_n,
                        "alg_bytes_per_launch": per_launch,
                        "share_of_step": ev_ms / (1e3 * T)}
+    copy = copy_bandwidth(dev)
+    out["roofline"]["copy_gbs_measured"] = copy
+    out["roofline"]["frac_of_copy"] = achieved / copy
     out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
     if not args.no_graph:
         G = P.GradientGraph(pm, modes)
