@@ -29,8 +29,12 @@ __device__ __forceinline__ int wavenumber(int i, int n) { return i <= n / 2 ? i 
 
 // ------------------------------------------------------------------ CIC helpers
 // Lower-corner index and fraction of one coordinate, FP64 (bit-identical rule everywhere):
-// u = x * scale, fl = floor(u), i0 = (int)fl mod n, f = u - fl.
+// u = x * scale, fl = floor(u), i0 = (int)fl mod n, f = u - fl, each operation rounded on
+// its own. Contraction is off here: fused into f = fma(x, scale, -fl) in some kernels and
+// not in others, the fraction of one position would differ in its last bits between the
+// kernel that first computes it and the one that recomputes it from the stored position.
 __device__ __forceinline__ int cic_corner(double x, double scale, int n, double* frac) {
+#pragma clang fp contract(off)
   double u = x * scale;
   double fl = floor(u);
   *frac = u - fl;
@@ -38,6 +42,7 @@ __device__ __forceinline__ int cic_corner(double x, double scale, int n, double*
 }
 
 __device__ __forceinline__ double wrap_box(double x, double box) {
+#pragma clang fp contract(off)
   return x - box * floor(x / box);
 }
 

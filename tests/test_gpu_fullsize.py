@@ -1,0 +1,114 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations bench.py times.
+
+* 128^3 particles on a 128^3 mesh, batch 4, 5 steps, FP32: batch item 0 (the benchmark's
+  oracle inputs) against the FP64 oracle gradient of the same item (about 12 s of oracle).
+* 256^3 particles on a 512^3 force mesh, 256^3 output, 10 steps: the oracle cannot finish
+  in seconds there, so properties that hold at any size are checked instead: the
+  checkpointed FP32 gradient equals the stored one bit for bit, the mixed-precision
+  (BF16 network) gradient stays within its bound of the FP32 one, total momentum is
+  conserved (the sum of all particle displacements vanishes), and the final density
+  contrast sums to zero (CIC conserves mass).
+"""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import paper_1805_02247_amd as P
+from paper_1805_02247_amd import cosmo
+from _gpu import DEV, cosine, rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _context(w, precision=None, ckpt=None):
+    """The benchmark's context for workload w (seeded modes, weights and data), with item 0
+    replaced by the oracle leg's inputs."""
+    w = dict(w)
+    if precision is not None:
+        w["precision"] = precision
+    if ckpt is not None:
+        w["ckpt_every"] = ckpt
+    pm, modes = bench.make_context(w, DEV)
+    inp = bench.oracle_inputs(w)
+    n, box = w["n_part"], w["box"]
+    power = cosmo.linear_power(0.8, 0.2)
+    modes[0] = torch.from_numpy(cosmo.modes_from_white_noise(inp["white"], box, power)
+                                ).reshape(-1).to(DEV)
+    target = pm.data[0].clone()
+    target[0] = torch.from_numpy(inp["target"].astype(np.float32)).reshape(-1).to(DEV)
+    pm.set_target(target)
+    prm = [P.LossParams(M0=inp["M0"], R_sm=inp["R_sm"])]
+    prm += [P.LossParams(M0=pm.data[1][b], R_sm=w["R_sm"][b % len(w["R_sm"])])
+            for b in range(1, w["batch"])]
+    pm.set_loss(prm)  # the network weights are the oracle leg's already (same seed)
+    return pm, modes
+
+
+def _gradient(pm, modes):
+    _, loss = pm.forward(modes, want_mass=False)
+    g = pm.adjoint(torch.ones(pm.cfg.batch, dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    return loss.cpu().numpy(), g
+
+
+def test_full_128_batch4_item0_against_oracle():
+    require_gpu()
+    w = bench.WORKLOADS["cfg2_128"]
+    say("full size: 128^3 B=4 FP32, item 0 vs the FP64 oracle")
+    pm, modes = _context(w)
+    loss, g = _gradient(pm, modes)
+    x = pm.debug("x", w["n_steps"]).cpu().numpy()[0]
+    g0 = g[0].cpu().numpy().astype(np.complex128)
+    del pm
+    torch.cuda.empty_cache()
+    _, (ref_loss, ref_g, ref_x) = bench.cpu_baseline(w)
+    err = bench.error_vs(ref_loss, ref_g, ref_x, float(loss[0, 0]), g0, x, box=w["box"],
+                         n_mesh=w["n_mesh"])
+    say("  " + ", ".join(f"{k}={v:.3e}" for k, v in err.items()))
+    assert err["loss_rel"] <= 1e-4
+    assert err["grad_cos"] >= 0.9999 and err["grad_rel_l2"] <= 1e-2
+    assert err["final_max_dx_cells"] <= 1e-3
+    assert err["final_cell_mismatch_frac"] <= 1e-4
+
+
+def test_full_256_on_512_properties():
+    require_gpu()
+    w = dict(bench.WORKLOADS["cfg3_256"])
+    n, box, nm = w["n_part"], w["box"], w["n_mesh"]
+    say("full size: 256^3 on 512^3, FP32 stored (no checkpoints)")
+    pm, modes = _context(w, precision=P.PMR_FP32, ckpt=0)
+    loss_s, g = _gradient(pm, modes)
+    g_stored = g.clone()
+    # momentum: sum over particles of the displacement x_n - x_0 (minimal image) vanishes
+    x0 = pm.debug("x", 0).cpu().numpy()[0]
+    xn = pm.debug("x", w["n_steps"]).cpu().numpy()[0]
+    d = (xn - x0 + box / 2) % box - box / 2
+    ratio = np.abs(d.sum(axis=1)) / np.abs(d).sum(axis=1)
+    dsum = pm.debug("delta_f").cpu().numpy().astype(np.float64)[0]
+    mass_ratio = abs(dsum.sum()) / np.abs(dsum).sum()
+    say(f"  momentum |sum d| / sum |d| = {ratio}, mass |sum delta| / sum |delta| = {mass_ratio:.2e}")
+    assert np.all(ratio <= 1e-5)
+    assert mass_ratio <= 1e-5
+    del pm, g
+    torch.cuda.empty_cache()
+
+    say("full size: 256^3 on 512^3, FP32 checkpoint every 2")
+    pm, modes = _context(w, precision=P.PMR_FP32, ckpt=2)
+    loss_c, g = _gradient(pm, modes)
+    assert np.array_equal(loss_c, loss_s)
+    assert torch.equal(g, g_stored)
+    del pm, g
+    torch.cuda.empty_cache()
+
+    say("full size: 256^3 on 512^3, mixed (BF16 network), checkpoint every 2")
+    pm, modes = _context(w, precision=P.PMR_MIXED, ckpt=2)
+    loss_m, g = _gradient(pm, modes)
+    gm = g.cpu().numpy()
+    gs = g_stored.cpu().numpy()
+    lr = abs(loss_m[0, 0] - loss_s[0, 0]) / abs(loss_s[0, 0])
+    say(f"  mixed vs FP32: loss {lr:.2e}, grad cos {cosine(gm, gs):.7f}, rel {rel_l2(gm, gs):.2e}")
+    assert lr <= 3e-3
+    assert cosine(gm, gs) >= 0.999 and rel_l2(gm, gs) <= 5e-2
+    del pm, g
+    torch.cuda.empty_cache()
