@@ -25,8 +25,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # published; counts the packed two-lane FP32 FM
 
 # Counter summaries (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a 1 GiB copy)
 # per workload, and the kernels each profiled class consists of.
-TRAFFIC_PROFILES = {"cfg2_128": "hbm_traffic_128cube_B4_fp32.txt",
-                    "cfg3_256": "hbm_traffic_256cube_512mesh.txt"}
+TRAFFIC_PROFILES = {"p128_m128_b4": "hbm_traffic_128cube_B4_fp32.txt",
+                    "p256_m512": "hbm_traffic_256cube_512mesh.txt"}
 CLASS_KERNELS = {
     "paint": r"paint_r2c_kernel<1,", "paint3": r"paint_r2c_kernel<3,",
     "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
@@ -77,17 +77,17 @@ def counter_traffic(workload, cls):
 WORKLOADS = {
     # L = 400 Mpc/h, 128^3 particles on a 128^3 mesh, 5 PM steps, 3-32-32-1 network, the
     # residual-smoothing anneal stages R_sm = 4, 2, 1, 0 Mpc/h as the 4 batch items.
-    "cfg2_128": dict(batch=4, n_part=128, n_mesh=128, n_out=128, n_steps=5, mlp_hidden=32,
+    "p128_m128_b4": dict(batch=4, n_part=128, n_mesh=128, n_out=128, n_steps=5, mlp_hidden=32,
                      precision=0, ckpt_every=0, box=400.0, R_sm=[4.0, 2.0, 1.0, 0.0]),
     # L = 400 Mpc/h, 256^3 particles, 512^3 force mesh, 256^3 output, 10 steps, 3-64-64-1,
     # checkpoint every 2 steps.
-    "cfg3_256": dict(batch=1, n_part=256, n_mesh=512, n_out=256, n_steps=10, mlp_hidden=64,
+    "p256_m512": dict(batch=1, n_part=256, n_mesh=512, n_out=256, n_steps=10, mlp_hidden=64,
                      precision=1, ckpt_every=2, box=400.0, R_sm=[2.0]),
     # Secondary shape of the 256^3 workload: the force mesh at the particle resolution.
-    "cfg3_256_mesh256": dict(batch=1, n_part=256, n_mesh=256, n_out=256, n_steps=10,
+    "p256_m256": dict(batch=1, n_part=256, n_mesh=256, n_out=256, n_steps=10,
                              mlp_hidden=64, precision=1, ckpt_every=2, box=400.0, R_sm=[2.0]),
     # 32 realisations at L = 200 Mpc/h, 64^3 on 64^3, 5 steps.
-    "cfg4_64x32": dict(batch=32, n_part=64, n_mesh=64, n_out=64, n_steps=5, mlp_hidden=32,
+    "p64_m64_b32": dict(batch=32, n_part=64, n_mesh=64, n_out=64, n_steps=5, mlp_hidden=32,
                        precision=0, ckpt_every=0, box=200.0, R_sm=[0.0]),
 }
 
@@ -279,7 +279,7 @@ def mixed_vs_fp32(dev, steps):
     inputs with the network on FP32 vector units): time per gradient, speedup, and the
     mixed path's error against the FP32 one at full size."""
     import torch
-    w = WORKLOADS["cfg3_256"]
+    w = WORKLOADS["p256_m512"]
     res = {}
     grads = {}
     data = None
@@ -297,7 +297,7 @@ def mixed_vs_fp32(dev, steps):
     del data
     res["speedup_mixed_over_fp32"] = res["fp32"]["ms_per_gradient"] / res["mixed"]["ms_per_gradient"]
     res["mixed_err_vs_fp32"] = error_vs(*grads["fp32"], *grads["mixed"])
-    res["workload"] = "cfg3_256"
+    res["workload"] = "p256_m512"
     return res
 
 
@@ -390,7 +390,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2_128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="p128_m128_b4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip timing the HIP-graph replay of a gradient evaluation")
@@ -492,7 +492,7 @@ def main():
                                "unit": "PM steps/s"}
         del G
     # mass-dependent noise: the same gradient with a 4-node table in log(M_R,data)
-    if args.workload == "cfg2_128":
+    if args.workload == "p128_m128_b4":
         t_plain, _ = time_gradient(pm, modes, max(2, args.steps // 2), 1)
         lm = np.log(np.percentile(pm.data[0].cpu().numpy(), [5, 35, 65, 95]))
         pm.set_noise_table(lm, [0.3, -0.1, 0.05, 0.2], [0.9, 0.35, 0.5, 0.7])
@@ -515,11 +515,11 @@ def main():
         out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev), box=w["box"],
                                            n_mesh=w["n_mesh"]),
                                   sample="batch item 0 inputs, full workload size")
-    if not args.no_256 and args.workload != "cfg3_256":
+    if not args.no_256 and args.workload != "p256_m512":
         del pm, modes, grad
         torch.cuda.empty_cache()
         out["at_256"] = mixed_vs_fp32(dev, max(2, min(args.steps, 10)))
-    if not args.no_recon and args.workload == "cfg2_128":
+    if not args.no_recon and args.workload == "p128_m128_b4":
         out["reconstruction"] = reconstruction_leg(dev)
     print(json.dumps(out), flush=True)
 

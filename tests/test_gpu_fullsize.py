@@ -54,7 +54,7 @@ def _gradient(pm, modes):
 
 def test_full_128_batch4_item0_against_oracle():
     require_gpu()
-    w = bench.WORKLOADS["cfg2_128"]
+    w = bench.WORKLOADS["p128_m128_b4"]
     say("full size: 128^3 B=4 FP32, item 0 vs the FP64 oracle")
     pm, modes = _context(w)
     loss, g = _gradient(pm, modes)
@@ -74,7 +74,7 @@ def test_full_128_batch4_item0_against_oracle():
 
 def test_full_256_on_512_properties():
     require_gpu()
-    w = dict(bench.WORKLOADS["cfg3_256"])
+    w = dict(bench.WORKLOADS["p256_m512"])
     n, box, nm = w["n_part"], w["box"], w["n_mesh"]
     say("full size: 256^3 on 512^3, FP32 stored (no checkpoints)")
     pm, modes = _context(w, precision=P.PMR_FP32, ckpt=0)
