@@ -218,14 +218,13 @@ __global__ __launch_bounds__(TB) void halo2_stencil_adj_kernel(const float* __re
   const size_t v = (size_t)blockIdx.x * TB + threadIdx.x;
   if (v >= total) return;
   const Vox p = vox(v, log_n);
-  const size_t n3 = (size_t)1 << (3 * log_n);
-  const float* ub = U + (v >> (3 * log_n)) * NF * n3;
   float s[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
-    const size_t q = nbr(p, log_n, 1 - o / 9, 1 - (o / 3) % 3, 1 - o % 3) - p.base;
+    const size_t q = nbr(p, log_n, 1 - o / 9, 1 - (o / 3) % 3, 1 - o % 3);
+    const float* uq = U + (q >> 4) * NF * 16 + (q & 15);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s[c] += ub[(size_t)(c * 27 + o) * n3 + q];
+    for (int c = 0; c < 3; ++c) s[c] += uq[(c * 27 + o) * 16];
   }
   g0[v] += s[0];
   g12[v] += s[1] + s[2];
@@ -339,7 +338,7 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_fwd_kernel(
 
 // Position network, adjoint: from Mbar (mbar), pos and m (aux, aux + total) and the stored
 // ReLU signs, u = W1^T ([a1 > 0] W2^T ([a2 > 0] W3 ybar)) with ybar = Mbar m a pos (1 - pos),
-// written per feature to U [B][81][n^3].
+// written to U [B n^3 / 16][81][16] (per 16-voxel group, feature-major: one 5 KB block).
 __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_bwd_kernel(
     int log_n, size_t groups, size_t total, const float* __restrict__ w,
     const double* __restrict__ prm, const float* __restrict__ mbar,
@@ -394,13 +393,13 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_bwd_kernel(
 #pragma unroll
       for (int mt = 0; mt < 6; ++mt)
         u[mt] = mx(f4g[(mt * 16 + kb) * 64 + l], a1b[kb >> 2][kb & 3], u[mt]);
-    float* uo = U + item * NF * n3 + (v & (n3 - 1));
+    float* uo = U + G * NF * 16 + n;  // [group][feature][16]: one 5 KB block per group
 #pragma unroll
     for (int mt = 0; mt < 6; ++mt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int f = 16 * mt + 4 * g + i;
-        if (f < NF) uo[(size_t)f * n3] = u[mt][i];
+        if (f < NF) uo[f * 16] = u[mt][i];
       }
   }
 }

@@ -100,7 +100,7 @@ struct pmr_ctx {
   float* inv_var;
   float* mlp_w;
   float* halo2_w;  // prepared weights of the two-network model
-  float* u2;       // its position network's input adjoint [B][81][no3]
+  float* u2;       // its position network's input adjoint [B no3 / 16][81][16]
   float* h2aux;    // its position mask and mass-network output [2][B][no3]
   uint32_t* h2sgn; // its position network's ReLU signs [B][no3][4]
   float* target;

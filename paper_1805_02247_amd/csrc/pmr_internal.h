@@ -237,8 +237,9 @@ void launch_halo2_prepare(const float* nnp, const float* nnm, float* w, hipStrea
 void launch_halo2_fwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
                       const float* w, const double* prm, float* aux, uint32_t* sgn, float* mass,
                       hipStream_t s);
-// Writes u, the position network's input adjoint [B][81][n^3], and the mass network's input
-// adjoint into (g0, g12, g2); launch_halo2_stencil_adj then adds the neighbourhood sums of u.
+// Writes u, the position network's input adjoint [B n^3 / 16][81][16] (16-voxel groups),
+// and the mass network's input adjoint into (g0, g12, g2); launch_halo2_stencil_adj then
+// adds the neighbourhood sums of u.
 void launch_halo2_bwd(const float* d0, const float* d1, const float* d2, int log_n, size_t total,
                       const float* w, const double* prm, const float* mbar, const float* aux,
                       const uint32_t* sgn, float* u, float* g0, float* g12, float* g2,
