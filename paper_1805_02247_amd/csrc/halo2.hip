@@ -351,7 +351,6 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_bwd_kernel(
   const float* f3 = sf;
   const float* f4 = sf + (H2::F4 - H2::F3);
   const int l = threadIdx.x & 63, g = l >> 4, n = l & 15;
-  const size_t n3 = (size_t)1 << (3 * log_n);
   const size_t stride = (size_t)gridDim.x * MX_WAVES;
   for (size_t G = (size_t)xcd_block(blockIdx.x, gridDim.x) * MX_WAVES + (threadIdx.x >> 6);
        G < groups; G += stride) {

@@ -625,7 +625,6 @@ void pm_run(pmr_ctx* c, int i0, int i1, bool take_ckpt) {
   }
 }
 
-int final_xslot(pmr_ctx* c) { return c->k == 0 ? c->n : ((c->n - 1) % c->k) + 1; }
 
 // x_data = log(G_Rmass * M_target + M0), enqueued as soon as both target and loss
 // parameters are known, so that captured forward passes never depend on host state.
@@ -819,7 +818,6 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   pm_run(c, 0, c->n, true);
   // H8: final paint on the output mesh
   const int total = (int)(B * c->np3);
-  double* xn = xslot(c, final_xslot(c));
   launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, c->frac_id,
               c->frac_o, s);
   launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
