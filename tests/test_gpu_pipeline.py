@@ -420,3 +420,35 @@ def test_non_finite_loss_check():
     pm.set_check_finite(False)
     _, loss = pm.forward(m)
     assert np.isnan(loss.cpu().numpy()[0, 0])
+
+
+def test_two_network_smallest_mesh_odd_batch():
+    """The two-network model on the smallest mesh (16^3, one 16-voxel group per row) with an
+    odd batch of 3 items, each with its own logistic sharpness."""
+    require_gpu()
+    say("pipeline: two-network model 16^3, B=3")
+    ocfg, inv, modes, nets, targets, params = _two_net_problem(16, 16, 50.0, 3, 3,
+                                                                (0.0, 1.0, 2.0), (1.0, 2.0, 3.0))
+    res = _gpu_run(ocfg, inv, modes, nets, targets, params)
+    _compare(ocfg, inv, modes, nets, targets, params, res, TOL_FP32)
+
+
+def test_two_network_state_and_argument_errors():
+    """Weights of the other halo model are refused (PMR_E_STATE), as is a non-positive
+    logistic sharpness for the two-network model (PMR_E_INVALID)."""
+    require_gpu()
+    nets = synth.halo_net_weights(3)
+    single = P.PMContext(P.Config(batch=1, n_part=16, n_mesh=16, n_out=16, n_steps=1,
+                                  mlp_hidden=8), DEV)
+    with pytest.raises(P.PmrError) as e:
+        single.set_halo_nets(nets)
+    assert e.value.status == -6
+    two = P.PMContext(P.Config(batch=1, n_part=16, n_mesh=16, n_out=16, n_steps=1,
+                               halo_model=P.PMR_HALO_TWO), DEV)
+    with pytest.raises(P.PmrError) as e:
+        two.set_mlp({k: torch.from_numpy(v) for k, v in synth.mlp_weights(3, 32).items()})
+    assert e.value.status == -6
+    with pytest.raises(P.PmrError) as e:
+        two.set_loss(P.LossParams(logistic_a=0.0))
+    assert e.value.status == -1
+    two.set_loss(P.LossParams(logistic_a=1.5))
