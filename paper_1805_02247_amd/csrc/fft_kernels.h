@@ -694,7 +694,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   const int n_out = xpass_outputs<OP>();
 
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
-  TileRegs<N, PC, NTH, V> pre;  // first input of the current tile (prefetched)
+  TileRegs<N, PC, NTH, V> pre;  // the next input to transform (prefetched)
   {
     const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
     const int kz0 = ch * PC;
@@ -715,15 +715,14 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
     float Rg = 0.f;
     if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * NPRM + a.param_index];
 
-    // -------- inputs
+    // -------- inputs (each prefetched into registers while the previous one is transformed:
+    // the next input of this tile, after the last input the first input of the next tile)
     for (int i = 0; i < n_in; ++i) {
-      if (i == 0) {
-        regs_to_lds<N, PC, NTH, V>(pre, lds);
-      } else {
-        load_tile<N, PC, NTH, V>(lds, a.in[i] + ioff, istride, ncols);
-      }
+      regs_to_lds<N, PC, NTH, V>(pre, lds);
       __syncthreads();
-      if (i == 0 && next < ntiles) {
+      if (i + 1 < n_in) {
+        load_regs<N, PC, NTH, V>(pre, a.in[i + 1] + ioff, istride, ncols);
+      } else if (next < ntiles) {
         const int nch = next % NCH, niy = (next / NCH) % N, nit = next / (NCH * N);
         const int nkz0 = nch * PC;
         load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
