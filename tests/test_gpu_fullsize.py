@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import bench
+import synth
 import paper_1805_02247_amd as P
 from paper_1805_02247_amd import cosmo
 from _gpu import DEV, cosine, rel_l2, require_gpu, say
@@ -112,3 +113,40 @@ def test_full_256_on_512_properties():
     assert cosine(gm, gs) >= 0.999 and rel_l2(gm, gs) <= 5e-2
     del pm, g
     torch.cuda.empty_cache()
+
+
+def test_full_128_paper_model_item0_against_oracle():
+    """The paper's model choices at the benchmark's size (128^3 x 4, FP32): second-order LPT
+    initial conditions and the two-network halo model; batch item 0 (the oracle leg's modes
+    and data, R_sm = 4, logistic sharpness a = 2) against the FP64 oracle (~40 s)."""
+    from oracle import cosmology as OC
+    from oracle import model as OM
+    require_gpu()
+    w = dict(bench.WORKLOADS["p128_m128_b4"], halo_model=P.PMR_HALO_TWO, ic_order=2)
+    say("full size: 128^3 B=4 FP32, 2LPT + two-network model, item 0 vs the FP64 oracle")
+    pm, modes = _context(w)
+    inp = bench.oracle_inputs(w)
+    prm = [P.LossParams(M0=inp["M0"], R_sm=inp["R_sm"], logistic_a=2.0)]
+    prm += [P.LossParams(M0=pm.data[1][b], R_sm=w["R_sm"][b % len(w["R_sm"])], logistic_a=3.0)
+            for b in range(1, w["batch"])]
+    pm.set_loss(prm)
+    loss, g = _gradient(pm, modes)
+    x = pm.debug("x", w["n_steps"]).cpu().numpy()[0]
+    g0 = g[0].cpu().numpy().astype(np.complex128)
+    del pm
+    torch.cuda.empty_cache()
+    n, box = w["n_part"], w["box"]
+    ocfg = OM.Config(box, n, w["n_mesh"], w["n_out"], w["n_steps"], ic_order=2,
+                     halo_model=OM.HALO_TWO)
+    power = OC.bbks_power()
+    s = OM.linear_modes(inp["white"], box, power)
+    fwd, G = OM.gradient(ocfg, s, OM.prior_inv_variance(n, box, power), inp["target"],
+                         OM.default_params(M0=inp["M0"], R_sm=inp["R_sm"], logistic_a=2.0),
+                         synth.halo_net_weights(3))
+    err = bench.error_vs(fwd["loss"], G, fwd["xs"][-1], float(loss[0, 0]), g0, x, box=box,
+                         n_mesh=w["n_mesh"])
+    say("  " + ", ".join(f"{k}={v:.3e}" for k, v in err.items()))
+    assert err["loss_rel"] <= 1e-4
+    assert err["grad_cos"] >= 0.9999 and err["grad_rel_l2"] <= 1e-2
+    assert err["final_max_dx_cells"] <= 1e-3
+    assert err["final_cell_mismatch_frac"] <= 1e-4
