@@ -259,8 +259,10 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_fwd_kernel(
     float* __restrict__ aux, uint32_t* __restrict__ sgn) {
   constexpr int NFRAG = H2::F3 - H2::F1;
   __shared__ __attribute__((aligned(16))) float sf[NFRAG];
+  __shared__ float sv[H2::M1];  // b1, b2, W3, b3: read per lane group, kept close
   for (int i = threadIdx.x; i < NFRAG / 4; i += 64 * MX_WAVES)
     reinterpret_cast<float4*>(sf)[i] = reinterpret_cast<const float4*>(w + H2::F1)[i];
+  for (int i = threadIdx.x; i < H2::M1; i += 64 * MX_WAVES) sv[i] = w[i];
   __syncthreads();
   const float* f1 = sf;
   const float* f2 = sf + (H2::F2 - H2::F1);
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_fwd_kernel(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = 16 * mt + 4 * g + i;
-        const float t = m < NP1 ? h1[mt][i] + w[H2::B1 + m] : 0.f;
+        const float t = m < NP1 ? h1[mt][i] + sv[H2::B1 + m] : 0.f;
         if (t > 0.f) bits |= 1u << (4 * mt + i);
         h1[mt][i] = fmaxf(t, 0.f);
       }
@@ -322,14 +324,14 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_fwd_kernel(
       for (int i = 0; i < 4; ++i) {
         const int m = 16 * mt + 4 * g + i;
         if (m < NP2) {
-          const float t = a2[mt][i] + w[H2::B2 + m];
+          const float t = a2[mt][i] + sv[H2::B2 + m];
           if (t > 0.f) bits |= 1u << (16 + 4 * mt + i);
-          ys = fmaf(w[H2::W3 + m], fmaxf(t, 0.f), ys);
+          ys = fmaf(sv[H2::W3 + m], fmaxf(t, 0.f), ys);
         }
       }
     ys += __shfl_xor(ys, 16, 64);
     ys += __shfl_xor(ys, 32, 64);
-    const float y = ys + w[H2::B3];
+    const float y = ys + sv[H2::B3];
     const float a = (float)prm[item * NPRM + 6];
     if (g == 0) aux[v] = 1.f / (1.f + expf(-a * y));
     sgn[v * 4 + g] = bits;
@@ -345,8 +347,10 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_bwd_kernel(
     const float* __restrict__ aux, const uint32_t* __restrict__ sgn, float* __restrict__ U) {
   constexpr int NFRAG = H2::SIZE - H2::F3;
   __shared__ __attribute__((aligned(16))) float sf[NFRAG];
+  __shared__ float sw3[32];  // W3, read per lane group
   for (int i = threadIdx.x; i < NFRAG / 4; i += 64 * MX_WAVES)
     reinterpret_cast<float4*>(sf)[i] = reinterpret_cast<const float4*>(w + H2::F3)[i];
+  if (threadIdx.x < 32) sw3[threadIdx.x] = w[H2::W3 + threadIdx.x];
   __syncthreads();
   const float* f3 = sf;
   const float* f4 = sf + (H2::F4 - H2::F3);
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(64 * MX_WAVES) void halo2_mx_bwd_kernel(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = 16 * mt + 4 * g + i;
-        a2b[mt][i] = (m < NP2 && ((bits >> (16 + 4 * mt + i)) & 1)) ? w[H2::W3 + m] * yb : 0.f;
+        a2b[mt][i] = (m < NP2 && ((bits >> (16 + 4 * mt + i)) & 1)) ? sw3[m] * yb : 0.f;
       }
     floatx4_t a1b[4];
 #pragma unroll
