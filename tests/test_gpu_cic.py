@@ -84,3 +84,54 @@ def test_paint_empty_rows_and_single_particle():
     ref = M.cic_paint(x[0], nm, box, np.ones(npart ** 3))
     np.testing.assert_allclose(d, ref, rtol=1e-6)
     assert np.count_nonzero(d) == 8
+
+
+@pytest.mark.parametrize("layout", ["one_cell", "lattice"])
+def test_degenerate_layouts_at_full_size(layout):
+    """The two extremes of cell occupancy at 128^3 particles on a 128^3 mesh, batch 4 (the
+    benchmark's launch size), cell size 1 so that the CIC weights are exact dyadics:
+    * one_cell: all 2^21 particles of item b in one cell (a different cell per item, with
+      fractions 1/4, 1/2, 3/4): every key of an item is equal, so the stable sort keeps the
+      ids in order, one row holds the whole item, and the paint puts N * w_corner into 8
+      cells (sums of equal dyadic terms: exact in FP32);
+    * lattice: one particle on every node: every key is distinct, each row holds 128
+      particles, and the density contrast is 0 everywhere."""
+    require_gpu()
+    B, npart, nm = 4, 128, 128
+    box = float(nm)
+    P = npart ** 3
+    say(f"degenerate layout {layout}: B={B} np={npart} nm={nm}")
+    if layout == "one_cell":
+        cells = [(5, 7, 100), (127, 0, 3), (64, 64, 127), (0, 127, 0)]
+        frac = (0.25, 0.5, 0.75)
+        x = np.empty((B, 3, P))
+        for b, c in enumerate(cells):
+            for a in range(3):
+                x[b, a] = c[a] + frac[a]
+    else:
+        q = np.arange(P)
+        lat = np.stack([q // (npart * npart), (q // npart) % npart, q % npart]).astype(np.float64)
+        x = np.broadcast_to(lat, (B, 3, P)).copy()
+    xt = torch.from_numpy(x).to(DEV)
+    keys, ids, rows = api.cic_sort(xt, nm, box)
+    k_ref, o_ref = _oracle_order(x, nm, box)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint32), k_ref.astype(np.uint32))
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), o_ref.astype(np.uint32))
+    row_ref = np.searchsorted(k_ref // nm, np.arange(B * nm * nm + 1), side="left")
+    assert np.array_equal(rows.cpu().numpy().view(np.uint32), row_ref.astype(np.uint32))
+    if layout == "one_cell":
+        # stable: equal keys keep id order
+        assert np.array_equal(o_ref, np.arange(B * P))
+    d = api.cic_paint(xt, keys, ids, rows, nm, box, 1.0, 0.0).cpu().numpy()
+    want = np.zeros((B, nm, nm, nm), dtype=np.float64)
+    if layout == "one_cell":
+        for b, c in enumerate(cells):
+            for ox in (0, 1):
+                for oy in (0, 1):
+                    for oz in (0, 1):
+                        w = ((frac[0] if ox else 1 - frac[0]) * (frac[1] if oy else 1 - frac[1])
+                             * (frac[2] if oz else 1 - frac[2]))
+                        want[b, (c[0] + ox) % nm, (c[1] + oy) % nm, (c[2] + oz) % nm] = P * w
+    else:
+        want[:] = 1.0
+    assert np.array_equal(d.astype(np.float64), want.reshape(B, -1))
