@@ -55,6 +55,24 @@ def test_perfect_lattice_feels_no_force():
     assert np.abs(F).max() < 1e-13
 
 
+def test_zero_modes_keep_the_lattice_exactly():
+    """An empty linear field through the whole forward model: with L = 32 on an 16^3
+    lattice and mesh every CIC fraction is exactly 1/2, so the density is exactly uniform,
+    the force exactly zero, and every position stays on its lattice site bit for bit."""
+    n = 16
+    cfg = OM.Config(32.0, n, n, n, 3, loss_kind=OM.LOSS_LOGNORMAL)
+    P = C.bbks_power()
+    inv = OM.prior_inv_variance(n, 32.0, P)
+    s = np.zeros_like(OM.linear_modes(synth.white_noise(3, n), 32.0, P))
+    out = OM.forward(cfg, s, inv, np.ones((n,) * 3), OM.default_params(), synth.mlp_weights(3, 8))
+    q = M.lattice_positions(n, 32.0, n)
+    for x in out["xs"]:
+        assert np.array_equal(x, q)
+    assert np.all(out["delta_f"] == 0.0) and out["loss_prior"] == 0.0
+    # the network then sees zero features everywhere: one mass value for every voxel
+    assert np.all(out["mass"] == out["mass"].ravel()[0])
+
+
 def test_total_momentum_is_conserved():
     """CIC both ways with an odd force kernel: sum_p F(x_p) = rho^T A rho = 0."""
     n, box = 16, 50.0
