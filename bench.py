@@ -32,6 +32,7 @@ CLASS_KERNELS = {
     "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
     "ypass": r"ypass(_reg)?_kernel<", "zpass": r"zpass_", "kick_drift": r"kick_drift_kernel",
     "adj_gather": r"adjoint_positions_kernel", "adj_update": r"adjoint_update_kernel",
+    "sort_scatter": r"radix_scatter_kernel<",
 }
 
 
@@ -498,13 +499,14 @@ def main():
     torch.cuda.synchronize()
     # the kernel class with the largest event time in one untimed gradient evaluation
     classes = ["paint", "paint3", "xpass_force", "xpass_force_adj", "ypass", "zpass",
-               "kick_drift", "adj_gather", "adj_update"]
+               "kick_drift", "adj_gather", "adj_update", "sort_scatter"]
     probe = {}
     for cls in classes:
         pm.profile_begin(cls)
         step()
         probe[cls] = pm.profile_end()
-    dominant = max(classes, key=lambda c: probe[c][0])
+    ranked = sorted(classes, key=lambda c: probe[c][0], reverse=True)
+    dominant = ranked[0]
     # timed region, with the dominant class bracketed by HIP events on the library's stream
     pm.profile_begin(dominant, max_launches=64 * (args.steps + 1))
     torch.cuda.synchronize()
@@ -545,6 +547,19 @@ def main():
     copy = copy_bandwidth(dev)
     out["roofline"]["copy_gbs_measured"] = copy
     out["roofline"]["frac_of_copy"] = achieved / copy
+    # the runner-up class, from its own untimed gradient evaluation
+    nxt = ranked[1]
+    pm.profile_begin(nxt, max_launches=256)
+    step()
+    n_ms, n_n, n_bytes = pm.profile_end()
+    n_avg = n_ms * 1e-3 / max(n_n, 1)
+    n_ach = n_bytes / max(n_n, 1) / n_avg / 1e9
+    out["roofline_next"] = {"bound": "hbm", "kernel": nxt, "achieved": n_ach,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": n_ach / HBM_PEAK_GBS,
+                            "traffic": counter_traffic(args.workload, nxt),
+                            "avg_launch_us": n_avg * 1e6, "launches": n_n,
+                            "alg_bytes_per_launch": n_bytes / max(n_n, 1),
+                            "frac_of_copy": n_ach / copy}
     out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
     if not args.no_graph:
         G = P.GradientGraph(pm, modes)

@@ -217,8 +217,10 @@ enum {
   PMR_PROF_ADJ_UPDATE = 9,        /* step-adjoint kick / drift transposes (id order) */
   PMR_PROF_HALO2 = 10,            /* two-network model kernels (forward, adjoint); their
                                      algorithmic figure is FLOPs, not bytes */
-  PMR_PROF_HALO2_STENCIL = 11     /* two-network model: neighbourhood sum of the position
+  PMR_PROF_HALO2_STENCIL = 11,    /* two-network model: neighbourhood sum of the position
                                      network's input adjoint */
+  PMR_PROF_SORT_SCATTER = 12      /* scatter passes of the cell-key radix sort (each pass
+                                     timed alone, without its histogram and scan) */
 };
 int pmr_profile_begin(pmr_ctx* ctx, int kernel_class, int max_launches);
 int pmr_profile_end(pmr_ctx* ctx, double* total_ms, long long* launches, double* alg_bytes);

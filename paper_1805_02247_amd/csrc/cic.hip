@@ -604,19 +604,27 @@ size_t sort_scratch_bytes(int n, int key_bits) {
 template <int D>
 static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
                       int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* dtot,
-                      const Vec3* pin, Vec3* pout, uint32_t* inv, hipStream_t s) {
+                      const Vec3* pin, Vec3* pout, uint32_t* inv, hipStream_t s,
+                      const ScatterProbe* probe) {
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
   radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
   digit_scan_kernel<<<1 << D, TB, 0, s>>>(hist, nb, offs, dtot);
+  if (probe) {
+    // keys (and ids, unless the identity) in, keys and ids out, the payload gathered and
+    // written, the inverse permutation written
+    const double per = (iin ? 16.0 : 12.0) + (pout ? 24.0 : 0.0) + (inv ? 4.0 : 0.0);
+    probe->before(probe->arg, per * n);
+  }
   radix_scatter_kernel<D><<<nb, SORT_TB, 0, s>>>(kin, iin, n, shift, offs, dtot, kout, iout, pin,
                                                   pout, inv);
+  if (probe) probe->after(probe->arg);
 }
 
 // Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
 // and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
 void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
                  uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
-                 hipStream_t s, uint32_t* inv) {
+                 hipStream_t s, uint32_t* inv, const ScatterProbe* probe) {
   const int passes = (key_bits + 8) / 9;
   const int D = (key_bits + passes - 1) / passes;
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
@@ -640,7 +648,7 @@ void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
 #define CASE(DD) \
   case DD:                                                                                  \
     sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, dtot, last ? pay_in : nullptr,      \
-                  last ? pay_out : nullptr, last ? inv : nullptr, s);                          \
+                  last ? pay_out : nullptr, last ? inv : nullptr, s, probe);                   \
     break;
       CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 #undef CASE

@@ -159,6 +159,7 @@ struct pmr_ctx {
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used;
   double prof_bytes;
+  bool prof_open;  // a scatter-probe event pair is open
 };
 
 namespace {
@@ -365,6 +366,33 @@ struct ProfScope {
   }
 };
 
+// Event timing of the sort's scatter launches alone (PMR_PROF_SORT_SCATTER).
+void scatter_probe_before(void* arg, double bytes) {
+  pmr_ctx* c = (pmr_ctx*)arg;
+  if (c->prof_class == PMR_PROF_SORT_SCATTER && c->prof_used + 2 <= c->prof_ev.size()) {
+    HIPC(c, hipEventRecord(c->prof_ev[c->prof_used], c->stream));
+    c->prof_bytes += bytes;
+    c->prof_open = true;
+  }
+}
+void scatter_probe_after(void* arg) {
+  pmr_ctx* c = (pmr_ctx*)arg;
+  if (c->prof_open) {
+    HIPC(c, hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream));
+    c->prof_used += 2;
+    c->prof_open = false;
+  }
+}
+// The probe of context c for one launch_sort call (a temporary: it lives for that call).
+struct ScatterProbeOf {
+  ScatterProbe p;
+  bool on;
+  explicit ScatterProbeOf(pmr_ctx* c)
+      : p{scatter_probe_before, scatter_probe_after, c},
+        on(c->prof_class == PMR_PROF_SORT_SCATTER) {}
+  const ScatterProbe* get() const { return on ? &p : nullptr; }
+};
+
 // ---------------------------------------------------------------- pass helpers
 FieldMap fmap(int fpi, size_t item_stride, size_t comp_stride, size_t pitch = 0) {
   FieldMap m;
@@ -567,7 +595,8 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
   double* x = xslot(c, xsl);
   double* xn = xslot(c, xsl + 1);
   launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
-              c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl));
+              c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl),
+              ScatterProbeOf(c).get());
   launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
                    c->stream);
   const size_t cm = c->sm;
@@ -819,7 +848,7 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   // H8: final paint on the output mesh
   const int total = (int)(B * c->np3);
   launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, c->frac_id,
-              c->frac_o, s);
+              c->frac_o, s, nullptr, ScatterProbeOf(c).get());
   launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
   launch_paint_mass(c->keys_sorted, c->frac_o, c->rows_o, B, c->no, c->mass_o, 1.f, c->delta_f, s);
   // H9-H11: halo model and likelihood
@@ -1047,6 +1076,7 @@ int pmr_profile_begin(pmr_ctx* c, int kernel_class, int max_launches) {
   c->prof_class = kernel_class;
   c->prof_used = 0;
   c->prof_bytes = 0.0;
+  c->prof_open = false;
   return PMR_OK;
 }
 

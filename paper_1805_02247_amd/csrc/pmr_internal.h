@@ -193,11 +193,18 @@ void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);
+// Host hooks called just before and just after each scatter launch of a sort (event timing
+// of that kernel alone); `bytes` is the launch's compulsory HBM traffic.
+struct ScatterProbe {
+  void (*before)(void* arg, double bytes);
+  void (*after)(void* arg);
+  void* arg;
+};
 // Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr,
 // and inv[id] = dst (the inverse permutation) when inv != nullptr.
 void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
                  uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
-                 hipStream_t s, uint32_t* inv = nullptr);
+                 hipStream_t s, uint32_t* inv = nullptr, const ScatterProbe* probe = nullptr);
 void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
                       uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
