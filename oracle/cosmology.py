@@ -8,6 +8,10 @@ Paper anchors
   keeps the linear (Zel'dovich) displacement exact on large scales.
 * The paper takes its spectrum from CAMB, which is not available; the synthetic
   stand-in is the BBKS transfer function with Gamma = 0.2, n = 1, sigma8 = 0.8.
+* bbks_transfer: parity unpinned. Its coefficients are pinned only by T(0) = 1 and the
+  sigma8 normalisation (the publication that defines them is not available here). The
+  spectrum only shapes the seeded inputs, which both sides receive identically, so it is
+  off the parity path.
 
 Conventions (readings, stated because the paper is silent)
 ----------------------------------------------------------
@@ -84,7 +88,8 @@ def kdk_factors(a0, a1, n_steps, om):
 # ---------------------------------------------------------------- spectrum
 
 def bbks_transfer(k, gamma=0.2):
-    """BBKS transfer function with shape parameter Gamma, k in h/Mpc."""
+    """BBKS transfer function with shape parameter Gamma, k in h/Mpc (parity unpinned: see
+    the module header)."""
     q = np.asarray(k, dtype=np.float64) / gamma
     with np.errstate(divide="ignore", invalid="ignore"):
         t = (np.log1p(2.34 * q) / (2.34 * q)

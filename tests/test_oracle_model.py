@@ -127,6 +127,30 @@ def test_zeldovich_displacement_divergence():
         np.testing.assert_allclose(psi[a], -0.01 * k[a] / (k @ k) * np.sin(ph), atol=1e-15)
 
 
+@pytest.mark.parametrize("m", [(1, 0, 0), (0, 2, 1), (3, -1, 2)])
+def test_features_single_mode_closed_form(m):
+    """Sec. 2.2 features of a single Fourier mode: for delta = A cos(k.x) on the mesh nodes,
+    a Gaussian smoothing on R multiplies it by exp(-k^2 R^2 / 2), so the three features are
+    (A cos, g1 A cos, (g1 - g2) A cos) with g_j = exp(-k^2 R_j^2 / 2). Written with the
+    trigonometric form directly (no FFT), so a swapped, dropped or mis-signed feature, or
+    a wrong k scaling in the multiplier, fails."""
+    n, box, A = 16, 50.0, 0.7
+    cfg = OM.Config(box, n, n, n, 1, R1=1.5, R2=4.0)
+    i = np.arange(n) * (box / n)
+    X, Y, Z = np.meshgrid(i, i, i, indexing="ij")
+    k = 2 * np.pi * np.array(m) / box
+    base = A * np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+    k2 = float(k @ k)
+    g1, g2 = np.exp(-0.5 * k2 * cfg.R1 ** 2), np.exp(-0.5 * k2 * cfg.R2 ** 2)
+    f = OM.features(cfg, base)
+    assert f.shape == (3, n, n, n)
+    np.testing.assert_allclose(f[0], base, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(f[1], g1 * base, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(f[2], (g1 - g2) * base, rtol=0, atol=1e-13)
+    # the two smoothings differ measurably at these scales, so f[2] != f[1] and != g2 base
+    assert abs(g1 - g2) > 1e-2 and g2 > 1e-3
+
+
 def test_mlp_matches_explicit_loops():
     w = synth.mlp_weights(3, 6)
     f = synth.unit_normal(4, (3, 5))
