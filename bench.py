@@ -144,29 +144,139 @@ def oracle_inputs(w):
                 M0=1.0, R_sm=w["R_sm"][0])
 
 
-def cpu_baseline(w):
-    """FP64 oracle gradient of one batch item of the same workload (single thread)."""
-    from threadpoolctl import threadpool_limits
+def _log(msg):
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+
+def host_cpu():
+    """(model name, cores this process may run on) of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+# Oracle configurations timed beside the GPU workloads (one FP64 gradient each, one thread):
+# the small box (32^3, L = 100 Mpc/h, density-L2 loss), the accuracy variant of the
+# 256^3 / 512^3 workload (64^3 particles on a 128^3 mesh, L = 400, 10 steps, 3-64-64-1),
+# and one realisation of the 32 x 64^3 batch.
+ORACLE_CONFIGS = {
+    "p32_m32_density_l2": dict(n_part=32, n_mesh=32, n_out=32, n_steps=5, box=100.0,
+                               mlp_hidden=0, R_sm=[0.0]),
+    "p64_m128_10steps": dict(n_part=64, n_mesh=128, n_out=64, n_steps=10, box=400.0,
+                             mlp_hidden=64, R_sm=[2.0]),
+    "p64_m64_item": dict(n_part=64, n_mesh=64, n_out=64, n_steps=5, box=200.0, mlp_hidden=32,
+                         R_sm=[0.0]),
+}
+
+
+def oracle_gradient(w, seed=1):
+    """One FP64 oracle gradient of one item of workload w (log-normal loss, or density-L2
+    when w has no network): (seconds, (loss, G, final positions))."""
     from oracle import cosmology as OC
     from oracle import model as OM
+    import synth
 
     n, box = w["n_part"], w["box"]
-    inp = oracle_inputs(w)
-    cfg = OM.Config(box, n, w["n_mesh"], w["n_out"], w["n_steps"])
+    l2 = w["mlp_hidden"] == 0
+    cfg = OM.Config(box, n, w["n_mesh"], w["n_out"], w["n_steps"],
+                    loss_kind=OM.LOSS_DENSITY_L2 if l2 else OM.LOSS_LOGNORMAL)
     power = OC.bbks_power()
     inv = OM.prior_inv_variance(n, box, power)
-    s = OM.linear_modes(inp["white"], box, power)
-    prm = OM.default_params(M0=inp["M0"], R_sm=inp["R_sm"])
+    s = OM.linear_modes(synth.white_noise(seed, n), box, power)
+    if l2:
+        target = synth.unit_normal(7, (w["n_out"],) * 3)
+        prm, mlp = OM.default_params(prior_weight=0.0), None
+    else:
+        target = np.exp(synth.unit_normal(7, (w["n_out"],) * 3))
+        prm, mlp = OM.default_params(M0=1.0, R_sm=w["R_sm"][0]), synth.mlp_weights(3, w["mlp_hidden"])
+    t0 = time.perf_counter()
+    fwd, G = OM.gradient(cfg, s, inv, target, prm, mlp)
+    return time.perf_counter() - t0, (fwd["loss"], G, fwd["xs"][-1])
+
+
+def _warm_worker(seconds):
+    """Imports what the oracle tasks need and holds the worker for a moment, so that a map
+    of these over the pool starts every worker process before anything is timed."""
+    from oracle import model as OM  # noqa: F401
+    import synth  # noqa: F401
+    import threadpoolctl  # noqa: F401
+    time.sleep(seconds)
+
+
+def _oracle_task(w, seed, start_at):
+    """Worker of the host-core legs: wait for the common start, run one FP64 gradient on one
+    thread, return (seconds, end time)."""
+    from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        fwd, G = OM.gradient(cfg, s, inv, inp["target"], prm, inp["mlp"])
-        dt = time.perf_counter() - t0
+        if start_at is not None:
+            time.sleep(max(0.0, start_at - time.time()))
+        t, _ = oracle_gradient(w, seed)
+    return t, time.time()
+
+
+def cpu_baseline(w):
+    """FP64 oracle gradient of batch item 0 of workload w on one thread:
+    (baseline dict, (loss, G, final positions)) -- the reference of the error leg."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        dt, ref = oracle_gradient(w)
     base = {"value": w["n_steps"] / dt, "unit": "PM steps/s", "cores": 1, "kind": "oracle",
             "sample": f"one batch item (of {w['batch']}): one FP64 gradient evaluation, "
-                      f"{n}^3 particles, {w['n_steps']} PM steps, {dt:.1f} s",
+                      f"{w['n_part']}^3 particles, {w['n_steps']} PM steps, {dt:.1f} s",
             "seconds": dt}
-    return base, (fwd["loss"], G, fwd["xs"][-1])
+    return base, ref
+
+
+def cpu_legs(w, max_workers=16):
+    """The oracle on the host's cores, run before any GPU work: one item of workload w on one
+    thread (also the reference of the error leg), the same gradient on every core (one
+    independent item per worker process, one thread each, started together), and one
+    gradient of each ORACLE_CONFIGS entry on one thread (run side by side with the first).
+    The full 256^3 / 512^3 gradient is extrapolated from the 64^3-on-128^3 one by
+    N^3 log N. Returns (cpu_baseline dict, reference)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    model, cores = host_cpu()
+    workers = max(1, min(cores, max_workers))
+    ctx = mp.get_context("spawn")  # fresh interpreters, no inherited state
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        # warm the workers (interpreter start and imports) before anything is timed
+        list(pool.map(_warm_worker, [0.5] * workers))
+        side = {k: pool.submit(_oracle_task, dict(c), 1, None) for k, c in ORACLE_CONFIGS.items()}
+        single, ref = cpu_baseline(w)
+        one_thread = {k: f.result()[0] for k, f in side.items()}
+        start = time.time() + 1.0
+        futs = [pool.submit(_oracle_task, w, 1 + b, start) for b in range(workers)]
+        ends = [f.result()[1] for f in futs]
+    wall = max(ends) - start
+    cfg3_var = one_thread["p64_m128_10steps"]
+    scale = 64.0 * np.log(512.0 ** 3) / np.log(128.0 ** 3)
+    base = {"value": workers * w["n_steps"] / wall, "unit": "PM steps/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{workers} independent items of the {w['n_part']}^3 workload, one FP64 "
+                      f"gradient each ({w['n_steps']} PM steps), one per worker process and "
+                      f"host core, started together: {wall:.1f} s wall",
+            "seconds": wall, "host_cpu": model, "host_cores": cores,
+            "single_thread": {k: single[k] for k in ("value", "unit", "seconds", "sample")},
+            "one_thread_other_configs_s": one_thread,
+            "p256_m512_extrapolated_s": cfg3_var * scale,
+            "p256_m512_extrapolation": "extrapolated: the 64^3-on-128^3 10-step gradient "
+                                       "times 64 (N^3) times log(512^3)/log(128^3)",
+            "p64_m64_b32_one_thread_s": 32 * one_thread["p64_m64_item"]}
+    return base, ref
 
 
 def gpu_item_gradient(w, dev):
@@ -265,8 +375,8 @@ def two_network_leg(w, dev, data, steps):
         avg = ms * 1e-3 / max(n, 1)
         if cls == "halo2":
             ach = alg / max(n, 1) / avg / 1e12
-            out[cls] = {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK_TFLOPS,
+            out[cls] = {"bound": "mfma", "achieved": ach, "peak": FP32_MATRIX_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / FP32_MATRIX_PEAK_TFLOPS,
                         "avg_launch_us": avg * 1e6, "launches": n}
         else:
             ach = alg / max(n, 1) / avg / 1e9
@@ -343,31 +453,156 @@ def reconstruction_paper_model_leg(dev, iterations=120, nbins=64):
             "k_h_per_mpc": [round((i + 0.5) * 2 * np.pi / box, 5) for i in range(nbins)]}
 
 
-def mixed_vs_fp32(dev, steps):
-    """The 256^3 / 512^3 mixed-precision workload against the plain FP32 GPU path (the same
-    inputs with the network on FP32 vector units): time per gradient, speedup, and the
-    mixed path's error against the FP32 one at full size."""
+# Kernel classes of the hot path whose algorithmic figure is HBM bytes (the sort is an
+# implementation cost: it counts in time only and is charged to the paint it serves).
+STEP_CLASSES = ["paint", "paint3", "xpass_force", "xpass_force_adj", "ypass", "zpass",
+                "kick_drift", "adj_gather", "adj_update"]
+FP32_MATRIX_PEAK_TFLOPS = 157.3
+BF16_MATRIX_PEAK_TFLOPS = 2500.0
+
+
+def pm_alg_bytes(w):
+    """Algorithmic HBM bytes of the PM part of one gradient evaluation: per item and step
+    the forward's 80 Nm^3 + 132 Np^3 (paint, two-pass r2c, three force c2r, readout, kick and
+    drift) and twice that for the step adjoint (with the force recomputed)."""
+    nm3, np3 = float(w["n_mesh"]) ** 3, float(w["n_part"]) ** 3
+    return w["batch"] * w["n_steps"] * 3.0 * (80.0 * nm3 + 132.0 * np3)
+
+
+def _r(v, d=4):
+    """Round to d significant digits (keeps the JSON line short)."""
+    if v is None or not isinstance(v, float) or v == 0.0 or not np.isfinite(v):
+        return v
+    return float(f"{v:.{d}g}")
+
+
+def probe_classes(pm, step, classes):
+    """(total ms, launches, algorithmic units) of each kernel class over one gradient each."""
+    out = {}
+    for cls in classes:
+        pm.profile_begin(cls)
+        step()
+        out[cls] = pm.profile_end()
+    return out
+
+
+def class_roofline(probe, cls, copy_gbs=None):
+    ms, n, alg = probe[cls]
+    avg = ms * 1e-3 / max(n, 1)
+    ach = alg / max(n, 1) / avg / 1e9 if avg > 0 else 0.0
+    r = {"bound": "hbm", "kernel": cls, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": ach / HBM_PEAK_GBS, "avg_launch_us": avg * 1e6, "launches": n,
+         "alg_bytes_per_launch": alg / max(n, 1)}
+    if copy_gbs:
+        r["copy_gbs_measured"] = copy_gbs
+        r["frac_of_copy"] = ach / copy_gbs
+    return r
+
+
+def step_summaries(w, probe, t_grad, precision):
+    """Whole-gradient fraction, the paint step with the sort's time charged to it (the sort
+    only serves the paint and the gathers), and the network against the matrix-core peak."""
+    alg = pm_alg_bytes(w)
+    whole = {"alg_bytes": alg, "ms_per_gradient": 1e3 * t_grad,
+             "achieved": alg / t_grad / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": alg / t_grad / 1e9 / HBM_PEAK_GBS,
+             "bytes_model": "batch * n_steps * 3 * (80 Nm^3 + 132 Np^3)"}
+    pms, pn, pbytes = probe["paint"]
+    sms = probe["sort"][0]
+    paint_sort = {"paint_ms": pms, "sort_ms": sms, "alg_bytes": pbytes,
+                  "achieved": pbytes / ((pms + sms) * 1e-3) / 1e9,
+                  "frac": pbytes / ((pms + sms) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "frac_without_sort": pbytes / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "sort_share_of_gradient": sms * 1e-3 / t_grad}
+    nms, nn, nflop = probe["network"]
+    peak = BF16_MATRIX_PEAK_TFLOPS if precision == 1 else FP32_MATRIX_PEAK_TFLOPS
+    net = None
+    if nn > 0 and nms > 0:
+        ach = nflop / (nms * 1e-3) / 1e12
+        net = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+               "frac": ach / peak, "launches": nn, "ms_per_gradient": nms,
+               "dtype": "bf16 (fp32 accumulate)" if precision == 1 else "fp32"}
+    return whole, paint_sort, net
+
+
+def workload_leg(name, dev, steps, data=None, graph=False, precision=None):
+    """One workload at full size: time per gradient (eager; and as one HIP-graph replay),
+    PM steps/s, per-class event times and rooflines, the whole-gradient fraction."""
     import torch
-    w = WORKLOADS["p256_m512"]
-    res = {}
-    grads = {}
-    data = None
-    for name, prec in (("fp32", 0), ("mixed", 1)):
-        pm, modes = make_context(dict(w, precision=prec), dev, data)
-        data = pm.data
-        t, g = time_gradient(pm, modes, steps, 1)
-        _, loss = pm.forward(modes, want_mass=False)
+    import paper_1805_02247_amd as P
+    w = dict(WORKLOADS[name])
+    if precision is not None:
+        w["precision"] = precision
+    pm, modes = make_context(w, dev, data)
+    t, g = time_gradient(pm, modes, steps, 1)
+    ones = torch.ones(w["batch"], dtype=torch.float64, device=dev)
+
+    def step():
+        pm.forward(modes, want_mass=False)
+        pm.adjoint(ones, out=g)
+
+    probe = probe_classes(pm, step, STEP_CLASSES + ["sort", "network"])
+    whole, paint_sort, net = step_summaries(w, probe, t, w["precision"])
+    dom = max(STEP_CLASSES, key=lambda c: probe[c][0])
+    out = {"workload": name, "ms_per_gradient": 1e3 * t,
+           "value": w["n_steps"] * w["batch"] / t, "unit": "PM steps/s",
+           "whole_gradient_frac": whole["frac"], "roofline": class_roofline(probe, dom),
+           "paint_step_with_sort_frac": paint_sort["frac"],
+           "sort_share_of_gradient": paint_sort["sort_share_of_gradient"],
+           "class_frac": {c: class_roofline(probe, c)["frac"] for c in STEP_CLASSES},
+           "class_ms": {c: probe[c][0] for c in STEP_CLASSES + ["sort", "network"]}}
+    if net:
+        out["network_frac_of_matrix_peak"] = net["frac"]
+    if graph:
+        G = P.GradientGraph(pm, modes)
+        for _ in range(2):
+            G.replay()
         torch.cuda.synchronize()
-        res[name] = {"ms_per_gradient": 1e3 * t, "value": w["n_steps"] * w["batch"] / t,
-                     "unit": "PM steps/s"}
-        grads[name] = (float(loss[0, 0]), g[0].cpu().numpy().astype(np.complex128), None)
-        del pm, modes, g
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            G.replay()
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / steps
+        out["graph_ms_per_gradient"] = 1e3 * tg
+        out["graph_value"] = w["n_steps"] * w["batch"] / tg
+        del G
+    _, loss = pm.forward(modes, want_mass=False)
+    res = (pm.data, g, float(loss[0, 0]))
+    del pm, modes
+    torch.cuda.empty_cache()
+    return out, res
+
+
+def mixed_vs_fp32(dev, steps):
+    """The 256^3 / 512^3 workload in mixed precision (BF16 network) against the plain FP32
+    GPU path on the same inputs: time per gradient, rooflines, the speedup, and the mixed
+    path's error against the FP32 one at full size. Compact: it is the last entry of the
+    benchmark's line."""
+    import torch
+    res, grads, data = {}, {}, None
+    for name, prec in (("fp32", 0), ("mixed", 1)):
+        leg, (data, g, loss) = workload_leg("p256_m512", dev, steps, data=data, precision=prec)
+        grads[name] = (loss, g[0].cpu().numpy().astype(np.complex128))
+        res[name] = leg
+        del g
         torch.cuda.empty_cache()
     del data
-    res["speedup_mixed_over_fp32"] = res["fp32"]["ms_per_gradient"] / res["mixed"]["ms_per_gradient"]
-    res["mixed_err_vs_fp32"] = error_vs(*grads["fp32"], *grads["mixed"])
-    res["workload"] = "p256_m512"
-    return res
+    err = error_vs(grads["fp32"][0], grads["fp32"][1], None, grads["mixed"][0],
+                   grads["mixed"][1], None)
+    m, f = res["mixed"], res["fp32"]
+    return {"workload": "p256_m512",
+            "mixed": {"ms": _r(m["ms_per_gradient"]), "value": _r(m["value"]),
+                      "whole_gradient_frac": _r(m["whole_gradient_frac"], 3),
+                      "dominant": m["roofline"]["kernel"],
+                      "dominant_frac": _r(m["roofline"]["frac"], 3),
+                      "paint_step_with_sort_frac": _r(m["paint_step_with_sort_frac"], 3),
+                      "sort_share": _r(m["sort_share_of_gradient"], 3),
+                      "network_frac_bf16_peak": _r(m.get("network_frac_of_matrix_peak"), 3),
+                      "class_frac": {k: _r(v, 3) for k, v in m["class_frac"].items()}},
+            "fp32": {"ms": _r(f["ms_per_gradient"]), "value": _r(f["value"]),
+                     "whole_gradient_frac": _r(f["whole_gradient_frac"], 3)},
+            "speedup_mixed_over_fp32": _r(f["ms_per_gradient"] / m["ms_per_gradient"]),
+            "mixed_err_vs_fp32": {k: _r(v, 3) for k, v in err.items()}}
 
 
 def reconstruction_leg(dev, iterations=200, nbins=64):
@@ -454,6 +689,17 @@ def reconstruction_leg(dev, iterations=200, nbins=64):
     return out
 
 
+def recon_summary(leg, k_bins):
+    """A reconstruction leg without its per-shell arrays: r_c of the recovered modes at a few
+    wavenumbers (h/Mpc), so the benchmark's line stays short."""
+    out = {k: v for k, v in leg.items() if k not in ("r_c", "transfer", "r_c_start")}
+    if "r_c" in leg:
+        ks = np.asarray(k_bins)
+        out["r_c_at_k"] = {str(k): leg["r_c"][int(np.argmin(np.abs(ks - k)))]
+                           for k in (0.05, 0.1, 0.2, 0.3, 0.5)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +713,8 @@ def main():
                     help="skip the 256^3/512^3 mixed-precision vs FP32 comparison")
     ap.add_argument("--no-recon", action="store_true",
                     help="skip the 128^3 reconstruction loop (L-BFGS over the anneal stages)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the secondary legs (noise table, 2LPT, two networks, batch 32)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for counters)")
     args = ap.parse_args()
@@ -474,6 +722,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
+    w = WORKLOADS[args.workload]
+    # the oracle on the host cores first, before this process touches the GPU (its worker
+    # processes start from fresh interpreters)
+    _log("oracle on the host cores")
+    base, ref = (None, None) if args.no_cpu_baseline else cpu_legs(w)
+    _log("GPU: context and warm-up")
 
     import torch
 
@@ -485,7 +739,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    w = WORKLOADS[args.workload]
     pm, modes = make_context(w, dev)
     ones = torch.ones(w["batch"], dtype=torch.float64, device=dev)
     grad = torch.empty(w["batch"], pm.n_modes, dtype=torch.complex64, device=dev)
@@ -497,18 +750,13 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # the kernel class with the largest event time in one untimed gradient evaluation
-    classes = ["paint", "paint3", "xpass_force", "xpass_force_adj", "ypass", "zpass",
-               "kick_drift", "adj_gather", "adj_update", "sort_scatter"]
-    probe = {}
-    for cls in classes:
-        pm.profile_begin(cls)
-        step()
-        probe[cls] = pm.profile_end()
-    ranked = sorted(classes, key=lambda c: probe[c][0], reverse=True)
+    # event time of every kernel class over one untimed gradient evaluation each; the
+    # dominant hot-path step class is timed in the timed region
+    probe = probe_classes(pm, step, STEP_CLASSES + ["sort", "network", "sort_scatter"])
+    ranked = sorted(STEP_CLASSES, key=lambda c: probe[c][0], reverse=True)
     dominant = ranked[0]
-    # timed region, with the dominant class bracketed by HIP events on the library's stream
     pm.profile_begin(dominant, max_launches=64 * (args.steps + 1))
+    _log(f"timed region: {args.steps} gradients of {args.workload}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -535,32 +783,27 @@ def main():
                    "mlp_hidden": w["mlp_hidden"], "box_mpch": w["box"],
                    "ckpt_every": w["ckpt_every"], "parallelism": "single GPU"},
     }
-    avg_s = ev_ms * 1e-3 / max(ev_n, 1)
-    per_launch = ev_bytes / max(ev_n, 1)
-    achieved = per_launch / avg_s / 1e9
-    out["roofline"] = {"bound": "hbm", "kernel": dominant, "achieved": achieved,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": counter_traffic(args.workload, dominant),
-                       "avg_launch_us": avg_s * 1e6, "launches": ev_n,
-                       "alg_bytes_per_launch": per_launch,
-                       "share_of_step": ev_ms / (1e3 * T)}
     copy = copy_bandwidth(dev)
-    out["roofline"]["copy_gbs_measured"] = copy
-    out["roofline"]["frac_of_copy"] = achieved / copy
-    # the runner-up class, from its own untimed gradient evaluation
-    nxt = ranked[1]
-    pm.profile_begin(nxt, max_launches=256)
-    step()
-    n_ms, n_n, n_bytes = pm.profile_end()
-    n_avg = n_ms * 1e-3 / max(n_n, 1)
-    n_ach = n_bytes / max(n_n, 1) / n_avg / 1e9
-    out["roofline_next"] = {"bound": "hbm", "kernel": nxt, "achieved": n_ach,
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": n_ach / HBM_PEAK_GBS,
-                            "traffic": counter_traffic(args.workload, nxt),
-                            "avg_launch_us": n_avg * 1e6, "launches": n_n,
-                            "alg_bytes_per_launch": n_bytes / max(n_n, 1),
-                            "frac_of_copy": n_ach / copy}
-    out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in classes}
+    roof = class_roofline({dominant: (ev_ms, ev_n, ev_bytes)}, dominant, copy)
+    roof["traffic"] = counter_traffic(args.workload, dominant)
+    roof["share_of_step"] = ev_ms / (1e3 * T)
+    out["roofline"] = roof
+    if base is not None:
+        out["cpu_baseline"] = base
+        out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev), box=w["box"],
+                                           n_mesh=w["n_mesh"]),
+                                  sample="batch item 0 inputs, full workload size")
+    else:
+        out["cpu_baseline"] = None
+    t_grad = T / args.steps
+    whole, paint_sort, net = step_summaries(w, probe, t_grad, w["precision"])
+    out["whole_gradient"] = whole
+    out["paint_step_with_sort"] = paint_sort
+    out["network"] = net
+    out["roofline_next"] = class_roofline(probe, ranked[1], copy)
+    out["roofline_next"]["traffic"] = counter_traffic(args.workload, ranked[1])
+    out["class_frac"] = {c: class_roofline(probe, c)["frac"] for c in STEP_CLASSES}
+    out["kernel_classes_ms_per_step"] = {c: probe[c][0] for c in probe}
     if not args.no_graph:
         G = P.GradientGraph(pm, modes)
         for _ in range(args.warmup):
@@ -574,8 +817,9 @@ def main():
         out["graph_replay"] = {"ms_per_step": 1e3 * Tg / args.steps, "value": pm_steps / Tg,
                                "unit": "PM steps/s"}
         del G
-    # mass-dependent noise: the same gradient with a 4-node table in log(M_R,data)
-    if args.workload == "p128_m128_b4":
+    if args.workload == "p128_m128_b4" and not args.no_legs:
+        _log("legs: noise table, second-order LPT, two networks")
+        # mass-dependent noise: the same gradient with a 4-node table in log(M_R,data)
         t_plain, _ = time_gradient(pm, modes, max(2, args.steps // 2), 1)
         lm = np.log(np.percentile(pm.data[0].cpu().numpy(), [5, 35, 65, 95]))
         pm.set_noise_table(lm, [0.3, -0.1, 0.05, 0.2], [0.9, 0.35, 0.5, 0.7])
@@ -590,21 +834,31 @@ def main():
                                    "ms_per_step_2lpt": 1e3 * t_2lpt}
         del pm2, modes2
         out["two_network"] = two_network_leg(w, dev, pm.data, max(2, args.steps // 2))
-    if args.no_cpu_baseline:
-        out["cpu_baseline"] = None
-    else:
-        base, ref = cpu_baseline(w)
-        out["cpu_baseline"] = base
-        out["err_vs_fp64"] = dict(error_vs(*ref, *gpu_item_gradient(w, dev), box=w["box"],
-                                           n_mesh=w["n_mesh"]),
-                                  sample="batch item 0 inputs, full workload size")
-    if not args.no_256 and args.workload != "p256_m512":
-        del pm, modes, grad
-        torch.cuda.empty_cache()
-        out["at_256"] = mixed_vs_fp32(dev, max(2, min(args.steps, 10)))
+    del pm, modes, grad
+    torch.cuda.empty_cache()
+    if args.workload == "p128_m128_b4" and not args.no_legs:
+        _log("leg: 32 x 64^3")
+        # 32 realisations of 64^3 in one launch, also as one captured HIP graph
+        leg, _ = workload_leg("p64_m64_b32", dev, max(5, args.steps // 2), graph=True)
+        out["batch32_64cube"] = {k: leg[k] for k in
+                                 ("workload", "ms_per_gradient", "value", "graph_ms_per_gradient",
+                                  "graph_value", "unit", "whole_gradient_frac")}
+        out["batch32_64cube"]["dominant"] = leg["roofline"]["kernel"]
+        out["batch32_64cube"]["dominant_frac"] = leg["roofline"]["frac"]
     if not args.no_recon and args.workload == "p128_m128_b4":
-        out["reconstruction"] = reconstruction_leg(dev)
-        out["reconstruction_paper_model"] = reconstruction_paper_model_leg(dev)
+        _log("legs: reconstruction loops")
+        rec = reconstruction_leg(dev)
+        kb = rec.pop("k_h_per_mpc")
+        rc0 = rec.pop("r_c_start", None)
+        out["reconstruction"] = {k: (recon_summary(v, kb) if isinstance(v, dict) else v)
+                                 for k, v in rec.items()}
+        if rc0 is not None:
+            out["reconstruction"]["r_c_start_at_k"] = recon_summary({"r_c": rc0}, kb)["r_c_at_k"]
+        recp = reconstruction_paper_model_leg(dev)
+        out["reconstruction_paper_model"] = recon_summary(recp, recp.pop("k_h_per_mpc"))
+    if not args.no_256 and args.workload != "p256_m512":
+        _log("leg: 256^3 on 512^3, FP32 and mixed")
+        out["at_256"] = mixed_vs_fp32(dev, max(2, min(args.steps, 10)))  # last: see docstring
     print(json.dumps(out), flush=True)
 
 

@@ -22,7 +22,9 @@
  * workspace passed to pmr_create. The library never allocates device memory. set_* calls
  * copy their inputs into the workspace (stream-ordered), so the caller may reuse its
  * buffers once the stream has passed the call. All calls enqueue work on the context's
- * stream and return without synchronising it (pmr_set_loss copies a small host array).
+ * stream and return without synchronising it, except where a declaration says otherwise
+ * (pmr_set_check_finite, pmr_profile_end). Small host arrays (loss parameters, noise
+ * tables) are passed to the device as kernel arguments, so they need not outlive the call.
  *
  * Errors: calls return PMR_OK or a negative status and never abort. Argument and shape
  * errors are detected synchronously. A HIP launch or runtime error is reported as
@@ -53,7 +55,7 @@ enum {
 enum { PMR_FP32 = 0, PMR_MIXED = 1 };
 enum { PMR_LOSS_DENSITY_L2 = 0, PMR_LOSS_LOGNORMAL = 1 };
 /* Halo model of the log-normal loss: one softplus network on the voxel's features, or the
- * paper's product of a position network and a mass network (Sec. 2.1, Sec. 2.3). */
+ * paper's product of a position network and a mass network (Sec. 2, Sec. 2.1). */
 enum { PMR_HALO_SINGLE = 0, PMR_HALO_TWO = 1 };
 /* Floats of the packed weight blocks of the two networks (pmr_set_halo_nets). */
 enum { PMR_NNP_FLOATS = 50 * 81 + 50 + 30 * 50 + 30 + 30 + 1, PMR_NNM_FLOATS = 20 * 3 + 20 + 10 * 20 + 10 + 10 + 1 };
@@ -113,7 +115,7 @@ int pmr_set_prior(pmr_ctx* ctx, const float* inv_var);
 int pmr_set_mlp(pmr_ctx* ctx, const float* W1, const float* b1, const float* W2,
                 const float* b2, const float* W3, const float* b3);
 
-/* Weights of the two-network halo model (Sec. 2.1: model = NNp x NNm; Sec. 2.3), device
+/* Weights of the two-network halo model (Sec. 2: model = NNp x NNm; Sec. 2.1), device
  * float32, each network packed as its layers in order, weights row-major [out][in]:
  *   nnp (PMR_NNP_FLOATS): W1 [50][81], b1 [50], W2 [30][50], b2 [30], W3 [1][30], b3 [1];
  *     ReLU hidden layers, output logistic(y, a) with a the loss parameter logistic_a;
@@ -130,15 +132,31 @@ int pmr_set_halo_nets(pmr_ctx* ctx, const float* nnp, const float* nnm);
  * contrast (density-L2 loss). Copied. */
 int pmr_set_target(pmr_ctx* ctx, const float* target);
 
-/* Loss parameters, HOST array [B]. Copied to device memory. */
+/* Loss parameters (Sec. 5.1, Eq. loss; the anneal stages of Sec. 5.2 change R_sm, M0 and
+ * the logistic sharpness a), HOST array [B]. Checked here (PMR_E_INVALID: sigma_N <= 0,
+ * M0 <= 0 for the log-normal loss, negative R, non-finite mu or prior_weight, a <= 0 with
+ * PMR_HALO_TWO) and stored in device memory stream-ordered, without synchronising; the data
+ * term x_data = log(G_Rmass * M_target + M0) is recomputed on the stream. Kernels read the
+ * parameters from device memory, so a forward captured in a HIP graph picks up a later
+ * pmr_set_loss at its next replay. */
 int pmr_set_loss(pmr_ctx* ctx, const pmr_loss_params* params);
+
+/* The same from DEVICE memory: params_device is a [B] array of pmr_loss_params (8-byte
+ * aligned) that the stream reads when it reaches this call, so the call itself can be
+ * captured in a HIP graph and the caller may write new values into the array between
+ * replays (the anneal stages of Sec. 5.2 without host synchronisation). The values are
+ * checked on the device with the rules of pmr_set_loss; an item that fails them gets a NaN
+ * loss (total, prior and data) from the next pmr_forward instead of an error status.
+ * PMR_E_INVALID for a null or misaligned pointer. */
+int pmr_set_loss_device(pmr_ctx* ctx, const pmr_loss_params* params_device);
 
 /* Mass-dependent noise of the log-normal likelihood (Sec. 5.1: mu_N and sigma_N of Eq.
  * (probnoise) depend on the smoothed data mass M_R at the cell). HOST arrays of n_nodes
  * (<= 64): nodes log_mass (natural log of M_R of the data, strictly increasing) and the
  * values mu and sigma (> 0) there. Each cell takes the linear interpolation at
  * log(M_R,data), constant beyond the end nodes, for every batch item; this replaces the
- * scalar mu and sigma_N of pmr_set_loss. n_nodes = 0 restores the scalars. Copied.
+ * scalar mu and sigma_N of pmr_set_loss. n_nodes = 0 restores the scalars. Copied to the
+ * device as kernel arguments (stream-ordered, no synchronisation).
  * Whether a table is in use is fixed into a forward pass captured in a HIP graph: capture
  * after switching it on or off (changing the values of a table in use needs no recapture). */
 int pmr_set_noise_table(pmr_ctx* ctx, int n_nodes, const double* log_mass, const double* mu,
@@ -149,6 +167,11 @@ int pmr_set_noise_table(pmr_ctx* ctx, int n_nodes, const double* log_mass, const
  * (density-L2); nullable. loss_out: device double [B][3] = (total, prior, data).
  * Keeps what the adjoint needs in the workspace; invalidated by the next forward. */
 int pmr_forward(pmr_ctx* ctx, const void* modes, float* mass_out, double* loss_out);
+
+/* Number of pmr_forward calls enqueued on this context so far (or PMR_E_INVALID for a null
+ * context). A caller that keeps the value of a forward can tell whether a later forward has
+ * replaced the state its adjoint would use. */
+long long pmr_forward_count(const pmr_ctx* ctx);
 
 /* Optional check of the loss: with on != 0, pmr_forward synchronises the context stream at
  * its end, reads the B x 3 loss values back and returns PMR_E_NONFINITE if any is NaN or
@@ -219,8 +242,15 @@ enum {
                                      algorithmic figure is FLOPs, not bytes */
   PMR_PROF_HALO2_STENCIL = 11,    /* two-network model: neighbourhood sum of the position
                                      network's input adjoint */
-  PMR_PROF_SORT_SCATTER = 12      /* scatter passes of the cell-key radix sort (each pass
+  PMR_PROF_SORT_SCATTER = 12,     /* scatter passes of the cell-key radix sort (each pass
                                      timed alone, without its histogram and scan) */
+  PMR_PROF_SORT = 13,             /* every kernel of one cell-key sort and its row index, as
+                                     one launch; an implementation cost that serves the paint
+                                     and the adjoint gathers: its algorithmic bytes are 0 */
+  PMR_PROF_NETWORK = 14           /* the single network's forward and adjoint kernels; their
+                                     algorithmic figure is FLOPs: 2 (4H + H^2) per voxel
+                                     forward, 2 (8H + 2H^2) adjoint (recomputed activations
+                                     and the transposed products) */
 };
 int pmr_profile_begin(pmr_ctx* ctx, int kernel_class, int max_launches);
 int pmr_profile_end(pmr_ctx* ctx, double* total_ms, long long* launches, double* alg_bytes);

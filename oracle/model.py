@@ -15,7 +15,7 @@ What is computed, in the paper's order
    mass = softplus(output) (halo_model = HALO_SINGLE), or the paper's two networks
    (HALO_TWO): a position network on the features of the 3 x 3 x 3 neighbourhood whose
    logistic output (sharpness a, Eq. logistic) is multiplied by a mass network on the
-   voxel's own features (Sec. 2.1, Sec. 2.3).
+   voxel's own features (Sec. 2, Sec. 2.1).
 4. Likelihood (Sec. 5.1, Eqs. var, probnoise, loss): x = log(M_R + M0) with M_R the
    Gaussian-smoothed mass; residual (mu + x - x_data) / (2 sigma_N); f_eff = 1.
    Residual smoothing anneal (Sec. 5.2): the residual is Gaussian-smoothed on R_sm
@@ -208,7 +208,7 @@ def mlp_backward(w, cache, mass_bar):
     return W1.T @ a1_bar
 
 
-# The paper's two-network model (Sec. 2.1: model = NNp x NNm; Sec. 2.3: architecture).
+# The paper's two-network model (Sec. 2: model = NNp x NNm; Sec. 2.1: architecture).
 
 # Offsets of the 3 x 3 x 3 neighbourhood; position-network feature c * 27 + o holds
 # feature field c at the voxel displaced by STENCIL[o] (periodic mesh).

@@ -12,6 +12,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pmr.h")
 
 PMR_OK = 0
 PMR_E_NONFINITE = -5
+PMR_E_STATE = -6
 PMR_FP32, PMR_MIXED = 0, 1
 PMR_LOSS_DENSITY_L2, PMR_LOSS_LOGNORMAL = 0, 1
 PMR_HALO_SINGLE, PMR_HALO_TWO = 0, 1
@@ -59,6 +60,8 @@ SIGNATURES = {
     "pmr_set_check_finite": (ci, [vp, ci]),
     "pmr_set_target": (ci, [vp, vp]),
     "pmr_set_loss": (ci, [vp, ctypes.POINTER(PmrLossParams)]),
+    "pmr_set_loss_device": (ci, [vp, vp]),
+    "pmr_forward_count": (ctypes.c_longlong, [vp]),
     "pmr_set_noise_table": (ci, [vp, ci, ctypes.POINTER(cd), ctypes.POINTER(cd),
                                  ctypes.POINTER(cd)]),
     "pmr_forward": (ci, [vp, vp, vp, vp]),
@@ -85,7 +88,8 @@ SIGNATURES = {
 }
 PROF = {"paint": 1, "xpass_force": 2, "ypass": 3, "zpass": 4, "kick_drift": 5, "paint3": 6,
         "xpass_force_adj": 7, "adj_gather": 8, "adj_update": 9, "halo2": 10,
-        "halo2_stencil": 11, "sort_scatter": 12}
+        "halo2_stencil": 11, "sort_scatter": 12, "sort": 13,
+        "network": 14}
 
 
 def lib():

@@ -68,6 +68,18 @@ class LossParams:
     logistic_a: float = 3.0  # sharpness of the position network's logistic (two-network model)
 
 
+LOSS_FIELDS = ("M0", "mu", "sigma_N", "R_mass", "R_sm", "prior_weight", "logistic_a")
+
+
+def loss_param_rows(params, batch):
+    """[batch] rows of the seven loss-parameter values from one LossParams or a list."""
+    if isinstance(params, LossParams):
+        params = [params] * batch
+    if len(params) != batch:
+        raise ValueError("one LossParams per batch item")
+    return [tuple(float(getattr(p, k)) for k in LOSS_FIELDS) for p in params]
+
+
 def workspace_bytes(cfg):
     c = cfg.c()
     return int(L.lib().pmr_workspace_bytes(ctypes.byref(c)))
@@ -157,16 +169,21 @@ class PMContext:
         self._keep_target = target
 
     def set_loss(self, params):
-        if isinstance(params, LossParams):
-            params = [params] * self.cfg.batch
-        if len(params) != self.cfg.batch:
-            raise ValueError("one LossParams per batch item")
-        arr = (L.PmrLossParams * self.cfg.batch)(
-            *[L.PmrLossParams(p.M0, p.mu, p.sigma_N, p.R_mass, p.R_sm, p.prior_weight,
-                              p.logistic_a)
-              for p in params])
+        arr = (L.PmrLossParams * self.cfg.batch)(*[L.PmrLossParams(*v)
+                                                    for v in loss_param_rows(params, self.cfg.batch)])
         self._sync_stream()
         L.check(L.lib().pmr_set_loss(self._ctx, arr))
+
+    def set_loss_device(self, params):
+        """Loss parameters from a device float64 tensor [B][7] (the fields of LossParams in
+        order), read by the stream when it reaches this call; invalid items give a NaN loss."""
+        _need(params, torch.float64, self.cfg.batch * 7, "params")
+        self._sync_stream()
+        L.check(L.lib().pmr_set_loss_device(self._ctx, _ptr(params)))
+
+    def forward_count(self):
+        """Number of forward passes enqueued on this context."""
+        return int(L.lib().pmr_forward_count(self._ctx))
 
     def set_noise_table(self, log_mass=(), mu=(), sigma=()):
         """Mass-dependent noise: nodes in log(M_R,data) with mu_N and sigma_N (empty: the
@@ -231,23 +248,35 @@ class PMContext:
 
 
 class PMForward(torch.autograd.Function):
-    """loss [B] (and mass [B][Nout^3]) from modes, with the hand-written adjoint as backward.
+    """(loss [B], mass [B][Nout^3]) from modes, with the hand-written adjoint (pmr_adjoint)
+    as the backward pass.
 
-    Usage: loss, mass = PMForward.apply(modes, pmctx)."""
+    Usage: loss, mass = PMForward.apply(modes, pmctx); loss.sum().backward().
+    modes: complex64 [B][n_modes] or [B][Np][Np][Np/2+1]; the gradient has the same shape
+    (dL/dRe + i dL/dIm, PyTorch's convention for real losses of complex tensors). The context
+    keeps the state of one forward only: a backward after another forward on the same context
+    raises PmrError with status PMR_E_STATE instead of returning that forward's gradient."""
 
     @staticmethod
     def forward(ctx, modes, pmctx):
-        mass, loss = pmctx.forward(modes.contiguous())
+        flat = modes.detach().reshape(pmctx.cfg.batch, -1).contiguous()
+        mass, loss = pmctx.forward(flat)
         ctx.pmctx = pmctx
+        ctx.generation = pmctx.forward_count()
+        ctx.modes_shape = modes.shape
+        ctx.set_materialize_grads(False)
         return loss[:, 0].clone(), mass
 
     @staticmethod
     def backward(ctx, loss_bar, mass_bar):
         pm = ctx.pmctx
+        if pm.forward_count() != ctx.generation:
+            raise L.PmrError("PMForward.backward: a later forward on the same context replaced "
+                             "the state of this one (PMR_E_STATE)", L.PMR_E_STATE)
         if loss_bar is None:
             loss_bar = torch.zeros(pm.cfg.batch, dtype=torch.float64, device=pm.device)
         g = pm.adjoint(loss_bar, mass_bar)
-        return g.view(pm.cfg.batch, pm.cfg.n_part, pm.cfg.n_part, pm.cfg.n_part // 2 + 1), None
+        return g.reshape(ctx.modes_shape), None
 
 
 # ---------------------------------------------------------------- primitives
@@ -318,12 +347,21 @@ class GradientGraph:
 
     The library enqueues only kernels and device-to-device copies (no memsets), so the
     captured graph replays exactly what the eager calls do.
+
+    With `params` (one LossParams or a list), the graph also captures pmr_set_loss_device on
+    a device buffer `self.params` [B][7]; `set_params` writes new stage values into it with a
+    stream-ordered copy, so an anneal stage changes between replays without a host
+    synchronisation in the library and without recapture.
     """
 
-    def __init__(self, pmctx, modes, warmup=1):
+    def __init__(self, pmctx, modes, warmup=1, params=None):
         self.pm = pmctx
         B = pmctx.cfg.batch
         self.modes = modes.clone().contiguous()
+        self.params = None
+        if params is not None:
+            self.params = torch.tensor(loss_param_rows(params, B), dtype=torch.float64,
+                                       device=pmctx.device)
         self.loss_bar = torch.ones(B, dtype=torch.float64, device=pmctx.device)
         self.loss = torch.empty(B, 3, dtype=torch.float64, device=pmctx.device)
         self.grad = torch.empty(B, pmctx.n_modes, dtype=torch.complex64, device=pmctx.device)
@@ -339,9 +377,18 @@ class GradientGraph:
             self._enqueue()
         torch.cuda.synchronize()
 
+    def set_params(self, params):
+        """New loss parameters for the next replays (captured with `params` only)."""
+        if self.params is None:
+            raise ValueError("GradientGraph was captured without device loss parameters")
+        rows = torch.tensor(loss_param_rows(params, self.pm.cfg.batch), dtype=torch.float64)
+        self.params.copy_(rows.pin_memory(), non_blocking=True)
+
     def _enqueue(self):
         pm = self.pm
         pm._sync_stream()
+        if self.params is not None:
+            L.check(L.lib().pmr_set_loss_device(pm._ctx, _ptr(self.params)))
         L.check(L.lib().pmr_forward(pm._ctx, _ptr(self.modes), None, _ptr(self.loss)))
         L.check(L.lib().pmr_adjoint(pm._ctx, _ptr(self.loss_bar), None, _ptr(self.grad)))
 

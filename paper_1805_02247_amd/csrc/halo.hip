@@ -610,9 +610,43 @@ __global__ void finalize_loss_kernel(const double* __restrict__ prior, const dou
                                      double* __restrict__ loss_out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
-  loss_out[3 * b + 0] = prm[b * NPRM + 5] * prior[b] + data[b];
-  loss_out[3 * b + 1] = prior[b];
-  loss_out[3 * b + 2] = data[b];
+  // an item whose parameters failed the device-side check reports a NaN loss
+  const double bad = prm[b * NPRM + PRM_VALID] != 0.0 ? 0.0 : __builtin_nan("");
+  loss_out[3 * b + 0] = prm[b * NPRM + 5] * prior[b] + data[b] + bad;
+  loss_out[3 * b + 1] = prior[b] + bad;
+  loss_out[3 * b + 2] = data[b] + bad;
+}
+
+// ---------------------------------------------------------------- loss parameters
+// Host parameters arrive as kernel arguments (copied at launch), so the host array need not
+// outlive the call and nothing waits for the copy.
+__global__ void params_store_kernel(ParamChunk c, double* __restrict__ prm) {
+  const int i = threadIdx.x;
+  if (i < c.count * NPRM) prm[(size_t)c.b0 * NPRM + i] = c.v[i];
+}
+
+// Parameters from device memory (PMR_LOSS_FIELDS doubles per item, the field order of the
+// public struct), checked here: an item that fails the check is stored with its validity
+// slot 0, which makes its loss NaN.
+__global__ void params_from_device_kernel(const double* __restrict__ src, int batch,
+                                          int density_l2, int halo_two,
+                                          double* __restrict__ prm) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double v[PMR_LOSS_FIELDS];
+#pragma unroll
+  for (int i = 0; i < PMR_LOSS_FIELDS; ++i) v[i] = src[(size_t)b * PMR_LOSS_FIELDS + i];
+  bool ok = v[2] > 0.0 && v[2] < INFINITY && (density_l2 || (v[0] > 0.0 && v[0] < INFINITY)) &&
+            v[3] >= 0.0 && v[3] < INFINITY && v[4] >= 0.0 && v[4] < INFINITY &&
+            isfinite(v[1]) && isfinite(v[5]);
+  if (halo_two) ok = ok && v[6] > 0.0 && v[6] < INFINITY;
+#pragma unroll
+  for (int i = 0; i < PMR_LOSS_FIELDS; ++i) prm[(size_t)b * NPRM + i] = v[i];
+  prm[(size_t)b * NPRM + PRM_VALID] = ok ? 1.0 : 0.0;
+}
+
+__global__ void noise_table_store_kernel(NoiseTable t, double* __restrict__ tab) {
+  for (int i = threadIdx.x; i < 3 * NOISE_MAX; i += blockDim.x) tab[i] = t.v[i];
 }
 
 // ---------------------------------------------------------------- modes
@@ -790,6 +824,28 @@ void launch_project_prior(const float2* modes, int n, int batch, const float* in
 void launch_finalize_loss(const double* prior, const double* data, const double* prm, int batch,
                           double* loss_out, hipStream_t s) {
   finalize_loss_kernel<<<(batch + 63) / 64, 64, 0, s>>>(prior, data, prm, batch, loss_out);
+}
+
+void launch_params_store(const double* host, int batch, double* prm, hipStream_t s) {
+  for (int b0 = 0; b0 < batch; b0 += PRM_CHUNK) {
+    ParamChunk c;
+    c.b0 = b0;
+    c.count = batch - b0 < PRM_CHUNK ? batch - b0 : PRM_CHUNK;
+    for (int i = 0; i < c.count * NPRM; ++i) c.v[i] = host[(size_t)b0 * NPRM + i];
+    params_store_kernel<<<1, PRM_CHUNK * NPRM, 0, s>>>(c, prm);
+  }
+}
+
+void launch_params_from_device(const double* src, int batch, int density_l2, int halo_two,
+                               double* prm, hipStream_t s) {
+  params_from_device_kernel<<<(batch + 63) / 64, 64, 0, s>>>(src, batch, density_l2, halo_two,
+                                                             prm);
+}
+
+void launch_noise_table_store(const double* host, double* tab, hipStream_t s) {
+  NoiseTable t;
+  for (int i = 0; i < 3 * NOISE_MAX; ++i) t.v[i] = host[i];
+  noise_table_store_kernel<<<1, 256, 0, s>>>(t, tab);
 }
 
 }  // namespace pmr

@@ -1,4 +1,4 @@
-// The paper's two-network halo model (Sec. 2.1: model = NNp x NNm; Sec. 2.3: architecture;
+// The paper's two-network halo model (Sec. 2: model = NNp x NNm; Sec. 2.1: architecture;
 // Sec. 2.2: features) and its input gradient, on the output mesh.
 //
 // Per voxel v with feature fields f = (delta_0, delta_R1, delta_R1 - delta_R2):

@@ -86,6 +86,7 @@ struct pmr_ctx {
   int status;       // sticky error
   int have_prior, have_mlp, have_target, have_loss, xd_dirty, fwd_done;
   int check_finite;  // pmr_set_check_finite
+  long long n_forward;  // pmr_forward calls enqueued (pmr_forward_count)
   // sizes
   int B, np, nm, no, n, H, k;
   size_t np3, nm3, no3, cp, cm, co;  // standard half-spectrum sizes n * n * (n/2 + 1)
@@ -594,11 +595,14 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
   const int fsl = fs_of(c, i);
   double* x = xslot(c, xsl);
   double* xn = xslot(c, xsl + 1);
-  launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
-              c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl),
-              ScatterProbeOf(c).get());
-  launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
-                   c->stream);
+  {
+    ProfScope ps(c, PMR_PROF_SORT, 0.0);
+    launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
+                c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl),
+                ScatterProbeOf(c).get());
+    launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
+                     c->stream);
+  }
   const size_t cm = c->sm;
   const FieldMap dm = fmap(1, cm, 0, spec_pitch(c->nm));
   {
@@ -628,7 +632,9 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
   {
-    ProfScope ps(c, PMR_PROF_KICK_DRIFT, 76.0 * B * c->np3 + 12.0 * B * c->nm3);
+    // compulsory: x (FP64) and p read and written per particle, the three force channels
+    // per cell (the keys and fractions of the next sort count in time only)
+    ProfScope ps(c, PMR_PROF_KICK_DRIFT, 72.0 * B * c->np3 + 12.0 * B * c->nm3);
     launch_kick_drift(x, xn, c->p, F, c->keys, c->frac_id, B, c->log_np3, c->nm, c->cfg.box,
                       (float)c->kick[i], c->drift[i], key_nm, c->stream);
   }
@@ -772,15 +778,16 @@ int pmr_set_noise_table(pmr_ctx* c, int n_nodes, const double* log_mass, const d
     h[NOISE_MAX + j] = mu[j];
     h[2 * NOISE_MAX + j] = sigma[j];
   }
-  // pageable source: the copy completes before this call returns
-  HIPC(c, hipMemcpyAsync(c->noise_tab, h.data(), h.size() * sizeof(double),
-                         hipMemcpyHostToDevice, c->stream));
-  HIPC(c, hipStreamSynchronize(c->stream));
+  // the table travels as kernel arguments: stream-ordered, no wait for the host
+  launch_noise_table_store(h.data(), c->noise_tab, c->stream);
   c->noise_k = n_nodes;
   c->xd_dirty = 1;
   refresh_xd(c);
   return check(c);
 }
+
+static_assert(sizeof(pmr_loss_params) == PMR_LOSS_FIELDS * sizeof(double),
+              "pmr_loss_params is read on the device as consecutive doubles");
 
 int pmr_set_loss(pmr_ctx* c, const pmr_loss_params* prm) {
   if (!c || !prm) return PMR_E_INVALID;
@@ -800,15 +807,29 @@ int pmr_set_loss(pmr_ctx* c, const pmr_loss_params* prm) {
     d[4] = q.R_sm;
     d[5] = q.prior_weight;
     d[6] = q.logistic_a;
+    d[PRM_VALID] = 1.0;
   }
-  // pageable source: the copy completes before this call returns
-  HIPC(c, hipMemcpyAsync(c->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPC(c, hipStreamSynchronize(c->stream));
+  // the values travel as kernel arguments: stream-ordered, no wait for the host
+  launch_params_store(h.data(), c->B, c->params, c->stream);
   c->have_loss = 1;
   c->xd_dirty = 1;
   refresh_xd(c);
   return check(c);
 }
+
+int pmr_set_loss_device(pmr_ctx* c, const pmr_loss_params* params_device) {
+  if (!c || !params_device) return PMR_E_INVALID;
+  if (((uintptr_t)params_device & 7) != 0) return PMR_E_INVALID;
+  launch_params_from_device((const double*)params_device, c->B,
+                            c->cfg.loss_kind == PMR_LOSS_DENSITY_L2,
+                            c->cfg.halo_model == PMR_HALO_TWO, c->params, c->stream);
+  c->have_loss = 1;
+  c->xd_dirty = 1;
+  refresh_xd(c);
+  return check(c);
+}
+
+long long pmr_forward_count(const pmr_ctx* c) { return c ? c->n_forward : PMR_E_INVALID; }
 
 int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out) {
   if (!c || !modes || !loss_out) return PMR_E_INVALID;
@@ -847,9 +868,12 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   pm_run(c, 0, c->n, true);
   // H8: final paint on the output mesh
   const int total = (int)(B * c->np3);
-  launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch, c->frac_id,
-              c->frac_o, s, nullptr, ScatterProbeOf(c).get());
-  launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
+  {
+    ProfScope ps(c, PMR_PROF_SORT, 0.0);
+    launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch,
+                c->frac_id, c->frac_o, s, nullptr, ScatterProbeOf(c).get());
+    launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
+  }
   launch_paint_mass(c->keys_sorted, c->frac_o, c->rows_o, B, c->no, c->mass_o, 1.f, c->delta_f, s);
   // H9-H11: halo model and likelihood
   if (c->cfg.loss_kind == PMR_LOSS_DENSITY_L2) {
@@ -874,6 +898,8 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
       launch_halo2_fwd(c->delta_f, c->dR, c->dR + (size_t)B * no3, c->log_no, (size_t)B * no3,
                        c->halo2_w, c->params, c->h2aux, c->h2sgn, c->mass, s);
     } else {
+      const double Hd = c->H;
+      ProfScope ps(c, PMR_PROF_NETWORK, 2.0 * (4.0 * Hd + Hd * Hd) * B * no3);
       const int rc = c->cfg.precision == PMR_MIXED
                          ? launch_mlp_fwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3,
                                                (size_t)B * no3, c->mlp_w, c->mass, s)
@@ -890,6 +916,7 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   }
   launch_finalize_loss(c->prior, c->data, c->params, B, loss_out, s);
   c->fwd_done = 1;
+  ++c->n_forward;
   const int st = check(c);
   if (st != PMR_OK || !c->check_finite) return st;
   std::vector<double> h(3 * (size_t)B);
@@ -936,12 +963,16 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       // compulsory: u (81 floats) read, three adjoint fields read and written, per voxel
       ProfScope ps(c, PMR_PROF_HALO2_STENCIL, (81.0 * 4 + 24.0) * B * no3);
       launch_halo2_stencil_adj(c->u2, c->log_no, (size_t)B * no3, o0, o1, dbar_f, s);
-    } else if (c->cfg.precision == PMR_MIXED)
-      launch_mlp_bwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,
-                          c->mlp_w, o2, o0, o1, dbar_f, s);
-    else
-      launch_mlp_bwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3, c->mlp_w,
-                     o2, o0, o1, dbar_f, s);
+    } else {
+      const double Hd = c->H;
+      ProfScope ps(c, PMR_PROF_NETWORK, 2.0 * (8.0 * Hd + 2.0 * Hd * Hd) * B * no3);
+      if (c->cfg.precision == PMR_MIXED)
+        launch_mlp_bwd_mfma(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,
+                            c->mlp_w, o2, o0, o1, dbar_f, s);
+      else
+        launch_mlp_bwd(c->H, c->delta_f, c->dR, c->dR + (size_t)B * no3, (size_t)B * no3,
+                       c->mlp_w, o2, o0, o1, dbar_f, s);
+    }
     // g0 -> o0, g12 -> o1, g2 -> dbar_f (temporarily); feature adjoint:
     // dbar_f = g0 + irfft(G1 rfft(g12) - G2 rfft(g2))
     const size_t po = spec_pitch(c->no);

@@ -140,8 +140,17 @@ enum XOp : int {
 };
 
 // Loss parameters per batch item in device memory (doubles):
-// M0, mu, sigma_N, R_mass, R_sm, prior_weight, logistic_a.
-constexpr int NPRM = 7;
+// M0, mu, sigma_N, R_mass, R_sm, prior_weight, logistic_a (the fields of the public struct,
+// PMR_LOSS_FIELDS of them), then a validity slot (1: the item's values passed the checks).
+constexpr int PMR_LOSS_FIELDS = 7;
+constexpr int PRM_VALID = 7;
+constexpr int NPRM = 8;
+// Items per launch of the kernel that stores host parameters from its arguments.
+constexpr int PRM_CHUNK = 32;
+struct ParamChunk {
+  double v[PRM_CHUNK * NPRM];
+  int b0, count;
+};
 
 struct XPassArgs {
   int n;            // points per axis
@@ -284,6 +293,15 @@ void launch_mrbar(const float* rbar, const float* mr, size_t per_item, int batch
                   const double* prm, const float* nw, float* out, hipStream_t s);
 // Per-cell noise offset and 1 / (2 sigma) from the interpolation table (k nodes).
 constexpr int NOISE_MAX = 64;
+struct NoiseTable {
+  double v[3 * NOISE_MAX];
+};
+// Loss parameters: from a host array of [batch][NPRM] doubles (passed as kernel arguments:
+// no staging, no wait), or from device memory as the public struct array (checked there).
+void launch_params_store(const double* host, int batch, double* prm, hipStream_t s);
+void launch_params_from_device(const double* src, int batch, int density_l2, int halo_two,
+                               double* prm, hipStream_t s);
+void launch_noise_table_store(const double* host, double* tab, hipStream_t s);
 void launch_noise_fields(const float* mrd, size_t total, const double* tab, int k, float* nmu,
                          float* nw, hipStream_t s);
 void launch_l2_adj(const float* d, const float* t, size_t per_item, int batch,

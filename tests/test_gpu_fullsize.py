@@ -150,3 +150,114 @@ def test_full_128_paper_model_item0_against_oracle():
     assert err["grad_cos"] >= 0.9999 and err["grad_rel_l2"] <= 1e-2
     assert err["final_max_dx_cells"] <= 1e-3
     assert err["final_cell_mismatch_frac"] <= 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_full_512_force_mesh_and_first_step_against_oracle():
+    """256^3 particles on the 512^3 force mesh (the benchmark's launch size, FP32, batch 1),
+    element by element against the FP64 oracle from the GPU's own x0 (so that both sides take
+    every CIC cell decision from the same FP64 positions): the step-0 force mesh (paint,
+    r2c, force operator and c2r on the 512 mesh), then the first kick and drift on a sample
+    of 2^20 particles (readout of that mesh), the final density contrast on the 256^3 output
+    mesh, and the stand-alone paint of the evolved (clustered) positions on the 512 mesh."""
+    from oracle import cosmology as OC
+    from oracle import mesh as M
+    from oracle import model as OM
+    require_gpu()
+    w = dict(bench.WORKLOADS["p256_m512"])
+    n, nm, box, steps = w["n_part"], w["n_mesh"], w["box"], w["n_steps"]
+    say("full size: 256^3 on 512^3 FP32, forward (positions and force slots kept)")
+    pm, modes = bench.make_context(dict(w, precision=P.PMR_FP32, ckpt_every=0), DEV)
+    pm.forward(modes, want_mass=False)
+    x0 = pm.debug("x", 0).cpu().numpy()[0]
+    x1 = pm.debug("x", 1).cpu().numpy()[0]
+    xn = pm.debug("x", steps)
+    F0 = pm.debug("force", 0).cpu().numpy()[0]  # [nm^3][3]
+    dfin = pm.debug("delta_f").cpu().numpy()[0].astype(np.float64)
+    s = modes[0].cpu().numpy().astype(np.complex128).reshape(n, n, n // 2 + 1)
+    del pm
+    torch.cuda.empty_cache()
+
+    say("  stand-alone paint of the evolved positions on the 512 mesh (pmr_cic_sort + paint)")
+    keys, ids, rows = P.cic_sort(xn, nm, box)
+    dpaint = P.cic_paint(xn, keys, ids, rows, nm, box, mass=(nm / n) ** 3, bias=1.0)
+    dpaint = dpaint.cpu().numpy()[0].astype(np.float64)
+    xn = xn.cpu().numpy()[0]
+    ocfg = OM.Config(box, n, nm, n, steps)
+
+    say("  oracle: paint of x_n on 512 and 256")
+    e = rel_l2(dpaint, OM.density(ocfg, xn, nm).ravel())
+    say(f"  paint 512 rel-L2 {e:.2e}")
+    assert e <= 1e-6
+    e = rel_l2(dfin, OM.density(ocfg, xn, n).ravel())
+    say(f"  final delta on the 256 output mesh rel-L2 {e:.2e}")
+    assert e <= 1e-6
+
+    say("  oracle: force mesh at x0 (paint, r2c, i k / k^2, three c2r on 512^3)")
+    F = OM.force_meshes(ocfg, OM.density(ocfg, x0, nm))
+    for a in range(3):
+        e = rel_l2(F0[:, a], F[a].ravel())
+        say(f"  F_{'xyz'[a]} rel-L2 {e:.2e}")
+        assert e <= 1e-5
+
+    say("  oracle: first kick and drift on 2^20 sampled particles")
+    pick = np.sort(np.random.default_rng(11).choice(n ** 3, 1 << 20, replace=False))
+    _, p0, _ = OM.zeldovich(OM.Config(box, n, nm, n, steps), s)
+    xs = x0[:, pick]
+    fr = M.cic_readout(xs, nm, box, F)
+    ph = p0[:, pick] + ocfg.fac["kick"][0] * fr
+    x1_ref = M.wrap(xs + ocfg.fac["drift"][0] * ph, box)
+    d = (x1[:, pick] - x1_ref + box / 2) % box - box / 2
+    dx = float(np.abs(d).max() / (box / nm))
+    say(f"  x1 max |dx| {dx:.2e} cells")
+    assert dx <= 1e-4
+
+
+def test_batch32_of_64cube_items_against_oracle_and_graph():
+    """32 realisations of 64^3 on a 64^3 mesh (L = 200 Mpc/h, 5 steps, the 3-32-32-1 network,
+    FP32) in one launch: items 0 and 31 against the FP64 oracle (seeded log-normal data,
+    per-item M0 and R_sm), then the whole gradient captured as a HIP graph replays bit for
+    bit what the eager calls compute (3 replays with eager work in between)."""
+    from oracle import cosmology as OC
+    from oracle import model as OM
+    require_gpu()
+    w = bench.WORKLOADS["p64_m64_b32"]
+    B, n, box, steps = w["batch"], w["n_part"], w["box"], w["n_steps"]
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    mlp = synth.mlp_weights(3, w["mlp_hidden"])
+    white = [synth.white_noise(100 + b, n) for b in range(B)]
+    targets = [np.exp(0.5 * synth.unit_normal(200 + b, (n, n, n))) for b in range(B)]
+    R = (4.0, 2.0, 1.0, 0.0)
+    params = [OM.default_params(M0=float(np.median(targets[b])), R_sm=R[b % 4]) for b in range(B)]
+    say("batch 32 x 64^3: GPU gradient of all items")
+    cfg = P.Config(batch=B, n_part=n, n_mesh=n, n_out=n, n_steps=steps,
+                   mlp_hidden=w["mlp_hidden"], box=box)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in mlp.items()})
+    pm.set_target(torch.from_numpy(np.stack(targets).astype(np.float32)).reshape(B, -1))
+    pm.set_loss([P.LossParams(**p) for p in params])
+    modes = torch.from_numpy(np.stack([OM.linear_modes(wn, box, power) for wn in white])
+                             .astype(np.complex64).reshape(B, -1)).to(DEV)
+    loss, g = _gradient(pm, modes)
+    x = pm.debug("x", steps).cpu().numpy()
+    ocfg = OM.Config(box, n, n, n, steps)
+    for b in (0, B - 1):
+        s = modes[b].cpu().numpy().astype(np.complex128).reshape(n, n, n // 2 + 1)
+        fwd, G = OM.gradient(ocfg, s, inv, targets[b], params[b], mlp)
+        err = bench.error_vs(fwd["loss"], G, fwd["xs"][-1], float(loss[b, 0]),
+                             g[b].cpu().numpy().astype(np.complex128), x[b], box=box, n_mesh=n)
+        say(f"  item {b}: " + ", ".join(f"{k}={v:.3e}" for k, v in err.items()))
+        assert err["loss_rel"] <= 1e-5
+        assert err["grad_cos"] >= 0.9999 and err["grad_rel_l2"] <= 1e-3
+        assert err["final_max_dx_cells"] <= 1e-4
+    say("batch 32 x 64^3: graph replays against eager")
+    ref_loss, ref_g = loss.copy(), g.clone()
+    G = P.GradientGraph(pm, modes)
+    for rep in range(3):
+        gl, gg = G.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(gl.cpu().numpy(), ref_loss), rep
+        assert torch.equal(gg, ref_g), rep
+        _gradient(pm, modes)  # eager work between replays

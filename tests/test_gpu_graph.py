@@ -63,3 +63,52 @@ def test_graph_replay_matches_eager():
     ref2 = eager(m0)
     assert torch.equal(loss, ref2[0]) and torch.equal(grad, ref2[1])
     assert not torch.equal(ref2[0], ref0[0])
+
+
+def test_graph_with_device_loss_params():
+    """Loss parameters captured from device memory (pmr_set_loss_device inside the graph):
+    new anneal-stage values written into the device buffer between replays give, bit for bit,
+    the eager gradient at those values (set through the host call), without recapture; an
+    invalid item (sigma_N = 0) gives a NaN loss for that item only."""
+    require_gpu()
+    n, box, B = 32, 100.0, 2
+    say("graph: device loss parameters, stage changes between replays")
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    w = synth.mlp_weights(3, 16)
+    cfg = P.Config(batch=B, n_part=n, n_mesh=n, n_out=n, n_steps=3, mlp_hidden=16, box=box)
+    pm = P.PMContext(cfg, DEV)
+    pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+    pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+    tgt = np.stack([np.exp(synth.unit_normal(50 + b, (n, n, n))) for b in range(B)])
+    pm.set_target(torch.from_numpy(tgt.astype(np.float32)).reshape(B, -1))
+    stages = [[P.LossParams(M0=1.0, R_sm=4.0), P.LossParams(M0=1.5, R_sm=2.0)],
+              [P.LossParams(M0=0.8, R_sm=1.0), P.LossParams(M0=1.1, R_sm=0.0)],
+              [P.LossParams(M0=1.3, R_sm=0.0, R_mass=2.0), P.LossParams(M0=0.7, R_sm=1.0)]]
+    pm.set_loss(stages[0])
+    m = torch.from_numpy(OM.linear_modes(synth.white_noise(3, n), box, power)
+                         .astype(np.complex64).reshape(1, -1)).repeat(B, 1).to(DEV)
+
+    def eager(prm):
+        pm.set_loss(prm)
+        _, loss = pm.forward(m, want_mass=False)
+        g = pm.adjoint(torch.ones(B, dtype=torch.float64, device=DEV))
+        torch.cuda.synchronize()
+        return loss.clone(), g.clone()
+
+    refs = [eager(st) for st in stages]
+    G = P.GradientGraph(pm, m, params=stages[0])
+    for rep, k in enumerate((0, 1, 2, 1, 0)):
+        G.set_params(stages[k])
+        loss, grad = G.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(loss, refs[k][0]), (rep, k)
+        assert torch.equal(grad, refs[k][1]), (rep, k)
+        eager(stages[(k + 1) % 3])  # eager work between replays
+    bad = [P.LossParams(M0=1.0, R_sm=4.0, sigma_N=0.0), stages[0][1]]
+    G.set_params(bad)
+    loss, _ = G.replay()
+    torch.cuda.synchronize()
+    lv = loss.cpu().numpy()
+    assert np.all(np.isnan(lv[0])) and np.all(np.isfinite(lv[1]))
+    assert np.array_equal(lv[1], refs[0][0].cpu().numpy()[1])

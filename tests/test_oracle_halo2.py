@@ -1,5 +1,5 @@
-"""Oracle pins for the paper's two-network halo model (Sec. 2.1: model = NNp x NNm;
-Sec. 2.3: NNp 81 -> 50 -> 30 -> 1 with ReLU and a sharpened logistic, NNm 3 -> 20 -> 10
+"""Oracle pins for the paper's two-network halo model (Sec. 2: model = NNp x NNm;
+Sec. 2.1: NNp 81 -> 50 -> 30 -> 1 with ReLU and a sharpened logistic, NNm 3 -> 20 -> 10
 -> 1 with ELU and a linear output; Sec. 2.2: NNp sees the three feature fields on the
 3 x 3 x 3 neighbourhood of the voxel)."""
 import math
