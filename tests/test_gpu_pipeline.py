@@ -103,8 +103,15 @@ def _compare(ocfg, inv, modes, w, targets, params, res, tol, refs=None):
                 assert out[k] <= lim, (k, out[k])
 
 
-TOL_FP32 = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "loss": 1e-4, "prior": 1e-5, "mass": 1e-4,
-            "grad_cos": 0.9999, "grad_rel": 1e-2}
+# FP32 path against the FP64 oracle (measured: loss <= 5e-7, gradient rel-L2 <= 2.3e-5 on
+# every case below except the two small two-network meshes).
+TOL_FP32 = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "loss": 1e-5, "prior": 1e-5, "mass": 1e-4,
+            "grad_cos": 0.9999, "grad_rel": 1e-3}
+# The two-network model on 16^3 particles: a few voxels have a ReLU pre-activation within
+# ~1e-6 of zero, where the FP32 sum may take the other side of the kink than the FP64 oracle
+# and that voxel's derivative changes (measured gradient rel-L2 7.8e-3 on the 32^3 meshes,
+# 1.0e-3 on the 16^3 mesh; cosine 0.99997).
+TOL_FP32_KINK = dict(TOL_FP32, grad_rel=1e-2)
 
 
 def test_density_l2_small_box():
@@ -209,8 +216,10 @@ def test_run_to_run_bitwise():
     assert np.array_equal(a["mass"], b["mass"])
 
 
-TOL_MIXED = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "prior": 1e-5, "loss": 3e-3, "mass": 2e-2,
-             "grad_cos": 0.999, "grad_rel": 5e-2}
+# BF16 network with FP32 accumulation (measured: loss <= 2.9e-4, mass <= 1.8e-3, gradient
+# rel-L2 <= 1.4e-3).
+TOL_MIXED = {"max_dx_cells": 1e-4, "delta_f": 1e-4, "prior": 1e-5, "loss": 1e-3, "mass": 2e-2,
+             "grad_cos": 0.999, "grad_rel": 3e-2}
 
 
 @pytest.mark.parametrize("hidden", [32, 64])
@@ -357,7 +366,7 @@ def test_two_network_halo_model_on_the_force_mesh():
     say("pipeline: two-network halo model 16^3 particles, 32^3 meshes")
     prob = _two_net_problem(16, 32, 60.0, 3, 1, (1.0,), (2.0,), seed=6)
     res = _gpu_run(*prob)
-    _compare(*prob, res, TOL_FP32)
+    _compare(*prob, res, TOL_FP32_KINK)
 
 
 def test_second_order_lpt_with_two_networks_64():
@@ -432,7 +441,7 @@ def test_two_network_smallest_mesh_odd_batch():
     ocfg, inv, modes, nets, targets, params = _two_net_problem(16, 16, 50.0, 3, 3,
                                                                 (0.0, 1.0, 2.0), (1.0, 2.0, 3.0))
     res = _gpu_run(ocfg, inv, modes, nets, targets, params)
-    _compare(ocfg, inv, modes, nets, targets, params, res, TOL_FP32)
+    _compare(ocfg, inv, modes, nets, targets, params, res, TOL_FP32_KINK)
 
 
 def test_two_network_state_and_argument_errors():
