@@ -282,6 +282,17 @@ enum { PMR_FFT_YPASS = 0, PMR_FFT_XPASS = 1, PMR_FFT_XPASS_MULTI = 2 };
 int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging);
 int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging);
 
+/* Slab width of the force transforms of the PM steps on an n^3 mesh (process-wide; the
+ * autotuner sets it): with `columns` > 0 the middle-axis pass, the outermost-axis pass with
+ * its k-space operator and the inverse middle-axis pass run window by window of that many kz
+ * columns (rounded up to a multiple of every strided pass's tile columns), so that a
+ * window's spectra stay in the memory-side cache between the three passes; 0 runs each pass
+ * over the whole half spectrum. The results are the same bit for bit. `columns`: 0 or a
+ * power of two up to 512; PMR_E_INVALID otherwise. Default 0. Not synchronised with work in
+ * flight: set it before enqueueing. */
+int pmr_fft_set_slab(int n, int columns);
+int pmr_fft_get_slab(int n, int* columns);
+
 /* Bytes of scratch for pmr_cic_sort with `n_particles` in total and `batch` items. */
 size_t pmr_sort_scratch_bytes(int n_particles_total, int n_mesh, int batch);
 

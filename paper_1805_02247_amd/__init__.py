@@ -8,6 +8,6 @@ from ._lib import (PMR_FP32, PMR_MIXED, PMR_LOSS_DENSITY_L2,  # noqa: F401
                    PMR_FFT_XPASS, PMR_FFT_XPASS_MULTI, PMR_E_STATE, PMR_E_NONFINITE,
                    PmrError)
 from .api import (Config, GradientGraph, LossParams, PMContext, PMForward,  # noqa: F401
-                  cic_paint, cic_sort, fft_c2r, fft_get_tile, fft_r2c, fft_set_tile,
-                  workspace_bytes)
+                  cic_paint, cic_sort, fft_c2r, fft_get_slab, fft_get_tile, fft_r2c,
+                  fft_set_slab, fft_set_tile, workspace_bytes)
 from . import recon  # noqa: F401,E402

@@ -75,6 +75,8 @@ SIGNATURES = {
     "pmr_cic_paint": (ci, [ci, ci, ci, cd, vp, vp, vp, vp, cf, cf, vp, vp, sz, vp]),
     "pmr_fft_set_tile": (ci, [ci, ci, ci, ci, ci]),
     "pmr_fft_get_tile": (ci, [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
+    "pmr_fft_set_slab": (ci, [ci, ci]),
+    "pmr_fft_get_slab": (ci, [ci, ctypes.POINTER(ci)]),
     "pmr_vec_work_bytes": (sz, [sz, ci]),
     "pmr_vec_dot": (ci, [sz, vp, vp, vp, vp, vp]),
     "pmr_vec_axpby": (ci, [sz, cd, vp, cd, vp, vp, vp]),

@@ -292,6 +292,17 @@ def fft_set_tile(n, pass_, columns, threads, staging):
     L.check(L.lib().pmr_fft_set_tile(n, pass_, columns, threads, staging))
 
 
+def fft_get_slab(n):
+    """kz-slab width of the force transforms on an n^3 mesh (0: off)."""
+    c = ctypes.c_int()
+    L.check(L.lib().pmr_fft_get_slab(n, ctypes.byref(c)))
+    return c.value
+
+
+def fft_set_slab(n, columns):
+    L.check(L.lib().pmr_fft_set_slab(n, columns))
+
+
 def fft_r2c(x):
     """Unnormalised 3-D real FFT of [B][n][n][n] float32 -> complex64 [B][n][n][n/2+1]."""
     B, n = x.shape[0], x.shape[-1]

@@ -25,42 +25,42 @@ void fft_zr2c_16(int, const float*, FieldMap, const float*, float, float, const 
 void fft_zc2r_16(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_16(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_16(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_16(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_16(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_16(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_32(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_32(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_32(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_32(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_32(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_32(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_32(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_64(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_64(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_64(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_64(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_64(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_64(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_64(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_128(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_128(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_128(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_128(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_128(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_128(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_128(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_256(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_256(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_256(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_256(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_256(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_256(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_256(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_512(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_512(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
 void fft_zc2r3_512(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_512(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
-void fft_ypass_512(int, float2*, FieldMap, bool, hipStream_t);
+void fft_ypass_512(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_512(int, const XPassArgs&, hipStream_t);
 
 #define PMR_FOR_N(MACRO) \
@@ -110,10 +110,11 @@ void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2
   }
 }
 
-void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s) {
+void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s,
+                  KzWin win) {
   switch (n) {
 #define CASE(NN) \
-  case NN: fft_ypass_##NN(fields, data, m, inverse, s); break;
+  case NN: fft_ypass_##NN(fields, data, m, inverse, s, win); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;
@@ -129,6 +130,35 @@ int set_fft_tile(int n, int pass, int pc, int nth, int lds) {
   if (lds != 0 && lds != 1) return -1;
   g_fft_tile[pass][log2i(n)] = {pc, nth, lds};
   return 0;
+}
+
+int g_fft_slab[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+int set_fft_slab(int n, int columns) {
+  if (n < 16 || n > 512 || (n & (n - 1))) return -1;
+  if (columns < 0 || columns > 512 || (columns & (columns - 1))) return -1;
+  g_fft_slab[log2i(n)] = columns;
+  return 0;
+}
+
+int get_fft_slab(int n) { return g_fft_slab[log2i(n)]; }
+
+// Columns of the kz window in which the y and x passes of one transform run back to back
+// (0: each pass over the whole half spectrum): the requested width rounded up to a multiple
+// of the column count of every strided pass at this size (all are powers of two), so that
+// no chunk straddles two windows.
+int fft_slab_columns(int n) {
+  const int want = g_fft_slab[log2i(n)];
+  if (want <= 0) return 0;
+  int w = want;
+  for (int pass = 0; pass < 3; ++pass) {
+    const TileShape t = g_fft_tile[pass][log2i(n)];
+    const bool ok = t.pc >= 8 && t.pc <= 32 && n * t.pc >= t.nth &&
+                    (n * t.pc + n) * 8 <= 160 * 1024 && n * t.pc / t.nth <= 16;
+    const int pc = ok ? t.pc : 16;  // the dispatch falls back to 16 columns
+    if (pc > w) w = pc;
+  }
+  return w >= n / 2 + 1 ? 0 : w;
 }
 
 void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds) {

@@ -570,14 +570,13 @@ __device__ __forceinline__ void regs_to_lds(const TileRegs<N, PC, NTH, V>& t, fl
 // prefetching the next tile into registers.
 template <int N, int DIR, int PC, int NTH, int V>
 __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, FieldMap m,
-                                                    int ntiles) {
+                                                    int ntiles, int ch0, int nchw) {
   constexpr int NH = N / 2 + 1;
-  constexpr int NCH = (NH + PC - 1) / PC;
   __shared__ __attribute__((aligned(16))) float2 lds[N * PC];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
   auto tile_base = [&](int tau, int& ncols) {
-    const int ch = tau % NCH, rest = tau / NCH;
+    const int ch = ch0 + tau % nchw, rest = tau / nchw;
     const int ix = rest % N, f = rest / N;
     ncols = min(PC, NH - ch * PC);
     return data + m.off(f) + (size_t)ix * N * m.pitch + ch * PC;
@@ -676,9 +675,8 @@ constexpr bool spectral_input() {
 }
 
 template <int N, int OP, int PC, int NTH, int V>
-__global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
+__global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int ch0, int nchw) {
   constexpr int NH = N / 2 + 1;
-  constexpr int NCH = (NH + PC - 1) / PC;
   constexpr int NE = N * PC;
   constexpr int PER = NE / NTH;
   static_assert(NE % NTH == 0, "tile");
@@ -696,13 +694,13 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   TileRegs<N, PC, NTH, V> pre;  // the next input to transform (prefetched)
   {
-    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
     load_regs<N, PC, NTH, V>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0,
                           istride, min(PC, NH - kz0));
   }
   for (;;) {
-    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
     const size_t ioff = item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0;
@@ -723,7 +721,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles) {
       if (i + 1 < n_in) {
         load_regs<N, PC, NTH, V>(pre, a.in[i + 1] + ioff, istride, ncols);
       } else if (next < ntiles) {
-        const int nch = next % NCH, niy = (next / NCH) % N, nit = next / (NCH * N);
+        const int nch = ch0 + next % nchw, niy = (next / nchw) % N, nit = next / (nchw * N);
         const int nkz0 = nch * PC;
         load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
                               istride, min(PC, NH - nkz0));
@@ -1012,9 +1010,8 @@ __device__ __forceinline__ void reg_slot(int q, int& pos, int& l) {
 
 template <int N, int DIR, int PC, int NTH>
 __global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ data, FieldMap m,
-                                                        int ntiles) {
+                                                        int ntiles, int ch0, int nchw) {
   constexpr int NH = N / 2 + 1;
-  constexpr int NCH = (NH + PC - 1) / PC;
   constexpr int P = N * PC / NTH;
   constexpr bool REV = DIR > 0;
   using PL = RPlan<N, REV>;
@@ -1023,7 +1020,7 @@ __global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ dat
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
   auto tile_base = [&](int tau, int& ncols) {
-    const int ch = tau % NCH, rest = tau / NCH;
+    const int ch = ch0 + tau % nchw, rest = tau / nchw;
     const int ix = rest % N, f = rest / N;
     ncols = min(PC, NH - ch * PC);
     return data + m.off(f) + (size_t)ix * N * m.pitch + ch * PC;
@@ -1054,9 +1051,9 @@ __global__ __launch_bounds__(NTH) void ypass_reg_kernel(float2* __restrict__ dat
 }
 
 template <int N, int OP, int PC, int NTH>
-__global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles) {
+__global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles, int ch0,
+                                                        int nchw) {
   constexpr int NH = N / 2 + 1;
-  constexpr int NCH = (NH + PC - 1) / PC;
   constexpr int P = N * PC / NTH;
   using PF = RPlan<N, false>;
   using PI = RPlan<N, true>;
@@ -1076,7 +1073,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   constexpr int n_out = xpass_outputs<OP>();
 
   auto in_base = [&](int tau, int i, int& ncols) {
-    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     ncols = min(PC, NH - ch * PC);
     return a.in[i] + item * a.in_item_stride + (size_t)iy * a.in_pitch + ch * PC;
   };
@@ -1089,7 +1086,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles)
   }
   __syncthreads();  // twiddles
   for (;;) {
-    const int ch = tau % NCH, iy = (tau / NCH) % N, item = tau / (NCH * N);
+    const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
     const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
@@ -1241,17 +1238,31 @@ int tile_grid(int ntiles) {
   return ntiles < res ? ntiles : res;
 }
 
+// Chunks [ch0, ch0 + nchw) of PC columns covering the kz window [lo, hi) (hi = 0: the whole
+// half spectrum); lo is a multiple of PC (the caller picks windows on multiples of every
+// pass's column count).
+template <int N, int PC>
+__host__ inline void kz_chunks(int lo, int hi, int& ch0, int& nchw) {
+  constexpr int NH = N / 2 + 1;
+  const int h = (hi > 0 && hi < NH) ? hi : NH;
+  ch0 = lo / PC;
+  nchw = (h + PC - 1) / PC - ch0;
+}
+
 template <int N, int PC, int NTH>
-void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t s) {
-  const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * fields;
+void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t s, KzWin win) {
+  int ch0, nchw;
+  kz_chunks<N, PC>(win.lo, win.hi, ch0, nchw);
+  if (nchw <= 0) return;
+  const int ntiles = nchw * N * fields;
   if constexpr (reg_ok<N, PC, NTH>()) {
     if (!lds) {
       if (inv) {
         constexpr auto k = ypass_reg_kernel<N, +1, PC, NTH>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
       } else {
         constexpr auto k = ypass_reg_kernel<N, -1, PC, NTH>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
       }
       return;
     }
@@ -1260,30 +1271,33 @@ void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t 
     if (m.pitch % 2 == 0) {
       if (inv) {
         constexpr auto k = ypass_kernel<N, +1, PC, NTH, 2>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
       } else {
         constexpr auto k = ypass_kernel<N, -1, PC, NTH, 2>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
       }
       return;
     }
   }
   if (inv) {
     constexpr auto k = ypass_kernel<N, +1, PC, NTH, 1>;
-    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
   } else {
     constexpr auto k = ypass_kernel<N, -1, PC, NTH, 1>;
-    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles);
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
   }
 }
 
 template <int N, int OP, int PC, int NTH>
 void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
-  const int ntiles = ((N / 2 + 1 + PC - 1) / PC) * N * a.batch;
+  int ch0, nchw;
+  kz_chunks<N, PC>(a.kz_lo, a.kz_hi, ch0, nchw);
+  if (nchw <= 0) return;
+  const int ntiles = nchw * N * a.batch;
   if constexpr (reg_ok<N, PC, NTH>()) {
     if (!lds) {
       constexpr auto k = xpass_reg_kernel<N, OP, PC, NTH>;
-      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
+      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
       return;
     }
   }
@@ -1291,12 +1305,12 @@ void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
                 OP != XOP_HESS_ADJ) {
     if (a.in_pitch % 2 == 0 && a.out_pitch % 2 == 0) {
       constexpr auto k = xpass_kernel<N, OP, PC, NTH, 2>;
-      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
+      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
       return;
     }
   }
   constexpr auto k = xpass_kernel<N, OP, PC, NTH, 1>;
-  k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles);
+  k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
 }
 
 // Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
@@ -1309,17 +1323,17 @@ constexpr bool shape_ok(int pc, int nth) {
 #define PMR_FOR_SHAPE(M) M(8, 256) M(16, 256) M(32, 256) M(8, 512) M(16, 512) M(32, 512)
 
 template <int N>
-void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s) {
+void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s, KzWin win) {
   const TileShape t = g_fft_tile[0][log2i(N)];
 #define SHAPE(PC, NTH)                                        \
   if constexpr (shape_ok<N>(PC, NTH))                         \
     if (t.pc == PC && t.nth == NTH) {                         \
-      ypass_t<N, PC, NTH>(fields, d, m, inv, t.lds, s);       \
+      ypass_t<N, PC, NTH>(fields, d, m, inv, t.lds, s, win);  \
       return;                                                 \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE
-  ypass_t<N, 16, 256>(fields, d, m, inv, t.lds, s);
+  ypass_t<N, 16, 256>(fields, d, m, inv, t.lds, s, win);
 }
 
 // Multi-input operators hold three register images (accumulator, current, prefetch); at

@@ -35,8 +35,8 @@ void PMR_CAT(fft_paint_r2c_, PMR_FFT_SIZE)(int channels, const PaintArgs& a, int
 }
 
 void PMR_CAT(fft_ypass_, PMR_FFT_SIZE)(int fields, float2* d, FieldMap m, bool inv,
-                                       hipStream_t s) {
-  ypass<PMR_FFT_SIZE>(fields, d, m, inv, s);
+                                       hipStream_t s, KzWin win) {
+  ypass<PMR_FFT_SIZE>(fields, d, m, inv, s, win);
 }
 
 void PMR_CAT(fft_xpass_, PMR_FFT_SIZE)(int op, const XPassArgs& a, hipStream_t s) {

@@ -487,6 +487,26 @@ void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_com
   }
 }
 
+// The kz windows of a transform on an n^3 mesh: one window of the whole half spectrum, or
+// consecutive slabs of fft_slab_columns(n) columns.
+std::vector<KzWin> kz_windows(int n) {
+  const int w = fft_slab_columns(n), nh = n / 2 + 1;
+  std::vector<KzWin> v;
+  if (w <= 0) {
+    v.push_back(KzWin{});
+    return v;
+  }
+  for (int lo = 0; lo < nh; lo += w) v.push_back(KzWin{lo, lo + w < nh ? lo + w : nh});
+  return v;
+}
+
+// Share of the half spectrum's columns in a window (for the algorithmic bytes of a launch).
+double window_share(int n, const KzWin& win) {
+  const int nh = n / 2 + 1;
+  const int hi = win.hi > 0 && win.hi < nh ? win.hi : nh;
+  return (double)(hi - win.lo) / nh;
+}
+
 // Gaussian smoothing of a real field [B][n^3] on R (per item, params[param_index]).
 void smooth(pmr_ctx* c, int n, const float* in, int param_index, float* out, const float* add,
             const double* scale = nullptr, float a1 = 1.f) {
@@ -612,23 +632,39 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
                                           rowslot(c, fsl), c->nm, c->mass_m, 1.f),
                      B, c->cA, dm, c->stream);
   }
-  {
-    ProfScope ps(c, PMR_PROF_YPASS, 16.0 * B * c->cm);
-    launch_ypass(c->nm, B, c->cA, dm, false, c->stream);
-  }
-  XPassArgs a = xargs(c, c->nm);
-  a.n_in = 1;
-  a.n_out = 3;
-  a.in[0] = c->cA;
-  for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cm;
-  a.in_item_stride = cm;
-  a.out_item_stride = 3 * cm;
-  {
-    ProfScope ps(c, PMR_PROF_XPASS_FORCE, 32.0 * B * c->cm);
-    launch_xpass(XOP_FORCE, a, c->stream);
+  // y forward, x pass with the force operator, y inverse of the three components: window by
+  // window of kz columns when slabs are on, so that each window's spectra stay in the
+  // memory-side cache between the three passes
+  const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
+  for (const KzWin& win : kz_windows(c->nm)) {
+    const double part = window_share(c->nm, win);
+    {
+      ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
+      launch_ypass(c->nm, B, c->cA, dm, false, c->stream, win);
+    }
+    XPassArgs a = xargs(c, c->nm);
+    a.n_in = 1;
+    a.n_out = 3;
+    a.in[0] = c->cA;
+    for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cm;
+    a.in_item_stride = cm;
+    a.out_item_stride = 3 * cm;
+    a.kz_lo = win.lo;
+    a.kz_hi = win.hi;
+    {
+      ProfScope ps(c, PMR_PROF_XPASS_FORCE, part * 32.0 * B * c->cm);
+      launch_xpass(XOP_FORCE, a, c->stream);
+    }
+    {
+      ProfScope ps(c, PMR_PROF_YPASS, part * 3 * 16.0 * B * c->cm);
+      launch_ypass(c->nm, 3 * B, c->cB, fm3, true, c->stream, win);
+    }
   }
   Vec3* F = fslot(c, fsl);
-  c2r_yz3(c, c->nm, c->cB, 3 * cm, cm, F);
+  {
+    ProfScope ps(c, PMR_PROF_ZPASS, 3 * 8.0 * B * c->cm + B * 12.0 * c->nm3);
+    launch_zpass_c2r3(c->nm, c->B, c->cB, fm3, F, c->nm3, c->stream);
+  }
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
   {
@@ -1036,22 +1072,35 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
                                             rowslot(c, fsl), c->nm, 1.f, 0.f),
                        B, c->cB, fm3, s);
     }
-    {
-      ProfScope ps(c, PMR_PROF_YPASS, 3 * 16.0 * B * c->cm);
-      launch_ypass(c->nm, 3 * B, c->cB, fm3, false, s);
+    const FieldMap dm1 = fmap(1, cm, 0, spec_pitch(c->nm));
+    for (const KzWin& win : kz_windows(c->nm)) {
+      const double part = window_share(c->nm, win);
+      {
+        ProfScope ps(c, PMR_PROF_YPASS, part * 3 * 16.0 * B * c->cm);
+        launch_ypass(c->nm, 3 * B, c->cB, fm3, false, s, win);
+      }
+      XPassArgs a = xargs(c, c->nm);
+      a.n_in = 3;
+      a.n_out = 1;
+      for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cm;
+      a.out[0] = c->cA;
+      a.in_item_stride = 3 * cm;
+      a.out_item_stride = cm;
+      a.kz_lo = win.lo;
+      a.kz_hi = win.hi;
+      {
+        ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, part * 32.0 * B * c->cm);
+        launch_xpass(XOP_FORCE_ADJ, a, s);
+      }
+      {
+        ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
+        launch_ypass(c->nm, B, c->cA, dm1, true, s, win);
+      }
     }
-    XPassArgs a = xargs(c, c->nm);
-    a.n_in = 3;
-    a.n_out = 1;
-    for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cm;
-    a.out[0] = c->cA;
-    a.in_item_stride = 3 * cm;
-    a.out_item_stride = cm;
     {
-      ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, 32.0 * B * c->cm);
-      launch_xpass(XOP_FORCE_ADJ, a, s);
+      ProfScope ps(c, PMR_PROF_ZPASS, B * (8.0 * c->cm + 4.0 * c->nm3));
+      launch_zpass_c2r(c->nm, B, c->cA, dm1, c->dbar, fmap(1, c->nm3, 0), nullptr, s);
     }
-    c2r_yz(c, c->nm, 1, c->cA, cm, 0, c->dbar, c->nm3, 0, nullptr);
     {
       // compulsory: position (FP64), Fbar in and g out per particle; F and dbar per cell
       ProfScope ps(c, PMR_PROF_ADJ_GATHER, 48.0 * B * c->np3 + 16.0 * B * c->nm3);
@@ -1244,6 +1293,16 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream) {
 
 int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging) {
   return set_fft_tile(n, pass, columns, threads, staging) == 0 ? PMR_OK : PMR_E_INVALID;
+}
+
+int pmr_fft_set_slab(int n, int columns) {
+  return set_fft_slab(n, columns) == 0 ? PMR_OK : PMR_E_INVALID;
+}
+
+int pmr_fft_get_slab(int n, int* columns) {
+  if (!columns || !pow2_in(n, 16, 512)) return PMR_E_INVALID;
+  *columns = get_fft_slab(n);
+  return PMR_OK;
 }
 
 int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging) {

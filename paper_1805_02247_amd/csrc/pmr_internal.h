@@ -169,6 +169,7 @@ struct XPassArgs {
   const float2* proj_modes;  // P s
   const float* inv_var;      // 1 / S(k), shared by all items
   const double* loss_bar;    // [B]
+  int kz_lo, kz_hi;          // kz window of the pass (kz_hi = 0: the whole half spectrum)
 };
 
 // z pass r2c over `fields` fields; loaded value = a1*in (+ a2*in2) (* scale_dev[item])
@@ -186,7 +187,12 @@ void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2
                       hipStream_t s);
 void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Vec3* out,
                        size_t out_item_stride, hipStream_t s);
-void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s);
+// A window [lo, hi) of kz columns of the half spectrum (hi = 0: all of them).
+struct KzWin {
+  int lo = 0, hi = 0;
+};
+void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hipStream_t s,
+                  KzWin win = KzWin{});
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
 // Tile shape of the strided passes (columns per tile, threads per workgroup, and whether the
 // butterflies run on register images (0) or on the LDS-staged tile (1)), per pass (0: y pass,
@@ -199,6 +205,11 @@ extern TileShape g_fft_tile[3][10];
 
 int set_fft_tile(int n, int pass, int pc, int nth, int lds);
 void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
+// kz-slab width of the strided passes per size (0: off); fft_slab_columns gives the width
+// in use (a multiple of every pass's tile columns, 0 when one slab would hold everything).
+int set_fft_slab(int n, int columns);
+int get_fft_slab(int n);
+int fft_slab_columns(int n);
 
 // cic.hip
 size_t sort_scratch_bytes(int n, int key_bits);

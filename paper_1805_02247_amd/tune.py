@@ -10,7 +10,8 @@ The first form times a batched forward + inverse 3-D real FFT through the librar
 supported shape. The second times whole gradient evaluations (forward + adjoint) of a
 workload given as n_part n_mesh n_out n_steps batch hidden [precision], tuning each pass of
 each mesh size it uses in turn with the others held fixed, which also ranks the operator
-passes (force, force adjoint, smoothing) by their real cost. --write stores the result in
+passes (force, force adjoint, smoothing) by their real cost, and then the kz-slab width of
+the force transforms on the force mesh. --write stores the result in
 fft_tiles.json next to this file, which the binding applies when it loads the library.
 """
 import argparse
@@ -148,12 +149,28 @@ def tune(sizes, write=False, log=print):
     return result
 
 
+SLABS = (0, 16, 32, 64)
+
+
+def _tune_slab(step, n, reps, log):
+    """kz-slab width of the force transforms on the n^3 mesh (0: whole passes)."""
+    times = {}
+    for cols in SLABS:
+        L.check(L.lib().pmr_fft_set_slab(n, cols))
+        times[cols] = _timer(step, reps)
+        log(f"n={n} slab={cols}: {times[cols] * 1e3:.3f} ms")
+    best = min(times, key=times.get)
+    L.check(L.lib().pmr_fft_set_slab(n, best))
+    return {"columns": best, "all_ms": {str(k): v * 1e3 for k, v in times.items()}}
+
+
 def tune_workload(n_part, n_mesh, n_out, n_steps, batch, hidden, precision=0, write=False,
                   log=print):
     step = _gradient_step(n_part, n_mesh, n_out, n_steps, batch, hidden, precision)
     sizes = sorted({n_mesh, n_out, n_part}, reverse=True)
     reps = 2 if n_mesh >= 512 else 5
     result = _tune_passes(step, sizes, reps, log)
+    result[str(n_mesh)]["slab"] = _tune_slab(step, n_mesh, reps, log)
     if write:
         _write(result)
     return result
@@ -180,6 +197,8 @@ def apply_cache():
             if p in PASSES:
                 L.lib().pmr_fft_set_tile(int(n), PASSES[p], int(t["columns"]), int(t["threads"]),
                                          int(t.get("staging", 0)))
+            elif p == "slab":
+                L.lib().pmr_fft_set_slab(int(n), int(t["columns"]))
     return tiles
 
 
