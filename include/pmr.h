@@ -341,6 +341,19 @@ int pmr_lbfgs_direction(size_t n, int m, int count, const int* order, const floa
                         const float* Y, const double* sy, const double* yy, const float* g,
                         float* d, void* work, void* stream);
 
+/* pmr_lbfgs_direction without the `work` argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight optimiser loops, harnesses that forbid it):
+ * the FP64 partial sums and the two-loop scalars live in a fixed array inside the library,
+ * one per GPU (1224 doubles, about 10 KB: up to 1088 partial sums and 2 m + 2 scalars), held until the process
+ * ends; the call allocates nothing and frees nothing. Same arguments, rules and results
+ * (bit for bit) as pmr_lbfgs_direction; PMR_E_SHAPE for m > 64 (beyond the fixed array),
+ * PMR_E_HIP if the array's address on the stream's GPU cannot be taken. All calls on one
+ * GPU share the array: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller. */
+int pmr_lbfgs_direction_noalloc(size_t n, int m, int count, const int* order, const float* S,
+                                const float* Y, const double* sy, const double* yy,
+                                const float* g, float* d, void* stream);
+
 /* Bytes of device scratch for pmr_power_bins with `nbins` shells. */
 size_t pmr_power_work_bytes(int nbins);
 

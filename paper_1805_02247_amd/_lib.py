@@ -82,6 +82,8 @@ SIGNATURES = {
     "pmr_vec_axpby": (ci, [sz, cd, vp, cd, vp, vp, vp]),
     "pmr_lbfgs_direction": (ci, [sz, ci, ci, ctypes.POINTER(ci), vp, vp, vp, vp, vp, vp, vp,
                                  vp]),
+    "pmr_lbfgs_direction_noalloc": (ci, [sz, ci, ci, ctypes.POINTER(ci), vp, vp, vp, vp, vp,
+                                         vp, vp]),
     "pmr_power_work_bytes": (sz, [ci]),
     "pmr_power_bins": (ci, [ci, cd, vp, vp, ci, vp, vp, sz, vp]),
     "pmr_profile_begin": (ci, [vp, ci, ci]),

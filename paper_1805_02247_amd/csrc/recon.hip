@@ -5,6 +5,9 @@
 // Inner products: each element product is exact in FP64 (two FP32 factors), the partial
 // sums of a fixed grid and the final tree are fixed, so results are bitwise reproducible.
 #include "../../include/pmr.h"
+
+#include <mutex>
+
 #include "pmr_internal.h"
 
 namespace pmr {
@@ -210,6 +213,43 @@ void launch_power_bins(int n, double box, const float2* a, const float2* b, int 
 
 }  // namespace pmr
 
+// ---------------------------------------------------------------- fixed scratch
+// The scratch of pmr_lbfgs_direction_noalloc: the partial sums of one inner product
+// (vec_work_doubles(n) <= DOT_BLOCKS + 64) followed by the two-loop scalars (alpha per slot,
+// beta: at most 2 * 64 + 8). One copy per GPU, held until the process ends; every call on a
+// GPU shares it, so calls that overlap on one GPU (several streams or threads) race.
+constexpr int NOALLOC_MAX_M = 64;
+constexpr size_t NOALLOC_DOUBLES = (size_t)pmr::DOT_BLOCKS + 64 + 2 * NOALLOC_MAX_M + 8;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` on each GPU
+
+// Device address of this GPU's copy of `scratch` (the GPU that runs `stream`), taken once per
+// device with that device current. In host code the array's name is only a stand-in for
+// the symbol, so kernels get this address instead.
+int scratch_of(hipStream_t stream, double** out) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return PMR_E_HIP;
+  int dev = cur;
+  if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess) return PMR_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return PMR_E_SHAPE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return PMR_E_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return PMR_E_HIP;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return PMR_OK;
+}
+}  // namespace
+
 // ---------------------------------------------------------------- C ABI
 using namespace pmr;
 
@@ -249,6 +289,29 @@ int pmr_lbfgs_direction(size_t n, int m, int count, const int* order, const floa
   double* w = (double*)work;
   launch_lbfgs_direction(n, m, count, order, S, Y, sy, yy, g, d, w, w + vec_work_doubles(n),
                          (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+int pmr_lbfgs_direction_noalloc(size_t n, int m, int count, const int* order, const float* S,
+                                const float* Y, const double* sy, const double* yy,
+                                const float* g, float* d, void* stream) {
+  if (!g || !d || n == 0 || g == d || m < 1 || count < 0 || count > m) return PMR_E_INVALID;
+  if (m > NOALLOC_MAX_M) return PMR_E_SHAPE;  // the fixed scratch holds 2 m + 2 scalars
+  if (count > 0) {
+    if (!order || !S || !Y || !sy || !yy) return PMR_E_INVALID;
+    unsigned long long seen = 0;
+    for (int j = 0; j < count; ++j) {
+      if (order[j] < 0 || order[j] >= m || (seen >> order[j]) & 1ull) return PMR_E_INVALID;
+      seen |= 1ull << order[j];
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* w = nullptr;
+  const int st = scratch_of(s, &w);
+  if (st != PMR_OK) return st;
+  const size_t part = vec_work_doubles(n);
+  if (part + 2 * (size_t)m + 2 > NOALLOC_DOUBLES) return PMR_E_SHAPE;
+  launch_lbfgs_direction(n, m, count, order, S, Y, sy, yy, g, d, w, w + part, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 
