@@ -32,7 +32,8 @@ CLASS_KERNELS = {
     "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
     "ypass": r"ypass(_reg)?_kernel<", "zpass": r"zpass_", "kick_drift": r"kick_drift_kernel",
     "adj_gather": r"adjoint_positions_kernel", "adj_update": r"adjoint_update_kernel",
-    "sort_scatter": r"radix_scatter_kernel<",
+    "sort": r"(fill_u32|row_count|scan_reduce|scan_partials|scan_write|bucket|row_sort_wave|"
+            r"row_sort_block)_kernel",
 }
 
 
@@ -752,7 +753,7 @@ def main():
     torch.cuda.synchronize()
     # event time of every kernel class over one untimed gradient evaluation each; the
     # dominant hot-path step class is timed in the timed region
-    probe = probe_classes(pm, step, STEP_CLASSES + ["sort", "network", "sort_scatter"])
+    probe = probe_classes(pm, step, STEP_CLASSES + ["sort", "network"])
     ranked = sorted(STEP_CLASSES, key=lambda c: probe[c][0], reverse=True)
     dominant = ranked[0]
     pm.profile_begin(dominant, max_launches=64 * (args.steps + 1))

@@ -242,8 +242,6 @@ enum {
                                      algorithmic figure is FLOPs, not bytes */
   PMR_PROF_HALO2_STENCIL = 11,    /* two-network model: neighbourhood sum of the position
                                      network's input adjoint */
-  PMR_PROF_SORT_SCATTER = 12,     /* scatter passes of the cell-key radix sort (each pass
-                                     timed alone, without its histogram and scan) */
   PMR_PROF_SORT = 13,             /* every kernel of one cell-key sort and its row index, as
                                      one launch; an implementation cost that serves the paint
                                      and the adjoint gathers: its algorithmic bytes are 0 */
@@ -344,8 +342,8 @@ int pmr_lbfgs_direction(size_t n, int m, int count, const int* order, const floa
 /* pmr_lbfgs_direction without the `work` argument, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight optimiser loops, harnesses that forbid it):
  * the FP64 partial sums and the two-loop scalars live in a fixed array inside the library,
- * one per GPU (1224 doubles, about 10 KB: up to 1088 partial sums and 2 m + 2 scalars), held until the process
- * ends; the call allocates nothing and frees nothing. Same arguments, rules and results
+ * one per GPU (1224 doubles, about 10 KB: up to 1088 partial sums and 2 m + 2 scalars),
+ * held until the process ends; the call allocates nothing and frees nothing. Same arguments, rules and results
  * (bit for bit) as pmr_lbfgs_direction; PMR_E_SHAPE for m > 64 (beyond the fixed array),
  * PMR_E_HIP if the array's address on the stream's GPU cannot be taken. All calls on one
  * GPU share the array: calls that overlap on one GPU (several streams or host threads)

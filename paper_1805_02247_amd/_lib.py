@@ -92,7 +92,7 @@ SIGNATURES = {
 }
 PROF = {"paint": 1, "xpass_force": 2, "ypass": 3, "zpass": 4, "kick_drift": 5, "paint3": 6,
         "xpass_force_adj": 7, "adj_gather": 8, "adj_update": 9, "halo2": 10,
-        "halo2_stencil": 11, "sort_scatter": 12, "sort": 13,
+        "halo2_stencil": 11, "sort": 13,
         "network": 14}
 
 

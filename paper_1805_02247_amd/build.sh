@@ -14,7 +14,7 @@ jobs=${MAX_JOBS:-8}
 [ "$jobs" -gt 16 ] && jobs=16
 units=()
 for n in 16 32 64 128 256 512; do units+=("fft_size.hip:-DPMR_FFT_SIZE=$n:fft_$n.o"); done
-for f in fft.hip cic.hip halo.hip halo2.hip recon.hip lpt2.hip pmr.cpp; do units+=("$f::${f%.*}.o"); done
+for f in fft.hip cic.hip sort.hip halo.hip halo2.hip recon.hip lpt2.hip pmr.cpp; do units+=("$f::${f%.*}.o"); done
 pids=()
 status=0
 for u in "${units[@]}"; do

@@ -7,9 +7,8 @@
 // Positions are FP64 [B][3][Np^3]; momenta and adjoints FP32 [B][3][Np^3].
 //
 // Keys carry the batch item: key = item*Nm^3 + (ix*Nm + iy)*Nm + iz, with (ix, iy, iz)
-// the lower CIC corner computed in FP64. A stable LSD radix sort of (key, id) gives the
-// unique (key, id) order; rows (item, ix, iy) are then contiguous and `row_start` indexes
-// them.
+// the lower CIC corner computed in FP64. The cell sort (sort.hip) gives the unique
+// (key, id) order; rows (item, ix, iy) are then contiguous and `row_start` indexes them.
 //
 // Paint is owner-computes and atomic-free across the device: one wavefront owns TY
 // consecutive target rows of Nm cells in LDS and walks the source rows that can reach them
@@ -54,253 +53,6 @@ __global__ void keys_kernel(const double* __restrict__ x, int log_np3, int total
   Vec3 f;
   keys[g] = key_frac(p, scale, nm, item, &f);
   if (frac) frac[g] = f;
-}
-
-// ---------------------------------------------------------------- radix sort
-#ifndef PMR_SORT_WAVES
-#define PMR_SORT_WAVES 8
-#endif
-constexpr int SORT_TILE = 4096;  // keys per tile
-constexpr int SORT_WAVES = PMR_SORT_WAVES;
-constexpr int SORT_TB = SORT_WAVES * PMR_WAVE;
-constexpr int SORT_ITEMS = SORT_TILE / SORT_TB;
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const int l = threadIdx.x & 63;
-  return l == 0 ? 0ull : (~0ull >> (64 - l));
-}
-
-// Lanes of this wavefront (among `valid`) whose digit equals mine.
-template <int D>
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
-  uint64_t m = valid;
-#pragma unroll
-  for (int b = 0; b < D; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    m &= bit ? bal : ~bal;
-  }
-  return m;
-}
-
-// Digit histogram of each tile: hist[digit * nblocks + block].
-template <int D>
-__global__ __launch_bounds__(TB) void radix_hist_kernel(const uint32_t* __restrict__ keys, int n,
-                                                        int shift, uint32_t* __restrict__ hist) {
-  constexpr int NBK = 1 << D;
-  __shared__ uint32_t cnt[NBK];
-  for (int i = threadIdx.x; i < NBK; i += TB) cnt[i] = 0;
-  __syncthreads();
-  const size_t base = (size_t)blockIdx.x * SORT_TILE;
-  for (int i = threadIdx.x; i < SORT_TILE; i += TB) {
-    const size_t j = base + i;
-    if (j < (size_t)n) atomicAdd(&cnt[(keys[j] >> shift) & (NBK - 1)], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < NBK; i += TB) hist[(size_t)i * gridDim.x + blockIdx.x] = cnt[i];
-}
-
-// Stable scatter. Key j of the tile is handled by wave w = (j / 64) / ITEMS in order, so
-// ranks follow j: local rank = (same digit in earlier waves) + (same digit earlier in this
-// wave). The tile is first placed in LDS in digit order, then each digit's run is written
-// to its global range [offset[digit][block], ...) contiguously.
-// ids_in == nullptr means identity payload (id = index).
-template <int D>
-__global__ __launch_bounds__(SORT_TB) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
-                                                           const uint32_t* __restrict__ ids_in,
-                                                           int n, int shift,
-                                                           const uint32_t* __restrict__ offsets,
-                                                           const uint32_t* __restrict__ digit_total,
-                                                           uint32_t* __restrict__ keys_out,
-                                                           uint32_t* __restrict__ ids_out,
-                                                           const Vec3* __restrict__ pay_in,
-                                                           Vec3* __restrict__ pay_out,
-                                                           uint32_t* __restrict__ inv_out) {
-  constexpr int NBK = 1 << D;
-  __shared__ uint32_t cnt[SORT_WAVES][NBK];
-  __shared__ uint32_t dstart[NBK];   // block-local start of each digit
-  __shared__ uint32_t gbase[NBK];    // global start of each digit for this block
-  __shared__ uint32_t skey[SORT_TILE];
-  __shared__ uint32_t sid[SORT_TILE];
-  __shared__ uint32_t wsum[2 * SORT_WAVES];
-  const int w = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < SORT_WAVES * NBK; i += SORT_TB) (&cnt[0][0])[i] = 0;
-  __syncthreads();
-  // consecutive tiles on one XCD: their runs of each digit are adjacent in the output, so
-  // the partial lines they write meet in one L2
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  const size_t tile0 = (size_t)tile * SORT_TILE;
-  const size_t base = tile0 + (size_t)w * PMR_WAVE * SORT_ITEMS;
-  uint32_t key[SORT_ITEMS], id[SORT_ITEMS], rank[SORT_ITEMS];
-  const uint64_t lt = lanemask_lt();
-#pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
-    const size_t j = base + (size_t)it * PMR_WAVE + lane;
-    const bool ok = j < (size_t)n;
-    key[it] = ok ? keys_in[j] : 0u;
-    id[it] = ok ? (ids_in ? ids_in[j] : (uint32_t)j) : 0u;
-    const uint32_t d = (key[it] >> shift) & (NBK - 1);
-    const uint64_t valid = __ballot(ok);
-    const uint64_t m = match_digit<D>(d, valid);
-    uint32_t r = 0;
-    if (ok) r = cnt[w][d] + (uint32_t)__popcll(m & lt);
-    rank[it] = r;
-    // the lowest lane of each digit group advances the running count
-    if (ok && (m & lt) == 0) cnt[w][d] += (uint32_t)__popcll(m);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS update visible to the next item
-  }
-  __syncthreads();
-  // per digit: exclusive prefix over waves, and the block total
-  constexpr int Q = (NBK + SORT_TB - 1) / SORT_TB;
-  uint32_t tot_local[Q], dig_tot[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int d = threadIdx.x + q * SORT_TB;
-    uint32_t run = 0, dt = 0;
-    if (d < NBK) {
-#pragma unroll
-      for (int ww = 0; ww < SORT_WAVES; ++ww) {
-        const uint32_t c = cnt[ww][d];
-        cnt[ww][d] = run;
-        run += c;
-      }
-      gbase[d] = offsets[(size_t)d * gridDim.x + tile];
-      dt = digit_total[d];
-    }
-    tot_local[q] = run;
-    dig_tot[q] = dt;
-  }
-  // exclusive scans over digits (digit d = thread + q * SORT_TB) of the block totals (start
-  // of each digit in the tile) and of the global digit totals (start of each digit's range)
-  {
-    uint32_t carry = 0, gcarry = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const uint32_t v = tot_local[q], gv = dig_tot[q];
-      // wave-level inclusive scans
-      uint32_t x = v, gx = gv;
-#pragma unroll
-      for (int dd = 1; dd < 64; dd <<= 1) {
-        const uint32_t y = __shfl_up(x, dd, 64);
-        const uint32_t gy = __shfl_up(gx, dd, 64);
-        if (lane >= dd) {
-          x += y;
-          gx += gy;
-        }
-      }
-      if (lane == 63) {
-        wsum[w] = x;
-        wsum[SORT_WAVES + w] = gx;
-      }
-      __syncthreads();
-      uint32_t wpre = 0, total = 0, gpre = 0, gtotal = 0;
-#pragma unroll
-      for (int ww = 0; ww < SORT_WAVES; ++ww) {
-        const uint32_t sv = wsum[ww], gs = wsum[SORT_WAVES + ww];
-        if (ww < w) {
-          wpre += sv;
-          gpre += gs;
-        }
-        total += sv;
-        gtotal += gs;
-      }
-      const int d = threadIdx.x + q * SORT_TB;
-      if (d < NBK) {
-        dstart[d] = carry + wpre + x - v;
-        gbase[d] += gcarry + gpre + gx - gv;
-      }
-      carry += total;
-      gcarry += gtotal;
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-  // place the tile in LDS in (digit, rank) order
-#pragma unroll
-  for (int it = 0; it < SORT_ITEMS; ++it) {
-    const size_t j = base + (size_t)it * PMR_WAVE + lane;
-    if (j < (size_t)n) {
-      const uint32_t d = (key[it] >> shift) & (NBK - 1);
-      const uint32_t lp = dstart[d] + cnt[w][d] + rank[it];
-      skey[lp] = key[it];
-      sid[lp] = id[it];
-    }
-  }
-  __syncthreads();
-  const int count = (int)min((size_t)SORT_TILE, (size_t)n - tile0);
-  for (int e = threadIdx.x; e < count; e += SORT_TB) {
-    const uint32_t k = skey[e];
-    const uint32_t d = (k >> shift) & (NBK - 1);
-    const uint32_t dst = gbase[d] + (uint32_t)e - dstart[d];
-    const uint32_t idv = sid[e];
-    keys_out[dst] = k;
-    ids_out[dst] = idv;
-    if (pay_out) pay_out[dst] = pay_in[idv];
-    if (inv_out) inv_out[idv] = dst;
-  }
-}
-
-// ---------------------------------------------------------------- exclusive scan (u32)
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = TB * SCAN_ITEMS;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // sh: TB words
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int d = 1; d < TB; d <<= 1) {
-    uint32_t a = t >= d ? sh[t - d] : 0u;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
-  }
-  const uint32_t incl = sh[t];
-  *total = sh[TB - 1];
-  __syncthreads();
-  return incl - v;
-}
-
-// Per digit (one block each): exclusive scan of the tile histograms over tiles, giving each
-// tile's start within the digit's range, and the digit's total.
-__global__ __launch_bounds__(TB) void digit_scan_kernel(const uint32_t* __restrict__ hist, int nb,
-                                                        uint32_t* __restrict__ offs,
-                                                        uint32_t* __restrict__ digit_total) {
-  __shared__ uint32_t sh[TB];
-  const size_t row = (size_t)blockIdx.x * nb;
-  uint32_t carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += SCAN_TILE) {
-    const int t0 = b0 + threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      v[i] = t0 + i < nb ? hist[row + t0 + i] : 0u;
-      sum += v[i];
-    }
-    uint32_t tot;
-    uint32_t run = carry + block_exclusive_scan(sum, sh, &tot);
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      if (t0 + i < nb) offs[row + t0 + i] = run;
-      run += v[i];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
-}
-
-// ---------------------------------------------------------------- row starts
-// row_start[r] = first sorted position whose row (key >> log_nm) is >= r; r = 0..rows.
-__global__ void row_start_kernel(const uint32_t* __restrict__ keys, int n, int log_nm, int rows,
-                                 uint32_t* __restrict__ row_start) {
-  const int j = blockIdx.x * TB + threadIdx.x;
-  if (j > n) return;
-  const int r_hi = j < n ? (int)(keys[j] >> log_nm) : rows;
-  const int r_lo = j > 0 ? (int)(keys[j - 1] >> log_nm) : -1;
-  for (int r = r_lo + 1; r <= r_hi; ++r) row_start[r] = j;
 }
 
 // ---------------------------------------------------------------- sorted particle streams
@@ -592,78 +344,6 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
 }  // namespace
 
 // ================================================================ host launchers
-size_t sort_scratch_bytes(int n, int key_bits) {
-  const int passes = (key_bits + 8) / 9;
-  const int D = (key_bits + passes - 1) / passes;
-  const size_t nb = (size_t)((n + SORT_TILE - 1) / SORT_TILE);
-  const size_t hist = nb << D;
-  // keys/ids ping-pong buffers (2 x n), histogram, offsets, digit totals
-  return (2 * (size_t)n + 2 * hist + ((size_t)1 << D) + 64) * sizeof(uint32_t);
-}
-
-template <int D>
-static void sort_pass(const uint32_t* kin, const uint32_t* iin, uint32_t* kout, uint32_t* iout,
-                      int n, int shift, uint32_t* hist, uint32_t* offs, uint32_t* dtot,
-                      const Vec3* pin, Vec3* pout, uint32_t* inv, hipStream_t s,
-                      const ScatterProbe* probe) {
-  const int nb = (n + SORT_TILE - 1) / SORT_TILE;
-  radix_hist_kernel<D><<<nb, TB, 0, s>>>(kin, n, shift, hist);
-  digit_scan_kernel<<<1 << D, TB, 0, s>>>(hist, nb, offs, dtot);
-  if (probe) {
-    // keys (and ids, unless the identity) in, keys and ids out, the payload gathered and
-    // written, the inverse permutation written
-    const double per = (iin ? 16.0 : 12.0) + (pout ? 24.0 : 0.0) + (inv ? 4.0 : 0.0);
-    probe->before(probe->arg, per * n);
-  }
-  radix_scatter_kernel<D><<<nb, SORT_TB, 0, s>>>(kin, iin, n, shift, offs, dtot, kout, iout, pin,
-                                                  pout, inv);
-  if (probe) probe->after(probe->arg);
-}
-
-// Sorts keys (in place semantics: keys_io holds the input; on return `keys_sorted`
-// and `ids_sorted` hold the (key, id) order). Payload starts as the identity.
-void launch_sort(uint32_t* keys_io, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
-                 hipStream_t s, uint32_t* inv, const ScatterProbe* probe) {
-  const int passes = (key_bits + 8) / 9;
-  const int D = (key_bits + passes - 1) / passes;
-  const int nb = (n + SORT_TILE - 1) / SORT_TILE;
-  const size_t hn = (size_t)nb << D;
-  uint32_t* w = (uint32_t*)scratch;
-  uint32_t* ka = w;
-  uint32_t* ia = ka + n;
-  uint32_t* hist = ia + n;
-  uint32_t* offs = hist + hn;
-  uint32_t* dtot = offs + hn;
-  const uint32_t* kin = keys_io;
-  const uint32_t* iin = nullptr;
-  for (int p = 0; p < passes; ++p) {
-    // last pass lands in the caller's output arrays
-    const bool last = p == passes - 1;
-    const bool to_a = ((passes - 1 - p) & 1) == 1;
-    uint32_t* ko = last ? keys_sorted : (to_a ? ka : keys_sorted);
-    uint32_t* io = last ? ids_sorted : (to_a ? ia : ids_sorted);
-    const int shift = p * D;
-    switch (D) {
-#define CASE(DD) \
-  case DD:                                                                                  \
-    sort_pass<DD>(kin, iin, ko, io, n, shift, hist, offs, dtot, last ? pay_in : nullptr,      \
-                  last ? pay_out : nullptr, last ? inv : nullptr, s, probe);                   \
-    break;
-      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
-#undef CASE
-      default: break;
-    }
-    kin = ko;
-    iin = io;
-  }
-}
-
-void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
-                      uint32_t* row_start, hipStream_t s) {
-  row_start_kernel<<<(n + 1 + TB - 1) / TB, TB, 0, s>>>(keys_sorted, n, log_nm, rows, row_start);
-}
-
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
                  Vec3* frac, hipStream_t s) {
   keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys, frac);

@@ -92,7 +92,6 @@ struct pmr_ctx {
   size_t np3, nm3, no3, cp, cm, co;  // standard half-spectrum sizes n * n * (n/2 + 1)
   size_t sp, sm, so, cmax;           // internal spectra: n * n * row pitch (rows of 128 B)
   int log_np3, log_nm, log_no;
-  int key_bits_m, key_bits_o;
   // factors
   double D0, Gp0;
   std::vector<double> kick, drift;
@@ -244,8 +243,8 @@ void plan(pmr_ctx* c, Plan& P) {
   c->keys = P.take<uint32_t>(B * c->np3);
   c->keys_sorted = P.take<uint32_t>(B * c->np3);
   {
-    const size_t sm = sort_scratch_bytes((int)(B * c->np3), c->key_bits_m);
-    const size_t so = sort_scratch_bytes((int)(B * c->np3), c->key_bits_o);
+    const size_t sm = cell_sort_scratch_bytes((int)(B * c->np3), B * c->nm * c->nm, c->log_nm);
+    const size_t so = cell_sort_scratch_bytes((int)(B * c->np3), B * c->no * c->no, c->log_no);
     c->sort_scratch_bytes = sm > so ? sm : so;
   }
   c->sort_scratch = P.take<char>(c->sort_scratch_bytes);
@@ -304,8 +303,6 @@ void init_sizes(pmr_ctx* c, const pmr_config* cfg) {
   c->log_np3 = ilog2(c->np3);
   c->log_nm = ilog2((size_t)c->nm);
   c->log_no = ilog2((size_t)c->no);
-  c->key_bits_m = ilog2((size_t)c->B * c->nm3);
-  c->key_bits_o = ilog2((size_t)c->B * c->no3);
   if (c->k == 0) {
     c->n_xslots = c->n + 1;
     c->n_fslots = c->n;
@@ -365,33 +362,6 @@ struct ProfScope {
       c->prof_used += 2;
     }
   }
-};
-
-// Event timing of the sort's scatter launches alone (PMR_PROF_SORT_SCATTER).
-void scatter_probe_before(void* arg, double bytes) {
-  pmr_ctx* c = (pmr_ctx*)arg;
-  if (c->prof_class == PMR_PROF_SORT_SCATTER && c->prof_used + 2 <= c->prof_ev.size()) {
-    HIPC(c, hipEventRecord(c->prof_ev[c->prof_used], c->stream));
-    c->prof_bytes += bytes;
-    c->prof_open = true;
-  }
-}
-void scatter_probe_after(void* arg) {
-  pmr_ctx* c = (pmr_ctx*)arg;
-  if (c->prof_open) {
-    HIPC(c, hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream));
-    c->prof_used += 2;
-    c->prof_open = false;
-  }
-}
-// The probe of context c for one launch_sort call (a temporary: it lives for that call).
-struct ScatterProbeOf {
-  ScatterProbe p;
-  bool on;
-  explicit ScatterProbeOf(pmr_ctx* c)
-      : p{scatter_probe_before, scatter_probe_after, c},
-        on(c->prof_class == PMR_PROF_SORT_SCATTER) {}
-  const ScatterProbe* get() const { return on ? &p : nullptr; }
 };
 
 // ---------------------------------------------------------------- pass helpers
@@ -607,8 +577,10 @@ int xs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 
 // One forward PM step i: sort x_i, paint, force, kick + drift (keys of x_{i+1} emitted on
-// the force mesh, or on the output mesh after the last step).
-void pm_step(pmr_ctx* c, int i, bool advance = true) {
+// the force mesh, or on the output mesh after the last step). `order`: the sorted ids of
+// step i - 1 where its slot still holds them (the sort visits the particles in that order,
+// which only makes it faster), else nullptr.
+void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nullptr) {
   const int B = c->B;
   const int total = (int)(B * c->np3);
   const int xsl = xs_of(c, i);
@@ -617,11 +589,9 @@ void pm_step(pmr_ctx* c, int i, bool advance = true) {
   double* xn = xslot(c, xsl + 1);
   {
     ProfScope ps(c, PMR_PROF_SORT, 0.0);
-    launch_sort(c->keys, total, c->key_bits_m, keyslot(c, fsl), idslot(c, fsl), c->sort_scratch,
-                c->frac_id, fracslot(c, fsl), c->stream, invslot(c, fsl),
-                ScatterProbeOf(c).get());
-    launch_row_start(keyslot(c, fsl), total, c->log_nm, B * c->nm * c->nm, rowslot(c, fsl),
-                     c->stream);
+    launch_cell_sort(c->keys, order, total, c->log_nm, (size_t)B * c->nm * c->nm, keyslot(c, fsl),
+                     idslot(c, fsl), rowslot(c, fsl), c->sort_scratch, c->frac_id,
+                     fracslot(c, fsl), invslot(c, fsl), c->stream);
   }
   const size_t cm = c->sm;
   const FieldMap dm = fmap(1, cm, 0, spec_pitch(c->nm));
@@ -692,7 +662,7 @@ void pm_run(pmr_ctx* c, int i0, int i1, bool take_ckpt) {
                        hipMemcpyDeviceToDevice, c->stream));
       }
     }
-    pm_step(c, i);
+    pm_step(c, i, true, i > 0 ? idslot(c, fs_of(c, i - 1)) : nullptr);
   }
 }
 
@@ -906,9 +876,9 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
   const int total = (int)(B * c->np3);
   {
     ProfScope ps(c, PMR_PROF_SORT, 0.0);
-    launch_sort(c->keys, total, c->key_bits_o, c->keys_sorted, c->ids_o, c->sort_scratch,
-                c->frac_id, c->frac_o, s, nullptr, ScatterProbeOf(c).get());
-    launch_row_start(c->keys_sorted, total, c->log_no, B * c->no * c->no, c->rows_o, s);
+    launch_cell_sort(c->keys, idslot(c, fs_of(c, c->n - 1)), total, c->log_no,
+                     (size_t)B * c->no * c->no, c->keys_sorted,
+                     c->ids_o, c->rows_o, c->sort_scratch, c->frac_id, c->frac_o, nullptr, s);
   }
   launch_paint_mass(c->keys_sorted, c->frac_o, c->rows_o, B, c->no, c->mass_o, 1.f, c->delta_f, s);
   // H9-H11: halo model and likelihood
@@ -1056,7 +1026,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
       const int end = j + c->k < c->n ? j + c->k : c->n;
       // the adjoint of steps j .. end-1 needs x, the sort and F of each step, not the
       // positions the last kick and drift would produce (the next checkpoint)
-      for (int q = j; q < end; ++q) pm_step(c, q, q + 1 < end);
+      for (int q = j; q < end; ++q)
+        pm_step(c, q, q + 1 < end, q > j ? idslot(c, fs_of(c, q - 1)) : nullptr);
       resident_lo = j;
       // the slots no longer hold the last segment: another adjoint needs a new forward
       c->fwd_done = 0;
@@ -1314,8 +1285,8 @@ int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging) 
 
 size_t pmr_sort_scratch_bytes(int n_total, int n_mesh, int batch) {
   if (n_total < 1 || !pow2_in(n_mesh, 16, 512) || batch < 1) return 0;
-  return sort_scratch_bytes(n_total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh)) +
-         2 * align256((size_t)n_total * sizeof(uint32_t));
+  return align256((size_t)n_total * sizeof(uint32_t)) +
+         cell_sort_scratch_bytes(n_total, (size_t)batch * n_mesh * n_mesh, ilog2((size_t)n_mesh));
 }
 
 int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
@@ -1332,12 +1303,10 @@ int pmr_cic_sort(int n_part, int n_mesh, int batch, double box, const double* x,
   if (scratch_bytes < pmr_sort_scratch_bytes(total, n_mesh, batch)) return PMR_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   uint32_t* keys = (uint32_t*)scratch;
-  void* rest = (char*)scratch + 2 * align256((size_t)total * sizeof(uint32_t));
+  void* rest = (char*)scratch + align256((size_t)total * sizeof(uint32_t));
   launch_keys(x, ilog2(np3), total, (double)n_mesh / box, n_mesh, keys, nullptr, s);
-  launch_sort(keys, total, ilog2((size_t)batch * n_mesh * n_mesh * n_mesh), keys_sorted,
-              ids_sorted, rest, nullptr, nullptr, s);
-  launch_row_start(keys_sorted, total, ilog2((size_t)n_mesh), batch * n_mesh * n_mesh, row_start,
-                   s);
+  launch_cell_sort(keys, nullptr, total, ilog2((size_t)n_mesh), (size_t)batch * n_mesh * n_mesh,
+                   keys_sorted, ids_sorted, row_start, rest, nullptr, nullptr, nullptr, s);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 

@@ -211,22 +211,17 @@ int set_fft_slab(int n, int columns);
 int get_fft_slab(int n);
 int fft_slab_columns(int n);
 
+// sort.hip: the unique (key, id) order of the id-order cell keys, sorted keys and ids, the
+// row index row_start [rows + 1] (rows = key >> shift), pay_out[pos] = pay_in[id] and
+// inv[id] = pos when given. `order` (nullable) is the order in which the particles are
+// visited (a permutation of the ids, e.g. the previous step's sorted ids; it changes only
+// the speed). Scratch of cell_sort_scratch_bytes(n, rows) bytes.
+size_t cell_sort_scratch_bytes(int n, size_t rows, int shift);
+void launch_cell_sort(const uint32_t* keys, const uint32_t* order, int n, int shift,
+                      size_t rows, uint32_t* keys_sorted, uint32_t* ids_sorted,
+                      uint32_t* row_start, void* scratch, const Vec3* pay_in, Vec3* pay_out,
+                      uint32_t* inv, hipStream_t s);
 // cic.hip
-size_t sort_scratch_bytes(int n, int key_bits);
-// Host hooks called just before and just after each scatter launch of a sort (event timing
-// of that kernel alone); `bytes` is the launch's compulsory HBM traffic.
-struct ScatterProbe {
-  void (*before)(void* arg, double bytes);
-  void (*after)(void* arg);
-  void* arg;
-};
-// Stable (key, id) sort; on the last pass pay_out[dst] = pay_in[id] when pay_out != nullptr,
-// and inv[id] = dst (the inverse permutation) when inv != nullptr.
-void launch_sort(uint32_t* keys_in, int n, int key_bits, uint32_t* keys_sorted,
-                 uint32_t* ids_sorted, void* scratch, const Vec3* pay_in, Vec3* pay_out,
-                 hipStream_t s, uint32_t* inv = nullptr, const ScatterProbe* probe = nullptr);
-void launch_row_start(const uint32_t* keys_sorted, int n, int log_nm, int rows,
-                      uint32_t* row_start, hipStream_t s);
 void launch_keys(const double* x, int log_np3, int total, double scale, int nm, uint32_t* keys,
                  Vec3* frac, hipStream_t s);
 void launch_stream_frac(const uint32_t* ids, const double* x, int total, int log_np3, int nm,

@@ -14,9 +14,9 @@ def _write_summary(tmp_path, fingerprint):
         f"# sources sha256: {fingerprint}",
         "dispatches   read_MiB  write_MiB  kernel",
         "        10      100.0       50.0  pmr::(anonymous namespace)::kick_drift_kernel(Args)",
-        "         2       10.0       20.0  void pmr::(anonymous namespace)::radix_scatter_kernel<8>(x)",
-        "         6       30.0       10.0  void pmr::(anonymous namespace)::radix_scatter_kernel<9>(x)",
-        "         4        1.0        1.0  void pmr::(anonymous namespace)::radix_hist_kernel<8>(x)",
+        "         2       10.0       20.0  pmr::(anonymous namespace)::row_count_kernel(x)",
+        "         6       30.0       10.0  pmr::(anonymous namespace)::bucket_kernel(x)",
+        "         4        1.0        1.0  pmr::(anonymous namespace)::adjoint_update_kernel(x)",
     ]
     (prof / bench.TRAFFIC_PROFILES["p128_m128_b4"]).write_text("\n".join(lines) + "\n")
 
@@ -27,10 +27,11 @@ def test_counter_traffic_averages_the_dispatches_of_a_class(tmp_path, monkeypatc
     _write_summary(tmp_path, "abc")
     MiB = 2 ** 20
     assert bench.counter_traffic("p128_m128_b4", "kick_drift") == 150.0 * MiB
-    # both scatter instantiations, weighted by their dispatch counts; the histogram is not
-    # part of the class
+    # the kernels of a class, weighted by their dispatch counts; other kernels are not part
+    # of the class
     want = (2 * 30.0 + 6 * 40.0) / 8 * MiB
-    assert abs(bench.counter_traffic("p128_m128_b4", "sort_scatter") - want) < 1e-6
+    assert abs(bench.counter_traffic("p128_m128_b4", "sort") - want) < 1e-6
+    assert bench.counter_traffic("p128_m128_b4", "adj_update") == 2.0 * MiB
     # a class with no dispatch in the summary, an unknown class, a workload with no summary
     assert bench.counter_traffic("p128_m128_b4", "paint") is None
     assert bench.counter_traffic("p128_m128_b4", "no_such_class") is None
