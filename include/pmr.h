@@ -291,6 +291,19 @@ int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging);
 int pmr_fft_set_slab(int n, int columns);
 int pmr_fft_get_slab(int n, int* columns);
 
+/* Rows per wavefront of the CIC paints on an n^3 mesh with `channels` channels (1: the
+ * density, 3: the adjoint's three force channels), process-wide; the autotuner sets it.
+ * A wavefront owns `rows` consecutive target rows of one plane and walks the source rows
+ * that reach them: more rows read each particle fewer times (2 (rows + 1) / rows walks)
+ * but leave fewer wavefronts to share the dense rows of late steps. rows: 0 (the default
+ * rule: 1024 floats of rows per wavefront, at most 8 rows), 1, 2, 4, 8 or 16; a value the
+ * size cannot take (LDS, rows per plane) falls back to the default. Each value gives
+ * bitwise reproducible results; different values group a cell's deposits differently and
+ * differ by FP32 rounding. PMR_E_INVALID for other values. Not synchronised with work in
+ * flight: set it before enqueueing. */
+int pmr_paint_set_rows(int n, int channels, int rows);
+int pmr_paint_get_rows(int n, int channels, int* rows);
+
 /* Bytes of scratch for pmr_cic_sort with `n_particles` in total and `batch` items. */
 size_t pmr_sort_scratch_bytes(int n_particles_total, int n_mesh, int batch);
 

@@ -9,5 +9,6 @@ from ._lib import (PMR_FP32, PMR_MIXED, PMR_LOSS_DENSITY_L2,  # noqa: F401
                    PmrError)
 from .api import (Config, GradientGraph, LossParams, PMContext, PMForward,  # noqa: F401
                   cic_paint, cic_sort, fft_c2r, fft_get_slab, fft_get_tile, fft_r2c,
-                  fft_set_slab, fft_set_tile, workspace_bytes)
+                  fft_set_slab, fft_set_tile, paint_get_rows, paint_set_rows,
+                  workspace_bytes)
 from . import recon  # noqa: F401,E402

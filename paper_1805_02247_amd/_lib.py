@@ -76,6 +76,8 @@ SIGNATURES = {
     "pmr_fft_set_tile": (ci, [ci, ci, ci, ci, ci]),
     "pmr_fft_get_tile": (ci, [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]),
     "pmr_fft_set_slab": (ci, [ci, ci]),
+    "pmr_paint_set_rows": (ci, [ci, ci, ci]),
+    "pmr_paint_get_rows": (ci, [ci, ci, ctypes.POINTER(ci)]),
     "pmr_fft_get_slab": (ci, [ci, ctypes.POINTER(ci)]),
     "pmr_vec_work_bytes": (sz, [sz, ci]),
     "pmr_vec_dot": (ci, [sz, vp, vp, vp, vp, vp]),

@@ -303,6 +303,17 @@ def fft_set_slab(n, columns):
     L.check(L.lib().pmr_fft_set_slab(n, columns))
 
 
+def paint_get_rows(n, channels):
+    """Rows per wavefront of the CIC paints on an n^3 mesh (0: the default rule)."""
+    c = ctypes.c_int()
+    L.check(L.lib().pmr_paint_get_rows(n, channels, ctypes.byref(c)))
+    return c.value
+
+
+def paint_set_rows(n, channels, rows):
+    L.check(L.lib().pmr_paint_set_rows(n, channels, rows))
+
+
 def fft_r2c(x):
     """Unnormalised 3-D real FFT of [B][n][n][n] float32 -> complex64 [B][n][n][n/2+1]."""
     B, n = x.shape[0], x.shape[-1]

@@ -349,8 +349,12 @@ void launch_keys(const double* x, int log_np3, int total, double scale, int nm, 
   keys_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(x, log_np3, total, scale, nm, keys, frac);
 }
 
-// Rows per wave (see PMR_PAINT_LDS_FLOATS).
+// Rows per wave: the tuned value when set and valid, else the default rule (see
+// PMR_PAINT_LDS_FLOATS).
 static int paint_ty(int nm, int C) {
+  const int want = get_paint_rows(nm, C);
+  if (want > 0 && want <= nm / 2 && (size_t)(TB / 64) * want * C * nm * 4 <= 64 * 1024)
+    return want;
   int ty = PMR_PAINT_LDS_FLOATS / (nm * C);
   if (ty > PMR_PAINT_TY_MAX) ty = PMR_PAINT_TY_MAX;
   if (ty > nm / 2) ty = nm / 2;  // TY + 1 distinct source rows per run

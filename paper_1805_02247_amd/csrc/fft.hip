@@ -133,6 +133,17 @@ int set_fft_tile(int n, int pass, int pc, int nth, int lds) {
 }
 
 int g_fft_slab[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+int g_paint_rows[2][10] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+
+int set_paint_rows(int n, int channels, int rows) {
+  if (n < 16 || n > 512 || (n & (n - 1))) return -1;
+  if (channels != 1 && channels != 3) return -1;
+  if (rows != 0 && rows != 1 && rows != 2 && rows != 4 && rows != 8 && rows != 16) return -1;
+  g_paint_rows[channels == 3][log2i(n)] = rows;
+  return 0;
+}
+
+int get_paint_rows(int n, int channels) { return g_paint_rows[channels == 3][log2i(n)]; }
 
 int set_fft_slab(int n, int columns) {
   if (n < 16 || n > 512 || (n & (n - 1))) return -1;

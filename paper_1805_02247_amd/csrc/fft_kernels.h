@@ -337,12 +337,37 @@ __global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __re
   }
 }
 
-template <int C, int N>
-void paint_r2c(const PaintArgs& a, int batch, float2* out, FieldMap om, hipStream_t s) {
-  constexpr int TY = paint_r2c_ty<N>(C);
+// Rows per wave TY the fused paint can take at size N with C channels: TY <= N / 2, whole
+// workgroups of rows per plane, and the workgroup's padded rows plus twiddles within 160 KB.
+template <int N, int C, int TY>
+constexpr bool paint_r2c_ty_ok() {
+  constexpr int W = NT / 64;
+  using T = ZTile<N>;
+  return TY <= N / 2 && TY <= N / W &&
+         (size_t)W * TY * C * 2 * T::PITCH * 4 + (size_t)N * 8 <= 160 * 1024;
+}
+
+template <int C, int TY, int N>
+void paint_r2c_launch(const PaintArgs& a, int batch, float2* out, FieldMap om, hipStream_t s) {
   constexpr int W = NT / 64;
   const int blocks = batch * N * (N / (W * TY));
   paint_r2c_kernel<C, TY, N><<<blocks, NT, 0, s>>>(a, out, om);
+}
+
+// TY from the tuned table (0: the default rule paint_r2c_ty), falling back to the default
+// when the tuned value is not a valid shape.
+template <int C, int N>
+void paint_r2c(const PaintArgs& a, int batch, float2* out, FieldMap om, hipStream_t s) {
+  const int want = get_paint_rows(N, C);
+#define TYCASE(T)                                                  \
+  if constexpr (paint_r2c_ty_ok<N, C, T>())                        \
+    if (want == T) {                                               \
+      paint_r2c_launch<C, T, N>(a, batch, out, om, s);             \
+      return;                                                      \
+    }
+  TYCASE(1) TYCASE(2) TYCASE(4) TYCASE(8) TYCASE(16)
+#undef TYCASE
+  paint_r2c_launch<C, paint_r2c_ty<N>(C), N>(a, batch, out, om, s);
 }
 
 // Row pairs (k, H - k) of a c2r tile held in registers: pair e = threadIdx + m NT of the

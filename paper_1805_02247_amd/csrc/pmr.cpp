@@ -1266,6 +1266,16 @@ int pmr_fft_set_tile(int n, int pass, int columns, int threads, int staging) {
   return set_fft_tile(n, pass, columns, threads, staging) == 0 ? PMR_OK : PMR_E_INVALID;
 }
 
+int pmr_paint_set_rows(int n, int channels, int rows) {
+  return set_paint_rows(n, channels, rows) == 0 ? PMR_OK : PMR_E_INVALID;
+}
+
+int pmr_paint_get_rows(int n, int channels, int* rows) {
+  if (!rows || !pow2_in(n, 16, 512) || (channels != 1 && channels != 3)) return PMR_E_INVALID;
+  *rows = get_paint_rows(n, channels);
+  return PMR_OK;
+}
+
 int pmr_fft_set_slab(int n, int columns) {
   return set_fft_slab(n, columns) == 0 ? PMR_OK : PMR_E_INVALID;
 }

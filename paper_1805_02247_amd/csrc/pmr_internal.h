@@ -203,6 +203,10 @@ struct TileShape {
 };
 extern TileShape g_fft_tile[3][10];
 
+// Rows per wavefront of the paints per size and channel count (1 or 3; 0: the default rule
+// from PMR_PAINT_LDS_FLOATS and PMR_PAINT_TY_MAX); set by pmr_paint_set_rows (the autotuner).
+int set_paint_rows(int n, int channels, int rows);
+int get_paint_rows(int n, int channels);
 int set_fft_tile(int n, int pass, int pc, int nth, int lds);
 void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
 // kz-slab width of the strided passes per size (0: off); fft_slab_columns gives the width

@@ -11,7 +11,8 @@ supported shape. The second times whole gradient evaluations (forward + adjoint)
 workload given as n_part n_mesh n_out n_steps batch hidden [precision], tuning each pass of
 each mesh size it uses in turn with the others held fixed, which also ranks the operator
 passes (force, force adjoint, smoothing) by their real cost, and then the kz-slab width of
-the force transforms on the force mesh. --write stores the result in
+the force transforms on the force mesh and the rows per wavefront of the paints (one and
+three channels on the force mesh, one on the output mesh). --write stores the result in
 fft_tiles.json next to this file, which the binding applies when it loads the library.
 """
 import argparse
@@ -164,6 +165,24 @@ def _tune_slab(step, n, reps, log):
     return {"columns": best, "all_ms": {str(k): v * 1e3 for k, v in times.items()}}
 
 
+PAINT_ROWS = (1, 2, 4, 8, 16)
+
+
+def _tune_paint(step, n, channels, reps, log):
+    """Rows per wavefront of the paint with `channels` channels on the n^3 mesh."""
+    import ctypes
+    times = {}
+    for rows in PAINT_ROWS:
+        L.check(L.lib().pmr_paint_set_rows(n, channels, rows))
+        c = ctypes.c_int()
+        L.check(L.lib().pmr_paint_get_rows(n, channels, ctypes.byref(c)))
+        times[rows] = _timer(step, reps)
+        log(f"n={n} paint channels={channels} rows={rows}: {times[rows] * 1e3:.3f} ms")
+    best = min(times, key=times.get)
+    L.check(L.lib().pmr_paint_set_rows(n, channels, best))
+    return {"columns": best, "all_ms": {str(k): v * 1e3 for k, v in times.items()}}
+
+
 def tune_workload(n_part, n_mesh, n_out, n_steps, batch, hidden, precision=0, write=False,
                   log=print):
     step = _gradient_step(n_part, n_mesh, n_out, n_steps, batch, hidden, precision)
@@ -171,6 +190,12 @@ def tune_workload(n_part, n_mesh, n_out, n_steps, batch, hidden, precision=0, wr
     reps = 2 if n_mesh >= 512 else 5
     result = _tune_passes(step, sizes, reps, log)
     result[str(n_mesh)]["slab"] = _tune_slab(step, n_mesh, reps, log)
+    # the paint shapes: density (1 channel) and adjoint (3 channels) on the force mesh, and
+    # the final paint on the output mesh
+    result[str(n_mesh)]["paint3"] = _tune_paint(step, n_mesh, 3, reps, log)
+    result[str(n_mesh)]["paint1"] = _tune_paint(step, n_mesh, 1, reps, log)
+    if n_out != n_mesh:
+        result[str(n_out)]["paint1"] = _tune_paint(step, n_out, 1, reps, log)
     if write:
         _write(result)
     return result
@@ -199,6 +224,8 @@ def apply_cache():
                                          int(t.get("staging", 0)))
             elif p == "slab":
                 L.lib().pmr_fft_set_slab(int(n), int(t["columns"]))
+            elif p in ("paint1", "paint3"):
+                L.lib().pmr_paint_set_rows(int(n), int(p[-1]), int(t["columns"]))
     return tiles
 
 

@@ -525,3 +525,25 @@ def test_kz_slab_windows_equal_whole_passes(columns):
     assert np.array_equal(a["loss"], b["loss"])
     assert np.array_equal(a["grad"], b["grad"])
     assert np.array_equal(a["mass"], b["mass"])
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4, 8])
+def test_paint_rows_per_wave_against_oracle(rows):
+    """Every rows-per-wavefront setting of the paints (the density and the adjoint's three
+    channels on the 128^3 force mesh, the final paint on the 64^3 output mesh) against the
+    oracle, and bitwise reproducible for the setting."""
+    require_gpu()
+    say(f"pipeline: paints with {rows} rows per wavefront, 64^3 on 128^3")
+    prob = _problem(64, 128, 64, 200.0, 3, OM.LOSS_LOGNORMAL, 1, hidden=32, R_sm=(2.0,))
+    keys = [(128, 1), (128, 3), (64, 1)]
+    saved = {k: P.paint_get_rows(*k) for k in keys}
+    try:
+        for k in keys:
+            P.paint_set_rows(*k, rows)
+        res = _gpu_run(*prob, hidden=32)
+        again = _gpu_run(*prob, hidden=32)
+    finally:
+        for k, v in saved.items():
+            P.paint_set_rows(*k, v)
+    _compare(*prob, res, TOL_FP32)
+    assert np.array_equal(res["grad"], again["grad"]) and np.array_equal(res["loss"], again["loss"])
