@@ -148,7 +148,9 @@ __device__ __forceinline__ uint32_t cidx(const Corner& c, int ox, int oy, int oz
 struct StepArgs {
   const double* x;    // [B][3][Np^3] positions x_i
   double* x_next;     // positions x_{i+1}
-  float* p;           // momenta, updated in place
+  const float* p_in;  // momenta before the kick (usually p_out: updated in place)
+  float* p_out;       // momenta after the kick
+  float* p_ck;        // nullable: a second copy of p_out (the checkpoint of the next step)
   const Vec3* F;    // [B][nm^3] interleaved force mesh (Fx, Fy, Fz) at x_i
   uint32_t* keys;     // keys of x_{i+1} (nullable)
   Vec3* frac;       // CIC fractions of x_{i+1} on the key mesh, id order
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   double xn[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const float pq = a.p[pi + q * np3] + a.kick * fa[q];
-    a.p[pi + q * np3] = pq;
+    const float pq = a.p_in[pi + q * np3] + a.kick * fa[q];
+    a.p_out[pi + q * np3] = pq;
+    if (a.p_ck) a.p_ck[pi + q * np3] = pq;
     xn[q] = wrap_box(xyz[q] + a.drift * (double)pq, a.box);
     a.x_next[pi + q * np3] = xn[q];
   }
@@ -315,6 +318,7 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
                                                      double half_cell, double D0, float Gp0,
                                                      double c2x, float c2p,
                                                      double* __restrict__ x, float* __restrict__ p,
+                                                     float* __restrict__ p_ck,
                                                      uint32_t* __restrict__ keys,
                                                      Vec3* __restrict__ frac, int key_nm,
                                                      double key_scale) {
@@ -335,6 +339,7 @@ __global__ __launch_bounds__(TB) void za_init_kernel(const float* __restrict__ p
     xn[q] = wrap_box(q0 + D0 * (double)ps + c2x * (double)ps2, box);
     x[pi + q * np3] = xn[q];
     p[pi + q * np3] = Gp0 * ps + c2p * ps2;
+    if (p_ck) p_ck[pi + q * np3] = Gp0 * ps + c2p * ps2;
   }
   Vec3 f;
   keys[g] = key_frac(xn, key_scale, key_nm, item, &f);
@@ -408,14 +413,17 @@ void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* r
   paint_dispatch<1>(a, batch, s);
 }
 
-void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,
-                       Vec3* frac, int batch, int log_np3, int nm, double box, float kick,
-                       double drift, int key_nm, hipStream_t s) {
+void launch_kick_drift(const double* x, double* x_next, const float* p_in, float* p,
+                       float* p_ck, const Vec3* F, uint32_t* keys, Vec3* frac, int batch,
+                       int log_np3, int nm, double box, float kick, double drift, int key_nm,
+                       hipStream_t s) {
   StepArgs a{};
   a.frac = frac;
   a.x = x;
   a.x_next = x_next;
-  a.p = p;
+  a.p_in = p_in ? p_in : p;
+  a.p_out = p;
+  a.p_ck = p_ck;
   a.F = F;
   a.keys = keys;
   a.log_np3 = log_np3;
@@ -472,11 +480,12 @@ void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch
 
 void launch_za_init(const float* psi, const float* psi2, int batch, int np, int log_np3,
                     double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
-                    double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s) {
+                    double* x, float* p, float* p_ck, uint32_t* keys, Vec3* frac, int key_nm,
+                    hipStream_t s) {
   const int total = batch << log_np3;
   za_init_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(psi, psi2, np, log_np3, total, box,
-                                                       half_cell, D0, Gp0, c2x, c2p, x, p, keys,
-                                                       frac, key_nm, (double)key_nm / box);
+                                                       half_cell, D0, Gp0, c2x, c2p, x, p, p_ck,
+                                                       keys, frac, key_nm, (double)key_nm / box);
 }
 
 }  // namespace pmr

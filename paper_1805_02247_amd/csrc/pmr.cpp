@@ -308,7 +308,7 @@ void init_sizes(pmr_ctx* c, const pmr_config* cfg) {
     c->n_fslots = c->n;
     c->n_ck = 0;
   } else {
-    c->n_xslots = c->k + 1;
+    c->n_xslots = c->k;  // ring slots 0..k-1 (segment starts live in the checkpoints)
     c->n_fslots = c->k;
     c->n_ck = (c->n + c->k - 1) / c->k;
   }
@@ -565,6 +565,17 @@ void lpt2_adjoint(pmr_ctx* c, float2* grad) {
 }
 
 double* xslot(pmr_ctx* c, int s) { return c->xs + (size_t)s * c->B * 3 * c->np3; }
+// Where x_i lives: with checkpointing, the positions at the start of a segment (i = j k < n)
+// are the checkpoint j itself (the kick and drift before it write them there, recomputation
+// reads them in place), the others a ring slot i mod k (x_n in slot 0 when k divides n);
+// without, slot i.
+double* xpos(pmr_ctx* c, int i) {
+  if (c->k == 0) return xslot(c, i);
+  if (i % c->k == 0 && i < c->n) return c->ckx + (size_t)(i / c->k) * c->B * 3 * c->np3;
+  return xslot(c, i % c->k);
+}
+// The checkpointed momenta of segment j (the momenta at the start of step j k).
+float* ckpt_p(pmr_ctx* c, int j) { return c->ckp + (size_t)j * c->B * 3 * c->np3; }
 Vec3* fslot(pmr_ctx* c, int s) { return c->F + (size_t)s * c->B * c->nm3; }
 uint32_t* idslot(pmr_ctx* c, int s) { return c->ids + (size_t)s * c->B * c->np3; }
 uint32_t* keyslot(pmr_ctx* c, int s) { return c->skeys + (size_t)s * c->B * c->np3; }
@@ -573,20 +584,21 @@ uint32_t* invslot(pmr_ctx* c, int s) {
   return direct_sorted_values(c) ? c->inv + (size_t)s * c->B * c->np3 : nullptr;
 }
 uint32_t* rowslot(pmr_ctx* c, int s) { return c->rows + (size_t)s * (c->B * c->nm * c->nm + 1); }
-int xs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 int fs_of(pmr_ctx* c, int i) { return c->k == 0 ? i : i % c->k; }
 
 // One forward PM step i: sort x_i, paint, force, kick + drift (keys of x_{i+1} emitted on
 // the force mesh, or on the output mesh after the last step). `order`: the sorted ids of
 // step i - 1 where its slot still holds them (the sort visits the particles in that order,
 // which only makes it faster), else nullptr.
-void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nullptr) {
+// `p_in`: the momenta before step i's kick when they are not in c->p (the checkpoint a
+// recomputed segment starts from).
+void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nullptr,
+             const float* p_in = nullptr) {
   const int B = c->B;
   const int total = (int)(B * c->np3);
-  const int xsl = xs_of(c, i);
   const int fsl = fs_of(c, i);
-  double* x = xslot(c, xsl);
-  double* xn = xslot(c, xsl + 1);
+  double* x = xpos(c, i);
+  double* xn = xpos(c, i + 1);
   {
     ProfScope ps(c, PMR_PROF_SORT, 0.0);
     launch_cell_sort(c->keys, order, total, c->log_nm, (size_t)B * c->nm * c->nm, keyslot(c, fsl),
@@ -641,29 +653,19 @@ void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nul
     // compulsory: x (FP64) and p read and written per particle, the three force channels
     // per cell (the keys and fractions of the next sort count in time only)
     ProfScope ps(c, PMR_PROF_KICK_DRIFT, 72.0 * B * c->np3 + 12.0 * B * c->nm3);
-    launch_kick_drift(x, xn, c->p, F, c->keys, c->frac_id, B, c->log_np3, c->nm, c->cfg.box,
-                      (float)c->kick[i], c->drift[i], key_nm, c->stream);
+    // the momenta that start the next segment also go to its checkpoint
+    float* pck = (c->k > 0 && (i + 1) % c->k == 0 && i + 1 < c->n) ? ckpt_p(c, (i + 1) / c->k)
+                                                                      : nullptr;
+    launch_kick_drift(x, xn, p_in, c->p, pck, F, c->keys, c->frac_id, B, c->log_np3, c->nm,
+                      c->cfg.box, (float)c->kick[i], c->drift[i], key_nm, c->stream);
   }
 }
 
-// Run forward steps [i0, i1) (positions x_{i0} in its slot, momenta in c->p), taking
-// checkpoints at segment starts when `take_ckpt`.
-void pm_run(pmr_ctx* c, int i0, int i1, bool take_ckpt) {
-  const size_t xbytes = c->B * 3 * c->np3 * sizeof(double);
-  const size_t pbytes = c->B * 3 * c->np3 * sizeof(float);
-  for (int i = i0; i < i1; ++i) {
-    if (c->k > 0 && i % c->k == 0) {
-      if (i > i0) HIPC(c, hipMemcpyAsync(xslot(c, 0), xslot(c, c->k), xbytes, hipMemcpyDeviceToDevice, c->stream));
-      if (take_ckpt) {
-        const int j = i / c->k;
-        HIPC(c, hipMemcpyAsync(c->ckx + (size_t)j * c->B * 3 * c->np3, xslot(c, 0), xbytes,
-                       hipMemcpyDeviceToDevice, c->stream));
-        HIPC(c, hipMemcpyAsync(c->ckp + (size_t)j * c->B * 3 * c->np3, c->p, pbytes,
-                       hipMemcpyDeviceToDevice, c->stream));
-      }
-    }
+// Run forward steps [i0, i1) (positions x_{i0} in place, momenta in c->p); the checkpoints
+// are written by the steps themselves (xpos, ckpt_p).
+void pm_run(pmr_ctx* c, int i0, int i1) {
+  for (int i = i0; i < i1; ++i)
     pm_step(c, i, true, i > 0 ? idslot(c, fs_of(c, i - 1)) : nullptr);
-  }
 }
 
 
@@ -867,11 +869,11 @@ int pmr_forward(pmr_ctx* c, const void* modes, float* mass_out, double* loss_out
     launch_za_init(c->psi, second ? c->psi2 : nullptr, B, c->np, c->log_np3, c->cfg.box,
                    0.5 * (c->cfg.box / c->nm), c->D0, (float)c->Gp0,
                    second ? kLpt2 * c->D0 * c->D0 : 0.0,
-                   second ? (float)(2.0 * kLpt2 * c->D0 * c->Gp0) : 0.f, xslot(c, 0), c->p,
-                   c->keys, c->frac_id, key_nm, s);
+                   second ? (float)(2.0 * kLpt2 * c->D0 * c->Gp0) : 0.f, xpos(c, 0), c->p,
+                   c->k > 0 ? ckpt_p(c, 0) : nullptr, c->keys, c->frac_id, key_nm, s);
   }
   // H2-H7: the PM steps
-  pm_run(c, 0, c->n, true);
+  pm_run(c, 0, c->n);
   // H8: final paint on the output mesh
   const int total = (int)(B * c->np3);
   {
@@ -1015,19 +1017,16 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
   for (int i = c->n - 1; i >= 0; --i) {
     if (c->k > 0 && i < resident_lo) {
       const int j = (i / c->k) * c->k;
-      const size_t xbytes = B * 3 * c->np3 * sizeof(double);
-      const size_t pbytes = B * 3 * c->np3 * sizeof(float);
-      HIPC(c, hipMemcpyAsync(xslot(c, 0), c->ckx + (size_t)(j / c->k) * B * 3 * c->np3, xbytes,
-                     hipMemcpyDeviceToDevice, s));
-      HIPC(c, hipMemcpyAsync(c->p, c->ckp + (size_t)(j / c->k) * B * 3 * c->np3, pbytes,
-                     hipMemcpyDeviceToDevice, s));
-      launch_keys(xslot(c, 0), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys, c->frac_id,
-                  s);
+      // the segment starts from its checkpoint, read in place (x) and as the first kick's
+      // input (p)
+      launch_keys(xpos(c, j), c->log_np3, (int)(B * c->np3), scale_m, c->nm, c->keys,
+                  c->frac_id, s);
       const int end = j + c->k < c->n ? j + c->k : c->n;
       // the adjoint of steps j .. end-1 needs x, the sort and F of each step, not the
       // positions the last kick and drift would produce (the next checkpoint)
       for (int q = j; q < end; ++q)
-        pm_step(c, q, q + 1 < end, q > j ? idslot(c, fs_of(c, q - 1)) : nullptr);
+        pm_step(c, q, q + 1 < end, q > j ? idslot(c, fs_of(c, q - 1)) : nullptr,
+                q == j ? ckpt_p(c, j / c->k) : nullptr);
       resident_lo = j;
       // the slots no longer hold the last segment: another adjoint needs a new forward
       c->fwd_done = 0;
@@ -1170,14 +1169,12 @@ long long pmr_debug_copy(pmr_ctx* c, int what, int step, void* dst) {
   switch (what) {
     case PMR_DBG_X: {
       if (step < 0 || step > c->n) return PMR_E_INVALID;
-      int sl;
-      if (c->k == 0) sl = step;
-      else {
+      if (c->k > 0 && step % c->k != 0) {
+        // ring slots hold the last segment (checkpointed steps are always held)
         const int lo = ((c->n - 1) / c->k) * c->k;
         if (step < lo) return PMR_E_STATE;
-        sl = step - lo;
       }
-      src = xslot(c, sl);
+      src = xpos(c, step);
       bytes = B * 3 * c->np3 * sizeof(double);
       break;
     }

@@ -234,10 +234,12 @@ void launch_stream_gather(const uint32_t* ids, const Vec3* src, int total, Vec3*
                           hipStream_t s);
 void launch_paint_mass(const uint32_t* keys, const Vec3* frac, const uint32_t* row_start,
                        int batch, int nm, float mass, float bias, float* out, hipStream_t s);
-// F: interleaved force mesh [B][nm^3] of Vec3 (Fx, Fy, Fz).
-void launch_kick_drift(const double* x, double* x_next, float* p, const Vec3* F, uint32_t* keys,
-                       Vec3* frac, int batch, int log_np3, int nm, double box, float kick,
-                       double drift, int key_nm, hipStream_t s);
+// F: interleaved force mesh [B][nm^3] of Vec3 (Fx, Fy, Fz). p = p_in + kick F (p_in
+// nullable: p itself); p_ck (nullable) receives a second copy of the new p.
+void launch_kick_drift(const double* x, double* x_next, const float* p_in, float* p,
+                       float* p_ck, const Vec3* F, uint32_t* keys, Vec3* frac, int batch,
+                       int log_np3, int nm, double box, float kick, double drift, int key_nm,
+                       hipStream_t s);
 // Position gradient of a step adjoint (or of the final paint: fbar = F = nullptr), computed in
 // sort order and written to g_out in id order:
 //   g = sum_corners dW/dx * (Fbar . F(corner) + mass * dbar(corner)).
@@ -254,7 +256,8 @@ void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch
 // not null, the second-order one: x = wrap(q + D0 psi + c2x psi2), p = Gp0 psi + c2p psi2.
 void launch_za_init(const float* psi, const float* psi2, int batch, int np, int log_np3,
                     double box, double half_cell, double D0, float Gp0, double c2x, float c2p,
-                    double* x, float* p, uint32_t* keys, Vec3* frac, int key_nm, hipStream_t s);
+                    double* x, float* p, float* p_ck, uint32_t* keys, Vec3* frac, int key_nm,
+                    hipStream_t s);
 // Two-network halo model (halo2.hip). Prepared weight block of HALO2_WEIGHT_FLOATS floats.
 constexpr int HALO2_WEIGHT_FLOATS = 448 + (4 * 21 + 2 * 16 + 4 * 8 + 6 * 16) * 64;
 void launch_halo2_prepare(const float* nnp, const float* nnm, float* w, hipStream_t s);

@@ -547,3 +547,28 @@ def test_paint_rows_per_wave_against_oracle(rows):
             P.paint_set_rows(*k, v)
     _compare(*prob, res, TOL_FP32)
     assert np.array_equal(res["grad"], again["grad"]) and np.array_equal(res["loss"], again["loss"])
+
+
+@pytest.mark.parametrize("ckpt", [1, 2, 3])
+def test_checkpointed_positions_equal_stored(ckpt):
+    """With checkpointing the positions at segment starts live in the checkpoints (written
+    by the steps before them) and the last segment in ring slots: every position the
+    context holds after a forward equals the one of the run that keeps every step, bit for
+    bit, and positions the ring no longer holds are refused (PMR_E_STATE)."""
+    require_gpu()
+    say(f"pipeline: positions held with checkpoints every {ckpt} steps, 32^3, 7 steps")
+    prob = _problem(32, 32, 32, 100.0, 7, OM.LOSS_LOGNORMAL, 2, hidden=16, R_sm=(0.0, 2.0))
+    ref = _gpu_run(*prob, hidden=16)
+    res = _gpu_run(*prob, hidden=16, ckpt=ckpt)
+    assert np.array_equal(res["grad"], ref["grad"]) and np.array_equal(res["loss"], ref["loss"])
+    pm = res["pm"]
+    pm.forward(res["modes"], want_mass=False)
+    n = 7
+    lo = ((n - 1) // ckpt) * ckpt
+    for step in range(n + 1):
+        if step % ckpt == 0 or step >= lo:
+            assert np.array_equal(pm.debug("x", step).cpu().numpy(), ref["xs"][step]), step
+        else:
+            with pytest.raises(P.PmrError) as e:
+                pm.debug("x", step)
+            assert e.value.status == P.PMR_E_STATE
