@@ -370,20 +370,25 @@ class GradientGraph:
     The library enqueues only kernels and device-to-device copies (no memsets), so the
     captured graph replays exactly what the eager calls do.
 
-    With `params` (one LossParams or a list), the graph also captures pmr_set_loss_device on
-    a device buffer `self.params` [B][7]; `set_params` writes new stage values into it with a
-    stream-ordered copy, so an anneal stage changes between replays without a host
-    synchronisation in the library and without recapture.
+    With `params` (one LossParams or a list) the loss parameters live in a device buffer
+    `self.params` [B][7]: `set_params` writes new stage values into it with a stream-ordered
+    copy and applies them with pmr_set_loss_device on the stream, once (the data term of the
+    target is recomputed there), so an anneal stage changes between replays without a host
+    synchronisation and without recapture. With capture_params=True the graph itself also
+    contains pmr_set_loss_device on that buffer, so every replay reads the buffer as it is
+    (at the cost of recomputing the data term in every replay).
     """
 
-    def __init__(self, pmctx, modes, warmup=1, params=None):
+    def __init__(self, pmctx, modes, warmup=1, params=None, capture_params=False):
         self.pm = pmctx
         B = pmctx.cfg.batch
         self.modes = modes.clone().contiguous()
         self.params = None
+        self.capture_params = bool(capture_params)
         if params is not None:
             self.params = torch.tensor(loss_param_rows(params, B), dtype=torch.float64,
                                        device=pmctx.device)
+            pmctx.set_loss_device(self.params)
         self.loss_bar = torch.ones(B, dtype=torch.float64, device=pmctx.device)
         self.loss = torch.empty(B, 3, dtype=torch.float64, device=pmctx.device)
         self.grad = torch.empty(B, pmctx.n_modes, dtype=torch.complex64, device=pmctx.device)
@@ -405,11 +410,13 @@ class GradientGraph:
             raise ValueError("GradientGraph was captured without device loss parameters")
         rows = torch.tensor(loss_param_rows(params, self.pm.cfg.batch), dtype=torch.float64)
         self.params.copy_(rows.pin_memory(), non_blocking=True)
+        if not self.capture_params:
+            self.pm.set_loss_device(self.params)
 
     def _enqueue(self):
         pm = self.pm
         pm._sync_stream()
-        if self.params is not None:
+        if self.params is not None and self.capture_params:
             L.check(L.lib().pmr_set_loss_device(pm._ctx, _ptr(self.params)))
         L.check(L.lib().pmr_forward(pm._ctx, _ptr(self.modes), None, _ptr(self.loss)))
         L.check(L.lib().pmr_adjoint(pm._ctx, _ptr(self.loss_bar), None, _ptr(self.grad)))

@@ -3,10 +3,11 @@ realisation, run over an anneal schedule of loss stages, and the binned two-poin
 statistics of Sec. 4.3 that score the result against the true modes.
 
 Every vector operation runs in libpmr kernels: FP64 inner products with device-resident
-scalars, the two-loop recursion (pmr_lbfgs_direction) and the updates. The host keeps the
-control flow: the Armijo test on the loss copied back once per evaluation, the curvature
-test on three inner products copied back once per accepted step, the history ring and the
-stopping rule. The parameters are all stored real and imaginary parts of the modes, so the
+scalars, the two-loop recursion (pmr_lbfgs_direction) and the updates; an evaluation can be
+one HIP-graph replay of forward + adjoint (GradientGraph with device loss parameters). The
+host keeps the control flow: the Armijo test on the loss copied back once per evaluation,
+the curvature test on three inner products copied back once per accepted step, the history
+ring and the stopping rule. The parameters are all stored real and imaginary parts of the modes, so the
 complex64 mode tensor is used as a float32 vector of twice its length.
 
 Readings (the paper names L-BFGS and the anneal but gives no optimiser parameters):
@@ -67,16 +68,19 @@ def _floats(modes):
 class StageResult:
     params: LossParams
     losses: list = field(default_factory=list)
+    times: list = field(default_factory=list)  # wall time (s from the stage start) per loss
     evals: int = 0
     iters: int = 0
     reason: str = "max_iter"
     seconds: float = 0.0
 
 
-def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop_below=None):
+def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop_below=None,
+             graph=None):
     """L-BFGS from `modes` (complex64 [1][n_modes], updated in place) with the loss already
-    set on `pm` (a PMContext of batch 1). stop_below: optional loss at which to stop early.
-    Returns a StageResult."""
+    set on `pm` (a PMContext of batch 1), or on `graph` (an api.GradientGraph of pm captured
+    with device loss parameters, whose replays then evaluate forward + adjoint as one graph
+    launch). stop_below: optional loss at which to stop early. Returns a StageResult."""
     if pm.cfg.batch != 1:
         raise ValueError("the driver optimises one realisation (batch 1)")
     dev = modes.device
@@ -98,13 +102,19 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
     t0 = time.perf_counter()
 
     def evaluate(src, grad_out):
+        res.evals += 1
+        if graph is not None:
+            graph.modes.view(torch.float32).reshape(-1).copy_(src)
+            loss, grad = graph.replay()
+            grad_out.copy_(grad.view(torch.float32).reshape(-1))
+            return float(loss[0, 0].item())
         _, loss = pm.forward(src.view(torch.complex64).reshape(1, -1), want_mass=False)
         pm.adjoint(ones, out=grad_out.view(torch.complex64).reshape(1, -1))
-        res.evals += 1
         return float(loss[0, 0].item())
 
     f = evaluate(x, g)
     res.losses.append(f)
+    res.times.append(time.perf_counter() - t0)
     order = []  # history slots, newest first (at most m)
     for it in range(max_iter):
         ops.dot(g, g, tmp[0:1])
@@ -146,6 +156,7 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
         rel = (f - fn) / abs(f) if f != 0.0 else 0.0
         f = fn
         res.losses.append(f)
+        res.times.append(time.perf_counter() - t0)
         res.iters = it + 1
         if log:
             log(it, f, t, res.evals)
@@ -160,13 +171,21 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
     return res
 
 
-def reconstruct(pm, modes, stages, max_iter=100, log=None):
+def reconstruct(pm, modes, stages, max_iter=100, log=None, graph=None, stop_below=None):
     """Runs minimize over the anneal stages (LossParams each) in order, from `modes`
-    (updated in place). Returns the list of StageResult."""
+    (updated in place); with `graph` (a GradientGraph of pm captured with device loss
+    parameters) each stage's parameters are written into the graph's parameter buffer and
+    every evaluation is a graph replay. stop_below applies to the last stage. Returns the
+    list of StageResult."""
     out = []
-    for p in stages:
-        pm.set_loss(p)
-        r = minimize(pm, modes, max_iter=max_iter, log=log)
+    for i, p in enumerate(stages):
+        if graph is not None:
+            graph.set_params(p)
+        else:
+            pm.set_loss(p)
+        last = i == len(stages) - 1
+        r = minimize(pm, modes, max_iter=max_iter, log=log, graph=graph,
+                     stop_below=stop_below if last else None)
         r.params = p
         out.append(r)
     return out

@@ -65,11 +65,13 @@ def test_graph_replay_matches_eager():
     assert not torch.equal(ref2[0], ref0[0])
 
 
-def test_graph_with_device_loss_params():
-    """Loss parameters captured from device memory (pmr_set_loss_device inside the graph):
-    new anneal-stage values written into the device buffer between replays give, bit for bit,
-    the eager gradient at those values (set through the host call), without recapture; an
-    invalid item (sigma_N = 0) gives a NaN loss for that item only."""
+@pytest.mark.parametrize("capture", [True, False])
+def test_graph_with_device_loss_params(capture):
+    """Loss parameters from device memory, read by pmr_set_loss_device inside the graph
+    (capture) or applied on the stream when they change: new anneal-stage values written
+    into the device buffer between replays give, bit for bit, the eager gradient at those
+    values (set through the host call), without recapture; an invalid item (sigma_N = 0)
+    gives a NaN loss for that item only."""
     require_gpu()
     n, box, B = 32, 100.0, 2
     say("graph: device loss parameters, stage changes between replays")
@@ -97,14 +99,14 @@ def test_graph_with_device_loss_params():
         return loss.clone(), g.clone()
 
     refs = [eager(st) for st in stages]
-    G = P.GradientGraph(pm, m, params=stages[0])
+    G = P.GradientGraph(pm, m, params=stages[0], capture_params=capture)
     for rep, k in enumerate((0, 1, 2, 1, 0)):
         G.set_params(stages[k])
         loss, grad = G.replay()
         torch.cuda.synchronize()
         assert torch.equal(loss, refs[k][0]), (rep, k)
         assert torch.equal(grad, refs[k][1]), (rep, k)
-        eager(stages[(k + 1) % 3])  # eager work between replays
+        eager(stages[(k + 1) % 3])  # eager work (other parameters) between replays
     bad = [P.LossParams(M0=1.0, R_sm=4.0, sigma_N=0.0), stages[0][1]]
     G.set_params(bad)
     loss, _ = G.replay()

@@ -226,3 +226,41 @@ def test_gpu_anneal_stages_two_network_model():
     pm2.set_loss(stages[1])
     _, loss = pm2.forward(m2, want_mass=False)
     assert float(loss[0, 0]) == out[1].losses[0]
+
+
+def test_gpu_graph_driven_stages_retrace_eager():
+    """The driver with every evaluation a replay of one captured forward + adjoint graph
+    whose stage parameters live in device memory (written between stages, no recapture)
+    follows the eager driver's trajectory bit for bit: the same losses at every iteration
+    and the same final modes, over two anneal stages."""
+    require_gpu()
+    say("recon: graph-driven stages vs eager, 16^3 log-normal")
+    n, box = 16, 100.0
+    ocfg = OM.Config(box, n, n, n, 3, loss_kind=OM.LOSS_LOGNORMAL)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    s_true = OM.linear_modes(synth.white_noise(31, n), box, power)
+    w = synth.mlp_weights(3, 8)
+    target = OM.forward(ocfg, s_true, inv, np.ones((n, n, n)), OM.default_params(), w)["mass"]
+    s0 = np.sqrt(0.1) * OM.linear_modes(synth.white_noise(32, n), box, power)
+    M0 = float(np.median(target))
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, mlp_hidden=8, box=box)
+    stages = [P.LossParams(M0=M0, R_sm=2.0), P.LossParams(M0=0.8 * M0, R_sm=0.0)]
+
+    def run(graph):
+        pm = P.PMContext(cfg, DEV)
+        pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+        pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+        pm.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+        pm.set_loss(stages[0])
+        modes = torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+        G = P.GradientGraph(pm, modes, params=stages[0]) if graph else None
+        out = R.reconstruct(pm, modes, stages, max_iter=5, graph=G)
+        torch.cuda.synchronize()
+        return [st.losses for st in out], modes.cpu().numpy()
+
+    eager_losses, eager_modes = run(False)
+    graph_losses, graph_modes = run(True)
+    assert graph_losses == eager_losses
+    assert np.array_equal(graph_modes, eager_modes)
+    assert len(eager_losses[0]) > 2 and len(eager_losses[1]) > 1
