@@ -162,9 +162,37 @@ struct StepArgs {
   double key_scale;
 };
 
+// First particle of block L when the lattice rows (item, i, j, :) are visited in patches of
+// 2^logP x 2^logP rows (j fastest within a patch, then i, then the patch): a lattice row
+// holds np / TB whole blocks, and the force-mesh rows a patch reads overlap those of its
+// neighbours in both i and j, so one XCD's blocks in flight share more of their corner
+// rows in L2 than with the plain row order. A bijection of the block indices, so the
+// result does not depend on it.
+__device__ __forceinline__ int patch_block_start(int L, int log_np, int logP) {
+  const int np = 1 << log_np;
+  const int bpr = np / TB;
+  const int kb = L % bpr;
+  int r = L / bpr;
+  const int item = r >> (2 * log_np);
+  r &= (1 << (2 * log_np)) - 1;
+  const int P = 1 << logP, tiles = np >> logP;
+  const int jj = r & (P - 1);
+  r >>= logP;
+  const int ii = r & (P - 1);
+  r >>= logP;
+  const int pj = r % tiles, pi = r / tiles;
+  const int i = pi * P + ii, j = pj * P + jj;
+  return (item << (3 * log_np)) + ((i * np + j) << log_np) + kb * TB;
+}
+constexpr int KD_PATCH_LOG = 5;  // 32 x 32 lattice rows per patch
+
 // p += kick * F(x_i);  x_{i+1} = wrap(x_i + drift * p);  key(x_{i+1})
 __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
-  const int g = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const int log_np = a.log_np3 / 3;
+  const int g = ((1 << log_np) >= TB && log_np >= KD_PATCH_LOG)
+                    ? patch_block_start(L, log_np, KD_PATCH_LOG) + threadIdx.x
+                    : L * TB + threadIdx.x;
   if (g >= a.total) return;
   const size_t np3 = (size_t)1 << a.log_np3;
   const int item = g >> a.log_np3;
