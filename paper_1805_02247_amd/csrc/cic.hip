@@ -248,6 +248,10 @@ struct AdjPosArgs {
   float scale, mass;
 };
 
+// WF: the force term is present (F and fbar set). A compile-time switch rather than a
+// per-corner test of F, so that the 16 corner loads are issued together instead of each
+// waiting behind a branch.
+template <bool WF>
 __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
   const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= a.total) return;
@@ -262,13 +266,13 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
   const float f[3] = {fr.x, fr.y, fr.z};
   const size_t cells = (size_t)1 << (3 * lg);
   float fb[3] = {0.f, 0.f, 0.f};
-  if (a.fbar) {
+  if (WF) {
     const Vec3 v = a.fbar[j];
     fb[0] = v.x;
     fb[1] = v.y;
     fb[2] = v.z;
   }
-  const Vec3* F = a.F ? a.F + (size_t)item * cells : nullptr;
+  const Vec3* F = WF ? a.F + (size_t)item * cells : nullptr;
   const float* D = a.dbar + (size_t)item * cells;
   const float s = a.scale;
   float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
     const uint32_t ci = ((ox ? i1[0] : i0[0]) * (uint32_t)nm + (oy ? i1[1] : i0[1])) * (uint32_t)nm +
                         (oz ? i1[2] : i0[2]);
     float v = a.mass * D[ci];
-    if (F) {
+    if (WF) {
       const Vec3 fv = F[ci];
       v += fb[0] * fv.x + fb[1] * fv.y + fb[2] * fv.z;
     }
@@ -484,7 +488,10 @@ void launch_adjoint_positions(const uint32_t* keys, const Vec3* frac, const Vec3
   a.total = total;
   a.scale = (float)((double)nm / box);
   a.mass = mass;
-  adjoint_positions_kernel<<<(total + TB - 1) / TB, TB, 0, s>>>(a);
+  if (a.F && a.fbar)
+    adjoint_positions_kernel<true><<<(total + TB - 1) / TB, TB, 0, s>>>(a);
+  else
+    adjoint_positions_kernel<false><<<(total + TB - 1) / TB, TB, 0, s>>>(a);
 }
 
 void launch_adjoint_update(float* xbar, float* pbar, const Vec3* gpos, int batch, int log_np3,
