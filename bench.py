@@ -612,12 +612,15 @@ def reconstruction_leg(dev, iterations=200, nbins=64):
     scatter exp(0.3 eps) (eps seed 4001); start = independent modes (seed 4002) at 10% of the
     fiducial power; L-BFGS over the anneal stages R_sm = 4, 2, 1, 0 Mpc/h at M0 = the 75th
     percentile of the target (25% of the cells above it), then R_sm = 1, 0 at the median
-    (50% above), at most iterations / 6 iterations per stage; every evaluation is one replay
-    of a captured forward + adjoint graph whose stage parameters live in device memory. Run
-    in FP32 and in mixed precision: wall time, evaluations, final loss, the wall time each
-    takes to reach a common target loss in the last stage (the larger of the two final
-    losses, which both runs reach), and the cross-correlation r_c of the recovered with the
-    true modes per k shell."""
+    (50% above), at most iterations / 6 iterations per stage. The line search runs on the
+    device: every evaluation is one replay of a captured graph holding the trial point,
+    forward, adjoint, Armijo test, history update and next direction, with the stage
+    parameters in device memory; the host reads the status every 2 replays. Run in FP32
+    and in mixed precision: wall time, evaluations, final loss, the wall time each takes to
+    reach a common target loss in the last stage (the larger of the two final losses,
+    which both runs reach), and the cross-correlation r_c of the recovered with the true
+    modes per k shell. Beside them the FP32 run with the host-side line search (one host
+    round trip per evaluation): its time and whether its losses equal the device run's."""
     import torch
 
     import synth
@@ -635,10 +638,12 @@ def reconstruction_leg(dev, iterations=200, nbins=64):
     true = modes(4000)
     out = {"workload": "128^3 particles/mesh, L = 400 Mpc/h, 5 PM steps, 3-32-32-1 network, "
                        "one realisation", "iteration_budget": iterations,
-           "evaluation": "one HIP-graph replay of forward + adjoint per evaluation"}
+           "evaluation": "one HIP-graph replay per evaluation: trial point, forward, adjoint, "
+                         "line-search test and L-BFGS update on the device"}
     target, stages = None, None
     runs = {}
-    for name, prec in (("fp32", P.PMR_FP32), ("mixed", P.PMR_MIXED)):
+    for name, prec, driver in (("fp32", P.PMR_FP32, "device"), ("mixed", P.PMR_MIXED, "device"),
+                               ("fp32_host_line_search", P.PMR_FP32, "host")):
         cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=steps, mlp_hidden=H,
                        precision=prec, box=box, loss_kind=P.PMR_LOSS_LOGNORMAL)
         pm = P.PMContext(cfg, dev)
@@ -658,18 +663,32 @@ def reconstruction_leg(dev, iterations=200, nbins=64):
         pm.set_loss(stages[0])
         x = modes(4002, np.sqrt(0.1))
         x0 = x.clone()
-        G = P.GradientGraph(pm, x, params=stages[0])
+        per_stage = iterations // len(stages)
+        if driver == "device":
+            G = R.DeviceLBFGS(pm, x, stages[0], max_iter=per_stage, check_every=2)
+            kw = dict(device=G)
+        else:
+            G = P.GradientGraph(pm, x, params=stages[0])
+            kw = dict(graph=G, max_iter=per_stage)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = R.reconstruct(pm, x, stages, max_iter=iterations // len(stages), graph=G)
+        res = R.reconstruct(pm, x, stages, **kw)
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
         ev = sum(r.evals for r in res)
         leg = {"seconds": T, "iterations": sum(r.iters for r in res), "evaluations": ev,
                "ms_per_evaluation": 1e3 * T / ev, "final_loss": res[-1].losses[-1],
-               "stages": [{"R_sm": st.R_sm, "M0": st.M0,
-                           "iters": r.iters, "evals": r.evals, "loss": r.losses[-1],
-                           "stop": r.reason} for r, st in zip(res, stages)]}
+               "line_search": driver}
+        if driver == "device":
+            leg["graph_replays"] = sum(r.replays for r in res)
+        if driver == "host":
+            leg["losses_equal_device_run"] = [r.losses for r in res] == runs["fp32"][2]
+            out[name] = leg
+            del G, pm
+            torch.cuda.empty_cache()
+            continue
+        leg["stages"] = [{"R_sm": st.R_sm, "M0": st.M0, "iters": r.iters, "evals": r.evals,
+                          "loss": r.losses[-1], "stop": r.reason} for r, st in zip(res, stages)]
         rc, _, tf = R.metrics(R.power_bins(true, x, n, box, nbins))
         leg["r_c"] = [round(float(v), 4) for v in rc]
         leg["transfer"] = [round(float(v), 4) for v in tf]
@@ -677,14 +696,14 @@ def reconstruction_leg(dev, iterations=200, nbins=64):
             rc0, _, _ = R.metrics(R.power_bins(true, x0, n, box, nbins))
             out["r_c_start"] = [round(float(v), 4) for v in rc0]
         before_last = sum(r.seconds for r in res[:-1])
-        runs[name] = (before_last, res[-1])
+        runs[name] = (before_last, res[-1], [r.losses for r in res])
         out[name] = leg
         del G, pm
         torch.cuda.empty_cache()
     # the wall time to the common target: the stages before the last, then the first loss of
     # the last stage at or below the target
     tgt = max(out["fp32"]["final_loss"], out["mixed"]["final_loss"])
-    for name, (before, last) in runs.items():
+    for name, (before, last, _) in runs.items():
         hit = next(t for loss, t in zip(last.losses, last.times) if loss <= tgt)
         out[name]["seconds_to_common_target"] = before + hit
     out["common_target_loss"] = tgt

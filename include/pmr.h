@@ -365,6 +365,101 @@ int pmr_lbfgs_direction_noalloc(size_t n, int m, int count, const int* order, co
                                 const float* Y, const double* sy, const double* yy,
                                 const float* g, float* d, void* stream);
 
+/* ---- L-BFGS with its line search on the device (Sec. 5.2) ----
+ * One optimiser iteration as device work only, so that a whole evaluation -- trial point,
+ * forward, adjoint, Armijo test, history update, next direction -- can be one HIP-graph
+ * replay with no host round trip; the host reads the status block every few replays.
+ * The rules are those of the host driver: the first step of a stage (or after a
+ * non-descent direction clears the history) has length one along -g (t = 1 / |g|), later
+ * searches start at t = 1; a trial at step t is accepted when f(x + t d) <= f + c1 t g.d,
+ * else t is halved, and the search fails after max_halvings + 1 rejected trials; an
+ * accepted step (s = x_t - x, y = g_t - g) enters the history (newest first, at most m
+ * pairs; the oldest leaves) only if s.y > curvature_eps |s| |y|; the stage ends when the
+ * relative decrease (f - f_t) / |f| of an accepted step falls below rel_tol (not for the
+ * unit probe step), when f_t <= stop_below, at a zero gradient, or after max_iter accepted
+ * steps. Scalars are FP64 in device memory, with the products, sums, square roots and
+ * quotients of those tests rounded once each in the order written above, so the decisions
+ * and iterates equal, bit for bit, those of a host driver evaluating the same expressions
+ * in FP64 on the same losses and inner products.
+ *
+ * state: device buffer of pmr_lbfgs_state_bytes(max_iter) bytes. It starts with a
+ * pmr_lbfgs_state (the host may copy that prefix back to read status, iters, evals, f)
+ * followed by f_hist[max_iter + 1] (double: the loss after each accepted step, f_hist[0]
+ * at the start) and clock_hist[max_iter + 1] (long long: the device wall clock, at
+ * clock_khz ticks per ms, when each was reached). A zeroed state is PMR_LBFGS_IDLE, in
+ * which pmr_lbfgs_trial and pmr_lbfgs_update do nothing. S, Y: device [m + 1][n] floats
+ * (the history and one slot for the candidate pair); sy, yy: device doubles [m + 1]; work:
+ * pmr_vec_work_bytes(n, 0) bytes. All calls enqueue kernels only (no copies, no memsets)
+ * and return without synchronising. */
+enum {
+  PMR_LBFGS_IDLE = 0,        /* zeroed state: trial and update do nothing */
+  PMR_LBFGS_RUNNING = 1,
+  PMR_LBFGS_CONVERGED = 2,   /* relative decrease below rel_tol */
+  PMR_LBFGS_STATIONARY = 3,  /* g = 0 */
+  PMR_LBFGS_LINE_SEARCH = 4, /* max_halvings + 1 rejected trials */
+  PMR_LBFGS_MAX_ITER = 5,
+  PMR_LBFGS_TARGET = 6       /* loss at or below stop_below */
+};
+enum { PMR_LBFGS_MAX_M = 64 };
+
+typedef struct pmr_lbfgs_params {
+  int m;              /* history pairs, 1..PMR_LBFGS_MAX_M */
+  int max_iter;       /* accepted steps per stage, >= 1 */
+  int max_halvings;   /* >= 0 */
+  double c1;          /* Armijo constant */
+  double curvature_eps;
+  double rel_tol;
+  double stop_below;  /* -INFINITY for none */
+} pmr_lbfgs_params;
+
+typedef struct pmr_lbfgs_state {
+  double f;       /* loss at the current point x */
+  double t;       /* step of the next trial */
+  double gd;      /* g.d at x */
+  double gg;      /* g.g at x */
+  double rel;     /* relative decrease of the last accepted step */
+  double ft;      /* loss at the last trial */
+  double ss;      /* s.s of the last candidate pair */
+  double beta;    /* two-loop scratch */
+  int status;     /* PMR_LBFGS_* */
+  int iters;      /* accepted steps */
+  int evals;      /* evaluations: the starting one and every trial */
+  int count;      /* history pairs held */
+  int halvings;   /* rejected trials of the current search */
+  int probe;      /* the current search is the unit-length probe step */
+  int accepted;   /* the last trial was accepted */
+  int slot;       /* slot of the last candidate pair */
+  int reset;      /* the last direction was not a descent direction */
+  int pad;
+  long long clock_khz;
+  pmr_lbfgs_params p;
+  int order[PMR_LBFGS_MAX_M];          /* history slots, newest first */
+  double alpha[PMR_LBFGS_MAX_M + 1];   /* two-loop scalars per slot */
+} pmr_lbfgs_state;
+
+size_t pmr_lbfgs_state_bytes(int max_iter);
+
+/* Starts a stage at x from the loss (device double) and gradient g at x: history cleared,
+ * f_hist[0] = loss, then the first direction (d = -g) and t = 1 / |g| (PMR_LBFGS_STATIONARY
+ * at g = 0). PMR_E_INVALID for bad parameters or pointers, PMR_E_HIP if the device clock
+ * rate cannot be read. */
+int pmr_lbfgs_init(size_t n, const pmr_lbfgs_params* params, void* state, const double* loss,
+                   const float* g, float* d, const float* S, const float* Y, const double* sy,
+                   const double* yy, void* work, void* stream);
+
+/* xt = x + t d with the state's t, while the state is PMR_LBFGS_RUNNING (else nothing). */
+int pmr_lbfgs_trial(size_t n, const void* state, const float* x, const float* d, float* xt,
+                    void* stream);
+
+/* After the evaluation at xt (its loss, device double, and gradient gt): the Armijo test;
+ * on acceptance the candidate pair, the curvature test and history update, x = xt,
+ * g = gt, the stopping rules and the next direction in d with its t; on rejection t is
+ * halved. m must equal the params' m given to pmr_lbfgs_init. Nothing while the state is
+ * not PMR_LBFGS_RUNNING. */
+int pmr_lbfgs_update(size_t n, int m, void* state, const double* loss, float* x, float* g,
+                     const float* xt, const float* gt, float* d, float* S, float* Y, double* sy,
+                     double* yy, void* work, void* stream);
+
 /* Bytes of device scratch for pmr_power_bins with `nbins` shells. */
 size_t pmr_power_work_bytes(int nbins);
 

@@ -39,6 +39,32 @@ class PmrLossParams(ctypes.Structure):
                 ("prior_weight", ctypes.c_double), ("logistic_a", ctypes.c_double)]
 
 
+class PmrLbfgsParams(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_halvings", ctypes.c_int),
+                ("c1", ctypes.c_double), ("curvature_eps", ctypes.c_double),
+                ("rel_tol", ctypes.c_double), ("stop_below", ctypes.c_double)]
+
+
+PMR_LBFGS_MAX_M = 64
+
+
+class PmrLbfgsState(ctypes.Structure):
+    """The leading block of the device-driven L-BFGS state (pmr_lbfgs_state)."""
+    _fields_ = [("f", ctypes.c_double), ("t", ctypes.c_double), ("gd", ctypes.c_double),
+                ("gg", ctypes.c_double), ("rel", ctypes.c_double), ("ft", ctypes.c_double),
+                ("ss", ctypes.c_double), ("beta", ctypes.c_double), ("status", ctypes.c_int),
+                ("iters", ctypes.c_int), ("evals", ctypes.c_int), ("count", ctypes.c_int),
+                ("halvings", ctypes.c_int), ("probe", ctypes.c_int), ("accepted", ctypes.c_int),
+                ("slot", ctypes.c_int), ("reset", ctypes.c_int), ("pad", ctypes.c_int),
+                ("clock_khz", ctypes.c_longlong), ("p", PmrLbfgsParams),
+                ("order", ctypes.c_int * PMR_LBFGS_MAX_M),
+                ("alpha", ctypes.c_double * (PMR_LBFGS_MAX_M + 1))]
+
+
+PMR_LBFGS_STATUS = {0: "idle", 1: "running", 2: "converged", 3: "stationary", 4: "line_search",
+                    5: "max_iter", 6: "target_loss"}
+
+
 class PmrError(RuntimeError):
     def __init__(self, msg, status=None):
         super().__init__(msg)
@@ -86,6 +112,11 @@ SIGNATURES = {
                                  vp]),
     "pmr_lbfgs_direction_noalloc": (ci, [sz, ci, ci, ctypes.POINTER(ci), vp, vp, vp, vp, vp,
                                          vp, vp]),
+    "pmr_lbfgs_state_bytes": (sz, [ci]),
+    "pmr_lbfgs_init": (ci, [sz, ctypes.POINTER(PmrLbfgsParams), vp, vp, vp, vp, vp, vp, vp, vp,
+                            vp, vp]),
+    "pmr_lbfgs_trial": (ci, [sz, vp, vp, vp, vp, vp]),
+    "pmr_lbfgs_update": (ci, [sz, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "pmr_power_work_bytes": (sz, [ci]),
     "pmr_power_bins": (ci, [ci, cd, vp, vp, ci, vp, vp, sz, vp]),
     "pmr_profile_begin": (ci, [vp, ci, ci]),

@@ -34,10 +34,14 @@ int dot_blocks(size_t n) {
   return (int)(b < 1 ? 1 : b > DOT_BLOCKS ? DOT_BLOCKS : b);
 }
 
+// The loop bodies below are shared by the kernels with host scalars and the kernels of the
+// device-driven optimiser, so both evaluate every element with the same operations: a
+// rounded FP32 product then one fused multiply-add, products exact in FP64.
+
 // partial[block] = sum over this block's grid-stride elements of a[i] b[i] (FP64).
-__global__ __launch_bounds__(TB) void dot_partial_kernel(const float* __restrict__ a,
-                                                         const float* __restrict__ b, size_t n,
-                                                         double* __restrict__ partial) {
+__device__ __forceinline__ void dot_partial_body(const float* __restrict__ a,
+                                                 const float* __restrict__ b, size_t n,
+                                                 double* __restrict__ partial) {
   __shared__ double sh[TB];
   double acc = 0.0;
   const size_t stride = (size_t)gridDim.x * TB;
@@ -48,9 +52,9 @@ __global__ __launch_bounds__(TB) void dot_partial_kernel(const float* __restrict
 }
 
 // out = (sum of the partials) / den (den: device scalar, or 1).
-__global__ __launch_bounds__(TB) void dot_final_kernel(const double* __restrict__ partial, int np,
-                                                       const double* __restrict__ den,
-                                                       double* __restrict__ out) {
+__device__ __forceinline__ void dot_final_body(const double* __restrict__ partial, int np,
+                                               const double* __restrict__ den,
+                                               double* __restrict__ out) {
   __shared__ double sh[TB];
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += TB) acc += partial[i];
@@ -58,31 +62,56 @@ __global__ __launch_bounds__(TB) void dot_final_kernel(const double* __restrict_
   if (threadIdx.x == 0) out[0] = den ? s / den[0] : s;
 }
 
+__device__ __forceinline__ void axpy_body(size_t n, float c, const float* __restrict__ x,
+                                          float* __restrict__ y) {
+  const size_t stride = (size_t)gridDim.x * TB;
+  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride)
+    y[i] = __fmaf_rn(c, x[i], y[i]);
+}
+
+__device__ __forceinline__ void scale_body(size_t n, float c, float* __restrict__ x) {
+  const size_t stride = (size_t)gridDim.x * TB;
+  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride) x[i] *= c;
+}
+
+__device__ __forceinline__ void axpby_body(size_t n, float alpha, const float* a, float beta,
+                                           const float* b, float* out) {
+  const size_t stride = (size_t)gridDim.x * TB;
+  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride)
+    out[i] = __fmaf_rn(beta, b[i], __fmul_rn(alpha, a[i]));
+}
+
+__global__ __launch_bounds__(TB) void dot_partial_kernel(const float* __restrict__ a,
+                                                         const float* __restrict__ b, size_t n,
+                                                         double* __restrict__ partial) {
+  dot_partial_body(a, b, n, partial);
+}
+
+__global__ __launch_bounds__(TB) void dot_final_kernel(const double* __restrict__ partial, int np,
+                                                       const double* __restrict__ den,
+                                                       double* __restrict__ out) {
+  dot_final_body(partial, np, den, out);
+}
+
 // y += sign * (A - B) * x with A, B device scalars (B nullable).
 __global__ __launch_bounds__(TB) void axpy_dev_kernel(size_t n, const double* __restrict__ A,
                                                       const double* __restrict__ B, double sign,
                                                       const float* __restrict__ x,
                                                       float* __restrict__ y) {
-  const float c = (float)(sign * (A[0] - (B ? B[0] : 0.0)));
-  const size_t stride = (size_t)gridDim.x * TB;
-  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride) y[i] += c * x[i];
+  axpy_body(n, (float)(sign * (A[0] - (B ? B[0] : 0.0))), x, y);
 }
 
 // x *= sign * num / den (device scalars).
 __global__ __launch_bounds__(TB) void scale_dev_kernel(size_t n, const double* __restrict__ num,
                                                        const double* __restrict__ den, double sign,
                                                        float* __restrict__ x) {
-  const float c = (float)(sign * num[0] / den[0]);
-  const size_t stride = (size_t)gridDim.x * TB;
-  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride) x[i] *= c;
+  scale_body(n, (float)(sign * num[0] / den[0]), x);
 }
 
 // out = alpha a + beta b (host scalars; out may alias a or b).
 __global__ __launch_bounds__(TB) void axpby_kernel(size_t n, float alpha, const float* a,
                                                    float beta, const float* b, float* out) {
-  const size_t stride = (size_t)gridDim.x * TB;
-  for (size_t i = (size_t)blockIdx.x * TB + threadIdx.x; i < n; i += stride)
-    out[i] = alpha * a[i] + beta * b[i];
+  axpby_body(n, alpha, a, beta, b, out);
 }
 
 unsigned stream_grid(size_t n) {
@@ -200,6 +229,259 @@ void launch_lbfgs_direction(size_t n, int m, int count, const int* order, const 
   axpby_kernel<<<gs, TB, 0, s>>>(n, -1.f, d, 0.f, d, d);
 }
 
+// ---------------------------------------------------------------- device-driven L-BFGS
+// Every kernel below reads the optimiser state first and returns at once (all threads
+// alike) unless the state is in the phase it belongs to; so a fixed sequence of launches --
+// capturable as a graph -- performs whichever branch the device-side tests chose.
+namespace {
+
+enum Gate {
+  G_RUN = 0,   // the stage is running
+  G_ACC = 1,   // the last trial was accepted (the pair and the move to x_t)
+  G_DIR = 2,   // accepted and still running (the next direction)
+  G_RESET = 3  // ... and that direction was not a descent direction
+};
+constexpr int NO_SLOT = -1;   // the vector as given
+constexpr int NEW_SLOT = -2;  // slot of the candidate pair (state.slot)
+// j >= 0: history entry j, slot state.order[j]; a kernel with jc >= 0 runs only while
+// jc < state.count.
+
+__device__ __forceinline__ bool gate_open(const pmr_lbfgs_state* st, int gate, int jc) {
+  bool on;
+  if (gate == G_RUN)
+    on = st->status == PMR_LBFGS_RUNNING;
+  else if (gate == G_ACC)
+    on = st->accepted != 0;
+  else if (gate == G_DIR)
+    on = st->accepted != 0 && st->status == PMR_LBFGS_RUNNING;
+  else
+    on = st->accepted != 0 && st->status == PMR_LBFGS_RUNNING && st->reset != 0;
+  return on && (jc < 0 || jc < st->count);
+}
+
+__device__ __forceinline__ size_t slot_of(const pmr_lbfgs_state* st, int j) {
+  return j == NO_SLOT ? 0 : (size_t)(j == NEW_SLOT ? st->slot : st->order[j]);
+}
+
+__device__ __forceinline__ double* f_hist(pmr_lbfgs_state* st) {
+  return reinterpret_cast<double*>(st + 1);
+}
+__device__ __forceinline__ long long* clock_hist(pmr_lbfgs_state* st) {
+  return reinterpret_cast<long long*>(f_hist(st) + st->p.max_iter + 1);
+}
+
+__global__ __launch_bounds__(TB) void lb_dot_partial_kernel(const pmr_lbfgs_state* st, int gate,
+                                                            int jc, const float* A, int ja,
+                                                            const float* B, int jb, size_t n,
+                                                            double* partial) {
+  if (!gate_open(st, gate, jc)) return;
+  dot_partial_body(A + slot_of(st, ja) * n, B + slot_of(st, jb) * n, n, partial);
+}
+
+__global__ __launch_bounds__(TB) void lb_dot_final_kernel(const pmr_lbfgs_state* st, int gate,
+                                                          int jc, const double* partial, int np,
+                                                          const double* den, int jden,
+                                                          double* out, int jout) {
+  if (!gate_open(st, gate, jc)) return;
+  dot_final_body(partial, np, den ? den + slot_of(st, jden) : nullptr, out + slot_of(st, jout));
+}
+
+// y += sign * (A[slot] - B) * X[slot]
+__global__ __launch_bounds__(TB) void lb_axpy_kernel(const pmr_lbfgs_state* st, int gate, int jc,
+                                                     size_t n, const double* A, int ja,
+                                                     const double* B, double sign,
+                                                     const float* X, int jx, float* y) {
+  if (!gate_open(st, gate, jc)) return;
+  axpy_body(n, (float)(sign * (A[slot_of(st, ja)] - (B ? B[0] : 0.0))), X + slot_of(st, jx) * n,
+            y);
+}
+
+// x *= sign * num[slot] / den[slot]
+__global__ __launch_bounds__(TB) void lb_scale_kernel(const pmr_lbfgs_state* st, int gate, int jc,
+                                                      size_t n, const double* num,
+                                                      const double* den, int j, double sign,
+                                                      float* x) {
+  if (!gate_open(st, gate, jc)) return;
+  const size_t i = slot_of(st, j);
+  scale_body(n, (float)(sign * num[i] / den[i]), x);
+}
+
+// out[slot] = alpha a + beta b
+__global__ __launch_bounds__(TB) void lb_axpby_kernel(const pmr_lbfgs_state* st, int gate, int jc,
+                                                      size_t n, float alpha, const float* a,
+                                                      float beta, const float* b, float* out,
+                                                      int jout) {
+  if (!gate_open(st, gate, jc)) return;
+  axpby_body(n, alpha, a, beta, b, out + slot_of(st, jout) * n);
+}
+
+// xt = x + t d
+__global__ __launch_bounds__(TB) void lb_trial_kernel(const pmr_lbfgs_state* st, size_t n,
+                                                      const float* x, const float* d, float* xt) {
+  if (st->status != PMR_LBFGS_RUNNING) return;
+  axpby_body(n, 1.f, x, (float)st->t, d, xt);
+}
+
+__global__ void lb_init_kernel(pmr_lbfgs_state* st, pmr_lbfgs_params p, const double* loss,
+                               long long clock_khz) {
+  st->p = p;
+  st->clock_khz = clock_khz;
+  st->f = loss[0];
+  st->ft = st->f;
+  st->t = 0.0;
+  st->gd = st->gg = st->rel = st->ss = st->beta = 0.0;
+  st->status = PMR_LBFGS_RUNNING;
+  st->iters = 0;
+  st->evals = 1;
+  st->count = 0;
+  st->halvings = 0;
+  st->probe = 1;
+  st->accepted = 1;  // opens the direction kernels that follow
+  st->slot = 0;
+  st->reset = 0;
+  f_hist(st)[0] = st->f;
+  clock_hist(st)[0] = wall_clock64();
+}
+
+// a zero gradient ends the stage
+__global__ void lb_gg_kernel(pmr_lbfgs_state* st) {
+  if (!gate_open(st, G_DIR, -1)) return;
+  if (st->gg == 0.0) st->status = PMR_LBFGS_STATIONARY;
+}
+
+// not a descent direction: clear the history, d = -g follows
+__global__ void lb_gd_kernel(pmr_lbfgs_state* st) {
+  if (!gate_open(st, G_DIR, -1)) return;
+  if (st->gd >= 0.0) {
+    st->count = 0;
+    st->reset = 1;
+    st->gd = -st->gg;
+  } else {
+    st->reset = 0;
+  }
+}
+
+// first trial step of the search
+__global__ void lb_step_kernel(pmr_lbfgs_state* st) {
+  if (!gate_open(st, G_DIR, -1)) return;
+  st->probe = st->count == 0;
+  st->t = st->probe ? __ddiv_rn(1.0, __dsqrt_rn(st->gg)) : 1.0;
+  st->halvings = 0;
+}
+
+// Armijo test of the trial; on rejection halve t, on acceptance pick the candidate slot
+__global__ void lb_test_kernel(pmr_lbfgs_state* st, const double* loss) {
+  if (st->status != PMR_LBFGS_RUNNING) {
+    st->accepted = 0;
+    return;
+  }
+  st->evals += 1;
+  st->ft = loss[0];
+  const double bound = __dadd_rn(st->f, __dmul_rn(__dmul_rn(st->p.c1, st->t), st->gd));
+  st->accepted = st->ft <= bound;
+  if (!st->accepted) {
+    st->t *= 0.5;
+    if (++st->halvings > st->p.max_halvings) st->status = PMR_LBFGS_LINE_SEARCH;
+    return;
+  }
+  for (int k = 0; k <= st->p.m; ++k) {
+    bool used = false;
+    for (int j = 0; j < st->count; ++j) used = used || st->order[j] == k;
+    if (!used) {
+      st->slot = k;
+      break;
+    }
+  }
+}
+
+// curvature test, history update, the move to x_t and the stopping rules
+__global__ void lb_accept_kernel(pmr_lbfgs_state* st, const double* sy, const double* yy) {
+  if (!gate_open(st, G_ACC, -1)) return;
+  const int i = st->slot;
+  if (sy[i] > __dmul_rn(st->p.curvature_eps, __dsqrt_rn(__dmul_rn(yy[i], st->ss)))) {
+    const int keep = st->count < st->p.m ? st->count : st->p.m - 1;
+    for (int k = keep; k > 0; --k) st->order[k] = st->order[k - 1];
+    st->order[0] = i;
+    st->count = keep + 1;
+  }
+  st->rel = st->f != 0.0 ? __ddiv_rn(__dsub_rn(st->f, st->ft), fabs(st->f)) : 0.0;
+  st->f = st->ft;
+  st->iters += 1;
+  f_hist(st)[st->iters] = st->f;
+  clock_hist(st)[st->iters] = wall_clock64();
+  if (st->f <= st->p.stop_below)
+    st->status = PMR_LBFGS_TARGET;
+  else if (st->rel < st->p.rel_tol && !st->probe)
+    st->status = PMR_LBFGS_CONVERGED;
+  else if (st->iters >= st->p.max_iter)
+    st->status = PMR_LBFGS_MAX_ITER;
+}
+
+}  // namespace
+
+// FP64 inner product out[jout] = A[ja] . B[jb] (/ den[jden]) under a gate.
+void lb_dot(const pmr_lbfgs_state* st, int gate, int jc, size_t n, const float* A, int ja,
+            const float* B, int jb, const double* den, int jden, double* out, int jout,
+            double* work, hipStream_t s) {
+  const int nb = dot_blocks(n);
+  lb_dot_partial_kernel<<<nb, TB, 0, s>>>(st, gate, jc, A, ja, B, jb, n, work);
+  lb_dot_final_kernel<<<1, TB, 0, s>>>(st, gate, jc, work, nb, den, jden, out, jout);
+}
+
+// The next direction at x (g): the zero-gradient test, the two-loop recursion over the
+// device-held history, the descent test with its fallback d = -g, and the first step.
+void lb_direction(pmr_lbfgs_state* st, size_t n, int m, const float* g, float* d, const float* S,
+                  const float* Y, const double* sy, const double* yy, double* work,
+                  hipStream_t s) {
+  const unsigned gs = stream_grid(n);
+  lb_dot(st, G_DIR, -1, n, g, NO_SLOT, g, NO_SLOT, nullptr, NO_SLOT, &st->gg, NO_SLOT, work, s);
+  lb_gg_kernel<<<1, 1, 0, s>>>(st);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_DIR, -1, n, 1.f, g, 0.f, g, d, NO_SLOT);  // q = g
+  for (int j = 0; j < m; ++j) {  // newest to oldest: alpha_i = s_i.q / s_i.y_i; q -= alpha_i y_i
+    lb_dot(st, G_DIR, j, n, S, j, d, NO_SLOT, sy, j, st->alpha, j, work, s);
+    lb_axpy_kernel<<<gs, TB, 0, s>>>(st, G_DIR, j, n, st->alpha, j, nullptr, -1.0, Y, j, d);
+  }
+  lb_scale_kernel<<<gs, TB, 0, s>>>(st, G_DIR, 0, n, sy, yy, 0, 1.0, d);  // r = gamma q
+  for (int j = m - 1; j >= 0; --j) {  // oldest to newest: beta = y_i.r / s_i.y_i
+    lb_dot(st, G_DIR, j, n, Y, j, d, NO_SLOT, sy, j, &st->beta, NO_SLOT, work, s);
+    lb_axpy_kernel<<<gs, TB, 0, s>>>(st, G_DIR, j, n, st->alpha, j, &st->beta, 1.0, S, j, d);
+  }
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_DIR, -1, n, -1.f, d, 0.f, d, d, NO_SLOT);
+  lb_dot(st, G_DIR, -1, n, g, NO_SLOT, d, NO_SLOT, nullptr, NO_SLOT, &st->gd, NO_SLOT, work, s);
+  lb_gd_kernel<<<1, 1, 0, s>>>(st);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_RESET, -1, n, -1.f, g, 0.f, g, d, NO_SLOT);
+  lb_step_kernel<<<1, 1, 0, s>>>(st);
+}
+
+void launch_lbfgs_init(size_t n, const pmr_lbfgs_params& p, pmr_lbfgs_state* st,
+                       const double* loss, const float* g, float* d, const float* S,
+                       const float* Y, const double* sy, const double* yy, double* work,
+                       long long clock_khz, hipStream_t s) {
+  lb_init_kernel<<<1, 1, 0, s>>>(st, p, loss, clock_khz);
+  lb_direction(st, n, p.m, g, d, S, Y, sy, yy, work, s);
+}
+
+void launch_lbfgs_trial(size_t n, const pmr_lbfgs_state* st, const float* x, const float* d,
+                        float* xt, hipStream_t s) {
+  lb_trial_kernel<<<stream_grid(n), TB, 0, s>>>(st, n, x, d, xt);
+}
+
+void launch_lbfgs_update(size_t n, int m, pmr_lbfgs_state* st, const double* loss, float* x,
+                         float* g, const float* xt, const float* gt, float* d, float* S,
+                         float* Y, double* sy, double* yy, double* work, hipStream_t s) {
+  const unsigned gs = stream_grid(n);
+  lb_test_kernel<<<1, 1, 0, s>>>(st, loss);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_ACC, -1, n, 1.f, xt, -1.f, x, S, NEW_SLOT);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_ACC, -1, n, 1.f, gt, -1.f, g, Y, NEW_SLOT);
+  lb_dot(st, G_ACC, -1, n, S, NEW_SLOT, Y, NEW_SLOT, nullptr, NO_SLOT, sy, NEW_SLOT, work, s);
+  lb_dot(st, G_ACC, -1, n, Y, NEW_SLOT, Y, NEW_SLOT, nullptr, NO_SLOT, yy, NEW_SLOT, work, s);
+  lb_dot(st, G_ACC, -1, n, S, NEW_SLOT, S, NEW_SLOT, nullptr, NO_SLOT, &st->ss, NO_SLOT, work, s);
+  lb_accept_kernel<<<1, 1, 0, s>>>(st, sy, yy);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_ACC, -1, n, 1.f, xt, 0.f, xt, x, NO_SLOT);
+  lb_axpby_kernel<<<gs, TB, 0, s>>>(st, G_ACC, -1, n, 1.f, gt, 0.f, gt, g, NO_SLOT);
+  lb_direction(st, n, m, g, d, S, Y, sy, yy, work, s);
+}
+
 size_t power_work_doubles(int nbins) { return (size_t)4 * nbins * PS_THREADS; }
 
 void launch_power_bins(int n, double box, const float2* a, const float2* b, int nbins,
@@ -312,6 +594,52 @@ int pmr_lbfgs_direction_noalloc(size_t n, int m, int count, const int* order, co
   const size_t part = vec_work_doubles(n);
   if (part + 2 * (size_t)m + 2 > NOALLOC_DOUBLES) return PMR_E_SHAPE;
   launch_lbfgs_direction(n, m, count, order, S, Y, sy, yy, g, d, w, w + part, s);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+size_t pmr_lbfgs_state_bytes(int max_iter) {
+  if (max_iter < 1) return 0;
+  return sizeof(pmr_lbfgs_state) + (size_t)(max_iter + 1) * (sizeof(double) + sizeof(long long));
+}
+
+int pmr_lbfgs_init(size_t n, const pmr_lbfgs_params* params, void* state, const double* loss,
+                   const float* g, float* d, const float* S, const float* Y, const double* sy,
+                   const double* yy, void* work, void* stream) {
+  if (!params || !state || !loss || !g || !d || !S || !Y || !sy || !yy || !work || n == 0 ||
+      g == d)
+    return PMR_E_INVALID;
+  const pmr_lbfgs_params& p = *params;
+  if (p.m < 1 || p.m > PMR_LBFGS_MAX_M || p.max_iter < 1 || p.max_halvings < 0 ||
+      !(p.c1 > 0.0 && p.c1 < 1.0) || !(p.curvature_eps >= 0.0) || !(p.rel_tol >= 0.0) ||
+      p.stop_below != p.stop_below)
+    return PMR_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PMR_E_HIP;
+  if (s && hipStreamGetDevice(s, &dev) != hipSuccess) return PMR_E_HIP;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return PMR_E_HIP;
+  launch_lbfgs_init(n, p, (pmr_lbfgs_state*)state, loss, g, d, S, Y, sy, yy, (double*)work, khz,
+                    s);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+int pmr_lbfgs_trial(size_t n, const void* state, const float* x, const float* d, float* xt,
+                    void* stream) {
+  if (!state || !x || !d || !xt || n == 0 || xt == x || xt == d) return PMR_E_INVALID;
+  launch_lbfgs_trial(n, (const pmr_lbfgs_state*)state, x, d, xt, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
+}
+
+int pmr_lbfgs_update(size_t n, int m, void* state, const double* loss, float* x, float* g,
+                     const float* xt, const float* gt, float* d, float* S, float* Y, double* sy,
+                     double* yy, void* work, void* stream) {
+  if (!state || !loss || !x || !g || !xt || !gt || !d || !S || !Y || !sy || !yy || !work ||
+      n == 0 || m < 1 || m > PMR_LBFGS_MAX_M || g == d || xt == x || gt == g)
+    return PMR_E_INVALID;
+  launch_lbfgs_update(n, m, (pmr_lbfgs_state*)state, loss, x, g, xt, gt, d, S, Y, sy, yy,
+                      (double*)work, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? PMR_OK : PMR_E_HIP;
 }
 

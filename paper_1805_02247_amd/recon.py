@@ -4,11 +4,17 @@ statistics of Sec. 4.3 that score the result against the true modes.
 
 Every vector operation runs in libpmr kernels: FP64 inner products with device-resident
 scalars, the two-loop recursion (pmr_lbfgs_direction) and the updates; an evaluation can be
-one HIP-graph replay of forward + adjoint (GradientGraph with device loss parameters). The
-host keeps the control flow: the Armijo test on the loss copied back once per evaluation,
-the curvature test on three inner products copied back once per accepted step, the history
-ring and the stopping rule. The parameters are all stored real and imaginary parts of the modes, so the
-complex64 mode tensor is used as a float32 vector of twice its length.
+one HIP-graph replay of forward + adjoint (GradientGraph with device loss parameters).
+Two drivers share the rules below. `minimize` keeps the control flow on the host: the
+Armijo test on the loss copied back once per evaluation, the curvature test on three inner
+products copied back once per accepted step, the history ring and the stopping rule.
+`DeviceLBFGS` moves all of it to the device (pmr_lbfgs_init/trial/update): one captured
+graph per evaluation holds the trial point, forward, adjoint, the Armijo and curvature tests,
+the history update and the next direction, and the host only reads the status block every
+few replays. On the same losses and inner products both take the same decisions and
+iterates, bit for bit (the scalar tests are the same FP64 expressions, rounded once per
+operation in the same order). The parameters are all stored real and imaginary parts of
+the modes, so the complex64 mode tensor is used as a float32 vector of twice its length.
 
 Readings (the paper names L-BFGS and the anneal but gives no optimiser parameters):
 history m = 10; the first iteration of a stage moves a unit distance along -g (step
@@ -20,13 +26,14 @@ max_iter iterations (the rule is not applied to a unit-length step taken without
 each stage starts from the previous optimum with an empty history.
 """
 import ctypes
+import math
 import time
 from dataclasses import dataclass, field
 
 import torch
 
 from . import _lib as L
-from .api import LossParams, _ptr, _stream
+from .api import GradientGraph, LossParams, _ptr, _stream
 
 HISTORY = 10
 C1 = 1e-4
@@ -73,6 +80,7 @@ class StageResult:
     iters: int = 0
     reason: str = "max_iter"
     seconds: float = 0.0
+    replays: int = 0  # graph replays (device driver: including those after the stage ended)
 
 
 def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop_below=None,
@@ -130,7 +138,7 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
             ops.axpby(-1.0, g, 0.0, g, d)
             gd = -gg
         probe = not order  # unit-length step without history
-        t = 1.0 if order else 1.0 / gg ** 0.5
+        t = 1.0 if order else 1.0 / math.sqrt(gg)
         ok = False
         for _ in range(MAX_HALVINGS + 1):
             ops.axpby(1.0, x, t, d, xt)
@@ -149,7 +157,7 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
         ops.dot(Y[slot], Y[slot], yy[slot:slot + 1])
         ops.dot(S[slot], S[slot], tmp[2:3])
         h = torch.stack([sy[slot], yy[slot], tmp[2]]).cpu()
-        if float(h[0]) > CURVATURE_EPS * (float(h[1]) * float(h[2])) ** 0.5:
+        if float(h[0]) > CURVATURE_EPS * math.sqrt(float(h[1]) * float(h[2])):
             order = ([slot] + order)[:m]  # the oldest pair leaves when m are held
         ops.axpby(1.0, xt, 0.0, xt, x)
         ops.axpby(1.0, gt, 0.0, gt, g)
@@ -171,19 +179,128 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
     return res
 
 
-def reconstruct(pm, modes, stages, max_iter=100, log=None, graph=None, stop_below=None):
+class _IterationGraph(GradientGraph):
+    """One optimiser evaluation as a captured graph: trial point x + t d into the graph's
+    modes, forward, adjoint, then the device-side test and update (pmr_lbfgs_update)."""
+
+    def __init__(self, opt, pm, modes, params):
+        self.opt = opt
+        super().__init__(pm, modes, warmup=1, params=params)
+
+    def _enqueue(self):
+        o = self.opt
+        xt = self.modes.view(torch.float32).reshape(-1)
+        gt = self.grad.view(torch.float32).reshape(-1)
+        L.check(L.lib().pmr_lbfgs_trial(o.n, _ptr(o.state), _ptr(o.x), _ptr(o.d), _ptr(xt),
+                                        _stream()))
+        super()._enqueue()
+        L.check(L.lib().pmr_lbfgs_update(o.n, o.m, _ptr(o.state), _ptr(self.loss), _ptr(o.x),
+                                         _ptr(o.g), _ptr(xt), _ptr(gt), _ptr(o.d), _ptr(o.S),
+                                         _ptr(o.Y), _ptr(o.sy), _ptr(o.yy), _ptr(o.work),
+                                         _stream()))
+
+
+class DeviceLBFGS:
+    """L-BFGS with its line search on the device (the rules of `minimize`): every
+    evaluation is one replay of a graph holding the trial point, forward, adjoint, the
+    Armijo test, the candidate pair with its curvature test, the move and the next
+    direction, so no evaluation waits for the host. The host reads the status block every
+    `check_every` replays; the replays after a stage has ended (at most check_every - 1)
+    run forward + adjoint and change nothing.
+
+    pm: a PMContext of batch 1; modes: complex64 [1][n_modes] start (the graph's shape);
+    params: the first stage's LossParams (later stages: `stage(params)`)."""
+
+    def __init__(self, pm, modes, params, m=HISTORY, max_iter=100, check_every=4):
+        if pm.cfg.batch != 1:
+            raise ValueError("the driver optimises one realisation (batch 1)")
+        if not 1 <= m <= L.PMR_LBFGS_MAX_M:
+            raise ValueError(f"history m must be in 1..{L.PMR_LBFGS_MAX_M}")
+        dev = modes.device
+        self.pm, self.m, self.max_iter, self.check_every = pm, int(m), int(max_iter), int(check_every)
+        self.n = 2 * pm.n_modes
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.x = torch.empty(self.n, **f32)
+        self.g = torch.empty(self.n, **f32)
+        self.d = torch.empty(self.n, **f32)
+        self.S = torch.empty(m + 1, self.n, **f32)
+        self.Y = torch.empty(m + 1, self.n, **f32)
+        self.sy = torch.zeros(m + 1, dtype=torch.float64, device=dev)
+        self.yy = torch.zeros(m + 1, dtype=torch.float64, device=dev)
+        nb = int(L.lib().pmr_vec_work_bytes(self.n, 0))
+        self.work = torch.empty(nb // 8 + 1, dtype=torch.float64, device=dev)
+        sb = int(L.lib().pmr_lbfgs_state_bytes(self.max_iter))
+        self.state = torch.zeros(sb // 8 + 1, dtype=torch.float64, device=dev)  # idle
+        self.head = ctypes.sizeof(L.PmrLbfgsState)
+        self.graph = _IterationGraph(self, pm, modes.reshape(1, -1), params)
+
+    def read_state(self):
+        """The status block (one device-to-host copy, synchronising)."""
+        raw = self.state.view(torch.uint8)[:self.head].cpu().numpy().tobytes()
+        return L.PmrLbfgsState.from_buffer_copy(raw)
+
+    def stage(self, modes, params, rel_tol=REL_TOL, stop_below=None):
+        """One anneal stage from `modes` (complex64 [1][n_modes], updated in place) at loss
+        parameters `params`. Returns a StageResult."""
+        G = self.graph
+        G.set_params(params)
+        self.state.zero_()  # idle: the next replay only evaluates at x
+        self.x.copy_(_floats(modes))
+        G.modes.view(torch.float32).reshape(-1).copy_(self.x)
+        res = StageResult(params=params)
+        t0 = time.perf_counter()
+        G.replay()
+        self.g.copy_(G.grad.view(torch.float32).reshape(-1))
+        p = L.PmrLbfgsParams(m=self.m, max_iter=self.max_iter, max_halvings=MAX_HALVINGS,
+                             c1=C1, curvature_eps=CURVATURE_EPS, rel_tol=float(rel_tol),
+                             stop_below=-math.inf if stop_below is None else float(stop_below))
+        L.check(L.lib().pmr_lbfgs_init(self.n, ctypes.byref(p), _ptr(self.state),
+                                       _ptr(G.loss), _ptr(self.g), _ptr(self.d), _ptr(self.S),
+                                       _ptr(self.Y), _ptr(self.sy), _ptr(self.yy),
+                                       _ptr(self.work), _stream()))
+        torch.cuda.synchronize(modes.device)
+        t_init = time.perf_counter() - t0
+        replays = 1
+        while True:
+            for _ in range(self.check_every):
+                G.replay()
+            replays += self.check_every
+            st = self.read_state()
+            if st.status != 1:
+                break
+        res.seconds = time.perf_counter() - t0
+        hist = self.state.view(torch.uint8)[self.head:].view(torch.float64)
+        k = self.max_iter + 1
+        f_hist = hist[:k].cpu().numpy()
+        clk = hist[k:2 * k].view(torch.int64).cpu().numpy()
+        res.iters, res.evals = st.iters, st.evals
+        res.reason = L.PMR_LBFGS_STATUS[st.status]
+        res.losses = [float(v) for v in f_hist[:st.iters + 1]]
+        res.times = [t_init + float(c - clk[0]) / (st.clock_khz * 1e3)
+                     for c in clk[:st.iters + 1]]
+        res.replays = replays
+        _floats(modes).copy_(self.x)
+        return res
+
+
+def reconstruct(pm, modes, stages, max_iter=100, log=None, graph=None, stop_below=None,
+                device=None):
     """Runs minimize over the anneal stages (LossParams each) in order, from `modes`
     (updated in place); with `graph` (a GradientGraph of pm captured with device loss
     parameters) each stage's parameters are written into the graph's parameter buffer and
-    every evaluation is a graph replay. stop_below applies to the last stage. Returns the
-    list of StageResult."""
+    every evaluation is a graph replay; with `device` (a DeviceLBFGS of pm) every stage runs
+    with the line search on the device (its own max_iter applies). stop_below applies to the
+    last stage. Returns the list of StageResult."""
     out = []
     for i, p in enumerate(stages):
+        last = i == len(stages) - 1
+        if device is not None:
+            out.append(device.stage(modes, p, stop_below=stop_below if last else None))
+            continue
         if graph is not None:
             graph.set_params(p)
         else:
             pm.set_loss(p)
-        last = i == len(stages) - 1
         r = minimize(pm, modes, max_iter=max_iter, log=log, graph=graph,
                      stop_below=stop_below if last else None)
         r.params = p

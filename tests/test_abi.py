@@ -137,3 +137,63 @@ def test_reconstruction_calls_validate_arguments_on_the_host():
     assert lib.pmr_power_bins(16, 100.0, fake, fake, 33, fake, fake, need, None) == -2
     assert lib.pmr_power_bins(16, 0.0, fake, fake, 8, fake, fake, need, None) == -1
     assert lib.pmr_power_bins(16, 100.0, fake, fake, 8, fake, fake, need - 8, None) == -3
+
+
+def test_device_lbfgs_validates_arguments_on_the_host():
+    """The device-driven optimiser's calls refuse bad parameters and pointers before any
+    device work."""
+    lib = L.lib()
+    P = ctypes.c_void_p
+    f = [P(4096 * (k + 1)) for k in range(12)]  # distinct, never dereferenced
+    assert lib.pmr_lbfgs_state_bytes(0) == 0
+    assert lib.pmr_lbfgs_state_bytes(10) == ctypes.sizeof(L.PmrLbfgsState) + 11 * 16
+
+    def params(**kw):
+        p = dict(m=10, max_iter=20, max_halvings=30, c1=1e-4, curvature_eps=1e-10,
+                 rel_tol=1e-3, stop_below=float("-inf"))
+        p.update(kw)
+        return L.PmrLbfgsParams(**p)
+
+    for bad in (dict(m=0), dict(m=65), dict(max_iter=0), dict(max_halvings=-1), dict(c1=0.0),
+                dict(c1=1.0), dict(rel_tol=-1.0), dict(stop_below=float("nan")),
+                dict(curvature_eps=float("nan"))):
+        assert lib.pmr_lbfgs_init(100, ctypes.byref(params(**bad)), *f[:10]) == -1, bad
+    assert lib.pmr_lbfgs_init(100, None, *f[:10]) == -1
+    assert lib.pmr_lbfgs_init(0, ctypes.byref(params()), *f[:10]) == -1
+    g_is_d = [f[0], f[1], f[2], f[2]] + f[4:10]
+    assert lib.pmr_lbfgs_init(100, ctypes.byref(params()), *g_is_d) == -1
+    assert lib.pmr_lbfgs_trial(100, f[0], f[1], f[2], f[1], None) == -1  # xt aliases x
+    assert lib.pmr_lbfgs_trial(100, None, f[1], f[2], f[3], None) == -1
+    upd = f[:12]
+    assert lib.pmr_lbfgs_update(100, 0, *upd, None) == -1
+    assert lib.pmr_lbfgs_update(100, 65, *upd, None) == -1
+    alias = list(upd)
+    alias[4] = alias[2]  # xt aliases x
+    assert lib.pmr_lbfgs_update(100, 4, *alias, None) == -1
+
+
+def test_lbfgs_state_layout_matches_the_header(tmp_path):
+    """The ctypes view of pmr_lbfgs_state and pmr_lbfgs_params has the C layout of the
+    header (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    names = [n for n, _ in L.PmrLbfgsState._fields_]
+    pnames = [n for n, _ in L.PmrLbfgsParams._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof(pmr_lbfgs_state, {n}));\n' for n in names)
+    body += "".join(f'  printf("%zu\\n", offsetof(pmr_lbfgs_params, {n}));\n' for n in pnames)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pmr.h"\nint main(void) {\n'
+                   '  printf("%zu\\n%zu\\n", sizeof(pmr_lbfgs_state), sizeof(pmr_lbfgs_params));\n'
+                   + body + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = str(__import__("os").path.dirname(L.HEADER_PATH))
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(L.PmrLbfgsState), ctypes.sizeof(L.PmrLbfgsParams)]
+    want += [getattr(L.PmrLbfgsState, n).offset for n in names]
+    want += [getattr(L.PmrLbfgsParams, n).offset for n in pnames]
+    assert got == want

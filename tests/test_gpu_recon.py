@@ -264,3 +264,68 @@ def test_gpu_graph_driven_stages_retrace_eager():
     assert graph_losses == eager_losses
     assert np.array_equal(graph_modes, eager_modes)
     assert len(eager_losses[0]) > 2 and len(eager_losses[1]) > 1
+
+
+@pytest.mark.parametrize("check_every", [1, 3])
+def test_gpu_device_driver_retraces_host_driver(check_every):
+    """The L-BFGS with its line search on the device (every evaluation one replay of a graph
+    holding the trial point, forward, adjoint, Armijo test, pair, curvature test and next
+    direction) takes the host driver's decisions bit for bit: the same losses at every
+    accepted step, the same evaluation counts, stop reasons and final modes, over three
+    stages (a max_iter stop, a target-loss stop, a free stage), whatever the polling
+    interval."""
+    require_gpu()
+    say(f"recon: device-driven line search vs host driver, check_every={check_every}")
+    n, box = 16, 100.0
+    ocfg = OM.Config(box, n, n, n, 3, loss_kind=OM.LOSS_LOGNORMAL)
+    power = OC.bbks_power()
+    inv = OM.prior_inv_variance(n, box, power)
+    s_true = OM.linear_modes(synth.white_noise(41, n), box, power)
+    w = synth.mlp_weights(3, 8)
+    target = OM.forward(ocfg, s_true, inv, np.ones((n, n, n)), OM.default_params(), w)["mass"]
+    s0 = np.sqrt(0.1) * OM.linear_modes(synth.white_noise(42, n), box, power)
+    M0 = float(np.median(target))
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, mlp_hidden=8, box=box)
+    stages = [P.LossParams(M0=M0, R_sm=2.0), P.LossParams(M0=0.8 * M0, R_sm=1.0),
+              P.LossParams(M0=0.8 * M0, R_sm=0.0)]
+    max_iters = [4, 30, 30]
+
+    def context():
+        pm = P.PMContext(cfg, DEV)
+        pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+        pm.set_mlp({k: torch.from_numpy(v) for k, v in w.items()})
+        pm.set_target(torch.from_numpy(target.astype(np.float32)).reshape(1, -1))
+        pm.set_loss(stages[0])
+        return pm, torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+
+    # the target of the second stage: the loss the host driver reaches there after 3 steps
+    pm, modes = context()
+    G = P.GradientGraph(pm, modes, params=stages[0])
+    pre = []
+    for p, it in zip(stages[:2], max_iters[:2]):
+        G.set_params(p)
+        pre.append(R.minimize(pm, modes, max_iter=it, graph=G))
+    stop1 = pre[1].losses[3]
+    pm, modes = context()
+    G = P.GradientGraph(pm, modes, params=stages[0])
+    host = []
+    for k, (p, it) in enumerate(zip(stages, max_iters)):
+        G.set_params(p)
+        host.append(R.minimize(pm, modes, max_iter=it, graph=G,
+                               stop_below=stop1 if k == 1 else None))
+    host_modes = modes.cpu().numpy()
+
+    pm, modes = context()
+    dev_out = []
+    for k, (p, it) in enumerate(zip(stages, max_iters)):
+        D = R.DeviceLBFGS(pm, modes, p, max_iter=it, check_every=check_every)
+        dev_out.append(D.stage(modes, p, stop_below=stop1 if k == 1 else None))
+    dev_modes = modes.cpu().numpy()
+    for k, (h, d) in enumerate(zip(host, dev_out)):
+        say(f"  stage {k}: host {h.reason} {h.iters} it {h.evals} ev; device {d.reason} "
+            f"{d.iters} it {d.evals} ev {d.replays} replays")
+        assert d.losses == h.losses, k
+        assert (d.iters, d.evals, d.reason) == (h.iters, h.evals, h.reason), k
+        assert len(d.times) == len(d.losses) and all(b >= a for a, b in zip(d.times, d.times[1:]))
+    assert host[0].reason == "max_iter" and host[1].reason == "target_loss"
+    assert np.array_equal(dev_modes, host_modes)
