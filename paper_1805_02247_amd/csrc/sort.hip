@@ -337,6 +337,7 @@ struct RowSortArgs {
   uint32_t zmask;      // nm - 1
   int idbits;          // bits of the largest id (32-bit composites: iz << idbits | id)
   size_t rows;
+  int block_rows;      // rows a workgroup of the long-row tiers tests per step (<= TB)
 };
 
 // Composite sort value of a particle within its row: (iz, id) as iz << 32 | id in 64 bits,
@@ -566,8 +567,11 @@ __device__ void block_radix_pass(const uint32_t* shi, const uint32_t* slo, uint3
 }
 
 // Tier 2 (rows of 257..4096 entries: bitonic sort in LDS) and tier 3 (larger rows: stable
-// LSD radix passes in global memory over the digits that vary in the row); each workgroup
-// takes rows blockIdx.x, blockIdx.x + gridDim.x, ...
+// LSD radix passes in global memory over the digits that vary in the row). A workgroup
+// takes block_rows consecutive rows at a time (blocks strided over the row range); its
+// threads test those rows' lengths together and the workgroup then sorts the long ones one
+// after the other (rows are independent, so the order in which they are done does not
+// matter). block_rows is chosen so that every resident workgroup gets rows to test.
 template <typename T>
 __global__ __launch_bounds__(TB) void row_sort_block_kernel(RowSortArgs a) {
   constexpr T PADT = (T)~(T)0;
@@ -575,95 +579,109 @@ __global__ __launch_bounds__(TB) void row_sort_block_kernel(RowSortArgs a) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[TB / 64][256];
   __shared__ uint32_t red[2][TB / 64];
+  __shared__ uint32_t found[TB];
+  __shared__ int nfound;
   const int t = threadIdx.x;
-  for (size_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
-    const uint32_t start = a.row_start[r];
-    const uint32_t c = a.row_start[r + 1] - start;
-    if (c <= WAVE_ROW_MAX) continue;
-    const uint32_t row = (uint32_t)r;
-    if (c <= BLOCK_ROW_MAX) {
-      uint32_t p2 = 512;
-      while (p2 < c) p2 <<= 1;
-      for (uint32_t i = t; i < p2; i += TB)
-        s[i] = i < c ? composite_t<T>(a, a.bucket[start + i]) : PADT;
-      __syncthreads();
-      for (uint32_t k = 2; k <= p2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-          for (uint32_t q = t; q < p2 / 2; q += TB) {
-            const uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
-            const uint32_t p = i | j;
-            const bool up = (i & k) == 0;
-            const T x = s[i], y = s[p];
-            if ((x > y) == up) {
-              s[i] = y;
-              s[p] = x;
+  const size_t br = (size_t)a.block_rows;
+  for (size_t r0 = (size_t)blockIdx.x * br; r0 < a.rows; r0 += (size_t)gridDim.x * br) {
+    if (t == 0) nfound = 0;
+    __syncthreads();
+    if ((size_t)t < br && r0 + t < a.rows &&
+        a.row_start[r0 + t + 1] - a.row_start[r0 + t] > WAVE_ROW_MAX)
+      found[atomicAdd(&nfound, 1)] = (uint32_t)t;
+    __syncthreads();
+    const int nf = nfound;
+    for (int f = 0; f < nf; ++f) {
+      const size_t r = r0 + found[f];
+      const uint32_t start = a.row_start[r];
+      const uint32_t c = a.row_start[r + 1] - start;
+      const uint32_t row = (uint32_t)r;
+      if (c <= BLOCK_ROW_MAX) {
+        uint32_t p2 = 512;
+        while (p2 < c) p2 <<= 1;
+        for (uint32_t i = t; i < p2; i += TB)
+          s[i] = i < c ? composite_t<T>(a, a.bucket[start + i]) : PADT;
+        __syncthreads();
+        for (uint32_t k = 2; k <= p2; k <<= 1) {
+          for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = t; q < p2 / 2; q += TB) {
+              const uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+              const uint32_t p = i | j;
+              const bool up = (i & k) == 0;
+              const T x = s[i], y = s[p];
+              if ((x > y) == up) {
+                s[i] = y;
+                s[p] = x;
+              }
             }
+            __syncthreads();
           }
-          __syncthreads();
         }
+        for (uint32_t i = t; i < c; i += TB) emit_t<T>(a, row, start + i, s[i]);
+        __syncthreads();
+        continue;
       }
-      for (uint32_t i = t; i < c; i += TB) emit_t<T>(a, row, start + i, s[i]);
+      // tier 3: (hi, lo) = (iz, id) pairs; A = the row's range of the sorted outputs, B = the
+      // radix scratch
+      uint32_t* ahi = a.keys_sorted + start;
+      uint32_t* alo = a.ids_sorted + start;
+      uint32_t* bhi = a.tmp_hi + start;
+      uint32_t* blo = a.tmp_lo + start;
+      uint32_t orv[2] = {0u, 0u}, andv[2] = {~0u, ~0u};
+      for (uint32_t i = t; i < c; i += TB) {
+        const uint32_t id = a.bucket[start + i];
+        const uint32_t hi = a.keys[id] & a.zmask;
+        ahi[i] = hi;
+        alo[i] = id;
+        orv[0] |= hi;
+        andv[0] &= hi;
+        orv[1] |= id;
+        andv[1] &= id;
+      }
+      // bits that vary across the row (passes over constant digits are skipped)
+      uint32_t var[2];
+      for (int h = 0; h < 2; ++h) {
+        uint32_t o = orv[h], n = andv[h];
+  #pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          o |= __shfl_xor(o, d, 64);
+          n &= __shfl_xor(n, d, 64);
+        }
+        if (lane_id() == 0) {
+          red[0][t >> 6] = o;
+          red[1][t >> 6] = n;
+        }
+        __syncthreads();
+        o = 0u;
+        n = ~0u;
+        for (int q = 0; q < TB / 64; ++q) {
+          o |= red[0][q];
+          n &= red[1][q];
+        }
+        var[h] = o ^ n;
+        __syncthreads();
+      }
+      bool in_a = true;
+      for (int bit = 0; bit < 64; bit += 8) {
+        const uint32_t vm = bit >= 32 ? var[0] >> (bit - 32) : var[1] >> bit;
+        if ((vm & 255u) == 0) continue;
+        __syncthreads();  // the previous pass's writes
+        if (in_a)
+          block_radix_pass(ahi, alo, bhi, blo, c, bit, base, wcnt);
+        else
+          block_radix_pass(bhi, blo, ahi, alo, c, bit, base, wcnt);
+        in_a = !in_a;
+      }
       __syncthreads();
-      continue;
-    }
-    // tier 3: (hi, lo) = (iz, id) pairs; A = the row's range of the sorted outputs, B = the
-    // radix scratch
-    uint32_t* ahi = a.keys_sorted + start;
-    uint32_t* alo = a.ids_sorted + start;
-    uint32_t* bhi = a.tmp_hi + start;
-    uint32_t* blo = a.tmp_lo + start;
-    uint32_t orv[2] = {0u, 0u}, andv[2] = {~0u, ~0u};
-    for (uint32_t i = t; i < c; i += TB) {
-      const uint32_t id = a.bucket[start + i];
-      const uint32_t hi = a.keys[id] & a.zmask;
-      ahi[i] = hi;
-      alo[i] = id;
-      orv[0] |= hi;
-      andv[0] &= hi;
-      orv[1] |= id;
-      andv[1] &= id;
-    }
-    // bits that vary across the row (passes over constant digits are skipped)
-    uint32_t var[2];
-    for (int h = 0; h < 2; ++h) {
-      uint32_t o = orv[h], n = andv[h];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        o |= __shfl_xor(o, d, 64);
-        n &= __shfl_xor(n, d, 64);
-      }
-      if (lane_id() == 0) {
-        red[0][t >> 6] = o;
-        red[1][t >> 6] = n;
-      }
-      __syncthreads();
-      o = 0u;
-      n = ~0u;
-      for (int q = 0; q < TB / 64; ++q) {
-        o |= red[0][q];
-        n &= red[1][q];
-      }
-      var[h] = o ^ n;
+      const uint32_t* fhi = in_a ? ahi : bhi;
+      const uint32_t* flo = in_a ? alo : blo;
+      // each thread reads and rewrites only its own indices of A (in place when the last pass
+      // landed there)
+      for (uint32_t i = t; i < c; i += TB)
+        emit(a, row, start + i, ((uint64_t)fhi[i] << 32) | flo[i]);
       __syncthreads();
     }
-    bool in_a = true;
-    for (int bit = 0; bit < 64; bit += 8) {
-      const uint32_t vm = bit >= 32 ? var[0] >> (bit - 32) : var[1] >> bit;
-      if ((vm & 255u) == 0) continue;
-      __syncthreads();  // the previous pass's writes
-      if (in_a)
-        block_radix_pass(ahi, alo, bhi, blo, c, bit, base, wcnt);
-      else
-        block_radix_pass(bhi, blo, ahi, alo, c, bit, base, wcnt);
-      in_a = !in_a;
-    }
-    __syncthreads();
-    const uint32_t* fhi = in_a ? ahi : bhi;
-    const uint32_t* flo = in_a ? alo : blo;
-    // each thread reads and rewrites only its own indices of A (in place when the last pass
-    // landed there)
-    for (uint32_t i = t; i < c; i += TB) emit(a, row, start + i, ((uint64_t)fhi[i] << 32) | flo[i]);
-    __syncthreads();
+    __syncthreads();  // every thread has read nfound before it is reset
   }
 }
 
@@ -725,7 +743,7 @@ void launch_cell_sort(const uint32_t* keys, const uint32_t* order, int n, int sh
     bucket_kernel<<<grid_for(n, TB * GROUPS), TB, 0, s>>>(keys, order, n, sshift, cursor, bucket);
   else
     bucket_loop_kernel<<<grid_for(n, TB), TB, 0, s>>>(keys, order, n, sshift, cursor, bucket);
-  RowSortArgs a;
+  RowSortArgs a{};
   a.keys = keys;
   a.row_start = seg_start;
   a.bucket = bucket;
@@ -749,13 +767,18 @@ void launch_cell_sort(const uint32_t* keys, const uint32_t* order, int n, int sh
     row_sort_wave_kernel<uint32_t><<<(int)need, TB, 0, s>>>(a);
   else
     row_sort_wave_kernel<uint64_t><<<(int)need, TB, 0, s>>>(a);
-  if (narrow) {
-    const int blk = resident_grid<row_sort_block_kernel<uint32_t>, TB>();
-    row_sort_block_kernel<uint32_t><<<segs < (size_t)blk ? (int)segs : blk, TB, 0, s>>>(a);
-  } else {
-    const int blk = resident_grid<row_sort_block_kernel<uint64_t>, TB>();
-    row_sort_block_kernel<uint64_t><<<segs < (size_t)blk ? (int)segs : blk, TB, 0, s>>>(a);
-  }
+  const int blk = narrow ? resident_grid<row_sort_block_kernel<uint32_t>, TB>()
+                         : resident_grid<row_sort_block_kernel<uint64_t>, TB>();
+  // rows tested per workgroup step: TB, halved (down to 32) while that leaves resident
+  // workgroups without rows
+  a.block_rows = TB;
+  while (a.block_rows > 32 && segs / (size_t)a.block_rows < (size_t)blk) a.block_rows /= 2;
+  const size_t chunks = (segs + a.block_rows - 1) / a.block_rows;
+  const int grid = chunks < (size_t)blk ? (int)chunks : blk;
+  if (narrow)
+    row_sort_block_kernel<uint32_t><<<grid, TB, 0, s>>>(a);
+  else
+    row_sort_block_kernel<uint64_t><<<grid, TB, 0, s>>>(a);
   if (pay_out || inv)
     sorted_payload_kernel<<<grid_for(n, TB * PAY_PER), TB, 0, s>>>(ids_sorted, n, pay_in, pay_out,
                                                                   inv);
