@@ -694,13 +694,13 @@ int grid_for(size_t n, int per_block) {
 
 // Row segments: the sort works on segments of 2^split cells of a row (split low bits of iz
 // moved into the segment number), chosen so that the (iz, id) composite of a segment fits
-// 32 bits and a segment holds about 128 particles or fewer on average (so the wavefront tier
+// 32 bits and a segment holds 64 particles or fewer on average (so the wavefront tier
 // takes nearly every segment).
 int cell_sort_split(int n, size_t rows, int shift) {
   int idbits = 0;
   while (idbits < 32 && ((size_t)1 << idbits) < (size_t)n) ++idbits;
   int split = shift + idbits > 32 ? shift + idbits - 32 : 0;
-  while (split < shift && (double)n / (double)(rows << split) > 128.0) ++split;
+  while (split < shift && (double)n / (double)(rows << split) > 64.0) ++split;
   return split > shift ? shift : split;
 }
 
