@@ -84,7 +84,7 @@ class StageResult:
 
 
 def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop_below=None,
-             graph=None):
+             graph=None, c1=C1, max_halvings=MAX_HALVINGS):
     """L-BFGS from `modes` (complex64 [1][n_modes], updated in place) with the loss already
     set on `pm` (a PMContext of batch 1), or on `graph` (an api.GradientGraph of pm captured
     with device loss parameters, whose replays then evaluate forward + adjoint as one graph
@@ -140,10 +140,10 @@ def minimize(pm, modes, max_iter=100, m=HISTORY, rel_tol=REL_TOL, log=None, stop
         probe = not order  # unit-length step without history
         t = 1.0 if order else 1.0 / math.sqrt(gg)
         ok = False
-        for _ in range(MAX_HALVINGS + 1):
+        for _ in range(max_halvings + 1):
             ops.axpby(1.0, x, t, d, xt)
             fn = evaluate(xt, gt)
-            if fn <= f + C1 * t * gd:
+            if fn <= f + c1 * t * gd:
                 ok = True
                 break
             t *= 0.5
@@ -239,7 +239,8 @@ class DeviceLBFGS:
         raw = self.state.view(torch.uint8)[:self.head].cpu().numpy().tobytes()
         return L.PmrLbfgsState.from_buffer_copy(raw)
 
-    def stage(self, modes, params, rel_tol=REL_TOL, stop_below=None):
+    def stage(self, modes, params, rel_tol=REL_TOL, stop_below=None, c1=C1,
+              max_halvings=MAX_HALVINGS):
         """One anneal stage from `modes` (complex64 [1][n_modes], updated in place) at loss
         parameters `params`. Returns a StageResult."""
         G = self.graph
@@ -251,8 +252,8 @@ class DeviceLBFGS:
         t0 = time.perf_counter()
         G.replay()
         self.g.copy_(G.grad.view(torch.float32).reshape(-1))
-        p = L.PmrLbfgsParams(m=self.m, max_iter=self.max_iter, max_halvings=MAX_HALVINGS,
-                             c1=C1, curvature_eps=CURVATURE_EPS, rel_tol=float(rel_tol),
+        p = L.PmrLbfgsParams(m=self.m, max_iter=self.max_iter, max_halvings=int(max_halvings),
+                             c1=float(c1), curvature_eps=CURVATURE_EPS, rel_tol=float(rel_tol),
                              stop_below=-math.inf if stop_below is None else float(stop_below))
         L.check(L.lib().pmr_lbfgs_init(self.n, ctypes.byref(p), _ptr(self.state),
                                        _ptr(G.loss), _ptr(self.g), _ptr(self.d), _ptr(self.S),

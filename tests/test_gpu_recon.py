@@ -329,3 +329,50 @@ def test_gpu_device_driver_retraces_host_driver(check_every):
         assert len(d.times) == len(d.losses) and all(b >= a for a, b in zip(d.times, d.times[1:]))
     assert host[0].reason == "max_iter" and host[1].reason == "target_loss"
     assert np.array_equal(dev_modes, host_modes)
+
+
+def test_gpu_device_driver_terminal_states():
+    """The device driver's other stopping rules, against the host driver: a failed line search
+    (Armijo constant 1 - 1e-6 and no halving: the first trial is rejected) and a zero gradient
+    at the start (density-L2 loss against the model's own output, prior weight 0: the residual
+    and so every adjoint field is exactly zero)."""
+    require_gpu()
+    say("recon: device driver, line-search failure and zero gradient")
+    n, box = 16, 100.0
+    ocfg, inv, s_true, target, s0 = _l2_problem(n, 3)
+    cfg = P.Config(batch=1, n_part=n, n_mesh=n, n_out=n, n_steps=3, box=box,
+                   loss_kind=P.PMR_LOSS_DENSITY_L2)
+
+    def context(tgt, prm):
+        pm = P.PMContext(cfg, DEV)
+        pm.set_prior(torch.from_numpy(inv.astype(np.float32)))
+        pm.set_target(tgt)
+        pm.set_loss(prm)
+        return pm, torch.from_numpy(s0.astype(np.complex64)).reshape(1, -1).to(DEV)
+
+    tgt = torch.from_numpy(target.astype(np.float32)).reshape(1, -1)
+    prm = P.LossParams()
+    pm, modes = context(tgt, prm)
+    host = R.minimize(pm, modes, max_iter=5, c1=1.0 - 1e-6, max_halvings=0)
+    pm, modes2 = context(tgt, prm)
+    D = R.DeviceLBFGS(pm, modes2, prm, max_iter=5, check_every=2)
+    dev = D.stage(modes2, prm, c1=1.0 - 1e-6, max_halvings=0)
+    say(f"  line search: host {host.reason} {host.evals} ev; device {dev.reason} {dev.evals} ev")
+    assert host.reason == "line_search" and dev.reason == "line_search"
+    assert (dev.losses, dev.evals, dev.iters) == (host.losses, host.evals, host.iters)
+    assert torch.equal(modes, modes2)
+
+    # the model's own final density as the target, no prior: g = 0 at the start
+    pm, modes = context(tgt, P.LossParams(prior_weight=0.0))
+    pm.forward(modes, want_mass=False)
+    own = pm.debug("delta_f").reshape(1, -1).float().clone()
+    prm0 = P.LossParams(prior_weight=0.0)
+    pm, modes = context(own, prm0)
+    host = R.minimize(pm, modes, max_iter=5)
+    pm, modes2 = context(own, prm0)
+    D = R.DeviceLBFGS(pm, modes2, prm0, max_iter=5)
+    dev = D.stage(modes2, prm0)
+    say(f"  zero gradient: host {host.reason} {host.losses}; device {dev.reason} {dev.losses}")
+    assert host.reason == "stationary" and dev.reason == "stationary"
+    assert dev.losses == host.losses == [0.0] and dev.evals == host.evals == 1
+    assert torch.equal(modes, modes2)
