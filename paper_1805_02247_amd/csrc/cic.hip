@@ -214,19 +214,25 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
     fa[1] += w * f.y;
     fa[2] += w * f.z;
   }
+  // The outputs go out with non-temporal stores, so that they do not displace the force
+  // mesh the corner gathers read from the caches: x and p are read again only a step later,
+  // the keys and fractions by the sort in another order (measured 2-5% faster per launch at
+  // 256^3/512^3 with the force mesh written the same way; bit for bit the same results).
   double xn[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const float pq = a.p_in[pi + q * np3] + a.kick * fa[q];
-    a.p_out[pi + q * np3] = pq;
-    if (a.p_ck) a.p_ck[pi + q * np3] = pq;
+    __builtin_nontemporal_store(pq, a.p_out + pi + q * np3);
+    if (a.p_ck) __builtin_nontemporal_store(pq, a.p_ck + pi + q * np3);
     xn[q] = wrap_box(xyz[q] + a.drift * (double)pq, a.box);
-    a.x_next[pi + q * np3] = xn[q];
+    __builtin_nontemporal_store(xn[q], a.x_next + pi + q * np3);
   }
   if (a.keys) {
     Vec3 f;
-    a.keys[g] = key_frac(xn, a.key_scale, a.key_nm, item, &f);
-    a.frac[g] = f;
+    __builtin_nontemporal_store(key_frac(xn, a.key_scale, a.key_nm, item, &f), a.keys + g);
+    __builtin_nontemporal_store(f.x, &a.frac[g].x);
+    __builtin_nontemporal_store(f.y, &a.frac[g].y);
+    __builtin_nontemporal_store(f.z, &a.frac[g].z);
   }
 }
 

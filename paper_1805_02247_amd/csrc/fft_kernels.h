@@ -505,8 +505,10 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
       const int e = threadIdx.x + m * NT;
       const int r = e / N, zz = e % N;
       const int q = 2 * zk(zz >> 1) + (zz & 1);  // float slot of real point zz
-      dst[e] = Vec3{l[(0 * R + r) * 2 * PITCH + q], l[(1 * R + r) * 2 * PITCH + q],
-                      l[(2 * R + r) * 2 * PITCH + q]};
+      // non-temporal: the force mesh is read only by the kick that follows the whole pass
+      __builtin_nontemporal_store(l[(0 * R + r) * 2 * PITCH + q], &dst[e].x);
+      __builtin_nontemporal_store(l[(1 * R + r) * 2 * PITCH + q], &dst[e].y);
+      __builtin_nontemporal_store(l[(2 * R + r) * 2 * PITCH + q], &dst[e].z);
     }
     if (next >= ntiles) break;
     __syncthreads();
