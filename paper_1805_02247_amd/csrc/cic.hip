@@ -79,7 +79,11 @@ __global__ __launch_bounds__(TB) void stream_gather_kernel(const uint32_t* __res
                                                            int total, Vec3* __restrict__ dst) {
   const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= total) return;
-  dst[j] = src[ids[j]];
+  const Vec3 v = src[ids[j]];
+  // non-temporal: the stream is read once, by the paint that follows the whole pass
+  __builtin_nontemporal_store(v.x, &dst[j].x);
+  __builtin_nontemporal_store(v.y, &dst[j].y);
+  __builtin_nontemporal_store(v.z, &dst[j].z);
 }
 
 // ---------------------------------------------------------------- paint

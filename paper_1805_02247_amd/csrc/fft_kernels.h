@@ -283,6 +283,20 @@ constexpr int paint_r2c_ty(int C) {
   return p;
 }
 
+// Store of one spectrum value; STREAM: past the caches (non-temporal), for spectra larger
+// than the memory-side cache, whose lines would be evicted before the next pass reads them
+// anyway (at 512^3 the fused paints measured 2-5% faster; at 128^3, where the next pass
+// finds the spectrum in that cache, slower).
+template <bool STREAM>
+__device__ __forceinline__ void store_spec(float2* p, float2 v) {
+  if constexpr (STREAM) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  } else {
+    *p = v;
+  }
+}
+
 template <int C, int TY, int N>
 __global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __restrict__ out,
                                                        FieldMap om) {
@@ -317,21 +331,21 @@ __global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __re
     float2* d = out + om.off(item * C + c) + ((size_t)ix * N + iyb + t) * om.pitch;
     if (k == 0) {
       const float2 z0 = z[0];
-      d[0] = make_float2(z0.x + z0.y - bN, 0.f);
-      d[H] = make_float2(z0.x - z0.y, 0.f);
+      store_spec<(N >= 512)>(&d[0], make_float2(z0.x + z0.y - bN, 0.f));
+      store_spec<(N >= 512)>(&d[H], make_float2(z0.x - z0.y, 0.f));
     } else {
       const float2 zv = z[zk(k)], zm = z[zk(H - k)];
       {
         float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
         float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
         float2 t2 = cmul(tw[k], df);
-        d[k] = make_float2(sm.x + t2.y, sm.y - t2.x);
+        store_spec<(N >= 512)>(&d[k], make_float2(sm.x + t2.y, sm.y - t2.x));
       }
       if (k != H - k) {
         float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
         float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
         float2 t2 = cmul(tw[H - k], df);
-        d[H - k] = make_float2(sm.x + t2.y, sm.y - t2.x);
+        store_spec<(N >= 512)>(&d[H - k], make_float2(sm.x + t2.y, sm.y - t2.x));
       }
     }
   }
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(NT) void zpass_c2r_kernel(const float2* __restrict_
         v.x += w.x;
         v.y += w.y;
       }
-      dst[e] = v;
+      store_spec<(N >= 512)>(&dst[e], v);
     }
     if (next >= ntiles) break;
     __syncthreads();

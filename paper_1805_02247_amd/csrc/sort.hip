@@ -504,7 +504,11 @@ __global__ __launch_bounds__(TB) void sorted_payload_kernel(const uint32_t* __re
       if (j0 + q * TB < n) v[q] = pay_in[id[q]];
 #pragma unroll
     for (int q = 0; q < PAY_PER; ++q)
-      if (j0 + q * TB < n) pay_out[j0 + q * TB] = v[q];
+      if (j0 + q * TB < n) {  // non-temporal: read once, by the paint after the sort
+        __builtin_nontemporal_store(v[q].x, &pay_out[j0 + q * TB].x);
+        __builtin_nontemporal_store(v[q].y, &pay_out[j0 + q * TB].y);
+        __builtin_nontemporal_store(v[q].z, &pay_out[j0 + q * TB].z);
+      }
   }
   if (inv) {
 #pragma unroll
