@@ -271,9 +271,11 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
  * adjoint, gradient assembly). `columns` consecutive kz columns per workgroup tile
  * (8, 16 or 32) and `threads` per workgroup (256 or 512), with
  * threads <= n * columns <= 16 * threads and the tile within 160 KB of LDS. `staging` 0 runs
- * the butterflies on register images of the tile (used where n * columns / threads is a
- * multiple of 8 and n >= 64; LDS only permutes between radix stages), 1 runs every stage on
- * the LDS-staged tile. Invalid values return PMR_E_INVALID and leave the shape unchanged.
+ * the butterflies on register images of the tile (radix-8 stages; used where n * columns /
+ * threads is a multiple of 8 and n >= 64; LDS only permutes between radix stages), 1 runs
+ * every stage on the LDS-staged tile with radix-8 stages (then one radix-4 or radix-2
+ * stage), 2 the same with radix-4 stages (then one radix-2 stage). Invalid values return
+ * PMR_E_INVALID and leave the shape unchanged.
  * Defaults: 16 columns, 256 threads, staging 0. Not synchronised with work in flight: set it
  * before enqueueing. */
 enum { PMR_FFT_YPASS = 0, PMR_FFT_XPASS = 1, PMR_FFT_XPASS_MULTI = 2 };

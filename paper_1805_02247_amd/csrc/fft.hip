@@ -121,14 +121,14 @@ void launch_ypass(int n, int fields, float2* data, FieldMap m, bool inverse, hip
   }
 }
 
-int set_fft_tile(int n, int pass, int pc, int nth, int lds) {
+int set_fft_tile(int n, int pass, int pc, int nth, int staging) {
   if (pass < 0 || pass > 2) return -1;
   if (n < 16 || n > 512 || (n & (n - 1))) return -1;
   if (pc != 8 && pc != 16 && pc != 32) return -1;
   if (nth != 256 && nth != 512) return -1;
   if (n * pc < nth || (n * pc + n) * 8 > 160 * 1024 || n * pc / nth > 16) return -1;
-  if (lds != 0 && lds != 1) return -1;
-  g_fft_tile[pass][log2i(n)] = {pc, nth, lds};
+  if (staging < 0 || staging > 2) return -1;
+  g_fft_tile[pass][log2i(n)] = {pc, nth, staging};
   return 0;
 }
 
@@ -172,11 +172,11 @@ int fft_slab_columns(int n) {
   return w >= n / 2 + 1 ? 0 : w;
 }
 
-void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds) {
+void get_fft_tile(int n, int pass, int* pc, int* nth, int* staging) {
   const TileShape t = g_fft_tile[pass][log2i(n)];
   *pc = t.pc;
   *nth = t.nth;
-  *lds = t.lds;
+  *staging = t.staging;
 }
 
 void launch_xpass(int op, const XPassArgs& a, hipStream_t s) {

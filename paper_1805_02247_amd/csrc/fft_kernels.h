@@ -138,18 +138,31 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* tw) {
   __syncthreads();
 }
 
-// Full M-point transform: radix-8 stages, then one radix-4 or radix-2 stage.
-template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT, bool PAD = false>
+// Full M-point transform. RMAX = 8: radix-8 stages, then one radix-4 or radix-2 stage;
+// RMAX = 4: radix-4 stages, then one radix-2 stage (more LDS round trips with fewer live
+// values per thread; the autotuner chooses per pass).
+template <int M, int LINES, int SN, int SL, int TWS, int DIR, int NTH = NT, bool PAD = false,
+          int RMAX = 8>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw) {
   static_assert(M >= 2 && (M & (M - 1)) == 0, "power of two");
-  if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
-  if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
-  if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
-  constexpr int P8 = M >= 512 ? 512 : M >= 64 ? 64 : M >= 8 ? 8 : 1;
-  constexpr int REM = M / P8;
-  if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
-  if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  static_assert(RMAX == 8 || RMAX == 4, "radix-8 or radix-4 plan");
   static_assert(M <= 512, "at most 512 points per line");
+  if constexpr (RMAX == 8) {
+    if constexpr (M >= 8) stockham_stage<M, 8, 1, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (M >= 64) stockham_stage<M, 8, 8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (M >= 512) stockham_stage<M, 8, 64, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    constexpr int P8 = M >= 512 ? 512 : M >= 64 ? 64 : M >= 8 ? 8 : 1;
+    constexpr int REM = M / P8;
+    if constexpr (REM == 4) stockham_stage<M, 4, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (REM == 2) stockham_stage<M, 2, P8, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  } else {
+    if constexpr (M >= 4) stockham_stage<M, 4, 1, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (M >= 16) stockham_stage<M, 4, 4, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (M >= 64) stockham_stage<M, 4, 16, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    if constexpr (M >= 256) stockham_stage<M, 4, 64, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+    constexpr int P4 = M >= 256 ? 256 : M >= 64 ? 64 : M >= 16 ? 16 : M >= 4 ? 4 : 1;
+    if constexpr (M / P4 == 2) stockham_stage<M, 2, P4, LINES, SN, SL, TWS, DIR, NTH, PAD>(lds, tw);
+  }
 }
 
 // exp(-2 pi i j / N) for j < N: copied from the compile-time table (twiddle.h).
@@ -609,7 +622,7 @@ __device__ __forceinline__ void regs_to_lds(const TileRegs<N, PC, NTH, V>& t, fl
 // y pass: in-place forward or inverse transform along y of each field. A workgroup walks
 // the tiles blockIdx.x, blockIdx.x + gridDim.x, ... (tile = (field, x plane, kz chunk)),
 // prefetching the next tile into registers.
-template <int N, int DIR, int PC, int NTH, int V>
+template <int N, int DIR, int PC, int NTH, int V, int RMAX = 8>
 __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, FieldMap m,
                                                     int ntiles, int ch0, int nchw) {
   constexpr int NH = N / 2 + 1;
@@ -637,7 +650,7 @@ __global__ __launch_bounds__(NTH) void ypass_kernel(float2* __restrict__ data, F
       b2 = tile_base(next, nc2);
       load_regs<N, PC, NTH, V>(pre, b2, m.pitch, nc2);
     }
-    fft_lds<N, PC, PC, 1, 1, DIR, NTH>(lds, tw);
+    fft_lds<N, PC, PC, 1, 1, DIR, NTH, false, RMAX>(lds, tw);
     store_tile<N, PC, NTH, V>(lds, b, m.pitch, nc);
     if (next >= ntiles) break;
     __syncthreads();
@@ -715,7 +728,7 @@ constexpr bool spectral_input() {
   return OP == XOP_ZA || OP == XOP_INV || OP == XOP_HESS;
 }
 
-template <int N, int OP, int PC, int NTH, int V>
+template <int N, int OP, int PC, int NTH, int V, int RMAX = 8>
 __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int ch0, int nchw) {
   constexpr int NH = N / 2 + 1;
   constexpr int NE = N * PC;
@@ -767,7 +780,8 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
         load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
                               istride, min(PC, NH - nkz0));
       }
-      if constexpr (!spectral_input<OP>()) fft_lds<N, PC, PC, 1, 1, -1, NTH>(lds, tw);
+      if constexpr (!spectral_input<OP>())
+        fft_lds<N, PC, PC, 1, 1, -1, NTH, false, RMAX>(lds, tw);
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
         const int e = t + m * NTH;
@@ -872,7 +886,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
           lds[e] = v;
         }
         __syncthreads();
-        fft_lds<N, PC, PC, 1, 1, +1, NTH>(lds, tw);
+        fft_lds<N, PC, PC, 1, 1, +1, NTH, false, RMAX>(lds, tw);
         store_tile<N, PC, NTH, V>(lds, a.out[o] + ooff, ostride, ncols);
         __syncthreads();
       }
@@ -1290,14 +1304,29 @@ __host__ inline void kz_chunks(int lo, int hi, int& ch0, int& nchw) {
   nchw = (h + PC - 1) / PC - ch0;
 }
 
+// Staging of the strided passes: 0 register-resident (radix-8 plan), 1 LDS-staged radix-8
+// plan, 2 LDS-staged radix-4 plan.
+template <int N, int DIR, int PC, int NTH, int V>
+void ypass_lds_launch(int staging, float2* d, FieldMap m, int ntiles, int ch0, int nchw,
+                      hipStream_t s) {
+  if (staging == 2) {
+    constexpr auto k = ypass_kernel<N, DIR, PC, NTH, V, 4>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
+  } else {
+    constexpr auto k = ypass_kernel<N, DIR, PC, NTH, V, 8>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
+  }
+}
+
 template <int N, int PC, int NTH>
-void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t s, KzWin win) {
+void ypass_t(int fields, float2* d, FieldMap m, bool inv, int staging, hipStream_t s,
+             KzWin win) {
   int ch0, nchw;
   kz_chunks<N, PC>(win.lo, win.hi, ch0, nchw);
   if (nchw <= 0) return;
   const int ntiles = nchw * N * fields;
   if constexpr (reg_ok<N, PC, NTH>()) {
-    if (!lds) {
+    if (staging == 0) {
       if (inv) {
         constexpr auto k = ypass_reg_kernel<N, +1, PC, NTH>;
         k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
@@ -1310,33 +1339,39 @@ void ypass_t(int fields, float2* d, FieldMap m, bool inv, bool lds, hipStream_t 
   }
   if constexpr (pairs_ok<N, PC, NTH>()) {
     if (m.pitch % 2 == 0) {
-      if (inv) {
-        constexpr auto k = ypass_kernel<N, +1, PC, NTH, 2>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
-      } else {
-        constexpr auto k = ypass_kernel<N, -1, PC, NTH, 2>;
-        k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
-      }
+      if (inv)
+        ypass_lds_launch<N, +1, PC, NTH, 2>(staging, d, m, ntiles, ch0, nchw, s);
+      else
+        ypass_lds_launch<N, -1, PC, NTH, 2>(staging, d, m, ntiles, ch0, nchw, s);
       return;
     }
   }
-  if (inv) {
-    constexpr auto k = ypass_kernel<N, +1, PC, NTH, 1>;
-    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
+  if (inv)
+    ypass_lds_launch<N, +1, PC, NTH, 1>(staging, d, m, ntiles, ch0, nchw, s);
+  else
+    ypass_lds_launch<N, -1, PC, NTH, 1>(staging, d, m, ntiles, ch0, nchw, s);
+}
+
+template <int N, int OP, int PC, int NTH, int V>
+void xpass_lds_launch(int staging, const XPassArgs& a, int ntiles, int ch0, int nchw,
+                      hipStream_t s) {
+  if (staging == 2) {
+    constexpr auto k = xpass_kernel<N, OP, PC, NTH, V, 4>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
   } else {
-    constexpr auto k = ypass_kernel<N, -1, PC, NTH, 1>;
-    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(d, m, ntiles, ch0, nchw);
+    constexpr auto k = xpass_kernel<N, OP, PC, NTH, V, 8>;
+    k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
   }
 }
 
 template <int N, int OP, int PC, int NTH>
-void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
+void xpass_t(const XPassArgs& a, int staging, hipStream_t s) {
   int ch0, nchw;
   kz_chunks<N, PC>(a.kz_lo, a.kz_hi, ch0, nchw);
   if (nchw <= 0) return;
   const int ntiles = nchw * N * a.batch;
   if constexpr (reg_ok<N, PC, NTH>()) {
-    if (!lds) {
+    if (staging == 0) {
       constexpr auto k = xpass_reg_kernel<N, OP, PC, NTH>;
       k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
       return;
@@ -1345,13 +1380,11 @@ void xpass_t(const XPassArgs& a, bool lds, hipStream_t s) {
   if constexpr (pairs_ok<N, PC, NTH>() && OP != XOP_ZA && OP != XOP_ZA_ADJ && OP != XOP_HESS &&
                 OP != XOP_HESS_ADJ) {
     if (a.in_pitch % 2 == 0 && a.out_pitch % 2 == 0) {
-      constexpr auto k = xpass_kernel<N, OP, PC, NTH, 2>;
-      k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
+      xpass_lds_launch<N, OP, PC, NTH, 2>(staging, a, ntiles, ch0, nchw, s);
       return;
     }
   }
-  constexpr auto k = xpass_kernel<N, OP, PC, NTH, 1>;
-  k<<<tile_grid<k, NTH>(ntiles), NTH, 0, s>>>(a, ntiles, ch0, nchw);
+  xpass_lds_launch<N, OP, PC, NTH, 1>(staging, a, ntiles, ch0, nchw, s);
 }
 
 // Supported shapes: PC in {8, 16, 32}, NTH in {256, 512}, with N * PC >= NTH and the LDS
@@ -1369,12 +1402,12 @@ void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s, KzWin win
 #define SHAPE(PC, NTH)                                        \
   if constexpr (shape_ok<N>(PC, NTH))                         \
     if (t.pc == PC && t.nth == NTH) {                         \
-      ypass_t<N, PC, NTH>(fields, d, m, inv, t.lds, s, win);  \
-      return;                                                 \
+      ypass_t<N, PC, NTH>(fields, d, m, inv, t.staging, s, win);  \
+      return;                                                     \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE
-  ypass_t<N, 16, 256>(fields, d, m, inv, t.lds, s, win);
+  ypass_t<N, 16, 256>(fields, d, m, inv, t.staging, s, win);
 }
 
 // Multi-input operators hold three register images (accumulator, current, prefetch); at
@@ -1391,16 +1424,16 @@ void xpass_op(const XPassArgs& a, hipStream_t s) {
   if constexpr (shape_ok<N>(PC, NTH))                                          \
     if (t.pc == PC && t.nth == NTH) {                                          \
       if constexpr (multi_input<OP>() && N * PC / NTH > 8 && PC > 8)           \
-        if (!t.lds) {                                                          \
-          xpass_t<N, OP, PC / 2, NTH>(a, false, s);                            \
+        if (t.staging == 0) {                                                  \
+          xpass_t<N, OP, PC / 2, NTH>(a, 0, s);                                \
           return;                                                              \
         }                                                                      \
-      xpass_t<N, OP, PC, NTH>(a, t.lds, s);                                    \
+      xpass_t<N, OP, PC, NTH>(a, t.staging, s);                                \
       return;                                                                  \
     }
   PMR_FOR_SHAPE(SHAPE)
 #undef SHAPE
-  xpass_t<N, OP, 16, 256>(a, t.lds, s);
+  xpass_t<N, OP, 16, 256>(a, t.staging, s);
 }
 
 template <int N>

@@ -199,7 +199,7 @@ void launch_xpass(int op, const XPassArgs& a, hipStream_t s);
 // 1: x pass with a single-input operator, 2: x pass with a multi-input operator) and log2(n);
 // set by pmr_fft_set_tile (the autotuner) or left at the defaults. Defined in fft.hip.
 struct TileShape {
-  int pc, nth, lds;
+  int pc, nth, staging;  // staging: 0 registers, 1 LDS radix-8, 2 LDS radix-4
 };
 extern TileShape g_fft_tile[3][10];
 
@@ -207,8 +207,8 @@ extern TileShape g_fft_tile[3][10];
 // from PMR_PAINT_LDS_FLOATS and PMR_PAINT_TY_MAX); set by pmr_paint_set_rows (the autotuner).
 int set_paint_rows(int n, int channels, int rows);
 int get_paint_rows(int n, int channels);
-int set_fft_tile(int n, int pass, int pc, int nth, int lds);
-void get_fft_tile(int n, int pass, int* pc, int* nth, int* lds);
+int set_fft_tile(int n, int pass, int pc, int nth, int staging);
+void get_fft_tile(int n, int pass, int* pc, int* nth, int* staging);
 // kz-slab width of the strided passes per size (0: off); fft_slab_columns gives the width
 // in use (a multiple of every pass's tile columns, 0 when one slab would hold everything).
 int set_fft_slab(int n, int columns);

@@ -1,5 +1,7 @@
 """Autotuner for the tile shapes of the strided FFT passes (columns per tile, threads per
-workgroup, register or LDS staging of the butterflies), separately for the y pass, the x pass
+workgroup, and the staging and radix of the butterflies: register images with radix-8
+stages, or the LDS-staged tile with radix-8 or radix-4 stages), separately for the y pass,
+the x pass
 with single-input k-space operators and the x pass with multi-input operators, per mesh size,
 on the current GPU.
 
@@ -31,9 +33,12 @@ def valid(n, pc, nth):
     return n * pc >= nth and (n * pc + n) * 8 <= 160 * 1024 and n * pc // nth <= 16
 
 
+STAGINGS = {0: "reg", 1: "lds", 2: "lds4"}  # registers (radix 8), LDS radix 8, LDS radix 4
+
+
 def register_capable(n, pc, nth):
-    """Shapes whose butterflies can run on register images (otherwise both stagings are the
-    LDS-staged passes)."""
+    """Shapes whose butterflies can run on register images (otherwise staging 0 falls back
+    to the LDS-staged radix-8 pass)."""
     p = n * pc // nth
     return n >= 64 and p >= 8 and p % 8 == 0
 
@@ -42,13 +47,13 @@ def candidates(n):
     out = []
     for pc, nth in SHAPES:
         if valid(n, pc, nth):
-            for lds in ((0, 1) if register_capable(n, pc, nth) else (1,)):
-                out.append((pc, nth, lds))
+            for st in ((0, 1, 2) if register_capable(n, pc, nth) else (1, 2)):
+                out.append((pc, nth, st))
     return out
 
 
 def _key(c):
-    return f"{c[0]}x{c[1]}x{'lds' if c[2] else 'reg'}"
+    return f"{c[0]}x{c[1]}x{STAGINGS[c[2]]}"
 
 
 def _set(n, pass_, c):
@@ -123,7 +128,7 @@ def _tune_passes(step, sizes, reps, log):
                 _set(n, pid, c)
                 times[c] = _timer(step, reps)
                 log(f"n={n} pass={p} columns={c[0]} threads={c[1]} "
-                    f"staging={'lds' if c[2] else 'reg'}: {times[c] * 1e3:.3f} ms")
+                    f"staging={STAGINGS[c[2]]}: {times[c] * 1e3:.3f} ms")
             c = min(times, key=times.get)
             _set(n, pid, c)
             best[n][p] = c

@@ -93,12 +93,14 @@ def test_fft_tile_shape_validation():
         return (c.value, t.value, s.value)
     saved = {p: get(128, p) for p in (0, 1)}
     try:
+        assert lib.pmr_fft_set_tile(128, 0, 32, 256, 2) == 0
+        assert get(128, 0) == (32, 256, 2)
         assert lib.pmr_fft_set_tile(128, 0, 32, 256, 1) == 0
         assert lib.pmr_fft_set_tile(128, 1, 8, 512, 0) == 0
         assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
         for bad in [(128, 3, 16, 256, 0), (128, 0, 12, 256, 0), (128, 0, 16, 384, 0),
-                    (128, 1, 32, 256, 2), (512, 0, 32, 256, 0), (96, 0, 16, 256, 0),
-                    (16, 1, 8, 256, 0)]:
+                    (128, 1, 32, 256, 3), (128, 1, 32, 256, -1), (512, 0, 32, 256, 0),
+                    (96, 0, 16, 256, 0), (16, 1, 8, 256, 0)]:
             assert lib.pmr_fft_set_tile(*bad) == -1, bad
         assert get(128, 0) == (32, 256, 1) and get(128, 1) == (8, 512, 0)
         assert lib.pmr_fft_get_tile(24, 0, ctypes.byref(c), ctypes.byref(t), ctypes.byref(s)) == -1

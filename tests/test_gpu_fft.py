@@ -97,8 +97,9 @@ SHAPES = [(8, 256), (16, 256), (32, 256), (8, 512), (16, 512), (32, 512)]
 
 @pytest.mark.parametrize("n", [64, 128])
 def test_every_tile_shape_and_staging(n):
-    """Each supported tile shape, with register and LDS staging, in each strided pass, against
-    the oracle (the other pass held at its current shape)."""
+    """Each supported tile shape, with register staging and LDS staging of radix-8 and of
+    radix-4 stages, in each strided pass, against the oracle (the other pass held at its
+    current shape)."""
     require_gpu()
     import paper_1805_02247_amd as P
     from paper_1805_02247_amd.tune import candidates

@@ -249,11 +249,12 @@ def tile_shape():
         P.fft_set_tile(n, p, *v)
 
 
-@pytest.mark.parametrize("staging", [0, 1])
+@pytest.mark.parametrize("staging", [0, 1, 2])
 def test_register_and_lds_fft_staging_64_on_128(tile_shape, staging):
     """64^3 particles on a 128^3 force mesh (64^3 output), 3 steps, H = 32: sizes where the
     strided passes and every fused k-space operator run on register images (staging 0,
-    8 and 16 points per thread) or on LDS-staged tiles (staging 1)."""
+    8 and 16 points per thread) or on LDS-staged tiles with radix-8 (staging 1) or radix-4
+    (staging 2) stages."""
     require_gpu()
     say(f"pipeline: 64^3 on 128^3, staging {staging}")
     tile_shape(64, 32, 256, staging)
