@@ -138,6 +138,76 @@ __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, 
   }
 }
 
+// One target row per wavefront (TY = 1): a particle of source row sy reaches that row
+// through one corner row only (oy = 1 from row iy0 - 1, oy = 0 from row iy0; its other
+// corner row belongs to another wavefront), so a chunk carries the 2 C values of that oy:
+// half the weights and half the scan of the general chunk. The same lanes deposit the same
+// values in the same phases as the general path, so the rows are bitwise the same.
+template <int C>
+struct Chunk1 {
+  uint32_t key;
+  int iz, oy;
+  bool ok;
+  float v[2 * C];
+};
+
+template <int C>
+__device__ __forceinline__ void load_chunk1(const PaintArgs& a, uint32_t j, uint32_t end, int ox,
+                                            int iy0, Chunk1<C>& ch) {
+  const int lane = threadIdx.x & 63;
+  const int nm = a.nm;
+  ch.ok = j < end;
+  ch.key = 0xffffffffu - lane;  // never equal across lanes when invalid
+  ch.iz = 0;
+  ch.oy = 0;
+#pragma unroll
+  for (int q = 0; q < 2 * C; ++q) ch.v[q] = 0.f;
+  if (ch.ok) {
+    const uint32_t key = a.keys[j];
+    const Vec3 f = a.frac[j];
+    ch.key = key;
+    ch.iz = (int)(key & (uint32_t)(nm - 1));
+    const int sy = (int)((key >> a.log_nm) & (uint32_t)(nm - 1));
+    ch.oy = sy == iy0 ? 0 : 1;
+    const float wx = ox ? f.x : 1.f - f.x;
+    float val[C];
+    if constexpr (C == 1) {
+      val[0] = a.mass * wx;
+    } else {
+      const Vec3 u = a.val[j];
+      val[0] = u.x * wx;
+      val[1] = u.y * wx;
+      val[2] = u.z * wx;
+    }
+    const float wy = ch.oy ? f.y : 1.f - f.y, wz0 = 1.f - f.z, wz1 = f.z;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ch.v[2 * c + 0] = val[c] * wy * wz0;
+      ch.v[2 * c + 1] = val[c] * wy * wz1;
+    }
+  }
+}
+
+template <int C, bool PAD = false>
+__device__ __forceinline__ void deposit1(const Chunk1<C>& ch, float* acc, int nm, int rp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kn = __shfl_down(ch.key, 1, 64);
+  const int ok_next = __shfl_down((int)ch.ok, 1, 64);
+  const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
+  const int iz1 = (ch.iz + 1) & (nm - 1);
+#pragma unroll
+  for (int ph = 0; ph < 4; ++ph) {
+    const int oy = ph >> 1, oz = ph & 1;
+    PMR_PHASE_FENCE();
+    if (tail && ch.oy == oy) {
+      float* row = acc + row_slot<PAD>(oz ? iz1 : ch.iz);
+#pragma unroll
+      for (int c = 0; c < C; ++c) row[c * rp] = row[c * rp] + ch.v[2 * c + oz];
+    }
+    PMR_PHASE_FENCE();
+  }
+}
+
 // Chunks of 64 particles loaded together before their scans and deposits (memory-level
 // parallelism of a wave's walk over its source rows).
 #ifndef PMR_PAINT_CHUNKS
@@ -181,14 +251,26 @@ __device__ __forceinline__ void paint_rows(const PaintArgs& a, int item, int ix,
       }
 #pragma unroll 1
       for (uint32_t c0 = beg; c0 < end; c0 += 64 * CH) {
-        Chunk<C> ch[CH];
+        if constexpr (TY == 1) {
+          Chunk1<C> ch[CH];
 #pragma unroll
-        for (int q = 0; q < CH; ++q) load_chunk<C>(a, c0 + 64 * q + lane, end, ox, ch[q]);
+          for (int q = 0; q < CH; ++q)
+            load_chunk1<C>(a, c0 + 64 * q + lane, end, ox, iy0, ch[q]);
 #pragma unroll
-        for (int q = 0; q < CH; ++q) seg_scan<4 * C>(ch[q].v, ch[q].key);
+          for (int q = 0; q < CH; ++q) seg_scan<2 * C>(ch[q].v, ch[q].key);
 #pragma unroll
-        for (int q = 0; q < CH; ++q)
-          if (q == 0 || c0 + 64 * q < end) deposit<C, TY, PAD>(ch[q], acc, nm, iy0, rp);
+          for (int q = 0; q < CH; ++q)
+            if (q == 0 || c0 + 64 * q < end) deposit1<C, PAD>(ch[q], acc, nm, rp);
+        } else {
+          Chunk<C> ch[CH];
+#pragma unroll
+          for (int q = 0; q < CH; ++q) load_chunk<C>(a, c0 + 64 * q + lane, end, ox, ch[q]);
+#pragma unroll
+          for (int q = 0; q < CH; ++q) seg_scan<4 * C>(ch[q].v, ch[q].key);
+#pragma unroll
+          for (int q = 0; q < CH; ++q)
+            if (q == 0 || c0 + 64 * q < end) deposit<C, TY, PAD>(ch[q], acc, nm, iy0, rp);
+        }
       }
     }
   }

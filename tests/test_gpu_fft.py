@@ -59,14 +59,24 @@ def _separable(n, seed):
     return v, x.astype(np.float32)
 
 
-@pytest.mark.parametrize("n", [256, 512])
-def test_r2c_large_separable(n):
+@pytest.mark.parametrize("n,staging", [(256, None), (512, None), (512, 2)])
+def test_r2c_large_separable(n, staging):
     """At full size: a sum of two separable fields, whose transform is the sum of outer
-    products of 1-D transforms; checked on 8 sampled kx planes."""
+    products of 1-D transforms; checked on 8 sampled kx planes. With the tuned tiles, and at
+    512 also with both strided passes on LDS-staged radix-4 stages."""
     require_gpu()
-    say(f"r2c separable n={n}")
+    import paper_1805_02247_amd as P
+    say(f"r2c separable n={n} staging={staging}")
     v, x = _separable(n, 7)
-    X = api.fft_r2c(torch.from_numpy(x).to(DEV)[None])[0]
+    saved = {p: P.fft_get_tile(n, p) for p in (P.PMR_FFT_YPASS, P.PMR_FFT_XPASS)}
+    try:
+        if staging is not None:
+            for p in saved:
+                P.fft_set_tile(n, p, 16, 512, staging)
+        X = api.fft_r2c(torch.from_numpy(x).to(DEV)[None])[0]
+    finally:
+        for p, t in saved.items():
+            P.fft_set_tile(n, p, *t)
     del x
     planes = np.random.default_rng(n).choice(n, 8, replace=False)
     # closed form from the FP64 factors; the float32 rounding of the input adds ~1e-7
