@@ -202,7 +202,11 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   const int item = g >> a.log_np3;
   const size_t id = g & (np3 - 1);
   const size_t pi = (size_t)item * 3 * np3 + id;
-  double xyz[3] = {a.x[pi], a.x[pi + np3], a.x[pi + 2 * np3]};
+  // the particle's own streams are read once: non-temporal loads, so that the force-mesh
+  // corners stay in the caches (likewise the sorted streams of the adjoint gather)
+  double xyz[3] = {__builtin_nontemporal_load(a.x + pi),
+                   __builtin_nontemporal_load(a.x + pi + np3),
+                   __builtin_nontemporal_load(a.x + pi + 2 * np3)};
   const int nm = a.nm;
   const Corner c = corner_of(xyz, a.scale, nm);
   const size_t cells = (size_t)nm * nm * nm;
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(TB) void kick_drift_kernel(StepArgs a) {
   double xn[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const float pq = a.p_in[pi + q * np3] + a.kick * fa[q];
+    const float pq = __builtin_nontemporal_load(a.p_in + pi + q * np3) + a.kick * fa[q];
     __builtin_nontemporal_store(pq, a.p_out + pi + q * np3);
     if (a.p_ck) __builtin_nontemporal_store(pq, a.p_ck + pi + q * np3);
     xn[q] = wrap_box(xyz[q] + a.drift * (double)pq, a.box);
@@ -265,8 +269,10 @@ template <bool WF>
 __global__ __launch_bounds__(TB) void adjoint_positions_kernel(AdjPosArgs a) {
   const int j = xcd_block(blockIdx.x, gridDim.x) * TB + threadIdx.x;
   if (j >= a.total) return;
-  const uint32_t key = a.keys[j];
-  const Vec3 fr = a.frac[j];
+  const uint32_t key = __builtin_nontemporal_load(a.keys + j);
+  const Vec3 fr = Vec3{__builtin_nontemporal_load(&a.frac[j].x),
+                       __builtin_nontemporal_load(&a.frac[j].y),
+                       __builtin_nontemporal_load(&a.frac[j].z)};
   const int nm = a.nm, lg = a.log_nm;
   const uint32_t item = key >> (3 * lg);
   const uint32_t i0[3] = {(key >> (2 * lg)) & (uint32_t)(nm - 1), (key >> lg) & (uint32_t)(nm - 1),
