@@ -29,8 +29,10 @@ TRAFFIC_PROFILES = {"p128_m128_b4": "hbm_traffic_128cube_B4_fp32.txt",
                     "p256_m512": "hbm_traffic_256cube_512mesh.txt"}
 CLASS_KERNELS = {
     "paint": r"paint_r2c_kernel<1,", "paint3": r"paint_r2c_kernel<3,",
-    "xpass_force": r"xpass(_reg)?_kernel<\d+, 2,", "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, 3,",
-    "ypass": r"ypass(_reg)?_kernel<", "zpass": r"zpass_", "kick_drift": r"kick_drift_kernel",
+    "xpass_force": r"xpass(_reg)?_kernel<\d+, (2|11),",
+    "xpass_force_adj": r"xpass(_reg)?_kernel<\d+, (3|12),",
+    "ypass": r"(ypass(_reg)?_kernel<|xpass(_reg)?_kernel<\d+, 1[34],)", "zpass": r"zpass_",
+    "kick_drift": r"kick_drift_kernel",
     "adj_gather": r"adjoint_positions_kernel", "adj_update": r"adjoint_update_kernel",
     "sort": r"(fill_u32|row_count|scan_reduce|scan_partials|scan_write|bucket|row_sort_wave|"
             r"row_sort_block)_kernel",

@@ -177,6 +177,15 @@ __device__ __forceinline__ void make_twiddles(float2* tw) {
   }
 }
 
+// ---------------------------------------------------------------- k-space factors
+// k_a = kf m of storage index i along one axis (m = i for i <= N / 2, else i - N; the half
+// kz axis needs no wrap), zero on the Nyquist plane as in the force operator's gradient factors.
+template <int N>
+__device__ __forceinline__ float axis_coef(int i, float kf) {
+  const int m = wavenumber(i, N);
+  return (m == N / 2 || m == -N / 2) ? 0.f : kf * m;
+}
+
 // ---------------------------------------------------------------- z pass, r2c
 template <int N>
 struct ZTile {
@@ -342,23 +351,36 @@ __global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __re
     const int c = line % C, t = line / C;  // t: row within the workgroup
     const float2* z = lds + line * PITCH;
     float2* d = out + om.off(item * C + c) + ((size_t)ix * N + iyb + t) * om.pitch;
+    // channel 2 of the adjoint force paint: times conj(i k_z) (kz = 0 and the Nyquist plane
+    // vanish)
+    const bool zg = C == 3 && c == 2 && a.kz_grad != 0.f;
     if (k == 0) {
       const float2 z0 = z[0];
-      store_spec<(N >= 512)>(&d[0], make_float2(z0.x + z0.y - bN, 0.f));
-      store_spec<(N >= 512)>(&d[H], make_float2(z0.x - z0.y, 0.f));
+      store_spec<(N >= 512)>(&d[0], make_float2(zg ? 0.f : z0.x + z0.y - bN, 0.f));
+      store_spec<(N >= 512)>(&d[H], make_float2(zg ? 0.f : z0.x - z0.y, 0.f));
     } else {
       const float2 zv = z[zk(k)], zm = z[zk(H - k)];
       {
         float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
         float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
         float2 t2 = cmul(tw[k], df);
-        store_spec<(N >= 512)>(&d[k], make_float2(sm.x + t2.y, sm.y - t2.x));
+        float2 x = make_float2(sm.x + t2.y, sm.y - t2.x);
+        if (zg) {
+          const float cz = axis_coef<N>(k, a.kz_grad);
+          x = cmul_i<-1>(make_float2(cz * x.x, cz * x.y));
+        }
+        store_spec<(N >= 512)>(&d[k], x);
       }
       if (k != H - k) {
         float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
         float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
         float2 t2 = cmul(tw[H - k], df);
-        store_spec<(N >= 512)>(&d[H - k], make_float2(sm.x + t2.y, sm.y - t2.x));
+        float2 x = make_float2(sm.x + t2.y, sm.y - t2.x);
+        if (zg) {
+          const float cz = axis_coef<N>(H - k, a.kz_grad);
+          x = cmul_i<-1>(make_float2(cz * x.x, cz * x.y));
+        }
+        store_spec<(N >= 512)>(&d[H - k], x);
       }
     }
   }
@@ -481,10 +503,12 @@ struct ZTile3 {
   static constexpr int R = ZTile<N>::ROWS / 2 > 0 ? ZTile<N>::ROWS / 2 : 1;  // rows per field
 };
 
+// kz_grad != 0: component 2 enters as i k_z times its spectrum, k_z = kz_grad * kz (zero on
+// the Nyquist plane): the z derivative of the force split over the axes.
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict__ in, FieldMap im,
                                                         Vec3* __restrict__ out,
-                                                        size_t out_item_stride,
+                                                        size_t out_item_stride, float kz_grad,
                                                         int tiles_per_item, int ntiles) {
   using T = ZTile<N>;
   constexpr int H = T::H, PITCH = T::PITCH, R = ZTile3<N>::R;
@@ -516,7 +540,17 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
 #pragma unroll
     for (int m = 0; m < PR::PER; ++m) {
       const int e = threadIdx.x + m * NT;
-      if (e < 3 * R * Q) inv_split<H>(lds + (e / Q) * PITCH, e % Q, pre.a[m], pre.b[m], tw);
+      if (e < 3 * R * Q) {
+        const int k = e % Q;
+        float2 xa = pre.a[m], xb = pre.b[m];
+        // (applied here, where the prefetched values are consumed, not where they are loaded)
+        if (e / Q >= 2 * R && kz_grad != 0.f) {  // component 2: X[kz] i k_z, kz = k and H - k
+          const float ca = axis_coef<N>(k, kz_grad), cb = axis_coef<N>(H - k, kz_grad);
+          xa = cmul_i<1>(make_float2(ca * xa.x, ca * xa.y));
+          xb = cmul_i<1>(make_float2(cb * xb.x, cb * xb.y));
+        }
+        inv_split<H>(lds + (e / Q) * PITCH, k, xa, xb, tw);
+      }
     }
     __syncthreads();
     const int next = tau + gridDim.x;
@@ -701,6 +735,12 @@ __device__ __forceinline__ float hess_coef(const KVec& k, int a, int b) {
   return ka * kb * __builtin_amdgcn_rcpf(k.k2);
 }
 
+// 1 / k^2 with k = 0 removed (the potential of the split force operator).
+template <int N>
+__device__ __forceinline__ float inv_k2(const KVec& k) {
+  return k.k2 == 0.f ? 0.f : __builtin_amdgcn_rcpf(k.k2);
+}
+
 // Pair o of a Hessian pair set: set 0 holds the diagonal (xx, yy, zz), set 1 the
 // off-diagonal (xy, xz, yz).
 __device__ __forceinline__ void hess_pair(int set, int o, int& a, int& b) {
@@ -715,17 +755,31 @@ __device__ __forceinline__ void hess_pair(int set, int o, int& a, int& b) {
 template <int OP>
 constexpr int xpass_inputs() {
   return (OP == XOP_FORCE_ADJ || OP == XOP_ZA_ADJ || OP == XOP_HESS_ADJ) ? 3
-         : OP == XOP_FEAT_ADJ                                          ? 2
-                                                                       : 1;
+         : (OP == XOP_FEAT_ADJ || OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ) ? 2
+                                                                                  : 1;
 }
 template <int OP>
 constexpr int xpass_outputs() {
-  return (OP == XOP_FORCE || OP == XOP_ZA || OP == XOP_HESS) ? 3 : (OP == XOP_GAUSS2 ? 2 : 1);
+  return (OP == XOP_FORCE || OP == XOP_ZA || OP == XOP_HESS) ? 3
+         : (OP == XOP_GAUSS2 || OP == XOP_FORCE_X || OP == XOP_YGRAD) ? 2
+                                                                      : 1;
 }
-// Operators whose input is already a full spectrum (no forward transform along x).
+// Operators whose input is already a full spectrum along the pass's axis (no forward
+// transform along it).
 template <int OP>
 constexpr bool spectral_input() {
-  return OP == XOP_ZA || OP == XOP_INV || OP == XOP_HESS;
+  return OP == XOP_ZA || OP == XOP_INV || OP == XOP_HESS || OP == XOP_YGRAD;
+}
+// Operators whose output is the forward transform itself (no inverse along the axis).
+template <int OP>
+constexpr bool spectral_output() {
+  return OP == XOP_FWD || OP == XOP_YGRAD_ADJ;
+}
+// Operators on y lines: the line of a tile strides one row (pitch) instead of one plane
+// (n rows), and the tile's fixed index is the x plane.
+template <int OP>
+constexpr bool yline() {
+  return OP == XOP_YGRAD || OP == XOP_YGRAD_ADJ;
 }
 
 template <int N, int OP, int PC, int NTH, int V, int RMAX = 8>
@@ -737,7 +791,12 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
   __shared__ __attribute__((aligned(16))) float2 lds[NE];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
-  const size_t istride = (size_t)N * a.in_pitch, ostride = (size_t)N * a.out_pitch;
+  constexpr bool YL = yline<OP>();
+  // point stride along the transformed axis and the stride of the tile's fixed index
+  const size_t istride = YL ? a.in_pitch : (size_t)N * a.in_pitch;
+  const size_t ostride = YL ? a.out_pitch : (size_t)N * a.out_pitch;
+  const size_t irow = YL ? (size_t)N * a.in_pitch : a.in_pitch;
+  const size_t orow = YL ? (size_t)N * a.out_pitch : a.out_pitch;
   const size_t stride = (size_t)N * NH;  // prior table and projected modes (standard layout)
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
@@ -750,15 +809,15 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
   {
     const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
-    load_regs<N, PC, NTH, V>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0,
+    load_regs<N, PC, NTH, V>(pre, a.in[0] + item * a.in_item_stride + (size_t)iy * irow + kz0,
                           istride, min(PC, NH - kz0));
   }
   for (;;) {
     const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
-    const size_t ioff = item * a.in_item_stride + (size_t)iy * a.in_pitch + kz0;
-    const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
+    const size_t ioff = item * a.in_item_stride + (size_t)iy * irow + kz0;
+    const size_t ooff = item * a.out_item_stride + (size_t)iy * orow + kz0;
     const int next = tau + gridDim.x;
 
     float2 hold[PER];  // spectrum (1-in ops) or accumulator (n-in ops)
@@ -777,7 +836,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
       } else if (next < ntiles) {
         const int nch = ch0 + next % nchw, niy = (next / nchw) % N, nit = next / (nchw * N);
         const int nkz0 = nch * PC;
-        load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * a.in_pitch + nkz0,
+        load_regs<N, PC, NTH, V>(pre, a.in[0] + nit * a.in_item_stride + (size_t)niy * irow + nkz0,
                               istride, min(PC, NH - nkz0));
       }
       if constexpr (!spectral_input<OP>())
@@ -793,6 +852,17 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
           const float2 w = cmul_i<-1>(v);
           hold[m].x += c * w.x;
           hold[m].y += c * w.y;
+        } else if constexpr (OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ) {
+          // conj(i k_a) A + B, k_a along the pass's axis (x, or y on y lines)
+          if (i == 0) {
+            const float c = axis_coef<N>(n, kf);
+            const float2 w = cmul_i<-1>(v);
+            hold[m].x += c * w.x;
+            hold[m].y += c * w.y;
+          } else {
+            hold[m].x += v.x;
+            hold[m].y += v.y;
+          }
         } else if constexpr (OP == XOP_HESS_ADJ) {
           const KVec k = kvec<N>(n, iy, kz0 + l, kf);
           int pa, pb;
@@ -814,7 +884,7 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
     }
 
     // -------- outputs
-    if constexpr (OP == XOP_FWD) {
+    if constexpr (spectral_output<OP>()) {
 #pragma unroll
       for (int m = 0; m < PER; ++m) lds[t + m * NTH] = hold[m];
       __syncthreads();
@@ -865,6 +935,24 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float c = grad_coef<N>(k, o) * inv_n3;
             v = cmul_i<1>(make_float2(c * v.x, c * v.y));
+          } else if constexpr (OP == XOP_FORCE_X) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            if (o == 0) {  // the x component
+              const float c = grad_coef<N>(k, 0) * inv_n3;
+              v = cmul_i<1>(make_float2(c * v.x, c * v.y));
+            } else {  // the potential
+              const float g = inv_k2<N>(k) * inv_n3;
+              v = make_float2(g * v.x, g * v.y);
+            }
+          } else if constexpr (OP == XOP_FORCE_X_ADJ) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            const float g = inv_k2<N>(k) * inv_n3;
+            v = make_float2(g * v.x, g * v.y);
+          } else if constexpr (OP == XOP_YGRAD) {
+            if (o == 0) {  // i k_y A; output 1 is A itself
+              const float c = axis_coef<N>(n, kf);
+              v = cmul_i<1>(make_float2(c * v.x, c * v.y));
+            }
           } else if constexpr (OP == XOP_HESS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             int pa, pb;
@@ -906,11 +994,11 @@ void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, 
 
 template <int N>
 void zc2r3(int items, const float2* in, FieldMap im, Vec3* out, size_t out_item_stride,
-           hipStream_t s) {
+           float kz_grad, hipStream_t s) {
   const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
   const int res = resident_grid<zpass_c2r3_kernel<N>, NT>();
   zpass_c2r3_kernel<N><<<ntiles < res ? ntiles : res, NT, 0, s>>>(
-      in, im, out, out_item_stride, per, ntiles);
+      in, im, out, out_item_stride, kz_grad, per, ntiles);
 }
 
 template <int N>
@@ -1120,7 +1208,12 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
   __shared__ float2 lds[N * PC];
   __shared__ float2 tw[N];
   make_twiddles<N, NTH>(tw);
-  const size_t istride = (size_t)N * a.in_pitch, ostride = (size_t)N * a.out_pitch;
+  constexpr bool YL = yline<OP>();
+  // point stride along the transformed axis and the stride of the tile's fixed index
+  const size_t istride = YL ? a.in_pitch : (size_t)N * a.in_pitch;
+  const size_t ostride = YL ? a.out_pitch : (size_t)N * a.out_pitch;
+  const size_t irow = YL ? (size_t)N * a.in_pitch : a.in_pitch;
+  const size_t orow = YL ? (size_t)N * a.out_pitch : a.out_pitch;
   const size_t stride = (size_t)N * NH;  // prior table, projected modes, gradient
   const float kf = (float)(2.0 * M_PI / a.box);
   const float inv_n3 = (float)(1.0 / ((double)N * N * N));
@@ -1130,7 +1223,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
   auto in_base = [&](int tau, int i, int& ncols) {
     const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     ncols = min(PC, NH - ch * PC);
-    return a.in[i] + item * a.in_item_stride + (size_t)iy * a.in_pitch + ch * PC;
+    return a.in[i] + item * a.in_item_stride + (size_t)iy * irow + ch * PC;
   };
   int tau = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
   float2 pre[P];
@@ -1144,7 +1237,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
     const int ch = ch0 + tau % nchw, iy = (tau / nchw) % N, item = tau / (nchw * N);
     const int kz0 = ch * PC;
     const int ncols = min(PC, NH - kz0);
-    const size_t ooff = item * a.out_item_stride + (size_t)iy * a.out_pitch + kz0;
+    const size_t ooff = item * a.out_item_stride + (size_t)iy * orow + kz0;
     const int next = tau + gridDim.x;
     float Rg = 0.f;
     if constexpr (OP == XOP_GAUSS) Rg = (float)a.params[item * NPRM + a.param_index];
@@ -1178,6 +1271,19 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
           const float2 w = cmul_i<-1>(v[q]);
           hold[q].x += c * w.x;
           hold[q].y += c * w.y;
+        } else if constexpr (OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ) {
+          // conj(i k_a) A + B, k_a along the pass's axis (x, or y on y lines)
+          if (i == 0) {
+            int n, l;
+            reg_slot<N, PC, NTH, RLF>(q, n, l);
+            const float c = axis_coef<N>(n, kf);
+            const float2 w = cmul_i<-1>(v[q]);
+            hold[q].x += c * w.x;
+            hold[q].y += c * w.y;
+          } else {
+            hold[q].x += v[q].x;
+            hold[q].y += v[q].y;
+          }
         } else if constexpr (OP == XOP_HESS_ADJ) {
           int n, l;
           reg_slot<N, PC, NTH, RLF>(q, n, l);
@@ -1201,7 +1307,7 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
       }
     }
     // -------- outputs
-    if constexpr (OP == XOP_FWD) {
+    if constexpr (spectral_output<OP>()) {
       reg_store<N, PC, NTH, RLF>(hold, a.out[0] + ooff, ostride, ncols);
     } else if constexpr (OP == XOP_ZA_ADJ) {
       // G = w(kz) (sum_a conj(M_a) g_a / n^3 + prior_weight loss_bar P s / S), G(0) = 0
@@ -1251,6 +1357,24 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float c = grad_coef<N>(k, o) * inv_n3;
             x = cmul_i<1>(make_float2(c * x.x, c * x.y));
+          } else if constexpr (OP == XOP_FORCE_X) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            if (o == 0) {  // the x component
+              const float c = grad_coef<N>(k, 0) * inv_n3;
+              x = cmul_i<1>(make_float2(c * x.x, c * x.y));
+            } else {  // the potential
+              const float g = inv_k2<N>(k) * inv_n3;
+              x = make_float2(g * x.x, g * x.y);
+            }
+          } else if constexpr (OP == XOP_FORCE_X_ADJ) {
+            const KVec k = kvec<N>(n, iy, kz0 + l, kf);
+            const float g = inv_k2<N>(k) * inv_n3;
+            x = make_float2(g * x.x, g * x.y);
+          } else if constexpr (OP == XOP_YGRAD) {
+            if (o == 0) {  // i k_y A; output 1 is A itself
+              const float c = axis_coef<N>(n, kf);
+              x = cmul_i<1>(make_float2(c * x.x, c * x.y));
+            }
           } else if constexpr (OP == XOP_HESS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             int pa, pb;
@@ -1414,7 +1538,8 @@ void ypass(int fields, float2* d, FieldMap m, bool inv, hipStream_t s, KzWin win
 // more than 8 points per thread they would spill, so they run on half-width tiles.
 template <int OP>
 constexpr bool multi_input() {
-  return OP == XOP_FORCE_ADJ || OP == XOP_FEAT_ADJ || OP == XOP_ZA_ADJ || OP == XOP_HESS_ADJ;
+  return OP == XOP_FORCE_ADJ || OP == XOP_FEAT_ADJ || OP == XOP_ZA_ADJ || OP == XOP_HESS_ADJ ||
+         OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ;
 }
 
 template <int N, int OP>
@@ -1450,6 +1575,10 @@ void xpass_dispatch(int op, const XPassArgs& a, hipStream_t s) {
     case XOP_ZA_ADJ: xpass_op<N, XOP_ZA_ADJ>(a, s); break;
     case XOP_HESS: xpass_op<N, XOP_HESS>(a, s); break;
     case XOP_HESS_ADJ: xpass_op<N, XOP_HESS_ADJ>(a, s); break;
+    case XOP_FORCE_X: xpass_op<N, XOP_FORCE_X>(a, s); break;
+    case XOP_FORCE_X_ADJ: xpass_op<N, XOP_FORCE_X_ADJ>(a, s); break;
+    case XOP_YGRAD: xpass_op<N, XOP_YGRAD>(a, s); break;
+    case XOP_YGRAD_ADJ: xpass_op<N, XOP_YGRAD_ADJ>(a, s); break;
     default: break;
   }
 }

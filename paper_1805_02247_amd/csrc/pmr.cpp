@@ -388,6 +388,9 @@ PaintArgs paint_args(const uint32_t* keys, const Vec3* frac, const Vec3* val,
   return a;
 }
 
+// Fundamental wavenumber 2 pi / L in the float the kernels compute it in.
+float kf_of(pmr_ctx* c) { return (float)(2.0 * M_PI / c->cfg.box); }
+
 XPassArgs xargs(pmr_ctx* c, int n) {
   XPassArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -437,23 +440,6 @@ void c2r_yz(pmr_ctx* c, int n, int ncomp, float2* in, size_t in_item_stride, siz
     ProfScope ps(c, PMR_PROF_ZPASS, fields * (8.0 * cn + (add ? 8.0 : 4.0) * n3));
     launch_zpass_c2r(n, fields, in, fmap(ncomp, in_item_stride, in_comp_stride, spec_pitch(n)), out,
                      fmap(ncomp, out_item_stride, out_comp_stride), add, c->stream);
-  }
-}
-
-// Spectra of the three force components after the x pass -> interleaved force mesh.
-void c2r_yz3(pmr_ctx* c, int n, float2* in, size_t in_item_stride, size_t in_comp_stride,
-             Vec3* out) {
-  const int fields = c->B * 3;
-  const double n3 = (double)n * n * n, cn = (double)n * n * (n / 2 + 1);
-  {
-    ProfScope ps(c, PMR_PROF_YPASS, fields * 16.0 * cn);
-    launch_ypass(n, fields, in, fmap(3, in_item_stride, in_comp_stride, spec_pitch(n)), true,
-                 c->stream);
-  }
-  {
-    ProfScope ps(c, PMR_PROF_ZPASS, fields * 8.0 * cn + c->B * 12.0 * n3);
-    launch_zpass_c2r3(n, c->B, in, fmap(3, in_item_stride, in_comp_stride, spec_pitch(n)), out,
-                      (size_t)n * n * n, c->stream);
   }
 }
 
@@ -614,10 +600,13 @@ void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nul
                                           rowslot(c, fsl), c->nm, c->mass_m, 1.f),
                      B, c->cA, dm, c->stream);
   }
-  // y forward, x pass with the force operator, y inverse of the three components: window by
-  // window of kz columns when slabs are on, so that each window's spectra stay in the
-  // memory-side cache between the three passes
+  // y forward; x pass: the x component i k_x / k^2 and the potential 1 / k^2 of the
+  // density; y inverse of the x component, and of the potential into its y derivative and
+  // itself (components 1 and 2); the z pass takes the z derivative of component 2. Window
+  // by window of kz columns when slabs are on, so that each window's spectra stay in the
+  // memory-side cache between the passes.
   const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
+  const FieldMap fc0 = fmap(1, 3 * cm, 0, spec_pitch(c->nm));  // component 0 of each item
   for (const KzWin& win : kz_windows(c->nm)) {
     const double part = window_share(c->nm, win);
     {
@@ -626,26 +615,40 @@ void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nul
     }
     XPassArgs a = xargs(c, c->nm);
     a.n_in = 1;
-    a.n_out = 3;
+    a.n_out = 2;
     a.in[0] = c->cA;
-    for (int q = 0; q < 3; ++q) a.out[q] = c->cB + q * cm;
+    a.out[0] = c->cB;
+    a.out[1] = c->cB + cm;
     a.in_item_stride = cm;
     a.out_item_stride = 3 * cm;
     a.kz_lo = win.lo;
     a.kz_hi = win.hi;
     {
-      ProfScope ps(c, PMR_PROF_XPASS_FORCE, part * 32.0 * B * c->cm);
-      launch_xpass(XOP_FORCE, a, c->stream);
+      ProfScope ps(c, PMR_PROF_XPASS_FORCE, part * 24.0 * B * c->cm);
+      launch_xpass(XOP_FORCE_X, a, c->stream);
     }
     {
-      ProfScope ps(c, PMR_PROF_YPASS, part * 3 * 16.0 * B * c->cm);
-      launch_ypass(c->nm, 3 * B, c->cB, fm3, true, c->stream, win);
+      ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
+      launch_ypass(c->nm, B, c->cB, fc0, true, c->stream, win);
+    }
+    XPassArgs y = xargs(c, c->nm);
+    y.n_in = 1;
+    y.n_out = 2;
+    y.in[0] = c->cB + cm;
+    y.out[0] = c->cB + cm;
+    y.out[1] = c->cB + 2 * cm;
+    y.in_item_stride = y.out_item_stride = 3 * cm;
+    y.kz_lo = win.lo;
+    y.kz_hi = win.hi;
+    {
+      ProfScope ps(c, PMR_PROF_YPASS, part * 24.0 * B * c->cm);
+      launch_xpass(XOP_YGRAD, y, c->stream);
     }
   }
   Vec3* F = fslot(c, fsl);
   {
     ProfScope ps(c, PMR_PROF_ZPASS, 3 * 8.0 * B * c->cm + B * 12.0 * c->nm3);
-    launch_zpass_c2r3(c->nm, c->B, c->cB, fm3, F, c->nm3, c->stream);
+    launch_zpass_c2r3(c->nm, c->B, c->cB, fm3, F, c->nm3, kf_of(c), c->stream);
   }
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
@@ -1035,32 +1038,50 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const float K = (float)c->kick[i], Dr = (float)c->drift[i];
     if (!vsorted) launch_stream_gather(idslot(c, fsl), c->vid, (int)(B * c->np3), c->vstream, s);
     const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
+    const FieldMap fc0 = fmap(1, 3 * cm, 0, spec_pitch(c->nm));  // component 0 of each item
     {
-      // adjoint paint of the three force channels, z-transformed in the same pass
+      // adjoint paint of the three force channels, z-transformed in the same pass (channel 2
+      // times conj(i k_z): the transpose of the z derivative)
       ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 24.0 * B * c->cm);
-      launch_paint_r2c(c->nm, 3, paint_args(keyslot(c, fsl), fracslot(c, fsl), c->vstream,
-                                            rowslot(c, fsl), c->nm, 1.f, 0.f),
-                       B, c->cB, fm3, s);
+      PaintArgs pa = paint_args(keyslot(c, fsl), fracslot(c, fsl), c->vstream, rowslot(c, fsl),
+                                c->nm, 1.f, 0.f);
+      pa.kz_grad = kf_of(c);
+      launch_paint_r2c(c->nm, 3, pa, B, c->cB, fm3, s);
     }
     const FieldMap dm1 = fmap(1, cm, 0, spec_pitch(c->nm));
     for (const KzWin& win : kz_windows(c->nm)) {
       const double part = window_share(c->nm, win);
       {
-        ProfScope ps(c, PMR_PROF_YPASS, part * 3 * 16.0 * B * c->cm);
-        launch_ypass(c->nm, 3 * B, c->cB, fm3, false, s, win);
+        ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
+        launch_ypass(c->nm, B, c->cB, fc0, false, s, win);
+      }
+      // components 1 and 2 forward along y, combined as conj(i k_y) Y + Z into component 1
+      XPassArgs y = xargs(c, c->nm);
+      y.n_in = 2;
+      y.n_out = 1;
+      y.in[0] = c->cB + cm;
+      y.in[1] = c->cB + 2 * cm;
+      y.out[0] = c->cB + cm;
+      y.in_item_stride = y.out_item_stride = 3 * cm;
+      y.kz_lo = win.lo;
+      y.kz_hi = win.hi;
+      {
+        ProfScope ps(c, PMR_PROF_YPASS, part * 24.0 * B * c->cm);
+        launch_xpass(XOP_YGRAD_ADJ, y, s);
       }
       XPassArgs a = xargs(c, c->nm);
-      a.n_in = 3;
+      a.n_in = 2;
       a.n_out = 1;
-      for (int q = 0; q < 3; ++q) a.in[q] = c->cB + q * cm;
+      a.in[0] = c->cB;
+      a.in[1] = c->cB + cm;
       a.out[0] = c->cA;
       a.in_item_stride = 3 * cm;
       a.out_item_stride = cm;
       a.kz_lo = win.lo;
       a.kz_hi = win.hi;
       {
-        ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, part * 32.0 * B * c->cm);
-        launch_xpass(XOP_FORCE_ADJ, a, s);
+        ProfScope ps(c, PMR_PROF_XPASS_FORCE_ADJ, part * 24.0 * B * c->cm);
+        launch_xpass(XOP_FORCE_X_ADJ, a, s);
       }
       {
         ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
