@@ -23,42 +23,42 @@ int log2i(int n) {
 void fft_zr2c_16(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_16(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_16(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_16(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_16(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_16(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_16(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_32(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_32(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_32(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_32(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_32(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_32(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_32(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_64(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_64(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_64(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_64(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_64(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_64(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_64(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_128(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_128(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_128(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_128(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_128(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_128(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_128(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_256(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_256(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_256(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_256(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_256(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_256(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_256(int, const XPassArgs&, hipStream_t);
 void fft_zr2c_512(int, const float*, FieldMap, const float*, float, float, const double*, float2*,
                FieldMap, hipStream_t);
 void fft_zc2r_512(int, const float2*, FieldMap, float*, FieldMap, const float*, hipStream_t);
-void fft_zc2r3_512(int, const float2*, FieldMap, Vec3*, size_t, float, hipStream_t);
+void fft_zc2r3_512(int, const float2*, FieldMap, Vec3*, size_t, hipStream_t);
 void fft_paint_r2c_512(int, const PaintArgs&, int, float2*, FieldMap, hipStream_t);
 void fft_ypass_512(int, float2*, FieldMap, bool, hipStream_t, KzWin);
 void fft_xpass_512(int, const XPassArgs&, hipStream_t);
@@ -89,10 +89,10 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
 }
 
 void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Vec3* out,
-                       size_t out_item_stride, float kz_grad, hipStream_t s) {
+                       size_t out_item_stride, hipStream_t s) {
   switch (n) {
 #define CASE(NN) \
-  case NN: fft_zc2r3_##NN(items, in, im, out, out_item_stride, kz_grad, s); break;
+  case NN: fft_zc2r3_##NN(items, in, im, out, out_item_stride, s); break;
     PMR_FOR_N(CASE)
 #undef CASE
     default: break;

@@ -351,36 +351,23 @@ __global__ __launch_bounds__(NT) void paint_r2c_kernel(PaintArgs a, float2* __re
     const int c = line % C, t = line / C;  // t: row within the workgroup
     const float2* z = lds + line * PITCH;
     float2* d = out + om.off(item * C + c) + ((size_t)ix * N + iyb + t) * om.pitch;
-    // channel 2 of the adjoint force paint: times conj(i k_z) (kz = 0 and the Nyquist plane
-    // vanish)
-    const bool zg = C == 3 && c == 2 && a.kz_grad != 0.f;
     if (k == 0) {
       const float2 z0 = z[0];
-      store_spec<(N >= 512)>(&d[0], make_float2(zg ? 0.f : z0.x + z0.y - bN, 0.f));
-      store_spec<(N >= 512)>(&d[H], make_float2(zg ? 0.f : z0.x - z0.y, 0.f));
+      store_spec<(N >= 512)>(&d[0], make_float2(z0.x + z0.y - bN, 0.f));
+      store_spec<(N >= 512)>(&d[H], make_float2(z0.x - z0.y, 0.f));
     } else {
       const float2 zv = z[zk(k)], zm = z[zk(H - k)];
       {
         float2 sm = make_float2(0.5f * (zv.x + zm.x), 0.5f * (zv.y - zm.y));
         float2 df = make_float2(0.5f * (zv.x - zm.x), 0.5f * (zv.y + zm.y));
         float2 t2 = cmul(tw[k], df);
-        float2 x = make_float2(sm.x + t2.y, sm.y - t2.x);
-        if (zg) {
-          const float cz = axis_coef<N>(k, a.kz_grad);
-          x = cmul_i<-1>(make_float2(cz * x.x, cz * x.y));
-        }
-        store_spec<(N >= 512)>(&d[k], x);
+        store_spec<(N >= 512)>(&d[k], make_float2(sm.x + t2.y, sm.y - t2.x));
       }
       if (k != H - k) {
         float2 sm = make_float2(0.5f * (zm.x + zv.x), 0.5f * (zm.y - zv.y));
         float2 df = make_float2(0.5f * (zm.x - zv.x), 0.5f * (zm.y + zv.y));
         float2 t2 = cmul(tw[H - k], df);
-        float2 x = make_float2(sm.x + t2.y, sm.y - t2.x);
-        if (zg) {
-          const float cz = axis_coef<N>(H - k, a.kz_grad);
-          x = cmul_i<-1>(make_float2(cz * x.x, cz * x.y));
-        }
-        store_spec<(N >= 512)>(&d[H - k], x);
+        store_spec<(N >= 512)>(&d[H - k], make_float2(sm.x + t2.y, sm.y - t2.x));
       }
     }
   }
@@ -503,12 +490,10 @@ struct ZTile3 {
   static constexpr int R = ZTile<N>::ROWS / 2 > 0 ? ZTile<N>::ROWS / 2 : 1;  // rows per field
 };
 
-// kz_grad != 0: component 2 enters as i k_z times its spectrum, k_z = kz_grad * kz (zero on
-// the Nyquist plane): the z derivative of the force split over the axes.
 template <int N>
 __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict__ in, FieldMap im,
                                                         Vec3* __restrict__ out,
-                                                        size_t out_item_stride, float kz_grad,
+                                                        size_t out_item_stride,
                                                         int tiles_per_item, int ntiles) {
   using T = ZTile<N>;
   constexpr int H = T::H, PITCH = T::PITCH, R = ZTile3<N>::R;
@@ -540,17 +525,7 @@ __global__ __launch_bounds__(NT) void zpass_c2r3_kernel(const float2* __restrict
 #pragma unroll
     for (int m = 0; m < PR::PER; ++m) {
       const int e = threadIdx.x + m * NT;
-      if (e < 3 * R * Q) {
-        const int k = e % Q;
-        float2 xa = pre.a[m], xb = pre.b[m];
-        // (applied here, where the prefetched values are consumed, not where they are loaded)
-        if (e / Q >= 2 * R && kz_grad != 0.f) {  // component 2: X[kz] i k_z, kz = k and H - k
-          const float ca = axis_coef<N>(k, kz_grad), cb = axis_coef<N>(H - k, kz_grad);
-          xa = cmul_i<1>(make_float2(ca * xa.x, ca * xa.y));
-          xb = cmul_i<1>(make_float2(cb * xb.x, cb * xb.y));
-        }
-        inv_split<H>(lds + (e / Q) * PITCH, k, xa, xb, tw);
-      }
+      if (e < 3 * R * Q) inv_split<H>(lds + (e / Q) * PITCH, e % Q, pre.a[m], pre.b[m], tw);
     }
     __syncthreads();
     const int next = tau + gridDim.x;
@@ -852,8 +827,8 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
           const float2 w = cmul_i<-1>(v);
           hold[m].x += c * w.x;
           hold[m].y += c * w.y;
-        } else if constexpr (OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ) {
-          // conj(i k_a) A + B, k_a along the pass's axis (x, or y on y lines)
+        } else if constexpr (OP == XOP_FORCE_X_ADJ) {
+          // conj(i k_x) A + B
           if (i == 0) {
             const float c = axis_coef<N>(n, kf);
             const float2 w = cmul_i<-1>(v);
@@ -863,6 +838,12 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
             hold[m].x += v.x;
             hold[m].y += v.y;
           }
+        } else if constexpr (OP == XOP_YGRAD_ADJ) {
+          // conj(i k_y) A + conj(i k_z) B
+          const float c = i == 0 ? axis_coef<N>(n, kf) : axis_coef<N>(kz0 + l, kf);
+          const float2 w = cmul_i<-1>(v);
+          hold[m].x += c * w.x;
+          hold[m].y += c * w.y;
         } else if constexpr (OP == XOP_HESS_ADJ) {
           const KVec k = kvec<N>(n, iy, kz0 + l, kf);
           int pa, pb;
@@ -948,11 +929,9 @@ __global__ __launch_bounds__(NTH) void xpass_kernel(XPassArgs a, int ntiles, int
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float g = inv_k2<N>(k) * inv_n3;
             v = make_float2(g * v.x, g * v.y);
-          } else if constexpr (OP == XOP_YGRAD) {
-            if (o == 0) {  // i k_y A; output 1 is A itself
-              const float c = axis_coef<N>(n, kf);
-              v = cmul_i<1>(make_float2(c * v.x, c * v.y));
-            }
+          } else if constexpr (OP == XOP_YGRAD) {  // i k_y A and i k_z A
+            const float c = o == 0 ? axis_coef<N>(n, kf) : axis_coef<N>(kz0 + l, kf);
+            v = cmul_i<1>(make_float2(c * v.x, c * v.y));
           } else if constexpr (OP == XOP_HESS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             int pa, pb;
@@ -994,11 +973,11 @@ void zr2c(int fields, const float* in, FieldMap im, const float* in2, float a1, 
 
 template <int N>
 void zc2r3(int items, const float2* in, FieldMap im, Vec3* out, size_t out_item_stride,
-           float kz_grad, hipStream_t s) {
+           hipStream_t s) {
   const int per = (N * N) / ZTile3<N>::R, ntiles = per * items;
   const int res = resident_grid<zpass_c2r3_kernel<N>, NT>();
   zpass_c2r3_kernel<N><<<ntiles < res ? ntiles : res, NT, 0, s>>>(
-      in, im, out, out_item_stride, kz_grad, per, ntiles);
+      in, im, out, out_item_stride, per, ntiles);
 }
 
 template <int N>
@@ -1271,8 +1250,8 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
           const float2 w = cmul_i<-1>(v[q]);
           hold[q].x += c * w.x;
           hold[q].y += c * w.y;
-        } else if constexpr (OP == XOP_FORCE_X_ADJ || OP == XOP_YGRAD_ADJ) {
-          // conj(i k_a) A + B, k_a along the pass's axis (x, or y on y lines)
+        } else if constexpr (OP == XOP_FORCE_X_ADJ) {
+          // conj(i k_x) A + B
           if (i == 0) {
             int n, l;
             reg_slot<N, PC, NTH, RLF>(q, n, l);
@@ -1284,6 +1263,14 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
             hold[q].x += v[q].x;
             hold[q].y += v[q].y;
           }
+        } else if constexpr (OP == XOP_YGRAD_ADJ) {
+          // conj(i k_y) A + conj(i k_z) B
+          int n, l;
+          reg_slot<N, PC, NTH, RLF>(q, n, l);
+          const float c = i == 0 ? axis_coef<N>(n, kf) : axis_coef<N>(kz0 + l, kf);
+          const float2 w = cmul_i<-1>(v[q]);
+          hold[q].x += c * w.x;
+          hold[q].y += c * w.y;
         } else if constexpr (OP == XOP_HESS_ADJ) {
           int n, l;
           reg_slot<N, PC, NTH, RLF>(q, n, l);
@@ -1370,11 +1357,9 @@ __global__ __launch_bounds__(NTH) void xpass_reg_kernel(XPassArgs a, int ntiles,
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             const float g = inv_k2<N>(k) * inv_n3;
             x = make_float2(g * x.x, g * x.y);
-          } else if constexpr (OP == XOP_YGRAD) {
-            if (o == 0) {  // i k_y A; output 1 is A itself
-              const float c = axis_coef<N>(n, kf);
-              x = cmul_i<1>(make_float2(c * x.x, c * x.y));
-            }
+          } else if constexpr (OP == XOP_YGRAD) {  // i k_y A and i k_z A
+            const float c = o == 0 ? axis_coef<N>(n, kf) : axis_coef<N>(kz0 + l, kf);
+            x = cmul_i<1>(make_float2(c * x.x, c * x.y));
           } else if constexpr (OP == XOP_HESS) {
             const KVec k = kvec<N>(n, iy, kz0 + l, kf);
             int pa, pb;

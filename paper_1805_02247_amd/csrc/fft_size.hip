@@ -22,8 +22,8 @@ void PMR_CAT(fft_zc2r_, PMR_FFT_SIZE)(int fields, const float2* in, FieldMap im,
 }
 
 void PMR_CAT(fft_zc2r3_, PMR_FFT_SIZE)(int items, const float2* in, FieldMap im, Vec3* out,
-                                       size_t out_item_stride, float kz_grad, hipStream_t s) {
-  zc2r3<PMR_FFT_SIZE>(items, in, im, out, out_item_stride, kz_grad, s);
+                                       size_t out_item_stride, hipStream_t s) {
+  zc2r3<PMR_FFT_SIZE>(items, in, im, out, out_item_stride, s);
 }
 
 void PMR_CAT(fft_paint_r2c_, PMR_FFT_SIZE)(int channels, const PaintArgs& a, int batch,

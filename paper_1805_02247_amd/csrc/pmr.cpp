@@ -388,9 +388,6 @@ PaintArgs paint_args(const uint32_t* keys, const Vec3* frac, const Vec3* val,
   return a;
 }
 
-// Fundamental wavenumber 2 pi / L in the float the kernels compute it in.
-float kf_of(pmr_ctx* c) { return (float)(2.0 * M_PI / c->cfg.box); }
-
 XPassArgs xargs(pmr_ctx* c, int n) {
   XPassArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -601,10 +598,9 @@ void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nul
                      B, c->cA, dm, c->stream);
   }
   // y forward; x pass: the x component i k_x / k^2 and the potential 1 / k^2 of the
-  // density; y inverse of the x component, and of the potential into its y derivative and
-  // itself (components 1 and 2); the z pass takes the z derivative of component 2. Window
-  // by window of kz columns when slabs are on, so that each window's spectra stay in the
-  // memory-side cache between the passes.
+  // density; y inverse of the x component, and of the potential into its y and z
+  // derivatives (components 1 and 2). Window by window of kz columns when slabs are on, so
+  // that each window's spectra stay in the memory-side cache between the passes.
   const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
   const FieldMap fc0 = fmap(1, 3 * cm, 0, spec_pitch(c->nm));  // component 0 of each item
   for (const KzWin& win : kz_windows(c->nm)) {
@@ -648,7 +644,7 @@ void pm_step(pmr_ctx* c, int i, bool advance = true, const uint32_t* order = nul
   Vec3* F = fslot(c, fsl);
   {
     ProfScope ps(c, PMR_PROF_ZPASS, 3 * 8.0 * B * c->cm + B * 12.0 * c->nm3);
-    launch_zpass_c2r3(c->nm, c->B, c->cB, fm3, F, c->nm3, kf_of(c), c->stream);
+    launch_zpass_c2r3(c->nm, c->B, c->cB, fm3, F, c->nm3, c->stream);
   }
   if (!advance) return;  // (x, p) of step i + 1 already held elsewhere (a checkpoint)
   const int key_nm = (i == c->n - 1) ? c->no : c->nm;
@@ -1040,13 +1036,11 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
     const FieldMap fm3 = fmap(3, 3 * cm, cm, spec_pitch(c->nm));
     const FieldMap fc0 = fmap(1, 3 * cm, 0, spec_pitch(c->nm));  // component 0 of each item
     {
-      // adjoint paint of the three force channels, z-transformed in the same pass (channel 2
-      // times conj(i k_z): the transpose of the z derivative)
+      // adjoint paint of the three force channels, z-transformed in the same pass
       ProfScope ps(c, PMR_PROF_PAINT3, (24.0 + 12.0) * B * c->np3 + 24.0 * B * c->cm);
-      PaintArgs pa = paint_args(keyslot(c, fsl), fracslot(c, fsl), c->vstream, rowslot(c, fsl),
-                                c->nm, 1.f, 0.f);
-      pa.kz_grad = kf_of(c);
-      launch_paint_r2c(c->nm, 3, pa, B, c->cB, fm3, s);
+      launch_paint_r2c(c->nm, 3, paint_args(keyslot(c, fsl), fracslot(c, fsl), c->vstream,
+                                            rowslot(c, fsl), c->nm, 1.f, 0.f),
+                       B, c->cB, fm3, s);
     }
     const FieldMap dm1 = fmap(1, cm, 0, spec_pitch(c->nm));
     for (const KzWin& win : kz_windows(c->nm)) {
@@ -1055,7 +1049,8 @@ int pmr_adjoint(pmr_ctx* c, const double* loss_bar, const float* mass_bar, void*
         ProfScope ps(c, PMR_PROF_YPASS, part * 16.0 * B * c->cm);
         launch_ypass(c->nm, B, c->cB, fc0, false, s, win);
       }
-      // components 1 and 2 forward along y, combined as conj(i k_y) Y + Z into component 1
+      // components 1 and 2 forward along y, combined as conj(i k_y) Y + conj(i k_z) Z into
+      // component 1
       XPassArgs y = xargs(c, c->nm);
       y.n_in = 2;
       y.n_out = 1;

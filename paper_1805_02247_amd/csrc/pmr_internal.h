@@ -121,9 +121,6 @@ struct PaintArgs {
   int nm, log_nm;
   float mass, bias;
   float* out;               // [B][C][nm^3]
-  // fused z pass, 3 channels: channel 2's half spectrum times conj(i k_z), k_z = kz_grad *
-  // kz (zero on the Nyquist plane); 0: no factor
-  float kz_grad;
 };
 
 // Kinds of fused k-space operation performed in the outermost-axis pass.
@@ -140,14 +137,16 @@ enum XOp : int {
   XOP_HESS = 9,       // 1 in (projected modes): * k_a k_b / k^2 / n^3, inv; -> 3 (pair set at
                       // param_index: 0 -> xx, yy, zz; 1 -> xy, xz, yz)
   XOP_HESS_ADJ = 10,  // 3 in (same pair sets): fwd, sum k_a k_b / k^2 / n^3; caller's gradient +=
-  // The force split over the axes: a factor that depends on one wavenumber only commutes
-  // with the transforms along the other two axes, so i k_y and i k_z are applied in the y
-  // and z passes to one shared potential instead of carrying three spectra through them.
+  // The force split over the axes: a factor that depends on k_y or k_z only commutes with
+  // the transform along x, so the x pass carries the x component and one potential, and
+  // the y pass takes both of the potential's other derivatives, instead of three spectra
+  // going through the x pass and back.
   XOP_FORCE_X = 11,      // fwd, * i k_x / k^2 / n^3 and * 1 / k^2 / n^3, inv; 1 in -> 2 out
   XOP_FORCE_X_ADJ = 12,  // 2 in (A, B): fwd each, (conj(i k_x) A + B) / k^2 / n^3, inv; -> 1 out
-  // Operators on y lines (tile = kz chunk of one x plane; only k_y enters):
-  XOP_YGRAD = 13,      // 1 in (spectral along y): i k_y A and A, inverse y; 1 -> 2
-  XOP_YGRAD_ADJ = 14,  // 2 in (A, B): forward y each, conj(i k_y) A + B; -> 1 out (spectral)
+  // Operators on y lines (tile = kz chunk of one x plane; k_y and k_z enter):
+  XOP_YGRAD = 13,      // 1 in (spectral along y): i k_y A and i k_z A, inverse y; 1 -> 2
+  XOP_YGRAD_ADJ = 14,  // 2 in (A, B): forward y each, conj(i k_y) A + conj(i k_z) B; -> 1
+                       // out (spectral)
 };
 
 // Loss parameters per batch item in device memory (doubles):
@@ -196,10 +195,8 @@ void launch_zpass_c2r(int n, int fields, const float2* in, FieldMap im, float* o
 // item = channels); the y and x passes complete the transform.
 void launch_paint_r2c(int n, int channels, const PaintArgs& a, int batch, float2* out, FieldMap om,
                       hipStream_t s);
-// kz_grad != 0: component 2 is first multiplied by i k_z, k_z = kz_grad * kz (zero on the
-// Nyquist plane).
 void launch_zpass_c2r3(int n, int items, const float2* in, FieldMap im, Vec3* out,
-                       size_t out_item_stride, float kz_grad, hipStream_t s);
+                       size_t out_item_stride, hipStream_t s);
 // A window [lo, hi) of kz columns of the half spectrum (hi = 0: all of them).
 struct KzWin {
   int lo = 0, hi = 0;
