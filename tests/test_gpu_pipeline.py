@@ -573,3 +573,28 @@ def test_checkpointed_positions_equal_stored(ckpt):
             with pytest.raises(P.PmrError) as e:
                 pm.debug("x", step)
             assert e.value.status == P.PMR_E_STATE
+
+
+@pytest.mark.parametrize("n,nm", [(16, 16), (16, 32), (32, 32)])
+def test_force_meshes_every_step_against_oracle(n, nm):
+    """The force mesh of every PM step (the operator split over the axes: i k_x / k^2 in the
+    x pass, i k_y and i k_z of the potential in the y pass) against the FP64 oracle's
+    irfft(i k_a / k^2 rfft(delta)) from the GPU's own positions, component by component, on
+    meshes small enough that the Nyquist planes and k = 0 carry a visible share of the
+    spectrum; the later steps paint clustered positions."""
+    require_gpu()
+    say(f"pipeline: force meshes of every step, {n}^3 particles on {nm}^3")
+    steps = 4
+    prob = _problem(n, nm, n, 50.0, steps, OM.LOSS_LOGNORMAL, 2, hidden=8, R_sm=(1.0,))
+    res = _gpu_run(*prob)
+    ocfg = prob[0]
+    worst = 0.0
+    for i in range(steps):
+        F = res["pm"].debug("force", i).cpu().numpy()  # [B][nm^3][3]
+        for b in range(2):
+            ref = OM.force_meshes(ocfg, OM.density(ocfg, res["xs"][i][b].astype(np.float64), nm))
+            for a in range(3):
+                e = rel_l2(F[b][:, a], ref[a].ravel())
+                worst = max(worst, e)
+                assert e <= 2e-6, (i, b, "xyz"[a], e)  # measured 2.4-2.8e-7
+    say(f"  worst component rel-L2 {worst:.2e}")
