@@ -8,10 +8,13 @@
 // Segmented inclusive scan over the 64 lanes by equal key, on DPP lane moves (VALU, no
 // LDS): row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and row_bcast 31
 // across rows. Keys are sorted across the lanes, so "source key == my key" means the
-// source lane is in my segment. Lanes whose DPP source is out of range read 0.
+// source lane is in my segment. A key whose DPP source is out of range or in a row the
+// move leaves out reads ~0 and matches no real key; the values use the bound control
+// (out of range reads 0) with no old operand, so no register has to be cleared first, and
+// a value whose key did not match is never added.
 template <int CTRL, int RMASK>
 __device__ __forceinline__ float dpp_f(float src) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, RMASK, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, RMASK, 0xF, true));
 }
 template <int CTRL, int RMASK>
 __device__ __forceinline__ uint32_t dpp_k(uint32_t src) {
