@@ -9,12 +9,17 @@
 // LDS): row_shr 1, 2, 4, 8 inside each row of 16 lanes, then row_bcast 15 and row_bcast 31
 // across rows. Keys are sorted across the lanes, so "source key == my key" means the
 // source lane is in my segment. A key whose DPP source is out of range or in a row the
-// move leaves out reads ~0 and matches no real key; the values use the bound control
-// (out of range reads 0) with no old operand, so no register has to be cleared first, and
-// a value whose key did not match is never added.
+// move leaves out reads ~0 (at most the key of the very last cell, whose added value is
+// then 0); the in-row shifts read values with the bound control (out of range reads 0)
+// and no old operand, so no register has to be cleared before them, and the row
+// broadcasts, which leave rows out, read 0 there from a cleared old operand.
 template <int CTRL, int RMASK>
 __device__ __forceinline__ float dpp_f(float src) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, RMASK, 0xF, true));
+  if constexpr (RMASK == 0xF)  // every row written: out-of-range lanes read 0
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, RMASK, 0xF, true));
+  else  // rows left out keep the old operand: 0
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, RMASK, 0xF, false));
 }
 template <int CTRL, int RMASK>
 __device__ __forceinline__ uint32_t dpp_k(uint32_t src) {
