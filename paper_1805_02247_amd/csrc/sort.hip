@@ -40,16 +40,18 @@ __device__ __forceinline__ uint64_t lanes_below() {
 // The value of lane (lane ^ J). Distances 1 and 2 are DPP quad permutations and 4 and 8
 // DPP row shifts (row_shl:J reads lane + J, row_shr:J lane - J, inside a row of 16 lanes,
 // where lane ^ J stays for these J): VALU moves with no LDS round trip. 16 and 32 go
-// through ds_bpermute.
+// through ds_bpermute. The moves carry no old operand (the bound control reads 0 out of
+// range, and the shift whose source is out of range is the one not selected), so no
+// register is cleared before them.
 template <int J>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
   if constexpr (J == 1) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // [1,0,3,2]
   } else if constexpr (J == 2) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
   } else if constexpr (J == 4 || J == 8) {
-    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + J, 0xF, 0xF, false);
-    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + J, 0xF, 0xF, false);
+    const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + J, 0xF, 0xF, true);
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + J, 0xF, 0xF, true);
     return (lane_id() & J) ? dn : up;
   } else {
     return __shfl_xor(v, J, 64);
