@@ -12,7 +12,10 @@
 // move leaves out reads ~0 (at most the key of the very last cell, whose added value is
 // then 0); the in-row shifts read values with the bound control (out of range reads 0)
 // and no old operand, so no register has to be cleared before them, and the row
-// broadcasts, which leave rows out, read 0 there from a cleared old operand.
+// broadcasts, which leave rows out, read 0 there from a cleared old operand. The
+// neighbour keys (previous and next lane across the whole wavefront) come from the DPP
+// wavefront shifts, VALU moves with no LDS round trip; lanes 0 and 63, which have no
+// neighbour there, are handled by the lane tests that follow.
 template <int CTRL, int RMASK>
 __device__ __forceinline__ float dpp_f(float src) {
   if constexpr (RMASK == 0xF)  // every row written: out-of-range lanes read 0
@@ -43,7 +46,7 @@ __device__ __forceinline__ void seg_step(float (&v)[NV], uint32_t key) {
 // row-crossing steps run only when a segment crosses lane 16/48 or 32.
 template <int NV>
 __device__ __forceinline__ void seg_scan(float (&v)[NV], uint32_t key) {
-  const uint32_t kp = __shfl_up(key, 1, 64);
+  const uint32_t kp = (uint32_t)__builtin_amdgcn_mov_dpp((int)key, 0x138, 0xF, 0xF, true);  // wave_shr:1
   const int lane = threadIdx.x & 63;
   const uint64_t eq = __ballot(lane > 0 && kp == key);
   if (eq == 0) return;
@@ -128,8 +131,8 @@ __device__ __forceinline__ int row_slot(int iz) {
 template <int C, int TY, bool PAD = false>
 __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, int iy0, int rp) {
   const int lane = threadIdx.x & 63;
-  const uint32_t kn = __shfl_down(ch.key, 1, 64);
-  const int ok_next = __shfl_down((int)ch.ok, 1, 64);
+  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);  // wave_shl:1
+  const int ok_next = __builtin_amdgcn_mov_dpp((int)ch.ok, 0x130, 0xF, 0xF, true);
   const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
   const int iz1 = (ch.iz + 1) & (nm - 1);
 #pragma unroll
@@ -199,8 +202,8 @@ __device__ __forceinline__ void load_chunk1(const PaintArgs& a, uint32_t j, uint
 template <int C, bool PAD = false>
 __device__ __forceinline__ void deposit1(const Chunk1<C>& ch, float* acc, int nm, int rp) {
   const int lane = threadIdx.x & 63;
-  const uint32_t kn = __shfl_down(ch.key, 1, 64);
-  const int ok_next = __shfl_down((int)ch.ok, 1, 64);
+  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);  // wave_shl:1
+  const int ok_next = __builtin_amdgcn_mov_dpp((int)ch.ok, 0x130, 0xF, 0xF, true);
   const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
   const int iz1 = (ch.iz + 1) & (nm - 1);
 #pragma unroll
