@@ -46,7 +46,8 @@ __device__ __forceinline__ void seg_step(float (&v)[NV], uint32_t key) {
 // row-crossing steps run only when a segment crosses lane 16/48 or 32.
 template <int NV>
 __device__ __forceinline__ void seg_scan(float (&v)[NV], uint32_t key) {
-  const uint32_t kp = (uint32_t)__builtin_amdgcn_mov_dpp((int)key, 0x138, 0xF, 0xF, true);  // wave_shr:1
+  // wave_shr:1
+  const uint32_t kp = (uint32_t)__builtin_amdgcn_mov_dpp((int)key, 0x138, 0xF, 0xF, true);
   const int lane = threadIdx.x & 63;
   const uint64_t eq = __ballot(lane > 0 && kp == key);
   if (eq == 0) return;
@@ -131,7 +132,8 @@ __device__ __forceinline__ int row_slot(int iz) {
 template <int C, int TY, bool PAD = false>
 __device__ __forceinline__ void deposit(const Chunk<C>& ch, float* acc, int nm, int iy0, int rp) {
   const int lane = threadIdx.x & 63;
-  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);  // wave_shl:1
+  // wave_shl:1
+  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);
   const int ok_next = __builtin_amdgcn_mov_dpp((int)ch.ok, 0x130, 0xF, 0xF, true);
   const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
   const int iz1 = (ch.iz + 1) & (nm - 1);
@@ -202,7 +204,8 @@ __device__ __forceinline__ void load_chunk1(const PaintArgs& a, uint32_t j, uint
 template <int C, bool PAD = false>
 __device__ __forceinline__ void deposit1(const Chunk1<C>& ch, float* acc, int nm, int rp) {
   const int lane = threadIdx.x & 63;
-  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);  // wave_shl:1
+  // wave_shl:1
+  const uint32_t kn = (uint32_t)__builtin_amdgcn_mov_dpp((int)ch.key, 0x130, 0xF, 0xF, true);
   const int ok_next = __builtin_amdgcn_mov_dpp((int)ch.ok, 0x130, 0xF, 0xF, true);
   const bool tail = ch.ok && (lane == 63 || !ok_next || kn != ch.key);
   const int iz1 = (ch.iz + 1) & (nm - 1);
