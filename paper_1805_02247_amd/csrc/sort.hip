@@ -39,10 +39,12 @@ __device__ __forceinline__ uint64_t lanes_below() {
 
 // The value of lane (lane ^ J). Distances 1 and 2 are DPP quad permutations and 4 and 8
 // DPP row shifts (row_shl:J reads lane + J, row_shr:J lane - J, inside a row of 16 lanes,
-// where lane ^ J stays for these J): VALU moves with no LDS round trip. 16 and 32 go
-// through ds_bpermute. The moves carry no old operand (the bound control reads 0 out of
-// range, and the shift whose source is out of range is the one not selected), so no
-// register is cleared before them.
+// where lane ^ J stays for these J): VALU moves with no LDS round trip. The moves carry no
+// old operand (the bound control reads 0 out of range, and the shift whose source is out of
+// range is the one not selected), so no register is cleared before them. 16 and 32 use the
+// row swaps of gfx950 on two copies of the value: permlane16_swap leaves the first copy
+// with rows (0, 0, 2, 2) and the second with (1, 1, 3, 3) of the original, permlane32_swap
+// the halves (lo, lo) and (hi, hi), so each lane picks the copy that holds its partner.
 template <int J>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
   if constexpr (J == 1) {
@@ -53,8 +55,12 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + J, 0xF, 0xF, true);
     const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + J, 0xF, 0xF, true);
     return (lane_id() & J) ? dn : up;
+  } else if constexpr (J == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane_id() & 16) ? p[0] : p[1];
   } else {
-    return __shfl_xor(v, J, 64);
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane_id() & 32) ? p[0] : p[1];
   }
 }
 
