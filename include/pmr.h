@@ -230,12 +230,15 @@ long long pmr_debug_copy(pmr_ctx* ctx, int what, int step, void* dst);
 enum {
   PMR_PROF_NONE = 0,
   PMR_PROF_PAINT = 1,             /* density paint on the force mesh (one channel) */
-  PMR_PROF_XPASS_FORCE = 2,       /* outermost-axis pass with the force operator, 1 -> 3 */
-  PMR_PROF_YPASS = 3,             /* middle-axis FFT passes */
+  PMR_PROF_XPASS_FORCE = 2,       /* outermost-axis pass with the force operator: the x
+                                     component and the potential, 1 -> 2 */
+  PMR_PROF_YPASS = 3,             /* middle-axis FFT passes, with the y and z derivatives of
+                                     the potential (force) and their transposes (adjoint) */
   PMR_PROF_ZPASS = 4,             /* contiguous-axis r2c / c2r passes */
   PMR_PROF_KICK_DRIFT = 5,        /* readout + kick + drift + keys */
   PMR_PROF_PAINT3 = 6,            /* three-channel adjoint paint */
-  PMR_PROF_XPASS_FORCE_ADJ = 7,   /* outermost-axis pass with the force adjoint, 3 -> 1 */
+  PMR_PROF_XPASS_FORCE_ADJ = 7,   /* outermost-axis pass with the force adjoint: the x
+                                     channel and the y pass's combination of y and z, 2 -> 1 */
   PMR_PROF_ADJ_GATHER = 8,        /* step-adjoint position gradient (sorted-order gather) */
   PMR_PROF_ADJ_UPDATE = 9,        /* step-adjoint kick / drift transposes (id order) */
   PMR_PROF_HALO2 = 10,            /* two-network model kernels (forward, adjoint); their
@@ -266,9 +269,11 @@ int pmr_fft_c2r(int n, int batch, void* inout, float* out, void* stream);
 
 /* Tile shape of one strided FFT pass for size n (process-wide; the autotuner sets it).
  * `pass` PMR_FFT_YPASS (the middle axis), PMR_FFT_XPASS (the outermost axis with a
- * single-input k-space operator: forward or inverse only, force, smoothing, Zel'dovich) or
+ * single-input k-space operator: forward or inverse only, force, smoothing, Zel'dovich; also
+ * the middle-axis pass that takes the y and z derivatives of the force's potential) or
  * PMR_FFT_XPASS_MULTI (the outermost axis with a multi-input operator: force adjoint, feature
- * adjoint, gradient assembly). `columns` consecutive kz columns per workgroup tile
+ * adjoint, gradient assembly; also the middle-axis pass that combines the adjoint's y and z
+ * channels). `columns` consecutive kz columns per workgroup tile
  * (8, 16 or 32) and `threads` per workgroup (256 or 512), with
  * threads <= n * columns <= 16 * threads and the tile within 160 KB of LDS. `staging` 0 runs
  * the butterflies on register images of the tile (radix-8 stages; used where n * columns /
@@ -284,9 +289,9 @@ int pmr_fft_get_tile(int n, int pass, int* columns, int* threads, int* staging);
 
 /* Slab width of the force transforms of the PM steps on an n^3 mesh (process-wide; the
  * autotuner sets it): with `columns` > 0 the middle-axis pass, the outermost-axis pass with
- * its k-space operator and the inverse middle-axis pass run window by window of that many kz
- * columns (rounded up to a multiple of every strided pass's tile columns), so that a
- * window's spectra stay in the memory-side cache between the three passes; 0 runs each pass
+ * its k-space operator and the inverse middle-axis passes run window by window of that many
+ * kz columns (rounded up to a multiple of every strided pass's tile columns), so that a
+ * window's spectra stay in the memory-side cache between the passes; 0 runs each pass
  * over the whole half spectrum. The results are the same bit for bit. `columns`: 0 or a
  * power of two up to 512; PMR_E_INVALID otherwise. Default 0. Not synchronised with work in
  * flight: set it before enqueueing. */
